@@ -1,0 +1,663 @@
+/*
+ * rift_oracle.c -- FP64 CPU oracle for the ILE marginalized likelihood.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It is written to be
+ * read against the paper (arXiv 2210.07912), not to be fast: every sample is
+ * evaluated literally, in double precision, with no blocking or fusion.
+ *
+ * Pins (tests/test_oracle_*.py) tie each function to something other than
+ * itself: closed-form antenna patterns, closed-form l=2 harmonics and their
+ * orthonormality, the noise-free peak rho^2/2, psi -> psi+pi invariance,
+ * brute-force quadrature of the Monte Carlo integral, Philox known-answer
+ * vectors, and central finite differences of the gradient.
+ */
+#include "rift_oracle.h"
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+int or_rows(const or_point *p) { return p->n_t + 2 * p->pad + 3; }
+
+/* ------------------------------------------------------------------------
+ * Geometry.  The paper says only that L_full accounts for the detector
+ * response and that Q_k is evaluated at the detector's arrival time t_k
+ * (Sec. II, Eq. (def:lnL:Decomposed)).  Reading used: the standard tensor
+ * antenna pattern F = F_+ + i F_x with F(psi) = F(0) exp(-2 i psi), and
+ * t_k = t_geo - r_k . n / c.
+ * ---------------------------------------------------------------------- */
+
+/* unit vector towards the source in Earth-fixed axes; Earth-fixed longitude
+ * of the source is alpha - gmst. */
+void or_direction(double alpha, double delta, double gmst, double n[3]) {
+  double h = alpha - gmst;
+  n[0] = cos(delta) * cos(h);
+  n[1] = cos(delta) * sin(h);
+  n[2] = sin(delta);
+}
+
+/* polarization basis e1, e2 (both orthogonal to n) and their derivatives
+ * with respect to alpha and delta */
+static void basis(double alpha, double delta, double gmst, double e1[3], double e2[3],
+                  double e1a[3], double e2a[3], double e1d[3], double e2d[3]) {
+  double h = alpha - gmst, ch = cos(h), sh = sin(h), cd = cos(delta), sd = sin(delta);
+  e1[0] = -sh; e1[1] = ch; e1[2] = 0.0;
+  e2[0] = sd * ch; e2[1] = sd * sh; e2[2] = -cd;
+  e1a[0] = -ch; e1a[1] = -sh; e1a[2] = 0.0;
+  e2a[0] = -sd * sh; e2a[1] = sd * ch; e2a[2] = 0.0;
+  e1d[0] = 0.0; e1d[1] = 0.0; e1d[2] = 0.0;
+  e2d[0] = cd * ch; e2d[1] = cd * sh; e2d[2] = sd;
+}
+
+/* x^T D y for symmetric 3x3 D */
+static double quad3(const double D[9], const double x[3], const double y[3]) {
+  double s = 0.0;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) s += x[i] * D[3 * i + j] * y[j];
+  return s;
+}
+
+/* F_+ = D : (X X^T - Y Y^T), F_x = D : (X Y^T + Y X^T),
+ * X = cos(psi) e1 + sin(psi) e2, Y = -sin(psi) e1 + cos(psi) e2.
+ * Optional derivatives with respect to alpha, delta, psi. */
+static void antenna_full(const double D[9], double alpha, double delta, double psi, double gmst,
+                         double F[2], double Fa[2], double Fd[2], double Fp[2]) {
+  double e1[3], e2[3], e1a[3], e2a[3], e1d[3], e2d[3];
+  basis(alpha, delta, gmst, e1, e2, e1a, e2a, e1d, e2d);
+  double c = cos(psi), s = sin(psi);
+  double X[3], Y[3], Xa[3], Ya[3], Xd[3], Yd[3];
+  for (int i = 0; i < 3; i++) {
+    X[i] = c * e1[i] + s * e2[i];
+    Y[i] = -s * e1[i] + c * e2[i];
+    Xa[i] = c * e1a[i] + s * e2a[i];
+    Ya[i] = -s * e1a[i] + c * e2a[i];
+    Xd[i] = c * e1d[i] + s * e2d[i];
+    Yd[i] = -s * e1d[i] + c * e2d[i];
+  }
+  F[0] = quad3(D, X, X) - quad3(D, Y, Y);
+  F[1] = 2.0 * quad3(D, X, Y);
+  if (Fa) {
+    Fa[0] = 2.0 * (quad3(D, X, Xa) - quad3(D, Y, Ya));
+    Fa[1] = 2.0 * (quad3(D, Xa, Y) + quad3(D, X, Ya));
+  }
+  if (Fd) {
+    Fd[0] = 2.0 * (quad3(D, X, Xd) - quad3(D, Y, Yd));
+    Fd[1] = 2.0 * (quad3(D, Xd, Y) + quad3(D, X, Yd));
+  }
+  if (Fp) { /* dF/dpsi = -2i F */
+    Fp[0] = 2.0 * F[1];
+    Fp[1] = -2.0 * F[0];
+  }
+}
+
+void or_antenna(const double D[9], double alpha, double delta, double psi, double gmst,
+                double *fplus, double *fcross) {
+  double F[2];
+  antenna_full(D, alpha, delta, psi, gmst, F, NULL, NULL, NULL);
+  *fplus = F[0];
+  *fcross = F[1];
+}
+
+double or_delay(const double r[3], double alpha, double delta, double gmst) {
+  double n[3];
+  or_direction(alpha, delta, gmst, n);
+  return -(r[0] * n[0] + r[1] * n[1] + r[2] * n[2]) / OR_C_SI;
+}
+
+/* ------------------------------------------------------------------------
+ * Spin-weighted spherical harmonics of spin weight -2 (the angular basis of
+ * the mode decomposition, Sec. II.A and App. D).  Written from the Wigner-d
+ * sum of Goldberg et al., J. Math. Phys. 8, 2155 (1967):
+ *   Y^{-2}_{lm}(iota, phi) = sqrt((2l+1)/4pi) d^l_{m,2}(iota) e^{i m phi},
+ *   d^l_{m,2} = sum_k (-1)^k sqrt((l+m)!(l-m)!(l+2)!(l-2)!)
+ *               / ((l+m-k)!(l-2-k)! k! (k+2-m)!)
+ *               cos(iota/2)^(2l+m-2-2k) sin(iota/2)^(2k+2-m).
+ * ---------------------------------------------------------------------- */
+static double fact(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; i++) f *= i;
+  return f;
+}
+
+/* d^l_{m,2}(iota) and its derivative */
+static void wigner_d(int l, int m, double iota, double *d, double *dd) {
+  double c = cos(0.5 * iota), s = sin(0.5 * iota);
+  int kmin = m - 2 > 0 ? m - 2 : 0;
+  int kmax = (l + m) < (l - 2) ? (l + m) : (l - 2);
+  double norm = sqrt(fact(l + m) * fact(l - m) * fact(l + 2) * fact(l - 2));
+  double sum = 0.0, dsum = 0.0;
+  for (int k = kmin; k <= kmax; k++) {
+    double coef = ((k & 1) ? -1.0 : 1.0) * norm /
+                  (fact(l + m - k) * fact(l - 2 - k) * fact(k) * fact(k + 2 - m));
+    int A = 2 * l + m - 2 - 2 * k; /* power of cos */
+    int Bp = 2 * k + 2 - m;        /* power of sin */
+    sum += coef * pow(c, A) * pow(s, Bp);
+    /* d/diota [c^A s^B] = -A/2 c^(A-1) s^(B+1) + B/2 c^(A+1) s^(B-1) */
+    double t = 0.0;
+    if (A > 0) t -= 0.5 * A * pow(c, A - 1) * pow(s, Bp + 1);
+    if (Bp > 0) t += 0.5 * Bp * pow(c, A + 1) * pow(s, Bp - 1);
+    dsum += coef * t;
+  }
+  *d = sum;
+  *dd = dsum;
+}
+
+static void sylm_full(int l, int m, double iota, double phi, double Y[2], double Yi[2]) {
+  double d, dd;
+  wigner_d(l, m, iota, &d, &dd);
+  double nrm = sqrt((2.0 * l + 1.0) / (4.0 * M_PI));
+  double cp = cos(m * phi), sp = sin(m * phi);
+  Y[0] = nrm * d * cp;
+  Y[1] = nrm * d * sp;
+  if (Yi) {
+    Yi[0] = nrm * dd * cp;
+    Yi[1] = nrm * dd * sp;
+  }
+}
+
+void or_sylm(int l, int m, double iota, double phi, double *re, double *im) {
+  double Y[2];
+  sylm_full(l, m, iota, phi, Y, NULL);
+  *re = Y[0];
+  *im = Y[1];
+}
+
+/* ------------------------------------------------------------------------
+ * Coefficients of the decomposed likelihood, App. D Eq. (def:lnL:Decomposed):
+ *   a_{k,lm} = (D_ref / D) F_k Y^{-2}_{lm}(iota, phi)
+ *   B = 1/4 sum_k [ a_k^dagger U_k a_k + Re(a_k^T V_k a_k) ]
+ * (the (D_ref/D)^2 / 4 prefactor of the printed U/V term is folded into a).
+ * Reading: the printed data term omits Re and D_ref/D; ln L is the real
+ * log-likelihood ratio Re[(D_ref/D) sum (F Y)^* Q] - B.
+ * ---------------------------------------------------------------------- */
+static void cmul(const double x[2], const double y[2], double z[2]) {
+  double re = x[0] * y[0] - x[1] * y[1];
+  double im = x[0] * y[1] + x[1] * y[0];
+  z[0] = re;
+  z[1] = im;
+}
+
+static double quadratic_term(const or_point *p, int k, const double *a /* [M][2] */) {
+  int M = p->M;
+  const double *U = p->U + (size_t)k * M * M * 2;
+  double uterm = 0.0, vterm = 0.0;
+  for (int m = 0; m < M; m++)
+    for (int mp = 0; mp < M; mp++) {
+      const double *u = U + ((size_t)m * M + mp) * 2;
+      /* conj(a_m) U_{m m'} a_{m'} */
+      double ca[2] = {a[2 * m], -a[2 * m + 1]}, t[2], z[2];
+      cmul(ca, u, t);
+      cmul(t, a + 2 * mp, z);
+      uterm += z[0];
+      if (p->V) {
+        const double *v = p->V + (size_t)k * M * M * 2 + ((size_t)m * M + mp) * 2;
+        cmul(a + 2 * m, v, t);
+        cmul(t, a + 2 * mp, z);
+        vterm += z[0];
+      }
+    }
+  return 0.25 * (uterm + vterm);
+}
+
+void or_coeffs(const or_point *p, const double *theta, double *a, double *B) {
+  double x = p->d_ref / theta[OR_DIST];
+  double Bsum = 0.0;
+  for (int k = 0; k < p->K; k++) {
+    double F[2];
+    antenna_full(p->det_resp + 9 * k, theta[OR_ALPHA], theta[OR_DELTA], theta[OR_PSI], p->gmst, F,
+                 NULL, NULL, NULL);
+    for (int m = 0; m < p->M; m++) {
+      double Y[2], z[2];
+      sylm_full(p->ell[m], p->em[m], theta[OR_IOTA], theta[OR_PHI], Y, NULL);
+      cmul(F, Y, z);
+      a[(k * p->M + m) * 2 + 0] = x * z[0];
+      a[(k * p->M + m) * 2 + 1] = x * z[1];
+    }
+    Bsum += quadratic_term(p, k, a + (size_t)k * p->M * 2);
+  }
+  *B = Bsum;
+}
+
+/* ------------------------------------------------------------------------
+ * Interpolation of Q at a fractional row.  The paper evaluates Q_k at the
+ * detector arrival time t_k without saying how off-grid times are handled.
+ * Reading: Catmull-Rom (Keys cubic, a = -1/2) over rows b-1..b+2.
+ * ---------------------------------------------------------------------- */
+void or_catmull_rom(double mu, double w[4], double dw[4]) {
+  double m2 = mu * mu, m3 = m2 * mu;
+  w[0] = 0.5 * (-m3 + 2.0 * m2 - mu);
+  w[1] = 0.5 * (3.0 * m3 - 5.0 * m2 + 2.0);
+  w[2] = 0.5 * (-3.0 * m3 + 4.0 * m2 + mu);
+  w[3] = 0.5 * (m3 - m2);
+  if (dw) {
+    dw[0] = 0.5 * (-3.0 * m2 + 4.0 * mu - 1.0);
+    dw[1] = 0.5 * (9.0 * m2 - 10.0 * mu);
+    dw[2] = 0.5 * (-9.0 * m2 + 8.0 * mu + 1.0);
+    dw[3] = 0.5 * (3.0 * m2 - 2.0 * mu);
+  }
+}
+
+/* fractional row offset of detector k: s = (tau + dt_k) f_s */
+static double shift_of(const or_point *p, int k, const double *theta) {
+  double dt = or_delay(p->det_pos + 3 * k, theta[OR_ALPHA], theta[OR_DELTA], p->gmst);
+  return (theta[OR_TAU] + dt) * p->f_s;
+}
+
+/* ln L_full on the window grid t_j = t_q0 + (P + 1 + j)/f_s + tau, j = 0..n_t-1:
+ *   ell_j = sum_k Re( sum_m conj(a_km) Qtilde_km(j) ) - B,
+ *   Qtilde_k(j) = sum_{q=-1..2} w_q(mu_k) Q_k[P + 1 + j + n_k + q]. */
+void or_ell(const or_point *p, const double *theta, double *ell) {
+  int K = p->K, M = p->M, L = or_rows(p);
+  double *a = (double *)malloc(sizeof(double) * 2 * K * M);
+  double B;
+  or_coeffs(p, theta, a, &B);
+  for (int j = 0; j < p->n_t; j++) ell[j] = -B;
+  for (int k = 0; k < K; k++) {
+    double s = shift_of(p, k, theta);
+    double nf = floor(s);
+    int n = (int)nf;
+    double w[4];
+    or_catmull_rom(s - nf, w, NULL);
+    const double *Qk = p->Q + (size_t)k * L * M * 2;
+    for (int j = 0; j < p->n_t; j++) {
+      int b = p->pad + 1 + j + n;
+      double acc = 0.0;
+      for (int m = 0; m < M; m++) {
+        double qt[2] = {0.0, 0.0};
+        for (int q = -1; q <= 2; q++) {
+          int r = b + q;
+          if (r < 0 || r >= L) { acc = NAN; break; } /* outside the stored rows */
+          qt[0] += w[q + 1] * Qk[((size_t)r * M + m) * 2 + 0];
+          qt[1] += w[q + 1] * Qk[((size_t)r * M + m) * 2 + 1];
+        }
+        const double *am = a + (k * M + m) * 2;
+        acc += am[0] * qt[0] + am[1] * qt[1]; /* Re(conj(a) qt) */
+      }
+      ell[j] += acc;
+    }
+  }
+  free(a);
+}
+
+/* ------------------------------------------------------------------------
+ * Time marginalization: uniform prior over the window grid, rectangle rule,
+ * evaluated as a max-shifted logsumexp (App. D.2):
+ *   ln L_t = max_j ell_j + ln sum_j exp(ell_j - max) - ln n_t.
+ * ---------------------------------------------------------------------- */
+static double lse_mean(const double *x, int n) {
+  double mx = -INFINITY;
+  for (int j = 0; j < n; j++)
+    if (x[j] > mx) mx = x[j];
+  if (!isfinite(mx)) return mx;
+  double s = 0.0;
+  for (int j = 0; j < n; j++) s += exp(x[j] - mx);
+  return mx + log(s) - log((double)n);
+}
+
+double or_lnL_t(const or_point *p, const double *theta) {
+  double *ell = (double *)malloc(sizeof(double) * p->n_t);
+  or_ell(p, theta, ell);
+  double r = lse_mean(ell, p->n_t);
+  free(ell);
+  return r;
+}
+
+void or_lnL_t_batch(const or_point *p, int64_t n, int64_t stride, const double *theta, double *out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; i++) {
+    double th[OR_NPAR];
+    for (int d = 0; d < OR_NPAR; d++) th[d] = theta[d * stride + i];
+    out[i] = or_lnL_t(p, th);
+  }
+}
+
+/* ------------------------------------------------------------------------
+ * Gradient of ln L_t with respect to the seven extrinsic parameters.
+ *   d lnL_t = sum_j p_j d ell_j,  p_j = softmax_j(ell_j)
+ *   d ell_j = sum_k Re( sum_m conj(d a_km) Qtilde_km(j) )
+ *           + sum_k Re( sum_m conj(a_km) Qtilde'_km(j) ) ds_k
+ *           - dB
+ * with Qtilde' built from the Catmull-Rom derivative weights (per row) and
+ * ds_k = f_s (d tau + d dt_k).
+ * ---------------------------------------------------------------------- */
+void or_grad(const or_point *p, const double *theta, double *lnL_t, double grad[7]) {
+  int K = p->K, M = p->M, L = or_rows(p), NT = p->n_t;
+  double alpha = theta[OR_ALPHA], delta = theta[OR_DELTA], psi = theta[OR_PSI];
+  double iota = theta[OR_IOTA], phi = theta[OR_PHI], dist = theta[OR_DIST];
+  double x = p->d_ref / dist;
+  double *ell = (double *)malloc(sizeof(double) * NT);
+  double *a = (double *)malloc(sizeof(double) * 2 * K * M);
+  double *da = (double *)calloc((size_t)7 * 2 * K * M, sizeof(double)); /* [7][K][M][2] */
+  double *Y = (double *)malloc(sizeof(double) * 2 * M);
+  double *Yi = (double *)malloc(sizeof(double) * 2 * M);
+  double *Fs = (double *)malloc(sizeof(double) * 8 * K); /* F, Fa, Fd, Fp per detector */
+  for (int m = 0; m < M; m++) sylm_full(p->ell[m], p->em[m], iota, phi, Y + 2 * m, Yi + 2 * m);
+  double B = 0.0;
+  for (int k = 0; k < K; k++) {
+    double *F = Fs + 8 * k;
+    antenna_full(p->det_resp + 9 * k, alpha, delta, psi, p->gmst, F, F + 2, F + 4, F + 6);
+    for (int m = 0; m < M; m++) {
+      double z[2];
+      size_t o = (size_t)(k * M + m) * 2;
+      cmul(F, Y + 2 * m, z);
+      a[o] = x * z[0];
+      a[o + 1] = x * z[1];
+      double t[2];
+      cmul(F + 2, Y + 2 * m, t); /* alpha */
+      da[0 * 2 * K * M + o] = x * t[0]; da[0 * 2 * K * M + o + 1] = x * t[1];
+      cmul(F + 4, Y + 2 * m, t); /* delta */
+      da[1 * 2 * K * M + o] = x * t[0]; da[1 * 2 * K * M + o + 1] = x * t[1];
+      cmul(F + 6, Y + 2 * m, t); /* psi */
+      da[2 * 2 * K * M + o] = x * t[0]; da[2 * 2 * K * M + o + 1] = x * t[1];
+      cmul(F, Yi + 2 * m, t); /* iota */
+      da[3 * 2 * K * M + o] = x * t[0]; da[3 * 2 * K * M + o + 1] = x * t[1];
+      /* phi: dY/dphi = i m Y */
+      double iy[2] = {-p->em[m] * Y[2 * m + 1], p->em[m] * Y[2 * m]};
+      cmul(F, iy, t);
+      da[4 * 2 * K * M + o] = x * t[0]; da[4 * 2 * K * M + o + 1] = x * t[1];
+      /* distance: da/dD = -a/D */
+      da[5 * 2 * K * M + o] = -a[o] / dist; da[5 * 2 * K * M + o + 1] = -a[o + 1] / dist;
+    }
+    B += quadratic_term(p, k, a + (size_t)k * M * 2);
+  }
+  /* ell_j and per-detector interpolated windows */
+  for (int j = 0; j < NT; j++) ell[j] = -B;
+  int *nk = (int *)malloc(sizeof(int) * K);
+  double *wk = (double *)malloc(sizeof(double) * 8 * K);
+  for (int k = 0; k < K; k++) {
+    double s = shift_of(p, k, theta), nf = floor(s);
+    nk[k] = (int)nf;
+    or_catmull_rom(s - nf, wk + 8 * k, wk + 8 * k + 4);
+    const double *Qk = p->Q + (size_t)k * L * M * 2;
+    for (int j = 0; j < NT; j++) {
+      int b = p->pad + 1 + j + nk[k];
+      double acc = 0.0;
+      for (int m = 0; m < M; m++) {
+        double qt[2] = {0, 0};
+        for (int q = -1; q <= 2; q++) {
+          qt[0] += wk[8 * k + q + 1] * Qk[((size_t)(b + q) * M + m) * 2];
+          qt[1] += wk[8 * k + q + 1] * Qk[((size_t)(b + q) * M + m) * 2 + 1];
+        }
+        acc += a[(k * M + m) * 2] * qt[0] + a[(k * M + m) * 2 + 1] * qt[1];
+      }
+      ell[j] += acc;
+    }
+  }
+  double lt = lse_mean(ell, NT);
+  *lnL_t = lt;
+  double lnN = log((double)NT);
+  for (int d = 0; d < 7; d++) grad[d] = 0.0;
+  /* direction derivatives for the delays */
+  double h = alpha - p->gmst;
+  double dn_a[3] = {-cos(delta) * sin(h), cos(delta) * cos(h), 0.0};
+  double dn_d[3] = {-sin(delta) * cos(h), -sin(delta) * sin(h), cos(delta)};
+  for (int k = 0; k < K; k++) {
+    const double *Qk = p->Q + (size_t)k * L * M * 2;
+    /* G_k = sum_j p_j Qtilde_k(j), H_k = sum_j p_j Re(a^dag Qtilde'_k(j)) */
+    double *G = (double *)calloc((size_t)2 * M, sizeof(double));
+    double H = 0.0;
+    for (int j = 0; j < NT; j++) {
+      double pj = exp(ell[j] - lt - lnN);
+      int b = p->pad + 1 + j + nk[k];
+      for (int m = 0; m < M; m++) {
+        double qt[2] = {0, 0}, qd[2] = {0, 0};
+        for (int q = -1; q <= 2; q++) {
+          double qr = Qk[((size_t)(b + q) * M + m) * 2], qi = Qk[((size_t)(b + q) * M + m) * 2 + 1];
+          qt[0] += wk[8 * k + q + 1] * qr;
+          qt[1] += wk[8 * k + q + 1] * qi;
+          qd[0] += wk[8 * k + 4 + q + 1] * qr;
+          qd[1] += wk[8 * k + 4 + q + 1] * qi;
+        }
+        G[2 * m] += pj * qt[0];
+        G[2 * m + 1] += pj * qt[1];
+        H += pj * (a[(k * M + m) * 2] * qd[0] + a[(k * M + m) * 2 + 1] * qd[1]);
+      }
+    }
+    const double *rk = p->det_pos + 3 * k;
+    double ddt_a = -(rk[0] * dn_a[0] + rk[1] * dn_a[1] + rk[2] * dn_a[2]) / OR_C_SI;
+    double ddt_d = -(rk[0] * dn_d[0] + rk[1] * dn_d[1] + rk[2] * dn_d[2]) / OR_C_SI;
+    grad[OR_ALPHA] += H * p->f_s * ddt_a;
+    grad[OR_DELTA] += H * p->f_s * ddt_d;
+    grad[OR_TAU] += H * p->f_s;
+    /* data term through a, minus the quadratic term:
+     * dB = 1/2 Re(da^dag U a) + 1/2 Re(da^T V a) */
+    const double *U = p->U + (size_t)k * M * M * 2;
+    const double *V = p->V ? p->V + (size_t)k * M * M * 2 : NULL;
+    const double *ak = a + (size_t)k * M * 2;
+    for (int d = 0; d < 6; d++) {
+      const double *dak = da + (size_t)d * 2 * K * M + (size_t)k * M * 2;
+      double g = 0.0;
+      for (int m = 0; m < M; m++) g += dak[2 * m] * G[2 * m] + dak[2 * m + 1] * G[2 * m + 1];
+      double dBk = 0.0;
+      for (int m = 0; m < M; m++)
+        for (int mp = 0; mp < M; mp++) {
+          double cda[2] = {dak[2 * m], -dak[2 * m + 1]}, t[2], z[2];
+          cmul(cda, U + ((size_t)m * M + mp) * 2, t);
+          cmul(t, ak + 2 * mp, z);
+          dBk += 0.5 * z[0];
+          if (V) {
+            cmul(dak + 2 * m, V + ((size_t)m * M + mp) * 2, t);
+            cmul(t, ak + 2 * mp, z);
+            dBk += 0.5 * z[0];
+          }
+        }
+      grad[d] += g - dBk;
+    }
+    free(G);
+  }
+  free(nk); free(wk); free(ell); free(a); free(da); free(Y); free(Yi); free(Fs);
+}
+
+void or_grad_batch(const or_point *p, int64_t n, int64_t stride, const double *theta,
+                   double *lnL_t, double *grad) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; i++) {
+    double th[OR_NPAR], g[7], l;
+    for (int d = 0; d < OR_NPAR; d++) th[d] = theta[d * stride + i];
+    or_grad(p, th, &l, g);
+    lnL_t[i] = l;
+    for (int d = 0; d < 7; d++) grad[d * stride + i] = g[d];
+  }
+}
+
+/* ------------------------------------------------------------------------
+ * Monte Carlo estimate and sample-size measures.
+ *   ln L_marg = ln[(1/N) sum_i w_i], Sec. II.A Eq. (lnL:MonteCarlo),
+ *   n_eff = sum w / max w  (App. B Eq. (neff)),
+ *   n_ESS = (sum w)^2 / sum w^2  (App. B Eq. (neff_ESS)),
+ *   n_var = N wbar^2 / s^2 with the unbiased sample variance s^2 (App. B, the
+ *           variance-based size; the printed formula is garbled, the words
+ *           following it fix this form), sigma_lnL = 1 / sqrt(n_var).
+ * Non-finite ln w are counted and excluded.  All sums are taken in log space
+ * shifted by max ln w (App. D.2).
+ * ---------------------------------------------------------------------- */
+void or_reduce(int64_t n, const double *lnw, or_result *out) {
+  double mx = -INFINITY;
+  int64_t nn = 0, bad = 0;
+  for (int64_t i = 0; i < n; i++) {
+    if (isnan(lnw[i]) || lnw[i] == INFINITY) { bad++; continue; }
+    if (lnw[i] > mx) mx = lnw[i];
+  }
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = 0; i < n; i++) {
+    if (isnan(lnw[i]) || lnw[i] == INFINITY) continue;
+    nn++;
+    if (mx == -INFINITY) continue;
+    double w = exp(lnw[i] - mx);
+    s1 += w;
+    s2 += w * w;
+  }
+  out->n = nn;
+  out->n_nonfinite = bad;
+  out->max_lnw = mx;
+  if (nn == 0 || mx == -INFINITY || s1 <= 0.0) {
+    out->lnL_marg = -INFINITY;
+    out->n_eff = 0.0;
+    out->n_ess = 0.0;
+    out->n_var = 0.0;
+    out->sigma_lnL = INFINITY;
+    return;
+  }
+  double N = (double)nn;
+  out->lnL_marg = mx + log(s1) - log(N);
+  out->n_eff = s1; /* sum w / max w with the max weight scaled to 1 */
+  out->n_ess = s1 * s1 / s2;
+  double wbar = s1 / N;
+  double var = nn > 1 ? (s2 - N * wbar * wbar) / (N - 1.0) : 0.0;
+  if (var <= 0.0) {
+    out->n_var = INFINITY;
+    out->sigma_lnL = 0.0;
+  } else {
+    out->n_var = N * wbar * wbar / var;
+    out->sigma_lnL = 1.0 / sqrt(out->n_var);
+  }
+}
+
+/* ------------------------------------------------------------------------
+ * Counter-based random numbers: Philox4x32-10 as defined by Salmon, Moraes,
+ * Dror and Shaw, "Parallel random numbers: as easy as 1, 2, 3" (SC'11):
+ * ten rounds of two 32x32->64 multiplies with multipliers 0xD2511F53 and
+ * 0xCD9E8D57, key schedule bumped by the Weyl constants 0x9E3779B9 and
+ * 0xBB67AE85 between rounds.
+ * ---------------------------------------------------------------------- */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; r++) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    if (r < 9) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* top 24 bits, centred in their cell: (0, 1), exactly representable */
+double or_u01(uint32_t x) { return ((double)(x >> 8) + 0.5) * (1.0 / 16777216.0); }
+
+/* prior inverse CDFs, u -> theta (priors of the workloads: alpha uniform on
+ * [0, 2pi), sin(delta) and cos(iota) uniform on [-1, 1], psi uniform on
+ * [0, pi), phi uniform on [0, 2pi), p(D) ~ D^2 on [d_min, d_max], tau uniform
+ * on [-w/2, w/2)). */
+static double prior_inv(int d, double u, double d_min, double d_max, double tau_width) {
+  switch (d) {
+  case OR_ALPHA: return 2.0 * M_PI * u;
+  case OR_DELTA: return asin(2.0 * u - 1.0);
+  case OR_PSI: return M_PI * u;
+  case OR_IOTA: return acos(2.0 * u - 1.0);
+  case OR_PHI: return 2.0 * M_PI * u;
+  case OR_DIST: {
+    double a3 = d_min * d_min * d_min, b3 = d_max * d_max * d_max;
+    return cbrt(a3 + u * (b3 - a3));
+  }
+  default: return (u - 0.5) * tau_width;
+  }
+}
+
+void or_prior_cdf(int d, const double *theta, double d_min, double d_max, double tau_width, double *u) {
+  double t = theta[d];
+  switch (d) {
+  case OR_ALPHA: *u = t / (2.0 * M_PI); break;
+  case OR_DELTA: *u = 0.5 * (sin(t) + 1.0); break;
+  case OR_PSI: *u = t / M_PI; break;
+  case OR_IOTA: *u = 0.5 * (1.0 + cos(t)); break;
+  case OR_PHI: *u = t / (2.0 * M_PI); break;
+  case OR_DIST: {
+    double a3 = d_min * d_min * d_min, b3 = d_max * d_max * d_max;
+    *u = (t * t * t - a3) / (b3 - a3);
+    break;
+  }
+  default: *u = tau_width > 0 ? t / tau_width + 0.5 : 0.5;
+  }
+}
+
+/* Sample i of (point, round).  Counter (i_lo, i_hi, 2 round + half, point),
+ * key (seed_lo, seed_hi); dimension d uses output word d of the two blocks.
+ * An adapted dimension draws its prior-CDF coordinate from the piecewise-
+ * constant histogram density by inverse CDF (Sec. III.B: separable sampling
+ * prior, 100-bin histograms in adaptive dimensions), so that
+ * ln p - ln p_s = -sum_d ln h_d(u_d).  bins[d] receives the histogram bin of
+ * the sample's prior-CDF coordinate in every dimension. */
+void or_draw(uint64_t seed, uint32_t point, uint32_t round, uint64_t i, double d_min, double d_max,
+             double tau_width, const double *cdf, int nb, unsigned adapt_mask, double theta[7],
+             double *ln_ratio, uint8_t bins[7], uint32_t raw[8]) {
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t r[8];
+  for (int half = 0; half < 2; half++) {
+    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)(i >> 32), 2u * round + (uint32_t)half, point};
+    or_philox4x32_10(ctr, key, r + 4 * half);
+  }
+  if (raw) memcpy(raw, r, sizeof(r));
+  double lr = 0.0;
+  for (int d = 0; d < 7; d++) {
+    double v = or_u01(r[d]);
+    double u = v;
+    int bin = (int)floor(v * nb); /* exact: v has 25 significant bits */
+    if (cdf && (adapt_mask >> d) & 1u) {
+      const double *c = cdf + (size_t)d * (nb + 1);
+      /* largest b with c[b] <= v */
+      int lo = 0, hi = nb; /* invariant c[lo] <= v < c[hi] */
+      while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (c[mid] <= v) lo = mid; else hi = mid;
+      }
+      double mass = c[lo + 1] - c[lo];
+      u = ((double)lo + (v - c[lo]) / mass) / nb;
+      lr -= log(mass * nb);
+      bin = lo;
+    }
+    if (bins) bins[d] = (uint8_t)bin;
+    theta[d] = prior_inv(d, u, d_min, d_max, tau_width);
+  }
+  *ln_ratio = lr;
+}
+
+/* Adaptation between rounds (Sec. III.B).  Reading of the garbled histogram
+ * formula: nb equal bins in each dimension's prior-CDF coordinate, bin mass
+ * proportional to the summed importance weight w = exp(lnw - max lnw) of the
+ * round's samples in the bin, mixed with a uniform floor eps and normalized:
+ *   h_b = (1 - eps) nb m_b / sum m + eps,   cdf[b+1] = cdf[b] + h_b / nb.
+ * bins[d][i] is the bin of sample i in dimension d (as returned by or_draw).
+ * A dimension outside adapt_mask, or a round without a finite weight, gets
+ * the uniform table. */
+void or_adapt(int64_t n, const uint8_t *bins, int64_t stride, const double *lnw, int nb,
+              double floor_eps, unsigned adapt_mask, double *cdf) {
+  double mx = -INFINITY;
+  for (int64_t i = 0; i < n; i++)
+    if (isfinite(lnw[i]) && lnw[i] > mx) mx = lnw[i];
+  double *mass = (double *)calloc(nb, sizeof(double));
+  for (int d = 0; d < 7; d++) {
+    double *c = cdf + (size_t)d * (nb + 1);
+    memset(mass, 0, sizeof(double) * nb);
+    double tot = 0.0;
+    if (((adapt_mask >> d) & 1u) && isfinite(mx)) {
+      for (int64_t i = 0; i < n; i++) {
+        if (!isfinite(lnw[i])) continue;
+        double w = exp(lnw[i] - mx);
+        mass[bins[d * stride + i]] += w;
+        tot += w;
+      }
+    }
+    c[0] = 0.0;
+    for (int b = 0; b < nb; b++) {
+      double h = tot > 0.0 ? (1.0 - floor_eps) * nb * mass[b] / tot + floor_eps : 1.0;
+      c[b + 1] = c[b] + h / nb;
+    }
+    /* the running sum may drift by rounding: pin the last edge to 1 */
+    for (int b = 1; b <= nb; b++) c[b] /= c[nb];
+  }
+  free(mass);
+}

@@ -1,0 +1,96 @@
+/*
+ * rift_oracle.h -- plain, slow, FP64 CPU reference for the ILE marginalized
+ * likelihood (arXiv 2210.07912).  TEST INFRASTRUCTURE ONLY: nothing in the
+ * product path may include, link or call this.  It shares no source with the
+ * HIP library; only the seeded input generator feeds both.
+ *
+ * Every routine follows one passage of the paper:
+ *   - ln L_full, mode decomposed ........ App. D, Eq. (loglikelihood) /
+ *                                         Eq. (def:lnL:Decomposed)
+ *   - Q, U, V inner products ............ App. D, Eq. (QUV)
+ *   - Monte Carlo estimate of L(lambda) . Sec. II.A, Eq. (lnL:MonteCarlo)
+ *   - log-space sums (logsumexp) ........ App. D.2 (finite-precision arithmetic)
+ *   - n_eff, n_ESS, n_var ............... App. B, Eqs. (neff), (neff_ESS) and the
+ *                                         variance-based sample size
+ *   - adaptive-Cartesian histograms ..... Sec. III.B (GPU-accelerated Monte
+ *                                         Carlo integration), n_bins = 100
+ * Readings where the paper is silent or garbled are listed in the repository's
+ * design notes and restated at the routine that uses them.
+ */
+#ifndef RIFT_ORACLE_H
+#define RIFT_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* extrinsic parameter order used everywhere */
+enum { OR_ALPHA = 0, OR_DELTA = 1, OR_PSI = 2, OR_IOTA = 3, OR_PHI = 4, OR_DIST = 5, OR_TAU = 6, OR_NPAR = 7 };
+
+#define OR_C_SI 299792458.0
+
+typedef struct {
+  int K;              /* detectors */
+  int M;              /* modes */
+  int n_t;            /* window length (marginalization grid) */
+  int pad;            /* P: rows before/after the window; L = n_t + 2P + 3 */
+  const int *ell, *em;/* [M] */
+  double f_s;         /* Hz */
+  double d_ref;       /* Mpc at which Q, U, V are computed */
+  double gmst;        /* rad */
+  const double *det_pos;  /* [K][3] m, Earth-fixed */
+  const double *det_resp; /* [K][3][3] response tensor */
+  const double *Q;    /* [K][L][M][2] */
+  const double *U;    /* [K][M][M][2] */
+  const double *V;    /* [K][M][M][2] or NULL */
+} or_point;
+
+typedef struct {
+  double lnL_marg, sigma_lnL, n_eff, n_ess, n_var, max_lnw;
+  int64_t n, n_nonfinite;
+} or_result;
+
+int or_rows(const or_point *p);
+
+/* geometry -------------------------------------------------------------- */
+void or_direction(double alpha, double delta, double gmst, double n[3]);
+void or_antenna(const double D[9], double alpha, double delta, double psi, double gmst,
+                double *fplus, double *fcross);
+double or_delay(const double r[3], double alpha, double delta, double gmst);
+void or_sylm(int l, int m, double iota, double phi, double *re, double *im);
+
+/* likelihood ------------------------------------------------------------ */
+void or_coeffs(const or_point *p, const double *theta, double *a /*[K][M][2]*/, double *B);
+void or_catmull_rom(double mu, double w[4], double dw[4]);
+void or_ell(const or_point *p, const double *theta, double *ell /*[n_t]*/);
+double or_lnL_t(const or_point *p, const double *theta);
+/* theta: [7][stride]; out[N]; OpenMP over samples */
+void or_lnL_t_batch(const or_point *p, int64_t n, int64_t stride, const double *theta, double *out);
+void or_grad(const or_point *p, const double *theta, double *lnL_t, double grad[7]);
+void or_grad_batch(const or_point *p, int64_t n, int64_t stride, const double *theta,
+                   double *lnL_t, double *grad /*[7][stride]*/);
+
+/* Monte Carlo reduction ------------------------------------------------- */
+void or_reduce(int64_t n, const double *lnw, or_result *out);
+
+/* sampler --------------------------------------------------------------- */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double or_u01(uint32_t x);
+/* Draw sample i of (point, round) from the product proposal.
+ * cdf: [7][nb+1] or NULL (=> the prior for every dimension); adapt_mask selects
+ * which dimensions use their histogram.  Writes theta[7] and ln p - ln p_s. */
+void or_draw(uint64_t seed, uint32_t point, uint32_t round, uint64_t i,
+             double d_min, double d_max, double tau_width,
+             const double *cdf, int nb, unsigned adapt_mask,
+             double theta[7], double *ln_ratio, uint8_t bins[7], uint32_t raw[8]);
+void or_prior_cdf(int dim, const double *theta, double d_min, double d_max, double tau_width, double *u);
+/* adapt: histogram of w = exp(lnw - max) over each dimension's prior-CDF
+ * coordinate bins, floor-mixed, normalized -> cdf[7][nb+1] */
+void or_adapt(int64_t n, const uint8_t *bins /*[7][stride]*/, int64_t stride, const double *lnw,
+              int nb, double floor_eps, unsigned adapt_mask, double *cdf);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
