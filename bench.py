@@ -1,0 +1,154 @@
+"""Benchmark of the ILE marginalized-likelihood step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single]
+
+A step is one pass of the whole hot path over one batch: on-device sampling
+of the extrinsic parameters, ln L_t for every sample (geometry, harmonics,
+coefficients, the time-shifted contraction, interpolation and the window
+log-sum-exp), ln w, and the FP64 reduction to ln L_marg with n_eff, n_ESS and
+n_var (one call of rift_ile_marginalize).  Inputs (Q, U) are resident in HBM
+before the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32_mfma_tflops": 157.3, "fp64_tflops": 78.6, "hbm_gbs": 8000.0}
+
+
+def flops_per_eval(K, M, n_t):
+    """Algorithmic FLOPs of one time-marginalized evaluation: the contraction
+    of the K (n_t + 3) needed rows (4 flops per complex mode product, real
+    part), the 4-tap interpolation (8 flops per window sample and detector),
+    the log-sum-exp (4 per window sample), the quadratic term (4 K M^2) and
+    the per-sample coefficients (6 K M + 200)."""
+    return K * (n_t + 3) * 4 * M + 8 * K * n_t + 4 * n_t + 4 * K * M * M + 6 * K * M + 200
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="single")
+    ap.add_argument("--n", type=int, default=0, help="samples per step (default: the workload's)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the multi-GPU path is not part of this build "
+              "(points shard across GPUs with one 40-byte FP64 exchange per point; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2210_07912_amd import ile
+
+    w = synth.workload(args.workload)
+    pts = [synth.make_point(s) for s in w.points]
+    n = args.n or w.n_samples[0]
+    counts = [n] * len(pts) if args.n else list(w.n_samples)
+    h = ile.RiftILE(pts, precision=w.precision, tau_width=w.tau_width)
+    seed = synth.BASE_SEED + 1
+    rounds = w.rounds if w.adaptive else 1
+    mask = 0x3F if w.adaptive else 0
+
+    def step(i):
+        return h.marginalize(seed + i, counts, n_rounds=rounds, adapt_mask=mask, floor_eps=0.1)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    h.profile(True)
+    t0 = time.perf_counter()
+    res = None
+    for i in range(args.steps):
+        res = step(100 + i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms, k_launches = h.profile(False)
+    evals_per_step = sum(counts) * rounds
+    dt = (t1 - t0) / args.steps
+    value = evals_per_step / dt
+
+    # roofline of the dominant kernel (the evaluation kernel)
+    fl = sum(c * flops_per_eval(p["det_pos"].shape[0], len(p["ell"]), p["n_t"]) for c, p in zip(counts, pts))
+    fl_per_launch = fl  # one evaluation launch per round covers every point
+    k_avg_ms = k_ms / max(k_launches, 1)
+    achieved = fl_per_launch / (k_avg_ms * 1e-3) / 1e12 if k_launches else None
+    dtype = "f32" if w.precision == "fp32" else "f64"
+    peak = PEAK["fp32_mfma_tflops"] if w.precision == "fp32" else PEAK["fp64_tflops"]
+    roof = {"bound": "mfma" if w.precision == "fp32" else "alu", "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": (achieved / peak) if achieved else None, "traffic": None,
+            "kernel": "mfma_kernel" if w.precision == "fp32" else "plain_kernel",
+            "kernel_ms": k_avg_ms, "flops_per_eval": fl / max(sum(counts), 1)}
+
+    out = {
+        "metric": "extrinsic lnL evals/sec (time-marginalized) at |dln L_marg|<=1e-3 vs FP64",
+        "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": dtype, "data": "synthetic",
+        "config": {"workload": args.workload, "points": len(pts), "samples_per_point": counts[0] if len(set(counts)) == 1 else "varied",
+                   "rounds": rounds, "K": [p["det_pos"].shape[0] for p in pts][:1], "M": [len(p["ell"]) for p in pts][:1],
+                   "n_t": [p["n_t"] for p in pts][:1], "seed": seed},
+        "roofline": roof,
+        "lnL_marg": [r["lnL_marg"] for r in res][:4], "n_eff": [r["n_eff"] for r in res][:4],
+    }
+
+    # FP32 vs FP64 on the same samples (same GPU): |d ln L_marg| and the FP64 rate
+    if not args.no_fp64 and w.precision == "fp32" and len(pts) == 1:
+        nn = min(counts[0], 200_000)
+        h64 = ile.RiftILE(pts, precision="fp64", tau_width=w.tau_width)
+        th64, _, _ = h64.sample(0, seed, 0, nn)
+        th32 = th64.float()
+        l32 = h.lnL(th32)
+        l64a = h64.lnL(th32.double())
+        torch.cuda.synchronize()
+        h64.profile(True)
+        t2 = time.perf_counter()
+        l64 = h64.lnL(th32.double())
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        h64.profile(False)
+        r32, r64 = h.reduce(l32), h64.reduce(l64)
+        out["fp64_plain"] = {"evals_per_s": nn / (t3 - t2), "samples": nn,
+                             "lnL_marg_fp32": r32["lnL_marg"], "lnL_marg_fp64": r64["lnL_marg"],
+                             "abs_delta_lnL_marg": abs(r32["lnL_marg"] - r64["lnL_marg"]),
+                             "max_abs_delta_lnL_t": float((l32.double() - l64a).abs().max())}
+        h64.close()
+
+    if not args.no_cpu_baseline:
+        from oracle import oracle
+        p = pts[0]
+        op = oracle.Point.from_dict(p, complex64=(w.precision == "fp32"))
+        th = synth.prior_samples(seed, 4096, w.tau_width)
+        t_a = time.perf_counter()
+        oracle.lnL_t(op, th[:, :256])
+        t_b = time.perf_counter()
+        rate = 256 / (t_b - t_a)
+        ns = int(min(4096, max(256, rate * args.cpu_seconds)))
+        if ns > 256:
+            t_a = time.perf_counter()
+            oracle.lnL_t(op, th[:, :ns])
+            t_b = time.perf_counter()
+            rate = ns / (t_b - t_a)
+        out["cpu_baseline"] = {"value": rate, "unit": "evals/s", "cores": oracle.threads(), "kind": "oracle",
+                               "sample": f"{ns} prior samples of point 0 ({args.workload}), ln L_t only, FP64"}
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
+if __name__ == "__main__":
+    main()

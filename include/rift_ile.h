@@ -1,0 +1,233 @@
+/*
+ * rift_ile.h -- C ABI of the MI355X (gfx950) ILE marginalized-likelihood
+ * library: for each intrinsic point, draw extrinsic samples, evaluate the
+ * mode-decomposed log-likelihood from the overlaps Q and U, marginalize it
+ * over a reference-time window with a log-sum-exp, and importance-weight the
+ * results into ln L_marg with FP64 sample-size diagnostics.
+ *
+ * Paper: "Expanding RIFT: Improving performance for GW parameter inference"
+ * (arXiv 2210.07912).  The likelihood is App. D Eq. (loglikelihood) /
+ * Eq. (def:lnL:Decomposed) with the overlaps of Eq. (QUV); the Monte Carlo
+ * estimate is Sec. II.A Eq. (lnL:MonteCarlo); the sample-size measures are
+ * App. B Eqs. (neff), (neff_ESS) and the variance-based size; the adaptive
+ * histogram proposal is Sec. III.B (GPU-accelerated Monte Carlo integration).
+ *
+ * Conventions common to every call
+ *   - No C++ exception crosses this boundary.  Every call returns a
+ *     rift_status; rift_ile_last_error() gives the text of the last failure
+ *     on a handle.
+ *   - "host" pointers are read during the call only.  "device" pointers are
+ *     HIP device allocations owned by the caller; they must stay valid until
+ *     the work enqueued on the handle's stream has completed.
+ *   - Extrinsic parameters are structure-of-arrays theta[7][stride] in the
+ *     order of rift_param below; angles in radians, distance in Mpc, tau in
+ *     seconds.  A RIFT_FP32 handle takes float theta and returns float
+ *     ln L_t; a RIFT_FP64 handle takes and returns double.
+ *   - Complex arrays are interleaved (re, im) doubles, row-major.
+ *   - Calls on one handle are serialized on its stream; a handle must not be
+ *     used from two threads at once.  Distinct handles are independent.
+ *   - Per-sample results that are not finite (a sample whose arrival time
+ *     falls outside the stored rows, a non-finite theta) never fail a call:
+ *     they are returned as NaN and counted in rift_ile_result.n_nonfinite,
+ *     and excluded from every sum.
+ */
+#ifndef RIFT_ILE_H
+#define RIFT_ILE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RIFT_ILE_ABI_VERSION 1
+
+typedef enum {
+  RIFT_OK = 0,
+  RIFT_E_INVALID = -1,       /* bad argument (NULL, negative count, unknown enum) */
+  RIFT_E_SHAPE = -2,         /* inconsistent or unsupported sizes */
+  RIFT_E_NOT_HERMITIAN = -3, /* U_k not Hermitian (relative 1e-6) or V_k not symmetric */
+  RIFT_E_WINDOW = -4,        /* pad too small for the detectors' light travel time */
+  RIFT_E_NONFINITE = -5,     /* NaN/Inf in Q, U, V or the point constants */
+  RIFT_E_OOM = -6,           /* device allocation failed */
+  RIFT_E_DEVICE = -7,        /* HIP runtime error (launch, copy, fault) */
+  RIFT_E_STATE = -8          /* call not valid in the handle's current state */
+} rift_status;
+
+typedef enum { RIFT_FP32 = 0, RIFT_FP64 = 1 } rift_precision;
+
+typedef enum {
+  RIFT_ALPHA = 0, /* right ascension */
+  RIFT_DELTA = 1, /* declination */
+  RIFT_PSI = 2,   /* polarization angle */
+  RIFT_IOTA = 3,  /* inclination */
+  RIFT_PHI = 4,   /* orbital phase */
+  RIFT_DIST = 5,  /* luminosity distance, Mpc */
+  RIFT_TAU = 6,   /* offset of the time window, s */
+  RIFT_NPAR = 7
+} rift_param;
+
+#define RIFT_MAX_DET 3
+#define RIFT_MAX_MODES 32
+#define RIFT_NBINS 100
+
+typedef struct rift_ile rift_ile;
+
+/* One intrinsic point: the overlaps of App. D Eq. (QUV) at reference
+ * distance d_ref.  Q_k holds L = n_t + 2*pad + 3 rows sampled at f_s; row r
+ * is time t_q0 + r / f_s.  Window sample j (j = 0..n_t-1) is the geocentric
+ * time t_q0 + (pad + 1 + j) / f_s + tau; detector k sees it at that time plus
+ * its delay dt_k = -r_k . n / c, so the 4-tap interpolation stencil stays
+ * inside the stored rows whenever |tau + dt_k| f_s <= pad. */
+typedef struct {
+  int n_det;              /* K, 1..RIFT_MAX_DET */
+  int n_modes;            /* M, 1..RIFT_MAX_MODES */
+  int n_t;                /* window samples, >= 1 */
+  int pad;                /* rows before and after the window, >= ceil(f_s max|r_k|/c) */
+  const int *ell, *em;    /* host [M]: mode (l, m), 2 <= l <= 8, |m| <= l */
+  double f_s;             /* sample rate, Hz */
+  double d_ref;           /* distance at which Q, U, V were computed, Mpc */
+  double gmst;            /* Greenwich sidereal angle, rad */
+  const double *det_pos;  /* host [K][3]: detector vertex, Earth-fixed, m */
+  const double *det_resp; /* host [K][3][3]: symmetric response tensor D_k */
+  const double *Q;        /* host [K][L][M] complex: Q_{k,lm}(t_r) */
+  const double *U;        /* host [K][M][M] complex Hermitian: U_{k,lm,l'm'} */
+  const double *V;        /* host [K][M][M] complex symmetric, or NULL (V = 0) */
+} rift_ile_point;
+
+typedef struct {
+  int n_points;
+  const rift_ile_point *points; /* host [n_points] */
+  int precision;                /* rift_precision */
+  double d_min, d_max;          /* distance prior p(D) ~ D^2 on [d_min, d_max], Mpc */
+  double tau_width;             /* tau prior: uniform on [-w/2, w/2) s; 0 fixes tau = 0 */
+} rift_ile_desc;
+
+/* A segment of a sample array evaluated against one point. */
+typedef struct {
+  int point;       /* index into the handle's points */
+  int64_t offset;  /* first column of theta / ln L_t */
+  int64_t count;   /* number of samples */
+} rift_ile_item;
+
+typedef struct {
+  double lnL_marg;   /* ln[(1/N) sum_i w_i], Sec. II.A Eq. (lnL:MonteCarlo) */
+  double sigma_lnL;  /* 1 / sqrt(n_var): relative error of the estimate */
+  double n_eff;      /* sum w / max w, App. B Eq. (neff) */
+  double n_ess;      /* (sum w)^2 / sum w^2, App. B Eq. (neff_ESS) */
+  double n_var;      /* N wbar^2 / s^2 (unbiased s^2), App. B variance-based size */
+  double max_lnw;    /* largest finite ln w */
+  int64_t n;         /* finite samples counted */
+  int64_t n_nonfinite;
+} rift_ile_result;
+
+typedef struct {
+  uint64_t seed;              /* Philox key */
+  int64_t n_per_round;        /* samples per point per round; ignored if n_per_point */
+  const int64_t *n_per_point; /* host [n_points] or NULL */
+  int n_rounds;               /* >= 1 */
+  unsigned adapt_mask;        /* bit d: adapt parameter d between rounds (0: prior only) */
+  double floor_eps;           /* uniform floor mixed into each adapted histogram, (0, 1] */
+  int reset_proposal;         /* 1: start from the prior (else from the current tables) */
+} rift_ile_mc;
+
+/* Create a handle for desc->n_points points on the current HIP device.
+ * Validates every point (shapes, finiteness, Hermitian U, symmetric V, pad
+ * large enough), then deep-copies Q/U/V into library-owned device memory in
+ * the kernels' layouts; the caller may free its inputs once this returns.
+ * stream: a hipStream_t (NULL = the null stream) used by every later call.
+ * Errors: RIFT_E_INVALID, RIFT_E_SHAPE, RIFT_E_NOT_HERMITIAN, RIFT_E_WINDOW,
+ * RIFT_E_NONFINITE, RIFT_E_OOM, RIFT_E_DEVICE.  On error *out is NULL. */
+rift_status rift_ile_create(rift_ile **out, const rift_ile_desc *desc, void *stream);
+
+/* Release the handle and its device memory (synchronizes its stream). */
+void rift_ile_destroy(rift_ile *h);
+
+/* Text of the last error on h (or of the last failed create when h is NULL). */
+const char *rift_ile_last_error(const rift_ile *h);
+const char *rift_ile_status_string(rift_status s);
+int rift_ile_abi_version(void);
+
+/* Diagnostics: time the dominant evaluation kernel (the persistent matrix-
+ * core kernel, or the plain kernel) with HIP events on the handle's stream.
+ * Returns, in *ms_total and *launches, the summed duration and the count of
+ * the launches timed since the previous call (synchronizing if there were
+ * any), then enables (enable != 0) or disables timing.  Either output may be
+ * NULL. */
+rift_status rift_ile_profile(rift_ile *h, int enable, double *ms_total, int64_t *launches);
+
+/* Rebind the handle to another stream. */
+rift_status rift_ile_set_stream(rift_ile *h, void *stream);
+
+/* Extrinsic sample draw (Sec. II.A; Sec. III.B: random numbers generated on
+ * the GPU).  Writes samples first..first+n-1 of (point, round): Philox4x32-10
+ * with key = seed and counter = (i_lo, i_hi, 2 round + half, point); each
+ * parameter takes one 32-bit word, mapped through the prior's inverse CDF or,
+ * for a parameter adapted in the point's proposal, through its 100-bin
+ * histogram.  theta: device [7][n]; ln_ratio: device [n] (handle precision)
+ * receives ln p - ln p_s (or NULL); bins: device uint8 [7][n] receives each
+ * sample's histogram bin per parameter (or NULL).  Asynchronous. */
+rift_status rift_ile_sample(rift_ile *h, int point, uint64_t seed, uint32_t round, int64_t first,
+                            int64_t n, void *theta, void *ln_ratio, uint8_t *bins);
+
+/* Time-marginalized log-likelihood (App. D Eq. (def:lnL:Decomposed), window
+ * log-sum-exp of App. D.2): for every item, columns offset..offset+count-1 of
+ * theta are evaluated against the item's point and
+ *   ln L_t = ln[(1/n_t) sum_j exp(ell_j)]
+ * is written to the same columns of lnL_t.  theta: device [7][stride];
+ * lnL_t: device [stride].  items: host [n_items].  Asynchronous. */
+rift_status rift_ile_lnL(rift_ile *h, int n_items, const rift_ile_item *items, int64_t stride,
+                         const void *theta, void *lnL_t);
+
+/* FP64 Monte Carlo reduction (Sec. II.A Eq. (lnL:MonteCarlo), App. B) of
+ * ln w_i = ln L_t,i + ln_ratio_i over n samples.  lnL_t and ln_ratio:
+ * device [n] in the handle's precision (ln_ratio may be NULL: 0).
+ * Synchronizes and writes *out on the host. */
+rift_status rift_ile_reduce(rift_ile *h, int64_t n, const void *lnL_t, const void *ln_ratio,
+                            rift_ile_result *out);
+
+/* Adapt the point's proposal (Sec. III.B): FP64 weighted 100-bin histograms of
+ * w = exp(ln w - max ln w) over each masked parameter's prior-CDF coordinate,
+ * mixed with a uniform floor:  h_b = (1 - eps) 100 m_b / sum m + eps.
+ * bins: device uint8 [7][n] (as written by rift_ile_sample); lnw: device
+ * [n] in the handle's precision.  Weights are accumulated as 40-bit fixed
+ * point, so n is limited to 2^23.  Parameters outside mask revert to the
+ * prior.  Asynchronous. */
+rift_status rift_ile_adapt(rift_ile *h, int point, int64_t n, const uint8_t *bins, const void *lnw,
+                           unsigned mask, double floor_eps);
+
+/* Read / replace a point's proposal: cdf host [7][101] bin edges of the
+ * prior-CDF coordinate (cdf[d][0] = 0, cdf[d][100] = 1, nondecreasing with
+ * positive steps), mask as in rift_ile_adapt.  get synchronizes. */
+rift_status rift_ile_get_proposal(rift_ile *h, int point, double *cdf, unsigned *mask);
+rift_status rift_ile_set_proposal(rift_ile *h, int point, const double *cdf, unsigned mask);
+
+/* The whole step for every point: for each round, draw samples from the
+ * current proposal, evaluate ln L_t, form ln w, fold them into a pooled FP64
+ * estimate over all rounds (each sample weighted with its own round's p_s),
+ * and, between rounds, adapt the masked parameters' histograms from that
+ * round's weights.  All points run together in each launch.  out: host
+ * [n_points].  theta_out (device [7][total]) and lnw_out (device [total]),
+ * both in the handle's precision, if not NULL, receive every sample in
+ * (round, point, sample) order, total = n_rounds * sum of per-point counts.
+ * Per-point counts per round are limited to 2^23 when adapting.
+ * Synchronizes. */
+rift_status rift_ile_marginalize(rift_ile *h, const rift_ile_mc *mc, rift_ile_result *out,
+                                 void *theta_out, void *lnw_out);
+
+/* Gradient of ln L_t with respect to the seven parameters, through the
+ * antenna patterns F_k(alpha, delta, psi), the delays dt_k(alpha, delta) and
+ * tau (via the Catmull-Rom derivative of Q), the harmonics Y_lm(iota, phi) and
+ * the distance.  grad_theta[d][i] = g_i d ln L_t,i / d theta_d with
+ * g = grad_lnL_t (device [stride], or NULL for 1).  lnL_t_out (device
+ * [stride] or NULL) receives ln L_t.  Same items/stride/layout as
+ * rift_ile_lnL.  Asynchronous. */
+rift_status rift_ile_backward(rift_ile *h, int n_items, const rift_ile_item *items, int64_t stride,
+                              const void *theta, const void *grad_lnL_t, void *grad_theta,
+                              void *lnL_t_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

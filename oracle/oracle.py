@@ -68,6 +68,10 @@ def lib():
     return _lib
 
 
+def threads():
+    return lib().or_threads()
+
+
 def _ptr(a):
     return a.ctypes.data_as(_dp) if a is not None else None
 

@@ -23,6 +23,13 @@
 
 int or_rows(const or_point *p) { return p->n_t + 2 * p->pad + 3; }
 
+#ifdef _OPENMP
+#include <omp.h>
+int or_threads(void) { return omp_get_max_threads(); }
+#else
+int or_threads(void) { return 1; }
+#endif
+
 /* ------------------------------------------------------------------------
  * Geometry.  The paper says only that L_full accounts for the detector
  * response and that Q_k is evaluated at the detector's arrival time t_k

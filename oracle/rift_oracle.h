@@ -52,6 +52,7 @@ typedef struct {
 } or_result;
 
 int or_rows(const or_point *p);
+int or_threads(void); /* OpenMP threads the batch routines use */
 
 /* geometry -------------------------------------------------------------- */
 void or_direction(double alpha, double delta, double gmst, double n[3]);

@@ -1,0 +1,109 @@
+// Launch interfaces between the C-ABI host code and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace rift {
+
+// Work description shared by the evaluation kernels: items are segments of
+// a sample array against one point; tiles are fixed-size runs of samples.
+struct ItemsDev {
+  const int *point;     // [n_items]
+  const int64_t *off;   // [n_items] first column
+  const int64_t *cnt;   // [n_items]
+  const int *tile0;     // [n_items + 1] prefix of plain tiles
+  const int64_t *samp0; // [n_items + 1] prefix of sample counts (flat index space)
+  const int *bin0;      // [n_items + 1] prefix of delay bins
+  int n_items;
+};
+
+template <typename R>
+struct PlainArgsT {
+  const PointDev *pts;
+  const int *item_point;
+  const int64_t *item_off, *item_cnt;
+  const int *item_tile0;
+  int n_items;
+  int64_t stride;
+  const R *theta;       // [7][stride]
+  R *lnL;               // [stride] or null
+  R *lnw;               // [stride] or null: ln L_t + ln_ratio
+  const R *ln_ratio;
+  const R *gin;         // adjoint: upstream gradient [stride] or null (1)
+  R *grad;              // adjoint: [7][stride]
+  int rows_cap, nt_cap;
+};
+
+template <typename R>
+hipError_t plain_launch(const PlainArgsT<R> &a, int TS, int n_tiles, bool bwd, hipStream_t st,
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+size_t plain_lds_bytes(int elem, int TS, int rows_cap, int nt_cap, bool bwd);
+
+// ---- FP32 MFMA path -------------------------------------------------------
+struct MfmaArgs {
+  const PointDev *pts;
+  ItemsDev items;
+  int64_t stride;
+  int64_t total;          // flat samples over all items
+  const float *theta;     // [7][stride]
+  float *lnL;             // [stride] or null
+  float *lnw;             // [stride] or null
+  const float *ln_ratio;  // [stride] or null
+  // workspace
+  uint32_t *key;          // [total] global bin of each flat sample
+  int16_t *nsh;           // [total][4] integer row offsets n_k (index 3: valid flag)
+  uint32_t *count;        // [n_bins]
+  uint32_t *cursor;       // [n_bins]
+  uint32_t *bin_pos;      // [n_bins] first sorted position of the bin (flat)
+  uint32_t *bin_tile;     // [n_bins] first tile of the bin
+  uint32_t *item_tiles;   // [n_items + 1] tile prefix over items (filled on device)
+  uint32_t *perm;         // [total] sorted position -> flat sample index
+  uint4 *tiles;           // [max_tiles] (item, sorted start, count, -)
+  uint32_t *ctl;          // [0]: tile counter, [1]: number of tiles
+  int n_bins;
+  int max_tiles;
+  int grid;               // persistent workgroups
+};
+
+// ev0/ev1 (or null): recorded around the persistent evaluation kernel
+hipError_t mfma_forward(const MfmaArgs &a, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
+// ---- sampler / reductions / adaptation -------------------------------------
+struct ProposalDev {
+  double cdf[7][kNB + 1];
+  unsigned mask;
+  unsigned pad_;
+};
+
+template <typename R>
+hipError_t sample_launch(const PointDev *pts, const ProposalDev *prop, int point, uint64_t seed, uint32_t round,
+                         int64_t first, int64_t n, int64_t stride, int64_t bin_stride, double d_min, double d_max,
+                         double tau_width, R *theta, R *ln_ratio, uint8_t *bins, hipStream_t st);
+
+struct ReduceTuple {
+  double m, s1, s2;
+  long long n, bad;
+  double pad_;
+};
+
+// per-segment partial tuples: partials[seg * bps + j]
+template <typename R>
+hipError_t reduce_partials(const R *lnL, const R *ln_ratio, const int64_t *seg_off, const int64_t *seg_cnt,
+                           int n_seg, int bps, ReduceTuple *partials, hipStream_t st);
+// merge each segment's partials in order; round_out (or null) receives the
+// segment tuple, accum (or null) is replaced by (accumulate ? accum + t : t),
+// out (or null) receives the result of accum (or of t without accum)
+hipError_t reduce_finish(const ReduceTuple *partials, int n_seg, int bps, ReduceTuple *round_out,
+                         ReduceTuple *accum, int accumulate, rift_ile_result *out, hipStream_t st);
+
+template <typename R>
+hipError_t adapt_launch(const uint8_t *bins, int64_t bin_stride, const R *lnw, const int64_t *seg_off,
+                        const int64_t *seg_cnt, const int *seg_prop, int n_seg, int bps,
+                        const ReduceTuple *seg_round, unsigned long long *hist, ProposalDev *props,
+                        unsigned mask, double floor_eps, hipStream_t st);
+
+hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+
+}  // namespace rift

@@ -1,0 +1,318 @@
+// Monte Carlo layer: on-device sampling (Sec. III.B: random numbers and the
+// likelihood both stay on the GPU), the FP64 importance-sampling reduction
+// (Sec. II.A Eq. (lnL:MonteCarlo); n_eff, n_ESS, n_var of App. B) and the
+// adaptive 100-bin histogram proposal (Sec. III.B).
+//
+// Reductions are deterministic: every block reduces a fixed range of samples
+// in a fixed order into (max, sum e^{x-max}, sum e^{2(x-max)}) tuples, and the
+// tuples of a segment are merged in index order.  Histograms accumulate
+// fixed-point weights with 64-bit integer atomics, which are associative.
+#include "common.h"
+#include "internal.h"
+
+namespace rift {
+
+// ---------------------------------------------------------------------------
+// sampler
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double u01(uint32_t x) { return ((double)(x >> 8) + 0.5) * (1.0 / 16777216.0); }
+
+// Prior inverse CDFs u -> theta, evaluated in FP64 and rounded once to the
+// bulk precision: asin/acos are ill-conditioned near the poles, where FP32
+// evaluation would move the drawn angle by far more than its own rounding.
+template <typename R>
+__device__ __forceinline__ R prior_inv(int d, double u, double d_min, double d_max, double tw) {
+  double t;
+  switch (d) {
+    case RIFT_ALPHA: t = 2.0 * kPi * u; break;
+    case RIFT_DELTA: t = asin(2.0 * u - 1.0); break;
+    case RIFT_PSI: t = kPi * u; break;
+    case RIFT_IOTA: t = acos(2.0 * u - 1.0); break;
+    case RIFT_PHI: t = 2.0 * kPi * u; break;
+    case RIFT_DIST: {
+      double a3 = d_min * d_min * d_min, b3 = d_max * d_max * d_max;
+      t = cbrt(a3 + u * (b3 - a3));
+      break;
+    }
+    default: t = (u - 0.5) * tw;
+  }
+  return (R)t;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) sample_kernel(const ProposalDev *prop, uint32_t point, uint64_t seed,
+                                                     uint32_t round, int64_t first, int64_t n, int64_t stride,
+                                                     int64_t bin_stride, double d_min, double d_max, double tau_width,
+                                                     R *theta, R *ln_ratio, uint8_t *bins) {
+  __shared__ double cdf[7][kNB + 1];
+  __shared__ unsigned mask;
+  for (int i = threadIdx.x; i < 7 * (kNB + 1); i += blockDim.x) cdf[i / (kNB + 1)][i % (kNB + 1)] = prop->cdf[i / (kNB + 1)][i % (kNB + 1)];
+  if (threadIdx.x == 0) mask = prop->mask;
+  __syncthreads();
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  uint64_t i = (uint64_t)(first + j);
+  uint32_t r[8];
+  for (int half = 0; half < 2; half++) {
+    uint32_t c[4] = {(uint32_t)i, (uint32_t)(i >> 32), 2u * round + (uint32_t)half, point};
+    philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    for (int q = 0; q < 4; q++) r[4 * half + q] = c[q];
+  }
+  double lr = 0.0;
+#pragma unroll
+  for (int d = 0; d < 7; d++) {
+    double v = u01(r[d]);
+    double u = v;
+    // bin of the raw uniform: floor(v nb), exactly, in integers
+    uint32_t bin = (uint32_t)((((uint64_t)(r[d] >> 8) * 2u + 1u) * kNB) >> 25);
+    if ((mask >> d) & 1u) {
+      int lo = 0, hi = kNB;
+      while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (cdf[d][mid] <= v) lo = mid; else hi = mid;
+      }
+      double mass = cdf[d][lo + 1] - cdf[d][lo];
+      u = ((double)lo + (v - cdf[d][lo]) / mass) / kNB;
+      lr -= log(mass * kNB);
+      bin = (uint32_t)lo;
+    }
+    theta[d * stride + j] = prior_inv<R>(d, u, d_min, d_max, tau_width);
+    if (bins) bins[d * bin_stride + j] = (uint8_t)bin;
+  }
+  if (ln_ratio) ln_ratio[j] = (R)lr;
+}
+
+template <typename R>
+hipError_t sample_launch(const PointDev *, const ProposalDev *prop, int point, uint64_t seed, uint32_t round,
+                         int64_t first, int64_t n, int64_t stride, int64_t bin_stride, double d_min, double d_max,
+                         double tau_width, R *theta, R *ln_ratio, uint8_t *bins, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sample_kernel<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, prop, (uint32_t)point,
+                     seed, round, first, n, stride, bin_stride, d_min, d_max, tau_width, theta, ln_ratio, bins);
+  return hipGetLastError();
+}
+template hipError_t sample_launch<float>(const PointDev *, const ProposalDev *, int, uint64_t, uint32_t, int64_t,
+                                         int64_t, int64_t, int64_t, double, double, double, float *, float *,
+                                         uint8_t *, hipStream_t);
+template hipError_t sample_launch<double>(const PointDev *, const ProposalDev *, int, uint64_t, uint32_t, int64_t,
+                                          int64_t, int64_t, int64_t, double, double, double, double *, double *,
+                                          uint8_t *, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// FP64 reduction
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void tup_add(ReduceTuple &t, double x) {
+  if (!(x == x) || x == INFINITY) {  // NaN or +inf
+    t.bad++;
+    return;
+  }
+  t.n++;
+  if (x == -INFINITY) return;
+  if (x > t.m) {
+    double e = exp(t.m - x);  // 0 when t.m = -inf
+    t.s1 = t.s1 * e + 1.0;
+    t.s2 = t.s2 * e * e + 1.0;
+    t.m = x;
+  } else {
+    double e = exp(x - t.m);
+    t.s1 += e;
+    t.s2 += e * e;
+  }
+}
+
+__device__ __forceinline__ ReduceTuple tup_merge(const ReduceTuple &a, const ReduceTuple &b) {
+  ReduceTuple r;
+  r.n = a.n + b.n;
+  r.bad = a.bad + b.bad;
+  r.pad_ = 0.0;
+  r.m = fmax(a.m, b.m);
+  if (r.m == -INFINITY) {
+    r.s1 = r.s2 = 0.0;
+    return r;
+  }
+  double ea = a.m == -INFINITY ? 0.0 : exp(a.m - r.m);
+  double eb = b.m == -INFINITY ? 0.0 : exp(b.m - r.m);
+  r.s1 = a.s1 * ea + b.s1 * eb;
+  r.s2 = a.s2 * ea * ea + b.s2 * eb * eb;
+  return r;
+}
+
+__device__ __forceinline__ ReduceTuple tup_zero() {
+  ReduceTuple t;
+  t.m = -INFINITY;
+  t.s1 = t.s2 = 0.0;
+  t.n = t.bad = 0;
+  t.pad_ = 0.0;
+  return t;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) reduce_partials_kernel(const R *lnL, const R *ln_ratio, const int64_t *seg_off,
+                                                              const int64_t *seg_cnt, int bps, ReduceTuple *partials) {
+  __shared__ ReduceTuple sh[256];
+  const int seg = blockIdx.x / bps, j = blockIdx.x % bps;
+  const int64_t cnt = seg_cnt[seg], off = seg_off[seg];
+  const int64_t chunk = (cnt + bps - 1) / bps;
+  const int64_t lo = min(cnt, (int64_t)j * chunk), hi = min(cnt, lo + chunk);
+  ReduceTuple t = tup_zero();
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+    double x = (double)lnL[off + i];
+    if (ln_ratio) x += (double)ln_ratio[off + i];
+    tup_add(t, x);
+  }
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] = tup_merge(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+
+template <typename R>
+hipError_t reduce_partials(const R *lnL, const R *ln_ratio, const int64_t *seg_off, const int64_t *seg_cnt,
+                           int n_seg, int bps, ReduceTuple *partials, hipStream_t st) {
+  if (n_seg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_partials_kernel<R>, dim3(n_seg * bps), dim3(256), 0, st, lnL, ln_ratio, seg_off, seg_cnt,
+                     bps, partials);
+  return hipGetLastError();
+}
+template hipError_t reduce_partials<float>(const float *, const float *, const int64_t *, const int64_t *, int, int,
+                                           ReduceTuple *, hipStream_t);
+template hipError_t reduce_partials<double>(const double *, const double *, const int64_t *, const int64_t *, int,
+                                            int, ReduceTuple *, hipStream_t);
+
+__device__ void tuple_result(const ReduceTuple &t, rift_ile_result &o) {
+  o.n = t.n;
+  o.n_nonfinite = t.bad;
+  o.max_lnw = t.m;
+  if (t.n == 0 || t.m == -INFINITY || !(t.s1 > 0.0)) {
+    o.lnL_marg = -INFINITY;
+    o.n_eff = o.n_ess = o.n_var = 0.0;
+    o.sigma_lnL = INFINITY;
+    return;
+  }
+  double N = (double)t.n;
+  o.lnL_marg = t.m + log(t.s1) - log(N);
+  o.n_eff = t.s1;
+  o.n_ess = t.s1 * t.s1 / t.s2;
+  double wbar = t.s1 / N;
+  double var = t.n > 1 ? (t.s2 - N * wbar * wbar) / (N - 1.0) : 0.0;
+  if (var <= 0.0) {
+    o.n_var = INFINITY;
+    o.sigma_lnL = 0.0;
+  } else {
+    o.n_var = N * wbar * wbar / var;
+    o.sigma_lnL = 1.0 / sqrt(o.n_var);
+  }
+}
+
+__global__ void reduce_finish_kernel(const ReduceTuple *partials, int n_seg, int bps, ReduceTuple *round_out,
+                                     ReduceTuple *accum, int accumulate, rift_ile_result *out) {
+  int seg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (seg >= n_seg) return;
+  ReduceTuple t = tup_zero();
+  for (int j = 0; j < bps; j++) t = tup_merge(t, partials[seg * bps + j]);
+  if (round_out) round_out[seg] = t;
+  if (accum) {
+    ReduceTuple a = accumulate ? tup_merge(accum[seg], t) : t;
+    accum[seg] = a;
+    t = a;
+  }
+  if (out) tuple_result(t, out[seg]);
+}
+
+hipError_t reduce_finish(const ReduceTuple *partials, int n_seg, int bps, ReduceTuple *round_out, ReduceTuple *accum,
+                         int accumulate, rift_ile_result *out, hipStream_t st) {
+  if (n_seg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_finish_kernel, dim3((n_seg + 63) / 64), dim3(64), 0, st, partials, n_seg, bps, round_out,
+                     accum, accumulate, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// adaptation: fixed-point weighted histograms (w = e^{ln w - max} <= 1 scaled
+// by 2^40; sums of up to 2^23 samples fit in 64 bits), then CDF tables
+// ---------------------------------------------------------------------------
+constexpr double kFix = 1099511627776.0;  // 2^40
+
+template <typename R>
+__global__ void __launch_bounds__(256) hist_kernel(const uint8_t *bins, int64_t bin_stride, const R *lnw,
+                                                   const int64_t *seg_off, const int64_t *seg_cnt, int bps,
+                                                   const ReduceTuple *seg_round, unsigned long long *hist) {
+  __shared__ unsigned long long h[7 * kNB];
+  for (int i = threadIdx.x; i < 7 * kNB; i += 256) h[i] = 0ull;
+  __syncthreads();
+  const int seg = blockIdx.x / bps, j = blockIdx.x % bps;
+  const int64_t cnt = seg_cnt[seg], off = seg_off[seg];
+  const int64_t chunk = (cnt + bps - 1) / bps;
+  const int64_t lo = min(cnt, (int64_t)j * chunk), hi = min(cnt, lo + chunk);
+  const double mx = seg_round[seg].m;
+  if (mx > -INFINITY) {
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+      double x = (double)lnw[off + i];
+      if (!(x == x) || x == INFINITY || x == -INFINITY) continue;
+      unsigned long long q = (unsigned long long)llrint(exp(x - mx) * kFix);
+      if (q == 0ull) continue;
+      for (int d = 0; d < 7; d++) atomicAdd(&h[d * kNB + bins[d * bin_stride + off + i]], q);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 7 * kNB; i += 256)
+    if (h[i]) atomicAdd(&hist[(size_t)seg * 7 * kNB + i], h[i]);
+}
+
+__global__ void cdf_kernel(const unsigned long long *hist, const int *seg_prop, int n_seg, ProposalDev *props,
+                           unsigned mask, double floor_eps) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_seg * 7) return;
+  int seg = idx / 7, d = idx % 7;
+  ProposalDev &P = props[seg_prop[seg]];
+  const unsigned long long *hh = hist + (size_t)seg * 7 * kNB + d * kNB;
+  double tot = 0.0;
+  for (int b = 0; b < kNB; b++) tot += (double)hh[b];
+  bool adapt = ((mask >> d) & 1u) && tot > 0.0;
+  double c = 0.0;
+  P.cdf[d][0] = 0.0;
+  for (int b = 0; b < kNB; b++) {
+    double hb = adapt ? (1.0 - floor_eps) * kNB * ((double)hh[b] / tot) + floor_eps : 1.0;
+    c += hb / kNB;
+    P.cdf[d][b + 1] = c;
+  }
+  for (int b = 1; b <= kNB; b++) P.cdf[d][b] /= c;
+  if (d == 0) P.mask = mask;
+}
+
+template <typename R>
+hipError_t adapt_launch(const uint8_t *bins, int64_t bin_stride, const R *lnw, const int64_t *seg_off,
+                        const int64_t *seg_cnt, const int *seg_prop, int n_seg, int bps, const ReduceTuple *seg_round,
+                        unsigned long long *hist, ProposalDev *props, unsigned mask, double floor_eps, hipStream_t st) {
+  if (n_seg <= 0) return hipSuccess;
+  hipError_t e = fill_u32((uint32_t *)hist, (int64_t)2 * 7 * kNB * n_seg, 0u, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(hist_kernel<R>, dim3(n_seg * bps), dim3(256), 0, st, bins, bin_stride, lnw, seg_off, seg_cnt, bps,
+                     seg_round, hist);
+  hipLaunchKernelGGL(cdf_kernel, dim3((n_seg * 7 + 63) / 64), dim3(64), 0, st, hist, seg_prop, n_seg, props, mask,
+                     floor_eps);
+  return hipGetLastError();
+}
+template hipError_t adapt_launch<float>(const uint8_t *, int64_t, const float *, const int64_t *, const int64_t *,
+                                        const int *, int, int, const ReduceTuple *, unsigned long long *,
+                                        ProposalDev *, unsigned, double, hipStream_t);
+template hipError_t adapt_launch<double>(const uint8_t *, int64_t, const double *, const int64_t *, const int64_t *,
+                                         const int *, int, int, const ReduceTuple *, unsigned long long *,
+                                         ProposalDev *, unsigned, double, hipStream_t);
+
+// ---------------------------------------------------------------------------
+__global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace rift

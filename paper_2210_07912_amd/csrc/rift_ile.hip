@@ -1,0 +1,797 @@
+// Host side of the C ABI declared in include/rift_ile.h: argument checks,
+// device layouts of the per-point data, workspace management and the order
+// of kernel launches for each entry point.  No exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "internal.h"
+
+using namespace rift;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t n = 0;
+};
+
+}  // namespace
+
+struct rift_ile {
+  int precision = RIFT_FP32;
+  unsigned flags = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  int n_points = 0;
+  double d_min = 10.0, d_max = 1000.0, tau_width = 0.0;
+  std::vector<PointDev> hp;       // host copies (device pointers inside)
+  std::vector<void *> owned;      // per-point allocations
+  PointDev *d_pts = nullptr;
+  ProposalDev *d_props = nullptr;
+  int max_L = 0, max_nt = 0;
+  int n_cu = 0;
+  int lds_max = 65536;
+  // grow-only workspace, indexed by name
+  DevBuf ws[32];
+  // optional timing of the dominant evaluation kernel
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+};
+
+namespace {
+
+enum WsId {
+  W_ITEM_POINT, W_ITEM_OFF, W_ITEM_CNT, W_ITEM_TILE0, W_ITEM_SAMP0, W_ITEM_BIN0,
+  W_KEY, W_NSH, W_COUNT, W_CURSOR, W_BINPOS, W_BINTILE, W_ITEMTILES, W_PERM, W_TILES, W_CTL,
+  W_PARTIALS, W_ROUND, W_ACCUM, W_RESULT, W_HIST, W_THETA, W_LNW, W_AUX, W_RATIO, W_BINS
+};
+
+rift_status fail(rift_ile *h, rift_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (h) h->err = buf; else g_create_error = buf;
+  return s;
+}
+
+rift_status hip_fail(rift_ile *h, hipError_t e, const char *what) {
+  return fail(h, e == hipErrorOutOfMemory ? RIFT_E_OOM : RIFT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(h, expr)                                   \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return hip_fail((h), e_, #expr); \
+  } while (0)
+
+rift_status ws_get(rift_ile *h, WsId id, size_t bytes, void **out) {
+  DevBuf &b = h->ws[id];
+  if (bytes == 0) bytes = 16;
+  if (b.n < bytes) {
+    if (b.p) {
+      hipError_t e = hipStreamSynchronize(h->stream);
+      if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+      (void)hipFree(b.p);
+      b.p = nullptr;
+      b.n = 0;
+    }
+    size_t want = bytes + bytes / 4;
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(h, RIFT_E_OOM, "workspace allocation of %zu bytes failed", want);
+    }
+    b.n = want;
+  }
+  *out = b.p;
+  return RIFT_OK;
+}
+
+template <typename T>
+rift_status upload(rift_ile *h, WsId id, const std::vector<T> &v, T **out) {
+  void *p;
+  rift_status s = ws_get(h, id, sizeof(T) * std::max<size_t>(v.size(), 1), &p);
+  if (s != RIFT_OK) return s;
+  if (!v.empty()) HIPCHK(h, hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, h->stream));
+  *out = (T *)p;
+  return RIFT_OK;
+}
+
+double factorial(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; i++) f *= i;
+  return f;
+}
+
+bool finite_all(const double *p, size_t n) {
+  for (size_t i = 0; i < n; i++)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+// Wigner-d sum for spin weight -2 (Goldberg et al. 1967): term k has
+// coefficient (-1)^k sqrt((l+m)!(l-m)!(l+2)!(l-2)!) / ((l+m-k)!(l-2-k)! k! (k+2-m)!)
+// and powers cos(iota/2)^(2l+m-2-2k), sin(iota/2)^(2k+2-m).
+void harmonic_table(PointDev &p, int m_idx, int l, int m) {
+  int kmin = std::max(0, m - 2), kmax = std::min(l + m, l - 2);
+  double nrm = std::sqrt(factorial(l + m) * factorial(l - m) * factorial(l + 2) * factorial(l - 2));
+  int n = 0;
+  for (int k = kmin; k <= kmax; k++, n++) {
+    double den = factorial(l + m - k) * factorial(l - 2 - k) * factorial(k) * factorial(k + 2 - m);
+    p.ycoef[m_idx][n] = ((k & 1) ? -1.0 : 1.0) * nrm / den;
+    p.ypc[m_idx][n] = 2 * l + m - 2 - 2 * k;
+    p.yps[m_idx][n] = 2 * k + 2 - m;
+  }
+  p.nterm[m_idx] = n;
+  p.ynorm[m_idx] = std::sqrt((2.0 * l + 1.0) / (4.0 * kPi));
+  p.em[m_idx] = m;
+}
+
+rift_status check_point(const rift_ile_point &q, int idx, double tau_width) {
+  if (q.n_det < 1 || q.n_det > RIFT_MAX_DET)
+    return fail(nullptr, RIFT_E_SHAPE, "point %d: n_det=%d outside 1..%d", idx, q.n_det, RIFT_MAX_DET);
+  if (q.n_modes < 1 || q.n_modes > RIFT_MAX_MODES)
+    return fail(nullptr, RIFT_E_SHAPE, "point %d: n_modes=%d outside 1..%d", idx, q.n_modes, RIFT_MAX_MODES);
+  if (q.n_t < 1 || q.n_t > (1 << 20)) return fail(nullptr, RIFT_E_SHAPE, "point %d: n_t=%d", idx, q.n_t);
+  if (q.pad < 0 || q.pad > (1 << 16)) return fail(nullptr, RIFT_E_SHAPE, "point %d: pad=%d", idx, q.pad);
+  if (!q.ell || !q.em || !q.det_pos || !q.det_resp || !q.Q || !q.U)
+    return fail(nullptr, RIFT_E_INVALID, "point %d: NULL array", idx);
+  for (int m = 0; m < q.n_modes; m++)
+    if (q.ell[m] < 2 || q.ell[m] > 8 || q.em[m] < -q.ell[m] || q.em[m] > q.ell[m])
+      return fail(nullptr, RIFT_E_INVALID, "point %d: mode %d = (%d,%d) unsupported", idx, m, q.ell[m], q.em[m]);
+  if (!(q.f_s > 0) || !std::isfinite(q.f_s) || !(q.d_ref > 0) || !std::isfinite(q.d_ref) || !std::isfinite(q.gmst))
+    return fail(nullptr, RIFT_E_NONFINITE, "point %d: f_s, d_ref or gmst invalid", idx);
+  const int K = q.n_det, M = q.n_modes;
+  const size_t L = (size_t)q.n_t + 2 * (size_t)q.pad + 3;
+  if (!finite_all(q.det_pos, 3 * K) || !finite_all(q.det_resp, 9 * K))
+    return fail(nullptr, RIFT_E_NONFINITE, "point %d: detector constants not finite", idx);
+  if (!finite_all(q.Q, 2 * (size_t)K * L * M)) return fail(nullptr, RIFT_E_NONFINITE, "point %d: Q not finite", idx);
+  if (!finite_all(q.U, 2 * (size_t)K * M * M)) return fail(nullptr, RIFT_E_NONFINITE, "point %d: U not finite", idx);
+  if (q.V && !finite_all(q.V, 2 * (size_t)K * M * M))
+    return fail(nullptr, RIFT_E_NONFINITE, "point %d: V not finite", idx);
+  for (int k = 0; k < K; k++) {
+    const double *U = q.U + 2 * (size_t)k * M * M;
+    double mx = 0.0;
+    for (int i = 0; i < M * M; i++) mx = std::max(mx, std::hypot(U[2 * i], U[2 * i + 1]));
+    for (int i = 0; i < M; i++)
+      for (int j = 0; j < M; j++) {
+        const double *a = U + 2 * (i * M + j), *b = U + 2 * (j * M + i);
+        if (std::fabs(a[0] - b[0]) > 1e-6 * mx || std::fabs(a[1] + b[1]) > 1e-6 * mx)
+          return fail(nullptr, RIFT_E_NOT_HERMITIAN, "point %d: U_%d not Hermitian at (%d,%d)", idx, k, i, j);
+      }
+    if (q.V) {
+      const double *V = q.V + 2 * (size_t)k * M * M;
+      double vx = 0.0;
+      for (int i = 0; i < M * M; i++) vx = std::max(vx, std::hypot(V[2 * i], V[2 * i + 1]));
+      for (int i = 0; i < M; i++)
+        for (int j = 0; j < M; j++) {
+          const double *a = V + 2 * (i * M + j), *b = V + 2 * (j * M + i);
+          if (std::fabs(a[0] - b[0]) > 1e-6 * vx || std::fabs(a[1] - b[1]) > 1e-6 * vx)
+            return fail(nullptr, RIFT_E_NOT_HERMITIAN, "point %d: V_%d not symmetric at (%d,%d)", idx, k, i, j);
+        }
+    }
+    const double *D = q.det_resp + 9 * k;
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++)
+        if (std::fabs(D[3 * i + j] - D[3 * j + i]) > 1e-9)
+          return fail(nullptr, RIFT_E_INVALID, "point %d: response tensor %d not symmetric", idx, k);
+  }
+  double rmax = 0.0;
+  for (int k = 0; k < K; k++)
+    rmax = std::max(rmax, std::sqrt(q.det_pos[3 * k] * q.det_pos[3 * k] + q.det_pos[3 * k + 1] * q.det_pos[3 * k + 1] +
+                                    q.det_pos[3 * k + 2] * q.det_pos[3 * k + 2]));
+  double need = q.f_s * (rmax / kC + 0.5 * tau_width);
+  if ((double)q.pad < need)
+    return fail(nullptr, RIFT_E_WINDOW, "point %d: pad=%d rows < %.3f needed for light travel time and tau", idx,
+                q.pad, need);
+  return RIFT_OK;
+}
+
+template <typename R>
+rift_status build_point(rift_ile *h, const rift_ile_point &q, PointDev &p) {
+  const int K = q.n_det, M = q.n_modes;
+  std::memset(&p, 0, sizeof(p));
+  p.K = K;
+  p.M = M;
+  p.n_t = q.n_t;
+  p.pad = q.pad;
+  p.L = q.n_t + 2 * q.pad + 3;
+  p.Lpad = p.L + 32;
+  p.f_s = q.f_s;
+  p.d_ref = q.d_ref;
+  p.gmst = q.gmst;
+  p.Mp = (M + 1) & ~1;
+  p.bin_w = 14;
+  p.nq = (2 * q.pad) / p.bin_w + 1;
+  long long nb = 1;
+  for (int k = 0; k < K; k++) nb *= p.nq;
+  p.n_bins_key = (int)std::min<long long>(nb, 1 << 30);
+  for (int k = 0; k < K; k++) {
+    for (int i = 0; i < 3; i++) p.rc[k][i] = q.det_pos[3 * k + i] / kC;
+    for (int i = 0; i < 9; i++) p.D[k][i] = q.det_resp[9 * k + i];
+  }
+  for (int m = 0; m < M; m++) harmonic_table(p, m, q.ell[m], q.em[m]);
+  // U (and V) in FP64, holding the values rounded to the bulk precision
+  std::vector<double> u(2 * (size_t)K * M * M);
+  for (size_t i = 0; i < u.size(); i++) u[i] = (double)(R)q.U[i];
+  void *d;
+  HIPCHK(h, hipMalloc(&d, sizeof(double) * u.size()));
+  h->owned.push_back(d);
+  HIPCHK(h, hipMemcpy(d, u.data(), sizeof(double) * u.size(), hipMemcpyHostToDevice));
+  p.U = (const double *)d;
+  if (q.V) {
+    for (size_t i = 0; i < u.size(); i++) u[i] = (double)(R)q.V[i];
+    HIPCHK(h, hipMalloc(&d, sizeof(double) * u.size()));
+    h->owned.push_back(d);
+    HIPCHK(h, hipMemcpy(d, u.data(), sizeof(double) * u.size(), hipMemcpyHostToDevice));
+    p.V = (const double *)d;
+  }
+  // Q, row layout [K][Lpad][M][2] with zero rows past L
+  {
+    std::vector<R> qv((size_t)K * p.Lpad * M * 2, R(0));
+    for (int k = 0; k < K; k++)
+      for (int r = 0; r < p.L; r++)
+        for (int i = 0; i < 2 * M; i++)
+          qv[((size_t)k * p.Lpad + r) * M * 2 + i] = (R)q.Q[((size_t)k * p.L + r) * M * 2 + i];
+    HIPCHK(h, hipMalloc(&d, sizeof(R) * qv.size()));
+    h->owned.push_back(d);
+    HIPCHK(h, hipMemcpy(d, qv.data(), sizeof(R) * qv.size(), hipMemcpyHostToDevice));
+    p.Q = d;
+  }
+  // Q for the matrix cores (FP32 handles): [K][2 Mp][Lpad], element e = 2m + part
+  if (sizeof(R) == 4) {
+    const int E = 2 * p.Mp;
+    std::vector<float> qm((size_t)K * E * p.Lpad, 0.f);
+    for (int k = 0; k < K; k++)
+      for (int r = 0; r < p.L; r++)
+        for (int e = 0; e < 2 * M; e++)
+          qm[((size_t)k * E + e) * p.Lpad + r] = (float)q.Q[((size_t)k * p.L + r) * M * 2 + e];
+    HIPCHK(h, hipMalloc(&d, sizeof(float) * qm.size()));
+    h->owned.push_back(d);
+    HIPCHK(h, hipMemcpy(d, qm.data(), sizeof(float) * qm.size(), hipMemcpyHostToDevice));
+    p.Qm = (const float *)d;
+  }
+  return RIFT_OK;
+}
+
+void uniform_proposal(ProposalDev &pr) {
+  for (int d = 0; d < 7; d++)
+    for (int b = 0; b <= kNB; b++) pr.cdf[d][b] = (double)b / kNB;
+  pr.mask = 0;
+  pr.pad_ = 0;
+}
+
+// ---- evaluation -------------------------------------------------------------
+struct Items {
+  std::vector<int> point;
+  std::vector<int64_t> off, cnt;
+};
+
+rift_status check_items(rift_ile *h, int n_items, const rift_ile_item *items, int64_t stride) {
+  if (n_items < 0 || (n_items > 0 && !items) || stride < 0) return fail(h, RIFT_E_INVALID, "bad item list");
+  for (int i = 0; i < n_items; i++) {
+    const rift_ile_item &it = items[i];
+    if (it.point < 0 || it.point >= h->n_points) return fail(h, RIFT_E_INVALID, "item %d: point %d", i, it.point);
+    if (it.offset < 0 || it.count < 0 || it.offset + it.count > stride)
+      return fail(h, RIFT_E_INVALID, "item %d: columns [%lld, %lld) outside stride %lld", i, (long long)it.offset,
+                  (long long)(it.offset + it.count), (long long)stride);
+  }
+  return RIFT_OK;
+}
+
+template <typename R>
+rift_status run_plain(rift_ile *h, const Items &it, int64_t stride, const R *theta, R *lnL, R *lnw,
+                      const R *ln_ratio, const R *gin, R *grad, bool bwd) {
+  const int n = (int)it.point.size();
+  int TS = 16;
+  while (TS > 1 && plain_lds_bytes(sizeof(R), TS, h->max_L, h->max_nt, bwd) > (size_t)h->lds_max) TS >>= 1;
+  if (plain_lds_bytes(sizeof(R), TS, h->max_L, h->max_nt, bwd) > (size_t)h->lds_max)
+    return fail(h, RIFT_E_SHAPE, "window too long for the plain kernel's LDS");
+  std::vector<int> tile0(n + 1, 0);
+  for (int i = 0; i < n; i++) tile0[i + 1] = tile0[i] + (int)((it.cnt[i] + TS - 1) / TS);
+  if (tile0[n] == 0) return RIFT_OK;
+  int *d_point, *d_tile0;
+  int64_t *d_off, *d_cnt;
+  rift_status s;
+  if ((s = upload(h, W_ITEM_POINT, it.point, &d_point)) != RIFT_OK) return s;
+  if ((s = upload(h, W_ITEM_OFF, it.off, &d_off)) != RIFT_OK) return s;
+  if ((s = upload(h, W_ITEM_CNT, it.cnt, &d_cnt)) != RIFT_OK) return s;
+  if ((s = upload(h, W_ITEM_TILE0, tile0, &d_tile0)) != RIFT_OK) return s;
+  PlainArgsT<R> a;
+  a.pts = h->d_pts;
+  a.item_point = d_point;
+  a.item_off = d_off;
+  a.item_cnt = d_cnt;
+  a.item_tile0 = d_tile0;
+  a.n_items = n;
+  a.stride = stride;
+  a.theta = theta;
+  a.lnL = lnL;
+  a.lnw = lnw;
+  a.ln_ratio = ln_ratio;
+  a.gin = gin;
+  a.grad = grad;
+  a.rows_cap = h->max_L;
+  a.nt_cap = h->max_nt;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->prof) {
+    HIPCHK(h, hipEventCreate(&e0));
+    HIPCHK(h, hipEventCreate(&e1));
+    h->prof_ev.emplace_back(e0, e1);
+  }
+  HIPCHK(h, plain_launch<R>(a, TS, tile0[n], bwd, h->stream, e0, e1));
+  return RIFT_OK;
+}
+
+rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const float *theta, float *lnL, float *lnw,
+                     const float *ln_ratio) {
+  // costliest points first: the persistent kernel takes tiles in this order
+  const int n = (int)it_in.point.size();
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  auto cost = [&](int i) {
+    const PointDev &p = h->hp[it_in.point[i]];
+    return (double)p.K * (p.Mp + 4) * p.n_t;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  Items it;
+  std::vector<int64_t> samp0(1, 0);
+  std::vector<int> bin0(1, 0);
+  int64_t max_tiles = 0;
+  for (int oi : order) {
+    if (it_in.cnt[oi] == 0) continue;
+    it.point.push_back(it_in.point[oi]);
+    it.off.push_back(it_in.off[oi]);
+    it.cnt.push_back(it_in.cnt[oi]);
+    samp0.push_back(samp0.back() + it_in.cnt[oi]);
+    long long nb = (long long)bin0.back() + h->hp[it_in.point[oi]].n_bins_key;
+    if (nb > (1 << 28)) return fail(h, RIFT_E_SHAPE, "too many delay bins in one call");
+    bin0.push_back((int)nb);
+    max_tiles += (it_in.cnt[oi] + 15) / 16 + h->hp[it_in.point[oi]].n_bins_key;
+  }
+  const int ni = (int)it.point.size();
+  const int64_t total = samp0.back();
+  if (total == 0) return RIFT_OK;
+  if (total >= (int64_t)1 << 31) return fail(h, RIFT_E_SHAPE, "more than 2^31 samples in one call");
+  MfmaArgs a;
+  std::memset(&a, 0, sizeof(a));
+  rift_status s;
+  int *d_point, *d_bin0;
+  int64_t *d_off, *d_cnt, *d_samp0;
+  if ((s = upload(h, W_ITEM_POINT, it.point, &d_point)) != RIFT_OK) return s;
+  if ((s = upload(h, W_ITEM_OFF, it.off, &d_off)) != RIFT_OK) return s;
+  if ((s = upload(h, W_ITEM_CNT, it.cnt, &d_cnt)) != RIFT_OK) return s;
+  if ((s = upload(h, W_ITEM_SAMP0, samp0, &d_samp0)) != RIFT_OK) return s;
+  if ((s = upload(h, W_ITEM_BIN0, bin0, &d_bin0)) != RIFT_OK) return s;
+  a.pts = h->d_pts;
+  a.items.point = d_point;
+  a.items.off = d_off;
+  a.items.cnt = d_cnt;
+  a.items.samp0 = d_samp0;
+  a.items.bin0 = d_bin0;
+  a.items.tile0 = nullptr;
+  a.items.n_items = ni;
+  a.stride = stride;
+  a.total = total;
+  a.theta = theta;
+  a.lnL = lnL;
+  a.lnw = lnw;
+  a.ln_ratio = ln_ratio;
+  a.n_bins = bin0.back();
+  a.max_tiles = (int)std::min<int64_t>(max_tiles, INT32_MAX);
+  void *p;
+  if ((s = ws_get(h, W_KEY, 4 * total, &p)) != RIFT_OK) return s;
+  a.key = (uint32_t *)p;
+  if ((s = ws_get(h, W_NSH, 8 * total, &p)) != RIFT_OK) return s;
+  a.nsh = (int16_t *)p;
+  if ((s = ws_get(h, W_COUNT, 4 * (size_t)a.n_bins, &p)) != RIFT_OK) return s;
+  a.count = (uint32_t *)p;
+  if ((s = ws_get(h, W_CURSOR, 4 * (size_t)a.n_bins, &p)) != RIFT_OK) return s;
+  a.cursor = (uint32_t *)p;
+  if ((s = ws_get(h, W_BINPOS, 4 * (size_t)a.n_bins, &p)) != RIFT_OK) return s;
+  a.bin_pos = (uint32_t *)p;
+  if ((s = ws_get(h, W_BINTILE, 4 * (size_t)a.n_bins, &p)) != RIFT_OK) return s;
+  a.bin_tile = (uint32_t *)p;
+  if ((s = ws_get(h, W_ITEMTILES, 4 * (size_t)(ni + 1), &p)) != RIFT_OK) return s;
+  a.item_tiles = (uint32_t *)p;
+  if ((s = ws_get(h, W_PERM, 4 * total, &p)) != RIFT_OK) return s;
+  a.perm = (uint32_t *)p;
+  if ((s = ws_get(h, W_TILES, 16 * (size_t)a.max_tiles, &p)) != RIFT_OK) return s;
+  a.tiles = (uint4 *)p;
+  if ((s = ws_get(h, W_CTL, 16, &p)) != RIFT_OK) return s;
+  a.ctl = (uint32_t *)p;
+  a.grid = h->n_cu * 4;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->prof) {
+    HIPCHK(h, hipEventCreate(&e0));
+    HIPCHK(h, hipEventCreate(&e1));
+    h->prof_ev.emplace_back(e0, e1);
+  }
+  HIPCHK(h, mfma_forward(a, h->stream, e0, e1));
+  return RIFT_OK;
+}
+
+Items make_items(int n_items, const rift_ile_item *items) {
+  Items it;
+  for (int i = 0; i < n_items; i++) {
+    it.point.push_back(items[i].point);
+    it.off.push_back(items[i].offset);
+    it.cnt.push_back(items[i].count);
+  }
+  return it;
+}
+
+template <typename R>
+rift_status eval(rift_ile *h, const Items &it, int64_t stride, const R *theta, R *lnL, R *lnw, const R *ln_ratio) {
+  if (sizeof(R) == 4 && !(h->flags & 1u))
+    return run_mfma(h, it, stride, (const float *)theta, (float *)lnL, (float *)lnw, (const float *)ln_ratio);
+  return run_plain<R>(h, it, stride, theta, lnL, lnw, ln_ratio, nullptr, nullptr, false);
+}
+
+template <typename R>
+rift_status reduce_segments(rift_ile *h, const R *lnL, const R *ln_ratio, const std::vector<int64_t> &off,
+                            const std::vector<int64_t> &cnt, ReduceTuple **round_out, ReduceTuple *accum,
+                            int accumulate, rift_ile_result *d_out) {
+  const int ns = (int)off.size();
+  int64_t mx = 1;
+  for (auto c : cnt) mx = std::max(mx, c);
+  int bps = (int)std::min<int64_t>(256, (mx + 8191) / 8192);
+  int64_t *d_off, *d_cnt;
+  rift_status s;
+  if ((s = upload(h, W_ITEM_OFF, off, &d_off)) != RIFT_OK) return s;
+  if ((s = upload(h, W_ITEM_CNT, cnt, &d_cnt)) != RIFT_OK) return s;
+  void *pp, *pr;
+  if ((s = ws_get(h, W_PARTIALS, sizeof(ReduceTuple) * (size_t)ns * bps, &pp)) != RIFT_OK) return s;
+  if ((s = ws_get(h, W_ROUND, sizeof(ReduceTuple) * (size_t)ns, &pr)) != RIFT_OK) return s;
+  HIPCHK(h, reduce_partials<R>(lnL, ln_ratio, d_off, d_cnt, ns, bps, (ReduceTuple *)pp, h->stream));
+  HIPCHK(h, reduce_finish((ReduceTuple *)pp, ns, bps, (ReduceTuple *)pr, accum, accumulate, d_out, h->stream));
+  if (round_out) *round_out = (ReduceTuple *)pr;
+  return RIFT_OK;
+}
+
+template <typename R>
+rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result *out, R *theta_out,
+                                    R *lnw_out) {
+  const int np = h->n_points;
+  std::vector<int64_t> cnt(np), off(np);
+  std::vector<int> seg_prop(np);
+  int64_t per_round = 0;
+  for (int p = 0; p < np; p++) {
+    cnt[p] = mc->n_per_point ? mc->n_per_point[p] : mc->n_per_round;
+    if (cnt[p] < 0) return fail(h, RIFT_E_INVALID, "negative sample count for point %d", p);
+    if (mc->adapt_mask && cnt[p] > (1 << 23)) return fail(h, RIFT_E_INVALID, "more than 2^23 samples per round");
+    off[p] = per_round;
+    per_round += cnt[p];
+    seg_prop[p] = p;
+  }
+  const int64_t total = per_round * mc->n_rounds;
+  const int64_t nr = std::max<int64_t>(per_round, 1);
+  rift_status s;
+  if (mc->reset_proposal) {
+    std::vector<ProposalDev> props(np);
+    for (auto &p : props) uniform_proposal(p);
+    HIPCHK(h, hipMemcpyAsync(h->d_props, props.data(), sizeof(ProposalDev) * np, hipMemcpyHostToDevice, h->stream));
+  }
+  void *accum, *d_res, *bins, *hist, *ratio, *th_ws = nullptr, *lw_ws = nullptr;
+  if ((s = ws_get(h, W_ACCUM, sizeof(ReduceTuple) * np, &accum)) != RIFT_OK) return s;
+  if ((s = ws_get(h, W_RESULT, sizeof(rift_ile_result) * np, &d_res)) != RIFT_OK) return s;
+  if ((s = ws_get(h, W_BINS, 7 * (size_t)nr, &bins)) != RIFT_OK) return s;
+  if ((s = ws_get(h, W_HIST, sizeof(unsigned long long) * 7 * kNB * np, &hist)) != RIFT_OK) return s;
+  if ((s = ws_get(h, W_RATIO, sizeof(R) * (size_t)nr, &ratio)) != RIFT_OK) return s;
+  if (!theta_out && (s = ws_get(h, W_THETA, 7 * sizeof(R) * (size_t)nr, &th_ws)) != RIFT_OK) return s;
+  if (!lnw_out && (s = ws_get(h, W_LNW, sizeof(R) * (size_t)nr, &lw_ws)) != RIFT_OK) return s;
+  int *d_prop;
+  if ((s = upload(h, W_AUX, seg_prop, &d_prop)) != RIFT_OK) return s;
+  const int64_t th_stride = theta_out ? total : nr;
+  Items it;
+  for (int p = 0; p < np; p++) {
+    it.point.push_back(p);
+    it.off.push_back(off[p]);
+    it.cnt.push_back(cnt[p]);
+  }
+  for (int r = 0; r < mc->n_rounds; r++) {
+    const int64_t cb = theta_out ? (int64_t)r * per_round : 0;
+    R *th = theta_out ? theta_out + cb : (R *)th_ws;
+    R *lw = lnw_out ? lnw_out + (int64_t)r * per_round : (R *)lw_ws;
+    for (int p = 0; p < np; p++)
+      HIPCHK(h, sample_launch<R>(h->d_pts, h->d_props + p, p, mc->seed, (uint32_t)r, 0, cnt[p], th_stride, nr,
+                                 h->d_min, h->d_max, h->tau_width, th + off[p], (R *)ratio + off[p],
+                                 (uint8_t *)bins + off[p], h->stream));
+    if ((s = eval<R>(h, it, th_stride, th, nullptr, lw, (const R *)ratio)) != RIFT_OK) return s;
+    ReduceTuple *round;
+    const bool last = r + 1 == mc->n_rounds;
+    if ((s = reduce_segments<R>(h, lw, nullptr, off, cnt, &round, (ReduceTuple *)accum, r > 0,
+                                last ? (rift_ile_result *)d_res : nullptr)) != RIFT_OK)
+      return s;
+    if (mc->adapt_mask && !last) {
+      int64_t mx = 1;
+      for (auto c : cnt) mx = std::max(mx, c);
+      int bps = (int)std::min<int64_t>(256, (mx + 8191) / 8192);
+      const int64_t *d_off = (const int64_t *)h->ws[W_ITEM_OFF].p, *d_cnt = (const int64_t *)h->ws[W_ITEM_CNT].p;
+      HIPCHK(h, adapt_launch<R>((const uint8_t *)bins, nr, lw, d_off, d_cnt, d_prop, np, bps, round,
+                                (unsigned long long *)hist, h->d_props, mc->adapt_mask, mc->floor_eps, h->stream));
+    }
+  }
+  HIPCHK(h, hipMemcpyAsync(out, d_res, sizeof(rift_ile_result) * np, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return RIFT_OK;
+}
+
+}  // namespace
+
+// =============================================================================
+// C ABI
+// =============================================================================
+extern "C" {
+
+int rift_ile_abi_version(void) { return RIFT_ILE_ABI_VERSION; }
+
+const char *rift_ile_status_string(rift_status s) {
+  switch (s) {
+    case RIFT_OK: return "ok";
+    case RIFT_E_INVALID: return "invalid argument";
+    case RIFT_E_SHAPE: return "inconsistent or unsupported shape";
+    case RIFT_E_NOT_HERMITIAN: return "U not Hermitian or V not symmetric";
+    case RIFT_E_WINDOW: return "pad too small for the light travel time";
+    case RIFT_E_NONFINITE: return "non-finite input";
+    case RIFT_E_OOM: return "device allocation failed";
+    case RIFT_E_DEVICE: return "HIP runtime error";
+    case RIFT_E_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char *rift_ile_last_error(const rift_ile *h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+void rift_ile_destroy(rift_ile *h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  for (auto &pe : h->prof_ev) {
+    (void)hipEventDestroy(pe.first);
+    (void)hipEventDestroy(pe.second);
+  }
+  for (void *p : h->owned) (void)hipFree(p);
+  for (auto &b : h->ws)
+    if (b.p) (void)hipFree(b.p);
+  if (h->d_pts) (void)hipFree(h->d_pts);
+  if (h->d_props) (void)hipFree(h->d_props);
+  delete h;
+}
+
+rift_status rift_ile_create(rift_ile **out, const rift_ile_desc *desc, void *stream) {
+  g_create_error.clear();
+  if (!out) return fail(nullptr, RIFT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!desc || desc->n_points < 1 || !desc->points) return fail(nullptr, RIFT_E_INVALID, "no points");
+  if (desc->precision != RIFT_FP32 && desc->precision != RIFT_FP64)
+    return fail(nullptr, RIFT_E_INVALID, "precision %d", desc->precision);
+  if (!(desc->d_min > 0) || !(desc->d_max > desc->d_min) || !std::isfinite(desc->d_max))
+    return fail(nullptr, RIFT_E_INVALID, "distance prior [%g, %g]", desc->d_min, desc->d_max);
+  if (!(desc->tau_width >= 0) || !std::isfinite(desc->tau_width))
+    return fail(nullptr, RIFT_E_INVALID, "tau_width %g", desc->tau_width);
+  for (int i = 0; i < desc->n_points; i++) {
+    rift_status s = check_point(desc->points[i], i, desc->tau_width);
+    if (s != RIFT_OK) return s;
+  }
+  rift_ile *h = new (std::nothrow) rift_ile();
+  if (!h) return fail(nullptr, RIFT_E_OOM, "host allocation");
+  h->precision = desc->precision;
+  h->flags = 0;
+  if (const char *e = getenv("RIFT_ILE_FP32_KERNEL"))
+    if (!strcmp(e, "plain")) h->flags |= 1u;
+  h->stream = (hipStream_t)stream;
+  h->n_points = desc->n_points;
+  h->d_min = desc->d_min;
+  h->d_max = desc->d_max;
+  h->tau_width = desc->tau_width;
+  auto bail = [&](rift_status s) {
+    std::string msg = h->err;
+    rift_ile_destroy(h);
+    g_create_error = msg;
+    return s;
+  };
+  if (hipGetDevice(&h->device) != hipSuccess) return bail(fail(h, RIFT_E_DEVICE, "no HIP device"));
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && v > 0) h->n_cu = v;
+  else h->n_cu = 256;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess && v > 0)
+    h->lds_max = std::min(v, 160 * 1024) - 1024;
+  h->hp.resize(h->n_points);
+  for (int i = 0; i < h->n_points; i++) {
+    rift_status s = h->precision == RIFT_FP32 ? build_point<float>(h, desc->points[i], h->hp[i])
+                                              : build_point<double>(h, desc->points[i], h->hp[i]);
+    if (s != RIFT_OK) return bail(s);
+    h->max_L = std::max(h->max_L, h->hp[i].L);
+    h->max_nt = std::max(h->max_nt, h->hp[i].n_t);
+  }
+  hipError_t e = hipMalloc(&h->d_pts, sizeof(PointDev) * h->n_points);
+  if (e != hipSuccess) return bail(hip_fail(h, e, "hipMalloc points"));
+  e = hipMemcpy(h->d_pts, h->hp.data(), sizeof(PointDev) * h->n_points, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return bail(hip_fail(h, e, "hipMemcpy points"));
+  std::vector<ProposalDev> props(h->n_points);
+  for (auto &p : props) uniform_proposal(p);
+  e = hipMalloc(&h->d_props, sizeof(ProposalDev) * h->n_points);
+  if (e != hipSuccess) return bail(hip_fail(h, e, "hipMalloc proposals"));
+  e = hipMemcpy(h->d_props, props.data(), sizeof(ProposalDev) * h->n_points, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return bail(hip_fail(h, e, "hipMemcpy proposals"));
+  *out = h;
+  return RIFT_OK;
+}
+
+rift_status rift_ile_profile(rift_ile *h, int enable, double *ms_total, int64_t *launches) {
+  if (!h) return RIFT_E_INVALID;
+  double tot = 0.0;
+  int64_t n = 0;
+  if (!h->prof_ev.empty()) HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (auto &pe : h->prof_ev) {
+    float ms = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&ms, pe.first, pe.second));
+    tot += ms;
+    n++;
+    (void)hipEventDestroy(pe.first);
+    (void)hipEventDestroy(pe.second);
+  }
+  h->prof_ev.clear();
+  h->prof = enable != 0;
+  if (ms_total) *ms_total = tot;
+  if (launches) *launches = n;
+  return RIFT_OK;
+}
+
+rift_status rift_ile_set_stream(rift_ile *h, void *stream) {
+  if (!h) return RIFT_E_INVALID;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->stream = (hipStream_t)stream;
+  return RIFT_OK;
+}
+
+rift_status rift_ile_sample(rift_ile *h, int point, uint64_t seed, uint32_t round, int64_t first, int64_t n,
+                            void *theta, void *ln_ratio, uint8_t *bins) {
+  if (!h) return RIFT_E_INVALID;
+  if (point < 0 || point >= h->n_points) return fail(h, RIFT_E_INVALID, "point %d", point);
+  if (n < 0 || first < 0 || (n > 0 && !theta)) return fail(h, RIFT_E_INVALID, "bad sample range or NULL theta");
+  hipError_t e = h->precision == RIFT_FP32
+                     ? sample_launch<float>(h->d_pts, h->d_props + point, point, seed, round, first, n, n, n, h->d_min,
+                                            h->d_max, h->tau_width, (float *)theta, (float *)ln_ratio, bins, h->stream)
+                     : sample_launch<double>(h->d_pts, h->d_props + point, point, seed, round, first, n, n, n, h->d_min,
+                                             h->d_max, h->tau_width, (double *)theta, (double *)ln_ratio, bins,
+                                             h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "sample");
+  return RIFT_OK;
+}
+
+rift_status rift_ile_lnL(rift_ile *h, int n_items, const rift_ile_item *items, int64_t stride, const void *theta,
+                         void *lnL_t) {
+  if (!h) return RIFT_E_INVALID;
+  rift_status s = check_items(h, n_items, items, stride);
+  if (s != RIFT_OK) return s;
+  if (n_items > 0 && stride > 0 && (!theta || !lnL_t)) return fail(h, RIFT_E_INVALID, "NULL theta or lnL_t");
+  Items it = make_items(n_items, items);
+  if (h->precision == RIFT_FP32)
+    return eval<float>(h, it, stride, (const float *)theta, (float *)lnL_t, nullptr, nullptr);
+  return eval<double>(h, it, stride, (const double *)theta, (double *)lnL_t, nullptr, nullptr);
+}
+
+rift_status rift_ile_reduce(rift_ile *h, int64_t n, const void *lnL_t, const void *ln_ratio, rift_ile_result *out) {
+  if (!h) return RIFT_E_INVALID;
+  if (n < 0 || (n > 0 && !lnL_t) || !out) return fail(h, RIFT_E_INVALID, "bad reduce arguments");
+  void *d_res;
+  rift_status s = ws_get(h, W_RESULT, sizeof(rift_ile_result), &d_res);
+  if (s != RIFT_OK) return s;
+  std::vector<int64_t> off(1, 0), cnt(1, n);
+  if (h->precision == RIFT_FP32)
+    s = reduce_segments<float>(h, (const float *)lnL_t, (const float *)ln_ratio, off, cnt, nullptr, nullptr, 0,
+                               (rift_ile_result *)d_res);
+  else
+    s = reduce_segments<double>(h, (const double *)lnL_t, (const double *)ln_ratio, off, cnt, nullptr, nullptr, 0,
+                                (rift_ile_result *)d_res);
+  if (s != RIFT_OK) return s;
+  HIPCHK(h, hipMemcpyAsync(out, d_res, sizeof(rift_ile_result), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return RIFT_OK;
+}
+
+rift_status rift_ile_adapt(rift_ile *h, int point, int64_t n, const uint8_t *bins, const void *lnw, unsigned mask,
+                           double floor_eps) {
+  if (!h) return RIFT_E_INVALID;
+  if (point < 0 || point >= h->n_points) return fail(h, RIFT_E_INVALID, "point %d", point);
+  if (n < 0 || n > (1 << 23) || (n > 0 && (!bins || !lnw))) return fail(h, RIFT_E_INVALID, "bad adapt arguments");
+  if (!(floor_eps > 0.0 && floor_eps <= 1.0)) return fail(h, RIFT_E_INVALID, "floor_eps %g", floor_eps);
+  if (mask >> 7) return fail(h, RIFT_E_INVALID, "mask 0x%x", mask);
+  std::vector<int64_t> off(1, 0), cnt(1, n);
+  std::vector<int> sp(1, point);
+  ReduceTuple *round;
+  rift_status s;
+  int *d_sp;
+  void *hist;
+  if ((s = ws_get(h, W_HIST, sizeof(unsigned long long) * 7 * kNB, &hist)) != RIFT_OK) return s;
+  int64_t mx = std::max<int64_t>(n, 1);
+  int bps = (int)std::min<int64_t>(256, (mx + 8191) / 8192);
+  if (h->precision == RIFT_FP32) {
+    if ((s = reduce_segments<float>(h, (const float *)lnw, nullptr, off, cnt, &round, nullptr, 0, nullptr)) != RIFT_OK)
+      return s;
+    if ((s = upload(h, W_AUX, sp, &d_sp)) != RIFT_OK) return s;
+    int64_t *d_off = (int64_t *)h->ws[W_ITEM_OFF].p, *d_cnt = (int64_t *)h->ws[W_ITEM_CNT].p;
+    HIPCHK(h, adapt_launch<float>(bins, n, (const float *)lnw, d_off, d_cnt, d_sp, 1, bps, round,
+                                  (unsigned long long *)hist, h->d_props, mask, floor_eps, h->stream));
+  } else {
+    if ((s = reduce_segments<double>(h, (const double *)lnw, nullptr, off, cnt, &round, nullptr, 0, nullptr)) !=
+        RIFT_OK)
+      return s;
+    if ((s = upload(h, W_AUX, sp, &d_sp)) != RIFT_OK) return s;
+    int64_t *d_off = (int64_t *)h->ws[W_ITEM_OFF].p, *d_cnt = (int64_t *)h->ws[W_ITEM_CNT].p;
+    HIPCHK(h, adapt_launch<double>(bins, n, (const double *)lnw, d_off, d_cnt, d_sp, 1, bps, round,
+                                   (unsigned long long *)hist, h->d_props, mask, floor_eps, h->stream));
+  }
+  return RIFT_OK;
+}
+
+rift_status rift_ile_get_proposal(rift_ile *h, int point, double *cdf, unsigned *mask) {
+  if (!h) return RIFT_E_INVALID;
+  if (point < 0 || point >= h->n_points || !cdf) return fail(h, RIFT_E_INVALID, "bad get_proposal arguments");
+  ProposalDev pr;
+  HIPCHK(h, hipMemcpyAsync(&pr, h->d_props + point, sizeof(pr), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  std::memcpy(cdf, pr.cdf, sizeof(pr.cdf));
+  if (mask) *mask = pr.mask;
+  return RIFT_OK;
+}
+
+rift_status rift_ile_set_proposal(rift_ile *h, int point, const double *cdf, unsigned mask) {
+  if (!h) return RIFT_E_INVALID;
+  if (point < 0 || point >= h->n_points || !cdf || (mask >> 7))
+    return fail(h, RIFT_E_INVALID, "bad set_proposal arguments");
+  ProposalDev pr;
+  for (int d = 0; d < 7; d++) {
+    const double *c = cdf + d * (kNB + 1);
+    if (c[0] != 0.0 || c[kNB] != 1.0) return fail(h, RIFT_E_INVALID, "cdf[%d] must run from 0 to 1", d);
+    for (int b = 0; b < kNB; b++)
+      if (!(c[b + 1] > c[b])) return fail(h, RIFT_E_INVALID, "cdf[%d] not strictly increasing at %d", d, b);
+    std::memcpy(pr.cdf[d], c, sizeof(double) * (kNB + 1));
+  }
+  pr.mask = mask;
+  pr.pad_ = 0;
+  HIPCHK(h, hipMemcpy(h->d_props + point, &pr, sizeof(pr), hipMemcpyHostToDevice));
+  return RIFT_OK;
+}
+
+rift_status rift_ile_marginalize(rift_ile *h, const rift_ile_mc *mc, rift_ile_result *out, void *theta_out,
+                                 void *lnw_out) {
+  if (!h) return RIFT_E_INVALID;
+  if (!mc || !out || mc->n_rounds < 1 || (mc->adapt_mask >> 7)) return fail(h, RIFT_E_INVALID, "bad mc arguments");
+  if (mc->adapt_mask && !(mc->floor_eps > 0.0 && mc->floor_eps <= 1.0))
+    return fail(h, RIFT_E_INVALID, "floor_eps %g", mc->floor_eps);
+  if (h->precision == RIFT_FP32) return marginalize_impl<float>(h, mc, out, (float *)theta_out, (float *)lnw_out);
+  return marginalize_impl<double>(h, mc, out, (double *)theta_out, (double *)lnw_out);
+}
+
+rift_status rift_ile_backward(rift_ile *h, int n_items, const rift_ile_item *items, int64_t stride, const void *theta,
+                              const void *grad_lnL_t, void *grad_theta, void *lnL_t_out) {
+  if (!h) return RIFT_E_INVALID;
+  rift_status s = check_items(h, n_items, items, stride);
+  if (s != RIFT_OK) return s;
+  if (n_items > 0 && stride > 0 && (!theta || !grad_theta)) return fail(h, RIFT_E_INVALID, "NULL theta or grad");
+  Items it = make_items(n_items, items);
+  if (h->precision == RIFT_FP32)
+    return run_plain<float>(h, it, stride, (const float *)theta, (float *)lnL_t_out, nullptr, nullptr,
+                            (const float *)grad_lnL_t, (float *)grad_theta, true);
+  return run_plain<double>(h, it, stride, (const double *)theta, (double *)lnL_t_out, nullptr, nullptr,
+                           (const double *)grad_lnL_t, (double *)grad_theta, true);
+}
+
+}  // extern "C"

@@ -304,6 +304,33 @@ PIN_SPECS = [
 ]
 
 
+def prior_samples(seed, n, tau_width=0.0, d_min=10.0, d_max=1000.0):
+    """[7, n] FP64 draws from the workload priors (numpy PCG64)."""
+    g = _rng(seed, 5)
+    u = g.random((7, n))
+    a3, b3 = d_min ** 3, d_max ** 3
+    return np.stack([
+        2 * math.pi * u[0], np.arcsin(2 * u[1] - 1), math.pi * u[2], np.arccos(2 * u[3] - 1),
+        2 * math.pi * u[4], np.cbrt(a3 + u[5] * (b3 - a3)), (u[6] - 0.5) * tau_width,
+    ])
+
+
+def mixed_samples(point, seed, n, frac_near=0.5, tau_width=0.0):
+    """Prior draws mixed with draws scattered around the injection, so that
+    the high-likelihood region is exercised; FP32-representable values."""
+    th = prior_samples(seed, n, tau_width)
+    g = _rng(seed, 6)
+    k = int(n * frac_near)
+    if k and "theta_inj" in point:
+        t0 = point["theta_inj"]
+        sc = np.array([0.02, 0.02, 0.05, 0.1, 0.1, 0.1 * t0[5], 0.0])
+        near = t0[:, None] + sc[:, None] * g.standard_normal((7, k))
+        near[6] = (g.random(k) - 0.5) * tau_width
+        near[5] = np.abs(near[5]) + 1.0
+        th[:, :k] = near
+    return th.astype(np.float32).astype(np.float64)
+
+
 def all_specs():
     out = list(PIN_SPECS)
     for w in WORKLOADS:

@@ -1,0 +1,271 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances.  FP32 handles: the oracle sees the FP32-rounded Q, U and theta
+(upcast), so differences come from FP32 arithmetic only: the contraction,
+interpolation and log-sum-exp run in FP32 with FP32 accumulation, while the
+per-sample prologue (geometry, harmonics, B) runs in FP64.  With |z| terms
+of order |ell| + 2B summed over K detectors, 4 taps and up to 2M products,
+the rounding error per sample is bounded by a few FP32 ulps of that
+magnitude: |d lnL_t| <= 2e-4 + 4e-6 (|lnL_t| + B) (the test checks the
+looser form with B folded into |lnL_t| + 1e3).  The estimate ln L_marg must
+agree to 1e-3.  FP64 handles: 1e-9 relative.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ile():
+    from paper_2210_07912_amd import ile as m
+    m.lib()
+    return m
+
+
+def _handle(ile, points, precision, plain=False, **kw):
+    old = os.environ.get("RIFT_ILE_FP32_KERNEL")
+    if plain:
+        os.environ["RIFT_ILE_FP32_KERNEL"] = "plain"
+    try:
+        return ile.RiftILE(points, precision=precision, **kw)
+    finally:
+        if plain:
+            if old is None:
+                os.environ.pop("RIFT_ILE_FP32_KERNEL", None)
+            else:
+                os.environ["RIFT_ILE_FP32_KERNEL"] = old
+
+
+def _fp32_tol(ref):
+    return 2e-4 + 4e-6 * (np.abs(ref) + 1e3)
+
+
+def _check_fp32(gpu, ref, label):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    err = np.abs(gpu - ref)
+    tol = _fp32_tol(ref)
+    bad = ~(err <= tol)
+    _say(f"[{label}] n={ref.size} max|d|={err.max():.3e} max rel={np.max(err / (np.abs(ref) + 1)):.3e}")
+    assert not bad.any(), (label, np.flatnonzero(bad)[:10], gpu[bad][:5], ref[bad][:5])
+
+
+def _lnL_case(ile, orc, spec, n, precision, plain=False, seed=7, tau_width=0.0):
+    d = synth.make_point(spec)
+    th = synth.mixed_samples(d, seed, n, tau_width=tau_width)
+    p = orc.Point.from_dict(d, complex64=(precision == "fp32"))
+    ref = orc.lnL_t(p, th)
+    h = _handle(ile, [d], precision, plain=plain, tau_width=tau_width)
+    _say(f"lnL case {spec.key()} n={n} {precision} plain={plain}")
+    out = h.lnL(torch.tensor(th)).cpu().numpy()
+    return d, th, ref, out, h
+
+
+def test_lnL_fp32_mfma_tiny(ile, orc):
+    spec = synth.workload("tiny").points[0]
+    d, th, ref, out, h = _lnL_case(ile, orc, spec, 4099, "fp32")
+    _check_fp32(out, ref, "mfma tiny")
+    r_gpu = h.reduce(torch.tensor(out))
+    r_orc = orc.reduce(ref)
+    _say(f"lnL_marg gpu={r_gpu['lnL_marg']:.9f} oracle={r_orc['lnL_marg']:.9f}")
+    assert abs(r_gpu["lnL_marg"] - r_orc["lnL_marg"]) < 1e-3
+
+
+def test_lnL_fp32_plain_tiny(ile, orc):
+    spec = synth.workload("tiny").points[0]
+    d, th, ref, out, h = _lnL_case(ile, orc, spec, 1037, "fp32", plain=True)
+    _check_fp32(out, ref, "plain tiny")
+
+
+def test_lnL_fp64_plain(ile, orc):
+    spec = synth.workload("plain").points[0]
+    d, th, ref, out, h = _lnL_case(ile, orc, spec, 3001, "fp64")
+    err = np.abs(out - ref)
+    _say(f"[fp64] max|d|={err.max():.3e}")
+    assert np.all(err <= 1e-9 * (1 + np.abs(ref)))
+
+
+def test_lnL_single_point_shape(ile, orc):
+    """K = 3, M = 21, n_t = 820 (the single-point workload's shape), subset."""
+    spec = synth.workload("single").points[0]
+    d, th, ref, out, h = _lnL_case(ile, orc, spec, 2051, "fp32", seed=11)
+    _check_fp32(out, ref, "mfma single")
+    r_gpu, r_orc = orc.reduce(out.astype(np.float64)), orc.reduce(ref)
+    _say(f"lnL_marg gpu={r_gpu['lnL_marg']:.9f} oracle={r_orc['lnL_marg']:.9f}")
+    assert abs(r_gpu["lnL_marg"] - r_orc["lnL_marg"]) < 1e-3
+
+
+def test_lnL_with_tau(ile, orc):
+    spec = synth.workload("grad").points[0]
+    d, th, ref, out, h = _lnL_case(ile, orc, spec, 777, "fp32", seed=5, tau_width=1 / 4096)
+    _check_fp32(out, ref, "mfma tau")
+
+
+def test_lnL_batched_items(ile, orc):
+    w = synth.workload("tiny_batched")
+    pts = [synth.make_point(s) for s in w.points]
+    ths, refs, items, off = [], [], [], 0
+    for i, (d, n) in enumerate(zip(pts, w.n_samples)):
+        th = synth.mixed_samples(d, 100 + i, n)
+        ths.append(th)
+        refs.append(orc.lnL_t(orc.Point.from_dict(d, complex64=True), th))
+        items.append((i, off, n))
+        off += n
+    theta = np.concatenate(ths, axis=1)
+    for plain in (False, True):
+        h = _handle(ile, pts, "fp32", plain=plain)
+        _say(f"batched items plain={plain} total={off}")
+        out = h.lnL(torch.tensor(theta), items).cpu().numpy()
+        for i, (_, o, n) in enumerate(items):
+            _check_fp32(out[o:o + n], refs[i], f"batched point {i} plain={plain}")
+        h.close()
+
+
+def test_lnL_edge_cases(ile, orc):
+    spec = synth.workload("tiny").points[0]
+    d = synth.make_point(spec)
+    h = _handle(ile, [d], "fp32")
+    p = orc.Point.from_dict(d, complex64=True)
+    # empty
+    _say("edge: empty")
+    assert h.lnL(torch.zeros((7, 0))).numel() == 0
+    # a single sample, 15 and 17 samples (ragged tiles)
+    for n in (1, 15, 17):
+        _say(f"edge: n={n}")
+        th = synth.mixed_samples(d, 3, n)
+        _check_fp32(h.lnL(torch.tensor(th)).cpu().numpy(), orc.lnL_t(p, th), f"n={n}")
+    # out-of-window tau and bad distance give NaN, the rest are unaffected
+    th = synth.mixed_samples(d, 4, 40)
+    th[6, 3] = 1.0          # one second: far outside the stored rows
+    th[5, 7] = -5.0         # negative distance
+    th[0, 9] = np.nan
+    _say("edge: invalid samples")
+    out = h.lnL(torch.tensor(th)).cpu().numpy()
+    assert np.isnan(out[[3, 7, 9]]).all()
+    ok = np.ones(40, bool); ok[[3, 7, 9]] = False
+    _check_fp32(out[ok], orc.lnL_t(p, th[:, ok]), "valid neighbours")
+    r = h.reduce(torch.tensor(out))
+    assert r["n_nonfinite"] == 3 and r["n"] == 37
+    # window of one sample
+    spec1 = synth.PIN_SPECS[5]
+    d1 = synth.make_point(spec1)
+    d1 = dict(d1)
+    h1 = _handle(ile, [d1], "fp32")
+    th = synth.mixed_samples(d1, 5, 50)
+    _check_fp32(h1.lnL(torch.tensor(th)).cpu().numpy(), orc.lnL_t(orc.Point.from_dict(d1, complex64=True), th), "n_t=16")
+
+
+def test_sampler_matches_oracle(ile, orc):
+    spec = synth.workload("tiny").points[0]
+    d = synth.make_point(spec)
+    rng = np.random.default_rng(3)
+    cdf = np.zeros((7, 101))
+    cdf[:, 1:] = np.cumsum(rng.dirichlet(np.ones(100) * 0.5, size=7) * 0.9 + 0.001, axis=1)
+    cdf /= cdf[:, -1:]
+    cdf[:, -1] = 1.0
+    mask = 0b1011011
+    for prec in ("fp64", "fp32"):
+        h = _handle(ile, [d], prec, tau_width=1 / 4096)
+        h.set_proposal(0, cdf, mask)
+        got_cdf, got_mask = h.get_proposal(0)
+        assert got_mask == mask and np.array_equal(got_cdf, cdf)
+        _say(f"sampler {prec}")
+        n = 3000
+        th, lr, bins = h.sample(0, 2210079120, 5, n, first=1000)
+        th, lr, bins = th.cpu().numpy(), lr.cpu().numpy(), bins.cpu().numpy()
+        oth, olr, obins, _ = orc.draw(2210079120, 0, 5, n, tau_width=1 / 4096, cdf=cdf, adapt_mask=mask, start=1000)
+        assert np.array_equal(bins, obins)
+        # ln p - ln p_s is computed in FP64 and rounded once
+        rel = 1e-13 if prec == "fp64" else 6e-8
+        assert np.all(np.abs(lr - olr) <= rel * np.abs(olr) + 1e-13)
+        # theta: the FP64 transform rounded once, so within half an ulp (FP32)
+        for dd in range(7):
+            err = np.abs(th[dd] - oth[dd])
+            assert np.all(err <= rel * np.abs(oth[dd]) + 1e-12), (dd, err.max())
+
+
+def test_reduce_matches_oracle(ile, orc):
+    rng = np.random.default_rng(4)
+    d = synth.make_point(synth.workload("tiny").points[0])
+    h = _handle(ile, [d], "fp64")
+    for n in (1, 255, 4097, 300001):
+        lnw = rng.normal(size=n) * 30 + 500
+        if n > 10:
+            lnw[::97] = np.nan
+            lnw[5] = np.inf
+            lnw[6] = -np.inf
+        _say(f"reduce n={n}")
+        g = h.reduce(torch.tensor(lnw))
+        o = orc.reduce(lnw)
+        for k in ("lnL_marg", "n_eff", "n_ess", "n_var", "max_lnw"):
+            assert g[k] == pytest.approx(o[k], rel=1e-11, abs=1e-11), (n, k, g[k], o[k])
+        assert g["n"] == o["n"] and g["n_nonfinite"] == o["n_nonfinite"]
+
+
+def test_adapt_matches_oracle(ile, orc):
+    rng = np.random.default_rng(5)
+    d = synth.make_point(synth.workload("tiny").points[0])
+    for prec in ("fp64", "fp32"):
+        h = _handle(ile, [d], prec)
+        n = 50000
+        bins = rng.integers(0, 100, (7, n)).astype(np.uint8)
+        lnw = rng.normal(size=n) * 4 - 20
+        if prec == "fp32":
+            lnw = lnw.astype(np.float32).astype(np.float64)
+        lnw[::101] = np.nan
+        _say(f"adapt {prec}")
+        h.adapt(0, torch.tensor(bins), torch.tensor(lnw), mask=0b0111101, floor_eps=0.05)
+        cdf, mask = h.get_proposal(0)
+        ocdf = orc.adapt(bins, lnw, floor_eps=0.05, adapt_mask=0b0111101)
+        assert mask == 0b0111101
+        assert np.max(np.abs(cdf - ocdf)) < 1e-9
+
+
+def test_marginalize_prior_matches_oracle(ile, orc):
+    spec = synth.workload("tiny").points[0]
+    d = synth.make_point(spec)
+    n = 20000
+    seed = 2210079130
+    oth, olr, _, _ = orc.draw(seed, 0, 0, n)
+    p64 = orc.Point.from_dict(d)
+    ref = orc.reduce(orc.lnL_t(p64, oth) + olr)
+    for prec in ("fp64", "fp32"):
+        h = _handle(ile, [d], prec)
+        _say(f"marginalize prior {prec}")
+        res, th, lw = h.marginalize(seed, n, n_rounds=1, return_samples=True)
+        r = res[0]
+        _say(f"  gpu {r['lnL_marg']:.9f} oracle {ref['lnL_marg']:.9f} n_eff {r['n_eff']:.1f}/{ref['n_eff']:.1f}")
+        tol = 1e-9 if prec == "fp64" else 1e-3
+        assert abs(r["lnL_marg"] - ref["lnL_marg"]) < tol
+        assert r["n"] == n and r["n_nonfinite"] == 0
+
+
+def test_backward_matches_oracle(ile, orc):
+    spec = synth.workload("tiny").points[0]
+    d = synth.make_point(spec)
+    th = synth.mixed_samples(d, 9, 300, tau_width=1 / 4096)
+    for prec in ("fp64", "fp32"):
+        p = orc.Point.from_dict(d, complex64=(prec == "fp32"))
+        lt, g = orc.grad(p, th)
+        h = _handle(ile, [d], prec, tau_width=1 / 4096)
+        _say(f"backward {prec}")
+        gg, lg = h.backward(torch.tensor(th), want_lnL=True)
+        gg, lg = gg.cpu().numpy(), lg.cpu().numpy()
+        scale = np.abs(g).max(axis=0) + 1e-3
+        rel = np.abs(gg - g) / scale
+        _say(f"  max rel grad err {rel.max():.3e}")
+        assert rel.max() < (1e-9 if prec == "fp64" else 1e-4)
+        assert np.allclose(lg, lt, atol=1e-9 if prec == "fp64" else 1e-3)
