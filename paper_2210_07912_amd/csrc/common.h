@@ -41,6 +41,8 @@ struct PointDev {
   int yps[kMaxModes][kMaxYTerms];  // power of sin(iota/2)
   const double *U;             // [K][M][M][2], values rounded to the bulk precision
   const double *V;             // same or nullptr
+  const double *Upk;           // [pairs m<=m'][kMaxDet][2]: U_mm', off-diagonal doubled
+  const double *Vpk;           // same packing of V, or nullptr
   const void *Q;               // plain layout: [K][Lpad][M][2] in the bulk precision
   const float *Qm;             // MFMA layout (FP32 handles): [K][nblk][Mp/2][64]
   int Mp;                      // modes padded to even

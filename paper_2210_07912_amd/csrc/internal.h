@@ -42,6 +42,17 @@ hipError_t plain_launch(const PlainArgsT<R> &a, int TS, int n_tiles, bool bwd, h
 size_t plain_lds_bytes(int elem, int TS, int rows_cap, int nt_cap, bool bwd);
 
 // ---- FP32 MFMA path -------------------------------------------------------
+constexpr int kMaxClasses = 16;  // one persistent launch per distinct T = Mp / 2
+
+// per-tile coefficients written by the coefficient pass (16 samples)
+struct CoefTile {
+  float B[16];               // quadratic term (FP64, rounded)
+  float mu[kMaxDet][16];     // interpolation fraction
+  int n[kMaxDet][16];        // integer row offset (1<<28 for padding / invalid)
+  int col[16];               // output column (-1: padding slot)
+  int flag[16];              // 0 padding, 1 valid, 2 invalid sample
+};
+
 struct MfmaArgs {
   const PointDev *pts;
   ItemsDev items;
@@ -56,19 +67,22 @@ struct MfmaArgs {
   int16_t *nsh;           // [total][4] integer row offsets n_k (index 3: valid flag)
   uint32_t *count;        // [n_bins]
   uint32_t *cursor;       // [n_bins]
-  uint32_t *bin_pos;      // [n_bins] first sorted position of the bin (flat)
-  uint32_t *bin_tile;     // [n_bins] first tile of the bin
+  uint32_t *bin_tile;     // [n_bins] first tile of the bin within its item
   uint32_t *item_tiles;   // [n_items + 1] tile prefix over items (filled on device)
-  uint32_t *perm;         // [total] sorted position -> flat sample index
-  uint4 *tiles;           // [max_tiles] (item, sorted start, count, -)
-  uint32_t *ctl;          // [0]: tile counter, [1]: number of tiles
+  uint32_t *perm;         // [16 max_tiles] slot -> flat sample index (0xFFFFFFFF: padding)
+  int *tile_item;         // [max_tiles]
+  float *cop;             // [max_tiles][kMaxDet][4 Tc][16] B operands of the MFMAs
+  CoefTile *ctile;        // [max_tiles]
+  uint32_t *ctl;          // [0]: number of tiles, [1 + c]: tile counter of class c
   int n_bins;
   int max_tiles;
+  int Tc;                 // largest T in the call (operand stride 4 Tc)
   int grid;               // persistent workgroups
 };
 
-// ev0/ev1 (or null): recorded around the persistent evaluation kernel
-hipError_t mfma_forward(const MfmaArgs &a, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// ev0/ev1 (or null): recorded around the persistent evaluation kernels
+hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_item0, int n_classes,
+                        hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // ---- sampler / reductions / adaptation -------------------------------------
 struct ProposalDev {

@@ -55,7 +55,7 @@ namespace {
 
 enum WsId {
   W_ITEM_POINT, W_ITEM_OFF, W_ITEM_CNT, W_ITEM_TILE0, W_ITEM_SAMP0, W_ITEM_BIN0,
-  W_KEY, W_NSH, W_COUNT, W_CURSOR, W_BINPOS, W_BINTILE, W_ITEMTILES, W_PERM, W_TILES, W_CTL,
+  W_KEY, W_NSH, W_COUNT, W_CURSOR, W_COP, W_BINTILE, W_ITEMTILES, W_PERM, W_TILES, W_CTL, W_CTILE,
   W_PARTIALS, W_ROUND, W_ACCUM, W_RESULT, W_HIST, W_THETA, W_LNW, W_AUX, W_RATIO, W_BINS
 };
 
@@ -241,6 +241,35 @@ rift_status build_point(rift_ile *h, const rift_ile_point &q, PointDev &p) {
     HIPCHK(h, hipMemcpy(d, u.data(), sizeof(double) * u.size(), hipMemcpyHostToDevice));
     p.V = (const double *)d;
   }
+  // U and V packed over pairs m <= m' (off-diagonal doubled) for the quadratic
+  // term of the coefficient pass: [pair][kMaxDet][2]
+  {
+    const int npair = M * (M + 1) / 2;
+    std::vector<double> up((size_t)npair * kMaxDet * 2, 0.0), vp((size_t)npair * kMaxDet * 2, 0.0);
+    int idx = 0;
+    for (int m = 0; m < M; m++)
+      for (int mp = m; mp < M; mp++, idx++)
+        for (int k = 0; k < K; k++) {
+          double f = (m == mp) ? 1.0 : 2.0;
+          size_t src = (((size_t)k * M + m) * M + mp) * 2;
+          up[((size_t)idx * kMaxDet + k) * 2] = f * (double)(R)q.U[src];
+          up[((size_t)idx * kMaxDet + k) * 2 + 1] = f * (double)(R)q.U[src + 1];
+          if (q.V) {
+            vp[((size_t)idx * kMaxDet + k) * 2] = f * (double)(R)q.V[src];
+            vp[((size_t)idx * kMaxDet + k) * 2 + 1] = f * (double)(R)q.V[src + 1];
+          }
+        }
+    HIPCHK(h, hipMalloc(&d, sizeof(double) * up.size()));
+    h->owned.push_back(d);
+    HIPCHK(h, hipMemcpy(d, up.data(), sizeof(double) * up.size(), hipMemcpyHostToDevice));
+    p.Upk = (const double *)d;
+    if (q.V) {
+      HIPCHK(h, hipMalloc(&d, sizeof(double) * vp.size()));
+      h->owned.push_back(d);
+      HIPCHK(h, hipMemcpy(d, vp.data(), sizeof(double) * vp.size(), hipMemcpyHostToDevice));
+      p.Vpk = (const double *)d;
+    }
+  }
   // Q, row layout [K][Lpad][M][2] with zero rows past L
   {
     std::vector<R> qv((size_t)K * p.Lpad * M * 2, R(0));
@@ -340,34 +369,49 @@ rift_status run_plain(rift_ile *h, const Items &it, int64_t stride, const R *the
 
 rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const float *theta, float *lnL, float *lnw,
                      const float *ln_ratio) {
-  // costliest points first: the persistent kernel takes tiles in this order
+  // points grouped by MFMA step count T (one persistent launch per group),
+  // costliest first within a group: the kernels take tiles in this order
   const int n = (int)it_in.point.size();
   std::vector<int> order(n);
   std::iota(order.begin(), order.end(), 0);
+  auto Tof = [&](int i) { return h->hp[it_in.point[i]].Mp >> 1; };
   auto cost = [&](int i) {
     const PointDev &p = h->hp[it_in.point[i]];
     return (double)p.K * (p.Mp + 4) * p.n_t;
   };
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (Tof(a) != Tof(b)) return Tof(a) > Tof(b);
+    return cost(a) > cost(b);
+  });
   Items it;
   std::vector<int64_t> samp0(1, 0);
-  std::vector<int> bin0(1, 0);
+  std::vector<int> bin0(1, 0), class_T, class_item0;
   int64_t max_tiles = 0;
+  int Tc = 1;
   for (int oi : order) {
     if (it_in.cnt[oi] == 0) continue;
+    const PointDev &p = h->hp[it_in.point[oi]];
+    const int T = p.Mp >> 1;
+    if (class_T.empty() || class_T.back() != T) {
+      class_T.push_back(T);
+      class_item0.push_back((int)it.point.size());
+    }
+    Tc = std::max(Tc, T);
     it.point.push_back(it_in.point[oi]);
     it.off.push_back(it_in.off[oi]);
     it.cnt.push_back(it_in.cnt[oi]);
     samp0.push_back(samp0.back() + it_in.cnt[oi]);
-    long long nb = (long long)bin0.back() + h->hp[it_in.point[oi]].n_bins_key;
+    long long nb = (long long)bin0.back() + p.n_bins_key;
     if (nb > (1 << 28)) return fail(h, RIFT_E_SHAPE, "too many delay bins in one call");
     bin0.push_back((int)nb);
-    max_tiles += (it_in.cnt[oi] + 15) / 16 + h->hp[it_in.point[oi]].n_bins_key;
+    max_tiles += (it_in.cnt[oi] + 15) / 16 + p.n_bins_key + 4;
   }
   const int ni = (int)it.point.size();
+  class_item0.push_back(ni);
   const int64_t total = samp0.back();
   if (total == 0) return RIFT_OK;
-  if (total >= (int64_t)1 << 31) return fail(h, RIFT_E_SHAPE, "more than 2^31 samples in one call");
+  if (total >= (int64_t)1 << 31 || max_tiles >= (int64_t)1 << 26)
+    return fail(h, RIFT_E_SHAPE, "more than 2^31 samples in one call");
   MfmaArgs a;
   std::memset(&a, 0, sizeof(a));
   rift_status s;
@@ -393,7 +437,8 @@ rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const floa
   a.lnw = lnw;
   a.ln_ratio = ln_ratio;
   a.n_bins = bin0.back();
-  a.max_tiles = (int)std::min<int64_t>(max_tiles, INT32_MAX);
+  a.max_tiles = (int)max_tiles;
+  a.Tc = Tc;
   void *p;
   if ((s = ws_get(h, W_KEY, 4 * total, &p)) != RIFT_OK) return s;
   a.key = (uint32_t *)p;
@@ -403,17 +448,19 @@ rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const floa
   a.count = (uint32_t *)p;
   if ((s = ws_get(h, W_CURSOR, 4 * (size_t)a.n_bins, &p)) != RIFT_OK) return s;
   a.cursor = (uint32_t *)p;
-  if ((s = ws_get(h, W_BINPOS, 4 * (size_t)a.n_bins, &p)) != RIFT_OK) return s;
-  a.bin_pos = (uint32_t *)p;
   if ((s = ws_get(h, W_BINTILE, 4 * (size_t)a.n_bins, &p)) != RIFT_OK) return s;
   a.bin_tile = (uint32_t *)p;
   if ((s = ws_get(h, W_ITEMTILES, 4 * (size_t)(ni + 1), &p)) != RIFT_OK) return s;
   a.item_tiles = (uint32_t *)p;
-  if ((s = ws_get(h, W_PERM, 4 * total, &p)) != RIFT_OK) return s;
+  if ((s = ws_get(h, W_PERM, 4 * 16 * (size_t)max_tiles, &p)) != RIFT_OK) return s;
   a.perm = (uint32_t *)p;
-  if ((s = ws_get(h, W_TILES, 16 * (size_t)a.max_tiles, &p)) != RIFT_OK) return s;
-  a.tiles = (uint4 *)p;
-  if ((s = ws_get(h, W_CTL, 16, &p)) != RIFT_OK) return s;
+  if ((s = ws_get(h, W_TILES, 4 * (size_t)max_tiles, &p)) != RIFT_OK) return s;
+  a.tile_item = (int *)p;
+  if ((s = ws_get(h, W_COP, sizeof(float) * (size_t)max_tiles * kMaxDet * 4 * Tc * 16, &p)) != RIFT_OK) return s;
+  a.cop = (float *)p;
+  if ((s = ws_get(h, W_CTILE, sizeof(CoefTile) * (size_t)max_tiles, &p)) != RIFT_OK) return s;
+  a.ctile = (CoefTile *)p;
+  if ((s = ws_get(h, W_CTL, 4 * (1 + kMaxClasses) + 64, &p)) != RIFT_OK) return s;
   a.ctl = (uint32_t *)p;
   a.grid = h->n_cu * 4;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -422,7 +469,7 @@ rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const floa
     HIPCHK(h, hipEventCreate(&e1));
     h->prof_ev.emplace_back(e0, e1);
   }
-  HIPCHK(h, mfma_forward(a, h->stream, e0, e1));
+  HIPCHK(h, mfma_forward(a, class_T.data(), class_item0.data(), (int)class_T.size(), h->stream, e0, e1));
   return RIFT_OK;
 }
 

@@ -108,6 +108,28 @@ def _dptr(a):
     return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
 
 
+def build_desc(points, precision=RIFT_FP32, d_min=10.0, d_max=1000.0, tau_width=0.0):
+    """rift_ile_desc for a list of point dicts; returns (desc, arrays to keep
+    alive for the duration of rift_ile_create)."""
+    keep = []
+    arr = (Point * len(points))()
+    for i, p in enumerate(points):
+        Q = np.ascontiguousarray(np.asarray(p["Q"]).astype(np.complex128)).view(np.float64)
+        U = np.ascontiguousarray(np.asarray(p["U"]).astype(np.complex128)).view(np.float64)
+        V = None if p.get("V") is None else np.ascontiguousarray(np.asarray(p["V"]).astype(np.complex128)).view(np.float64)
+        pos = np.ascontiguousarray(p["det_pos"], dtype=np.float64)
+        resp = np.ascontiguousarray(p["det_resp"], dtype=np.float64)
+        ell = np.ascontiguousarray(p["ell"], dtype=np.int32)
+        em = np.ascontiguousarray(p["em"], dtype=np.int32)
+        keep += [Q, U, V, pos, resp, ell, em]
+        arr[i] = Point(pos.shape[0], ell.shape[0], int(p["n_t"]), int(p["pad"]),
+                       ell.ctypes.data_as(C.POINTER(C.c_int)), em.ctypes.data_as(C.POINTER(C.c_int)),
+                       float(p["f_s"]), float(p["d_ref"]), float(p["gmst"]), _dptr(pos), _dptr(resp),
+                       _dptr(Q), _dptr(U), _dptr(V))
+    keep.append(arr)
+    return Desc(len(points), arr, precision, d_min, d_max, tau_width), keep
+
+
 class RiftILE:
     """A handle on one or more intrinsic points.
 
@@ -123,28 +145,13 @@ class RiftILE:
         self.precision = RIFT_FP32 if precision == "fp32" else RIFT_FP64
         self.dtype = torch.float32 if self.precision == RIFT_FP32 else torch.float64
         self.n_points = len(points)
-        self.meta = []
-        keep = []
-        arr = (Point * len(points))()
-        for i, p in enumerate(points):
-            Q = np.ascontiguousarray(np.asarray(p["Q"]).astype(np.complex128)).view(np.float64)
-            U = np.ascontiguousarray(np.asarray(p["U"]).astype(np.complex128)).view(np.float64)
-            V = None if p.get("V") is None else np.ascontiguousarray(np.asarray(p["V"]).astype(np.complex128)).view(np.float64)
-            pos = np.ascontiguousarray(p["det_pos"], dtype=np.float64)
-            resp = np.ascontiguousarray(p["det_resp"], dtype=np.float64)
-            ell = np.ascontiguousarray(p["ell"], dtype=np.int32)
-            em = np.ascontiguousarray(p["em"], dtype=np.int32)
-            keep += [Q, U, V, pos, resp, ell, em]
-            arr[i] = Point(pos.shape[0], ell.shape[0], int(p["n_t"]), int(p["pad"]),
-                           ell.ctypes.data_as(C.POINTER(C.c_int)), em.ctypes.data_as(C.POINTER(C.c_int)),
-                           float(p["f_s"]), float(p["d_ref"]), float(p["gmst"]), _dptr(pos), _dptr(resp),
-                           _dptr(Q), _dptr(U), _dptr(V))
-            self.meta.append(dict(K=pos.shape[0], M=ell.shape[0], n_t=int(p["n_t"])))
-        desc = Desc(len(points), arr, self.precision, d_min, d_max, tau_width)
+        desc, keep = build_desc(points, self.precision, d_min, d_max, tau_width)
+        self.meta = [dict(K=int(np.asarray(p["det_pos"]).shape[0]), M=len(p["ell"]), n_t=int(p["n_t"])) for p in points]
         h = C.c_void_p()
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
             st = lib().rift_ile_create(C.byref(h), C.byref(desc), C.c_void_p(self.stream.cuda_stream))
+        del keep
         if st != 0:
             raise RiftError(st, lib().rift_ile_last_error(None).decode())
         self.h = h

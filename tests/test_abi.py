@@ -53,3 +53,48 @@ def test_binding_refuses_without_device():
         pytest.skip("device present")
     with pytest.raises(RuntimeError):
         ile.RiftILE([{}])
+
+
+def _create_status(points, **kw):
+    from paper_2210_07912_amd import ile
+    desc, keep = ile.build_desc(points, **kw)
+    h = ctypes.c_void_p()
+    st = ile.lib().rift_ile_create(ctypes.byref(h), ctypes.byref(desc), None)
+    msg = ile.lib().rift_ile_last_error(None).decode()
+    if st == 0:
+        ile.lib().rift_ile_destroy(h)
+    return st, msg
+
+
+def test_create_validates_points_on_the_host():
+    """Argument, shape, Hermiticity, finiteness and window checks happen on the
+    host before any device call."""
+    import numpy as np
+    import synth
+    d = synth.make_point(synth.workload("tiny").points[0])
+
+    def mod(**kv):
+        e = dict(d)
+        e.update(kv)
+        return e
+
+    U = d["U"].copy(); U[1, 0, 2] += 0.5
+    st, msg = _create_status([mod(U=U)])
+    assert st == -3 and "Hermitian" in msg
+    Q = d["Q"].copy(); Q[2, 5, 1] = np.nan
+    st, msg = _create_status([mod(Q=Q)])
+    assert st == -5 and "Q" in msg
+    st, msg = _create_status([mod(pad=10, Q=d["Q"][:, : d["n_t"] + 23])])
+    assert st == -4
+    st, msg = _create_status([mod(ell=np.array([2, 2, 9, 2, 2], np.int32))])
+    assert st == -1
+    st, msg = _create_status([d], tau_width=1.0)  # a 1 s tau prior cannot fit in 88 rows
+    assert st == -4
+    st, msg = _create_status([d], d_min=5.0, d_max=1.0)
+    assert st == -1
+    V = np.zeros_like(d["U"]); V[0, 0, 1] = 1.0  # not symmetric
+    st, msg = _create_status([mod(V=V)])
+    assert st == -3 and "V" in msg
+    # a valid description passes the host checks (then needs a device)
+    st, msg = _create_status([d])
+    assert st in (0, -7), msg

@@ -269,3 +269,89 @@ def test_backward_matches_oracle(ile, orc):
         _say(f"  max rel grad err {rel.max():.3e}")
         assert rel.max() < (1e-9 if prec == "fp64" else 1e-4)
         assert np.allclose(lg, lt, atol=1e-9 if prec == "fp64" else 1e-3)
+
+
+def test_lnL_with_V(ile, orc):
+    """Optional symmetric overlap V != 0 (App. D Eq. (QUV)) through both kernels."""
+    spec = synth.PIN_SPECS[3]
+    d = synth.make_point(spec)
+    th = synth.mixed_samples(d, 21, 500)
+    for prec, plain in (("fp32", False), ("fp32", True), ("fp64", False)):
+        p = orc.Point.from_dict(d, complex64=(prec == "fp32"))
+        ref = orc.lnL_t(p, th)
+        h = _handle(ile, [d], prec, plain=plain)
+        _say(f"V != 0 {prec} plain={plain}")
+        out = h.lnL(torch.tensor(th)).cpu().numpy()
+        if prec == "fp32":
+            _check_fp32(out, ref, f"V {prec} plain={plain}")
+        else:
+            assert np.all(np.abs(out - ref) <= 1e-9 * (1 + np.abs(ref)))
+
+
+def test_single_point_full_size(ile, orc):
+    """10^6 samples through the FP32 launch the benchmark times: sampled
+    per-sample parity against the oracle, the FP64 reduction against the
+    oracle's reduction of the same values, and ln L_marg against the FP64
+    plain form on the same samples."""
+    w = synth.workload("single")
+    d = synth.make_point(w.points[0])
+    n = w.n_samples[0]
+    th = synth.prior_samples(2210079121, n).astype(np.float32).astype(np.float64)
+    h32 = _handle(ile, [d], "fp32")
+    h64 = _handle(ile, [d], "fp64")
+    _say(f"full size n={n}")
+    t = torch.tensor(th)
+    l32 = h32.lnL(t.float())
+    l64 = h64.lnL(t)
+    r32, r64 = h32.reduce(l32), h64.reduce(l64)
+    l32 = l32.cpu().numpy().astype(np.float64)
+    l64 = l64.cpu().numpy()
+    idx = np.random.default_rng(0).choice(n, 1500, replace=False)
+    # include the dominant samples
+    idx = np.unique(np.concatenate([idx, np.argsort(l64)[-20:]]))
+    ref = orc.lnL_t(orc.Point.from_dict(d, complex64=True), th[:, idx])
+    _check_fp32(l32[idx], ref, "full-size sample")
+    assert np.all(np.abs(l64[idx] - ref) <= 1e-9 * (1 + np.abs(ref)))
+    o = orc.reduce(l32)
+    assert r32["lnL_marg"] == pytest.approx(o["lnL_marg"], abs=1e-10)
+    assert r32["n_ess"] == pytest.approx(o["n_ess"], rel=1e-10)
+    _say(f"  lnL_marg fp32={r32['lnL_marg']:.8f} fp64={r64['lnL_marg']:.8f} n_eff={r64['n_eff']:.2f}")
+    assert abs(r32["lnL_marg"] - r64["lnL_marg"]) <= 1e-3
+
+
+def _oracle_marginalize(orc, pts, seed, counts, rounds, mask, eps, tau_width=0.0):
+    """Adaptive importance sampling composed from the oracle's pinned pieces:
+    draw (Philox + histogram proposal) -> ln L_t -> ln w -> adapt, pooled over
+    rounds."""
+    cdf = [None] * len(pts)
+    masks = [0] * len(pts)
+    lnw_all = [[] for _ in pts]
+    for r in range(rounds):
+        for i, (p, n) in enumerate(zip(pts, counts)):
+            th, lr, bins, _ = orc.draw(seed, i, r, n, tau_width=tau_width, cdf=cdf[i], adapt_mask=masks[i])
+            lnw = orc.lnL_t(p, th) + lr
+            lnw_all[i].append(lnw)
+            if mask and r + 1 < rounds:
+                cdf[i] = orc.adapt(bins, lnw, floor_eps=eps, adapt_mask=mask)
+                masks[i] = mask
+    return [orc.reduce(np.concatenate(x)) for x in lnw_all]
+
+
+def test_marginalize_adaptive_matches_oracle(ile, orc):
+    """Several points, several rounds, all six angles/distance adapted."""
+    w = synth.workload("tiny_batched")
+    specs = w.points[:3]
+    pts = [synth.make_point(s) for s in specs]
+    counts = [3000, 2000, 2500]
+    seed, rounds, mask, eps = 2210079124, 3, 0x3F, 0.1
+    for prec in ("fp64", "fp32"):
+        ops = [orc.Point.from_dict(d, complex64=(prec == "fp32")) for d in pts]
+        ref = _oracle_marginalize(orc, ops, seed, counts, rounds, mask, eps)
+        h = _handle(ile, pts, prec)
+        _say(f"adaptive marginalize {prec}")
+        res = h.marginalize(seed, counts, n_rounds=rounds, adapt_mask=mask, floor_eps=eps)
+        for i, (r, o) in enumerate(zip(res, ref)):
+            _say(f"  point {i}: gpu {r['lnL_marg']:.9f} oracle {o['lnL_marg']:.9f} n_eff {r['n_eff']:.1f}/{o['n_eff']:.1f}")
+            assert r["n"] == o["n"] == counts[i] * rounds
+            tol = 1e-9 if prec == "fp64" else 1e-3
+            assert abs(r["lnL_marg"] - o["lnL_marg"]) < tol
