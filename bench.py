@@ -33,12 +33,20 @@ def flops_per_eval(K, M, n_t):
     return K * (n_t + 3) * 4 * M + 8 * K * n_t + 4 * n_t + 4 * K * M * M + 6 * K * M + 200
 
 
+def flops_per_grad(K, M, n_t):
+    """Forward evaluation plus the adjoint: the transposed contraction
+    G_k = sum_r c_k[r] Q_k[r] (K (n_t + 3) 4 M), the derivative interpolation
+    (8 K n_t), the softmax weights (2 n_t) and the chain rule (40 K M)."""
+    return flops_per_eval(K, M, n_t) + K * (n_t + 3) * 4 * M + 8 * K * n_t + 2 * n_t + 40 * K * M
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="single")
+    ap.add_argument("--workload", default="single",
+                    help="plain | single | batched | grad | adaptive (default: single, 1e6 samples)")
     ap.add_argument("--n", type=int, default=0, help="samples per step (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -61,12 +69,20 @@ def main():
     n = args.n or w.n_samples[0]
     counts = [n] * len(pts) if args.n else list(w.n_samples)
     h = ile.RiftILE(pts, precision=w.precision, tau_width=w.tau_width)
-    seed = synth.BASE_SEED + 1
+    seed = synth.BASE_SEED + synth.WORKLOADS.index(args.workload)
     rounds = w.rounds if w.adaptive else 1
     mask = 0x3F if w.adaptive else 0
-
-    def step(i):
-        return h.marginalize(seed + i, counts, n_rounds=rounds, adapt_mask=mask, floor_eps=0.1)
+    grad = args.workload == "grad"
+    if grad:
+        # a step: draw the samples on the device, then ln L_t and its gradient
+        # in the seven parameters (one adjoint launch)
+        def step(i):
+            th, _, _ = h.sample(0, seed + i, 0, counts[0])
+            g, lt = h.backward(th, want_lnL=True)
+            return [h.reduce(lt)]
+    else:
+        def step(i):
+            return h.marginalize(seed + i, counts, n_rounds=rounds, adapt_mask=mask, floor_eps=0.1)
 
     for i in range(args.warmup):
         step(i)
@@ -84,15 +100,18 @@ def main():
     value = evals_per_step / dt
 
     # roofline of the dominant kernel (the evaluation kernel)
-    fl = sum(c * flops_per_eval(p["det_pos"].shape[0], len(p["ell"]), p["n_t"]) for c, p in zip(counts, pts))
+    per = flops_per_grad if grad else flops_per_eval
+    fl = sum(c * per(p["det_pos"].shape[0], len(p["ell"]), p["n_t"]) for c, p in zip(counts, pts))
     fl_per_launch = fl  # one evaluation launch per round covers every point
     k_avg_ms = k_ms / max(k_launches, 1)
     achieved = fl_per_launch / (k_avg_ms * 1e-3) / 1e12 if k_launches else None
     dtype = "f32" if w.precision == "fp32" else "f64"
-    peak = PEAK["fp32_mfma_tflops"] if w.precision == "fp32" else PEAK["fp64_tflops"]
-    roof = {"bound": "mfma" if w.precision == "fp32" else "alu", "achieved": achieved, "peak": peak,
+    mfma = w.precision == "fp32" and not grad
+    # the plain kernel is FP32 or FP64 vector-ALU bound (no packed FP32: 78.6)
+    peak = PEAK["fp32_mfma_tflops"] if mfma else PEAK["fp64_tflops"]
+    roof = {"bound": "mfma" if mfma else "alu", "achieved": achieved, "peak": peak,
             "unit": "TFLOP/s", "frac": (achieved / peak) if achieved else None, "traffic": None,
-            "kernel": "mfma_kernel" if w.precision == "fp32" else "plain_kernel",
+            "kernel": "mfma_kernel" if mfma else ("plain_kernel(adjoint)" if grad else "plain_kernel"),
             "kernel_ms": k_avg_ms, "flops_per_eval": fl / max(sum(counts), 1)}
 
     out = {
@@ -100,7 +119,8 @@ def main():
         "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype, "data": "synthetic",
-        "config": {"workload": args.workload, "points": len(pts), "samples_per_point": counts[0] if len(set(counts)) == 1 else "varied",
+        "config": {"workload": args.workload, "points": len(pts),
+                   "samples_per_point": counts[0] if len(set(counts)) == 1 else "varied", "samples_per_step": evals_per_step,
                    "rounds": rounds, "K": [p["det_pos"].shape[0] for p in pts][:1], "M": [len(p["ell"]) for p in pts][:1],
                    "n_t": [p["n_t"] for p in pts][:1], "seed": seed},
         "roofline": roof,
@@ -108,7 +128,7 @@ def main():
     }
 
     # FP32 vs FP64 on the same samples (same GPU): |d ln L_marg| and the FP64 rate
-    if not args.no_fp64 and w.precision == "fp32" and len(pts) == 1:
+    if not args.no_fp64 and w.precision == "fp32" and len(pts) == 1 and not grad:
         nn = min(counts[0], 200_000)
         h64 = ile.RiftILE(pts, precision="fp64", tau_width=w.tau_width)
         th64, _, _ = h64.sample(0, seed, 0, nn)
@@ -134,18 +154,20 @@ def main():
         p = pts[0]
         op = oracle.Point.from_dict(p, complex64=(w.precision == "fp32"))
         th = synth.prior_samples(seed, 4096, w.tau_width)
+        fn = oracle.grad if grad else oracle.lnL_t
         t_a = time.perf_counter()
-        oracle.lnL_t(op, th[:, :256])
+        fn(op, th[:, :256])
         t_b = time.perf_counter()
         rate = 256 / (t_b - t_a)
         ns = int(min(4096, max(256, rate * args.cpu_seconds)))
         if ns > 256:
             t_a = time.perf_counter()
-            oracle.lnL_t(op, th[:, :ns])
+            fn(op, th[:, :ns])
             t_b = time.perf_counter()
             rate = ns / (t_b - t_a)
         out["cpu_baseline"] = {"value": rate, "unit": "evals/s", "cores": oracle.threads(), "kind": "oracle",
-                               "sample": f"{ns} prior samples of point 0 ({args.workload}), ln L_t only, FP64"}
+                               "sample": f"{ns} prior samples of point 0 ({args.workload}), "
+                               + ("ln L_t and gradient" if grad else "ln L_t only") + ", FP64"}
     print(json.dumps(out), flush=True)
     h.close()
 
