@@ -191,8 +191,9 @@ rift_status rift_ile_reduce(rift_ile *h, int64_t n, const void *lnL_t, const voi
  * w = exp(ln w - max ln w) over each masked parameter's prior-CDF coordinate,
  * mixed with a uniform floor:  h_b = (1 - eps) 100 m_b / sum m + eps.
  * bins: device uint8 [7][n] (as written by rift_ile_sample); lnw: device
- * [n] in the handle's precision.  Weights are accumulated as 40-bit fixed
- * point, so n is limited to 2^23.  Parameters outside mask revert to the
+ * [n] in the handle's precision, n <= 2^23.  Weights are accumulated
+ * deterministically (50-bit fixed point within blocks of 8192 samples, FP64
+ * across blocks in block order).  Parameters outside mask revert to the
  * prior.  Asynchronous. */
 rift_status rift_ile_adapt(rift_ile *h, int point, int64_t n, const uint8_t *bins, const void *lnw,
                            unsigned mask, double floor_eps);

@@ -81,7 +81,11 @@ struct MfmaArgs {
 };
 
 // ev0/ev1 (or null): recorded around the persistent evaluation kernels
+// classes: runs of points with the same MFMA step count T (evaluation
+// launches) and with the same mode count M (coefficient launches; mclass_tiles
+// bounds the tiles of each run)
 hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_item0, int n_classes,
+                        const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles, int n_mclasses,
                         hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // ---- sampler / reductions / adaptation -------------------------------------
@@ -112,6 +116,9 @@ hipError_t reduce_partials(const R *lnL, const R *ln_ratio, const int64_t *seg_o
 hipError_t reduce_finish(const ReduceTuple *partials, int n_seg, int bps, ReduceTuple *round_out,
                          ReduceTuple *accum, int accumulate, rift_ile_result *out, hipStream_t st);
 
+// blocks per segment of the histogram pass (and partial histograms kept)
+int hist_blocks(int64_t max_count);
+// hist: [n_seg][bps][7][100] 64-bit partial histograms
 template <typename R>
 hipError_t adapt_launch(const uint8_t *bins, int64_t bin_stride, const R *lnw, const int64_t *seg_off,
                         const int64_t *seg_cnt, const int *seg_prop, int n_seg, int bps,

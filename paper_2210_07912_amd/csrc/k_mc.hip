@@ -10,6 +10,8 @@
 #include "common.h"
 #include "internal.h"
 
+#include <algorithm>
+
 namespace rift {
 
 // ---------------------------------------------------------------------------
@@ -231,10 +233,14 @@ hipError_t reduce_finish(const ReduceTuple *partials, int n_seg, int bps, Reduce
 }
 
 // ---------------------------------------------------------------------------
-// adaptation: fixed-point weighted histograms (w = e^{ln w - max} <= 1 scaled
-// by 2^40; sums of up to 2^23 samples fit in 64 bits), then CDF tables
+// adaptation.  Each block histograms at most kHistChunk samples of one
+// segment in 64-bit fixed point (w = e^{ln w - max} <= 1 scaled by 2^50, so a
+// block's sums stay below 2^63), with integer LDS atomics, which are
+// associative; the block histograms are merged in block order in FP64 by the
+// CDF kernel.  The result does not depend on scheduling.
 // ---------------------------------------------------------------------------
-constexpr double kFix = 1099511627776.0;  // 2^40
+constexpr double kFix = 1125899906842624.0;  // 2^50
+constexpr int kHistChunk = 8192;
 
 template <typename R>
 __global__ void __launch_bounds__(256) hist_kernel(const uint8_t *bins, int64_t bin_stride, const R *lnw,
@@ -245,8 +251,7 @@ __global__ void __launch_bounds__(256) hist_kernel(const uint8_t *bins, int64_t 
   __syncthreads();
   const int seg = blockIdx.x / bps, j = blockIdx.x % bps;
   const int64_t cnt = seg_cnt[seg], off = seg_off[seg];
-  const int64_t chunk = (cnt + bps - 1) / bps;
-  const int64_t lo = min(cnt, (int64_t)j * chunk), hi = min(cnt, lo + chunk);
+  const int64_t lo = min(cnt, (int64_t)j * kHistChunk), hi = min(cnt, lo + kHistChunk);
   const double mx = seg_round[seg].m;
   if (mx > -INFINITY) {
     for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
@@ -258,24 +263,29 @@ __global__ void __launch_bounds__(256) hist_kernel(const uint8_t *bins, int64_t 
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 7 * kNB; i += 256)
-    if (h[i]) atomicAdd(&hist[(size_t)seg * 7 * kNB + i], h[i]);
+  unsigned long long *dst = hist + ((size_t)seg * bps + j) * 7 * kNB;
+  for (int i = threadIdx.x; i < 7 * kNB; i += 256) dst[i] = h[i];
 }
 
-__global__ void cdf_kernel(const unsigned long long *hist, const int *seg_prop, int n_seg, ProposalDev *props,
-                           unsigned mask, double floor_eps) {
+__global__ void cdf_kernel(const unsigned long long *hist, int bps, const int *seg_prop, int n_seg,
+                           ProposalDev *props, unsigned mask, double floor_eps) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n_seg * 7) return;
   int seg = idx / 7, d = idx % 7;
   ProposalDev &P = props[seg_prop[seg]];
-  const unsigned long long *hh = hist + (size_t)seg * 7 * kNB + d * kNB;
+  double m[kNB];
   double tot = 0.0;
-  for (int b = 0; b < kNB; b++) tot += (double)hh[b];
+  for (int b = 0; b < kNB; b++) {
+    double v = 0.0;
+    for (int j = 0; j < bps; j++) v += (double)hist[((size_t)seg * bps + j) * 7 * kNB + d * kNB + b];
+    m[b] = v;
+    tot += v;
+  }
   bool adapt = ((mask >> d) & 1u) && tot > 0.0;
   double c = 0.0;
   P.cdf[d][0] = 0.0;
   for (int b = 0; b < kNB; b++) {
-    double hb = adapt ? (1.0 - floor_eps) * kNB * ((double)hh[b] / tot) + floor_eps : 1.0;
+    double hb = adapt ? (1.0 - floor_eps) * kNB * (m[b] / tot) + floor_eps : 1.0;
     c += hb / kNB;
     P.cdf[d][b + 1] = c;
   }
@@ -283,16 +293,16 @@ __global__ void cdf_kernel(const unsigned long long *hist, const int *seg_prop, 
   if (d == 0) P.mask = mask;
 }
 
+int hist_blocks(int64_t max_count) { return (int)std::max<int64_t>(1, (max_count + kHistChunk - 1) / kHistChunk); }
+
 template <typename R>
 hipError_t adapt_launch(const uint8_t *bins, int64_t bin_stride, const R *lnw, const int64_t *seg_off,
                         const int64_t *seg_cnt, const int *seg_prop, int n_seg, int bps, const ReduceTuple *seg_round,
                         unsigned long long *hist, ProposalDev *props, unsigned mask, double floor_eps, hipStream_t st) {
   if (n_seg <= 0) return hipSuccess;
-  hipError_t e = fill_u32((uint32_t *)hist, (int64_t)2 * 7 * kNB * n_seg, 0u, st);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(hist_kernel<R>, dim3(n_seg * bps), dim3(256), 0, st, bins, bin_stride, lnw, seg_off, seg_cnt, bps,
                      seg_round, hist);
-  hipLaunchKernelGGL(cdf_kernel, dim3((n_seg * 7 + 63) / 64), dim3(64), 0, st, hist, seg_prop, n_seg, props, mask,
+  hipLaunchKernelGGL(cdf_kernel, dim3((n_seg * 7 + 63) / 64), dim3(64), 0, st, hist, bps, seg_prop, n_seg, props, mask,
                      floor_eps);
   return hipGetLastError();
 }

@@ -158,25 +158,33 @@ __global__ void __launch_bounds__(256) tile_item_kernel(MfmaArgs a) {
 // host: q_k = Y^dag U_k Y = sum_{m <= m'} Re(conj(Y_m) c_{mm'} Y_m'),
 // t_k = Y^T V_k Y = sum_{m <= m'} c'_{mm'} Y_m Y_m', with the off-diagonal
 // factor 2 folded into c, c'; B = x^2/4 sum_k [|F_k|^2 q_k + Re(F_k^2 t_k)].
-__global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a) {
-  __shared__ double Ys[64][kMaxModes][2];
-  const int64_t pos = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  const uint32_t n_tiles = a.ctl[0];
-  if (pos >= (int64_t)kTS * n_tiles) return;
+// MC > 0: the mode count is a compile-time constant, Y lives in registers and
+// the pair sums unroll (point data then comes through scalar loads); MC = 0
+// is the general form, with Y staged in LDS.
+template <int MC>
+__global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int item_hi) {
+  constexpr int YS = MC > 0 ? 1 : 64;
+  constexpr int YM = MC > 0 ? 1 : kMaxModes;
+  constexpr int YR = MC > 0 ? MC : 1;
+  __shared__ double Ys[YS][YM][2];
+  const int64_t t_lo = a.item_tiles[item_lo], t_hi = a.item_tiles[item_hi];
+  const int64_t pos = t_lo * kTS + (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (pos >= t_hi * kTS) return;
   const int64_t t = pos / kTS;
   const int s = (int)(pos % kTS);
   const uint32_t f = a.perm[pos];
   // a block is 4 whole tiles of one point (tiles are padded per point)
   const int it = __builtin_amdgcn_readfirstlane(a.tile_item[t]);
   const PointDev &p = a.pts[a.items.point[it]];
-  const int K = p.K, M = p.M, E = 4 * a.Tc;
+  const int K = p.K, E = 4 * a.Tc;
+  const int M = MC > 0 ? MC : p.M;
   float *op = a.cop + (size_t)t * kMaxDet * E * kTS + s;
   CoefTile *ct = a.ctile + t;
   bool pad = f == 0xFFFFFFFFu;
   bool valid = !pad && a.nsh[(int64_t)f * 4 + 3] != 0;
   if (!valid) {
     for (int k = 0; k < K; k++)
-      for (int e = 0; e < 4 * ((p.Mp) >> 1); e++) op[((size_t)k * E + e) * kTS] = 0.f;
+      for (int e = 0; e < 2 * p.Mp; e++) op[((size_t)k * E + e) * kTS] = 0.f;
     ct->B[s] = 0.f;
     for (int k = 0; k < kMaxDet; k++) {
       ct->mu[k][s] = 0.f;
@@ -207,12 +215,16 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a) {
       ct->n[k][s] = 1 << 28;
     }
   }
-  // harmonics: Y_m = ynorm d(iota) exp(i m phi), powers of cos/sin(iota/2)
+  // harmonics: Y_m = ynorm d(iota) exp(i m phi); exp(i m phi) by repeated
+  // products of exp(i phi)
   double ci, si, c1, s1;
   sincos(0.5 * th[RIFT_IOTA], &si, &ci);
   sincos(th[RIFT_PHI], &s1, &c1);
-  double (*Y)[2] = Ys[threadIdx.x];
-  for (int m = 0; m < M; m++) {
+  double Yr[YR], Yi[YR];
+  double (*Yl)[2] = Ys[MC > 0 ? 0 : threadIdx.x];
+#pragma unroll
+  for (int m = 0; m < (MC > 0 ? MC : kMaxModes); m++) {
+    if (m >= M) break;
     int em = p.em[m], am = em < 0 ? -em : em;
     double cr = 1.0, cim = 0.0;
     for (int q = 0; q < am; q++) {
@@ -223,13 +235,21 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a) {
     if (em < 0) cim = -cim;
     double yr, yi;
     harmonic(p, m, ci, si, cr, cim, yr, yi);
-    Y[m][0] = yr;
-    Y[m][1] = yi;
+    if constexpr (MC > 0) {
+      Yr[m] = yr;
+      Yi[m] = yi;
+    } else {
+      Yl[m][0] = yr;
+      Yl[m][1] = yi;
+    }
     // B operand elements 2m (Re a) and 2m+1 (Im a), for every detector
-    for (int k = 0; k < K; k++) {
-      double ar = x * (Fr[k] * yr - Fi[k] * yi), ai = x * (Fr[k] * yi + Fi[k] * yr);
-      op[((size_t)k * E + 2 * m) * kTS] = (float)ar;
-      op[((size_t)k * E + 2 * m + 1) * kTS] = (float)ai;
+#pragma unroll
+    for (int k = 0; k < kMaxDet; k++) {
+      if (k < K) {
+        double ar = x * (Fr[k] * yr - Fi[k] * yi), ai = x * (Fr[k] * yi + Fi[k] * yr);
+        op[((size_t)k * E + 2 * m) * kTS] = (float)ar;
+        op[((size_t)k * E + 2 * m + 1) * kTS] = (float)ai;
+      }
     }
   }
   for (int k = 0; k < K; k++)
@@ -237,32 +257,37 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a) {
   double q[kMaxDet] = {0.0, 0.0, 0.0}, vr[kMaxDet] = {0.0, 0.0, 0.0}, vi[kMaxDet] = {0.0, 0.0, 0.0};
   const double *Uq = p.Upk;
   const double *Vq = p.Vpk;
-  int idx = 0;
-  for (int m = 0; m < M; m++) {
-    const double ymr = Y[m][0], ymi = Y[m][1];
-    for (int mp = m; mp < M; mp++, idx++) {
-      const double ypr = Y[mp][0], ypi = Y[mp][1];
-      // conj(Y_m) Y_m' and Y_m Y_m'
-      const double pr = ymr * ypr + ymi * ypi, pi = ymr * ypi - ymi * ypr;
+  auto pair = [&](int idx, double ymr, double ymi, double ypr, double ypi) {
+    // conj(Y_m) Y_m' and Y_m Y_m'
+    const double pr = ymr * ypr + ymi * ypi, pi = ymr * ypi - ymi * ypr;
+#pragma unroll
+    for (int k = 0; k < kMaxDet; k++) {
+      if (k < K) {
+        const double ur = Uq[((size_t)idx * kMaxDet + k) * 2], ui = Uq[((size_t)idx * kMaxDet + k) * 2 + 1];
+        q[k] += ur * pr - ui * pi;
+      }
+    }
+    if (Vq) {
+      const double sr = ymr * ypr - ymi * ypi, s_i = ymr * ypi + ymi * ypr;
 #pragma unroll
       for (int k = 0; k < kMaxDet; k++) {
         if (k < K) {
-          const double ur = Uq[((size_t)idx * kMaxDet + k) * 2], ui = Uq[((size_t)idx * kMaxDet + k) * 2 + 1];
-          q[k] += ur * pr - ui * pi;
-        }
-      }
-      if (Vq) {
-        const double sr = ymr * ypr - ymi * ypi, s_i = ymr * ypi + ymi * ypr;
-#pragma unroll
-        for (int k = 0; k < kMaxDet; k++) {
-          if (k < K) {
-            const double wr = Vq[((size_t)idx * kMaxDet + k) * 2], wi = Vq[((size_t)idx * kMaxDet + k) * 2 + 1];
-            vr[k] += wr * sr - wi * s_i;
-            vi[k] += wr * s_i + wi * sr;
-          }
+          const double wr = Vq[((size_t)idx * kMaxDet + k) * 2], wi = Vq[((size_t)idx * kMaxDet + k) * 2 + 1];
+          vr[k] += wr * sr - wi * s_i;
+          vi[k] += wr * s_i + wi * sr;
         }
       }
     }
+  };
+  if constexpr (MC > 0) {
+#pragma unroll
+    for (int m = 0; m < MC; m++)
+#pragma unroll
+      for (int mp = m; mp < MC; mp++) pair(m * MC - m * (m - 1) / 2 + (mp - m), Yr[m], Yi[m], Yr[mp], Yi[mp]);
+  } else {
+    int idx = 0;
+    for (int m = 0; m < M; m++)
+      for (int mp = m; mp < M; mp++, idx++) pair(idx, Yl[m][0], Yl[m][1], Yl[mp][0], Yl[mp][1]);
   }
   double b = 0.0;
 #pragma unroll
@@ -330,8 +355,10 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
     }
     bool valid = flag == 1;
 #pragma unroll
-    for (int k = 0; k < kMaxDet; k++)
+    for (int k = 0; k < kMaxDet; k++) {
+      if (k >= K) sh[k] = 0;
       if (sh[k] < 0 || sh[k] > 13) { valid = false; sh[k] = 0; }
+    }
 
     const int JB = (NT + 15) >> 4;
     // A operands of block 0
@@ -421,6 +448,7 @@ static void launch_class(const MfmaArgs &a, int lo, int hi, int cls, hipStream_t
 }
 
 hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_item0, int n_classes,
+                        const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles, int n_mclasses,
                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (a.total <= 0) return hipSuccess;
   hipError_t e = fill_u32(a.count, a.n_bins, 0u, st);
@@ -432,7 +460,17 @@ hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_
   hipLaunchKernelGGL(item_scan_kernel, dim3(1), dim3(64), 0, st, a);
   hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)((a.total + 255) / 256)), dim3(256), 0, st, a);
   hipLaunchKernelGGL(tile_item_kernel, dim3((unsigned)((a.max_tiles + 255) / 256)), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(coef_kernel, dim3((unsigned)(((int64_t)kTS * a.max_tiles + 63) / 64)), dim3(64), 0, st, a);
+  for (int c = 0; c < n_mclasses; c++) {
+    const int lo = mclass_item0[c], hi = mclass_item0[c + 1];
+    const dim3 grid((unsigned)(((int64_t)kTS * mclass_tiles[c] + 63) / 64));
+    switch (mclass_M[c]) {
+      case 2: hipLaunchKernelGGL(coef_kernel<2>, grid, dim3(64), 0, st, a, lo, hi); break;
+      case 5: hipLaunchKernelGGL(coef_kernel<5>, grid, dim3(64), 0, st, a, lo, hi); break;
+      case 9: hipLaunchKernelGGL(coef_kernel<9>, grid, dim3(64), 0, st, a, lo, hi); break;
+      case 21: hipLaunchKernelGGL(coef_kernel<21>, grid, dim3(64), 0, st, a, lo, hi); break;
+      default: hipLaunchKernelGGL(coef_kernel<0>, grid, dim3(64), 0, st, a, lo, hi); break;
+    }
+  }
   if (ev0) (void)hipEventRecord(ev0, st);
   for (int c = 0; c < n_classes; c++) {
     const int lo = class_item0[c], hi = class_item0[c + 1];

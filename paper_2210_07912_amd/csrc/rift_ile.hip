@@ -379,13 +379,15 @@ rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const floa
     const PointDev &p = h->hp[it_in.point[i]];
     return (double)p.K * (p.Mp + 4) * p.n_t;
   };
+  auto Mof = [&](int i) { return h->hp[it_in.point[i]].M; };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     if (Tof(a) != Tof(b)) return Tof(a) > Tof(b);
+    if (Mof(a) != Mof(b)) return Mof(a) > Mof(b);
     return cost(a) > cost(b);
   });
   Items it;
-  std::vector<int64_t> samp0(1, 0);
-  std::vector<int> bin0(1, 0), class_T, class_item0;
+  std::vector<int64_t> samp0(1, 0), mclass_tiles;
+  std::vector<int> bin0(1, 0), class_T, class_item0, mclass_M, mclass_item0;
   int64_t max_tiles = 0;
   int Tc = 1;
   for (int oi : order) {
@@ -396,6 +398,12 @@ rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const floa
       class_T.push_back(T);
       class_item0.push_back((int)it.point.size());
     }
+    if (mclass_M.empty() || mclass_M.back() != p.M) {
+      mclass_M.push_back(p.M);
+      mclass_item0.push_back((int)it.point.size());
+      mclass_tiles.push_back(0);
+    }
+    mclass_tiles.back() += (it_in.cnt[oi] + 15) / 16 + p.n_bins_key + 4;
     Tc = std::max(Tc, T);
     it.point.push_back(it_in.point[oi]);
     it.off.push_back(it_in.off[oi]);
@@ -408,6 +416,7 @@ rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const floa
   }
   const int ni = (int)it.point.size();
   class_item0.push_back(ni);
+  mclass_item0.push_back(ni);
   const int64_t total = samp0.back();
   if (total == 0) return RIFT_OK;
   if (total >= (int64_t)1 << 31 || max_tiles >= (int64_t)1 << 26)
@@ -469,7 +478,8 @@ rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const floa
     HIPCHK(h, hipEventCreate(&e1));
     h->prof_ev.emplace_back(e0, e1);
   }
-  HIPCHK(h, mfma_forward(a, class_T.data(), class_item0.data(), (int)class_T.size(), h->stream, e0, e1));
+  HIPCHK(h, mfma_forward(a, class_T.data(), class_item0.data(), (int)class_T.size(), mclass_M.data(),
+                         mclass_item0.data(), mclass_tiles.data(), (int)mclass_M.size(), h->stream, e0, e1));
   return RIFT_OK;
 }
 
@@ -538,7 +548,10 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
   if ((s = ws_get(h, W_ACCUM, sizeof(ReduceTuple) * np, &accum)) != RIFT_OK) return s;
   if ((s = ws_get(h, W_RESULT, sizeof(rift_ile_result) * np, &d_res)) != RIFT_OK) return s;
   if ((s = ws_get(h, W_BINS, 7 * (size_t)nr, &bins)) != RIFT_OK) return s;
-  if ((s = ws_get(h, W_HIST, sizeof(unsigned long long) * 7 * kNB * np, &hist)) != RIFT_OK) return s;
+  int64_t mxc = 1;
+  for (auto c : cnt) mxc = std::max(mxc, c);
+  const int hbps = hist_blocks(mxc);
+  if ((s = ws_get(h, W_HIST, sizeof(unsigned long long) * 7 * kNB * np * (size_t)hbps, &hist)) != RIFT_OK) return s;
   if ((s = ws_get(h, W_RATIO, sizeof(R) * (size_t)nr, &ratio)) != RIFT_OK) return s;
   if (!theta_out && (s = ws_get(h, W_THETA, 7 * sizeof(R) * (size_t)nr, &th_ws)) != RIFT_OK) return s;
   if (!lnw_out && (s = ws_get(h, W_LNW, sizeof(R) * (size_t)nr, &lw_ws)) != RIFT_OK) return s;
@@ -566,11 +579,8 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
                                 last ? (rift_ile_result *)d_res : nullptr)) != RIFT_OK)
       return s;
     if (mc->adapt_mask && !last) {
-      int64_t mx = 1;
-      for (auto c : cnt) mx = std::max(mx, c);
-      int bps = (int)std::min<int64_t>(256, (mx + 8191) / 8192);
       const int64_t *d_off = (const int64_t *)h->ws[W_ITEM_OFF].p, *d_cnt = (const int64_t *)h->ws[W_ITEM_CNT].p;
-      HIPCHK(h, adapt_launch<R>((const uint8_t *)bins, nr, lw, d_off, d_cnt, d_prop, np, bps, round,
+      HIPCHK(h, adapt_launch<R>((const uint8_t *)bins, nr, lw, d_off, d_cnt, d_prop, np, hbps, round,
                                 (unsigned long long *)hist, h->d_props, mc->adapt_mask, mc->floor_eps, h->stream));
     }
   }
@@ -766,9 +776,8 @@ rift_status rift_ile_adapt(rift_ile *h, int point, int64_t n, const uint8_t *bin
   rift_status s;
   int *d_sp;
   void *hist;
-  if ((s = ws_get(h, W_HIST, sizeof(unsigned long long) * 7 * kNB, &hist)) != RIFT_OK) return s;
-  int64_t mx = std::max<int64_t>(n, 1);
-  int bps = (int)std::min<int64_t>(256, (mx + 8191) / 8192);
+  const int bps = hist_blocks(n);
+  if ((s = ws_get(h, W_HIST, sizeof(unsigned long long) * 7 * kNB * bps, &hist)) != RIFT_OK) return s;
   if (h->precision == RIFT_FP32) {
     if ((s = reduce_segments<float>(h, (const float *)lnw, nullptr, off, cnt, &round, nullptr, 0, nullptr)) != RIFT_OK)
       return s;
