@@ -130,7 +130,21 @@ typedef struct {
   unsigned adapt_mask;        /* bit d: adapt parameter d between rounds (0: prior only) */
   double floor_eps;           /* uniform floor mixed into each adapted histogram, (0, 1] */
   int reset_proposal;         /* 1: start from the prior (else from the current tables) */
+  /* Gradient-informed refinement (flags & RIFT_MC_GRADIENT, adapt_mask != 0):
+   * between rounds, the n_ascent samples of largest ln w of each point climb
+   * ln L_t for ascent_steps steps along the adjoint gradient (normalized
+   * steps in the prior-CDF coordinates of the adapted parameters, each step
+   * kept only if ln L_t rises), and the next proposal places a fraction
+   * ascent_mix of each adapted histogram around the points reached.  Every
+   * round's proposal is fixed before the round is drawn, so the pooled
+   * estimate stays unbiased. */
+  unsigned flags;
+  int n_ascent;               /* 1..256 (0: 64) */
+  int ascent_steps;           /* >= 1 (0: 12) */
+  double ascent_mix;          /* [0, 1 - floor_eps) (0: 0.3) */
 } rift_ile_mc;
+
+#define RIFT_MC_GRADIENT 1u
 
 /* Create a handle for desc->n_points points on the current HIP device.
  * Validates every point (shapes, finiteness, Hermitian U, symmetric V, pad

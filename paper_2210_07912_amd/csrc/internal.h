@@ -16,6 +16,8 @@ struct ItemsDev {
   const int *tile0;     // [n_items + 1] prefix of plain tiles
   const int64_t *samp0; // [n_items + 1] prefix of sample counts (flat index space)
   const int *bin0;      // [n_items + 1] prefix of delay bins
+  const int *blk0;      // [n_items + 1] prefix of sort blocks (kSortBlock samples)
+  const int64_t *hoff;  // [n_items] offset of the point's block histograms
   int n_items;
 };
 
@@ -44,6 +46,17 @@ size_t plain_lds_bytes(int elem, int TS, int rows_cap, int nt_cap, bool bwd);
 // ---- FP32 MFMA path -------------------------------------------------------
 constexpr int kMaxClasses = 16;  // one persistent launch per distinct T = Mp / 2
 
+constexpr int kSortBlock = 4096;  // samples per sort block
+constexpr int kLdsBins = 8192;    // delay bins counted in LDS (more: in global memory)
+
+// one sample at its sorted slot
+struct SampleRec {
+  float th[7];
+  int col;        // column of theta / ln L_t
+  int16_t n[3];   // integer row offset per detector
+  int16_t flag;   // 0 padding slot, 1 valid, 2 invalid sample
+};
+
 // per-tile coefficients written by the coefficient pass (16 samples)
 struct CoefTile {
   float B[16];               // quadratic term (FP64, rounded)
@@ -63,20 +76,22 @@ struct MfmaArgs {
   float *lnw;             // [stride] or null
   const float *ln_ratio;  // [stride] or null
   // workspace
-  uint32_t *key;          // [total] global bin of each flat sample
+  uint32_t *key;          // [total] bin of each flat sample within its point
   int16_t *nsh;           // [total][4] integer row offsets n_k (index 3: valid flag)
   uint32_t *count;        // [n_bins]
-  uint32_t *cursor;       // [n_bins]
+  uint32_t *bhist;        // per point [sort blocks][bins]: counts, then block offsets
   uint32_t *bin_tile;     // [n_bins] first tile of the bin within its item
   uint32_t *item_tiles;   // [n_items + 1] tile prefix over items (filled on device)
-  uint32_t *perm;         // [16 max_tiles] slot -> flat sample index (0xFFFFFFFF: padding)
+  SampleRec *rec;         // [16 max_tiles] sorted samples (flag 0: padding)
   int *tile_item;         // [max_tiles]
-  float *cop;             // [max_tiles][kMaxDet][4 Tc][16] B operands of the MFMAs
+  float *cop;             // per point [tiles][K][2 Mp][16]: B operands of the MFMAs
+  int64_t *item_cop;      // [n_items] offset of each point's operands in cop
   CoefTile *ctile;        // [max_tiles]
   uint32_t *ctl;          // [0]: number of tiles, [1 + c]: tile counter of class c
   int n_bins;
+  int max_item_bins;      // largest bin count of one point
+  int n_sort_blocks;
   int max_tiles;
-  int Tc;                 // largest T in the call (operand stride 4 Tc)
   int grid;               // persistent workgroups
 };
 
@@ -116,6 +131,22 @@ hipError_t reduce_partials(const R *lnL, const R *ln_ratio, const int64_t *seg_o
 hipError_t reduce_finish(const ReduceTuple *partials, int n_seg, int bps, ReduceTuple *round_out,
                          ReduceTuple *accum, int accumulate, rift_ile_result *out, hipStream_t st);
 
+// gradient-informed refinement (k_grad.hip)
+struct AscentState {
+  double best_th[7];
+  double best_g[7];
+  double best_l;
+  double eta;
+};
+template <typename R>
+hipError_t ascent_select(const R *lnw, const R *theta, int64_t stride, const int64_t *seg_off, const int64_t *seg_cnt,
+                         int n_seg, int k, int *idx, R *th_a, AscentState *st, hipStream_t s);
+template <typename R>
+hipError_t ascent_step(R *th_a, const R *grad, const R *lnl, AscentState *st, int n, unsigned mask, double d_min,
+                       double d_max, double tw, hipStream_t s);
+hipError_t ascent_hist(const AscentState *st, int k, int n_seg, unsigned mask, double d_min, double d_max, double tw,
+                       double *ahist, hipStream_t s);
+
 // blocks per segment of the histogram pass (and partial histograms kept)
 int hist_blocks(int64_t max_count);
 // hist: [n_seg][bps][7][100] 64-bit partial histograms
@@ -123,7 +154,8 @@ template <typename R>
 hipError_t adapt_launch(const uint8_t *bins, int64_t bin_stride, const R *lnw, const int64_t *seg_off,
                         const int64_t *seg_cnt, const int *seg_prop, int n_seg, int bps,
                         const ReduceTuple *seg_round, unsigned long long *hist, ProposalDev *props,
-                        unsigned mask, double floor_eps, hipStream_t st);
+                        unsigned mask, double floor_eps, hipStream_t st, const double *ahist = nullptr,
+                        double ascent_mix = 0.0);
 
 hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 

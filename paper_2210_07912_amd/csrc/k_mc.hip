@@ -267,8 +267,10 @@ __global__ void __launch_bounds__(256) hist_kernel(const uint8_t *bins, int64_t 
   for (int i = threadIdx.x; i < 7 * kNB; i += 256) dst[i] = h[i];
 }
 
+// h_b = (1 - eps - beta) nb m_b / sum m + beta nb a_b / sum a + eps, with a the
+// histogram of the points reached by the gradient ascent (beta = 0 without)
 __global__ void cdf_kernel(const unsigned long long *hist, int bps, const int *seg_prop, int n_seg,
-                           ProposalDev *props, unsigned mask, double floor_eps) {
+                           ProposalDev *props, unsigned mask, double floor_eps, const double *ahist, double beta) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n_seg * 7) return;
   int seg = idx / 7, d = idx % 7;
@@ -282,10 +284,17 @@ __global__ void cdf_kernel(const unsigned long long *hist, int bps, const int *s
     tot += v;
   }
   bool adapt = ((mask >> d) & 1u) && tot > 0.0;
+  const double *ah = ahist ? ahist + ((size_t)seg * 7 + d) * kNB : nullptr;
+  double atot = 0.0;
+  if (ah)
+    for (int b = 0; b < kNB; b++) atot += ah[b];
+  const double bw = (ah && atot > 0.0) ? beta : 0.0;
   double c = 0.0;
   P.cdf[d][0] = 0.0;
   for (int b = 0; b < kNB; b++) {
-    double hb = adapt ? (1.0 - floor_eps) * kNB * (m[b] / tot) + floor_eps : 1.0;
+    double hb = adapt ? (1.0 - floor_eps - bw) * kNB * (m[b] / tot) + (bw > 0.0 ? bw * kNB * ah[b] / atot : 0.0) +
+                            floor_eps
+                      : 1.0;
     c += hb / kNB;
     P.cdf[d][b + 1] = c;
   }
@@ -298,20 +307,21 @@ int hist_blocks(int64_t max_count) { return (int)std::max<int64_t>(1, (max_count
 template <typename R>
 hipError_t adapt_launch(const uint8_t *bins, int64_t bin_stride, const R *lnw, const int64_t *seg_off,
                         const int64_t *seg_cnt, const int *seg_prop, int n_seg, int bps, const ReduceTuple *seg_round,
-                        unsigned long long *hist, ProposalDev *props, unsigned mask, double floor_eps, hipStream_t st) {
+                        unsigned long long *hist, ProposalDev *props, unsigned mask, double floor_eps, hipStream_t st,
+                        const double *ahist, double ascent_mix) {
   if (n_seg <= 0) return hipSuccess;
   hipLaunchKernelGGL(hist_kernel<R>, dim3(n_seg * bps), dim3(256), 0, st, bins, bin_stride, lnw, seg_off, seg_cnt, bps,
                      seg_round, hist);
   hipLaunchKernelGGL(cdf_kernel, dim3((n_seg * 7 + 63) / 64), dim3(64), 0, st, hist, bps, seg_prop, n_seg, props, mask,
-                     floor_eps);
+                     floor_eps, ahist, ascent_mix);
   return hipGetLastError();
 }
 template hipError_t adapt_launch<float>(const uint8_t *, int64_t, const float *, const int64_t *, const int64_t *,
                                         const int *, int, int, const ReduceTuple *, unsigned long long *,
-                                        ProposalDev *, unsigned, double, hipStream_t);
+                                        ProposalDev *, unsigned, double, hipStream_t, const double *, double);
 template hipError_t adapt_launch<double>(const uint8_t *, int64_t, const double *, const int64_t *, const int64_t *,
                                          const int *, int, int, const ReduceTuple *, unsigned long long *,
-                                         ProposalDev *, unsigned, double, hipStream_t);
+                                         ProposalDev *, unsigned, double, hipStream_t, const double *, double);
 
 // ---------------------------------------------------------------------------
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {

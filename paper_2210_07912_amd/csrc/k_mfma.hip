@@ -16,10 +16,12 @@
 // sorted slots [16 t, 16 t + 16).
 //
 // Kernels, in launch order:
-//   bin_kernel    integer delays n_k, bin key, bin counts
-//   scan_kernel   per point: tiles before each bin
+//   bin_kernel    integer delays n_k, bin key, per-sort-block bin counts
+//   scan_kernel   per point: offset of each sort block in each bin, tiles
+//                 before each bin
 //   item_scan     tiles before each point; per-class tile counters reset
-//   scatter       sorted slot of every sample; point of every tile
+//   scatter       a 40-byte record (theta, column, n_k) at the sorted slot
+//   tile_item     point of every tile
 //   coef_kernel   one thread per slot, FP64: antenna patterns, harmonics,
 //                 a_{k,lm} (rounded to FP32, in the MFMA operand layout), the
 //                 quadratic term B, and the interpolation fraction mu_k
@@ -31,6 +33,8 @@
 //                 log-sum-exp.  ell_j never leaves registers.
 #include "common.h"
 #include "internal.h"
+
+#include <algorithm>
 
 namespace rift {
 
@@ -59,38 +63,77 @@ __device__ __forceinline__ int item_of_bin(const ItemsDev &it, int b) {
   return lo;
 }
 
-// ---- 1. integer delays, bin keys and bin counts ---------------------------
-__global__ void __launch_bounds__(256) bin_kernel(MfmaArgs a) {
-  int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (f >= a.total) return;
-  int it = item_of_flat(a.items, f);
-  const PointDev &p = a.pts[a.items.point[it]];
-  int64_t col = a.items.off[it] + (f - a.items.samp0[it]);
-  double al = a.theta[RIFT_ALPHA * a.stride + col], de = a.theta[RIFT_DELTA * a.stride + col];
-  double io = a.theta[RIFT_IOTA * a.stride + col], ph = a.theta[RIFT_PHI * a.stride + col];
-  double di = a.theta[RIFT_DIST * a.stride + col], ta = a.theta[RIFT_TAU * a.stride + col];
-  SkyTrig tr = sky_trig(al, de, 0.0, p.gmst);
-  Shift sh = shifts(p, tr, ta);
-  bool ok = sh.ok && isfinite(io) && isfinite(ph) && isfinite(di) && di > 0.0 &&
-            isfinite((double)a.theta[RIFT_PSI * a.stride + col]);
-  uint32_t key = 0, mul = 1;
-  for (int k = 0; k < p.K; k++) {
-    int q = ok ? (sh.n[k] + p.pad) / p.bin_w : 0;
-    key += q * mul;
-    mul *= p.nq;
-    a.nsh[f * 4 + k] = (int16_t)(ok ? sh.n[k] : 0);
+// ---- 1. integer delays, bin keys, per-block bin counts ----------------------
+// A sort block is kSortBlock consecutive samples of one point.  Counts go to an
+// LDS histogram (the point's bins), then to the block's row of the global
+// block histogram; no global atomics, so no contention on busy bins.
+__device__ __forceinline__ int block_item(const ItemsDev &it, int b) {
+  int lo = 0, hi = it.n_items;  // blk0[lo] <= b < blk0[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (it.blk0[mid] <= b) lo = mid; else hi = mid;
   }
-  a.nsh[f * 4 + 3] = ok ? 1 : 0;
-  uint32_t gb = a.items.bin0[it] + key;
-  a.key[f] = gb;
-  atomicAdd(&a.count[gb], 1u);
+  return lo;
 }
 
-// ---- 2. per-item scans: tiles before each bin --------------------------------
+__global__ void __launch_bounds__(256) bin_kernel(MfmaArgs a) {
+  extern __shared__ uint32_t cnt_l[];
+  const int it = block_item(a.items, blockIdx.x);
+  const int lb = blockIdx.x - a.items.blk0[it];
+  const PointDev &p = a.pts[a.items.point[it]];
+  const int nb = a.items.bin0[it + 1] - a.items.bin0[it];
+  const bool lds = nb <= kLdsBins;
+  uint32_t *cnt = lds ? cnt_l : a.bhist + a.items.hoff[it] + (int64_t)lb * nb;
+  for (int i = threadIdx.x; i < nb; i += 256) cnt[i] = 0u;
+  __syncthreads();
+  const int64_t n = a.items.cnt[it];
+  const int64_t j0 = (int64_t)lb * kSortBlock, j1 = min(n, j0 + kSortBlock);
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
+    const int64_t f = a.items.samp0[it] + j;
+    const int64_t col = a.items.off[it] + j;
+    double al = a.theta[RIFT_ALPHA * a.stride + col], de = a.theta[RIFT_DELTA * a.stride + col];
+    double io = a.theta[RIFT_IOTA * a.stride + col], ph = a.theta[RIFT_PHI * a.stride + col];
+    double di = a.theta[RIFT_DIST * a.stride + col], ta = a.theta[RIFT_TAU * a.stride + col];
+    SkyTrig tr = sky_trig(al, de, 0.0, p.gmst);
+    Shift sh = shifts(p, tr, ta);
+    bool ok = sh.ok && isfinite(io) && isfinite(ph) && isfinite(di) && di > 0.0 &&
+              isfinite((double)a.theta[RIFT_PSI * a.stride + col]);
+    uint32_t key = 0, mul = 1;
+    for (int k = 0; k < p.K; k++) {
+      int q = ok ? (sh.n[k] + p.pad) / p.bin_w : 0;
+      key += q * mul;
+      mul *= p.nq;
+      a.nsh[f * 4 + k] = (int16_t)(ok ? sh.n[k] : 0);
+    }
+    a.nsh[f * 4 + 3] = ok ? 1 : 0;
+    a.key[f] = key;
+    atomicAdd(&cnt[key], 1u);
+  }
+  __syncthreads();
+  if (lds) {
+    uint32_t *row = a.bhist + a.items.hoff[it] + (int64_t)lb * nb;
+    for (int i = threadIdx.x; i < nb; i += 256) row[i] = cnt_l[i];
+  }
+}
+
+// ---- 2. per-item scans: block offsets within each bin, tiles before each bin --
 __global__ void __launch_bounds__(256) scan_kernel(MfmaArgs a) {
   __shared__ uint32_t pt[256];
   const int it = blockIdx.x;
   const int b0 = a.items.bin0[it], nb = a.items.bin0[it + 1] - b0;
+  const int nblk = a.items.blk0[it + 1] - a.items.blk0[it];
+  uint32_t *h = a.bhist + a.items.hoff[it];
+  // column scan: offset of each sort block within each bin, and bin totals
+  for (int b = threadIdx.x; b < nb; b += 256) {
+    uint32_t run = 0;
+    for (int lb = 0; lb < nblk; lb++) {
+      uint32_t v = h[(int64_t)lb * nb + b];
+      h[(int64_t)lb * nb + b] = run;
+      run += v;
+    }
+    a.count[b0 + b] = run;
+  }
+  __syncthreads();
   const int per = (nb + 255) / 256;
   const int lo = min(nb, (int)threadIdx.x * per), hi = min(nb, lo + per);
   uint32_t ct = 0;
@@ -109,10 +152,8 @@ __global__ void __launch_bounds__(256) scan_kernel(MfmaArgs a) {
   __syncthreads();
   uint32_t rt = pt[threadIdx.x];
   for (int b = lo; b < hi; b++) {
-    uint32_t c = a.count[b0 + b];
     a.bin_tile[b0 + b] = rt;
-    a.cursor[b0 + b] = 0;
-    rt += (c + kTS - 1) / kTS;
+    rt += (a.count[b0 + b] + kTS - 1) / kTS;
   }
 }
 
@@ -127,17 +168,47 @@ __global__ void item_scan_kernel(MfmaArgs a) {
     }
     a.ctl[0] = r;
     for (int c = 0; c < kMaxClasses; c++) a.ctl[1 + c] = 0;
+    // coefficient storage: K 2Mp 16 floats per tile of each point
+    int64_t c = 0;
+    for (int i = 0; i < a.items.n_items; i++) {
+      a.item_cop[i] = c;
+      const PointDev &p = a.pts[a.items.point[i]];
+      c += (int64_t)(a.item_tiles[i + 1] - a.item_tiles[i]) * p.K * 2 * p.Mp * kTS;
+    }
   }
 }
 
-// ---- 3. scatter to (padded) sorted order; point of each tile ----------------
+// ---- 3. scatter: one record per sample at its (padded) sorted slot ------------
 __global__ void __launch_bounds__(256) scatter_kernel(MfmaArgs a) {
-  int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (f < a.total) {
-    uint32_t gb = a.key[f];
-    int it = item_of_flat(a.items, f);
-    uint32_t pos = kTS * (a.item_tiles[it] + a.bin_tile[gb]) + atomicAdd(&a.cursor[gb], 1u);
-    a.perm[pos] = (uint32_t)f;
+  extern __shared__ uint32_t cur_l[];
+  const int it = block_item(a.items, blockIdx.x);
+  const int lb = blockIdx.x - a.items.blk0[it];
+  const int b0 = a.items.bin0[it], nb = a.items.bin0[it + 1] - b0;
+  const bool lds = nb <= kLdsBins;
+  uint32_t *cur = lds ? cur_l : a.bhist + a.items.hoff[it] + (int64_t)lb * nb;
+  if (lds) {
+    const uint32_t *row = a.bhist + a.items.hoff[it] + (int64_t)lb * nb;
+    for (int i = threadIdx.x; i < nb; i += 256) cur_l[i] = row[i];
+  }
+  __syncthreads();
+  const int64_t n = a.items.cnt[it];
+  const int64_t j0 = (int64_t)lb * kSortBlock, j1 = min(n, j0 + kSortBlock);
+  const uint32_t tbase = a.item_tiles[it];
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
+    const int64_t f = a.items.samp0[it] + j;
+    const int64_t col = a.items.off[it] + j;
+    const uint32_t key = a.key[f];
+    const uint32_t r = atomicAdd(&cur[key], 1u);
+    const uint32_t pos = kTS * (tbase + a.bin_tile[b0 + key]) + r;
+    SampleRec rec;
+#pragma unroll
+    for (int d = 0; d < 7; d++) rec.th[d] = a.theta[d * a.stride + col];
+    rec.col = (int)col;
+    rec.n[0] = a.nsh[f * 4 + 0];
+    rec.n[1] = a.nsh[f * 4 + 1];
+    rec.n[2] = a.nsh[f * 4 + 2];
+    rec.flag = a.nsh[f * 4 + 3] ? 1 : 2;
+    a.rec[pos] = rec;
   }
 }
 
@@ -172,16 +243,16 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
   if (pos >= t_hi * kTS) return;
   const int64_t t = pos / kTS;
   const int s = (int)(pos % kTS);
-  const uint32_t f = a.perm[pos];
+  const SampleRec rec = a.rec[pos];
   // a block is 4 whole tiles of one point (tiles are padded per point)
   const int it = __builtin_amdgcn_readfirstlane(a.tile_item[t]);
   const PointDev &p = a.pts[a.items.point[it]];
-  const int K = p.K, E = 4 * a.Tc;
+  const int K = p.K, E = 2 * p.Mp;
   const int M = MC > 0 ? MC : p.M;
-  float *op = a.cop + (size_t)t * kMaxDet * E * kTS + s;
+  float *op = a.cop + a.item_cop[it] + (int64_t)(t - a.item_tiles[it]) * K * E * kTS + s;
   CoefTile *ct = a.ctile + t;
-  bool pad = f == 0xFFFFFFFFu;
-  bool valid = !pad && a.nsh[(int64_t)f * 4 + 3] != 0;
+  bool pad = rec.flag == 0;
+  bool valid = rec.flag == 1;
   if (!valid) {
     for (int k = 0; k < K; k++)
       for (int e = 0; e < 2 * p.Mp; e++) op[((size_t)k * E + e) * kTS] = 0.f;
@@ -190,14 +261,14 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
       ct->mu[k][s] = 0.f;
       ct->n[k][s] = 1 << 28;
     }
-    ct->col[s] = pad ? -1 : (int)(a.items.off[it] + ((int64_t)f - a.items.samp0[it]));
+    ct->col[s] = pad ? -1 : rec.col;
     ct->flag[s] = pad ? 0 : 2;
     return;
   }
-  const int64_t col = a.items.off[it] + ((int64_t)f - a.items.samp0[it]);
+  const int64_t col = rec.col;
   double th[7];
 #pragma unroll
-  for (int d = 0; d < 7; d++) th[d] = (double)a.theta[d * a.stride + col];
+  for (int d = 0; d < 7; d++) th[d] = (double)rec.th[d];
   const double x = p.d_ref / th[RIFT_DIST];
   SkyTrig tr = sky_trig(th[RIFT_ALPHA], th[RIFT_DELTA], th[RIFT_PSI], p.gmst);
   double Fr[kMaxDet], Fi[kMaxDet];
@@ -206,7 +277,7 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
     Fr[k] = Fi[k] = 0.0;
     if (k < K) {
       antenna(p.D[k], tr, Fr[k], Fi[k]);
-      int n = (int)a.nsh[(int64_t)f * 4 + k];
+      int n = (int)rec.n[k];
       double sk = (th[RIFT_TAU] + delay(p.rc[k], tr)) * p.f_s;
       ct->mu[k][s] = (float)(sk - (double)n);
       ct->n[k][s] = n;
@@ -322,7 +393,7 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
   float *ring = lds_all + (threadIdx.x >> 6) * kRingFloats;  // [det][16][kRS]
   const int s = lane & 15, g = lane >> 4;
   const uint32_t t_lo = a.item_tiles[item_lo], t_hi = a.item_tiles[item_hi];
-  const int E = 4 * a.Tc;
+  constexpr int E = 4 * T;
 
   for (;;) {
     uint32_t t = 0;
@@ -333,7 +404,7 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
     const PointDev &p = a.pts[a.items.point[it]];
     const int K = p.K, NT = p.n_t, P = p.pad, Lpad = p.Lpad;
     const CoefTile *ct = a.ctile + t;
-    const float *op = a.cop + (size_t)t * kMaxDet * E * kTS;
+    const float *op = a.cop + a.item_cop[it] + (int64_t)(t - a.item_tiles[it]) * K * E * kTS;
     const int flag = ct->flag[s];
     if (!__any(flag != 0)) continue;  // padding tile
     const int col = ct->col[s];
@@ -451,14 +522,13 @@ hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_
                         const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles, int n_mclasses,
                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (a.total <= 0) return hipSuccess;
-  hipError_t e = fill_u32(a.count, a.n_bins, 0u, st);
-  if (e == hipSuccess) e = fill_u32(a.perm, (int64_t)kTS * a.max_tiles, 0xFFFFFFFFu, st);
+  hipError_t e = fill_u32((uint32_t *)a.rec, (int64_t)kTS * a.max_tiles * (sizeof(SampleRec) / 4), 0u, st);
   if (e != hipSuccess) return e;
-  int nb = (int)((a.total + 255) / 256);
-  hipLaunchKernelGGL(bin_kernel, dim3(nb), dim3(256), 0, st, a);
+  const size_t lds = sizeof(uint32_t) * (size_t)std::min(a.max_item_bins, kLdsBins);
+  hipLaunchKernelGGL(bin_kernel, dim3(a.n_sort_blocks), dim3(256), lds, st, a);
   hipLaunchKernelGGL(scan_kernel, dim3(a.items.n_items), dim3(256), 0, st, a);
   hipLaunchKernelGGL(item_scan_kernel, dim3(1), dim3(64), 0, st, a);
-  hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)((a.total + 255) / 256)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(scatter_kernel, dim3(a.n_sort_blocks), dim3(256), lds, st, a);
   hipLaunchKernelGGL(tile_item_kernel, dim3((unsigned)((a.max_tiles + 255) / 256)), dim3(256), 0, st, a);
   for (int c = 0; c < n_mclasses; c++) {
     const int lo = mclass_item0[c], hi = mclass_item0[c + 1];

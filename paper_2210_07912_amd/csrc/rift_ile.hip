@@ -45,7 +45,7 @@ struct rift_ile {
   int n_cu = 0;
   int lds_max = 65536;
   // grow-only workspace, indexed by name
-  DevBuf ws[32];
+  DevBuf ws[40];
   // optional timing of the dominant evaluation kernel
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
@@ -56,7 +56,8 @@ namespace {
 enum WsId {
   W_ITEM_POINT, W_ITEM_OFF, W_ITEM_CNT, W_ITEM_TILE0, W_ITEM_SAMP0, W_ITEM_BIN0,
   W_KEY, W_NSH, W_COUNT, W_CURSOR, W_COP, W_BINTILE, W_ITEMTILES, W_PERM, W_TILES, W_CTL, W_CTILE,
-  W_PARTIALS, W_ROUND, W_ACCUM, W_RESULT, W_HIST, W_THETA, W_LNW, W_AUX, W_RATIO, W_BINS
+  W_PARTIALS, W_ROUND, W_ACCUM, W_RESULT, W_HIST, W_THETA, W_LNW, W_AUX, W_RATIO, W_BINS, W_ITEM_BLK0,
+  W_ITEM_HOFF, W_ITEM_COP, W_SEG_OFF, W_SEG_CNT, W_ASC, W_AHIST
 };
 
 rift_status fail(rift_ile *h, rift_status s, const char *fmt, ...) {
@@ -367,71 +368,66 @@ rift_status run_plain(rift_ile *h, const Items &it, int64_t stride, const R *the
   return RIFT_OK;
 }
 
-rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const float *theta, float *lnL, float *lnw,
-                     const float *ln_ratio) {
-  // points grouped by MFMA step count T (one persistent launch per group),
-  // costliest first within a group: the kernels take tiles in this order
-  const int n = (int)it_in.point.size();
-  std::vector<int> order(n);
-  std::iota(order.begin(), order.end(), 0);
-  auto Tof = [&](int i) { return h->hp[it_in.point[i]].Mp >> 1; };
-  auto cost = [&](int i) {
-    const PointDev &p = h->hp[it_in.point[i]];
-    return (double)p.K * (p.Mp + 4) * p.n_t;
-  };
-  auto Mof = [&](int i) { return h->hp[it_in.point[i]].M; };
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    if (Tof(a) != Tof(b)) return Tof(a) > Tof(b);
-    if (Mof(a) != Mof(b)) return Mof(a) > Mof(b);
-    return cost(a) > cost(b);
-  });
-  Items it;
-  std::vector<int64_t> samp0(1, 0), mclass_tiles;
-  std::vector<int> bin0(1, 0), class_T, class_item0, mclass_M, mclass_item0;
+// One group of points (already in evaluation order) through the sort, the
+// coefficient pass and the persistent MFMA launches.
+rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const float *theta, float *lnL, float *lnw,
+                           const float *ln_ratio) {
+  std::vector<int64_t> samp0(1, 0), mclass_tiles, hoff;
+  std::vector<int> bin0(1, 0), blk0(1, 0), class_T, class_item0, mclass_M, mclass_item0;
+  int64_t hist_total = 0, cop_floats = 0;
+  int max_item_bins = 1;
   int64_t max_tiles = 0;
-  int Tc = 1;
-  for (int oi : order) {
-    if (it_in.cnt[oi] == 0) continue;
-    const PointDev &p = h->hp[it_in.point[oi]];
+  for (size_t i = 0; i < it.point.size(); i++) {
+    const PointDev &p = h->hp[it.point[i]];
     const int T = p.Mp >> 1;
     if (class_T.empty() || class_T.back() != T) {
       class_T.push_back(T);
-      class_item0.push_back((int)it.point.size());
+      class_item0.push_back((int)i);
     }
+    const int64_t tiles_i = (it.cnt[i] + 15) / 16 + p.n_bins_key + 4;
     if (mclass_M.empty() || mclass_M.back() != p.M) {
       mclass_M.push_back(p.M);
-      mclass_item0.push_back((int)it.point.size());
+      mclass_item0.push_back((int)i);
       mclass_tiles.push_back(0);
     }
-    mclass_tiles.back() += (it_in.cnt[oi] + 15) / 16 + p.n_bins_key + 4;
-    Tc = std::max(Tc, T);
-    it.point.push_back(it_in.point[oi]);
-    it.off.push_back(it_in.off[oi]);
-    it.cnt.push_back(it_in.cnt[oi]);
-    samp0.push_back(samp0.back() + it_in.cnt[oi]);
+    mclass_tiles.back() += tiles_i;
+    samp0.push_back(samp0.back() + it.cnt[i]);
     long long nb = (long long)bin0.back() + p.n_bins_key;
     if (nb > (1 << 28)) return fail(h, RIFT_E_SHAPE, "too many delay bins in one call");
     bin0.push_back((int)nb);
-    max_tiles += (it_in.cnt[oi] + 15) / 16 + p.n_bins_key + 4;
+    const int nblk = (int)((it.cnt[i] + kSortBlock - 1) / kSortBlock);
+    blk0.push_back(blk0.back() + nblk);
+    hoff.push_back(hist_total);
+    hist_total += (int64_t)nblk * p.n_bins_key;
+    max_item_bins = std::max(max_item_bins, p.n_bins_key);
+    max_tiles += tiles_i;
+    cop_floats += tiles_i * p.K * 2 * p.Mp * 16;
   }
   const int ni = (int)it.point.size();
   class_item0.push_back(ni);
   mclass_item0.push_back(ni);
   const int64_t total = samp0.back();
+  if (ni == 0) return RIFT_OK;
   if (total == 0) return RIFT_OK;
   if (total >= (int64_t)1 << 31 || max_tiles >= (int64_t)1 << 26)
     return fail(h, RIFT_E_SHAPE, "more than 2^31 samples in one call");
   MfmaArgs a;
   std::memset(&a, 0, sizeof(a));
   rift_status s;
-  int *d_point, *d_bin0;
-  int64_t *d_off, *d_cnt, *d_samp0;
+  int *d_point, *d_bin0, *d_blk0;
+  int64_t *d_off, *d_cnt, *d_samp0, *d_hoff;
   if ((s = upload(h, W_ITEM_POINT, it.point, &d_point)) != RIFT_OK) return s;
   if ((s = upload(h, W_ITEM_OFF, it.off, &d_off)) != RIFT_OK) return s;
   if ((s = upload(h, W_ITEM_CNT, it.cnt, &d_cnt)) != RIFT_OK) return s;
   if ((s = upload(h, W_ITEM_SAMP0, samp0, &d_samp0)) != RIFT_OK) return s;
   if ((s = upload(h, W_ITEM_BIN0, bin0, &d_bin0)) != RIFT_OK) return s;
+  if ((s = upload(h, W_ITEM_BLK0, blk0, &d_blk0)) != RIFT_OK) return s;
+  if ((s = upload(h, W_ITEM_HOFF, hoff, &d_hoff)) != RIFT_OK) return s;
   a.pts = h->d_pts;
+  a.items.blk0 = d_blk0;
+  a.items.hoff = d_hoff;
+  a.n_sort_blocks = blk0.back();
+  a.max_item_bins = max_item_bins;
   a.items.point = d_point;
   a.items.off = d_off;
   a.items.cnt = d_cnt;
@@ -447,7 +443,6 @@ rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const floa
   a.ln_ratio = ln_ratio;
   a.n_bins = bin0.back();
   a.max_tiles = (int)max_tiles;
-  a.Tc = Tc;
   void *p;
   if ((s = ws_get(h, W_KEY, 4 * total, &p)) != RIFT_OK) return s;
   a.key = (uint32_t *)p;
@@ -455,18 +450,20 @@ rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const floa
   a.nsh = (int16_t *)p;
   if ((s = ws_get(h, W_COUNT, 4 * (size_t)a.n_bins, &p)) != RIFT_OK) return s;
   a.count = (uint32_t *)p;
-  if ((s = ws_get(h, W_CURSOR, 4 * (size_t)a.n_bins, &p)) != RIFT_OK) return s;
-  a.cursor = (uint32_t *)p;
+  if ((s = ws_get(h, W_CURSOR, 4 * (size_t)std::max<int64_t>(hist_total, 1), &p)) != RIFT_OK) return s;
+  a.bhist = (uint32_t *)p;
   if ((s = ws_get(h, W_BINTILE, 4 * (size_t)a.n_bins, &p)) != RIFT_OK) return s;
   a.bin_tile = (uint32_t *)p;
   if ((s = ws_get(h, W_ITEMTILES, 4 * (size_t)(ni + 1), &p)) != RIFT_OK) return s;
   a.item_tiles = (uint32_t *)p;
-  if ((s = ws_get(h, W_PERM, 4 * 16 * (size_t)max_tiles, &p)) != RIFT_OK) return s;
-  a.perm = (uint32_t *)p;
+  if ((s = ws_get(h, W_PERM, sizeof(SampleRec) * 16 * (size_t)max_tiles, &p)) != RIFT_OK) return s;
+  a.rec = (SampleRec *)p;
   if ((s = ws_get(h, W_TILES, 4 * (size_t)max_tiles, &p)) != RIFT_OK) return s;
   a.tile_item = (int *)p;
-  if ((s = ws_get(h, W_COP, sizeof(float) * (size_t)max_tiles * kMaxDet * 4 * Tc * 16, &p)) != RIFT_OK) return s;
+  if ((s = ws_get(h, W_COP, sizeof(float) * (size_t)cop_floats, &p)) != RIFT_OK) return s;
   a.cop = (float *)p;
+  if ((s = ws_get(h, W_ITEM_COP, sizeof(int64_t) * (size_t)ni, &p)) != RIFT_OK) return s;
+  a.item_cop = (int64_t *)p;
   if ((s = ws_get(h, W_CTILE, sizeof(CoefTile) * (size_t)max_tiles, &p)) != RIFT_OK) return s;
   a.ctile = (CoefTile *)p;
   if ((s = ws_get(h, W_CTL, 4 * (1 + kMaxClasses) + 64, &p)) != RIFT_OK) return s;
@@ -480,6 +477,56 @@ rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const floa
   }
   HIPCHK(h, mfma_forward(a, class_T.data(), class_item0.data(), (int)class_T.size(), mclass_M.data(),
                          mclass_item0.data(), mclass_tiles.data(), (int)mclass_M.size(), h->stream, e0, e1));
+  return RIFT_OK;
+}
+
+// Points grouped by MFMA step count T (one persistent launch per group),
+// then mode count, costliest first: the kernels take tiles in this order.
+// The points are evaluated in runs whose workspace stays under a budget.
+rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const float *theta, float *lnL, float *lnw,
+                     const float *ln_ratio) {
+  const int n = (int)it_in.point.size();
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  auto Tof = [&](int i) { return h->hp[it_in.point[i]].Mp >> 1; };
+  auto Mof = [&](int i) { return h->hp[it_in.point[i]].M; };
+  auto cost = [&](int i) {
+    const PointDev &p = h->hp[it_in.point[i]];
+    return (double)p.K * (p.Mp + 4) * p.n_t;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (Tof(a) != Tof(b)) return Tof(a) > Tof(b);
+    if (Mof(a) != Mof(b)) return Mof(a) > Mof(b);
+    return cost(a) > cost(b);
+  });
+  const double budget = 6.0e9;  // bytes of per-sample workspace per run
+  Items grp;
+  double used = 0.0;
+  for (int oi : order) {
+    if (it_in.cnt[oi] == 0) continue;
+    const PointDev &p = h->hp[it_in.point[oi]];
+    int64_t remaining = it_in.cnt[oi], off = it_in.off[oi];
+    while (remaining > 0) {
+      const double per = 4.0 + 8.0 + 44.0 + 40.0 + (double)p.K * 2 * p.Mp * 4 * 1.1;
+      int64_t take = remaining;
+      if (used + per * take > budget) {
+        if (!grp.point.empty()) {
+          rift_status s = run_mfma_group(h, grp, stride, theta, lnL, lnw, ln_ratio);
+          if (s != RIFT_OK) return s;
+          grp = Items();
+          used = 0.0;
+        }
+        take = std::min<int64_t>(remaining, std::max<int64_t>(4096, (int64_t)(budget / per)));
+      }
+      grp.point.push_back(it_in.point[oi]);
+      grp.off.push_back(off);
+      grp.cnt.push_back(take);
+      used += per * take;
+      off += take;
+      remaining -= take;
+    }
+  }
+  if (!grp.point.empty()) return run_mfma_group(h, grp, stride, theta, lnL, lnw, ln_ratio);
   return RIFT_OK;
 }
 
@@ -557,7 +604,46 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
   if (!lnw_out && (s = ws_get(h, W_LNW, sizeof(R) * (size_t)nr, &lw_ws)) != RIFT_OK) return s;
   int *d_prop;
   if ((s = upload(h, W_AUX, seg_prop, &d_prop)) != RIFT_OK) return s;
+  int64_t *d_soff, *d_scnt;
+  if ((s = upload(h, W_SEG_OFF, off, &d_soff)) != RIFT_OK) return s;
+  if ((s = upload(h, W_SEG_CNT, cnt, &d_scnt)) != RIFT_OK) return s;
   const int64_t th_stride = theta_out ? total : nr;
+  // gradient-informed refinement: ascent set of k points per point
+  const bool grad = (mc->flags & RIFT_MC_GRADIENT) && mc->adapt_mask;
+  const int ka = mc->n_ascent > 0 ? mc->n_ascent : 64;
+  const int steps = mc->ascent_steps > 0 ? mc->ascent_steps : 12;
+  const double beta = mc->ascent_mix > 0.0 ? mc->ascent_mix : 0.3;
+  if (grad && (ka > 256 || !(beta + mc->floor_eps < 1.0)))
+    return fail(h, RIFT_E_INVALID, "n_ascent %d (<= 256) or ascent_mix %g (< 1 - floor_eps)", ka, beta);
+  const int na = np * ka;
+  int *a_idx = nullptr;
+  R *a_th = nullptr, *a_g = nullptr, *a_l = nullptr;
+  AscentState *a_st = nullptr;
+  double *ahist = nullptr;
+  Items ita;
+  if (grad) {
+    void *pa;
+    const size_t bytes = sizeof(int) * na + sizeof(R) * (size_t)na * 15 + sizeof(AscentState) * na + 256;
+    if ((s = ws_get(h, W_ASC, bytes, &pa)) != RIFT_OK) return s;
+    char *c = (char *)pa;
+    a_st = (AscentState *)c;
+    c += sizeof(AscentState) * na;
+    a_th = (R *)c;
+    c += sizeof(R) * 7 * (size_t)na;
+    a_g = (R *)c;
+    c += sizeof(R) * 7 * (size_t)na;
+    a_l = (R *)c;
+    c += sizeof(R) * (size_t)na;
+    a_idx = (int *)c;
+    void *ph;
+    if ((s = ws_get(h, W_AHIST, sizeof(double) * 7 * kNB * np, &ph)) != RIFT_OK) return s;
+    ahist = (double *)ph;
+    for (int p = 0; p < np; p++) {
+      ita.point.push_back(p);
+      ita.off.push_back((int64_t)p * ka);
+      ita.cnt.push_back(ka);
+    }
+  }
   Items it;
   for (int p = 0; p < np; p++) {
     it.point.push_back(p);
@@ -579,9 +665,24 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
                                 last ? (rift_ile_result *)d_res : nullptr)) != RIFT_OK)
       return s;
     if (mc->adapt_mask && !last) {
-      const int64_t *d_off = (const int64_t *)h->ws[W_ITEM_OFF].p, *d_cnt = (const int64_t *)h->ws[W_ITEM_CNT].p;
-      HIPCHK(h, adapt_launch<R>((const uint8_t *)bins, nr, lw, d_off, d_cnt, d_prop, np, hbps, round,
-                                (unsigned long long *)hist, h->d_props, mc->adapt_mask, mc->floor_eps, h->stream));
+      if (grad) {
+        HIPCHK(h, ascent_select<R>(lw, th, th_stride, d_soff, d_scnt, np, ka, a_idx, a_th, a_st, h->stream));
+        const bool prof = h->prof;  // the timing hook follows the evaluation launches only
+        h->prof = false;
+        for (int it_s = 0; it_s <= steps; it_s++) {
+          if ((s = run_plain<R>(h, ita, na, a_th, a_l, nullptr, nullptr, nullptr, a_g, true)) != RIFT_OK) {
+            h->prof = prof;
+            return s;
+          }
+          HIPCHK(h, ascent_step<R>(a_th, a_g, a_l, a_st, na, mc->adapt_mask, h->d_min, h->d_max, h->tau_width,
+                                   h->stream));
+        }
+        h->prof = prof;
+        HIPCHK(h, ascent_hist(a_st, ka, np, mc->adapt_mask, h->d_min, h->d_max, h->tau_width, ahist, h->stream));
+      }
+      HIPCHK(h, adapt_launch<R>((const uint8_t *)bins, nr, lw, d_soff, d_scnt, d_prop, np, hbps, round,
+                                (unsigned long long *)hist, h->d_props, mc->adapt_mask, mc->floor_eps, h->stream,
+                                grad ? ahist : nullptr, grad ? beta : 0.0));
     }
   }
   HIPCHK(h, hipMemcpyAsync(out, d_res, sizeof(rift_ile_result) * np, hipMemcpyDeviceToHost, h->stream));

@@ -59,7 +59,11 @@ class Result(C.Structure):
 class MC(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("n_per_round", C.c_int64), ("n_per_point", C.POINTER(C.c_int64)),
                 ("n_rounds", C.c_int), ("adapt_mask", C.c_uint), ("floor_eps", C.c_double),
-                ("reset_proposal", C.c_int)]
+                ("reset_proposal", C.c_int), ("flags", C.c_uint), ("n_ascent", C.c_int),
+                ("ascent_steps", C.c_int), ("ascent_mix", C.c_double)]
+
+
+RIFT_MC_GRADIENT = 1
 
 
 FUNCTIONS = {
@@ -226,9 +230,10 @@ class RiftILE:
         self._check(lib().rift_ile_set_proposal(self.h, point, _dptr(cdf), mask))
 
     def marginalize(self, seed, n_per_point, n_rounds=1, adapt_mask=0, floor_eps=0.1, reset=True,
-                    return_samples=False):
+                    return_samples=False, gradient=False, n_ascent=0, ascent_steps=0, ascent_mix=0.0):
         npp = np.ascontiguousarray(np.broadcast_to(np.asarray(n_per_point, dtype=np.int64), (self.n_points,)))
-        mc = MC(seed, 0, npp.ctypes.data_as(C.POINTER(C.c_int64)), n_rounds, adapt_mask, floor_eps, int(reset))
+        mc = MC(seed, 0, npp.ctypes.data_as(C.POINTER(C.c_int64)), n_rounds, adapt_mask, floor_eps, int(reset),
+                RIFT_MC_GRADIENT if gradient else 0, n_ascent, ascent_steps, ascent_mix)
         res = (Result * self.n_points)()
         th = lw = None
         if return_samples:
