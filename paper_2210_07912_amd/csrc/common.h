@@ -15,6 +15,20 @@
 
 namespace rift {
 
+// Pointers read from device-resident structs are generic to the compiler,
+// and generic (flat) loads are counted by both the vector-memory and the LDS
+// counters, so every LDS wait would also wait for them.  Kernels cast such
+// pointers to the global address space.
+#define RIFT_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const RIFT_GLOBAL T *gp(const T *p) {
+  return (const RIFT_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ RIFT_GLOBAL T *gpw(T *p) {
+  return (RIFT_GLOBAL T *)p;
+}
+
 constexpr int kMaxDet = RIFT_MAX_DET;
 constexpr int kMaxModes = RIFT_MAX_MODES;
 constexpr int kMaxYTerms = 8;   // Wigner-d sum terms for l <= 8

@@ -44,7 +44,7 @@ hipError_t plain_launch(const PlainArgsT<R> &a, int TS, int n_tiles, bool bwd, h
 size_t plain_lds_bytes(int elem, int TS, int rows_cap, int nt_cap, bool bwd);
 
 // ---- FP32 MFMA path -------------------------------------------------------
-constexpr int kMaxClasses = 16;  // one persistent launch per distinct T = Mp / 2
+constexpr int kMaxClasses = 48;  // one persistent launch per distinct (T = Mp / 2, K)
 
 constexpr int kSortBlock = 4096;  // samples per sort block
 constexpr int kLdsBins = 8192;    // delay bins counted in LDS (more: in global memory)
@@ -99,7 +99,7 @@ struct MfmaArgs {
 // classes: runs of points with the same MFMA step count T (evaluation
 // launches) and with the same mode count M (coefficient launches; mclass_tiles
 // bounds the tiles of each run)
-hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_item0, int n_classes,
+hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_K, const int *class_item0, int n_classes,
                         const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles, int n_mclasses,
                         hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 

@@ -249,8 +249,8 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
   const PointDev &p = a.pts[a.items.point[it]];
   const int K = p.K, E = 2 * p.Mp;
   const int M = MC > 0 ? MC : p.M;
-  float *op = a.cop + a.item_cop[it] + (int64_t)(t - a.item_tiles[it]) * K * E * kTS + s;
-  CoefTile *ct = a.ctile + t;
+  RIFT_GLOBAL float *op = gpw(a.cop + a.item_cop[it] + (int64_t)(t - a.item_tiles[it]) * K * E * kTS + s);
+  RIFT_GLOBAL CoefTile *ct = gpw(a.ctile + t);
   bool pad = rec.flag == 0;
   bool valid = rec.flag == 1;
   if (!valid) {
@@ -326,8 +326,8 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
   for (int k = 0; k < K; k++)
     for (int e = 2 * M; e < 2 * p.Mp; e++) op[((size_t)k * E + e) * kTS] = 0.f;
   double q[kMaxDet] = {0.0, 0.0, 0.0}, vr[kMaxDet] = {0.0, 0.0, 0.0}, vi[kMaxDet] = {0.0, 0.0, 0.0};
-  const double *Uq = p.Upk;
-  const double *Vq = p.Vpk;
+  const RIFT_GLOBAL double *Uq = gp(p.Upk);
+  const RIFT_GLOBAL double *Vq = p.Vpk ? gp(p.Vpk) : nullptr;
   auto pair = [&](int idx, double ymr, double ymi, double ypr, double ypi) {
     // conj(Y_m) Y_m' and Y_m Y_m'
     const double pr = ymr * ypr + ymi * ypi, pi = ymr * ypi - ymi * ypr;
@@ -386,7 +386,7 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int T>
+template <int T, int K>
 __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int item_hi, int cls) {
   __shared__ __align__(16) float lds_all[kWaves * kRingFloats];
   const int lane = threadIdx.x & 63;
@@ -402,80 +402,75 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
     if (t >= t_hi) break;
     const int it = __builtin_amdgcn_readfirstlane(a.tile_item[t]);
     const PointDev &p = a.pts[a.items.point[it]];
-    const int K = p.K, NT = p.n_t, P = p.pad, Lpad = p.Lpad;
-    const CoefTile *ct = a.ctile + t;
-    const float *op = a.cop + a.item_cop[it] + (int64_t)(t - a.item_tiles[it]) * K * E * kTS;
+    const int NT = p.n_t, P = p.pad, Lpad = p.Lpad;
+    const RIFT_GLOBAL CoefTile *ct = gp(a.ctile + t);
+    const RIFT_GLOBAL float *op = gp(a.cop + a.item_cop[it] + (int64_t)(t - a.item_tiles[it]) * K * E * kTS);
+    const RIFT_GLOBAL float *Qm = gp(p.Qm);
     const int flag = ct->flag[s];
     if (!__any(flag != 0)) continue;  // padding tile
     const int col = ct->col[s];
     const float Bf = ct->B[s];
     // B operands: element e = g T + tt of sample s
-    float Bop[kMaxDet][T];
-    float w[kMaxDet][4];
-    int base[kMaxDet], sh[kMaxDet];
+    float Bop[K][T];
+    float w[K][4];
+    int base[K], sh[K];
+    bool valid = flag == 1;
 #pragma unroll
-    for (int k = 0; k < kMaxDet; k++) {
+    for (int k = 0; k < K; k++) {
 #pragma unroll
-      for (int tt = 0; tt < T; tt++) Bop[k][tt] = (k < K) ? op[((size_t)k * E + g * T + tt) * kTS + s] : 0.f;
-      int n = ct->n[k][s];
+      for (int tt = 0; tt < T; tt++) Bop[k][tt] = op[((size_t)k * E + g * T + tt) * kTS + s];
+      const int n = ct->n[k][s];
       cr_weights<float>(ct->mu[k][s], w[k]);
       int nmin = wave_min(n);
       if (nmin >= (1 << 28)) nmin = 0;
       base[k] = __builtin_amdgcn_readfirstlane(P + nmin);
-      sh[k] = (flag == 1) ? n - nmin : 0;
+      sh[k] = valid ? n - nmin : 0;
+      if (sh[k] < 0 || sh[k] > 13) {
+        valid = false;
+        sh[k] = 0;
+      }
     }
-    bool valid = flag == 1;
-#pragma unroll
-    for (int k = 0; k < kMaxDet; k++) {
-      if (k >= K) sh[k] = 0;
-      if (sh[k] < 0 || sh[k] > 13) { valid = false; sh[k] = 0; }
-    }
-
     const int JB = (NT + 15) >> 4;
-    // A operands of block 0
-    float Acur[kMaxDet][T], Anext[kMaxDet][T];
+    // A operands of block b: element e = g T + tt, row base + 16 b + s
+    float Acur[K][T], Anext[K][T];
 #pragma unroll
-    for (int k = 0; k < kMaxDet; k++) {
-      const float *qa = p.Qm + ((size_t)k * 4 * T + g * T) * Lpad + base[k] + s;
+    for (int k = 0; k < K; k++) {
+      const RIFT_GLOBAL float *qa = Qm + ((size_t)k * E + g * T) * Lpad + base[k] + s;
 #pragma unroll
-      for (int tt = 0; tt < T; tt++) Acur[k][tt] = (k < K) ? qa[(size_t)tt * Lpad] : 0.f;
+      for (int tt = 0; tt < T; tt++) Acur[k][tt] = qa[(size_t)tt * Lpad];
     }
     float m_run = -INFINITY, s_run = 0.f;
     for (int b = 0; b <= JB; b++) {
       // operands of the next block in flight while this one computes
       if (b < JB) {
 #pragma unroll
-        for (int k = 0; k < kMaxDet; k++) {
-          const float *qa = p.Qm + ((size_t)k * 4 * T + g * T) * Lpad + base[k] + 16 * (b + 1) + s;
+        for (int k = 0; k < K; k++) {
+          const RIFT_GLOBAL float *qa = Qm + ((size_t)k * E + g * T) * Lpad + base[k] + 16 * (b + 1) + s;
 #pragma unroll
-          for (int tt = 0; tt < T; tt++) Anext[k][tt] = (k < K) ? qa[(size_t)tt * Lpad] : 0.f;
+          for (int tt = 0; tt < T; tt++) Anext[k][tt] = qa[(size_t)tt * Lpad];
         }
       }
 #pragma unroll
-      for (int k = 0; k < kMaxDet; k++) {
-        if (k < K) {
-          f4 acc = {0.f, 0.f, 0.f, 0.f};
+      for (int k = 0; k < K; k++) {
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int tt = 0; tt < T; tt++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Acur[k][tt], Bop[k][tt], acc, 0, 0, 0);
-          // acc[v] = z_k[base + 16 b + 4 g + v] of sample s
-          *(f4 *)(ring + (k * 16 + s) * kRS + ((16 * b + 4 * g) & 31)) = acc;
-        }
+        for (int tt = 0; tt < T; tt++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Acur[k][tt], Bop[k][tt], acc, 0, 0, 0);
+        // acc[v] = z_k[base + 16 b + 4 g + v] of sample s
+        *(f4 *)(ring + (k * 16 + s) * kRS + ((16 * b + 4 * g) & 31)) = acc;
       }
       wave_sync();
       if (b >= 1) {
         const int j0 = 16 * (b - 1) + 4 * g;
         float ell[4] = {-Bf, -Bf, -Bf, -Bf};
 #pragma unroll
-        for (int k = 0; k < kMaxDet; k++) {
-          if (k < K) {
-            const float *zr = ring + (k * 16 + s) * kRS;
-            float z[7];
+        for (int k = 0; k < K; k++) {
+          const float *zr = ring + (k * 16 + s) * kRS;
+          float z[7];
 #pragma unroll
-            for (int o = 0; o < 7; o++) z[o] = zr[(j0 + sh[k] + o) & 31];
+          for (int o = 0; o < 7; o++) z[o] = zr[(j0 + sh[k] + o) & 31];
 #pragma unroll
-            for (int i = 0; i < 4; i++)
-              ell[i] += w[k][0] * z[i] + w[k][1] * z[i + 1] + w[k][2] * z[i + 2] + w[k][3] * z[i + 3];
-          }
+          for (int i = 0; i < 4; i++)
+            ell[i] += w[k][0] * z[i] + w[k][1] * z[i + 1] + w[k][2] * z[i + 2] + w[k][3] * z[i + 3];
         }
         float cmax = -INFINITY;
 #pragma unroll
@@ -493,7 +488,7 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
       }
       wave_sync();
 #pragma unroll
-      for (int k = 0; k < kMaxDet; k++)
+      for (int k = 0; k < K; k++)
 #pragma unroll
         for (int tt = 0; tt < T; tt++) Acur[k][tt] = Anext[k][tt];
     }
@@ -507,18 +502,20 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
     float lt = mo + __logf(sc) - __logf((float)NT);
     if (!valid || !isfinite(lt)) lt = NAN;
     if (flag != 0 && g == 0) {
-      if (a.lnL) a.lnL[col] = lt;
-      if (a.lnw) a.lnw[col] = lt + (a.ln_ratio ? a.ln_ratio[col] : 0.f);
+      if (a.lnL) gpw(a.lnL)[col] = lt;
+      if (a.lnw) gpw(a.lnw)[col] = lt + (a.ln_ratio ? gp(a.ln_ratio)[col] : 0.f);
     }
   }
 }
 
 template <int T>
-static void launch_class(const MfmaArgs &a, int lo, int hi, int cls, hipStream_t st) {
-  hipLaunchKernelGGL(mfma_kernel<T>, dim3(a.grid), dim3(256), 0, st, a, lo, hi, cls);
+static void launch_class(const MfmaArgs &a, int K, int lo, int hi, int cls, hipStream_t st) {
+  if (K == 1) hipLaunchKernelGGL((mfma_kernel<T, 1>), dim3(a.grid), dim3(256), 0, st, a, lo, hi, cls);
+  else if (K == 2) hipLaunchKernelGGL((mfma_kernel<T, 2>), dim3(a.grid), dim3(256), 0, st, a, lo, hi, cls);
+  else hipLaunchKernelGGL((mfma_kernel<T, 3>), dim3(a.grid), dim3(256), 0, st, a, lo, hi, cls);
 }
 
-hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_item0, int n_classes,
+hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_K, const int *class_item0, int n_classes,
                         const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles, int n_mclasses,
                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (a.total <= 0) return hipSuccess;
@@ -544,9 +541,10 @@ hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_
   if (ev0) (void)hipEventRecord(ev0, st);
   for (int c = 0; c < n_classes; c++) {
     const int lo = class_item0[c], hi = class_item0[c + 1];
+    const int K = class_K[c];
     switch (class_T[c]) {
 #define RIFT_T_CASE(TT) \
-  case TT: launch_class<TT>(a, lo, hi, c, st); break;
+  case TT: launch_class<TT>(a, K, lo, hi, c, st); break;
       RIFT_T_CASE(1) RIFT_T_CASE(2) RIFT_T_CASE(3) RIFT_T_CASE(4) RIFT_T_CASE(5) RIFT_T_CASE(6) RIFT_T_CASE(7)
       RIFT_T_CASE(8) RIFT_T_CASE(9) RIFT_T_CASE(10) RIFT_T_CASE(11) RIFT_T_CASE(12) RIFT_T_CASE(13)
       RIFT_T_CASE(14) RIFT_T_CASE(15) RIFT_T_CASE(16)

@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgsT<R> args) {
   // (U a)_m and (V a)_m for every (sample, detector, mode), FP64
   for (int idx = tid; idx < TS * K * M; idx += blockDim.x) {
     int s = idx / (K * M), km = idx % (K * M), k = km / M, m = km % M;
-    const double *U = p.U + ((size_t)k * M + m) * M * 2;
+    const RIFT_GLOBAL double *U = gp(p.U) + ((size_t)k * M + m) * M * 2;
     const double *a = a_d + (s * kMaxDet + k) * MM * 2;
     double ur = 0.0, ui = 0.0, vr = 0.0, vi = 0.0;
     for (int mp = 0; mp < M; mp++) {
@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgsT<R> args) {
       ui += xr * bi + xi * br;
     }
     if (p.V) {
-      const double *V = p.V + ((size_t)k * M + m) * M * 2;
+      const RIFT_GLOBAL double *V = gp(p.V) + ((size_t)k * M + m) * M * 2;
       for (int mp = 0; mp < M; mp++) {
         double xr = V[2 * mp], xi = V[2 * mp + 1], br = a[2 * mp], bi = a[2 * mp + 1];
         vr += xr * br - xi * bi;
@@ -179,12 +179,12 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgsT<R> args) {
   for (int pass = 0; pass < passes; pass++) {
     for (int k = 0; k < K; k++) {
       const int rlo = rng[2 * k], rhi = rng[2 * k + 1];
-      const R *Qk = (const R *)p.Q + (size_t)k * p.Lpad * M * 2;
+      const RIFT_GLOBAL R *Qk = gp((const R *)p.Q) + (size_t)k * p.Lpad * M * 2;
       for (int r = rlo + tid; r < rhi; r += blockDim.x) {
         R acc[TS];
 #pragma unroll
         for (int s = 0; s < TS; s++) acc[s] = R(0);
-        const R *qr = Qk + (size_t)r * M * 2;
+        const RIFT_GLOBAL R *qr = Qk + (size_t)r * M * 2;
         for (int m = 0; m < M; m++) {
           R q0 = qr[2 * m], q1 = qr[2 * m + 1];
 #pragma unroll

@@ -373,15 +373,16 @@ rift_status run_plain(rift_ile *h, const Items &it, int64_t stride, const R *the
 rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const float *theta, float *lnL, float *lnw,
                            const float *ln_ratio) {
   std::vector<int64_t> samp0(1, 0), mclass_tiles, hoff;
-  std::vector<int> bin0(1, 0), blk0(1, 0), class_T, class_item0, mclass_M, mclass_item0;
+  std::vector<int> bin0(1, 0), blk0(1, 0), class_T, class_K, class_item0, mclass_M, mclass_item0;
   int64_t hist_total = 0, cop_floats = 0;
   int max_item_bins = 1;
   int64_t max_tiles = 0;
   for (size_t i = 0; i < it.point.size(); i++) {
     const PointDev &p = h->hp[it.point[i]];
     const int T = p.Mp >> 1;
-    if (class_T.empty() || class_T.back() != T) {
+    if (class_T.empty() || class_T.back() != T || class_K.back() != p.K) {
       class_T.push_back(T);
+      class_K.push_back(p.K);
       class_item0.push_back((int)i);
     }
     const int64_t tiles_i = (it.cnt[i] + 15) / 16 + p.n_bins_key + 4;
@@ -475,7 +476,7 @@ rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const f
     HIPCHK(h, hipEventCreate(&e1));
     h->prof_ev.emplace_back(e0, e1);
   }
-  HIPCHK(h, mfma_forward(a, class_T.data(), class_item0.data(), (int)class_T.size(), mclass_M.data(),
+  HIPCHK(h, mfma_forward(a, class_T.data(), class_K.data(), class_item0.data(), (int)class_T.size(), mclass_M.data(),
                          mclass_item0.data(), mclass_tiles.data(), (int)mclass_M.size(), h->stream, e0, e1));
   return RIFT_OK;
 }
@@ -494,8 +495,10 @@ rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const floa
     const PointDev &p = h->hp[it_in.point[i]];
     return (double)p.K * (p.Mp + 4) * p.n_t;
   };
+  auto Kof = [&](int i) { return h->hp[it_in.point[i]].K; };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     if (Tof(a) != Tof(b)) return Tof(a) > Tof(b);
+    if (Kof(a) != Kof(b)) return Kof(a) > Kof(b);
     if (Mof(a) != Mof(b)) return Mof(a) > Mof(b);
     return cost(a) > cost(b);
   });

@@ -331,8 +331,16 @@ def mixed_samples(point, seed, n, frac_near=0.5, tau_width=0.0):
     return th.astype(np.float32).astype(np.float64)
 
 
+# points for Monte Carlo agreement tests: low SNR, so that a few 1e4 samples
+# per round give n_eff in the tens to hundreds and the sigma estimates mean
+# something
+MC_SPECS = [
+    PointSpec(seed=BASE_SEED + 40, dets=("H1", "L1", "V1"), n_modes=5, n_t=100, snr=3.0),
+]
+
+
 def all_specs():
-    out = list(PIN_SPECS)
+    out = list(PIN_SPECS) + list(MC_SPECS)
     for w in WORKLOADS:
         out.extend(workload(w).points)
     return out
