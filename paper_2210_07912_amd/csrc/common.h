@@ -28,6 +28,23 @@ template <typename T>
 __device__ __forceinline__ RIFT_GLOBAL T *gpw(T *p) {
   return (RIFT_GLOBAL T *)p;
 }
+// A pointer the whole wavefront shares, moved to scalar registers, so that
+// loads can use it as their scalar base with a 32-bit per-lane offset.
+template <typename T>
+__device__ __forceinline__ T *uniform_ptr(T *p) {
+  const uint64_t v = (uint64_t)(uintptr_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (T *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+// Tables that no kernel writes while it reads them (per-point U, V) are read
+// through the constant address space: wave-uniform loads from it become
+// scalar loads even in kernels that store to global memory.
+#define RIFT_CONST __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ const RIFT_CONST T *cp(const T *p) {
+  return (const RIFT_CONST T *)p;
+}
 
 constexpr int kMaxDet = RIFT_MAX_DET;
 constexpr int kMaxModes = RIFT_MAX_MODES;
@@ -58,7 +75,7 @@ struct PointDev {
   const double *Upk;           // [pairs m<=m'][kMaxDet][2]: U_mm', off-diagonal doubled
   const double *Vpk;           // same packing of V, or nullptr
   const void *Q;               // plain layout: [K][Lpad][M][2] in the bulk precision
-  const float *Qm;             // MFMA layout (FP32 handles): [K][nblk][Mp/2][64]
+  const float *Qm;             // MFMA layout (FP32 handles): [K][Lpad][2 Mp], zero-padded
   int Mp;                      // modes padded to even
 };
 

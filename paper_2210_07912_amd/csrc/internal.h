@@ -66,6 +66,14 @@ struct CoefTile {
   int flag[16];              // 0 padding, 1 valid, 2 invalid sample
 };
 
+// Up to four tiles of one delay bin, evaluated by one workgroup that stages
+// the rows of Q they share in LDS once for all of them.
+struct WorkUnit {
+  uint32_t tile;    // first tile
+  uint32_t ntiles;  // 1..4
+  uint32_t key;     // the bin, within its point
+};
+
 struct MfmaArgs {
   const PointDev *pts;
   ItemsDev items;
@@ -87,7 +95,10 @@ struct MfmaArgs {
   float *cop;             // per point [tiles][K][2 Mp][16]: B operands of the MFMAs
   int64_t *item_cop;      // [n_items] offset of each point's operands in cop
   CoefTile *ctile;        // [max_tiles]
-  uint32_t *ctl;          // [0]: number of tiles, [1 + c]: tile counter of class c
+  WorkUnit *unit;         // [max_tiles] work units, bins in order, points in order
+  uint32_t *bin_unit;     // [n_bins] first unit of the bin within its item
+  uint32_t *item_units;   // [n_items + 1] unit prefix over items (filled on device)
+  uint32_t *ctl;          // [0]: number of tiles, [1 + c]: unit counter of class c
   int n_bins;
   int max_item_bins;      // largest bin count of one point
   int n_sort_blocks;

@@ -17,8 +17,8 @@
 //
 // Kernels, in launch order:
 //   bin_kernel    integer delays n_k, bin key, per-sort-block bin counts
-//   scan_kernel   per point: offset of each sort block in each bin, tiles
-//                 before each bin
+//   colscan       per point: offset of each sort block in each bin
+//   tilescan      per point: tiles before each bin
 //   item_scan     tiles before each point; per-class tile counters reset
 //   scatter       a 40-byte record (theta, column, n_k) at the sorted slot
 //   tile_item     point of every tile
@@ -41,9 +41,11 @@ namespace rift {
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTS = 16;          // samples per tile (MFMA columns)
-constexpr int kRS = 36;          // floats per ring row (32 used, padded for banks)
+constexpr int kRS = 68;          // floats per ring row: a 32-row ring stored twice, padded for banks
 constexpr int kWaves = 4;        // wavefronts per workgroup
-constexpr int kRingFloats = kMaxDet * kTS * kRS;
+constexpr int kSortThreads = 1024;  // threads per sort block (kSortBlock samples)
+constexpr double kLog2e = 1.4426950408889634074;  // the MFMA path works in base-2 logarithms
+constexpr float kLn2f = 0.693147180559945309f;
 
 __device__ __forceinline__ int item_of_flat(const ItemsDev &it, int64_t f) {
   int lo = 0, hi = it.n_items;  // samp0[lo] <= f < samp0[hi]
@@ -76,7 +78,7 @@ __device__ __forceinline__ int block_item(const ItemsDev &it, int b) {
   return lo;
 }
 
-__global__ void __launch_bounds__(256) bin_kernel(MfmaArgs a) {
+__global__ void __launch_bounds__(kSortThreads) bin_kernel(MfmaArgs a) {
   extern __shared__ uint32_t cnt_l[];
   const int it = block_item(a.items, blockIdx.x);
   const int lb = blockIdx.x - a.items.blk0[it];
@@ -84,11 +86,11 @@ __global__ void __launch_bounds__(256) bin_kernel(MfmaArgs a) {
   const int nb = a.items.bin0[it + 1] - a.items.bin0[it];
   const bool lds = nb <= kLdsBins;
   uint32_t *cnt = lds ? cnt_l : a.bhist + a.items.hoff[it] + (int64_t)lb * nb;
-  for (int i = threadIdx.x; i < nb; i += 256) cnt[i] = 0u;
+  for (int i = threadIdx.x; i < nb; i += kSortThreads) cnt[i] = 0u;
   __syncthreads();
   const int64_t n = a.items.cnt[it];
   const int64_t j0 = (int64_t)lb * kSortBlock, j1 = min(n, j0 + kSortBlock);
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += kSortThreads) {
     const int64_t f = a.items.samp0[it] + j;
     const int64_t col = a.items.off[it] + j;
     double al = a.theta[RIFT_ALPHA * a.stride + col], de = a.theta[RIFT_DELTA * a.stride + col];
@@ -112,48 +114,84 @@ __global__ void __launch_bounds__(256) bin_kernel(MfmaArgs a) {
   __syncthreads();
   if (lds) {
     uint32_t *row = a.bhist + a.items.hoff[it] + (int64_t)lb * nb;
-    for (int i = threadIdx.x; i < nb; i += 256) row[i] = cnt_l[i];
+    for (int i = threadIdx.x; i < nb; i += kSortThreads) row[i] = cnt_l[i];
   }
 }
 
 // ---- 2. per-item scans: block offsets within each bin, tiles before each bin --
-__global__ void __launch_bounds__(256) scan_kernel(MfmaArgs a) {
-  __shared__ uint32_t pt[256];
+// Column scan of the [sort block][bin] histogram of one point: a workgroup
+// takes 64 bins; its four wavefronts each sum a quarter of the sort blocks,
+// then rewrite their quarter as running offsets.  Reads are coalesced along
+// the bins, and every point's bins are spread over many workgroups.
+constexpr int kScanBins = 64;
+
+__global__ void __launch_bounds__(256) colscan_kernel(MfmaArgs a) {
+  __shared__ uint32_t part[4][kScanBins];
+  const int q = threadIdx.x >> 6, bl = threadIdx.x & 63;
+  for (int it = blockIdx.y; it < a.items.n_items; it += gridDim.y) {
+    const int b0 = a.items.bin0[it], nb = a.items.bin0[it + 1] - b0;
+    if ((int)blockIdx.x * kScanBins >= nb) continue;  // uniform over the workgroup
+    const int nblk = a.items.blk0[it + 1] - a.items.blk0[it];
+    const int lb_per = (nblk + 3) / 4;
+    const int b = (int)blockIdx.x * kScanBins + bl;
+    const int lo = min(nblk, q * lb_per), hi = min(nblk, lo + lb_per);
+    uint32_t *h = a.bhist + a.items.hoff[it];
+    uint32_t sum = 0;
+    if (b < nb)
+      for (int lb = lo; lb < hi; lb++) sum += h[(int64_t)lb * nb + b];
+    __syncthreads();  // part[] of the previous item fully read
+    part[q][bl] = sum;
+    __syncthreads();
+    uint32_t run = 0;
+    for (int i = 0; i < q; i++) run += part[i][bl];
+    if (b < nb) {
+      for (int lb = lo; lb < hi; lb++) {
+        const uint32_t v = h[(int64_t)lb * nb + b];
+        h[(int64_t)lb * nb + b] = run;
+        run += v;
+      }
+      if (q == 3) a.count[b0 + b] = run;
+    }
+  }
+}
+
+// tiles of each bin (bins padded to whole tiles), work units of each bin
+// (groups of up to 4 of its tiles), and their prefixes per point
+__global__ void __launch_bounds__(256) tilescan_kernel(MfmaArgs a) {
+  __shared__ uint32_t pt[256], pu[256];
   const int it = blockIdx.x;
   const int b0 = a.items.bin0[it], nb = a.items.bin0[it + 1] - b0;
-  const int nblk = a.items.blk0[it + 1] - a.items.blk0[it];
-  uint32_t *h = a.bhist + a.items.hoff[it];
-  // column scan: offset of each sort block within each bin, and bin totals
-  for (int b = threadIdx.x; b < nb; b += 256) {
-    uint32_t run = 0;
-    for (int lb = 0; lb < nblk; lb++) {
-      uint32_t v = h[(int64_t)lb * nb + b];
-      h[(int64_t)lb * nb + b] = run;
-      run += v;
-    }
-    a.count[b0 + b] = run;
-  }
-  __syncthreads();
   const int per = (nb + 255) / 256;
   const int lo = min(nb, (int)threadIdx.x * per), hi = min(nb, lo + per);
-  uint32_t ct = 0;
-  for (int b = lo; b < hi; b++) ct += (a.count[b0 + b] + kTS - 1) / kTS;
+  uint32_t ct = 0, cu = 0;
+  for (int b = lo; b < hi; b++) {
+    const uint32_t tb = (a.count[b0 + b] + kTS - 1) / kTS;
+    ct += tb;
+    cu += (tb + 3) / 4;
+  }
   pt[threadIdx.x] = ct;
+  pu[threadIdx.x] = cu;
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t rt = 0;
+    uint32_t rt = 0, ru = 0;
     for (int i = 0; i < 256; i++) {
-      uint32_t y = pt[i];
+      uint32_t y = pt[i], z = pu[i];
       pt[i] = rt;
+      pu[i] = ru;
       rt += y;
+      ru += z;
     }
     a.item_tiles[it + 1] = (rt + 3u) & ~3u;  // whole groups of 4 tiles per point
+    a.item_units[it + 1] = ru;
   }
   __syncthreads();
-  uint32_t rt = pt[threadIdx.x];
+  uint32_t rt = pt[threadIdx.x], ru = pu[threadIdx.x];
   for (int b = lo; b < hi; b++) {
+    const uint32_t tb = (a.count[b0 + b] + kTS - 1) / kTS;
     a.bin_tile[b0 + b] = rt;
-    rt += (a.count[b0 + b] + kTS - 1) / kTS;
+    a.bin_unit[b0 + b] = ru;
+    rt += tb;
+    ru += (tb + 3) / 4;
   }
 }
 
@@ -168,6 +206,12 @@ __global__ void item_scan_kernel(MfmaArgs a) {
     }
     a.ctl[0] = r;
     for (int c = 0; c < kMaxClasses; c++) a.ctl[1 + c] = 0;
+    uint32_t u = 0;
+    a.item_units[0] = 0;
+    for (int i = 0; i < a.items.n_items; i++) {
+      u += a.item_units[i + 1];
+      a.item_units[i + 1] = u;
+    }
     // coefficient storage: K 2Mp 16 floats per tile of each point
     int64_t c = 0;
     for (int i = 0; i < a.items.n_items; i++) {
@@ -179,7 +223,7 @@ __global__ void item_scan_kernel(MfmaArgs a) {
 }
 
 // ---- 3. scatter: one record per sample at its (padded) sorted slot ------------
-__global__ void __launch_bounds__(256) scatter_kernel(MfmaArgs a) {
+__global__ void __launch_bounds__(kSortThreads) scatter_kernel(MfmaArgs a) {
   extern __shared__ uint32_t cur_l[];
   const int it = block_item(a.items, blockIdx.x);
   const int lb = blockIdx.x - a.items.blk0[it];
@@ -188,13 +232,13 @@ __global__ void __launch_bounds__(256) scatter_kernel(MfmaArgs a) {
   uint32_t *cur = lds ? cur_l : a.bhist + a.items.hoff[it] + (int64_t)lb * nb;
   if (lds) {
     const uint32_t *row = a.bhist + a.items.hoff[it] + (int64_t)lb * nb;
-    for (int i = threadIdx.x; i < nb; i += 256) cur_l[i] = row[i];
+    for (int i = threadIdx.x; i < nb; i += kSortThreads) cur_l[i] = row[i];
   }
   __syncthreads();
   const int64_t n = a.items.cnt[it];
   const int64_t j0 = (int64_t)lb * kSortBlock, j1 = min(n, j0 + kSortBlock);
   const uint32_t tbase = a.item_tiles[it];
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += kSortThreads) {
     const int64_t f = a.items.samp0[it] + j;
     const int64_t col = a.items.off[it] + j;
     const uint32_t key = a.key[f];
@@ -222,6 +266,22 @@ __global__ void __launch_bounds__(256) tile_item_kernel(MfmaArgs a) {
     if (a.item_tiles[mid] <= t) lo = mid; else hi = mid;
   }
   a.tile_item[t] = lo;
+}
+
+// work units of every bin: consecutive runs of up to 4 of its tiles
+__global__ void __launch_bounds__(256) unit_kernel(MfmaArgs a) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  if (g >= a.n_bins) return;
+  const int it = item_of_bin(a.items, g);
+  const uint32_t tb = (a.count[g] + kTS - 1) / kTS;
+  const uint32_t t0 = a.item_tiles[it] + a.bin_tile[g], u0 = a.item_units[it] + a.bin_unit[g];
+  for (uint32_t c = 0; 4 * c < tb; c++) {
+    WorkUnit w;
+    w.tile = t0 + 4 * c;
+    w.ntiles = min(4u, tb - 4 * c);
+    w.key = (uint32_t)(g - a.items.bin0[it]);
+    a.unit[u0 + c] = w;
+  }
 }
 
 // ---- 4. per-sample coefficients (FP64), tile-major ---------------------------
@@ -270,6 +330,7 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
 #pragma unroll
   for (int d = 0; d < 7; d++) th[d] = (double)rec.th[d];
   const double x = p.d_ref / th[RIFT_DIST];
+  const double xl = x * kLog2e;
   SkyTrig tr = sky_trig(th[RIFT_ALPHA], th[RIFT_DELTA], th[RIFT_PSI], p.gmst);
   double Fr[kMaxDet], Fi[kMaxDet];
 #pragma unroll
@@ -317,7 +378,8 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
 #pragma unroll
     for (int k = 0; k < kMaxDet; k++) {
       if (k < K) {
-        double ar = x * (Fr[k] * yr - Fi[k] * yi), ai = x * (Fr[k] * yi + Fi[k] * yr);
+        // in base-2 units (times log2 e) for the evaluation kernel's exp2/log2
+        double ar = xl * (Fr[k] * yr - Fi[k] * yi), ai = xl * (Fr[k] * yi + Fi[k] * yr);
         op[((size_t)k * E + 2 * m) * kTS] = (float)ar;
         op[((size_t)k * E + 2 * m + 1) * kTS] = (float)ai;
       }
@@ -326,8 +388,8 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
   for (int k = 0; k < K; k++)
     for (int e = 2 * M; e < 2 * p.Mp; e++) op[((size_t)k * E + e) * kTS] = 0.f;
   double q[kMaxDet] = {0.0, 0.0, 0.0}, vr[kMaxDet] = {0.0, 0.0, 0.0}, vi[kMaxDet] = {0.0, 0.0, 0.0};
-  const RIFT_GLOBAL double *Uq = gp(p.Upk);
-  const RIFT_GLOBAL double *Vq = p.Vpk ? gp(p.Vpk) : nullptr;
+  const RIFT_CONST double *Uq = cp(p.Upk);
+  const RIFT_CONST double *Vq = p.Vpk ? cp(p.Vpk) : nullptr;
   auto pair = [&](int idx, double ymr, double ymi, double ypr, double ypi) {
     // conj(Y_m) Y_m' and Y_m Y_m'
     const double pr = ymr * ypr + ymi * ypi, pi = ymr * ypi - ymi * ypr;
@@ -369,7 +431,7 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
       b += f2 * q[k] + (F2r * vr[k] - F2i * vi[k]);
     }
   }
-  ct->B[s] = (float)(0.25 * x * x * b);
+  ct->B[s] = (float)(0.25 * x * x * b * kLog2e);
   ct->col[s] = (int)col;
   ct->flag[s] = 1;
 }
@@ -386,133 +448,275 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Element of the (re, im)-interleaved operand vector (length 2 Mp = 4 T) that
+// MFMA instruction tt of a detector takes in lane group g.  For the first
+// 4 (T / 4) instructions, lane group g holds elements 16 j + 4 g .. 16 j + 4 g + 3
+// of quad j = tt / 4, one per instruction, so a lane fetches them with one
+// 16-byte load; the other T % 4 instructions take element 16 (T / 4) + 4 r + g.
+// The B operands use the same assignment, so the sum over elements is complete.
+template <int T>
+__device__ __forceinline__ int op_elem(int tt, int g) {
+  constexpr int J = T / 4;
+  return tt < 4 * J ? 16 * (tt >> 2) + 4 * g + (tt & 3) : 16 * J + 4 * (tt - 4 * J) + g;
+}
+
+// Row stride (floats) of a staged block of Q in LDS: 4T elements, padded to
+// an odd number of 16-byte groups so that the 16-byte reads of 8 consecutive
+// rows fall in distinct banks.
+template <int T>
+constexpr int stage_stride() {
+  return 4 * T + ((T % 2 == 0) ? 4 : 0);
+}
+
+// One workgroup per work unit: its four wavefronts take the unit's tiles
+// (wavefronts past ntiles only help stage).  The rows of block b of every
+// detector are loaded once per workgroup, coalesced, into a double-buffered
+// LDS stage; each wavefront reads its MFMA A operands from there.  Base row
+// of detector k: the lower edge of the unit's delay bin, so every sample's
+// stencil starts 0..bin_w-1 rows above it.
 template <int T, int K>
 __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int item_hi, int cls) {
-  __shared__ __align__(16) float lds_all[kWaves * kRingFloats];
-  const int lane = threadIdx.x & 63;
-  float *ring = lds_all + (threadIdx.x >> 6) * kRingFloats;  // [det][16][kRS]
+  constexpr int E = 4 * T, J = T / 4, R = T % 4;
+  constexpr int JA = J > 0 ? J : 1, RA = R > 0 ? R : 1;
+  constexpr int ES = stage_stride<T>();
+  constexpr int SF = K * kTS * ES;  // floats of one staged block
+  __shared__ __align__(16) float ring_all[kWaves * K * kTS * kRS];
+  __shared__ __align__(16) float stage[3][SF];  // block b in buffer b % 3
+  __shared__ WorkUnit unit_sh;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float *ring = ring_all + wave * (K * kTS * kRS);  // [det][sample][kRS]
   const int s = lane & 15, g = lane >> 4;
-  const uint32_t t_lo = a.item_tiles[item_lo], t_hi = a.item_tiles[item_hi];
-  constexpr int E = 4 * T;
+  const uint32_t u_lo = a.item_units[item_lo], u_hi = a.item_units[item_hi];
+  // staging: thread i < 16 T copies 16-byte group i of the 16 rows x 4 T
+  // floats of a detector's block (row i / T, group i % T)
+  const int tid = threadIdx.x;
+  const bool st_on = tid < 16 * T;
+  const uint32_t st_goff = 16u * (uint32_t)tid;                         // bytes into the block
+  const int st_loff = (tid / T) * ES + 4 * (tid % T);                   // floats into the stage
 
   for (;;) {
-    uint32_t t = 0;
-    if (lane == 0) t = t_lo + atomicAdd(&a.ctl[1 + cls], 1u);
-    t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
-    if (t >= t_hi) break;
-    const int it = __builtin_amdgcn_readfirstlane(a.tile_item[t]);
+    if (tid == 0) {
+      const uint32_t u = u_lo + atomicAdd(&a.ctl[1 + cls], 1u);
+      WorkUnit w;
+      if (u < u_hi) {
+        w = a.unit[u];
+      } else {
+        w.tile = 0xffffffffu;
+        w.ntiles = 0;
+        w.key = 0;
+      }
+      unit_sh = w;
+    }
+    __syncthreads();
+    const uint32_t t0 = __builtin_amdgcn_readfirstlane(unit_sh.tile);
+    const int ntiles = __builtin_amdgcn_readfirstlane(unit_sh.ntiles);
+    uint32_t key = __builtin_amdgcn_readfirstlane(unit_sh.key);
+    if (t0 == 0xffffffffu) break;  // the same for the whole workgroup
+    const bool active = wave < ntiles;
+    const uint32_t t = t0 + (active ? wave : 0);
+    const int it = __builtin_amdgcn_readfirstlane(a.tile_item[t0]);
     const PointDev &p = a.pts[a.items.point[it]];
     const int NT = p.n_t, P = p.pad, Lpad = p.Lpad;
+    // detector k of the bin: key digit q_k; lowest integer delay of the bin
+    const RIFT_GLOBAL float *qk[K];
+    int lo_k[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const int q = (int)(key % (uint32_t)p.nq);
+      key /= (uint32_t)p.nq;
+      lo_k[k] = q * p.bin_w - P;
+      qk[k] = gp(uniform_ptr(p.Qm + (size_t)(k * Lpad + P + lo_k[k]) * E));
+    }
     const RIFT_GLOBAL CoefTile *ct = gp(a.ctile + t);
     const RIFT_GLOBAL float *op = gp(a.cop + a.item_cop[it] + (int64_t)(t - a.item_tiles[it]) * K * E * kTS);
-    const RIFT_GLOBAL float *Qm = gp(p.Qm);
-    const int flag = ct->flag[s];
-    if (!__any(flag != 0)) continue;  // padding tile
+    const int flag = active ? ct->flag[s] : 0;
     const int col = ct->col[s];
-    const float Bf = ct->B[s];
-    // B operands: element e = g T + tt of sample s
+    const float Bf = active ? ct->B[s] : 0.f;
     float Bop[K][T];
     float w[K][4];
-    int base[K], sh[K];
+    int sh[K];
     bool valid = flag == 1;
 #pragma unroll
     for (int k = 0; k < K; k++) {
 #pragma unroll
-      for (int tt = 0; tt < T; tt++) Bop[k][tt] = op[((size_t)k * E + g * T + tt) * kTS + s];
-      const int n = ct->n[k][s];
+      for (int tt = 0; tt < T; tt++) Bop[k][tt] = active ? op[((size_t)k * E + op_elem<T>(tt, g)) * kTS + s] : 0.f;
       cr_weights<float>(ct->mu[k][s], w[k]);
-      int nmin = wave_min(n);
-      if (nmin >= (1 << 28)) nmin = 0;
-      base[k] = __builtin_amdgcn_readfirstlane(P + nmin);
-      sh[k] = valid ? n - nmin : 0;
-      if (sh[k] < 0 || sh[k] > 13) {
+      sh[k] = valid ? ct->n[k][s] - lo_k[k] : 0;
+      if (sh[k] < 0 || sh[k] > kTS - 3) {
         valid = false;
         sh[k] = 0;
       }
     }
     const int JB = (NT + 15) >> 4;
-    // A operands of block b: element e = g T + tt, row base + 16 b + s
-    float Acur[K][T], Anext[K][T];
+    // z ring: block c in rows 16 (c % 3) .. + 15 of a 64-row ring (slot 0
+    // also in rows 48..63), so the 7 rows a window read needs are contiguous
+    const float *rz[K];
 #pragma unroll
-    for (int k = 0; k < K; k++) {
-      const RIFT_GLOBAL float *qa = Qm + ((size_t)k * E + g * T) * Lpad + base[k] + s;
+    for (int k = 0; k < K; k++) rz[k] = ring + (k * kTS + s) * kRS + 4 * g + sh[k];
+    float *const wz = ring + s * kRS + 4 * g;
+    const float *const sa = &stage[0][s * ES + 4 * g];       // this lane's quads in buffer 0
+    const float *const st = &stage[0][s * ES + 16 * J + g];  // and the rest
+    const int rem = NT - 16 * (JB - 1);
+    float last_pen[4];  // -inf for window samples past n_t in the last block
 #pragma unroll
-      for (int tt = 0; tt < T; tt++) Acur[k][tt] = qa[(size_t)tt * Lpad];
-    }
-    float m_run = -INFINITY, s_run = 0.f;
-    for (int b = 0; b <= JB; b++) {
-      // operands of the next block in flight while this one computes
-      if (b < JB) {
+    for (int i = 0; i < 4; i++) last_pen[i] = (4 * g + i < rem) ? 0.f : -INFINITY;
+
+    f4 pre[K];
+    auto stage_load = [&](int blk) {
+      if (st_on) {
+        const uint32_t ob = (uint32_t)(64 * E) * (uint32_t)blk + st_goff;
 #pragma unroll
-        for (int k = 0; k < K; k++) {
-          const RIFT_GLOBAL float *qa = Qm + ((size_t)k * E + g * T) * Lpad + base[k] + 16 * (b + 1) + s;
-#pragma unroll
-          for (int tt = 0; tt < T; tt++) Anext[k][tt] = qa[(size_t)tt * Lpad];
-        }
+        for (int k = 0; k < K; k++) pre[k] = *(const RIFT_GLOBAL f4 *)((const RIFT_GLOBAL char *)qk[k] + ob);
       }
+    };
+    auto stage_store = [&](auto buf_c) {
+      constexpr int BUF = decltype(buf_c)::value;
+      if (st_on) {
+#pragma unroll
+        for (int k = 0; k < K; k++) *(f4 *)(&stage[BUF][k * kTS * ES + st_loff]) = pre[k];
+      }
+    };
+    // block in buffer BUF on the matrix cores; z_k[base + 16 b + 4 g + v] of
+    // sample s -> ring slot BUF (the ring slot of a block is its buffer)
+    auto product = [&](auto buf_c) {
+      constexpr int BUF = decltype(buf_c)::value;
+      const float *sb = sa + BUF * SF;
+      f4 Aq[K][JA];
+      float At[K][RA];
 #pragma unroll
       for (int k = 0; k < K; k++) {
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int tt = 0; tt < T; tt++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Acur[k][tt], Bop[k][tt], acc, 0, 0, 0);
-        // acc[v] = z_k[base + 16 b + 4 g + v] of sample s
-        *(f4 *)(ring + (k * 16 + s) * kRS + ((16 * b + 4 * g) & 31)) = acc;
+        for (int j = 0; j < J; j++) Aq[k][j] = *(const f4 *)(sb + k * kTS * ES + 16 * j);
+#pragma unroll
+        for (int r = 0; r < R; r++) At[k][r] = st[BUF * SF + k * kTS * ES + 4 * r];
       }
-      wave_sync();
-      if (b >= 1) {
-        const int j0 = 16 * (b - 1) + 4 * g;
-        float ell[4] = {-Bf, -Bf, -Bf, -Bf};
+      f4 acc[K];
+#pragma unroll
+      for (int tt = 0; tt < T; tt++)
 #pragma unroll
         for (int k = 0; k < K; k++) {
-          const float *zr = ring + (k * 16 + s) * kRS;
-          float z[7];
-#pragma unroll
-          for (int o = 0; o < 7; o++) z[o] = zr[(j0 + sh[k] + o) & 31];
-#pragma unroll
-          for (int i = 0; i < 4; i++)
-            ell[i] += w[k][0] * z[i] + w[k][1] * z[i + 1] + w[k][2] * z[i + 2] + w[k][3] * z[i + 3];
+          const float av = tt < 4 * J ? Aq[k][tt < 4 * J ? tt >> 2 : 0][tt & 3] : At[k][tt < 4 * J ? 0 : tt - 4 * J];
+          acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, Bop[k][tt], tt == 0 ? f4{0.f, 0.f, 0.f, 0.f} : acc[k], 0,
+                                                        0, 0);
         }
-        float cmax = -INFINITY;
 #pragma unroll
-        for (int i = 0; i < 4; i++)
-          if (j0 + i < NT) cmax = fmaxf(cmax, ell[i]);
-        const float mn = fmaxf(m_run, cmax);
-        if (mn > -INFINITY) {
-          float acc = (m_run > -INFINITY) ? s_run * __expf(m_run - mn) : 0.f;
+      for (int k = 0; k < K; k++) {
+        *(f4 *)(wz + k * kTS * kRS + 16 * BUF) = acc[k];
+        if constexpr (BUF == 0) *(f4 *)(wz + k * kTS * kRS + 48) = acc[k];
+      }
+    };
+    // window samples 16 c + 4 g + i (i < 4) of the block in ring slot SL:
+    // interpolation, then the log-sum-exp with a lazy reference m_run: sums
+    // are kept as exp2(ell - m_run), m_run is the first block's maximum and
+    // moves only when a value exceeds it by 64, which keeps every sum far
+    // from overflow while terms lost below it are under 2^-126 of the sum
+    float m_run = 0.f, s_run = 0.f;
+    auto window = [&](auto sl_c, bool last, bool first) {
+      constexpr int SL = decltype(sl_c)::value;
+      const float base = -Bf - m_run;
+      float ell[4];
 #pragma unroll
-          for (int i = 0; i < 4; i++)
-            if (j0 + i < NT) acc += __expf(ell[i] - mn);
-          s_run = acc;
-          m_run = mn;
+      for (int i = 0; i < 4; i++) ell[i] = last ? base + last_pen[i] : base;
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        const float *zr = rz[k] + 16 * SL;
+        float z[7];
+#pragma unroll
+        for (int o = 0; o < 7; o++) z[o] = zr[o];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          ell[i] = fmaf(w[k][0], z[i], ell[i]);
+          ell[i] = fmaf(w[k][1], z[i + 1], ell[i]);
+          ell[i] = fmaf(w[k][2], z[i + 2], ell[i]);
+          ell[i] = fmaf(w[k][3], z[i + 3], ell[i]);
         }
       }
-      wave_sync();
+      const float cmax = fmaxf(fmaxf(ell[0], ell[1]), fmaxf(ell[2], ell[3]));
+      if ((first || cmax > 64.f) && cmax > -3.0e38f) {  // rare after the first block
+        // (the first block starts from an empty sum; its maximum can be far
+        // below zero, where exp2(-cmax) would overflow)
+        s_run = first ? 0.f : s_run * __builtin_amdgcn_exp2f(-cmax);
+        m_run += cmax;
 #pragma unroll
-      for (int k = 0; k < K; k++)
+        for (int i = 0; i < 4; i++) ell[i] -= cmax;
+      }
 #pragma unroll
-        for (int tt = 0; tt < T; tt++) Acur[k][tt] = Anext[k][tt];
+      for (int i = 0; i < 4; i++) s_run += __builtin_amdgcn_exp2f(ell[i]);
+    };
+    using C0 = std::integral_constant<int, 0>;
+    using C1 = std::integral_constant<int, 1>;
+    using C2 = std::integral_constant<int, 2>;
+    // step b (buffer and ring slot b % 3): stage block b + 1, the MFMAs of
+    // block b, the window samples of block b - 2 (ring slot (b + 1) % 3)
+    auto step = [&](auto ph_c, int b) {
+      constexpr int PH = decltype(ph_c)::value;
+      constexpr int NX = (PH + 1) % 3;
+      stage_load(min(b + 1, JB));
+      if (active) {
+        product(ph_c);
+        if (b >= 2) window(std::integral_constant<int, NX>{}, false, b == 2);
+      }
+      stage_store(std::integral_constant<int, NX>{});
+      __syncthreads();
+    };
+
+    stage_load(0);
+    stage_store(C0{});
+    __syncthreads();
+    step(C0{}, 0);
+    step(C1{}, 1);
+    int b = 2;
+    for (; b + 2 <= JB; b += 3) {
+      step(C2{}, b);
+      step(C0{}, b + 1);
+      step(C1{}, b + 2);
     }
-    // combine the four lanes of each sample
-    float mo = m_run;
-    mo = fmaxf(mo, __shfl_xor(mo, 16));
-    mo = fmaxf(mo, __shfl_xor(mo, 32));
-    float sc = (m_run > -INFINITY) ? s_run * __expf(m_run - mo) : 0.f;
-    sc += __shfl_xor(sc, 16);
-    sc += __shfl_xor(sc, 32);
-    float lt = mo + __logf(sc) - __logf((float)NT);
-    if (!valid || !isfinite(lt)) lt = NAN;
-    if (flag != 0 && g == 0) {
-      if (a.lnL) gpw(a.lnL)[col] = lt;
-      if (a.lnw) gpw(a.lnw)[col] = lt + (a.ln_ratio ? gp(a.ln_ratio)[col] : 0.f);
+    if (b <= JB) step(C2{}, b++);
+    if (b <= JB) step(C0{}, b++);
+    // the last window block, c = JB - 1, in ring slot (JB - 1) % 3
+    if (active) {
+      wave_sync();
+      const int sl = (JB - 1) % 3;
+      if (sl == 0) window(C0{}, true, JB == 1);
+      else if (sl == 1) window(C1{}, true, JB == 1);
+      else window(C2{}, true, JB == 1);
+    }
+    if (active) {
+      // combine the four lanes of each sample (base 2), then ln L_t
+      float mo = m_run;
+      mo = fmaxf(mo, __shfl_xor(mo, 16));
+      mo = fmaxf(mo, __shfl_xor(mo, 32));
+      float sc = s_run * __builtin_amdgcn_exp2f(m_run - mo);
+      sc += __shfl_xor(sc, 16);
+      sc += __shfl_xor(sc, 32);
+      float lt = (mo + __log2f(sc)) * kLn2f - __logf((float)NT);
+      if (!valid || !isfinite(lt)) lt = NAN;
+      if (flag != 0 && g == 0) {
+        if (a.lnL) gpw(a.lnL)[col] = lt;
+        if (a.lnw) gpw(a.lnw)[col] = lt + (a.ln_ratio ? gp(a.ln_ratio)[col] : 0.f);
+      }
     }
   }
 }
 
+// persistent grid: as many workgroups as the device keeps resident
+template <int T, int K>
+static void launch_tk(const MfmaArgs &a, int lo, int hi, int cls, hipStream_t st) {
+  static int per_cu = 0;
+  if (per_cu == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mfma_kernel<T, K>, 256, 0) != hipSuccess || nb < 1) nb = 1;
+    per_cu = nb;
+  }
+  const int grid = std::max(1, a.grid / 4 * per_cu);  // a.grid = 4 per compute unit
+  hipLaunchKernelGGL((mfma_kernel<T, K>), dim3(grid), dim3(256), 0, st, a, lo, hi, cls);
+}
+
 template <int T>
 static void launch_class(const MfmaArgs &a, int K, int lo, int hi, int cls, hipStream_t st) {
-  if (K == 1) hipLaunchKernelGGL((mfma_kernel<T, 1>), dim3(a.grid), dim3(256), 0, st, a, lo, hi, cls);
-  else if (K == 2) hipLaunchKernelGGL((mfma_kernel<T, 2>), dim3(a.grid), dim3(256), 0, st, a, lo, hi, cls);
-  else hipLaunchKernelGGL((mfma_kernel<T, 3>), dim3(a.grid), dim3(256), 0, st, a, lo, hi, cls);
+  if (K == 1) launch_tk<T, 1>(a, lo, hi, cls, st);
+  else if (K == 2) launch_tk<T, 2>(a, lo, hi, cls, st);
+  else launch_tk<T, 3>(a, lo, hi, cls, st);
 }
 
 hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_K, const int *class_item0, int n_classes,
@@ -522,11 +726,14 @@ hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_
   hipError_t e = fill_u32((uint32_t *)a.rec, (int64_t)kTS * a.max_tiles * (sizeof(SampleRec) / 4), 0u, st);
   if (e != hipSuccess) return e;
   const size_t lds = sizeof(uint32_t) * (size_t)std::min(a.max_item_bins, kLdsBins);
-  hipLaunchKernelGGL(bin_kernel, dim3(a.n_sort_blocks), dim3(256), lds, st, a);
-  hipLaunchKernelGGL(scan_kernel, dim3(a.items.n_items), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(bin_kernel, dim3(a.n_sort_blocks), dim3(kSortThreads), lds, st, a);
+  hipLaunchKernelGGL(colscan_kernel, dim3((unsigned)((a.max_item_bins + kScanBins - 1) / kScanBins), std::min(a.items.n_items, 65535)),
+                     dim3(256), 0, st, a);
+  hipLaunchKernelGGL(tilescan_kernel, dim3(a.items.n_items), dim3(256), 0, st, a);
   hipLaunchKernelGGL(item_scan_kernel, dim3(1), dim3(64), 0, st, a);
-  hipLaunchKernelGGL(scatter_kernel, dim3(a.n_sort_blocks), dim3(256), lds, st, a);
+  hipLaunchKernelGGL(scatter_kernel, dim3(a.n_sort_blocks), dim3(kSortThreads), lds, st, a);
   hipLaunchKernelGGL(tile_item_kernel, dim3((unsigned)((a.max_tiles + 255) / 256)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(unit_kernel, dim3((unsigned)((a.n_bins + 255) / 256)), dim3(256), 0, st, a);
   for (int c = 0; c < n_mclasses; c++) {
     const int lo = mclass_item0[c], hi = mclass_item0[c + 1];
     const dim3 grid((unsigned)(((int64_t)kTS * mclass_tiles[c] + 63) / 64));

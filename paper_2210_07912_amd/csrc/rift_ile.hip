@@ -57,8 +57,9 @@ enum WsId {
   W_ITEM_POINT, W_ITEM_OFF, W_ITEM_CNT, W_ITEM_TILE0, W_ITEM_SAMP0, W_ITEM_BIN0,
   W_KEY, W_NSH, W_COUNT, W_CURSOR, W_COP, W_BINTILE, W_ITEMTILES, W_PERM, W_TILES, W_CTL, W_CTILE,
   W_PARTIALS, W_ROUND, W_ACCUM, W_RESULT, W_HIST, W_THETA, W_LNW, W_AUX, W_RATIO, W_BINS, W_ITEM_BLK0,
-  W_ITEM_HOFF, W_ITEM_COP, W_SEG_OFF, W_SEG_CNT, W_ASC, W_AHIST
+  W_ITEM_HOFF, W_ITEM_COP, W_SEG_OFF, W_SEG_CNT, W_ASC, W_AHIST, W_UNIT, W_BINUNIT, W_ITEMUNITS, W_COUNT_IDS
 };
+static_assert(W_COUNT_IDS <= 40, "workspace table too small");
 
 rift_status fail(rift_ile *h, rift_status s, const char *fmt, ...) {
   char buf[512];
@@ -283,14 +284,15 @@ rift_status build_point(rift_ile *h, const rift_ile_point &q, PointDev &p) {
     HIPCHK(h, hipMemcpy(d, qv.data(), sizeof(R) * qv.size(), hipMemcpyHostToDevice));
     p.Q = d;
   }
-  // Q for the matrix cores (FP32 handles): [K][2 Mp][Lpad], element e = 2m + part
+  // Q for the matrix cores (FP32 handles): [K][Lpad][2 Mp], element e = 2m + part,
+  // zero past M and past L
   if (sizeof(R) == 4) {
     const int E = 2 * p.Mp;
     std::vector<float> qm((size_t)K * E * p.Lpad, 0.f);
     for (int k = 0; k < K; k++)
       for (int r = 0; r < p.L; r++)
         for (int e = 0; e < 2 * M; e++)
-          qm[((size_t)k * E + e) * p.Lpad + r] = (float)q.Q[((size_t)k * p.L + r) * M * 2 + e];
+          qm[((size_t)k * p.Lpad + r) * E + e] = (float)q.Q[((size_t)k * p.L + r) * M * 2 + e];
     HIPCHK(h, hipMalloc(&d, sizeof(float) * qm.size()));
     h->owned.push_back(d);
     HIPCHK(h, hipMemcpy(d, qm.data(), sizeof(float) * qm.size(), hipMemcpyHostToDevice));
@@ -467,6 +469,12 @@ rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const f
   a.item_cop = (int64_t *)p;
   if ((s = ws_get(h, W_CTILE, sizeof(CoefTile) * (size_t)max_tiles, &p)) != RIFT_OK) return s;
   a.ctile = (CoefTile *)p;
+  if ((s = ws_get(h, W_UNIT, sizeof(WorkUnit) * (size_t)max_tiles, &p)) != RIFT_OK) return s;
+  a.unit = (WorkUnit *)p;
+  if ((s = ws_get(h, W_BINUNIT, 4 * (size_t)a.n_bins, &p)) != RIFT_OK) return s;
+  a.bin_unit = (uint32_t *)p;
+  if ((s = ws_get(h, W_ITEMUNITS, 4 * (size_t)(ni + 1), &p)) != RIFT_OK) return s;
+  a.item_units = (uint32_t *)p;
   if ((s = ws_get(h, W_CTL, 4 * (1 + kMaxClasses) + 64, &p)) != RIFT_OK) return s;
   a.ctl = (uint32_t *)p;
   a.grid = h->n_cu * 4;
