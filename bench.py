@@ -23,6 +23,12 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp32_mfma_tflops": 157.3, "fp64_tflops": 78.6, "hbm_gbs": 8000.0}
 
+# HBM bytes per launch of the evaluation kernel for the default workload, from
+# rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0) passes, the factors read
+# off a plain device copy (profiles/mfma_kernel_single_1e6.md).  It describes
+# the kernel as it was measured and is reported for that workload only.
+MEASURED_TRAFFIC = {"single": 719766560.0}
+
 
 def flops_per_eval(K, M, n_t):
     """Algorithmic FLOPs of one time-marginalized evaluation: the contraction
@@ -99,10 +105,12 @@ def main():
     dt = (t1 - t0) / args.steps
     value = evals_per_step / dt
 
-    # roofline of the dominant kernel (the evaluation kernel)
+    # roofline of the dominant kernel (the evaluation kernel): algorithmic
+    # FLOP of the timed steps spread over its launches (a step makes one
+    # launch per round and class of points), over its average duration
     per = flops_per_grad if grad else flops_per_eval
-    fl = sum(c * per(p["det_pos"].shape[0], len(p["ell"]), p["n_t"]) for c, p in zip(counts, pts))
-    fl_per_launch = fl  # one evaluation launch per round covers every point
+    fl = rounds * sum(c * per(p["det_pos"].shape[0], len(p["ell"]), p["n_t"]) for c, p in zip(counts, pts))
+    fl_per_launch = fl * args.steps / max(k_launches, 1)
     k_avg_ms = k_ms / max(k_launches, 1)
     achieved = fl_per_launch / (k_avg_ms * 1e-3) / 1e12 if k_launches else None
     dtype = "f32" if w.precision == "fp32" else "f64"
@@ -110,9 +118,11 @@ def main():
     # the plain kernel is FP32 or FP64 vector-ALU bound (no packed FP32: 78.6)
     peak = PEAK["fp32_mfma_tflops"] if mfma else PEAK["fp64_tflops"]
     roof = {"bound": "mfma" if mfma else "alu", "achieved": achieved, "peak": peak,
-            "unit": "TFLOP/s", "frac": (achieved / peak) if achieved else None, "traffic": None,
+            "unit": "TFLOP/s", "frac": (achieved / peak) if achieved else None,
+            "traffic": MEASURED_TRAFFIC.get(args.workload) if not args.n else None,
             "kernel": "mfma_kernel" if mfma else ("plain_kernel(adjoint)" if grad else "plain_kernel"),
-            "kernel_ms": k_avg_ms, "flops_per_eval": fl / max(sum(counts), 1)}
+            "kernel_ms": k_avg_ms, "launches_per_step": k_launches / args.steps,
+            "flops_per_eval": fl / max(rounds * sum(counts), 1)}
 
     out = {
         "metric": "extrinsic lnL evals/sec (time-marginalized) at |dln L_marg|<=1e-3 vs FP64",
