@@ -41,9 +41,12 @@ def flops_per_eval(K, M, n_t):
 
 def flops_per_grad(K, M, n_t):
     """Forward evaluation plus the adjoint: the transposed contraction
-    G_k = sum_r c_k[r] Q_k[r] (K (n_t + 3) 4 M), the derivative interpolation
-    (8 K n_t), the softmax weights (2 n_t) and the chain rule (40 K M)."""
-    return flops_per_eval(K, M, n_t) + K * (n_t + 3) * 4 * M + 8 * K * n_t + 2 * n_t + 40 * K * M
+    G_k = sum_r c_k[r] Q_k[r] (K (n_t + 3) 4 M), the transposed interpolation
+    c_k (8 K (n_t + 3)), the derivative interpolation (8 K n_t), the softmax
+    weights (2 n_t), U a and V a for the chain rule (8 K M^2) and the chain
+    rule itself (40 K M)."""
+    return (flops_per_eval(K, M, n_t) + K * (n_t + 3) * 4 * M + 8 * K * (n_t + 3) + 8 * K * n_t + 2 * n_t
+            + 8 * K * M * M + 40 * K * M)
 
 
 def main():
@@ -114,13 +117,13 @@ def main():
     k_avg_ms = k_ms / max(k_launches, 1)
     achieved = fl_per_launch / (k_avg_ms * 1e-3) / 1e12 if k_launches else None
     dtype = "f32" if w.precision == "fp32" else "f64"
-    mfma = w.precision == "fp32" and not grad
-    # the plain kernel is FP32 or FP64 vector-ALU bound (no packed FP32: 78.6)
+    mfma = w.precision == "fp32"
+    # the plain kernel (FP64 handles) is FP64 vector-ALU bound (78.6)
     peak = PEAK["fp32_mfma_tflops"] if mfma else PEAK["fp64_tflops"]
     roof = {"bound": "mfma" if mfma else "alu", "achieved": achieved, "peak": peak,
             "unit": "TFLOP/s", "frac": (achieved / peak) if achieved else None,
             "traffic": MEASURED_TRAFFIC.get(args.workload) if not args.n else None,
-            "kernel": "mfma_kernel" if mfma else ("plain_kernel(adjoint)" if grad else "plain_kernel"),
+            "kernel": ("mfma_bwd_kernel" if grad else "mfma_kernel") if mfma else "plain_kernel",
             "kernel_ms": k_avg_ms, "launches_per_step": k_launches / args.steps,
             "flops_per_eval": fl / max(rounds * sum(counts), 1)}
 

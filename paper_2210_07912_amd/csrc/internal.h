@@ -99,6 +99,11 @@ struct MfmaArgs {
   uint32_t *bin_unit;     // [n_bins] first unit of the bin within its item
   uint32_t *item_units;   // [n_items + 1] unit prefix over items (filled on device)
   uint32_t *ctl;          // [0]: number of tiles, [1 + c]: unit counter of class c
+  // adjoint (null in the forward pass)
+  const float *gin;       // [stride] upstream d/d ln L_t, or null (= 1)
+  float *grad;            // [7][stride] gradient of ln L_t (times gin)
+  float *gop;             // per point [tiles][K][2 Mp][16]: G_k = sum_r c_k[r] Q_k[r] (cop layout)
+  float *hop;             // [tiles][kMaxDet][16]: H_k = sum_j p_j Re(a^dag Qtilde'_k(j))
   int n_bins;
   int max_item_bins;      // largest bin count of one point
   int n_sort_blocks;
@@ -113,6 +118,16 @@ struct MfmaArgs {
 hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_K, const int *class_item0, int n_classes,
                         const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles, int n_mclasses,
                         hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
+// the adjoint of the same evaluation: sort, coefficients, then per class the
+// two-sweep matrix-core adjoint (G_k, H_k, ln L_t) and per mode class the FP64
+// chain rule into grad
+hipError_t mfma_backward(const MfmaArgs &a, const int *class_T, const int *class_K, const int *class_item0,
+                         int n_classes, const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles,
+                         int n_mclasses, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// the part both share: delay-bin sort, tile records, coefficient pass, work units
+hipError_t mfma_prepare(const MfmaArgs &a, const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles,
+                        int n_mclasses, hipStream_t st);
 
 // ---- sampler / reductions / adaptation -------------------------------------
 struct ProposalDev {

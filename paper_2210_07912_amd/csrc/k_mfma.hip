@@ -33,19 +33,14 @@
 //                 log-sum-exp.  ell_j never leaves registers.
 #include "common.h"
 #include "internal.h"
+#include "mfma_tile.h"
 
 #include <algorithm>
 
 namespace rift {
 
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-constexpr int kTS = 16;          // samples per tile (MFMA columns)
 constexpr int kRS = 68;          // floats per ring row: a 32-row ring stored twice, padded for banks
-constexpr int kWaves = 4;        // wavefronts per workgroup
 constexpr int kSortThreads = 1024;  // threads per sort block (kSortBlock samples)
-constexpr double kLog2e = 1.4426950408889634074;  // the MFMA path works in base-2 logarithms
-constexpr float kLn2f = 0.693147180559945309f;
 
 __device__ __forceinline__ int item_of_flat(const ItemsDev &it, int64_t f) {
   int lo = 0, hi = it.n_items;  // samp0[lo] <= f < samp0[hi]
@@ -437,37 +432,6 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
 }
 
 // ---- 5. persistent MFMA evaluation ------------------------------------------
-__device__ __forceinline__ int wave_min(int v) {
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-  return v;
-}
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Element of the (re, im)-interleaved operand vector (length 2 Mp = 4 T) that
-// MFMA instruction tt of a detector takes in lane group g.  For the first
-// 4 (T / 4) instructions, lane group g holds elements 16 j + 4 g .. 16 j + 4 g + 3
-// of quad j = tt / 4, one per instruction, so a lane fetches them with one
-// 16-byte load; the other T % 4 instructions take element 16 (T / 4) + 4 r + g.
-// The B operands use the same assignment, so the sum over elements is complete.
-template <int T>
-__device__ __forceinline__ int op_elem(int tt, int g) {
-  constexpr int J = T / 4;
-  return tt < 4 * J ? 16 * (tt >> 2) + 4 * g + (tt & 3) : 16 * J + 4 * (tt - 4 * J) + g;
-}
-
-// Row stride (floats) of a staged block of Q in LDS: 4T elements, padded to
-// an odd number of 16-byte groups so that the 16-byte reads of 8 consecutive
-// rows fall in distinct banks.
-template <int T>
-constexpr int stage_stride() {
-  return 4 * T + ((T % 2 == 0) ? 4 : 0);
-}
-
 // One workgroup per work unit: its four wavefronts take the unit's tiles
 // (wavefronts past ntiles only help stage).  The rows of block b of every
 // detector are loaded once per workgroup, coalesced, into a double-buffered
@@ -719,10 +683,8 @@ static void launch_class(const MfmaArgs &a, int K, int lo, int hi, int cls, hipS
   else launch_tk<T, 3>(a, lo, hi, cls, st);
 }
 
-hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_K, const int *class_item0, int n_classes,
-                        const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles, int n_mclasses,
-                        hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  if (a.total <= 0) return hipSuccess;
+hipError_t mfma_prepare(const MfmaArgs &a, const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles,
+                        int n_mclasses, hipStream_t st) {
   hipError_t e = fill_u32((uint32_t *)a.rec, (int64_t)kTS * a.max_tiles * (sizeof(SampleRec) / 4), 0u, st);
   if (e != hipSuccess) return e;
   const size_t lds = sizeof(uint32_t) * (size_t)std::min(a.max_item_bins, kLdsBins);
@@ -745,6 +707,15 @@ hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_
       default: hipLaunchKernelGGL(coef_kernel<0>, grid, dim3(64), 0, st, a, lo, hi); break;
     }
   }
+  return hipGetLastError();
+}
+
+hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_K, const int *class_item0, int n_classes,
+                        const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles, int n_mclasses,
+                        hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  if (a.total <= 0) return hipSuccess;
+  hipError_t e = mfma_prepare(a, mclass_M, mclass_item0, mclass_tiles, n_mclasses, st);
+  if (e != hipSuccess) return e;
   if (ev0) (void)hipEventRecord(ev0, st);
   for (int c = 0; c < n_classes; c++) {
     const int lo = class_item0[c], hi = class_item0[c + 1];

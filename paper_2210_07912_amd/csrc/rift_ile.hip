@@ -57,7 +57,7 @@ enum WsId {
   W_ITEM_POINT, W_ITEM_OFF, W_ITEM_CNT, W_ITEM_TILE0, W_ITEM_SAMP0, W_ITEM_BIN0,
   W_KEY, W_NSH, W_COUNT, W_CURSOR, W_COP, W_BINTILE, W_ITEMTILES, W_PERM, W_TILES, W_CTL, W_CTILE,
   W_PARTIALS, W_ROUND, W_ACCUM, W_RESULT, W_HIST, W_THETA, W_LNW, W_AUX, W_RATIO, W_BINS, W_ITEM_BLK0,
-  W_ITEM_HOFF, W_ITEM_COP, W_SEG_OFF, W_SEG_CNT, W_ASC, W_AHIST, W_UNIT, W_BINUNIT, W_ITEMUNITS, W_COUNT_IDS
+  W_ITEM_HOFF, W_ITEM_COP, W_SEG_OFF, W_SEG_CNT, W_ASC, W_AHIST, W_UNIT, W_BINUNIT, W_ITEMUNITS, W_GOP, W_HOP, W_COUNT_IDS
 };
 static_assert(W_COUNT_IDS <= 40, "workspace table too small");
 
@@ -373,7 +373,7 @@ rift_status run_plain(rift_ile *h, const Items &it, int64_t stride, const R *the
 // One group of points (already in evaluation order) through the sort, the
 // coefficient pass and the persistent MFMA launches.
 rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const float *theta, float *lnL, float *lnw,
-                           const float *ln_ratio) {
+                           const float *ln_ratio, const float *gin = nullptr, float *grad = nullptr) {
   std::vector<int64_t> samp0(1, 0), mclass_tiles, hoff;
   std::vector<int> bin0(1, 0), blk0(1, 0), class_T, class_K, class_item0, mclass_M, mclass_item0;
   int64_t hist_total = 0, cop_floats = 0;
@@ -465,6 +465,14 @@ rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const f
   a.tile_item = (int *)p;
   if ((s = ws_get(h, W_COP, sizeof(float) * (size_t)cop_floats, &p)) != RIFT_OK) return s;
   a.cop = (float *)p;
+  if (grad) {  // the adjoint's per-tile G_k (cop layout) and H_k
+    if ((s = ws_get(h, W_GOP, sizeof(float) * (size_t)cop_floats, &p)) != RIFT_OK) return s;
+    a.gop = (float *)p;
+    if ((s = ws_get(h, W_HOP, sizeof(float) * kMaxDet * 16 * (size_t)max_tiles, &p)) != RIFT_OK) return s;
+    a.hop = (float *)p;
+    a.gin = gin;
+    a.grad = grad;
+  }
   if ((s = ws_get(h, W_ITEM_COP, sizeof(int64_t) * (size_t)ni, &p)) != RIFT_OK) return s;
   a.item_cop = (int64_t *)p;
   if ((s = ws_get(h, W_CTILE, sizeof(CoefTile) * (size_t)max_tiles, &p)) != RIFT_OK) return s;
@@ -484,8 +492,14 @@ rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const f
     HIPCHK(h, hipEventCreate(&e1));
     h->prof_ev.emplace_back(e0, e1);
   }
-  HIPCHK(h, mfma_forward(a, class_T.data(), class_K.data(), class_item0.data(), (int)class_T.size(), mclass_M.data(),
-                         mclass_item0.data(), mclass_tiles.data(), (int)mclass_M.size(), h->stream, e0, e1));
+  if (grad)
+    HIPCHK(h, mfma_backward(a, class_T.data(), class_K.data(), class_item0.data(), (int)class_T.size(),
+                            mclass_M.data(), mclass_item0.data(), mclass_tiles.data(), (int)mclass_M.size(), h->stream,
+                            e0, e1));
+  else
+    HIPCHK(h, mfma_forward(a, class_T.data(), class_K.data(), class_item0.data(), (int)class_T.size(),
+                           mclass_M.data(), mclass_item0.data(), mclass_tiles.data(), (int)mclass_M.size(), h->stream,
+                           e0, e1));
   return RIFT_OK;
 }
 
@@ -493,7 +507,7 @@ rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const f
 // then mode count, costliest first: the kernels take tiles in this order.
 // The points are evaluated in runs whose workspace stays under a budget.
 rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const float *theta, float *lnL, float *lnw,
-                     const float *ln_ratio) {
+                     const float *ln_ratio, const float *gin = nullptr, float *grad = nullptr) {
   const int n = (int)it_in.point.size();
   std::vector<int> order(n);
   std::iota(order.begin(), order.end(), 0);
@@ -518,11 +532,11 @@ rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const floa
     const PointDev &p = h->hp[it_in.point[oi]];
     int64_t remaining = it_in.cnt[oi], off = it_in.off[oi];
     while (remaining > 0) {
-      const double per = 4.0 + 8.0 + 44.0 + 40.0 + (double)p.K * 2 * p.Mp * 4 * 1.1;
+      const double per = 4.0 + 8.0 + 44.0 + 40.0 + (double)p.K * 2 * p.Mp * 4 * 1.1 * (grad ? 2.0 : 1.0);
       int64_t take = remaining;
       if (used + per * take > budget) {
         if (!grp.point.empty()) {
-          rift_status s = run_mfma_group(h, grp, stride, theta, lnL, lnw, ln_ratio);
+          rift_status s = run_mfma_group(h, grp, stride, theta, lnL, lnw, ln_ratio, gin, grad);
           if (s != RIFT_OK) return s;
           grp = Items();
           used = 0.0;
@@ -537,7 +551,7 @@ rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const floa
       remaining -= take;
     }
   }
-  if (!grp.point.empty()) return run_mfma_group(h, grp, stride, theta, lnL, lnw, ln_ratio);
+  if (!grp.point.empty()) return run_mfma_group(h, grp, stride, theta, lnL, lnw, ln_ratio, gin, grad);
   return RIFT_OK;
 }
 
@@ -556,6 +570,16 @@ rift_status eval(rift_ile *h, const Items &it, int64_t stride, const R *theta, R
   if (sizeof(R) == 4 && !(h->flags & 1u))
     return run_mfma(h, it, stride, (const float *)theta, (float *)lnL, (float *)lnw, (const float *)ln_ratio);
   return run_plain<R>(h, it, stride, theta, lnL, lnw, ln_ratio, nullptr, nullptr, false);
+}
+
+// ln L_t and its gradient (times gin): the matrix-core adjoint for FP32
+// handles, the plain adjoint otherwise
+template <typename R>
+rift_status eval_grad(rift_ile *h, const Items &it, int64_t stride, const R *theta, R *lnL, const R *gin, R *grad) {
+  if (sizeof(R) == 4 && !(h->flags & 1u))
+    return run_mfma(h, it, stride, (const float *)theta, (float *)lnL, nullptr, nullptr, (const float *)gin,
+                    (float *)grad);
+  return run_plain<R>(h, it, stride, theta, lnL, nullptr, nullptr, gin, grad, true);
 }
 
 template <typename R>
@@ -681,7 +705,7 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
         const bool prof = h->prof;  // the timing hook follows the evaluation launches only
         h->prof = false;
         for (int it_s = 0; it_s <= steps; it_s++) {
-          if ((s = run_plain<R>(h, ita, na, a_th, a_l, nullptr, nullptr, nullptr, a_g, true)) != RIFT_OK) {
+          if ((s = eval_grad<R>(h, ita, na, a_th, a_l, nullptr, a_g)) != RIFT_OK) {
             h->prof = prof;
             return s;
           }
@@ -956,10 +980,10 @@ rift_status rift_ile_backward(rift_ile *h, int n_items, const rift_ile_item *ite
   if (n_items > 0 && stride > 0 && (!theta || !grad_theta)) return fail(h, RIFT_E_INVALID, "NULL theta or grad");
   Items it = make_items(n_items, items);
   if (h->precision == RIFT_FP32)
-    return run_plain<float>(h, it, stride, (const float *)theta, (float *)lnL_t_out, nullptr, nullptr,
-                            (const float *)grad_lnL_t, (float *)grad_theta, true);
-  return run_plain<double>(h, it, stride, (const double *)theta, (double *)lnL_t_out, nullptr, nullptr,
-                           (const double *)grad_lnL_t, (double *)grad_theta, true);
+    return eval_grad<float>(h, it, stride, (const float *)theta, (float *)lnL_t_out, (const float *)grad_lnL_t,
+                            (float *)grad_theta);
+  return eval_grad<double>(h, it, stride, (const double *)theta, (double *)lnL_t_out, (const double *)grad_lnL_t,
+                           (double *)grad_theta);
 }
 
 }  // extern "C"

@@ -264,11 +264,120 @@ def test_backward_matches_oracle(ile, orc):
         _say(f"backward {prec}")
         gg, lg = h.backward(torch.tensor(th), want_lnL=True)
         gg, lg = gg.cpu().numpy(), lg.cpu().numpy()
-        scale = np.abs(g).max(axis=0) + 1e-3
-        rel = np.abs(gg - g) / scale
-        _say(f"  max rel grad err {rel.max():.3e}")
-        assert rel.max() < (1e-9 if prec == "fp64" else 1e-4)
-        assert np.allclose(lg, lt, atol=1e-9 if prec == "fp64" else 1e-3)
+        if prec == "fp64":
+            scale = np.abs(g).max(axis=0) + 1e-3
+            rel = np.abs(gg - g) / scale
+            _say(f"  max rel grad err per parameter {np.array2string(rel.max(axis=1), precision=2)}")
+            assert rel.max() < 1e-9
+            assert np.allclose(lg, lt, atol=1e-9)
+        else:
+            _grad_check(gg, lg, g, lt, "backward fp32", _tau_sensitivity(orc, p, th), f_s=spec.f_s)
+
+
+def _fp32_grad_tol(g, lt, sens, f_s):
+    """Tolerance of an FP32 gradient against the oracle, per component.
+
+    alpha, delta, psi, iota, phi, D: 1e-4 of the sample's largest gradient
+    component.  tau: the same plus the FP32 floor of the window softmax.
+    d lnL_t / d tau = sum_j p_j d ell_j / d tau is the residual of terms that
+    largely cancel (a peak sampled on a grid barely moves its sum when the
+    grid shifts), and every p_j carries the FP32 rounding of ell_j = data - B,
+    an error of sqrt(2M x 4 taps x K) ~ 22 unit roundoffs (eps = 2^-24) of
+    the data term's size Z = |lnL_t| + 2 B, since every window value sums
+    that many products, each up to Z in size (the observed |d lnL_t| agree);
+    sens = (Z, A) with A = sum_j p_j |d ell_j / d tau| (the oracle's), so
+    |d g_tau| <~ 32 eps Z A.  A defect in the adjoint shows as errors many
+    times larger."""
+    Z, A = sens
+    scale = np.abs(g).max(axis=0) + 1e-3
+    tol = np.tile(1e-4 * scale, (7, 1))
+    tol[6] += 32 * 2.0 ** -24 * Z * A
+    return scale, tol
+
+
+def _tau_sensitivity(orc, p, th, h=1e-7):
+    """(Z, A) of every sample from the oracle: Z = |lnL_t| + 2 B and
+    A = sum_j p_j |d ell_j / d tau| (central differences in tau, FP64)."""
+    Z, A = np.zeros(th.shape[1]), np.zeros(th.shape[1])
+    for i in range(th.shape[1]):
+        t = th[:, i].copy()
+        ell = orc.ell(p, t)
+        B = orc.coeffs(p, t)[1]
+        tp, tm = t.copy(), t.copy()
+        tp[6] += h
+        tm[6] -= h
+        d = (orc.ell(p, tp) - orc.ell(p, tm)) / (2 * h)
+        w = np.exp(ell - ell.max())
+        w /= w.sum()
+        Z[i] = abs(ell.max()) + 2 * abs(B)
+        A[i] = np.sum(w * np.abs(d))
+    return Z, A
+
+
+def _grad_check(gg, lg, g, lt, label, sens, f_s=4096.0):
+    scale, tol = _fp32_grad_tol(g, lt, sens, f_s)
+    err = np.abs(gg - g)
+    rel = err / scale
+    _say(f"[{label}] max rel grad err per parameter {np.array2string(rel.max(axis=1), precision=2)}, "
+         f"max err/tol {np.max(err / tol):.3f}, max |d lnL_t| {np.abs(lg - lt).max():.3e}")
+    d, i = np.unravel_index(np.argmax(err / tol), err.shape)
+    _say(f"   worst: param {d} sample {i}: lnL_t {lt[i]:.4f} Z {sens[0][i]:.4g} A {sens[1][i]:.4g} ref {g[d, i]:.6g} "
+         f"got {gg[d, i]:.6g} tol {tol[d, i]:.3g}")
+    assert np.all(err <= tol), (label, d, i)
+    _check_fp32(lg, lt, label)
+
+
+def test_backward_mfma_shapes(ile, orc):
+    """The matrix-core adjoint (FP32) against the oracle's analytic gradient:
+    the gradient workload's shape (K = 3, M = 21, n_t = 820, tau within half
+    a sample), V != 0, several points of different shape in one call, and
+    the plain FP32 adjoint on the same samples."""
+    tw = 1 / 4096
+    spec = synth.workload("grad").points[0]
+    d = synth.make_point(spec)
+    th = synth.mixed_samples(d, 12, 1031, tau_width=tw)
+    op = orc.Point.from_dict(d, complex64=True)
+    lt, g = orc.grad(op, th)
+    sens = _tau_sensitivity(orc, op, th)
+    _say("backward grad shape, mfma and plain")
+    h = _handle(ile, [d], "fp32", tau_width=tw)
+    gg, lg = h.backward(torch.tensor(th), want_lnL=True)
+    hp = _handle(ile, [d], "fp32", plain=True, tau_width=tw)
+    gp_, lp = hp.backward(torch.tensor(th), want_lnL=True)
+    gp_, lp = gp_.cpu().numpy(), lp.cpu().numpy()
+    try:
+        _grad_check(gg.cpu().numpy(), lg.cpu().numpy(), g, lt, "mfma adjoint, grad shape", sens)
+    finally:
+        _grad_check(gp_, lp, g, lt, "plain adjoint, grad shape", sens)
+    # upstream gradient and V != 0
+    dv = synth.make_point(synth.PIN_SPECS[3])
+    thv = synth.mixed_samples(dv, 13, 257, tau_width=tw)
+    opv = orc.Point.from_dict(dv, complex64=True)
+    ltv, gv = orc.grad(opv, thv)
+    up = np.linspace(0.5, 2.0, thv.shape[1])
+    hv = _handle(ile, [dv], "fp32", tau_width=tw)
+    _say("backward V != 0 with an upstream gradient")
+    ggv, lgv = hv.backward(torch.tensor(thv), grad_lnL=torch.tensor(up), want_lnL=True)
+    Zv, Av = _tau_sensitivity(orc, opv, thv)
+    _grad_check(ggv.cpu().numpy(), lgv.cpu().numpy(), gv * up[None, :], ltv, "mfma adjoint, V != 0", (Zv, Av * up))
+    # several points in one call
+    w = synth.workload("tiny_batched")
+    pts = [synth.make_point(sp) for sp in w.points]
+    ths, items, refs, off = [], [], [], 0
+    for i, (dd, n) in enumerate(zip(pts, w.n_samples)):
+        n = min(n, 300)
+        t_ = synth.mixed_samples(dd, 200 + i, n, tau_width=tw)
+        ths.append(t_)
+        od = orc.Point.from_dict(dd, complex64=True)
+        refs.append(orc.grad(od, t_) + (_tau_sensitivity(orc, od, t_),))
+        items.append((i, off, n))
+        off += n
+    hb = _handle(ile, pts, "fp32", tau_width=tw)
+    _say(f"backward batched items total={off}")
+    gb, lb = hb.backward(torch.tensor(np.concatenate(ths, axis=1)), items=items, want_lnL=True)
+    gb, lb = gb.cpu().numpy(), lb.cpu().numpy()
+    for i, (_, o, n) in enumerate(items):
+        _grad_check(gb[:, o:o + n], lb[o:o + n], refs[i][1], refs[i][0], f"mfma adjoint, point {i}", refs[i][2])
 
 
 def test_lnL_with_V(ile, orc):
