@@ -111,20 +111,50 @@ struct MfmaArgs {
   int grid;               // persistent workgroups
 };
 
+// Streams a call may fan out on: the class kernels of one evaluation run
+// concurrently on side streams (default priority), forked from and joined
+// back to the caller's stream with events, so each class fills the tail of
+// the one before it.
+constexpr int kSideStreams = 3;
+struct Fanout {
+  hipStream_t side[kSideStreams];
+  hipEvent_t fork;
+  hipEvent_t join[kSideStreams];
+  int n;  // 0: everything on the caller's stream
+};
+
 // ev0/ev1 (or null): recorded around the persistent evaluation kernels
 // classes: runs of points with the same MFMA step count T (evaluation
 // launches) and with the same mode count M (coefficient launches; mclass_tiles
 // bounds the tiles of each run)
 hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_K, const int *class_item0, int n_classes,
                         const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles, int n_mclasses,
-                        hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                        hipStream_t st, const Fanout &fo, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // the adjoint of the same evaluation: sort, coefficients, then per class the
 // two-sweep matrix-core adjoint (G_k, H_k, ln L_t) and per mode class the FP64
 // chain rule into grad
 hipError_t mfma_backward(const MfmaArgs &a, const int *class_T, const int *class_K, const int *class_item0,
                          int n_classes, const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles,
-                         int n_mclasses, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                         int n_mclasses, hipStream_t st, const Fanout &fo, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);
+// the stream of class c (0: the caller's) and the fork / join around a run
+// of classes
+inline hipStream_t fan_stream(const Fanout &fo, hipStream_t st, int c) {
+  return (fo.n == 0 || c == 0) ? st : fo.side[(c - 1) % fo.n];
+}
+inline void fan_fork(const Fanout &fo, hipStream_t st, int n_classes) {
+  if (fo.n == 0 || n_classes < 2) return;
+  (void)hipEventRecord(fo.fork, st);
+  for (int i = 0; i < fo.n && i < n_classes - 1; i++) (void)hipStreamWaitEvent(fo.side[i], fo.fork, 0);
+}
+inline void fan_join(const Fanout &fo, hipStream_t st, int n_classes) {
+  if (fo.n == 0 || n_classes < 2) return;
+  for (int i = 0; i < fo.n && i < n_classes - 1; i++) {
+    (void)hipEventRecord(fo.join[i], fo.side[i]);
+    (void)hipStreamWaitEvent(st, fo.join[i], 0);
+  }
+}
 // the part both share: delay-bin sort, tile records, coefficient pass, work units
 hipError_t mfma_prepare(const MfmaArgs &a, const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles,
                         int n_mclasses, hipStream_t st);
@@ -140,6 +170,13 @@ template <typename R>
 hipError_t sample_launch(const PointDev *pts, const ProposalDev *prop, int point, uint64_t seed, uint32_t round,
                          int64_t first, int64_t n, int64_t stride, int64_t bin_stride, double d_min, double d_max,
                          double tau_width, R *theta, R *ln_ratio, uint8_t *bins, hipStream_t st);
+// every point of a round in one launch (blk0: [np + 1] prefix of 256-sample
+// blocks; off, cnt: columns and counts of each point; device arrays)
+template <typename R>
+hipError_t sample_multi_launch(const ProposalDev *props, const int *blk0, int n_blocks, int np, const int64_t *off,
+                               const int64_t *cnt, uint64_t seed, uint32_t round, int64_t stride, int64_t bin_stride,
+                               double d_min, double d_max, double tau_width, R *theta, R *ln_ratio, uint8_t *bins,
+                               hipStream_t st);
 
 struct ReduceTuple {
   double m, s1, s2;

@@ -450,17 +450,19 @@ static void launch_bwd_class(const MfmaArgs &a, int K, int lo, int hi, int cls, 
 
 hipError_t mfma_backward(const MfmaArgs &a, const int *class_T, const int *class_K, const int *class_item0,
                          int n_classes, const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles,
-                         int n_mclasses, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                         int n_mclasses, hipStream_t st, const Fanout &fo, hipEvent_t ev0, hipEvent_t ev1) {
   if (a.total <= 0) return hipSuccess;
   hipError_t e = mfma_prepare(a, mclass_M, mclass_item0, mclass_tiles, n_mclasses, st);
   if (e != hipSuccess) return e;
   if (ev0) (void)hipEventRecord(ev0, st);
+  fan_fork(fo, st, n_classes);
   for (int c = 0; c < n_classes; c++) {
+    hipStream_t sc = fan_stream(fo, st, c);
     const int lo = class_item0[c], hi = class_item0[c + 1];
     const int K = class_K[c];
     switch (class_T[c]) {
 #define RIFT_T_CASE(TT) \
-  case TT: launch_bwd_class<TT>(a, K, lo, hi, c, st); break;
+  case TT: launch_bwd_class<TT>(a, K, lo, hi, c, sc); break;
       RIFT_T_CASE(1) RIFT_T_CASE(2) RIFT_T_CASE(3) RIFT_T_CASE(4) RIFT_T_CASE(5) RIFT_T_CASE(6) RIFT_T_CASE(7)
       RIFT_T_CASE(8) RIFT_T_CASE(9) RIFT_T_CASE(10) RIFT_T_CASE(11) RIFT_T_CASE(12) RIFT_T_CASE(13)
       RIFT_T_CASE(14) RIFT_T_CASE(15) RIFT_T_CASE(16)
@@ -468,6 +470,7 @@ hipError_t mfma_backward(const MfmaArgs &a, const int *class_T, const int *class
       default: return hipErrorInvalidValue;
     }
   }
+  fan_join(fo, st, n_classes);
   if (ev1) (void)hipEventRecord(ev1, st);
   for (int c = 0; c < n_mclasses; c++) {
     const int lo = mclass_item0[c], hi = mclass_item0[c + 1];

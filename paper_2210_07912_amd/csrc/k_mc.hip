@@ -41,19 +41,14 @@ __device__ __forceinline__ R prior_inv(int d, double u, double d_min, double d_m
   return (R)t;
 }
 
+// one draw: Philox words (counter: sample index, 2 round + half, point; key:
+// seed) -> seven parameters through the proposal's inverse CDFs in FP64,
+// rounded once, their bins and ln p - ln p_s
 template <typename R>
-__global__ void __launch_bounds__(256) sample_kernel(const ProposalDev *prop, uint32_t point, uint64_t seed,
-                                                     uint32_t round, int64_t first, int64_t n, int64_t stride,
-                                                     int64_t bin_stride, double d_min, double d_max, double tau_width,
-                                                     R *theta, R *ln_ratio, uint8_t *bins) {
-  __shared__ double cdf[7][kNB + 1];
-  __shared__ unsigned mask;
-  for (int i = threadIdx.x; i < 7 * (kNB + 1); i += blockDim.x) cdf[i / (kNB + 1)][i % (kNB + 1)] = prop->cdf[i / (kNB + 1)][i % (kNB + 1)];
-  if (threadIdx.x == 0) mask = prop->mask;
-  __syncthreads();
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  uint64_t i = (uint64_t)(first + j);
+__device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned mask, uint32_t point, uint64_t seed,
+                                         uint32_t round, uint64_t i, double d_min, double d_max, double tau_width,
+                                         R *theta, int64_t stride, R *ln_ratio, uint8_t *bins, int64_t bin_stride,
+                                         int64_t col) {
   uint32_t r[8];
   for (int half = 0; half < 2; half++) {
     uint32_t c[4] = {(uint32_t)i, (uint32_t)(i >> 32), 2u * round + (uint32_t)half, point};
@@ -78,10 +73,52 @@ __global__ void __launch_bounds__(256) sample_kernel(const ProposalDev *prop, ui
       lr -= log(mass * kNB);
       bin = (uint32_t)lo;
     }
-    theta[d * stride + j] = prior_inv<R>(d, u, d_min, d_max, tau_width);
-    if (bins) bins[d * bin_stride + j] = (uint8_t)bin;
+    theta[d * stride + col] = prior_inv<R>(d, u, d_min, d_max, tau_width);
+    if (bins) bins[d * bin_stride + col] = (uint8_t)bin;
   }
-  if (ln_ratio) ln_ratio[j] = (R)lr;
+  if (ln_ratio) ln_ratio[col] = (R)lr;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) sample_kernel(const ProposalDev *prop, uint32_t point, uint64_t seed,
+                                                     uint32_t round, int64_t first, int64_t n, int64_t stride,
+                                                     int64_t bin_stride, double d_min, double d_max, double tau_width,
+                                                     R *theta, R *ln_ratio, uint8_t *bins) {
+  __shared__ double cdf[7][kNB + 1];
+  __shared__ unsigned mask;
+  for (int i = threadIdx.x; i < 7 * (kNB + 1); i += blockDim.x) cdf[i / (kNB + 1)][i % (kNB + 1)] = prop->cdf[i / (kNB + 1)][i % (kNB + 1)];
+  if (threadIdx.x == 0) mask = prop->mask;
+  __syncthreads();
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  draw_one<R>(cdf, mask, point, seed, round, (uint64_t)(first + j), d_min, d_max, tau_width, theta, stride, ln_ratio,
+              bins, bin_stride, j);
+}
+
+// every point of a round in one launch: blocks [blk0[p], blk0[p + 1]) draw
+// point p's samples into columns off[p] ..
+template <typename R>
+__global__ void __launch_bounds__(256) sample_multi_kernel(const ProposalDev *props, const int *blk0, int np,
+                                                           const int64_t *off, const int64_t *cnt, uint64_t seed,
+                                                           uint32_t round, int64_t stride, int64_t bin_stride,
+                                                           double d_min, double d_max, double tau_width, R *theta,
+                                                           R *ln_ratio, uint8_t *bins) {
+  __shared__ double cdf[7][kNB + 1];
+  __shared__ unsigned mask;
+  int lo = 0, hi = np;  // blk0[lo] <= blockIdx.x < blk0[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (blk0[mid] <= (int)blockIdx.x) lo = mid; else hi = mid;
+  }
+  const int p = lo;
+  const ProposalDev *prop = props + p;
+  for (int i = threadIdx.x; i < 7 * (kNB + 1); i += blockDim.x) cdf[i / (kNB + 1)][i % (kNB + 1)] = prop->cdf[i / (kNB + 1)][i % (kNB + 1)];
+  if (threadIdx.x == 0) mask = prop->mask;
+  __syncthreads();
+  const int64_t j = (int64_t)(blockIdx.x - blk0[p]) * blockDim.x + threadIdx.x;
+  if (j >= cnt[p]) return;
+  draw_one<R>(cdf, mask, (uint32_t)p, seed, round, (uint64_t)j, d_min, d_max, tau_width, theta, stride, ln_ratio,
+              bins, bin_stride, off[p] + j);
 }
 
 template <typename R>
@@ -93,6 +130,23 @@ hipError_t sample_launch(const PointDev *, const ProposalDev *prop, int point, u
                      seed, round, first, n, stride, bin_stride, d_min, d_max, tau_width, theta, ln_ratio, bins);
   return hipGetLastError();
 }
+
+template <typename R>
+hipError_t sample_multi_launch(const ProposalDev *props, const int *blk0, int n_blocks, int np, const int64_t *off,
+                               const int64_t *cnt, uint64_t seed, uint32_t round, int64_t stride, int64_t bin_stride,
+                               double d_min, double d_max, double tau_width, R *theta, R *ln_ratio, uint8_t *bins,
+                               hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sample_multi_kernel<R>, dim3((unsigned)n_blocks), dim3(256), 0, st, props, blk0, np, off, cnt,
+                     seed, round, stride, bin_stride, d_min, d_max, tau_width, theta, ln_ratio, bins);
+  return hipGetLastError();
+}
+template hipError_t sample_multi_launch<float>(const ProposalDev *, const int *, int, int, const int64_t *,
+                                               const int64_t *, uint64_t, uint32_t, int64_t, int64_t, double, double,
+                                               double, float *, float *, uint8_t *, hipStream_t);
+template hipError_t sample_multi_launch<double>(const ProposalDev *, const int *, int, int, const int64_t *,
+                                                const int64_t *, uint64_t, uint32_t, int64_t, int64_t, double, double,
+                                                double, double *, double *, uint8_t *, hipStream_t);
 template hipError_t sample_launch<float>(const PointDev *, const ProposalDev *, int, uint64_t, uint32_t, int64_t,
                                          int64_t, int64_t, int64_t, double, double, double, float *, float *,
                                          uint8_t *, hipStream_t);

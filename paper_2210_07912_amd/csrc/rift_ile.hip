@@ -46,6 +46,9 @@ struct rift_ile {
   int lds_max = 65536;
   // grow-only workspace, indexed by name
   DevBuf ws[40];
+  // side streams for concurrent class kernels, and the workspace budget
+  Fanout fan{};
+  double ws_budget = 6.0e9;
   // optional timing of the dominant evaluation kernel
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
@@ -57,7 +60,7 @@ enum WsId {
   W_ITEM_POINT, W_ITEM_OFF, W_ITEM_CNT, W_ITEM_TILE0, W_ITEM_SAMP0, W_ITEM_BIN0,
   W_KEY, W_NSH, W_COUNT, W_CURSOR, W_COP, W_BINTILE, W_ITEMTILES, W_PERM, W_TILES, W_CTL, W_CTILE,
   W_PARTIALS, W_ROUND, W_ACCUM, W_RESULT, W_HIST, W_THETA, W_LNW, W_AUX, W_RATIO, W_BINS, W_ITEM_BLK0,
-  W_ITEM_HOFF, W_ITEM_COP, W_SEG_OFF, W_SEG_CNT, W_ASC, W_AHIST, W_UNIT, W_BINUNIT, W_ITEMUNITS, W_GOP, W_HOP, W_COUNT_IDS
+  W_ITEM_HOFF, W_ITEM_COP, W_SEG_OFF, W_SEG_CNT, W_ASC, W_AHIST, W_UNIT, W_BINUNIT, W_ITEMUNITS, W_GOP, W_HOP, W_SEG_BLK, W_COUNT_IDS
 };
 static_assert(W_COUNT_IDS <= 40, "workspace table too small");
 
@@ -495,11 +498,11 @@ rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const f
   if (grad)
     HIPCHK(h, mfma_backward(a, class_T.data(), class_K.data(), class_item0.data(), (int)class_T.size(),
                             mclass_M.data(), mclass_item0.data(), mclass_tiles.data(), (int)mclass_M.size(), h->stream,
-                            e0, e1));
+                            h->fan, e0, e1));
   else
     HIPCHK(h, mfma_forward(a, class_T.data(), class_K.data(), class_item0.data(), (int)class_T.size(),
                            mclass_M.data(), mclass_item0.data(), mclass_tiles.data(), (int)mclass_M.size(), h->stream,
-                           e0, e1));
+                           h->fan, e0, e1));
   return RIFT_OK;
 }
 
@@ -524,7 +527,7 @@ rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const floa
     if (Mof(a) != Mof(b)) return Mof(a) > Mof(b);
     return cost(a) > cost(b);
   });
-  const double budget = 6.0e9;  // bytes of per-sample workspace per run
+  const double budget = h->ws_budget;  // bytes of per-sample workspace per run
   Items grp;
   double used = 0.0;
   for (int oi : order) {
@@ -642,6 +645,11 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
   int64_t *d_soff, *d_scnt;
   if ((s = upload(h, W_SEG_OFF, off, &d_soff)) != RIFT_OK) return s;
   if ((s = upload(h, W_SEG_CNT, cnt, &d_scnt)) != RIFT_OK) return s;
+  // sampling blocks of 256 per point, for one launch per round
+  std::vector<int> sblk(np + 1, 0);
+  for (int p = 0; p < np; p++) sblk[p + 1] = sblk[p] + (int)((cnt[p] + 255) / 256);
+  int *d_sblk;
+  if ((s = upload(h, W_SEG_BLK, sblk, &d_sblk)) != RIFT_OK) return s;
   const int64_t th_stride = theta_out ? total : nr;
   // gradient-informed refinement: ascent set of k points per point
   const bool grad = (mc->flags & RIFT_MC_GRADIENT) && mc->adapt_mask;
@@ -689,10 +697,9 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
     const int64_t cb = theta_out ? (int64_t)r * per_round : 0;
     R *th = theta_out ? theta_out + cb : (R *)th_ws;
     R *lw = lnw_out ? lnw_out + (int64_t)r * per_round : (R *)lw_ws;
-    for (int p = 0; p < np; p++)
-      HIPCHK(h, sample_launch<R>(h->d_pts, h->d_props + p, p, mc->seed, (uint32_t)r, 0, cnt[p], th_stride, nr,
-                                 h->d_min, h->d_max, h->tau_width, th + off[p], (R *)ratio + off[p],
-                                 (uint8_t *)bins + off[p], h->stream));
+    HIPCHK(h, sample_multi_launch<R>(h->d_props, d_sblk, sblk[np], np, d_soff, d_scnt, mc->seed, (uint32_t)r,
+                                     th_stride, nr, h->d_min, h->d_max, h->tau_width, th, (R *)ratio,
+                                     (uint8_t *)bins, h->stream));
     if ((s = eval<R>(h, it, th_stride, th, nullptr, lw, (const R *)ratio)) != RIFT_OK) return s;
     ReduceTuple *round;
     const bool last = r + 1 == mc->n_rounds;
@@ -758,6 +765,12 @@ void rift_ile_destroy(rift_ile *h) {
     (void)hipEventDestroy(pe.first);
     (void)hipEventDestroy(pe.second);
   }
+  for (int i = 0; i < h->fan.n; i++) {
+    (void)hipStreamSynchronize(h->fan.side[i]);
+    (void)hipStreamDestroy(h->fan.side[i]);
+    (void)hipEventDestroy(h->fan.join[i]);
+  }
+  if (h->fan.n) (void)hipEventDestroy(h->fan.fork);
   for (void *p : h->owned) (void)hipFree(p);
   for (auto &b : h->ws)
     if (b.p) (void)hipFree(b.p);
@@ -804,6 +817,26 @@ rift_status rift_ile_create(rift_ile **out, const rift_ile_desc *desc, void *str
   else h->n_cu = 256;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess && v > 0)
     h->lds_max = std::min(v, 160 * 1024) - 1024;
+  // per-sample workspace of one evaluation run: a third of the free device
+  // memory, between 2 and 64 GB (fewer, larger runs on a 288 GB device)
+  size_t mfree = 0, mtot = 0;
+  if (hipMemGetInfo(&mfree, &mtot) == hipSuccess && mfree > 0)
+    h->ws_budget = std::min(64.0e9, std::max(2.0e9, (double)mfree / 3.0));
+  if (h->precision == RIFT_FP32) {
+    bool ok = hipEventCreateWithFlags(&h->fan.fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; ok && i < kSideStreams; i++) {
+      ok = hipStreamCreateWithFlags(&h->fan.side[i], hipStreamNonBlocking) == hipSuccess;
+      if (ok && hipEventCreateWithFlags(&h->fan.join[i], hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(h->fan.side[i]);
+        ok = false;
+      }
+      if (ok) h->fan.n = i + 1;
+    }
+    if (h->fan.n == 0 && h->fan.fork) {
+      (void)hipEventDestroy(h->fan.fork);
+      h->fan.fork = nullptr;
+    }
+  }
   h->hp.resize(h->n_points);
   for (int i = 0; i < h->n_points; i++) {
     rift_status s = h->precision == RIFT_FP32 ? build_point<float>(h, desc->points[i], h->hp[i])
