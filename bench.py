@@ -60,6 +60,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the multi-GPU path is not part of this build "
@@ -139,6 +140,23 @@ def main():
         "roofline": roof,
         "lnL_marg": [r["lnL_marg"] for r in res][:4], "n_eff": [r["n_eff"] for r in res][:4],
     }
+
+    # the same steps with the evaluation runs replayed from captured hipGraphs
+    # (FP32 handles; host-timed, the kernel timing hook stays off)
+    if not args.no_graph and w.precision == "fp32" and not grad:
+        h.set_graph(True)
+        for i in range(max(args.warmup, 1)):
+            step(i)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for i in range(args.steps):
+            step(100 + i)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        cap, rep = h.graph_stats()
+        h.set_graph(False)
+        gdt = (t3 - t2) / args.steps
+        out["graph"] = {"value": evals_per_step / gdt, "ms_per_step": gdt * 1e3, "captures": cap, "replays": rep}
 
     # FP32 vs FP64 on the same samples (same GPU): |d ln L_marg| and the FP64 rate
     if not args.no_fp64 and w.precision == "fp32" and len(pts) == 1 and not grad:

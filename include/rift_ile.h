@@ -174,6 +174,23 @@ rift_status rift_ile_profile(rift_ile *h, int enable, double *ms_total, int64_t 
 /* Rebind the handle to another stream. */
 rift_status rift_ile_set_stream(rift_ile *h, void *stream);
 
+/* Graph replay of the FP32 evaluation (batching: the evaluation of many
+ * points launched as one unit).  With enable != 0, each evaluation run of
+ * rift_ile_lnL / rift_ile_marginalize on an FP32 handle (the delay-bin sort,
+ * the coefficient pass and the persistent matrix-core launches of all (T, K)
+ * classes, fanned out over the handle's side streams) is captured once into a
+ * hipGraph on the handle's stream and replayed whenever a later run has the
+ * same shape and buffers (later rounds of marginalize, repeated calls on the
+ * same workspace).  Results are bit-identical to the direct launches.  Not
+ * used while rift_ile_profile timing is on, for FP64 handles or for the
+ * adjoint.  The handle owns the graphs until destroy or until disabled.
+ * Returns RIFT_E_INVALID for a NULL handle. */
+rift_status rift_ile_set_graph(rift_ile *h, int enable);
+
+/* Diagnostics of the graph replay: graphs captured and replays launched since
+ * the handle was created (either output may be NULL). */
+rift_status rift_ile_graph_stats(const rift_ile *h, int64_t *captures, int64_t *replays);
+
 /* Extrinsic sample draw (Sec. II.A; Sec. III.B: random numbers generated on
  * the GPU).  Writes samples first..first+n-1 of (point, round): Philox4x32-10
  * with key = seed and counter = (i_lo, i_hi, 2 round + half, point); each

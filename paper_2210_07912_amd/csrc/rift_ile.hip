@@ -48,6 +48,12 @@ struct rift_ile {
   DevBuf ws[40];
   // side streams for concurrent class kernels, and the workspace budget
   Fanout fan{};
+  // captured evaluation runs: key (launch arguments and class layout) -> graph
+  bool use_graph = false;
+  std::vector<std::pair<std::vector<char>, hipGraphExec_t>> graphs;
+  hipStream_t gstream = nullptr;  // graph stream when the handle's stream is the null stream
+  hipEvent_t gfork = nullptr, gjoin = nullptr;
+  int64_t n_captures = 0, n_replays = 0;
   double ws_budget = 6.0e9;
   // optional timing of the dominant evaluation kernel
   bool prof = false;
@@ -373,6 +379,77 @@ rift_status run_plain(rift_ile *h, const Items &it, int64_t stride, const R *the
   return RIFT_OK;
 }
 
+// The evaluation launches of one run from a captured graph: the key is the
+// bytes of the launch arguments and of the class layout, so a replay happens
+// only when every kernel would see the same arguments.
+template <typename V>
+void key_add(std::vector<char> &k, const V &v) {
+  const char *b = (const char *)v.data();
+  k.insert(k.end(), b, b + sizeof(v[0]) * v.size());
+  k.push_back('|');
+}
+
+rift_status launch_graph(rift_ile *h, const MfmaArgs &a, const std::vector<int> &class_T,
+                         const std::vector<int> &class_K, const std::vector<int> &class_item0,
+                         const std::vector<int> &mclass_M, const std::vector<int> &mclass_item0,
+                         const std::vector<int64_t> &mclass_tiles) {
+  std::vector<char> key((const char *)&a, (const char *)&a + sizeof(a));
+  key_add(key, class_T);
+  key_add(key, class_K);
+  key_add(key, class_item0);
+  key_add(key, mclass_M);
+  key_add(key, mclass_item0);
+  key_add(key, mclass_tiles);
+  // the null stream cannot be captured: then the graph runs on the handle's
+  // own stream, ordered after and before the caller's work by events
+  hipStream_t gs = h->stream;
+  if (!gs) {
+    if (!h->gstream) {
+      HIPCHK(h, hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+      HIPCHK(h, hipEventCreateWithFlags(&h->gfork, hipEventDisableTiming));
+      HIPCHK(h, hipEventCreateWithFlags(&h->gjoin, hipEventDisableTiming));
+    }
+    gs = h->gstream;
+    HIPCHK(h, hipEventRecord(h->gfork, h->stream));
+    HIPCHK(h, hipStreamWaitEvent(gs, h->gfork, 0));
+  }
+  auto join = [&]() -> rift_status {
+    if (gs != h->stream) {
+      HIPCHK(h, hipEventRecord(h->gjoin, gs));
+      HIPCHK(h, hipStreamWaitEvent(h->stream, h->gjoin, 0));
+    }
+    return RIFT_OK;
+  };
+  for (auto &g : h->graphs)
+    if (g.first == key) {
+      HIPCHK(h, hipGraphLaunch(g.second, gs));
+      h->n_replays++;
+      return join();
+    }
+  hipGraph_t graph = nullptr;
+  HIPCHK(h, hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+  hipError_t e = mfma_forward(a, class_T.data(), class_K.data(), class_item0.data(), (int)class_T.size(),
+                              mclass_M.data(), mclass_item0.data(), mclass_tiles.data(), (int)mclass_M.size(),
+                              gs, h->fan, nullptr, nullptr);
+  hipError_t e2 = hipStreamEndCapture(gs, &graph);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return hip_fail(h, e != hipSuccess ? e : e2, "capturing the evaluation graph");
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(h, e, "instantiating the evaluation graph");
+  if (h->graphs.size() >= 16) {  // keep the most recent runs
+    (void)hipGraphExecDestroy(h->graphs.front().second);
+    h->graphs.erase(h->graphs.begin());
+  }
+  h->graphs.emplace_back(std::move(key), exec);
+  h->n_captures++;
+  HIPCHK(h, hipGraphLaunch(exec, gs));
+  return join();
+}
+
 // One group of points (already in evaluation order) through the sort, the
 // coefficient pass and the persistent MFMA launches.
 rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const float *theta, float *lnL, float *lnw,
@@ -495,6 +572,8 @@ rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const f
     HIPCHK(h, hipEventCreate(&e1));
     h->prof_ev.emplace_back(e0, e1);
   }
+  if (!grad && h->use_graph && !h->prof) return launch_graph(h, a, class_T, class_K, class_item0, mclass_M,
+                                                             mclass_item0, mclass_tiles);
   if (grad)
     HIPCHK(h, mfma_backward(a, class_T.data(), class_K.data(), class_item0.data(), (int)class_T.size(),
                             mclass_M.data(), mclass_item0.data(), mclass_tiles.data(), (int)mclass_M.size(), h->stream,
@@ -765,6 +844,13 @@ void rift_ile_destroy(rift_ile *h) {
     (void)hipEventDestroy(pe.first);
     (void)hipEventDestroy(pe.second);
   }
+  for (auto &g : h->graphs) (void)hipGraphExecDestroy(g.second);
+  if (h->gstream) {
+    (void)hipStreamSynchronize(h->gstream);
+    (void)hipStreamDestroy(h->gstream);
+  }
+  if (h->gfork) (void)hipEventDestroy(h->gfork);
+  if (h->gjoin) (void)hipEventDestroy(h->gjoin);
   for (int i = 0; i < h->fan.n; i++) {
     (void)hipStreamSynchronize(h->fan.side[i]);
     (void)hipStreamDestroy(h->fan.side[i]);
@@ -876,6 +962,24 @@ rift_status rift_ile_profile(rift_ile *h, int enable, double *ms_total, int64_t 
   h->prof = enable != 0;
   if (ms_total) *ms_total = tot;
   if (launches) *launches = n;
+  return RIFT_OK;
+}
+
+rift_status rift_ile_set_graph(rift_ile *h, int enable) {
+  if (!h) return RIFT_E_INVALID;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (!enable) {
+    for (auto &g : h->graphs) (void)hipGraphExecDestroy(g.second);
+    h->graphs.clear();
+  }
+  h->use_graph = enable != 0;
+  return RIFT_OK;
+}
+
+rift_status rift_ile_graph_stats(const rift_ile *h, int64_t *captures, int64_t *replays) {
+  if (!h) return RIFT_E_INVALID;
+  if (captures) *captures = h->n_captures;
+  if (replays) *replays = h->n_replays;
   return RIFT_OK;
 }
 

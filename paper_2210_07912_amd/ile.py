@@ -73,6 +73,8 @@ FUNCTIONS = {
     "rift_ile_status_string": (C.c_char_p, [C.c_int]),
     "rift_ile_abi_version": (C.c_int, []),
     "rift_ile_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "rift_ile_set_graph": (C.c_int, [C.c_void_p, C.c_int]),
+    "rift_ile_graph_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "rift_ile_profile": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "rift_ile_sample": (C.c_int, [C.c_void_p, C.c_int, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64,
                                   C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -180,6 +182,17 @@ class RiftILE:
         if t.dim() != 2 or t.shape[0] != NPAR:
             raise ValueError("theta must be [7, N]")
         return t.contiguous()
+
+    def set_graph(self, enable=True):
+        """Capture each FP32 evaluation run into a hipGraph once and replay it
+        when a later run has the same shape and buffers."""
+        self._check(lib().rift_ile_set_graph(self.h, int(enable)))
+
+    def graph_stats(self):
+        """(graphs captured, replays launched) since the handle was created."""
+        c, r = C.c_int64(), C.c_int64()
+        self._check(lib().rift_ile_graph_stats(self.h, C.byref(c), C.byref(r)))
+        return c.value, r.value
 
     def profile(self, enable=True):
         """(ms, launches) of the dominant kernel since the last call; then
