@@ -39,7 +39,7 @@
 
 namespace rift {
 
-constexpr int kRS = 68;          // floats per ring row: a 32-row ring stored twice, padded for banks
+constexpr int kRS = 52;          // floats per z ring row: two 16-row slots and slot 0 again (48 rows), padded
 constexpr int kSortThreads = 1024;  // threads per sort block (kSortBlock samples)
 
 __device__ __forceinline__ int item_of_flat(const ItemsDev &it, int64_t f) {
@@ -445,7 +445,7 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
   constexpr int ES = stage_stride<T>();
   constexpr int SF = K * kTS * ES;  // floats of one staged block
   __shared__ __align__(16) float ring_all[kWaves * K * kTS * kRS];
-  __shared__ __align__(16) float stage[3][SF];  // block b in buffer b % 3
+  __shared__ __align__(16) float stage[4][SF];  // block b in slot b % 4; two blocks per barrier
   __shared__ WorkUnit unit_sh;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float *ring = ring_all + wave * (K * kTS * kRS);  // [det][sample][kRS]
@@ -512,39 +512,45 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
       }
     }
     const int JB = (NT + 15) >> 4;
-    // z ring: block c in rows 16 (c % 3) .. + 15 of a 64-row ring (slot 0
-    // also in rows 48..63), so the 7 rows a window read needs are contiguous
+    // z ring: block b in rows 16 (b % 2) .. + 15 (slot 0 also in rows 32..47),
+    // so the 7 rows a window read needs are contiguous
     const float *rz[K];
 #pragma unroll
     for (int k = 0; k < K; k++) rz[k] = ring + (k * kTS + s) * kRS + 4 * g + sh[k];
     float *const wz = ring + s * kRS + 4 * g;
-    const float *const sa = &stage[0][s * ES + 4 * g];       // this lane's quads in buffer 0
+    const float *const sa = &stage[0][s * ES + 4 * g];       // this lane's quads in slot 0
     const float *const st = &stage[0][s * ES + 16 * J + g];  // and the rest
     const int rem = NT - 16 * (JB - 1);
     float last_pen[4];  // -inf for window samples past n_t in the last block
 #pragma unroll
     for (int i = 0; i < 4; i++) last_pen[i] = (4 * g + i < rem) ? 0.f : -INFINITY;
 
-    f4 pre[K];
-    auto stage_load = [&](int blk) {
-      if (st_on) {
-        const uint32_t ob = (uint32_t)(64 * E) * (uint32_t)blk + st_goff;
-#pragma unroll
-        for (int k = 0; k < K; k++) pre[k] = *(const RIFT_GLOBAL f4 *)((const RIFT_GLOBAL char *)qk[k] + ob);
-      }
-    };
-    auto stage_store = [&](auto buf_c) {
-      constexpr int BUF = decltype(buf_c)::value;
+    f4 pre[2][K];
+    // global loads of blocks b and b + 1 (clamped to the last block)
+    auto stage_load2 = [&](int b) {
       if (st_on) {
 #pragma unroll
-        for (int k = 0; k < K; k++) *(f4 *)(&stage[BUF][k * kTS * ES + st_loff]) = pre[k];
+        for (int hb = 0; hb < 2; hb++) {
+          const uint32_t ob = (uint32_t)(64 * E) * (uint32_t)min(b + hb, JB) + st_goff;
+#pragma unroll
+          for (int k = 0; k < K; k++) pre[hb][k] = *(const RIFT_GLOBAL f4 *)((const RIFT_GLOBAL char *)qk[k] + ob);
+        }
       }
     };
-    // block in buffer BUF on the matrix cores; z_k[base + 16 b + 4 g + v] of
-    // sample s -> ring slot BUF (the ring slot of a block is its buffer)
-    auto product = [&](auto buf_c) {
-      constexpr int BUF = decltype(buf_c)::value;
-      const float *sb = sa + BUF * SF;
+    auto stage_store2 = [&](auto slot_c) {
+      constexpr int S0 = decltype(slot_c)::value;
+      if (st_on) {
+#pragma unroll
+        for (int hb = 0; hb < 2; hb++)
+#pragma unroll
+          for (int k = 0; k < K; k++) *(f4 *)(&stage[(S0 + hb) & 3][k * kTS * ES + st_loff]) = pre[hb][k];
+      }
+    };
+    // the block in stage slot S4 on the matrix cores; z_k[base + 16 b + 4 g + v]
+    // of sample s -> ring slot S4 % 2
+    auto product = [&](auto s4_c) {
+      constexpr int S4 = decltype(s4_c)::value;
+      const float *sb = sa + S4 * SF;
       f4 Aq[K][JA];
       float At[K][RA];
 #pragma unroll
@@ -552,7 +558,7 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
 #pragma unroll
         for (int j = 0; j < J; j++) Aq[k][j] = *(const f4 *)(sb + k * kTS * ES + 16 * j);
 #pragma unroll
-        for (int r = 0; r < R; r++) At[k][r] = st[BUF * SF + k * kTS * ES + 4 * r];
+        for (int r = 0; r < R; r++) At[k][r] = st[S4 * SF + k * kTS * ES + 4 * r];
       }
       f4 acc[K];
 #pragma unroll
@@ -565,8 +571,8 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
         }
 #pragma unroll
       for (int k = 0; k < K; k++) {
-        *(f4 *)(wz + k * kTS * kRS + 16 * BUF) = acc[k];
-        if constexpr (BUF == 0) *(f4 *)(wz + k * kTS * kRS + 48) = acc[k];
+        *(f4 *)(wz + k * kTS * kRS + 16 * (S4 & 1)) = acc[k];
+        if constexpr ((S4 & 1) == 0) *(f4 *)(wz + k * kTS * kRS + 32) = acc[k];
       }
     };
     // window samples 16 c + 4 g + i (i < 4) of the block in ring slot SL:
@@ -608,43 +614,38 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
       for (int i = 0; i < 4; i++) s_run += __builtin_amdgcn_exp2f(ell[i]);
     };
     using C0 = std::integral_constant<int, 0>;
-    using C1 = std::integral_constant<int, 1>;
     using C2 = std::integral_constant<int, 2>;
-    // step b (buffer and ring slot b % 3): stage block b + 1, the MFMAs of
-    // block b, the window samples of block b - 2 (ring slot (b + 1) % 3)
-    auto step = [&](auto ph_c, int b) {
-      constexpr int PH = decltype(ph_c)::value;
-      constexpr int NX = (PH + 1) % 3;
-      stage_load(min(b + 1, JB));
+    // block b (stage slot S4 = b % 4): its MFMAs, then the window samples of
+    // block b - 1, whose rows (blocks b - 1 and b) are then in the ring
+    auto block = [&](auto s4_c, int b) {
+      constexpr int S4 = decltype(s4_c)::value;
+      product(s4_c);
+      wave_sync();
+      if (b >= 1) window(std::integral_constant<int, (S4 + 1) & 1>{}, b == JB, b == 1);
+    };
+    // blocks b, b + 1 (slots S0, S0 + 1) with one barrier; blocks b + 2, b + 3
+    // are loaded meanwhile into the other two slots
+    auto pair = [&](auto s0_c, int b) {
+      constexpr int S0 = decltype(s0_c)::value;
+      stage_load2(b + 2);
       if (active) {
-        product(ph_c);
-        if (b >= 2) window(std::integral_constant<int, NX>{}, false, b == 2);
+        block(std::integral_constant<int, S0>{}, b);
+        if (b + 1 <= JB) block(std::integral_constant<int, S0 + 1>{}, b + 1);
       }
-      stage_store(std::integral_constant<int, NX>{});
+      stage_store2(std::integral_constant<int, (S0 + 2) & 3>{});
       __syncthreads();
     };
 
-    stage_load(0);
-    stage_store(C0{});
+    stage_load2(0);
+    stage_store2(C0{});
     __syncthreads();
-    step(C0{}, 0);
-    step(C1{}, 1);
-    int b = 2;
-    for (; b + 2 <= JB; b += 3) {
-      step(C2{}, b);
-      step(C0{}, b + 1);
-      step(C1{}, b + 2);
+    int b = 0;
+    for (; b + 3 <= JB; b += 4) {
+      pair(C0{}, b);
+      pair(C2{}, b + 2);
     }
-    if (b <= JB) step(C2{}, b++);
-    if (b <= JB) step(C0{}, b++);
-    // the last window block, c = JB - 1, in ring slot (JB - 1) % 3
-    if (active) {
-      wave_sync();
-      const int sl = (JB - 1) % 3;
-      if (sl == 0) window(C0{}, true, JB == 1);
-      else if (sl == 1) window(C1{}, true, JB == 1);
-      else window(C2{}, true, JB == 1);
-    }
+    if (b <= JB) pair(C0{}, b);
+    if (b + 2 <= JB) pair(C2{}, b + 2);
     if (active) {
       // combine the four lanes of each sample (base 2), then ln L_t
       float mo = m_run;
