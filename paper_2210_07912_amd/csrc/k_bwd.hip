@@ -352,11 +352,12 @@ __global__ void __launch_bounds__(64) chain_kernel(MfmaArgs a, int item_lo, int 
     double ci, si, c1, s1;
     sincos(0.5 * th[RIFT_IOTA], &si, &ci);
     sincos(th[RIFT_PHI], &s1, &c1);
-    // Y_m and dY_m / d iota
-    double Yr[YR], Yi[YR], dYr[YR], dYi[YR];
+    // Y_m in registers (the U Y and V Y products use all of them); Y_m and
+    // dY_m / d iota again, one mode at a time, in the loop below
+    double Yr[YR], Yi[YR];
 #pragma unroll
     for (int m = 0; m < YR; m++) {
-      Yr[m] = Yi[m] = dYr[m] = dYi[m] = 0.0;
+      Yr[m] = Yi[m] = 0.0;
       if (m < M) {
         int em = p.em[m], am = em < 0 ? -em : em;
         double cr = 1.0, cim = 0.0;
@@ -366,13 +367,14 @@ __global__ void __launch_bounds__(64) chain_kernel(MfmaArgs a, int item_lo, int 
           cr = nr;
         }
         if (em < 0) cim = -cim;
-        harmonic(p, m, ci, si, cr, cim, Yr[m], Yi[m], &dYr[m], &dYi[m]);
+        harmonic(p, m, ci, si, cr, cim, Yr[m], Yi[m]);
       }
     }
     const double dn_a[3] = {-tr.cd * tr.sh, tr.cd * tr.ch, 0.0};
     const double dn_d[3] = {-tr.sd * tr.ch, -tr.sd * tr.sh, tr.cd};
     const RIFT_CONST double *Uc = cp(p.U);
     const RIFT_CONST double *Vc = p.V ? cp(p.V) : nullptr;
+#pragma unroll 1
     for (int k = 0; k < K; k++) {
       double Fp, Fc, dFa[2], dFd[2];
       antenna(p.D[k], tr, Fp, Fc, dFa, dFd);
@@ -382,9 +384,19 @@ __global__ void __launch_bounds__(64) chain_kernel(MfmaArgs a, int item_lo, int 
       out[RIFT_ALPHA] += H * p.f_s * ddt_a;
       out[RIFT_DELTA] += H * p.f_s * ddt_d;
       out[RIFT_TAU] += H * p.f_s;
-#pragma unroll
-      for (int m = 0; m < YR; m++) {
-        if (m >= M) break;
+#pragma unroll 1
+      for (int m = 0; m < M; m++) {
+        // Y_m and its iota derivative for this mode
+        int em = p.em[m], am = em < 0 ? -em : em;
+        double cr = 1.0, cim = 0.0;
+        for (int q = 0; q < am; q++) {
+          double nr = cr * c1 - cim * s1;
+          cim = cr * s1 + cim * c1;
+          cr = nr;
+        }
+        if (em < 0) cim = -cim;
+        double yr, yi, dyr, dyi;
+        harmonic(p, m, ci, si, cr, cim, yr, yi, &dyr, &dyi);
         // (U a)_m = x F_k (U Y)_m, (V a)_m = x F_k (V Y)_m
         const RIFT_CONST double *U = Uc + ((size_t)k * M + m) * M * 2;
         double uyr = 0.0, uyi = 0.0, vyr = 0.0, vyi = 0.0;
@@ -410,13 +422,12 @@ __global__ void __launch_bounds__(64) chain_kernel(MfmaArgs a, int item_lo, int 
         const double Gr = (double)gk[((size_t)k * E + 2 * m) * kTS], Gi = (double)gk[((size_t)k * E + 2 * m + 1) * kTS];
         const double er = Gr - 0.5 * uar, ei = Gi - 0.5 * uai;
         auto contrib = [&](double dar, double dai) { return dar * er + dai * ei - 0.5 * (dar * var - dai * vai); };
-        const double yr = Yr[m], yi = Yi[m];
         out[RIFT_ALPHA] += contrib(x * (dFa[0] * yr - dFa[1] * yi), x * (dFa[0] * yi + dFa[1] * yr));
         out[RIFT_DELTA] += contrib(x * (dFd[0] * yr - dFd[1] * yi), x * (dFd[0] * yi + dFd[1] * yr));
         const double Fpr = 2.0 * Fc, Fpi = -2.0 * Fp;  // dF / dpsi = -2 i F
         out[RIFT_PSI] += contrib(x * (Fpr * yr - Fpi * yi), x * (Fpr * yi + Fpi * yr));
-        out[RIFT_IOTA] += contrib(x * (Fp * dYr[m] - Fc * dYi[m]), x * (Fp * dYi[m] + Fc * dYr[m]));
-        const double iyr = -p.em[m] * yi, iyi = p.em[m] * yr;
+        out[RIFT_IOTA] += contrib(x * (Fp * dyr - Fc * dyi), x * (Fp * dyi + Fc * dyr));
+        const double iyr = -em * yi, iyi = em * yr;
         out[RIFT_PHI] += contrib(x * (Fp * iyr - Fc * iyi), x * (Fp * iyi + Fc * iyr));
         const double ar = x * (Fp * yr - Fc * yi), ai = x * (Fp * yi + Fc * yr);
         out[RIFT_DIST] += contrib(-ar / th[RIFT_DIST], -ai / th[RIFT_DIST]);
