@@ -49,6 +49,7 @@ __device__ __forceinline__ const RIFT_CONST T *cp(const T *p) {
 constexpr int kMaxDet = RIFT_MAX_DET;
 constexpr int kMaxModes = RIFT_MAX_MODES;
 constexpr int kMaxYTerms = 8;   // Wigner-d sum terms for l <= 8
+constexpr int kMaxHDeg = 8;     // degree of the harmonic polynomial for l <= 8
 constexpr int kNB = RIFT_NBINS;
 constexpr double kC = 299792458.0;
 constexpr double kPi = 3.14159265358979323846;
@@ -70,6 +71,12 @@ struct PointDev {
   double ycoef[kMaxModes][kMaxYTerms];
   int ypc[kMaxModes][kMaxYTerms];  // power of cos(iota/2)
   int yps[kMaxModes][kMaxYTerms];  // power of sin(iota/2)
+  // The same harmonic as a polynomial: ynorm d(iota) = (sin(iota)/2)^hpar[m]
+  // sum_j hpoly[m][j] u^j with u = cos^2(iota/2), degree hdeg[m] = l - hpar[m]
+  // (every term of the Wigner-d sum has powers of one parity, that of m)
+  double hpoly[kMaxModes][kMaxHDeg + 1];
+  int hdeg[kMaxModes];
+  int hpar[kMaxModes];
   const double *U;             // [K][M][M][2], values rounded to the bulk precision
   const double *V;             // same or nullptr
   const double *Upk;           // [pairs m<=m'][kMaxDet][2]: U_mm', off-diagonal doubled

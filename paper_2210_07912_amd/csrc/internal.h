@@ -125,8 +125,9 @@ struct Fanout {
 
 // ev0/ev1 (or null): recorded around the persistent evaluation kernels
 // classes: runs of points with the same MFMA step count T (evaluation
-// launches) and with the same mode count M (coefficient launches; mclass_tiles
-// bounds the tiles of each run)
+// launches) and with the same mode count M (coefficient launches; mclass_M is
+// -M for runs of points that carry a V table, mclass_tiles bounds the tiles
+// of each run)
 hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_K, const int *class_item0, int n_classes,
                         const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles, int n_mclasses,
                         hipStream_t st, const Fanout &fo, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);

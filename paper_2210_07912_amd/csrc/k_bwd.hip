@@ -323,18 +323,25 @@ __global__ void __launch_bounds__(256) mfma_bwd_kernel(MfmaArgs a, int item_lo, 
 }
 
 // ---- chain rule, FP64, one thread per sorted slot --------------------------
+// Point constants come through the constant address space (a block is 4 whole
+// tiles of one point).  Harmonics and their iota derivatives from the
+// polynomial tables: Y = s^par P(u) e^{i m phi} with s = sin(iota)/2 and
+// u = cos^2(iota/2), so dY/diota = (par cos(iota)/2 P(u) - s^(par+1) P'(u))
+// e^{i m phi}, with P and P' by one Horner pass.
 template <int MC>
 __global__ void __launch_bounds__(64) chain_kernel(MfmaArgs a, int item_lo, int item_hi) {
   constexpr int YR = MC > 0 ? MC : kMaxModes;
   const int64_t t_lo = a.item_tiles[item_lo], t_hi = a.item_tiles[item_hi];
-  const int64_t pos = t_lo * kTS + (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (pos >= t_hi * kTS) return;
+  const int64_t t_blk = t_lo + 4 * (int64_t)blockIdx.x;
+  if (t_blk >= t_hi) return;  // whole block (items hold whole blocks of 4 tiles)
+  const int64_t pos = t_blk * kTS + threadIdx.x;
   const int64_t t = pos / kTS;
   const int s = (int)(pos % kTS);
   const SampleRec rec = a.rec[pos];
   if (rec.flag == 0) return;  // padding
-  const int it = __builtin_amdgcn_readfirstlane(a.tile_item[t]);
-  const PointDev &p = a.pts[a.items.point[it]];
+  const int it = __builtin_amdgcn_readfirstlane(a.tile_item[t_blk]);
+  const int pt = __builtin_amdgcn_readfirstlane(a.items.point[it]);
+  const RIFT_CONST PointDev &p = *cp(a.pts + pt);
   const int K = p.K, E = 2 * p.Mp;
   const int M = MC > 0 ? MC : p.M;
   const int64_t col = rec.col;
@@ -352,23 +359,45 @@ __global__ void __launch_bounds__(64) chain_kernel(MfmaArgs a, int item_lo, int 
     double ci, si, c1, s1;
     sincos(0.5 * th[RIFT_IOTA], &si, &ci);
     sincos(th[RIFT_PHI], &s1, &c1);
+    const double u = ci * ci, hs = si * ci, hc = 0.5 * (ci * ci - si * si);
+    // Y_m (and, with dy, dY_m / d iota) of mode m
+    auto mode = [&](int m, double &yr, double &yi, double *dyr, double *dyi) {
+      const int deg = p.hdeg[m];
+      double P = p.hpoly[m][deg], dP = 0.0;
+      for (int j = deg - 1; j >= 0; j--) {
+        dP = fma(dP, u, P);
+        P = fma(P, u, p.hpoly[m][j]);
+      }
+      double y, dy;
+      if (p.hpar[m]) {
+        y = hs * P;
+        dy = hc * P - hs * hs * dP;
+      } else {
+        y = P;
+        dy = -hs * dP;
+      }
+      const int em = p.em[m], am = em < 0 ? -em : em;
+      double cr = 1.0, cim = 0.0;
+      for (int q = 0; q < am; q++) {
+        double nr = cr * c1 - cim * s1;
+        cim = cr * s1 + cim * c1;
+        cr = nr;
+      }
+      if (em < 0) cim = -cim;
+      yr = y * cr;
+      yi = y * cim;
+      if (dyr) {
+        *dyr = dy * cr;
+        *dyi = dy * cim;
+      }
+    };
     // Y_m in registers (the U Y and V Y products use all of them); Y_m and
     // dY_m / d iota again, one mode at a time, in the loop below
     double Yr[YR], Yi[YR];
 #pragma unroll
     for (int m = 0; m < YR; m++) {
       Yr[m] = Yi[m] = 0.0;
-      if (m < M) {
-        int em = p.em[m], am = em < 0 ? -em : em;
-        double cr = 1.0, cim = 0.0;
-        for (int q = 0; q < am; q++) {
-          double nr = cr * c1 - cim * s1;
-          cim = cr * s1 + cim * c1;
-          cr = nr;
-        }
-        if (em < 0) cim = -cim;
-        harmonic(p, m, ci, si, cr, cim, Yr[m], Yi[m]);
-      }
+      if (m < M) mode(m, Yr[m], Yi[m], nullptr, nullptr);
     }
     const double dn_a[3] = {-tr.cd * tr.sh, tr.cd * tr.ch, 0.0};
     const double dn_d[3] = {-tr.sd * tr.ch, -tr.sd * tr.sh, tr.cd};
@@ -376,27 +405,24 @@ __global__ void __launch_bounds__(64) chain_kernel(MfmaArgs a, int item_lo, int 
     const RIFT_CONST double *Vc = p.V ? cp(p.V) : nullptr;
 #pragma unroll 1
     for (int k = 0; k < K; k++) {
+      double D[9], rc[3];
+#pragma unroll
+      for (int i = 0; i < 9; i++) D[i] = p.D[k][i];
+#pragma unroll
+      for (int i = 0; i < 3; i++) rc[i] = p.rc[k][i];
       double Fp, Fc, dFa[2], dFd[2];
-      antenna(p.D[k], tr, Fp, Fc, dFa, dFd);
+      antenna(D, tr, Fp, Fc, dFa, dFd);
       const double H = (double)hk[k * kTS];
-      const double ddt_a = -(p.rc[k][0] * dn_a[0] + p.rc[k][1] * dn_a[1] + p.rc[k][2] * dn_a[2]);
-      const double ddt_d = -(p.rc[k][0] * dn_d[0] + p.rc[k][1] * dn_d[1] + p.rc[k][2] * dn_d[2]);
+      const double ddt_a = -(rc[0] * dn_a[0] + rc[1] * dn_a[1] + rc[2] * dn_a[2]);
+      const double ddt_d = -(rc[0] * dn_d[0] + rc[1] * dn_d[1] + rc[2] * dn_d[2]);
       out[RIFT_ALPHA] += H * p.f_s * ddt_a;
       out[RIFT_DELTA] += H * p.f_s * ddt_d;
       out[RIFT_TAU] += H * p.f_s;
 #pragma unroll 1
       for (int m = 0; m < M; m++) {
-        // Y_m and its iota derivative for this mode
-        int em = p.em[m], am = em < 0 ? -em : em;
-        double cr = 1.0, cim = 0.0;
-        for (int q = 0; q < am; q++) {
-          double nr = cr * c1 - cim * s1;
-          cim = cr * s1 + cim * c1;
-          cr = nr;
-        }
-        if (em < 0) cim = -cim;
         double yr, yi, dyr, dyi;
-        harmonic(p, m, ci, si, cr, cim, yr, yi, &dyr, &dyi);
+        mode(m, yr, yi, &dyr, &dyi);
+        const int em = p.em[m];
         // (U a)_m = x F_k (U Y)_m, (V a)_m = x F_k (V Y)_m
         const RIFT_CONST double *U = Uc + ((size_t)k * M + m) * M * 2;
         double uyr = 0.0, uyi = 0.0, vyr = 0.0, vyi = 0.0;
@@ -404,8 +430,8 @@ __global__ void __launch_bounds__(64) chain_kernel(MfmaArgs a, int item_lo, int 
         for (int mp = 0; mp < YR; mp++) {
           if (mp >= M) break;
           const double ur = U[2 * mp], ui = U[2 * mp + 1];
-          uyr += ur * Yr[mp] - ui * Yi[mp];
-          uyi += ur * Yi[mp] + ui * Yr[mp];
+          uyr = fma(-ui, Yi[mp], fma(ur, Yr[mp], uyr));
+          uyi = fma(ui, Yr[mp], fma(ur, Yi[mp], uyi));
         }
         if (Vc) {
           const RIFT_CONST double *V = Vc + ((size_t)k * M + m) * M * 2;
@@ -413,8 +439,8 @@ __global__ void __launch_bounds__(64) chain_kernel(MfmaArgs a, int item_lo, int 
           for (int mp = 0; mp < YR; mp++) {
             if (mp >= M) break;
             const double vr = V[2 * mp], vi = V[2 * mp + 1];
-            vyr += vr * Yr[mp] - vi * Yi[mp];
-            vyi += vr * Yi[mp] + vi * Yr[mp];
+            vyr = fma(-vi, Yi[mp], fma(vr, Yr[mp], vyr));
+            vyi = fma(vi, Yr[mp], fma(vr, Yi[mp], vyi));
           }
         }
         const double uar = x * (Fp * uyr - Fc * uyi), uai = x * (Fp * uyi + Fc * uyr);
@@ -486,7 +512,7 @@ hipError_t mfma_backward(const MfmaArgs &a, const int *class_T, const int *class
   for (int c = 0; c < n_mclasses; c++) {
     const int lo = mclass_item0[c], hi = mclass_item0[c + 1];
     const dim3 grid((unsigned)(((int64_t)kTS * mclass_tiles[c] + 63) / 64));
-    switch (mclass_M[c]) {
+    switch (mclass_M[c] < 0 ? -mclass_M[c] : mclass_M[c]) {
       case 2: hipLaunchKernelGGL(chain_kernel<2>, grid, dim3(64), 0, st, a, lo, hi); break;
       case 5: hipLaunchKernelGGL(chain_kernel<5>, grid, dim3(64), 0, st, a, lo, hi); break;
       case 9: hipLaunchKernelGGL(chain_kernel<9>, grid, dim3(64), 0, st, a, lo, hi); break;

@@ -263,12 +263,23 @@ __device__ void tuple_result(const ReduceTuple &t, rift_ile_result &o) {
   }
 }
 
-__global__ void reduce_finish_kernel(const ReduceTuple *partials, int n_seg, int bps, ReduceTuple *round_out,
-                                     ReduceTuple *accum, int accumulate, rift_ile_result *out) {
-  int seg = blockIdx.x * blockDim.x + threadIdx.x;
-  if (seg >= n_seg) return;
+// One workgroup per segment: lane i merges partials i, i + 64, ... in order,
+// then a fixed tree over the lanes; the order depends only on bps.
+__global__ void __launch_bounds__(64) reduce_finish_kernel(const ReduceTuple *partials, int n_seg, int bps,
+                                                           ReduceTuple *round_out, ReduceTuple *accum,
+                                                           int accumulate, rift_ile_result *out) {
+  __shared__ ReduceTuple sh[64];
+  const int seg = blockIdx.x;
   ReduceTuple t = tup_zero();
-  for (int j = 0; j < bps; j++) t = tup_merge(t, partials[seg * bps + j]);
+  for (int j = threadIdx.x; j < bps; j += 64) t = tup_merge(t, partials[(size_t)seg * bps + j]);
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] = tup_merge(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  t = sh[0];
   if (round_out) round_out[seg] = t;
   if (accum) {
     ReduceTuple a = accumulate ? tup_merge(accum[seg], t) : t;
@@ -281,8 +292,8 @@ __global__ void reduce_finish_kernel(const ReduceTuple *partials, int n_seg, int
 hipError_t reduce_finish(const ReduceTuple *partials, int n_seg, int bps, ReduceTuple *round_out, ReduceTuple *accum,
                          int accumulate, rift_ile_result *out, hipStream_t st) {
   if (n_seg <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_finish_kernel, dim3((n_seg + 63) / 64), dim3(64), 0, st, partials, n_seg, bps, round_out,
-                     accum, accumulate, out);
+  hipLaunchKernelGGL(reduce_finish_kernel, dim3(n_seg), dim3(64), 0, st, partials, n_seg, bps, round_out, accum,
+                     accumulate, out);
   return hipGetLastError();
 }
 

@@ -284,84 +284,97 @@ __global__ void __launch_bounds__(256) unit_kernel(MfmaArgs a) {
 // host: q_k = Y^dag U_k Y = sum_{m <= m'} Re(conj(Y_m) c_{mm'} Y_m'),
 // t_k = Y^T V_k Y = sum_{m <= m'} c'_{mm'} Y_m Y_m', with the off-diagonal
 // factor 2 folded into c, c'; B = x^2/4 sum_k [|F_k|^2 q_k + Re(F_k^2 t_k)].
-// MC > 0: the mode count is a compile-time constant, Y lives in registers and
-// the pair sums unroll (point data then comes through scalar loads); MC = 0
-// is the general form, with Y staged in LDS.
+// A block is 4 whole tiles of one point, so the point's constants are read
+// through the constant address space (scalar loads) and every branch on them
+// is uniform.  The packed tables are zero for detectors past K and F_k = 0
+// there, so the pair sums run over all kMaxDet detectors without branches.
+// Harmonics use the polynomial form of the host tables (Horner in
+// u = cos^2(iota/2)).  MC > 0: the mode count is a compile-time constant, Y
+// lives in registers and the pair sums unroll over a copy of the packed table
+// in LDS (read at immediate offsets; as scalar loads the unrolled sums would
+// need more scalar registers than there are).  MC = 0 is the general form,
+// with Y staged in LDS and the tables read by scalar loads in loops; points
+// with a V table always take it (the host gives them classes of their own).
+// Padding and invalid slots run the same code on a harmless angle set and
+// store zeros, so every lane reaches the barriers.
 template <int MC>
 __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int item_hi) {
   constexpr int YS = MC > 0 ? 1 : 64;
   constexpr int YM = MC > 0 ? 1 : kMaxModes;
   constexpr int YR = MC > 0 ? MC : 1;
+  constexpr int NTAB = MC > 0 ? MC * (MC + 1) / 2 * kMaxDet * 2 : 1;
   __shared__ double Ys[YS][YM][2];
+  __shared__ __align__(16) double tab[NTAB];
   const int64_t t_lo = a.item_tiles[item_lo], t_hi = a.item_tiles[item_hi];
-  const int64_t pos = t_lo * kTS + (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (pos >= t_hi * kTS) return;
+  const int64_t t_blk = t_lo + 4 * (int64_t)blockIdx.x;
+  if (t_blk >= t_hi) return;  // whole block (items hold whole blocks of 4 tiles)
+  const int64_t pos = t_blk * kTS + threadIdx.x;
   const int64_t t = pos / kTS;
   const int s = (int)(pos % kTS);
   const SampleRec rec = a.rec[pos];
-  // a block is 4 whole tiles of one point (tiles are padded per point)
-  const int it = __builtin_amdgcn_readfirstlane(a.tile_item[t]);
-  const PointDev &p = a.pts[a.items.point[it]];
+  const int it = __builtin_amdgcn_readfirstlane(a.tile_item[t_blk]);
+  const int pt = __builtin_amdgcn_readfirstlane(a.items.point[it]);
+  const RIFT_CONST PointDev &p = *cp(a.pts + pt);
   const int K = p.K, E = 2 * p.Mp;
   const int M = MC > 0 ? MC : p.M;
+  if constexpr (MC > 0) {
+    const RIFT_GLOBAL double *src = gp(p.Upk);
+    for (int i = threadIdx.x; i < NTAB; i += 64) tab[i] = src[i];
+    __syncthreads();
+  }
   RIFT_GLOBAL float *op = gpw(a.cop + a.item_cop[it] + (int64_t)(t - a.item_tiles[it]) * K * E * kTS + s);
   RIFT_GLOBAL CoefTile *ct = gpw(a.ctile + t);
-  bool pad = rec.flag == 0;
-  bool valid = rec.flag == 1;
-  if (!valid) {
-    for (int k = 0; k < K; k++)
-      for (int e = 0; e < 2 * p.Mp; e++) op[((size_t)k * E + e) * kTS] = 0.f;
-    ct->B[s] = 0.f;
-    for (int k = 0; k < kMaxDet; k++) {
-      ct->mu[k][s] = 0.f;
-      ct->n[k][s] = 1 << 28;
-    }
-    ct->col[s] = pad ? -1 : rec.col;
-    ct->flag[s] = pad ? 0 : 2;
-    return;
-  }
-  const int64_t col = rec.col;
+  const bool pad = rec.flag == 0;
+  const bool valid = rec.flag == 1;
   double th[7];
 #pragma unroll
-  for (int d = 0; d < 7; d++) th[d] = (double)rec.th[d];
+  for (int d = 0; d < 7; d++) th[d] = valid ? (double)rec.th[d] : (d == RIFT_DIST ? 1.0 : 0.0);
   const double x = p.d_ref / th[RIFT_DIST];
-  const double xl = x * kLog2e;
+  const double xl = valid ? x * kLog2e : 0.0;
   SkyTrig tr = sky_trig(th[RIFT_ALPHA], th[RIFT_DELTA], th[RIFT_PSI], p.gmst);
   double Fr[kMaxDet], Fi[kMaxDet];
 #pragma unroll
   for (int k = 0; k < kMaxDet; k++) {
     Fr[k] = Fi[k] = 0.0;
     if (k < K) {
-      antenna(p.D[k], tr, Fr[k], Fi[k]);
-      int n = (int)rec.n[k];
-      double sk = (th[RIFT_TAU] + delay(p.rc[k], tr)) * p.f_s;
-      ct->mu[k][s] = (float)(sk - (double)n);
-      ct->n[k][s] = n;
+      double D[9], rc[3];
+#pragma unroll
+      for (int i = 0; i < 9; i++) D[i] = p.D[k][i];
+#pragma unroll
+      for (int i = 0; i < 3; i++) rc[i] = p.rc[k][i];
+      antenna(D, tr, Fr[k], Fi[k]);
+      const int n = (int)rec.n[k];
+      const double sk = (th[RIFT_TAU] + delay(rc, tr)) * p.f_s;
+      ct->mu[k][s] = valid ? (float)(sk - (double)n) : 0.f;
+      ct->n[k][s] = valid ? n : 1 << 28;
     } else {
       ct->mu[k][s] = 0.f;
       ct->n[k][s] = 1 << 28;
     }
   }
-  // harmonics: Y_m = ynorm d(iota) exp(i m phi); exp(i m phi) by repeated
-  // products of exp(i phi)
+  // harmonics: Y_m = (sin(iota)/2)^par P_m(cos^2(iota/2)) exp(i m phi), with
+  // exp(i m phi) by repeated products of exp(i phi)
   double ci, si, c1, s1;
   sincos(0.5 * th[RIFT_IOTA], &si, &ci);
   sincos(th[RIFT_PHI], &s1, &c1);
+  const double u = ci * ci, hs = si * ci;
   double Yr[YR], Yi[YR];
   double (*Yl)[2] = Ys[MC > 0 ? 0 : threadIdx.x];
 #pragma unroll
   for (int m = 0; m < (MC > 0 ? MC : kMaxModes); m++) {
     if (m >= M) break;
-    int em = p.em[m], am = em < 0 ? -em : em;
-    double cr = 1.0, cim = 0.0;
+    const int deg = p.hdeg[m];
+    double d = p.hpoly[m][deg];
+    for (int j = deg - 1; j >= 0; j--) d = fma(d, u, p.hpoly[m][j]);
+    if (p.hpar[m]) d *= hs;
+    const int em = p.em[m], am = em < 0 ? -em : em;
+    double cr = d, cim = 0.0;
     for (int q = 0; q < am; q++) {
       double nr = cr * c1 - cim * s1;
       cim = cr * s1 + cim * c1;
       cr = nr;
     }
-    if (em < 0) cim = -cim;
-    double yr, yi;
-    harmonic(p, m, ci, si, cr, cim, yr, yi);
+    const double yr = cr, yi = em < 0 ? -cim : cim;
     if constexpr (MC > 0) {
       Yr[m] = yr;
       Yi[m] = yi;
@@ -369,66 +382,65 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
       Yl[m][0] = yr;
       Yl[m][1] = yi;
     }
-    // B operand elements 2m (Re a) and 2m+1 (Im a), for every detector
+    // B operand elements 2m (Re a) and 2m+1 (Im a), for every detector, in
+    // base-2 units (times log2 e) for the evaluation kernel's exp2/log2
 #pragma unroll
     for (int k = 0; k < kMaxDet; k++) {
       if (k < K) {
-        // in base-2 units (times log2 e) for the evaluation kernel's exp2/log2
-        double ar = xl * (Fr[k] * yr - Fi[k] * yi), ai = xl * (Fr[k] * yi + Fi[k] * yr);
+        const double ar = xl * (Fr[k] * yr - Fi[k] * yi), ai = xl * (Fr[k] * yi + Fi[k] * yr);
         op[((size_t)k * E + 2 * m) * kTS] = (float)ar;
         op[((size_t)k * E + 2 * m + 1) * kTS] = (float)ai;
       }
     }
   }
   for (int k = 0; k < K; k++)
-    for (int e = 2 * M; e < 2 * p.Mp; e++) op[((size_t)k * E + e) * kTS] = 0.f;
+    for (int e = 2 * M; e < E; e++) op[((size_t)k * E + e) * kTS] = 0.f;
   double q[kMaxDet] = {0.0, 0.0, 0.0}, vr[kMaxDet] = {0.0, 0.0, 0.0}, vi[kMaxDet] = {0.0, 0.0, 0.0};
-  const RIFT_CONST double *Uq = cp(p.Upk);
-  const RIFT_CONST double *Vq = p.Vpk ? cp(p.Vpk) : nullptr;
-  auto pair = [&](int idx, double ymr, double ymi, double ypr, double ypi) {
-    // conj(Y_m) Y_m' and Y_m Y_m'
+  // conj(Y_m) Y_m' against U, Y_m Y_m' against V
+  auto upair = [&](const auto *T, int idx, double ymr, double ymi, double ypr, double ypi) {
     const double pr = ymr * ypr + ymi * ypi, pi = ymr * ypi - ymi * ypr;
 #pragma unroll
     for (int k = 0; k < kMaxDet; k++) {
-      if (k < K) {
-        const double ur = Uq[((size_t)idx * kMaxDet + k) * 2], ui = Uq[((size_t)idx * kMaxDet + k) * 2 + 1];
-        q[k] += ur * pr - ui * pi;
-      }
+      const double ur = T[(idx * kMaxDet + k) * 2], ui = T[(idx * kMaxDet + k) * 2 + 1];
+      q[k] = fma(-ui, pi, fma(ur, pr, q[k]));
     }
-    if (Vq) {
-      const double sr = ymr * ypr - ymi * ypi, s_i = ymr * ypi + ymi * ypr;
+  };
+  auto vpair = [&](const auto *T, int idx, double ymr, double ymi, double ypr, double ypi) {
+    const double sr = ymr * ypr - ymi * ypi, s_i = ymr * ypi + ymi * ypr;
 #pragma unroll
-      for (int k = 0; k < kMaxDet; k++) {
-        if (k < K) {
-          const double wr = Vq[((size_t)idx * kMaxDet + k) * 2], wi = Vq[((size_t)idx * kMaxDet + k) * 2 + 1];
-          vr[k] += wr * sr - wi * s_i;
-          vi[k] += wr * s_i + wi * sr;
-        }
-      }
+    for (int k = 0; k < kMaxDet; k++) {
+      const double wr = T[(idx * kMaxDet + k) * 2], wi = T[(idx * kMaxDet + k) * 2 + 1];
+      vr[k] = fma(-wi, s_i, fma(wr, sr, vr[k]));
+      vi[k] = fma(wi, sr, fma(wr, s_i, vi[k]));
     }
   };
   if constexpr (MC > 0) {
 #pragma unroll
     for (int m = 0; m < MC; m++)
 #pragma unroll
-      for (int mp = m; mp < MC; mp++) pair(m * MC - m * (m - 1) / 2 + (mp - m), Yr[m], Yi[m], Yr[mp], Yi[mp]);
+      for (int mp = m; mp < MC; mp++) upair(tab, m * MC - m * (m - 1) / 2 + (mp - m), Yr[m], Yi[m], Yr[mp], Yi[mp]);
   } else {
+    const RIFT_CONST double *Uq = cp(p.Upk);
     int idx = 0;
     for (int m = 0; m < M; m++)
-      for (int mp = m; mp < M; mp++, idx++) pair(idx, Yl[m][0], Yl[m][1], Yl[mp][0], Yl[mp][1]);
+      for (int mp = m; mp < M; mp++, idx++) upair(Uq, idx, Yl[m][0], Yl[m][1], Yl[mp][0], Yl[mp][1]);
+    if (p.Vpk) {
+      const RIFT_CONST double *Vq = cp(p.Vpk);
+      idx = 0;
+      for (int m = 0; m < M; m++)
+        for (int mp = m; mp < M; mp++, idx++) vpair(Vq, idx, Yl[m][0], Yl[m][1], Yl[mp][0], Yl[mp][1]);
+    }
   }
   double b = 0.0;
 #pragma unroll
   for (int k = 0; k < kMaxDet; k++) {
-    if (k < K) {
-      double f2 = Fr[k] * Fr[k] + Fi[k] * Fi[k];
-      double F2r = Fr[k] * Fr[k] - Fi[k] * Fi[k], F2i = 2.0 * Fr[k] * Fi[k];
-      b += f2 * q[k] + (F2r * vr[k] - F2i * vi[k]);
-    }
+    const double f2 = Fr[k] * Fr[k] + Fi[k] * Fi[k];
+    const double F2r = Fr[k] * Fr[k] - Fi[k] * Fi[k], F2i = 2.0 * Fr[k] * Fi[k];
+    b += f2 * q[k] + (F2r * vr[k] - F2i * vi[k]);
   }
-  ct->B[s] = (float)(0.25 * x * x * b * kLog2e);
-  ct->col[s] = (int)col;
-  ct->flag[s] = 1;
+  ct->B[s] = valid ? (float)(0.25 * x * x * b * kLog2e) : 0.f;
+  ct->col[s] = pad ? -1 : (int)rec.col;
+  ct->flag[s] = valid ? 1 : (pad ? 0 : 2);
 }
 
 // ---- 5. persistent MFMA evaluation ------------------------------------------
@@ -700,7 +712,7 @@ hipError_t mfma_prepare(const MfmaArgs &a, const int *mclass_M, const int *mclas
   for (int c = 0; c < n_mclasses; c++) {
     const int lo = mclass_item0[c], hi = mclass_item0[c + 1];
     const dim3 grid((unsigned)(((int64_t)kTS * mclass_tiles[c] + 63) / 64));
-    switch (mclass_M[c]) {
+    switch (mclass_M[c]) {  // negative: points with a V table, general form
       case 2: hipLaunchKernelGGL(coef_kernel<2>, grid, dim3(64), 0, st, a, lo, hi); break;
       case 5: hipLaunchKernelGGL(coef_kernel<5>, grid, dim3(64), 0, st, a, lo, hi); break;
       case 9: hipLaunchKernelGGL(coef_kernel<9>, grid, dim3(64), 0, st, a, lo, hi); break;

@@ -151,6 +151,22 @@ void harmonic_table(PointDev &p, int m_idx, int l, int m) {
   p.nterm[m_idx] = n;
   p.ynorm[m_idx] = std::sqrt((2.0 * l + 1.0) / (4.0 * kPi));
   p.em[m_idx] = m;
+  // Polynomial form: with c = cos(iota/2), s = sin(iota/2) and par = |m| mod 2,
+  // c^A s^B = (s c)^par u^((A - par)/2) (1 - u)^((B - par)/2), u = c^2;
+  // expanding (1 - u)^n binomially gives a polynomial in u of degree l - par.
+  const int par = m & 1;
+  const int deg = l - par;
+  for (int j = 0; j <= kMaxHDeg; j++) p.hpoly[m_idx][j] = 0.0;
+  for (int t = 0; t < n; t++) {
+    const int a = (p.ypc[m_idx][t] - par) / 2, nb = (p.yps[m_idx][t] - par) / 2;
+    double binom = 1.0;  // C(nb, i)
+    for (int i = 0; i <= nb; i++) {
+      p.hpoly[m_idx][a + i] += p.ynorm[m_idx] * p.ycoef[m_idx][t] * ((i & 1) ? -binom : binom);
+      binom = binom * (nb - i) / (i + 1);
+    }
+  }
+  p.hdeg[m_idx] = deg;
+  p.hpar[m_idx] = par;
 }
 
 rift_status check_point(const rift_ile_point &q, int idx, double tau_width) {
@@ -468,8 +484,9 @@ rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const f
       class_item0.push_back((int)i);
     }
     const int64_t tiles_i = (it.cnt[i] + 15) / 16 + p.n_bins_key + 4;
-    if (mclass_M.empty() || mclass_M.back() != p.M) {
-      mclass_M.push_back(p.M);
+    const int mkey = p.Vpk ? -p.M : p.M;  // V tables: the general coefficient kernel
+    if (mclass_M.empty() || mclass_M.back() != mkey) {
+      mclass_M.push_back(mkey);
       mclass_item0.push_back((int)i);
       mclass_tiles.push_back(0);
     }
@@ -671,7 +688,8 @@ rift_status reduce_segments(rift_ile *h, const R *lnL, const R *ln_ratio, const 
   const int ns = (int)off.size();
   int64_t mx = 1;
   for (auto c : cnt) mx = std::max(mx, c);
-  int bps = (int)std::min<int64_t>(256, (mx + 8191) / 8192);
+  // enough blocks per segment to spread a large segment over the device
+  int bps = (int)std::min<int64_t>(1024, (mx + 2047) / 2048);
   int64_t *d_off, *d_cnt;
   rift_status s;
   if ((s = upload(h, W_ITEM_OFF, off, &d_off)) != RIFT_OK) return s;
