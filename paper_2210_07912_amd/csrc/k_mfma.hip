@@ -290,21 +290,18 @@ __global__ void __launch_bounds__(256) unit_kernel(MfmaArgs a) {
 // there, so the pair sums run over all kMaxDet detectors without branches.
 // Harmonics use the polynomial form of the host tables (Horner in
 // u = cos^2(iota/2)).  MC > 0: the mode count is a compile-time constant, Y
-// lives in registers and the pair sums unroll over a copy of the packed table
-// in LDS (read at immediate offsets; as scalar loads the unrolled sums would
-// need more scalar registers than there are).  MC = 0 is the general form,
-// with Y staged in LDS and the tables read by scalar loads in loops; points
-// with a V table always take it (the host gives them classes of their own).
-// Padding and invalid slots run the same code on a harmless angle set and
-// store zeros, so every lane reaches the barriers.
+// lives in registers and the pair sums unroll (table values as scalar
+// operands).  MC = 0 is the general form, with Y staged in LDS and the sums
+// in loops; points with a V table always take it (the host gives them
+// classes of their own: a second unrolled pass would keep every mode product
+// of the first alive).  Padding and invalid slots run the same code on a
+// harmless angle set and store zeros.
 template <int MC>
 __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int item_hi) {
   constexpr int YS = MC > 0 ? 1 : 64;
   constexpr int YM = MC > 0 ? 1 : kMaxModes;
   constexpr int YR = MC > 0 ? MC : 1;
-  constexpr int NTAB = MC > 0 ? MC * (MC + 1) / 2 * kMaxDet * 2 : 1;
   __shared__ double Ys[YS][YM][2];
-  __shared__ __align__(16) double tab[NTAB];
   const int64_t t_lo = a.item_tiles[item_lo], t_hi = a.item_tiles[item_hi];
   const int64_t t_blk = t_lo + 4 * (int64_t)blockIdx.x;
   if (t_blk >= t_hi) return;  // whole block (items hold whole blocks of 4 tiles)
@@ -317,11 +314,6 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
   const RIFT_CONST PointDev &p = *cp(a.pts + pt);
   const int K = p.K, E = 2 * p.Mp;
   const int M = MC > 0 ? MC : p.M;
-  if constexpr (MC > 0) {
-    const RIFT_GLOBAL double *src = gp(p.Upk);
-    for (int i = threadIdx.x; i < NTAB; i += 64) tab[i] = src[i];
-    __syncthreads();
-  }
   RIFT_GLOBAL float *op = gpw(a.cop + a.item_cop[it] + (int64_t)(t - a.item_tiles[it]) * K * E * kTS + s);
   RIFT_GLOBAL CoefTile *ct = gpw(a.ctile + t);
   const bool pad = rec.flag == 0;
@@ -404,6 +396,8 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
       const double ur = T[(idx * kMaxDet + k) * 2], ui = T[(idx * kMaxDet + k) * 2 + 1];
       q[k] = fma(-ui, pi, fma(ur, pr, q[k]));
     }
+    // unrolled: one wait per four pairs of table loads
+    if ((idx & 3) == 3) __builtin_amdgcn_sched_barrier(0);
   };
   auto vpair = [&](const auto *T, int idx, double ymr, double ymi, double ypr, double ypi) {
     const double sr = ymr * ypr - ymi * ypi, s_i = ymr * ypi + ymi * ypr;
@@ -414,13 +408,13 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
       vi[k] = fma(wi, sr, fma(wr, s_i, vi[k]));
     }
   };
+  const RIFT_CONST double *Uq = cp(p.Upk);
   if constexpr (MC > 0) {
 #pragma unroll
     for (int m = 0; m < MC; m++)
 #pragma unroll
-      for (int mp = m; mp < MC; mp++) upair(tab, m * MC - m * (m - 1) / 2 + (mp - m), Yr[m], Yi[m], Yr[mp], Yi[mp]);
+      for (int mp = m; mp < MC; mp++) upair(Uq, m * MC - m * (m - 1) / 2 + (mp - m), Yr[m], Yi[m], Yr[mp], Yi[mp]);
   } else {
-    const RIFT_CONST double *Uq = cp(p.Upk);
     int idx = 0;
     for (int m = 0; m < M; m++)
       for (int mp = m; mp < M; mp++, idx++) upair(Uq, idx, Yl[m][0], Yl[m][1], Yl[mp][0], Yl[mp][1]);
