@@ -397,6 +397,36 @@ def test_lnL_with_V(ile, orc):
             assert np.all(np.abs(out - ref) <= 1e-9 * (1 + np.abs(ref)))
 
 
+def test_high_l_modes(ile, orc):
+    """Modes up to the largest degree the library accepts (l = 8), through the
+    coefficient pass and chain rule (polynomial harmonic tables): ln L_t for
+    FP32 (matrix cores) and FP64, and the FP32 adjoint, against the oracle's
+    Wigner-d sum.  Noise-only Q with random U (the modes' ell, em replaced;
+    U scaled by 1e4 and Q by 1e2 so ln L_t spans about -500..2)."""
+    spec = synth.PointSpec(seed=synth.BASE_SEED + 1201, dets=("H1", "L1", "V1"), n_modes=9, n_t=100, snr=1.0,
+                           kernel="none")
+    d = dict(synth.make_point(spec))
+    d["U"] = d["U"] * 1e4
+    d["Q"] = d["Q"] * 1e2
+    d["ell"] = np.array([5, 5, 6, 6, 7, 7, 8, 8, 8], dtype=np.int32)
+    d["em"] = np.array([5, -4, 3, -6, 0, 7, -8, 1, 2], dtype=np.int32)
+    th = synth.mixed_samples(d, 31, 700)
+    for prec in ("fp32", "fp64"):
+        p = orc.Point.from_dict(d, complex64=(prec == "fp32"))
+        ref = orc.lnL_t(p, th)
+        h = _handle(ile, [d], prec)
+        _say(f"high-l modes {prec}")
+        out = h.lnL(torch.tensor(th)).cpu().numpy()
+        if prec == "fp32":
+            _check_fp32(out, ref, "high-l fp32")
+            lt, g = orc.grad(p, th)
+            gg, lg = h.backward(torch.tensor(th), want_lnL=True)
+            _grad_check(gg.cpu().numpy(), lg.cpu().numpy(), g, lt, "high-l backward fp32", _tau_sensitivity(orc, p, th),
+                        f_s=spec.f_s)
+        else:
+            assert np.all(np.abs(out - ref) <= 1e-9 * (1 + np.abs(ref)))
+
+
 def test_single_point_full_size(ile, orc):
     """10^6 samples through the FP32 launch the benchmark times: sampled
     per-sample parity against the oracle, the FP64 reduction against the

@@ -1,7 +1,8 @@
 """Oracle pins: spin-weight -2 spherical harmonics.
 
 Pinned to the l = 2 closed forms, to orthonormality of all 21 modes with
-l = 2..4 (quadrature on the sphere), to the addition theorem
+l = 2..4 and of every mode with l = 5..8, the largest degree the library
+accepts (quadrature on the sphere), to the addition theorem
 sum_m |Y_lm|^2 = (2l+1)/4pi, and to the parity relation
 Y_{l,-m}(iota, phi) = (-1)^l conj(Y_{l,m}(pi - iota, phi)).
 """
@@ -37,8 +38,9 @@ def test_l2_closed_forms(orc):
             assert abs(orc.sylm(2, m, iota, phi) - closed_l2(m, iota, phi)) < 1e-14
 
 
-def test_orthonormal_and_addition(orc):
-    modes = synth.MODE_SETS[21]
+@pytest.mark.parametrize("ls", [(2, 3, 4), (5, 6, 7, 8)])
+def test_orthonormal_and_addition(orc, ls):
+    modes = synth.MODE_SETS[21] if ls == (2, 3, 4) else [(l, m) for l in ls for m in range(-l, l + 1)]
     xg, wg = np.polynomial.legendre.leggauss(60)   # in cos(iota)
     nphi = 64
     phis = 2 * math.pi * np.arange(nphi) / nphi
@@ -50,7 +52,7 @@ def test_orthonormal_and_addition(orc):
                 Y[a, i, j] = orc.sylm(l, m, io, ph)
     G = np.einsum("aij,bij,i->ab", Y, Y.conj(), wg) * (2 * math.pi / nphi)
     assert np.abs(G - np.eye(len(modes))).max() < 1e-12
-    for l in (2, 3, 4):
+    for l in ls:
         idx = [a for a, (ll, _) in enumerate(modes) if ll == l]
         tot = (np.abs(Y[idx]) ** 2).sum(axis=0)
         assert np.abs(tot - (2 * l + 1) / (4 * math.pi)).max() < 1e-12
