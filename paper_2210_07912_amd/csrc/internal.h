@@ -59,7 +59,8 @@ struct SampleRec {
 
 // per-tile coefficients written by the coefficient pass (16 samples)
 struct CoefTile {
-  float B[16];               // quadratic term (FP64, rounded)
+  float B[16];               // quadratic term (FP64, rounded), times log2 e
+  float xf[kMaxDet][2][16];  // (D_ref / D) F_k times log2 e (re, im); zero past K
   float mu[kMaxDet][16];     // interpolation fraction
   int n[kMaxDet][16];        // integer row offset (1<<28 for padding / invalid)
   int col[16];               // output column (-1: padding slot)

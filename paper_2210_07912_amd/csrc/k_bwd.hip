@@ -84,18 +84,16 @@ __global__ void __launch_bounds__(256) mfma_bwd_kernel(MfmaArgs a, int item_lo, 
     }
     const int64_t top = a.item_cop[it] + (int64_t)(t - a.item_tiles[it]) * K * E * kTS;
     const RIFT_GLOBAL CoefTile *ct = gp(a.ctile + t);
-    const RIFT_GLOBAL float *op = gp(a.cop + top);
     const int flag = active ? ct->flag[s] : 0;
     const int col = ct->col[s];
     const float Bf = active ? ct->B[s] : 0.f;
     float Bop[K][T];
+    b_operands<T, K>(gp(a.cop + top + s), ct, s, g, active, Bop);
     float w[K][4], wd[K][4];
     int sh[K];
     bool valid = flag == 1;
 #pragma unroll
     for (int k = 0; k < K; k++) {
-#pragma unroll
-      for (int tt = 0; tt < T; tt++) Bop[k][tt] = active ? op[((size_t)k * E + op_elem<T>(tt, g)) * kTS + s] : 0.f;
       const float mu = ct->mu[k][s];
       cr_weights<float>(mu, w[k]);
       cr_dweights<float>(mu, wd[k]);

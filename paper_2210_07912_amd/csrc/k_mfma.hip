@@ -288,6 +288,9 @@ __global__ void __launch_bounds__(256) unit_kernel(MfmaArgs a) {
 // through the constant address space (scalar loads) and every branch on them
 // is uniform.  The packed tables are zero for detectors past K and F_k = 0
 // there, so the pair sums run over all kMaxDet detectors without branches.
+// Per tile the pass stores Y_m (2 M_p floats per sample, shared by the
+// detectors) and x F_k (in the tile record); the evaluation kernels form the
+// B operands a_km = x F_k Y_m themselves.
 // Harmonics use the polynomial form of the host tables (Horner in
 // u = cos^2(iota/2)).  MC > 0: the mode count is a compile-time constant, Y
 // lives in registers and the pair sums unroll (table values as scalar
@@ -343,6 +346,9 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
       ct->mu[k][s] = 0.f;
       ct->n[k][s] = 1 << 28;
     }
+    // in base-2 units (times log2 e) for the evaluation kernel's exp2/log2
+    ct->xf[k][0][s] = (float)(xl * Fr[k]);
+    ct->xf[k][1][s] = (float)(xl * Fi[k]);
   }
   // harmonics: Y_m = (sin(iota)/2)^par P_m(cos^2(iota/2)) exp(i m phi), with
   // exp(i m phi) by repeated products of exp(i phi)
@@ -374,19 +380,12 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
       Yl[m][0] = yr;
       Yl[m][1] = yi;
     }
-    // B operand elements 2m (Re a) and 2m+1 (Im a), for every detector, in
-    // base-2 units (times log2 e) for the evaluation kernel's exp2/log2
-#pragma unroll
-    for (int k = 0; k < kMaxDet; k++) {
-      if (k < K) {
-        const double ar = xl * (Fr[k] * yr - Fi[k] * yi), ai = xl * (Fr[k] * yi + Fi[k] * yr);
-        op[((size_t)k * E + 2 * m) * kTS] = (float)ar;
-        op[((size_t)k * E + 2 * m + 1) * kTS] = (float)ai;
-      }
-    }
+    // elements 2m, 2m + 1 of the tile's harmonic block; the evaluation
+    // kernels form a_km = (x F_k) Y_m from it and xf
+    op[(2 * m) * kTS] = valid ? (float)yr : 0.f;
+    op[(2 * m + 1) * kTS] = valid ? (float)yi : 0.f;
   }
-  for (int k = 0; k < K; k++)
-    for (int e = 2 * M; e < E; e++) op[((size_t)k * E + e) * kTS] = 0.f;
+  for (int e = 2 * M; e < E; e++) op[e * kTS] = 0.f;
   double q[kMaxDet] = {0.0, 0.0, 0.0}, vr[kMaxDet] = {0.0, 0.0, 0.0}, vi[kMaxDet] = {0.0, 0.0, 0.0};
   // conj(Y_m) Y_m' against U, Y_m Y_m' against V
   auto upair = [&](const auto *T, int idx, double ymr, double ymi, double ypr, double ypi) {
@@ -498,18 +497,17 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
       qk[k] = gp(uniform_ptr(p.Qm + (size_t)(k * Lpad + P + lo_k[k]) * E));
     }
     const RIFT_GLOBAL CoefTile *ct = gp(a.ctile + t);
-    const RIFT_GLOBAL float *op = gp(a.cop + a.item_cop[it] + (int64_t)(t - a.item_tiles[it]) * K * E * kTS);
+    const RIFT_GLOBAL float *yop = gp(a.cop + a.item_cop[it] + (int64_t)(t - a.item_tiles[it]) * K * E * kTS + s);
     const int flag = active ? ct->flag[s] : 0;
     const int col = ct->col[s];
     const float Bf = active ? ct->B[s] : 0.f;
     float Bop[K][T];
+    b_operands<T, K>(yop, ct, s, g, active, Bop);
     float w[K][4];
     int sh[K];
     bool valid = flag == 1;
 #pragma unroll
     for (int k = 0; k < K; k++) {
-#pragma unroll
-      for (int tt = 0; tt < T; tt++) Bop[k][tt] = active ? op[((size_t)k * E + op_elem<T>(tt, g)) * kTS + s] : 0.f;
       cr_weights<float>(ct->mu[k][s], w[k]);
       sh[k] = valid ? ct->n[k][s] - lo_k[k] : 0;
       if (sh[k] < 0 || sh[k] > kTS - 3) {

@@ -4,6 +4,7 @@
 #pragma once
 
 #include "common.h"
+#include "internal.h"
 
 namespace rift {
 
@@ -35,6 +36,32 @@ template <int T>
 __device__ __forceinline__ int op_elem(int tt, int g) {
   constexpr int J = T / 4;
   return tt < 4 * J ? 16 * (tt >> 2) + 4 * g + (tt & 3) : 16 * J + 4 * (tt - 4 * J) + g;
+}
+
+// B operands of one lane (sample s, element group g) for every detector:
+// a_k[e] = (x F_k)(Y_m), e = 2m + part, formed in FP32 from the tile's
+// harmonic block (yop: element e of the lane's sample at yop[16 e]) and the
+// tile record's x F_k.  The quads hold whole modes (elements 4i..4i+3), so
+// their partner element is the lane's own; a tail element's partner is read.
+template <int T, int K>
+__device__ __forceinline__ void b_operands(const RIFT_GLOBAL float *yop, const RIFT_GLOBAL CoefTile *ct, int s,
+                                           int g, bool active, float (&Bop)[K][T]) {
+  constexpr int J = T / 4;
+  float yv[T], yq[T];
+#pragma unroll
+  for (int tt = 0; tt < T; tt++) yv[tt] = active ? yop[16 * op_elem<T>(tt, g)] : 0.f;
+#pragma unroll
+  for (int tt = 0; tt < T; tt++) yq[tt] = tt < 4 * J ? yv[tt ^ 1] : (active ? yop[16 * (op_elem<T>(tt, g) ^ 1)] : 0.f);
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const float xr = active ? ct->xf[k][0][s] : 0.f, xi = active ? ct->xf[k][1][s] : 0.f;
+#pragma unroll
+    for (int tt = 0; tt < T; tt++) {
+      const bool im = tt < 4 * J ? (tt & 1) != 0 : (g & 1) != 0;
+      // Re a = xr y_re - xi y_im; Im a = xr y_im + xi y_re
+      Bop[k][tt] = fmaf(xr, yv[tt], (im ? xi : -xi) * yq[tt]);
+    }
+  }
 }
 
 // Row stride (floats) of a staged block of Q in LDS: 4T elements, padded to
