@@ -138,6 +138,9 @@ def main():
                    "rounds": rounds, "K": [p["det_pos"].shape[0] for p in pts][:1], "M": [len(p["ell"]) for p in pts][:1],
                    "n_t": [p["n_t"] for p in pts][:1], "seed": seed},
         "roofline": roof,
+        # matrix-core feed measured per (T, K) class by the handle (staged | direct)
+        "autotune": ({f"T{t}K{k}": m for (t, k), m in sorted(h.autotune_table().items())}
+                     if mfma and not grad else None),
         "lnL_marg": [r["lnL_marg"] for r in res][:4], "n_eff": [r["n_eff"] for r in res][:4],
     }
 

@@ -191,6 +191,27 @@ rift_status rift_ile_set_graph(rift_ile *h, int enable);
  * the handle was created (either output may be NULL). */
 rift_status rift_ile_graph_stats(const rift_ile *h, int64_t *captures, int64_t *replays);
 
+/* Per-class choice of how the FP32 evaluation feeds the matrix cores
+ * (batching: every (T, K) class of points, T = ceil(M / 2) MFMA steps and K
+ * detectors, is one persistent launch).  Two forms of the same kernel exist:
+ * "staged" (each workgroup copies the rows of Q its unit needs into LDS, one
+ * barrier per two 16-row blocks) and "direct" (each wavefront loads its own
+ * operands from global memory one block ahead, no barrier, less LDS and more
+ * resident workgroups).  Their results are bit-identical; which is faster
+ * depends on T and K.  mode 1 (the default): the first evaluation of each
+ * class on the handle runs both forms on that call's data, timed with events
+ * (that call waits for them), and later calls use the faster.  mode 0: every
+ * class runs staged; mode 2: every class runs direct (measurements made so
+ * far are kept for a later mode 1).  Runs with a class not yet measured are
+ * not captured by the graph replay.  Returns RIFT_E_INVALID for a NULL
+ * handle or another mode. */
+rift_status rift_ile_set_autotune(rift_ile *h, int mode);
+
+/* The measured choices: modes[(T - 1) * 3 + (K - 1)] for T = 1..16 and
+ * K = 1..3 (48 ints, caller-owned) is 0 (not measured), 1 (staged) or
+ * 2 (direct).  Returns RIFT_E_INVALID for a NULL handle or array. */
+rift_status rift_ile_autotune_table(const rift_ile *h, int *modes);
+
 /* Extrinsic sample draw (Sec. II.A; Sec. III.B: random numbers generated on
  * the GPU).  Writes samples first..first+n-1 of (point, round): Philox4x32-10
  * with key = seed and counter = (i_lo, i_hi, 2 round + half, point); each

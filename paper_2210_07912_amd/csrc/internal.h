@@ -44,6 +44,7 @@ hipError_t plain_launch(const PlainArgsT<R> &a, int TS, int n_tiles, bool bwd, h
 size_t plain_lds_bytes(int elem, int TS, int rows_cap, int nt_cap, bool bwd);
 
 // ---- FP32 MFMA path -------------------------------------------------------
+constexpr int kMaxT = kMaxModes / 2;  // MFMA steps of 4 elements per detector: M_p / 2
 constexpr int kMaxClasses = 48;  // one persistent launch per distinct (T = Mp / 2, K)
 
 constexpr int kSortBlock = 4096;  // samples per sort block
@@ -129,9 +130,14 @@ struct Fanout {
 // launches) and with the same mode count M (coefficient launches; mclass_M is
 // -M for runs of points that carry a V table, mclass_tiles bounds the tiles
 // of each run)
+// class_mode (per class, in/out): how the class feeds the matrix cores, 1
+// staged through LDS, 2 direct from global memory, 0 not measured yet: with
+// tune such a class runs both forms on this call's data, timed (the call
+// then waits for them), and gets the faster; without tune it runs staged.
 hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_K, const int *class_item0, int n_classes,
                         const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles, int n_mclasses,
-                        hipStream_t st, const Fanout &fo, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                        int *class_mode, bool tune, hipStream_t st, const Fanout &fo, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
 
 // the adjoint of the same evaluation: sort, coefficients, then per class the
 // two-sweep matrix-core adjoint (G_k, H_k, ln L_t) and per mode class the FP64

@@ -437,20 +437,26 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
 }
 
 // ---- 5. persistent MFMA evaluation ------------------------------------------
-// One workgroup per work unit: its four wavefronts take the unit's tiles
-// (wavefronts past ntiles only help stage).  The rows of block b of every
-// detector are loaded once per workgroup, coalesced, into a double-buffered
-// LDS stage; each wavefront reads its MFMA A operands from there.  Base row
-// of detector k: the lower edge of the unit's delay bin, so every sample's
-// stencil starts 0..bin_w-1 rows above it.
-template <int T, int K>
+// One workgroup per work unit: its four wavefronts take the unit's tiles.
+// Base row of detector k: the lower edge of the unit's delay bin, so every
+// sample's stencil starts 0..bin_w-1 rows above it.  Two ways to feed the
+// matrix cores, chosen per (T, K) class by measurement:
+//  * staged (DIRECT = false): the rows of blocks b, b + 1 of every detector
+//    are loaded once per workgroup, coalesced, into a 4-slot LDS stage (one
+//    barrier per two blocks); each wavefront reads its A operands from there
+//    (wavefronts past ntiles only help stage);
+//  * direct (DIRECT = true): each wavefront loads its own A operands from
+//    global memory one block ahead (the four wavefronts of a unit read the
+//    same rows, so three of the four reads hit in L1), with no stage and no
+//    barrier between blocks; less LDS, so more workgroups per compute unit.
+template <int T, int K, bool DIRECT>
 __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int item_hi, int cls) {
   constexpr int E = 4 * T, J = T / 4, R = T % 4;
   constexpr int JA = J > 0 ? J : 1, RA = R > 0 ? R : 1;
   constexpr int ES = stage_stride<T>();
   constexpr int SF = K * kTS * ES;  // floats of one staged block
   __shared__ __align__(16) float ring_all[kWaves * K * kTS * kRS];
-  __shared__ __align__(16) float stage[4][SF];  // block b in slot b % 4; two blocks per barrier
+  __shared__ __align__(16) float stage[DIRECT ? 1 : 4][DIRECT ? 4 : SF];  // staged: block b in slot b % 4
   __shared__ WorkUnit unit_sh;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float *ring = ring_all + wave * (K * kTS * kRS);  // [det][sample][kRS]
@@ -462,8 +468,12 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
   const bool st_on = tid < 16 * T;
   const uint32_t st_goff = 16u * (uint32_t)tid;                         // bytes into the block
   const int st_loff = (tid / T) * ES + 4 * (tid % T);                   // floats into the stage
+  // direct: lane (s, g) reads row s of a block, quads at 64 j + 16 g bytes,
+  // tails at 64 J + 16 r + 4 g
+  const uint32_t a_row = (uint32_t)(4 * E) * (uint32_t)s;
 
   for (;;) {
+    if constexpr (DIRECT) __syncthreads();  // every wavefront is done with the previous unit
     if (tid == 0) {
       const uint32_t u = u_lo + atomicAdd(&a.ctl[1 + cls], 1u);
       WorkUnit w;
@@ -550,19 +560,44 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
           for (int k = 0; k < K; k++) *(f4 *)(&stage[(S0 + hb) & 3][k * kTS * ES + st_loff]) = pre[hb][k];
       }
     };
-    // the block in stage slot S4 on the matrix cores; z_k[base + 16 b + 4 g + v]
-    // of sample s -> ring slot S4 % 2
-    auto product = [&](auto s4_c) {
-      constexpr int S4 = decltype(s4_c)::value;
-      const float *sb = sa + S4 * SF;
-      f4 Aq[K][JA];
-      float At[K][RA];
+    // direct: A operands of blocks in two register sets, one block ahead
+    f4 Ad[2][K][JA];
+    float Atd[2][K][RA];
+    auto load_a = [&](auto buf_c, int b) {
+      constexpr int BF = decltype(buf_c)::value;
+      const uint32_t ob = (uint32_t)(64 * E) * (uint32_t)min(b, JB) + a_row;
 #pragma unroll
       for (int k = 0; k < K; k++) {
+        const RIFT_GLOBAL char *base = (const RIFT_GLOBAL char *)qk[k] + ob;
 #pragma unroll
-        for (int j = 0; j < J; j++) Aq[k][j] = *(const f4 *)(sb + k * kTS * ES + 16 * j);
+        for (int j = 0; j < J; j++) Ad[BF][k][j] = *(const RIFT_GLOBAL f4 *)(base + 64 * j + 16 * g);
 #pragma unroll
-        for (int r = 0; r < R; r++) At[k][r] = st[S4 * SF + k * kTS * ES + 4 * r];
+        for (int r = 0; r < R; r++) Atd[BF][k][r] = *(const RIFT_GLOBAL float *)(base + 64 * J + 16 * r + 4 * g);
+      }
+    };
+    // the block in stage slot S4 (staged) or register set S4 % 2 (direct) on
+    // the matrix cores; z_k[base + 16 b + 4 g + v] of sample s -> ring slot S4 % 2
+    auto product = [&](auto s4_c) {
+      constexpr int S4 = decltype(s4_c)::value;
+      f4 Aq[K][JA];
+      float At[K][RA];
+      if constexpr (DIRECT) {
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+#pragma unroll
+          for (int j = 0; j < JA; j++) Aq[k][j] = Ad[S4 & 1][k][j];
+#pragma unroll
+          for (int r = 0; r < RA; r++) At[k][r] = Atd[S4 & 1][k][r];
+        }
+      } else {
+        const float *sb = sa + S4 * SF;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+#pragma unroll
+          for (int j = 0; j < J; j++) Aq[k][j] = *(const f4 *)(sb + k * kTS * ES + 16 * j);
+#pragma unroll
+          for (int r = 0; r < R; r++) At[k][r] = st[S4 * SF + k * kTS * ES + 4 * r];
+        }
       }
       f4 acc[K];
 #pragma unroll
@@ -640,16 +675,38 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
       __syncthreads();
     };
 
-    stage_load2(0);
-    stage_store2(C0{});
-    __syncthreads();
-    int b = 0;
-    for (; b + 3 <= JB; b += 4) {
-      pair(C0{}, b);
-      pair(C2{}, b + 2);
+    if constexpr (DIRECT) {
+      // block b (register set and ring slot b % 2): prefetch block b + 1,
+      // its MFMAs, then the window samples of block b - 1
+      using C1 = std::integral_constant<int, 1>;
+      auto dblock = [&](auto s2_c, int b) {
+        constexpr int S2 = decltype(s2_c)::value;
+        load_a(std::integral_constant<int, S2 ^ 1>{}, b + 1);
+        product(s2_c);
+        wave_sync();
+        if (b >= 1) window(std::integral_constant<int, S2 ^ 1>{}, b == JB, b == 1);
+      };
+      if (active) {
+        load_a(C0{}, 0);
+        int b = 0;
+        for (; b + 1 <= JB; b += 2) {
+          dblock(C0{}, b);
+          dblock(C1{}, b + 1);
+        }
+        if (b <= JB) dblock(C0{}, b);
+      }
+    } else {
+      stage_load2(0);
+      stage_store2(C0{});
+      __syncthreads();
+      int b = 0;
+      for (; b + 3 <= JB; b += 4) {
+        pair(C0{}, b);
+        pair(C2{}, b + 2);
+      }
+      if (b <= JB) pair(C0{}, b);
+      if (b + 2 <= JB) pair(C2{}, b + 2);
     }
-    if (b <= JB) pair(C0{}, b);
-    if (b + 2 <= JB) pair(C2{}, b + 2);
     if (active) {
       // combine the four lanes of each sample (base 2), then ln L_t
       float mo = m_run;
@@ -669,23 +726,66 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
 }
 
 // persistent grid: as many workgroups as the device keeps resident
-template <int T, int K>
+template <int T, int K, bool D>
 static void launch_tk(const MfmaArgs &a, int lo, int hi, int cls, hipStream_t st) {
   static int per_cu = 0;
   if (per_cu == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mfma_kernel<T, K>, 256, 0) != hipSuccess || nb < 1) nb = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mfma_kernel<T, K, D>, 256, 0) != hipSuccess || nb < 1) nb = 1;
     per_cu = nb;
   }
   const int grid = std::max(1, a.grid / 4 * per_cu);  // a.grid = 4 per compute unit
-  hipLaunchKernelGGL((mfma_kernel<T, K>), dim3(grid), dim3(256), 0, st, a, lo, hi, cls);
+  hipLaunchKernelGGL((mfma_kernel<T, K, D>), dim3(grid), dim3(256), 0, st, a, lo, hi, cls);
+}
+
+template <int T, int K>
+static void launch_tkm(const MfmaArgs &a, bool direct, int lo, int hi, int cls, hipStream_t st) {
+  if (direct) launch_tk<T, K, true>(a, lo, hi, cls, st);
+  else launch_tk<T, K, false>(a, lo, hi, cls, st);
 }
 
 template <int T>
-static void launch_class(const MfmaArgs &a, int K, int lo, int hi, int cls, hipStream_t st) {
-  if (K == 1) launch_tk<T, 1>(a, lo, hi, cls, st);
-  else if (K == 2) launch_tk<T, 2>(a, lo, hi, cls, st);
-  else launch_tk<T, 3>(a, lo, hi, cls, st);
+static void launch_class(const MfmaArgs &a, int K, bool direct, int lo, int hi, int cls, hipStream_t st) {
+  if (K == 1) launch_tkm<T, 1>(a, direct, lo, hi, cls, st);
+  else if (K == 2) launch_tkm<T, 2>(a, direct, lo, hi, cls, st);
+  else launch_tkm<T, 3>(a, direct, lo, hi, cls, st);
+}
+
+static hipError_t launch_mode(const MfmaArgs &a, int T, int K, bool direct, int lo, int hi, int cls, hipStream_t st) {
+  switch (T) {
+#define RIFT_T_CASE(TT) \
+  case TT: launch_class<TT>(a, K, direct, lo, hi, cls, st); break;
+    RIFT_T_CASE(1) RIFT_T_CASE(2) RIFT_T_CASE(3) RIFT_T_CASE(4) RIFT_T_CASE(5) RIFT_T_CASE(6) RIFT_T_CASE(7)
+    RIFT_T_CASE(8) RIFT_T_CASE(9) RIFT_T_CASE(10) RIFT_T_CASE(11) RIFT_T_CASE(12) RIFT_T_CASE(13)
+    RIFT_T_CASE(14) RIFT_T_CASE(15) RIFT_T_CASE(16)
+#undef RIFT_T_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipSuccess;
+}
+
+// Both forms of class c on the call's own data, one after the other on st
+// (direct first, so a tie keeps the staged form), timed with events; the
+// results are bit-identical, so the second run only rewrites the outputs.
+static hipError_t tune_class(const MfmaArgs &a, int T, int K, int lo, int hi, int c, hipStream_t st, int &mode) {
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 4 && e == hipSuccess; i++) e = hipEventCreate(&ev[i]);
+  if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+  if (e == hipSuccess) e = launch_mode(a, T, K, true, lo, hi, c, st);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+  if (e == hipSuccess) e = fill_u32(a.ctl + 1 + c, 1, 0u, st);  // the class's unit counter
+  if (e == hipSuccess) e = hipEventRecord(ev[2], st);
+  if (e == hipSuccess) e = launch_mode(a, T, K, false, lo, hi, c, st);
+  if (e == hipSuccess) e = hipEventRecord(ev[3], st);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
+  float td = 0.f, ts = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&td, ev[0], ev[1]);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ts, ev[2], ev[3]);
+  if (e == hipSuccess) mode = td < 0.97f * ts ? 2 : 1;
+  for (int i = 0; i < 4; i++)
+    if (ev[i]) (void)hipEventDestroy(ev[i]);
+  return e;
 }
 
 hipError_t mfma_prepare(const MfmaArgs &a, const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles,
@@ -717,25 +817,26 @@ hipError_t mfma_prepare(const MfmaArgs &a, const int *mclass_M, const int *mclas
 
 hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_K, const int *class_item0, int n_classes,
                         const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles, int n_mclasses,
-                        hipStream_t st, const Fanout &fo, hipEvent_t ev0, hipEvent_t ev1) {
+                        int *class_mode, bool tune, hipStream_t st, const Fanout &fo, hipEvent_t ev0,
+                        hipEvent_t ev1) {
   if (a.total <= 0) return hipSuccess;
   hipError_t e = mfma_prepare(a, mclass_M, mclass_item0, mclass_tiles, n_mclasses, st);
   if (e != hipSuccess) return e;
+  uint64_t done = 0;  // classes evaluated while being measured
+  if (tune)
+    for (int c = 0; c < n_classes && c < 64; c++)
+      if (class_mode[c] == 0) {
+        e = tune_class(a, class_T[c], class_K[c], class_item0[c], class_item0[c + 1], c, st, class_mode[c]);
+        if (e != hipSuccess) return e;
+        done |= 1ull << c;
+      }
   if (ev0) (void)hipEventRecord(ev0, st);
   fan_fork(fo, st, n_classes);
   for (int c = 0; c < n_classes; c++) {
-    hipStream_t sc = fan_stream(fo, st, c);
-    const int lo = class_item0[c], hi = class_item0[c + 1];
-    const int K = class_K[c];
-    switch (class_T[c]) {
-#define RIFT_T_CASE(TT) \
-  case TT: launch_class<TT>(a, K, lo, hi, c, sc); break;
-      RIFT_T_CASE(1) RIFT_T_CASE(2) RIFT_T_CASE(3) RIFT_T_CASE(4) RIFT_T_CASE(5) RIFT_T_CASE(6) RIFT_T_CASE(7)
-      RIFT_T_CASE(8) RIFT_T_CASE(9) RIFT_T_CASE(10) RIFT_T_CASE(11) RIFT_T_CASE(12) RIFT_T_CASE(13)
-      RIFT_T_CASE(14) RIFT_T_CASE(15) RIFT_T_CASE(16)
-#undef RIFT_T_CASE
-      default: return hipErrorInvalidValue;
-    }
+    if (c < 64 && (done >> c) & 1) continue;
+    e = launch_mode(a, class_T[c], class_K[c], class_mode[c] == 2, class_item0[c], class_item0[c + 1], c,
+                    fan_stream(fo, st, c));
+    if (e != hipSuccess) return e;
   }
   e = hipGetLastError();
   fan_join(fo, st, n_classes);

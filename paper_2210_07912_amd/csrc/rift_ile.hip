@@ -54,6 +54,10 @@ struct rift_ile {
   hipStream_t gstream = nullptr;  // graph stream when the handle's stream is the null stream
   hipEvent_t gfork = nullptr, gjoin = nullptr;
   int64_t n_captures = 0, n_replays = 0;
+  // how each (T, K) class feeds the matrix cores: 0 not measured, 1 staged, 2
+  // direct; feed: 1 measure on first use, 0 all staged, 2 all direct
+  int feed = 1;
+  int kmode[kMaxT + 1][kMaxDet + 1] = {};
   double ws_budget = 6.0e9;
   // optional timing of the dominant evaluation kernel
   bool prof = false;
@@ -408,8 +412,9 @@ void key_add(std::vector<char> &k, const V &v) {
 rift_status launch_graph(rift_ile *h, const MfmaArgs &a, const std::vector<int> &class_T,
                          const std::vector<int> &class_K, const std::vector<int> &class_item0,
                          const std::vector<int> &mclass_M, const std::vector<int> &mclass_item0,
-                         const std::vector<int64_t> &mclass_tiles) {
+                         const std::vector<int64_t> &mclass_tiles, std::vector<int> &class_mode) {
   std::vector<char> key((const char *)&a, (const char *)&a + sizeof(a));
+  key_add(key, class_mode);
   key_add(key, class_T);
   key_add(key, class_K);
   key_add(key, class_item0);
@@ -446,7 +451,7 @@ rift_status launch_graph(rift_ile *h, const MfmaArgs &a, const std::vector<int> 
   HIPCHK(h, hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
   hipError_t e = mfma_forward(a, class_T.data(), class_K.data(), class_item0.data(), (int)class_T.size(),
                               mclass_M.data(), mclass_item0.data(), mclass_tiles.data(), (int)mclass_M.size(),
-                              gs, h->fan, nullptr, nullptr);
+                              class_mode.data(), false, gs, h->fan, nullptr, nullptr);
   hipError_t e2 = hipStreamEndCapture(gs, &graph);
   if (e != hipSuccess || e2 != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -589,16 +594,26 @@ rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const f
     HIPCHK(h, hipEventCreate(&e1));
     h->prof_ev.emplace_back(e0, e1);
   }
-  if (!grad && h->use_graph && !h->prof) return launch_graph(h, a, class_T, class_K, class_item0, mclass_M,
-                                                             mclass_item0, mclass_tiles);
+  // matrix-core feed of each class (measured on first use when autotuning)
+  std::vector<int> class_mode(class_T.size());
+  bool measured = true;
+  for (size_t c = 0; c < class_T.size(); c++) {
+    class_mode[c] = h->feed == 1 ? h->kmode[class_T[c]][class_K[c]] : h->feed == 2 ? 2 : 1;
+    measured = measured && class_mode[c] != 0;
+  }
+  if (!grad && h->use_graph && !h->prof && measured)
+    return launch_graph(h, a, class_T, class_K, class_item0, mclass_M, mclass_item0, mclass_tiles, class_mode);
   if (grad)
     HIPCHK(h, mfma_backward(a, class_T.data(), class_K.data(), class_item0.data(), (int)class_T.size(),
                             mclass_M.data(), mclass_item0.data(), mclass_tiles.data(), (int)mclass_M.size(), h->stream,
                             h->fan, e0, e1));
-  else
+  else {
     HIPCHK(h, mfma_forward(a, class_T.data(), class_K.data(), class_item0.data(), (int)class_T.size(),
-                           mclass_M.data(), mclass_item0.data(), mclass_tiles.data(), (int)mclass_M.size(), h->stream,
-                           h->fan, e0, e1));
+                           mclass_M.data(), mclass_item0.data(), mclass_tiles.data(), (int)mclass_M.size(),
+                           class_mode.data(), h->feed == 1, h->stream, h->fan, e0, e1));
+    if (h->feed == 1)
+      for (size_t c = 0; c < class_T.size(); c++) h->kmode[class_T[c]][class_K[c]] = class_mode[c];
+  }
   return RIFT_OK;
 }
 
@@ -998,6 +1013,19 @@ rift_status rift_ile_graph_stats(const rift_ile *h, int64_t *captures, int64_t *
   if (!h) return RIFT_E_INVALID;
   if (captures) *captures = h->n_captures;
   if (replays) *replays = h->n_replays;
+  return RIFT_OK;
+}
+
+rift_status rift_ile_set_autotune(rift_ile *h, int mode) {
+  if (!h || mode < 0 || mode > 2) return RIFT_E_INVALID;
+  h->feed = mode;
+  return RIFT_OK;
+}
+
+rift_status rift_ile_autotune_table(const rift_ile *h, int *modes) {
+  if (!h || !modes) return RIFT_E_INVALID;
+  for (int T = 1; T <= kMaxT; T++)
+    for (int K = 1; K <= kMaxDet; K++) modes[(T - 1) * kMaxDet + (K - 1)] = h->kmode[T][K];
   return RIFT_OK;
 }
 

@@ -75,6 +75,8 @@ FUNCTIONS = {
     "rift_ile_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "rift_ile_set_graph": (C.c_int, [C.c_void_p, C.c_int]),
     "rift_ile_graph_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "rift_ile_set_autotune": (C.c_int, [C.c_void_p, C.c_int]),
+    "rift_ile_autotune_table": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
     "rift_ile_profile": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "rift_ile_sample": (C.c_int, [C.c_void_p, C.c_int, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64,
                                   C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -193,6 +195,20 @@ class RiftILE:
         c, r = C.c_int64(), C.c_int64()
         self._check(lib().rift_ile_graph_stats(self.h, C.byref(c), C.byref(r)))
         return c.value, r.value
+
+    def set_autotune(self, mode=1):
+        """How FP32 evaluations feed the matrix cores: 1 (default) measure the
+        staged and the direct form of each (T, K) class on its first
+        evaluation and use the faster; 0 always staged; 2 always direct.
+        ``True``/``False`` mean 1/0."""
+        self._check(lib().rift_ile_set_autotune(self.h, int(mode)))
+
+    def autotune_table(self):
+        """{(T, K): "staged" | "direct"} for the classes measured so far."""
+        arr = (C.c_int * 48)()
+        self._check(lib().rift_ile_autotune_table(self.h, arr))
+        names = {1: "staged", 2: "direct"}
+        return {(i // 3 + 1, i % 3 + 1): names[v] for i, v in enumerate(arr) if v in names}
 
     def profile(self, enable=True):
         """(ms, launches) of the dominant kernel since the last call; then

@@ -44,6 +44,9 @@ def test_host_only_calls():
     h = ctypes.c_void_p()
     assert L.rift_ile_create(ctypes.byref(h), None, None) == -1
     assert b"no points" in L.rift_ile_last_error(None)
+    # handle-less calls are refused without touching a device
+    assert L.rift_ile_set_autotune(None, 1) == -1
+    assert L.rift_ile_autotune_table(None, None) == -1
 
 
 def test_binding_refuses_without_device():

@@ -134,6 +134,51 @@ def test_lnL_batched_items(ile, orc):
         h.close()
 
 
+def test_matrix_core_feeds(ile, orc):
+    """The staged (LDS) and the direct (global-memory) feed of the matrix
+    cores give bit-identical ln L_t for every (T, K) class of the batched
+    parity case, the direct one within the oracle tolerance; the autotuner
+    measures each class once, its later runs agree with both forms, and the
+    graph replay starts only once every class is measured."""
+    w = synth.workload("tiny_batched")
+    pts = [synth.make_point(s) for s in w.points]
+    ths, refs, items, off = [], [], [], 0
+    for i, (d, n) in enumerate(zip(pts, w.n_samples)):
+        th = synth.mixed_samples(d, 300 + i, n)
+        ths.append(th)
+        refs.append(orc.lnL_t(orc.Point.from_dict(d, complex64=True), th))
+        items.append((i, off, n))
+        off += n
+    theta = torch.tensor(np.concatenate(ths, axis=1))
+    classes = {((s.n_modes + 1) // 2, len(s.dets)) for s in w.points}
+    outs = {}
+    for mode in (0, 2, 1):
+        h = _handle(ile, pts, "fp32")
+        h.set_autotune(mode)
+        _say(f"feed mode {mode}")
+        r1 = h.lnL(theta, items).cpu().numpy()
+        r2 = h.lnL(theta, items).cpu().numpy()
+        assert np.array_equal(r1, r2, equal_nan=True)
+        outs[mode] = r2
+        if mode == 1:
+            table = h.autotune_table()
+            _say(f"  measured: {sorted(table.items())}")
+            assert set(table) == classes
+        h.close()
+    assert np.array_equal(outs[0], outs[2], equal_nan=True)
+    assert np.array_equal(outs[0], outs[1], equal_nan=True)
+    for i, (_, o, n) in enumerate(items):
+        _check_fp32(outs[2][o:o + n], refs[i], f"direct feed, point {i}")
+    h = _handle(ile, pts, "fp32")
+    h.set_graph(True)
+    a = h.lnL(theta, items).cpu().numpy()
+    assert h.graph_stats() == (0, 0)  # classes being measured: not captured
+    b = h.lnL(theta, items).cpu().numpy()
+    assert h.graph_stats()[0] == 1
+    assert np.array_equal(a, outs[0], equal_nan=True) and np.array_equal(b, outs[0], equal_nan=True)
+    h.close()
+
+
 def test_lnL_edge_cases(ile, orc):
     spec = synth.workload("tiny").points[0]
     d = synth.make_point(spec)
