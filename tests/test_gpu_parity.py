@@ -472,6 +472,39 @@ def test_high_l_modes(ile, orc):
             assert np.all(np.abs(out - ref) <= 1e-9 * (1 + np.abs(ref)))
 
 
+def test_single_detector_ragged_window(ile, orc):
+    """One detector (K = 1) and a window of 37 samples (a ragged last block):
+    both matrix-core feeds and FP64 for ln L_t, and the FP32 adjoint, against
+    the oracle.  Noise-only Q scaled like the high-l case."""
+    spec = synth.PointSpec(seed=synth.BASE_SEED + 1202, dets=("V1",), n_modes=9, n_t=37, snr=1.0, kernel="none")
+    d = dict(synth.make_point(spec))
+    d["U"] = d["U"] * 1e4
+    d["Q"] = d["Q"] * 1e2
+    th = synth.mixed_samples(d, 32, 900)
+    p32 = orc.Point.from_dict(d, complex64=True)
+    ref = orc.lnL_t(p32, th)
+    outs = []
+    for mode in (0, 2):
+        h = _handle(ile, [d], "fp32")
+        h.set_autotune(mode)
+        _say(f"K=1 n_t=37 feed {mode}")
+        out = h.lnL(torch.tensor(th)).cpu().numpy()
+        _check_fp32(out, ref, f"K=1 feed {mode}")
+        outs.append(out)
+        if mode == 0:
+            lt, g = orc.grad(p32, th)
+            gg, lg = h.backward(torch.tensor(th), want_lnL=True)
+            _grad_check(gg.cpu().numpy(), lg.cpu().numpy(), g, lt, "K=1 backward fp32", _tau_sensitivity(orc, p32, th),
+                        f_s=spec.f_s)
+        h.close()
+    assert np.array_equal(outs[0], outs[1], equal_nan=True)
+    p64 = orc.Point.from_dict(d)
+    ref64 = orc.lnL_t(p64, th)
+    h = _handle(ile, [d], "fp64")
+    out = h.lnL(torch.tensor(th)).cpu().numpy()
+    assert np.all(np.abs(out - ref64) <= 1e-9 * (1 + np.abs(ref64)))
+
+
 def test_single_point_full_size(ile, orc):
     """10^6 samples through the FP32 launch the benchmark times: sampled
     per-sample parity against the oracle, the FP64 reduction against the
