@@ -127,6 +127,17 @@ def main():
             "kernel": ("mfma_bwd_kernel" if grad else "mfma_kernel") if mfma else "plain_kernel",
             "kernel_ms": k_avg_ms, "launches_per_step": k_launches / args.steps,
             "flops_per_eval": fl / max(rounds * sum(counts), 1)}
+    if mfma:
+        # matrix-core FLOP the forward kernel executes per evaluation: 16-row
+        # blocks 0..ceil(n_t/16) of every detector times 2 M_p elements
+        # (excluding the padding slots of partly filled tiles)
+        ex = [2 * p["det_pos"].shape[0] * 16 * ((p["n_t"] + 15) // 16 + 1) * 2 * ((len(p["ell"]) + 1) // 2 * 2)
+              for p in pts]
+        # (the adjoint: z and the transposed product G_k, one sweep)
+        roof["mfma_executed_per_eval"] = sum(c * e for c, e in zip(counts, ex)) / max(sum(counts), 1) * (2 if grad else 1)
+    if roof["traffic"] and k_avg_ms:
+        roof["hbm_gbs"] = roof["traffic"] / (k_avg_ms * 1e-3) / 1e9
+        roof["hbm_frac"] = roof["hbm_gbs"] / PEAK["hbm_gbs"]
 
     out = {
         "metric": "extrinsic lnL evals/sec (time-marginalized) at |dln L_marg|<=1e-3 vs FP64",

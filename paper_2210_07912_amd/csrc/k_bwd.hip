@@ -11,12 +11,14 @@
 // (App. D Eq. (def:lnL:Decomposed) differentiated; no separate passage of the
 // paper covers the gradient).
 //
-// mfma_bwd_kernel takes the work units of the forward evaluation.  Sweep 1
-// recomputes z_k (the MFMA contraction) and the window log-sum-exp, giving
-// ln L_t.  Sweep 2 recomputes z_k, forms p_j, accumulates H_k from the
-// derivative interpolation, spreads p onto rows as c_k (through a small LDS
-// ring of p per sample) and accumulates G_k = Q_k^T c_k as a second MFMA
-// contraction whose A operand is the staged block of Q read transposed.
+// mfma_bwd_kernel takes the work units of the forward evaluation and makes
+// one sweep over the rows: it recomputes z_k (the MFMA contraction), forms
+// the softmax weights p_j online (unnormalized, against a running reference,
+// as in a streaming softmax), accumulates H_k from the derivative
+// interpolation, spreads p onto rows as c_k (through a small LDS ring of p
+// per sample) and accumulates G_k = Q_k^T c_k as a second MFMA contraction
+// whose A operand is the staged block of Q read transposed; the sums are
+// normalized at the end, which also gives ln L_t.
 // chain_kernel then applies the chain rule in FP64, one thread per sample.
 #include "common.h"
 #include "internal.h"
@@ -30,7 +32,7 @@ constexpr int kRZ = 52;  // z ring row: two 16-row slots, slot 0 again at 32 (48
 constexpr int kRP = 52;  // p ring of a sample: the same arrangement over window blocks
 
 template <int T, int K>
-__global__ void __launch_bounds__(256) mfma_bwd_kernel(MfmaArgs a, int item_lo, int item_hi, int cls) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) mfma_bwd_kernel(MfmaArgs a, int item_lo, int item_hi, int cls) {
   constexpr int E = 4 * T, J = T / 4, R = T % 4;
   constexpr int JA = J > 0 ? J : 1, RA = R > 0 ? R : 1;
   constexpr int ES = stage_stride<T>();
@@ -175,50 +177,15 @@ __global__ void __launch_bounds__(256) mfma_bwd_kernel(MfmaArgs a, int item_lo, 
       }
     };
 
-    // ---- sweep 1: ln L_t (lazy base-2 log-sum-exp, as in the forward kernel)
-    float m_run = 0.f, s_run = 0.f;
-    stage_load(0);
-    stage_store(0);
-    __syncthreads();
-    for (int b = 0; b <= JB; b++) {
-      stage_load(min(b + 1, JB));
-      if (active) {
-        product(b);
-        wave_sync();
-        if (b >= 1) {
-          float ell[4], zd[K][4];
-          interp(b - 1, ell, zd, false);
-#pragma unroll
-          for (int i = 0; i < 4; i++) ell[i] -= m_run;
-          const float cmax = fmaxf(fmaxf(ell[0], ell[1]), fmaxf(ell[2], ell[3]));
-          if ((b == 1 || cmax > 64.f) && cmax > -3.0e38f) {
-            s_run = b == 1 ? 0.f : s_run * __builtin_amdgcn_exp2f(-cmax);
-            m_run += cmax;
-#pragma unroll
-            for (int i = 0; i < 4; i++) ell[i] -= cmax;
-          }
-#pragma unroll
-          for (int i = 0; i < 4; i++) s_run += __builtin_amdgcn_exp2f(ell[i]);
-        }
-      }
-      stage_store((b + 1) % 3);
-      __syncthreads();
-    }
-    // the normalizer of the softmax, base 2, shared by the 4 lanes of a sample
-    float mo = m_run;
-    mo = fmaxf(mo, __shfl_xor(mo, 16));
-    mo = fmaxf(mo, __shfl_xor(mo, 32));
-    float sc = s_run * __builtin_amdgcn_exp2f(m_run - mo);
-    sc += __shfl_xor(sc, 16);
-    sc += __shfl_xor(sc, 32);
-    const float L2 = mo + __log2f(sc);
-    float lt = L2 * kLn2f - __logf((float)NT);
-    if (!valid || !isfinite(lt)) {
-      lt = NAN;
-      valid = false;
-    }
-
-    // ---- sweep 2: p_j, H_k, c_k, G_k
+    // ---- one sweep: z_k, then per window block ell_j, the unnormalized
+    // softmax weights p_j = 2^(ell_j - m_ref), H_k, c_k and G_k = Q_k^T c_k.
+    // m_ref is shared by the 4 lanes of a sample (the G products and the
+    // rows' taps mix their p): the first window block's maximum, moved only
+    // when a block's maximum exceeds it by 64, and then every sum kept so far
+    // (G, H, the sum of p and the p of the previous block in the ring) is
+    // scaled by 2^(m_ref - m_new).  At the end all of them are divided by the
+    // sum of p, which also gives ln L_t.
+    float m_ref = 0.f, s_run = 0.f;
     float hsum[K];
 #pragma unroll
     for (int k = 0; k < K; k++) hsum[k] = 0.f;
@@ -266,9 +233,31 @@ __global__ void __launch_bounds__(256) mfma_bwd_kernel(MfmaArgs a, int item_lo, 
           const int c = b - 1;
           float ell[4], zd[K][4];
           interp(c, ell, zd, true);
+          float cmax = fmaxf(fmaxf(ell[0], ell[1]), fmaxf(ell[2], ell[3]));
+          cmax = fmaxf(cmax, __shfl_xor(cmax, 16));
+          cmax = fmaxf(cmax, __shfl_xor(cmax, 32));
+          if ((c == 0 || cmax > m_ref + 64.f) && cmax > -3.0e38f) {  // uniform over a sample's lanes
+            if (c > 0) {
+              const float f = __builtin_amdgcn_exp2f(m_ref - cmax);
+              s_run *= f;
+#pragma unroll
+              for (int k = 0; k < K; k++) {
+                hsum[k] *= f;
+#pragma unroll
+                for (int mt = 0; mt < MT; mt++) gacc[k][mt] *= f;
+              }
+              float *pq = pr + 16 * ((c - 1) & 1) + 4 * g;  // this lane's p of block c - 1
+              f4 pv = *(f4 *)pq * f;
+              *(f4 *)pq = pv;
+              if (((c - 1) & 1) == 0) *(f4 *)(pq + 32) = pv;
+            }
+            m_ref = cmax;
+          }
           float pj[4];
 #pragma unroll
-          for (int i = 0; i < 4; i++) pj[i] = valid ? __builtin_amdgcn_exp2f(ell[i] - L2) : 0.f;
+          for (int i = 0; i < 4; i++) pj[i] = __builtin_amdgcn_exp2f(ell[i] - m_ref);
+#pragma unroll
+          for (int i = 0; i < 4; i++) s_run += pj[i];
 #pragma unroll
           for (int k = 0; k < K; k++)
 #pragma unroll
@@ -283,6 +272,18 @@ __global__ void __launch_bounds__(256) mfma_bwd_kernel(MfmaArgs a, int item_lo, 
       stage_store((b + 1) % 3);
       __syncthreads();
     }
+    // the softmax normalizer (base 2) of the sample, from its 4 lanes
+    float ssum = s_run;
+    ssum += __shfl_xor(ssum, 16);
+    ssum += __shfl_xor(ssum, 32);
+    const float L2 = m_ref + __log2f(ssum);
+    float lt = L2 * kLn2f - __logf((float)NT);
+    if (!valid || !isfinite(lt)) {
+      lt = NAN;
+      valid = false;
+    }
+    const float inv = 1.f / ssum;
+
     if (active) {
       // the last row block: window block JB does not exist (p = 0)
       float *pw = pr + 16 * (JB & 1) + 4 * g;
@@ -298,7 +299,7 @@ __global__ void __launch_bounds__(256) mfma_bwd_kernel(MfmaArgs a, int item_lo, 
           float h = hsum[k];
           h += __shfl_xor(h, 16);
           h += __shfl_xor(h, 32);
-          if (g == 0) ho[k * kTS + s] = valid ? h * kLn2f : NAN;
+          if (g == 0) ho[k * kTS + s] = valid ? h * inv * kLn2f : NAN;
         }
         // G_k[e = 16 mt + 4 g + v] of sample s
         RIFT_GLOBAL float *go = gpw(a.gop + top);
@@ -309,7 +310,7 @@ __global__ void __launch_bounds__(256) mfma_bwd_kernel(MfmaArgs a, int item_lo, 
 #pragma unroll
             for (int v = 0; v < 4; v++) {
               const int e = 16 * mt + 4 * g + v;
-              if (e < E) go[((size_t)k * E + e) * kTS + s] = gacc[k][mt][v];
+              if (e < E) go[((size_t)k * E + e) * kTS + s] = gacc[k][mt][v] * inv;
             }
         if (g == 0) {
           if (a.lnL) gpw(a.lnL)[col] = lt;

@@ -179,6 +179,34 @@ def test_matrix_core_feeds(ile, orc):
     h.close()
 
 
+def test_batched_workload_sampled(ile, orc):
+    """All 512 points of the batched workload (M in {2, 5, 9, 21}, K in {2, 3},
+    n_t in 200..800, SNR 8..40) in one call, 48 samples per point (half prior,
+    half near the injection), autotuned feeds, against the oracle per sample."""
+    w = synth.workload("batched")
+    pts = [synth.make_point(s) for s in w.points]
+    n = 48
+    ths, items = [], []
+    for i, d in enumerate(pts):
+        ths.append(synth.mixed_samples(d, 500 + i, n))
+        items.append((i, i * n, n))
+    theta = np.concatenate(ths, axis=1)
+    h = _handle(ile, pts, "fp32")
+    _say(f"batched workload: {len(pts)} points x {n} samples")
+    out = h.lnL(torch.tensor(theta), items).cpu().numpy()
+    out2 = h.lnL(torch.tensor(theta), items).cpu().numpy()  # classes measured: the kept forms
+    assert np.array_equal(out, out2, equal_nan=True)
+    _say(f"  feeds: {sorted(h.autotune_table().items())}")
+    h.close()
+    worst = 0.0
+    for i, d in enumerate(pts):
+        ref = orc.lnL_t(orc.Point.from_dict(d, complex64=True), ths[i])
+        err = np.abs(out[i * n:(i + 1) * n] - ref)
+        assert np.all(err <= _fp32_tol(ref)), (i, w.points[i], err.max())
+        worst = max(worst, float(err.max()))
+    _say(f"  max |d lnL_t| over all points {worst:.3e}")
+
+
 def test_lnL_edge_cases(ile, orc):
     spec = synth.workload("tiny").points[0]
     d = synth.make_point(spec)
