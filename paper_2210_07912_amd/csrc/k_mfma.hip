@@ -115,19 +115,20 @@ __global__ void __launch_bounds__(kSortThreads) bin_kernel(MfmaArgs a) {
 
 // ---- 2. per-item scans: block offsets within each bin, tiles before each bin --
 // Column scan of the [sort block][bin] histogram of one point: a workgroup
-// takes 64 bins; its four wavefronts each sum a quarter of the sort blocks,
-// then rewrite their quarter as running offsets.  Reads are coalesced along
+// takes 64 bins; its 16 wavefronts each sum a sixteenth of the sort blocks,
+// then rewrite their share as running offsets.  Reads are coalesced along
 // the bins, and every point's bins are spread over many workgroups.
 constexpr int kScanBins = 64;
+constexpr int kScanRanges = 16;  // block ranges per column scan: 1024 threads
 
-__global__ void __launch_bounds__(256) colscan_kernel(MfmaArgs a) {
-  __shared__ uint32_t part[4][kScanBins];
+__global__ void __launch_bounds__(kScanRanges * kScanBins) colscan_kernel(MfmaArgs a) {
+  __shared__ uint32_t part[kScanRanges][kScanBins];
   const int q = threadIdx.x >> 6, bl = threadIdx.x & 63;
   for (int it = blockIdx.y; it < a.items.n_items; it += gridDim.y) {
     const int b0 = a.items.bin0[it], nb = a.items.bin0[it + 1] - b0;
     if ((int)blockIdx.x * kScanBins >= nb) continue;  // uniform over the workgroup
     const int nblk = a.items.blk0[it + 1] - a.items.blk0[it];
-    const int lb_per = (nblk + 3) / 4;
+    const int lb_per = (nblk + kScanRanges - 1) / kScanRanges;
     const int b = (int)blockIdx.x * kScanBins + bl;
     const int lo = min(nblk, q * lb_per), hi = min(nblk, lo + lb_per);
     uint32_t *h = a.bhist + a.items.hoff[it];
@@ -145,7 +146,7 @@ __global__ void __launch_bounds__(256) colscan_kernel(MfmaArgs a) {
         h[(int64_t)lb * nb + b] = run;
         run += v;
       }
-      if (q == 3) a.count[b0 + b] = run;
+      if (q == kScanRanges - 1) a.count[b0 + b] = run;
     }
   }
 }
@@ -264,8 +265,8 @@ __global__ void __launch_bounds__(256) tile_item_kernel(MfmaArgs a) {
 }
 
 // work units of every bin: consecutive runs of up to 4 of its tiles
-__global__ void __launch_bounds__(256) unit_kernel(MfmaArgs a) {
-  const int g = blockIdx.x * 256 + threadIdx.x;
+__global__ void __launch_bounds__(64) unit_kernel(MfmaArgs a) {
+  const int g = blockIdx.x * 64 + threadIdx.x;
   if (g >= a.n_bins) return;
   const int it = item_of_bin(a.items, g);
   const uint32_t tb = (a.count[g] + kTS - 1) / kTS;
@@ -795,12 +796,12 @@ hipError_t mfma_prepare(const MfmaArgs &a, const int *mclass_M, const int *mclas
   const size_t lds = sizeof(uint32_t) * (size_t)std::min(a.max_item_bins, kLdsBins);
   hipLaunchKernelGGL(bin_kernel, dim3(a.n_sort_blocks), dim3(kSortThreads), lds, st, a);
   hipLaunchKernelGGL(colscan_kernel, dim3((unsigned)((a.max_item_bins + kScanBins - 1) / kScanBins), std::min(a.items.n_items, 65535)),
-                     dim3(256), 0, st, a);
+                     dim3(kScanRanges * kScanBins), 0, st, a);
   hipLaunchKernelGGL(tilescan_kernel, dim3(a.items.n_items), dim3(256), 0, st, a);
   hipLaunchKernelGGL(item_scan_kernel, dim3(1), dim3(64), 0, st, a);
   hipLaunchKernelGGL(scatter_kernel, dim3(a.n_sort_blocks), dim3(kSortThreads), lds, st, a);
   hipLaunchKernelGGL(tile_item_kernel, dim3((unsigned)((a.max_tiles + 255) / 256)), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(unit_kernel, dim3((unsigned)((a.n_bins + 255) / 256)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(unit_kernel, dim3((unsigned)((a.n_bins + 63) / 64)), dim3(64), 0, st, a);
   for (int c = 0; c < n_mclasses; c++) {
     const int lo = mclass_item0[c], hi = mclass_item0[c + 1];
     const dim3 grid((unsigned)(((int64_t)kTS * mclass_tiles[c] + 63) / 64));
