@@ -567,6 +567,27 @@ def test_single_point_full_size(ile, orc):
     assert abs(r32["lnL_marg"] - r64["lnL_marg"]) <= 1e-3
 
 
+def test_gradient_full_size(ile, orc):
+    """The gradient workload at full size through the launch the benchmark
+    times (10^5 samples drawn on the device, one adjoint call): sampled
+    gradients (random samples plus the 20 largest ln L_t) against the oracle's
+    FP64 gradient, with the FP32 tolerance of the smaller adjoint tests."""
+    w = synth.workload("grad")
+    d = synth.make_point(w.points[0])
+    n = w.n_samples[0]
+    h = _handle(ile, [d], "fp32", tau_width=w.tau_width)
+    th, _, _ = h.sample(0, 2210079124, 0, n)
+    _say(f"gradient full size n={n}")
+    g, lt = h.backward(th, want_lnL=True)
+    th = th.cpu().numpy().astype(np.float64)
+    g, lt = g.cpu().numpy(), lt.cpu().numpy()
+    idx = np.random.default_rng(1).choice(n, 250, replace=False)
+    idx = np.unique(np.concatenate([idx, np.argsort(lt)[-20:]]))
+    p = orc.Point.from_dict(d, complex64=True)
+    lref, gref = orc.grad(p, th[:, idx])
+    _grad_check(g[:, idx], lt[idx], gref, lref, "grad full size", _tau_sensitivity(orc, p, th[:, idx]), f_s=d["f_s"])
+
+
 def _oracle_marginalize(orc, pts, seed, counts, rounds, mask, eps, tau_width=0.0, trace=None):
     """Adaptive importance sampling composed from the oracle's pinned pieces:
     draw (Philox + histogram proposal) -> ln L_t -> ln w -> adapt, pooled over
