@@ -184,6 +184,24 @@ def main():
     else:
         out["config"]["launch"] = "direct"
 
+    # the gradient configuration's second part: 20 rounds of 1e5 samples of
+    # adaptive importance sampling, histogram proposal alone and refined by the
+    # gradient (the top samples climb ln L_t along the adjoint between rounds)
+    if grad and not args.n:
+        ref = {}
+        for name, gflag in (("histogram", False), ("gradient_refined", True)):
+            h.marginalize(seed, counts[0], n_rounds=2, adapt_mask=0x3F, floor_eps=0.1, gradient=gflag)  # warm-up
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            r = h.marginalize(seed + 7, counts[0], n_rounds=w.rounds, adapt_mask=0x3F, floor_eps=0.1, gradient=gflag,
+                              n_ascent=64, ascent_steps=12, ascent_mix=0.3)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            ref[name] = {"evals_per_s": counts[0] * w.rounds / (t3 - t2), "s": t3 - t2,
+                         "lnL_marg": r[0]["lnL_marg"], "sigma_lnL": r[0]["sigma_lnL"], "n_eff": r[0]["n_eff"]}
+        out["refinement"] = {"rounds": w.rounds, "samples_per_round": counts[0], "adapt": "alpha, delta, psi, iota, "
+                             "phi, D histograms", **ref}
+
     # FP32 vs FP64 on the same samples (same GPU): |d ln L_marg| and the FP64 rate
     if not args.no_fp64 and w.precision == "fp32" and len(pts) == 1 and not grad:
         nn = min(counts[0], 200_000)
