@@ -210,9 +210,10 @@ def u01(x):
 
 
 def draw(seed, point, rnd, n, *, d_min=10.0, d_max=1000.0, tau_width=0.0, cdf=None, nb=100,
-         adapt_mask=0, start=0):
+         adapt_mask=0, start=0, frame=None):
     """Samples start..start+n-1 of (point, round): theta [7, n], ln_ratio [n],
-    bins [7, n] (uint8), raw Philox words [8, n]."""
+    bins [7, n] (uint8), raw Philox words [8, n].  frame = (det_pos [>=2, 3],
+    gmst): the sky is drawn in the network frame of detectors 0 and 1."""
     th = np.zeros((7, n))
     lr = np.zeros(n)
     bins = np.zeros((7, n), dtype=np.uint8)
@@ -223,15 +224,33 @@ def draw(seed, point, rnd, n, *, d_min=10.0, d_max=1000.0, tau_width=0.0, cdf=No
     b7 = (C.c_uint8 * 7)()
     r8 = (C.c_uint32 * 8)()
     L = lib()
+    fp = None if frame is None else np.ascontiguousarray(np.asarray(frame[0], dtype=np.float64)[:2].reshape(6))
+    gm = 0.0 if frame is None else float(frame[1])
     for i in range(n):
-        L.or_draw(C.c_uint64(seed), C.c_uint32(point), C.c_uint32(rnd), C.c_uint64(start + i),
-                  C.c_double(d_min), C.c_double(d_max), C.c_double(tau_width), _ptr(cd), nb,
-                  C.c_uint(adapt_mask), _ptr(t7), C.byref(l1), b7, r8)
+        L.or_draw_frame(C.c_uint64(seed), C.c_uint32(point), C.c_uint32(rnd), C.c_uint64(start + i),
+                        C.c_double(d_min), C.c_double(d_max), C.c_double(tau_width), _ptr(cd), nb,
+                        C.c_uint(adapt_mask), _ptr(fp), C.c_double(gm), _ptr(t7), C.byref(l1), b7, r8)
         th[:, i] = t7
         lr[i] = l1.value
         bins[:, i] = list(b7)
         raw[:, i] = list(r8)
     return th, lr, bins, raw
+
+
+def network_frame(det_pos):
+    """[3, 3] rows x', y', z' of the network sky frame of detectors 0 and 1."""
+    fp = np.ascontiguousarray(np.asarray(det_pos, dtype=np.float64)[:2].reshape(6))
+    ax = np.zeros(9)
+    lib().or_network_frame(_ptr(fp), _ptr(ax))
+    return ax.reshape(3, 3)
+
+
+def frame_u(det_pos, gmst, alpha, delta):
+    """(alpha, delta) -> (u_phi', u_cos theta') in the network frame."""
+    fp = np.ascontiguousarray(np.asarray(det_pos, dtype=np.float64)[:2].reshape(6))
+    u0, u1 = C.c_double(), C.c_double()
+    lib().or_frame_u(_ptr(fp), C.c_double(gmst), C.c_double(alpha), C.c_double(delta), C.byref(u0), C.byref(u1))
+    return u0.value, u1.value
 
 
 def adapt(bins, lnw, *, nb=100, floor_eps=0.1, adapt_mask=0x3F):

@@ -598,9 +598,71 @@ void or_prior_cdf(int d, const double *theta, double d_min, double d_max, double
  * prior, 100-bin histograms in adaptive dimensions), so that
  * ln p - ln p_s = -sum_d ln h_d(u_d).  bins[d] receives the histogram bin of
  * the sample's prior-CDF coordinate in every dimension. */
-void or_draw(uint64_t seed, uint32_t point, uint32_t round, uint64_t i, double d_min, double d_max,
-             double tau_width, const double *cdf, int nb, unsigned adapt_mask, double theta[7],
-             double *ln_ratio, uint8_t bins[7], uint32_t raw[8]) {
+/* Rotated detector-network-frame sky coordinates (Sec. II.A, added
+ * coordinate systems; Sec. II.C: usable with the GPU integrator): the north
+ * pole of the sampled sky is the unit vector from detector 0 to detector 1,
+ * so the arrival-time difference of that pair depends on the polar angle
+ * alone.  Axes: z' along the baseline, x' = normalize(e_z x z') (e_x x z' if
+ * the baseline lies along e_z), y' = z' x x'.  The sky prior is isotropic,
+ * so phi' uniform on [0, 2pi) and cos theta' uniform on [-1, 1] is the same
+ * prior; only the coordinates the histograms adapt in change. */
+static void cross3(const double a[3], const double b[3], double c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static void unit3(double a[3]) {
+  double n = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+  for (int i = 0; i < 3; i++) a[i] /= n;
+}
+
+void or_network_frame(const double *pos, double axes[9]) {
+  double z[3] = {pos[3] - pos[0], pos[4] - pos[1], pos[5] - pos[2]}, x[3], y[3];
+  unit3(z);
+  const double ez[3] = {0.0, 0.0, 1.0}, ex[3] = {1.0, 0.0, 0.0};
+  cross3(ez, z, x);
+  if (sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) < 1e-6) cross3(ex, z, x);
+  unit3(x);
+  cross3(z, x, y);
+  for (int i = 0; i < 3; i++) {
+    axes[i] = x[i];
+    axes[3 + i] = y[i];
+    axes[6 + i] = z[i];
+  }
+}
+
+void or_frame_u(const double *pos, double gmst, double alpha, double delta, double *u0, double *u1) {
+  double ax[9];
+  or_network_frame(pos, ax);
+  const double h = alpha - gmst;
+  const double n[3] = {cos(delta) * cos(h), cos(delta) * sin(h), sin(delta)};
+  double np[3];
+  for (int i = 0; i < 3; i++) np[i] = ax[3 * i] * n[0] + ax[3 * i + 1] * n[1] + ax[3 * i + 2] * n[2];
+  double ph = atan2(np[1], np[0]);
+  if (ph < 0.0) ph += 2.0 * M_PI;
+  *u0 = ph / (2.0 * M_PI);
+  *u1 = 0.5 * (np[2] + 1.0);
+}
+
+/* (u0, u1) in the frame -> (alpha, delta) */
+static void frame_sky(const double *pos, double gmst, double u0, double u1, double *alpha, double *delta) {
+  double ax[9];
+  or_network_frame(pos, ax);
+  const double ph = 2.0 * M_PI * u0, ct = 2.0 * u1 - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct));
+  const double np[3] = {st * cos(ph), st * sin(ph), ct};
+  double n[3];
+  for (int i = 0; i < 3; i++) n[i] = np[0] * ax[i] + np[1] * ax[3 + i] + np[2] * ax[6 + i];
+  *delta = asin(fmax(-1.0, fmin(1.0, n[2])));
+  double a = atan2(n[1], n[0]) + gmst;
+  a = fmod(a, 2.0 * M_PI);
+  if (a < 0.0) a += 2.0 * M_PI;
+  *alpha = a;
+}
+
+void or_draw_frame(uint64_t seed, uint32_t point, uint32_t round, uint64_t i, double d_min, double d_max,
+                   double tau_width, const double *cdf, int nb, unsigned adapt_mask, const double *frame_pos,
+                   double gmst, double theta[7], double *ln_ratio, uint8_t bins[7], uint32_t raw[8]) {
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   uint32_t r[8];
   for (int half = 0; half < 2; half++) {
@@ -608,7 +670,7 @@ void or_draw(uint64_t seed, uint32_t point, uint32_t round, uint64_t i, double d
     or_philox4x32_10(ctr, key, r + 4 * half);
   }
   if (raw) memcpy(raw, r, sizeof(r));
-  double lr = 0.0;
+  double lr = 0.0, us[7];
   for (int d = 0; d < 7; d++) {
     double v = or_u01(r[d]);
     double u = v;
@@ -627,9 +689,18 @@ void or_draw(uint64_t seed, uint32_t point, uint32_t round, uint64_t i, double d
       bin = lo;
     }
     if (bins) bins[d] = (uint8_t)bin;
+    us[d] = u;
     theta[d] = prior_inv(d, u, d_min, d_max, tau_width);
   }
+  if (frame_pos) frame_sky(frame_pos, gmst, us[OR_ALPHA], us[OR_DELTA], &theta[OR_ALPHA], &theta[OR_DELTA]);
   *ln_ratio = lr;
+}
+
+void or_draw(uint64_t seed, uint32_t point, uint32_t round, uint64_t i, double d_min, double d_max,
+             double tau_width, const double *cdf, int nb, unsigned adapt_mask, double theta[7],
+             double *ln_ratio, uint8_t bins[7], uint32_t raw[8]) {
+  or_draw_frame(seed, point, round, i, d_min, d_max, tau_width, cdf, nb, adapt_mask, NULL, 0.0, theta, ln_ratio,
+                bins, raw);
 }
 
 /* Adaptation between rounds (Sec. III.B).  Reading of the garbled histogram

@@ -85,6 +85,19 @@ void or_draw(uint64_t seed, uint32_t point, uint32_t round, uint64_t i,
              double d_min, double d_max, double tau_width,
              const double *cdf, int nb, unsigned adapt_mask,
              double theta[7], double *ln_ratio, uint8_t bins[7], uint32_t raw[8]);
+/* The same draw with the sky in the network frame (frame_pos = the Earth-fixed
+ * positions of two detectors, [2][3] metres; NULL: the equatorial frame):
+ * (u_alpha, u_delta) become (phi'/2pi, (cos theta' + 1)/2) about the
+ * baseline, mapped back to (alpha, delta) with gmst. */
+void or_draw_frame(uint64_t seed, uint32_t point, uint32_t round, uint64_t i,
+                   double d_min, double d_max, double tau_width,
+                   const double *cdf, int nb, unsigned adapt_mask,
+                   const double *frame_pos, double gmst,
+                   double theta[7], double *ln_ratio, uint8_t bins[7], uint32_t raw[8]);
+/* axes[3][3]: rows x', y', z' of the network frame in Earth-fixed coordinates */
+void or_network_frame(const double *frame_pos, double axes[9]);
+/* (alpha, delta) -> the frame's prior-CDF coordinates (u_phi', u_cos theta') */
+void or_frame_u(const double *frame_pos, double gmst, double alpha, double delta, double *u0, double *u1);
 void or_prior_cdf(int dim, const double *theta, double d_min, double d_max, double tau_width, double *u);
 /* adapt: histogram of w = exp(lnw - max) over each dimension's prior-CDF
  * coordinate bins, floor-mixed, normalized -> cdf[7][nb+1] */

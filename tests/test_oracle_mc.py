@@ -50,6 +50,54 @@ def test_prior_draws_follow_the_priors(orc):
     assert abs(np.corrcoef(th[0], th2[0])[0, 1]) < 0.05
 
 
+def _hl_positions():
+    return np.array([synth.DETECTORS["H1"]["vertex"], synth.DETECTORS["L1"]["vertex"]])
+
+
+def test_network_frame_axes(orc):
+    """The network sky frame (Sec. II.A, rotated detector-network-frame sky
+    coordinates): orthonormal, right-handed, north pole along the H1 -> L1
+    baseline; for a baseline along the Earth's axis the fallback axis is used."""
+    pos = _hl_positions()
+    ax = orc.network_frame(pos)
+    assert np.abs(ax @ ax.T - np.eye(3)).max() < 1e-14
+    assert abs(np.linalg.det(ax) - 1.0) < 1e-14
+    b = pos[1] - pos[0]
+    assert np.abs(ax[2] - b / np.linalg.norm(b)).max() < 1e-15
+    polar = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 5.0]])
+    ax2 = orc.network_frame(polar)
+    assert np.abs(ax2 @ ax2.T - np.eye(3)).max() < 1e-14 and np.allclose(ax2[2], [0, 0, 1])
+
+
+def test_network_frame_draws(orc):
+    """Sky drawn in the network frame: (i) still the isotropic prior (alpha
+    uniform, sin(delta) uniform: Kolmogorov-Smirnov), with ln p - ln p_s = 0;
+    (ii) the H1 - L1 arrival-time difference is a function of the frame's
+    polar coordinate alone, dt = -|b| cos(theta') / c with cos(theta') =
+    2 u - 1 of the sample's raw uniform; (iii) frame_u inverts the draw; the
+    other five parameters and the bins equal those of the equatorial draw."""
+    pos = _hl_positions()
+    gmst = 1.234
+    n = 20000
+    th, lr, bins, raw = orc.draw(2210079120, 3, 1, n, tau_width=1 / 4096, frame=(pos, gmst))
+    assert np.all(lr == 0.0)
+    assert stats.kstest(th[0], lambda x: x / (2 * math.pi)).pvalue > 1e-3
+    assert stats.kstest(th[1], lambda x: 0.5 * (np.sin(x) + 1)).pvalue > 1e-3
+    u = ((raw[:2] >> 8).astype(np.float64) + 0.5) / 2 ** 24
+    h = th[0] - gmst
+    nhat = np.array([np.cos(th[1]) * np.cos(h), np.cos(th[1]) * np.sin(h), np.sin(th[1])])
+    b = pos[1] - pos[0]
+    c = 299792458.0
+    dt = -(b @ nhat) / c
+    assert np.abs(dt - (-np.linalg.norm(b) * (2 * u[1] - 1) / c)).max() < 1e-15
+    for i in range(0, n, 997):
+        u0, u1 = orc.frame_u(pos, gmst, th[0, i], th[1, i])
+        assert abs(u1 - u[1, i]) < 1e-12
+        assert min(abs(u0 - u[0, i]), 1 - abs(u0 - u[0, i])) < 1e-12
+    th_e, lr_e, bins_e, raw_e = orc.draw(2210079120, 3, 1, n, tau_width=1 / 4096)
+    assert np.array_equal(th[2:], th_e[2:]) and np.array_equal(bins, bins_e) and np.array_equal(raw, raw_e)
+
+
 def test_histogram_proposal(orc):
     rng = np.random.default_rng(8)
     nb = 100
