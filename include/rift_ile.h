@@ -191,6 +191,20 @@ rift_status rift_ile_set_graph(rift_ile *h, int enable);
  * the handle was created (either output may be NULL). */
 rift_status rift_ile_graph_stats(const rift_ile *h, int64_t *captures, int64_t *replays);
 
+/* Sky coordinates of the sampler (Sec. II.A, rotated detector-network-frame
+ * sky coordinates; Sec. II.C: usable with the GPU integrator).  With
+ * enable != 0, rift_ile_sample and rift_ile_marginalize draw the sky of each
+ * point in its network frame: the north pole is the unit vector from the
+ * point's detector 0 to its detector 1 (Earth-fixed), the x axis is
+ * normalize(e_z x pole) (e_x x pole for a pole along e_z), y = pole x x.  The
+ * sky's two uniform coordinates become the frame azimuth / 2 pi and
+ * (cos(polar angle) + 1) / 2, so the adaptive histograms of dimensions 0 and
+ * 1 (and the bins written by rift_ile_sample) refer to those; the prior is
+ * isotropic either way, so ln p - ln p_s keeps its form, and the returned
+ * theta is still (alpha, delta).  A point with one detector keeps the
+ * equatorial axes.  Default off.  Returns RIFT_E_INVALID for a NULL handle. */
+rift_status rift_ile_set_network_frame(rift_ile *h, int enable);
+
 /* Per-class choice of how the FP32 evaluation feeds the matrix cores
  * (batching: every (T, K) class of points, T = ceil(M / 2) MFMA steps and K
  * detectors, is one persistent launch).  Two forms of the same kernel exist:

@@ -64,6 +64,7 @@ struct PointDev {
   int bin_w;                   // rows per delay bin
   double f_s, d_ref, gmst;
   double rc[kMaxDet][3];       // detector vertex / c  (s)
+  double frame[3][3];          // network sky frame: rows x', y', z' (z' along detector 0 -> 1), Earth-fixed
   double D[kMaxDet][9];        // response tensor
   int em[kMaxModes];
   int nterm[kMaxModes];

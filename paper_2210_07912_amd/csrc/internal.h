@@ -174,14 +174,17 @@ struct ProposalDev {
   unsigned pad_;
 };
 
+// pt / pts: the point(s) whose network frame the sky is drawn in, or null for
+// the equatorial coordinates
 template <typename R>
-hipError_t sample_launch(const PointDev *pts, const ProposalDev *prop, int point, uint64_t seed, uint32_t round,
+hipError_t sample_launch(const PointDev *pt, const ProposalDev *prop, int point, uint64_t seed, uint32_t round,
                          int64_t first, int64_t n, int64_t stride, int64_t bin_stride, double d_min, double d_max,
                          double tau_width, R *theta, R *ln_ratio, uint8_t *bins, hipStream_t st);
 // every point of a round in one launch (blk0: [np + 1] prefix of 256-sample
 // blocks; off, cnt: columns and counts of each point; device arrays)
 template <typename R>
-hipError_t sample_multi_launch(const ProposalDev *props, const int *blk0, int n_blocks, int np, const int64_t *off,
+hipError_t sample_multi_launch(const ProposalDev *props, const PointDev *pts, const int *blk0, int n_blocks, int np,
+                               const int64_t *off,
                                const int64_t *cnt, uint64_t seed, uint32_t round, int64_t stride, int64_t bin_stride,
                                double d_min, double d_max, double tau_width, R *theta, R *ln_ratio, uint8_t *bins,
                                hipStream_t st);
@@ -215,8 +218,10 @@ hipError_t ascent_select(const R *lnw, const R *theta, int64_t stride, const int
 template <typename R>
 hipError_t ascent_step(R *th_a, const R *grad, const R *lnl, AscentState *st, int n, unsigned mask, double d_min,
                        double d_max, double tw, hipStream_t s);
+// pts: the points (one per segment) whose network sky frame the sky
+// histograms use, or null for the equatorial coordinates
 hipError_t ascent_hist(const AscentState *st, int k, int n_seg, unsigned mask, double d_min, double d_max, double tw,
-                       double *ahist, hipStream_t s);
+                       const PointDev *pts, double *ahist, hipStream_t s);
 
 // blocks per segment of the histogram pass (and partial histograms kept)
 int hist_blocks(int64_t max_count);

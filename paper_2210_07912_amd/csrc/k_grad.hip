@@ -184,8 +184,26 @@ __global__ void ascent_step_kernel(R *th_a, const R *grad, const R *lnl, AscentS
 }
 
 // ---- histogram of the points reached (per segment, deterministic) ------------------
+// (alpha, delta) -> the prior-CDF coordinates of the point's network sky frame
+// (azimuth / 2 pi, (cos theta' + 1) / 2)
+__device__ __forceinline__ double frame_u(const PointDev &p, int d, double alpha, double delta) {
+  double sh, ch, sd, cd;
+  sincos(alpha - p.gmst, &sh, &ch);
+  sincos(delta, &sd, &cd);
+  const double n[3] = {cd * ch, cd * sh, sd};
+  const double x = p.frame[0][0] * n[0] + p.frame[0][1] * n[1] + p.frame[0][2] * n[2];
+  const double y = p.frame[1][0] * n[0] + p.frame[1][1] * n[1] + p.frame[1][2] * n[2];
+  const double z = p.frame[2][0] * n[0] + p.frame[2][1] * n[1] + p.frame[2][2] * n[2];
+  if (d == RIFT_ALPHA) {
+    const double a = atan2(y, x);
+    return (a < 0.0 ? a + 2.0 * kPi : a) / (2.0 * kPi);
+  }
+  return 0.5 * (fmax(-1.0, fmin(1.0, z)) + 1.0);
+}
+
+// pts != null: the sky histograms live in each point's network frame
 __global__ void ascent_hist_kernel(const AscentState *st, int k, int n_seg, unsigned mask, double d_min,
-                                   double d_max, double tw, double *ahist) {
+                                   double d_max, double tw, const PointDev *pts, double *ahist) {
   const int seg = blockIdx.x, d = threadIdx.x;
   if (d >= 7) return;
   double *h = ahist + ((size_t)seg * 7 + d) * kNB;
@@ -198,7 +216,9 @@ __global__ void ascent_hist_kernel(const AscentState *st, int k, int n_seg, unsi
     const AscentState &S = st[seg * k + j];
     if (!(S.best_l > -INFINITY)) continue;
     const double w = exp(S.best_l - mx);
-    int b = (int)floor(prior_u(d, S.best_th[d], d_min, d_max, tw) * kNB);
+    const double u = (pts && d < 2) ? frame_u(pts[seg], d, S.best_th[RIFT_ALPHA], S.best_th[RIFT_DELTA])
+                                    : prior_u(d, S.best_th[d], d_min, d_max, tw);
+    int b = (int)floor(u * kNB);
     b = b < 0 ? 0 : (b >= kNB ? kNB - 1 : b);
     int bl = b - 1, br = b + 1;
     if (periodic(d)) {
@@ -233,8 +253,9 @@ hipError_t ascent_step(R *th_a, const R *grad, const R *lnl, AscentState *st, in
 }
 
 hipError_t ascent_hist(const AscentState *st, int k, int n_seg, unsigned mask, double d_min, double d_max, double tw,
-                       double *ahist, hipStream_t s) {
-  hipLaunchKernelGGL(ascent_hist_kernel, dim3(n_seg), dim3(64), 0, s, st, k, n_seg, mask, d_min, d_max, tw, ahist);
+                       const PointDev *pts, double *ahist, hipStream_t s) {
+  hipLaunchKernelGGL(ascent_hist_kernel, dim3(n_seg), dim3(64), 0, s, st, k, n_seg, mask, d_min, d_max, tw, pts,
+                     ahist);
   return hipGetLastError();
 }
 

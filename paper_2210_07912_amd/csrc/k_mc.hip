@@ -41,21 +41,40 @@ __device__ __forceinline__ R prior_inv(int d, double u, double d_min, double d_m
   return (R)t;
 }
 
+// Sky in the network frame of the point (rows of fr: x', y', z' in Earth-fixed
+// coordinates): phi' = 2 pi u0, cos theta' = 2 u1 - 1 give the direction
+// n = sum_i n'_i e'_i, then delta = asin n_z and alpha = atan2(n_y, n_x) + gmst.
+// The sky prior is isotropic, so this is the same prior in other coordinates.
+__device__ __forceinline__ void frame_sky(const double (*fr)[3], double gmst, double u0, double u1, double &alpha,
+                                          double &delta) {
+  double sp, cp;
+  sincos(2.0 * kPi * u0, &sp, &cp);
+  const double ct = 2.0 * u1 - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct));
+  const double a = st * cp, b = st * sp;
+  const double nx = a * fr[0][0] + b * fr[1][0] + ct * fr[2][0];
+  const double ny = a * fr[0][1] + b * fr[1][1] + ct * fr[2][1];
+  const double nz = a * fr[0][2] + b * fr[1][2] + ct * fr[2][2];
+  delta = asin(fmax(-1.0, fmin(1.0, nz)));
+  double al = fmod(atan2(ny, nx) + gmst, 2.0 * kPi);
+  alpha = al < 0.0 ? al + 2.0 * kPi : al;
+}
+
 // one draw: Philox words (counter: sample index, 2 round + half, point; key:
 // seed) -> seven parameters through the proposal's inverse CDFs in FP64,
-// rounded once, their bins and ln p - ln p_s
+// rounded once, their bins and ln p - ln p_s.  pt != null: the sky in the
+// point's network frame (u_alpha, u_delta are its azimuth and polar cosine).
 template <typename R>
 __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned mask, uint32_t point, uint64_t seed,
                                          uint32_t round, uint64_t i, double d_min, double d_max, double tau_width,
-                                         R *theta, int64_t stride, R *ln_ratio, uint8_t *bins, int64_t bin_stride,
-                                         int64_t col) {
+                                         const PointDev *pt, R *theta, int64_t stride, R *ln_ratio, uint8_t *bins,
+                                         int64_t bin_stride, int64_t col) {
   uint32_t r[8];
   for (int half = 0; half < 2; half++) {
     uint32_t c[4] = {(uint32_t)i, (uint32_t)(i >> 32), 2u * round + (uint32_t)half, point};
     philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
     for (int q = 0; q < 4; q++) r[4 * half + q] = c[q];
   }
-  double lr = 0.0;
+  double lr = 0.0, us[2] = {0.0, 0.0};
 #pragma unroll
   for (int d = 0; d < 7; d++) {
     double v = u01(r[d]);
@@ -73,17 +92,24 @@ __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned 
       lr -= log(mass * kNB);
       bin = (uint32_t)lo;
     }
+    if (d < 2) us[d] = u;
     theta[d * stride + col] = prior_inv<R>(d, u, d_min, d_max, tau_width);
     if (bins) bins[d * bin_stride + col] = (uint8_t)bin;
+  }
+  if (pt) {
+    double al, de;
+    frame_sky(pt->frame, pt->gmst, us[0], us[1], al, de);
+    theta[RIFT_ALPHA * stride + col] = (R)al;
+    theta[RIFT_DELTA * stride + col] = (R)de;
   }
   if (ln_ratio) ln_ratio[col] = (R)lr;
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) sample_kernel(const ProposalDev *prop, uint32_t point, uint64_t seed,
-                                                     uint32_t round, int64_t first, int64_t n, int64_t stride,
-                                                     int64_t bin_stride, double d_min, double d_max, double tau_width,
-                                                     R *theta, R *ln_ratio, uint8_t *bins) {
+__global__ void __launch_bounds__(256) sample_kernel(const ProposalDev *prop, const PointDev *pt, uint32_t point,
+                                                     uint64_t seed, uint32_t round, int64_t first, int64_t n,
+                                                     int64_t stride, int64_t bin_stride, double d_min, double d_max,
+                                                     double tau_width, R *theta, R *ln_ratio, uint8_t *bins) {
   __shared__ double cdf[7][kNB + 1];
   __shared__ unsigned mask;
   for (int i = threadIdx.x; i < 7 * (kNB + 1); i += blockDim.x) cdf[i / (kNB + 1)][i % (kNB + 1)] = prop->cdf[i / (kNB + 1)][i % (kNB + 1)];
@@ -91,18 +117,19 @@ __global__ void __launch_bounds__(256) sample_kernel(const ProposalDev *prop, ui
   __syncthreads();
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  draw_one<R>(cdf, mask, point, seed, round, (uint64_t)(first + j), d_min, d_max, tau_width, theta, stride, ln_ratio,
-              bins, bin_stride, j);
+  draw_one<R>(cdf, mask, point, seed, round, (uint64_t)(first + j), d_min, d_max, tau_width, pt, theta, stride,
+              ln_ratio, bins, bin_stride, j);
 }
 
 // every point of a round in one launch: blocks [blk0[p], blk0[p + 1]) draw
 // point p's samples into columns off[p] ..
 template <typename R>
-__global__ void __launch_bounds__(256) sample_multi_kernel(const ProposalDev *props, const int *blk0, int np,
-                                                           const int64_t *off, const int64_t *cnt, uint64_t seed,
-                                                           uint32_t round, int64_t stride, int64_t bin_stride,
-                                                           double d_min, double d_max, double tau_width, R *theta,
-                                                           R *ln_ratio, uint8_t *bins) {
+__global__ void __launch_bounds__(256) sample_multi_kernel(const ProposalDev *props, const PointDev *pts,
+                                                           const int *blk0, int np, const int64_t *off,
+                                                           const int64_t *cnt, uint64_t seed, uint32_t round,
+                                                           int64_t stride, int64_t bin_stride, double d_min,
+                                                           double d_max, double tau_width, R *theta, R *ln_ratio,
+                                                           uint8_t *bins) {
   __shared__ double cdf[7][kNB + 1];
   __shared__ unsigned mask;
   int lo = 0, hi = np;  // blk0[lo] <= blockIdx.x < blk0[hi]
@@ -117,34 +144,37 @@ __global__ void __launch_bounds__(256) sample_multi_kernel(const ProposalDev *pr
   __syncthreads();
   const int64_t j = (int64_t)(blockIdx.x - blk0[p]) * blockDim.x + threadIdx.x;
   if (j >= cnt[p]) return;
-  draw_one<R>(cdf, mask, (uint32_t)p, seed, round, (uint64_t)j, d_min, d_max, tau_width, theta, stride, ln_ratio,
-              bins, bin_stride, off[p] + j);
+  draw_one<R>(cdf, mask, (uint32_t)p, seed, round, (uint64_t)j, d_min, d_max, tau_width, pts ? pts + p : nullptr,
+              theta, stride, ln_ratio, bins, bin_stride, off[p] + j);
 }
 
 template <typename R>
-hipError_t sample_launch(const PointDev *, const ProposalDev *prop, int point, uint64_t seed, uint32_t round,
+hipError_t sample_launch(const PointDev *pt, const ProposalDev *prop, int point, uint64_t seed, uint32_t round,
                          int64_t first, int64_t n, int64_t stride, int64_t bin_stride, double d_min, double d_max,
                          double tau_width, R *theta, R *ln_ratio, uint8_t *bins, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sample_kernel<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, prop, (uint32_t)point,
-                     seed, round, first, n, stride, bin_stride, d_min, d_max, tau_width, theta, ln_ratio, bins);
+  hipLaunchKernelGGL(sample_kernel<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, prop, pt,
+                     (uint32_t)point, seed, round, first, n, stride, bin_stride, d_min, d_max, tau_width, theta,
+                     ln_ratio, bins);
   return hipGetLastError();
 }
 
 template <typename R>
-hipError_t sample_multi_launch(const ProposalDev *props, const int *blk0, int n_blocks, int np, const int64_t *off,
-                               const int64_t *cnt, uint64_t seed, uint32_t round, int64_t stride, int64_t bin_stride,
-                               double d_min, double d_max, double tau_width, R *theta, R *ln_ratio, uint8_t *bins,
-                               hipStream_t st) {
+hipError_t sample_multi_launch(const ProposalDev *props, const PointDev *pts, const int *blk0, int n_blocks, int np,
+                               const int64_t *off, const int64_t *cnt, uint64_t seed, uint32_t round, int64_t stride,
+                               int64_t bin_stride, double d_min, double d_max, double tau_width, R *theta,
+                               R *ln_ratio, uint8_t *bins, hipStream_t st) {
   if (n_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sample_multi_kernel<R>, dim3((unsigned)n_blocks), dim3(256), 0, st, props, blk0, np, off, cnt,
-                     seed, round, stride, bin_stride, d_min, d_max, tau_width, theta, ln_ratio, bins);
+  hipLaunchKernelGGL(sample_multi_kernel<R>, dim3((unsigned)n_blocks), dim3(256), 0, st, props, pts, blk0, np, off,
+                     cnt, seed, round, stride, bin_stride, d_min, d_max, tau_width, theta, ln_ratio, bins);
   return hipGetLastError();
 }
-template hipError_t sample_multi_launch<float>(const ProposalDev *, const int *, int, int, const int64_t *,
+template hipError_t sample_multi_launch<float>(const ProposalDev *, const PointDev *, const int *, int, int,
+                                               const int64_t *,
                                                const int64_t *, uint64_t, uint32_t, int64_t, int64_t, double, double,
                                                double, float *, float *, uint8_t *, hipStream_t);
-template hipError_t sample_multi_launch<double>(const ProposalDev *, const int *, int, int, const int64_t *,
+template hipError_t sample_multi_launch<double>(const ProposalDev *, const PointDev *, const int *, int, int,
+                                                const int64_t *,
                                                 const int64_t *, uint64_t, uint32_t, int64_t, int64_t, double, double,
                                                 double, double *, double *, uint8_t *, hipStream_t);
 template hipError_t sample_launch<float>(const PointDev *, const ProposalDev *, int, uint64_t, uint32_t, int64_t,

@@ -55,6 +55,8 @@ struct rift_ile {
   hipStream_t gstream = nullptr;  // graph stream when the handle's stream is the null stream
   hipEvent_t gfork = nullptr, gjoin = nullptr;
   int64_t n_captures = 0, n_replays = 0;
+  // sky drawn in each point's network frame (rift_ile_set_network_frame)
+  bool net_frame = false;
   // how each (T, K) class feeds the matrix cores: 0 not measured, 1 staged, 2
   // direct; feed: 1 measure on first use, 0 all staged, 2 all direct
   int feed = 1;
@@ -182,6 +184,38 @@ void harmonic_table(PointDev &p, int m_idx, int l, int m) {
   p.hpar[m_idx] = par;
 }
 
+// Network sky frame of the point (Sec. II.A, rotated detector-network-frame
+// sky coordinates): z' the unit vector from detector 0 to detector 1,
+// x' = normalize(e_z x z') (e_x x z' when the baseline is along e_z),
+// y' = z' x x'.  One detector: the equatorial axes.
+void network_frame(const rift_ile_point &q, PointDev &p) {
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) p.frame[i][j] = i == j ? 1.0 : 0.0;
+  if (q.n_det < 2) return;
+  auto unit = [](double v[3]) {
+    const double n = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (int i = 0; i < 3; i++) v[i] /= n;
+  };
+  auto cross = [](const double a[3], const double b[3], double c[3]) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+  };
+  double z[3], x[3], y[3];
+  for (int i = 0; i < 3; i++) z[i] = q.det_pos[3 + i] - q.det_pos[i];
+  unit(z);
+  const double ez[3] = {0.0, 0.0, 1.0}, ex[3] = {1.0, 0.0, 0.0};
+  cross(ez, z, x);
+  if (std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) < 1e-6) cross(ex, z, x);
+  unit(x);
+  cross(z, x, y);
+  for (int i = 0; i < 3; i++) {
+    p.frame[0][i] = x[i];
+    p.frame[1][i] = y[i];
+    p.frame[2][i] = z[i];
+  }
+}
+
 rift_status check_point(const rift_ile_point &q, int idx, double tau_width) {
   if (q.n_det < 1 || q.n_det > RIFT_MAX_DET)
     return fail(nullptr, RIFT_E_SHAPE, "point %d: n_det=%d outside 1..%d", idx, q.n_det, RIFT_MAX_DET);
@@ -265,6 +299,7 @@ rift_status build_point(rift_ile *h, const rift_ile_point &q, PointDev &p) {
     for (int i = 0; i < 3; i++) p.rc[k][i] = q.det_pos[3 * k + i] / kC;
     for (int i = 0; i < 9; i++) p.D[k][i] = q.det_resp[9 * k + i];
   }
+  network_frame(q, p);
   for (int m = 0; m < M; m++) harmonic_table(p, m, q.ell[m], q.em[m]);
   // U (and V) in FP64, holding the values rounded to the bulk precision
   std::vector<double> u(2 * (size_t)K * M * M);
@@ -818,7 +853,8 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
     const int64_t cb = theta_out ? (int64_t)r * per_round : 0;
     R *th = theta_out ? theta_out + cb : (R *)th_ws;
     R *lw = lnw_out ? lnw_out + (int64_t)r * per_round : (R *)lw_ws;
-    HIPCHK(h, sample_multi_launch<R>(h->d_props, d_sblk, sblk[np], np, d_soff, d_scnt, mc->seed, (uint32_t)r,
+    HIPCHK(h, sample_multi_launch<R>(h->d_props, h->net_frame ? h->d_pts : nullptr, d_sblk, sblk[np], np, d_soff,
+                                     d_scnt, mc->seed, (uint32_t)r,
                                      th_stride, nr, h->d_min, h->d_max, h->tau_width, th, (R *)ratio,
                                      (uint8_t *)bins, h->stream));
     if ((s = eval<R>(h, it, th_stride, th, nullptr, lw, (const R *)ratio)) != RIFT_OK) return s;
@@ -841,7 +877,8 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
                                    h->stream));
         }
         h->prof = prof;
-        HIPCHK(h, ascent_hist(a_st, ka, np, mc->adapt_mask, h->d_min, h->d_max, h->tau_width, ahist, h->stream));
+        HIPCHK(h, ascent_hist(a_st, ka, np, mc->adapt_mask, h->d_min, h->d_max, h->tau_width,
+                              h->net_frame ? h->d_pts : nullptr, ahist, h->stream));
       }
       HIPCHK(h, adapt_launch<R>((const uint8_t *)bins, nr, lw, d_soff, d_scnt, d_prop, np, hbps, round,
                                 (unsigned long long *)hist, h->d_props, mc->adapt_mask, mc->floor_eps, h->stream,
@@ -1025,6 +1062,12 @@ rift_status rift_ile_graph_stats(const rift_ile *h, int64_t *captures, int64_t *
   return RIFT_OK;
 }
 
+rift_status rift_ile_set_network_frame(rift_ile *h, int enable) {
+  if (!h) return RIFT_E_INVALID;
+  h->net_frame = enable != 0;
+  return RIFT_OK;
+}
+
 rift_status rift_ile_set_autotune(rift_ile *h, int mode) {
   if (!h || mode < 0 || mode > 2) return RIFT_E_INVALID;
   h->feed = mode;
@@ -1051,9 +1094,11 @@ rift_status rift_ile_sample(rift_ile *h, int point, uint64_t seed, uint32_t roun
   if (point < 0 || point >= h->n_points) return fail(h, RIFT_E_INVALID, "point %d", point);
   if (n < 0 || first < 0 || (n > 0 && !theta)) return fail(h, RIFT_E_INVALID, "bad sample range or NULL theta");
   hipError_t e = h->precision == RIFT_FP32
-                     ? sample_launch<float>(h->d_pts, h->d_props + point, point, seed, round, first, n, n, n, h->d_min,
+                     ? sample_launch<float>(h->net_frame ? h->d_pts + point : nullptr, h->d_props + point, point, seed,
+                                            round, first, n, n, n, h->d_min,
                                             h->d_max, h->tau_width, (float *)theta, (float *)ln_ratio, bins, h->stream)
-                     : sample_launch<double>(h->d_pts, h->d_props + point, point, seed, round, first, n, n, n, h->d_min,
+                     : sample_launch<double>(h->net_frame ? h->d_pts + point : nullptr, h->d_props + point, point, seed,
+                                             round, first, n, n, n, h->d_min,
                                              h->d_max, h->tau_width, (double *)theta, (double *)ln_ratio, bins,
                                              h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "sample");

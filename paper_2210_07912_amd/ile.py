@@ -76,6 +76,7 @@ FUNCTIONS = {
     "rift_ile_set_graph": (C.c_int, [C.c_void_p, C.c_int]),
     "rift_ile_graph_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "rift_ile_set_autotune": (C.c_int, [C.c_void_p, C.c_int]),
+    "rift_ile_set_network_frame": (C.c_int, [C.c_void_p, C.c_int]),
     "rift_ile_autotune_table": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
     "rift_ile_profile": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "rift_ile_sample": (C.c_int, [C.c_void_p, C.c_int, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64,
@@ -195,6 +196,12 @@ class RiftILE:
         c, r = C.c_int64(), C.c_int64()
         self._check(lib().rift_ile_graph_stats(self.h, C.byref(c), C.byref(r)))
         return c.value, r.value
+
+    def set_network_frame(self, enable=True):
+        """Draw the sky in each point's detector-network frame (pole along
+        the baseline of its detectors 0 and 1); the histograms of dimensions
+        0 and 1 then adapt in that frame's azimuth and polar cosine."""
+        self._check(lib().rift_ile_set_network_frame(self.h, int(enable)))
 
     def set_autotune(self, mode=1):
         """How FP32 evaluations feed the matrix cores: 1 (default) measure the

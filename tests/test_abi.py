@@ -46,6 +46,7 @@ def test_host_only_calls():
     assert b"no points" in L.rift_ile_last_error(None)
     # handle-less calls are refused without touching a device
     assert L.rift_ile_set_autotune(None, 1) == -1
+    assert L.rift_ile_set_network_frame(None, 1) == -1
     assert L.rift_ile_autotune_table(None, None) == -1
 
 

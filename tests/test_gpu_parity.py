@@ -270,6 +270,81 @@ def test_sampler_matches_oracle(ile, orc):
             assert np.all(err <= rel * np.abs(oth[dd]) + 1e-12), (dd, err.max())
 
 
+def test_sampler_network_frame(ile, orc):
+    """Sky drawn in the detector-network frame (pole along detectors 0 -> 1):
+    bins exact and theta within one rounding of the oracle's draw, with a
+    histogram proposal in every dimension; the frame's polar cosine of every
+    drawn sky position (oracle's inverse map) is that of the sample's
+    uniform."""
+    spec = synth.workload("tiny").points[0]
+    d = synth.make_point(spec)
+    rng = np.random.default_rng(13)
+    cdf = np.zeros((7, 101))
+    cdf[:, 1:] = np.cumsum(rng.dirichlet(np.ones(100) * 0.5, size=7) * 0.9 + 0.001, axis=1)
+    cdf /= cdf[:, -1:]
+    cdf[:, -1] = 1.0
+    mask = 0b1111011
+    frame = (d["det_pos"], d["gmst"])
+    for prec in ("fp64", "fp32"):
+        h = _handle(ile, [d], prec, tau_width=1 / 4096)
+        h.set_network_frame(True)
+        h.set_proposal(0, cdf, mask)
+        _say(f"network-frame sampler {prec}")
+        n = 3000
+        th, lr, bins = h.sample(0, 2210079126, 2, n, first=77)
+        th, lr, bins = th.cpu().numpy(), lr.cpu().numpy(), bins.cpu().numpy()
+        oth, olr, obins, _ = orc.draw(2210079126, 0, 2, n, tau_width=1 / 4096, cdf=cdf, adapt_mask=mask, start=77,
+                                      frame=frame)
+        assert np.array_equal(bins, obins)
+        rel = 1e-13 if prec == "fp64" else 6e-8
+        assert np.all(np.abs(lr - olr) <= rel * np.abs(olr) + 1e-13)
+        for dd in range(7):
+            err = np.abs(th[dd] - oth[dd])
+            if dd == 0:  # alpha wraps at 2 pi
+                err = np.minimum(err, 2 * math.pi - err)
+            assert np.all(err <= rel * np.abs(oth[dd]) + 1e-12 + (2e-7 if prec == "fp32" and dd < 2 else 0)), \
+                (dd, err.max())
+        if prec == "fp64":
+            u1 = np.array([orc.frame_u(d["det_pos"], d["gmst"], th[0, i], th[1, i])[1] for i in range(0, n, 50)])
+            b = bins[1, ::50]
+            assert np.all((u1 >= b / 100 - 1e-9) & (u1 <= (b + 1) / 100 + 1e-9))
+
+
+def test_marginalize_network_frame(ile, orc):
+    """Adaptive marginalization with the sky in the network frame (FP64): the
+    GPU run follows the oracle's run composed from the frame-aware draws,
+    round by round (1e-6 on ln L_marg, as for the equatorial frame).  On a
+    two-detector point, where the sky posterior is a ring about the baseline,
+    n_eff with and without the frame is reported."""
+    w = synth.workload("tiny_batched")
+    pts = [synth.make_point(s) for s in w.points[:2]]
+    counts = [2500, 2000]
+    seed, rounds, mask, eps = 2210079127, 3, 0x3F, 0.1
+    ops = [orc.Point.from_dict(d) for d in pts]
+    ref = _oracle_marginalize(orc, ops, seed, counts, rounds, mask, eps, frames=[(d["det_pos"], d["gmst"]) for d in pts])
+    h = _handle(ile, pts, "fp64")
+    h.set_network_frame(True)
+    _say("network-frame adaptive marginalize fp64")
+    res = h.marginalize(seed, counts, n_rounds=rounds, adapt_mask=mask, floor_eps=eps)
+    for r, o in zip(res, ref):
+        _say(f"  gpu {r['lnL_marg']:.9f} oracle {o['lnL_marg']:.9f} n_eff {r['n_eff']:.1f}/{o['n_eff']:.1f}")
+        assert r["n"] == o["n"]
+        assert abs(r["lnL_marg"] - o["lnL_marg"]) < 1e-6
+    # report: a two-detector point, equatorial vs network frame
+    d2 = synth.make_point(synth.workload("plain").points[0])
+    for prec in ("fp32",):
+        out = {}
+        for net in (False, True):
+            h2 = _handle(ile, [d2], prec)
+            h2.set_network_frame(net)
+            r = h2.marginalize(2210079128, 20000, n_rounds=6, adapt_mask=0x3F, floor_eps=0.1)[0]
+            out[net] = r
+            assert math.isfinite(r["lnL_marg"])
+        _say(f"  H1-L1 point, 6 x 2e4 adaptive: equatorial n_eff {out[False]['n_eff']:.1f} "
+             f"(lnL_marg {out[False]['lnL_marg']:.4f} +- {out[False]['sigma_lnL']:.3g}), network frame "
+             f"n_eff {out[True]['n_eff']:.1f} ({out[True]['lnL_marg']:.4f} +- {out[True]['sigma_lnL']:.3g})")
+
+
 def test_reduce_matches_oracle(ile, orc):
     rng = np.random.default_rng(4)
     d = synth.make_point(synth.workload("tiny").points[0])
@@ -588,16 +663,19 @@ def test_gradient_full_size(ile, orc):
     _grad_check(g[:, idx], lt[idx], gref, lref, "grad full size", _tau_sensitivity(orc, p, th[:, idx]), f_s=d["f_s"])
 
 
-def _oracle_marginalize(orc, pts, seed, counts, rounds, mask, eps, tau_width=0.0, trace=None):
+def _oracle_marginalize(orc, pts, seed, counts, rounds, mask, eps, tau_width=0.0, trace=None, frames=None):
     """Adaptive importance sampling composed from the oracle's pinned pieces:
     draw (Philox + histogram proposal) -> ln L_t -> ln w -> adapt, pooled over
-    rounds.  trace (a list) receives (round, point, theta, lnw) for diagnostics."""
+    rounds.  trace (a list) receives (round, point, theta, lnw) for
+    diagnostics; frames (per point (det_pos, gmst)) draws the sky in the
+    network frame."""
     cdf = [None] * len(pts)
     masks = [0] * len(pts)
     lnw_all = [[] for _ in pts]
     for r in range(rounds):
         for i, (p, n) in enumerate(zip(pts, counts)):
-            th, lr, bins, _ = orc.draw(seed, i, r, n, tau_width=tau_width, cdf=cdf[i], adapt_mask=masks[i])
+            th, lr, bins, _ = orc.draw(seed, i, r, n, tau_width=tau_width, cdf=cdf[i], adapt_mask=masks[i],
+                                       frame=None if frames is None else frames[i])
             lnw = orc.lnL_t(p, th) + lr
             lnw_all[i].append(lnw)
             if trace is not None:
