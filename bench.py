@@ -202,6 +202,21 @@ def main():
         out["refinement"] = {"rounds": w.rounds, "samples_per_round": counts[0], "adapt": "alpha, delta, psi, iota, "
                              "phi, D histograms", **ref}
 
+    # adaptive sampling with the sky in each point's detector-network frame
+    # against the equatorial frame: n_eff and sigma of ln L_marg on the first
+    # points of the workload (10 rounds of 1e5 samples)
+    if w.adaptive and not args.n:
+        sub = pts[:8]
+        hs = ile.RiftILE(sub, precision=w.precision, tau_width=w.tau_width)
+        nf = {}
+        for name, net in (("equatorial", False), ("network_frame", True)):
+            hs.set_network_frame(net)
+            r = hs.marginalize(seed + 11, 100_000, n_rounds=10, adapt_mask=0x3F, floor_eps=0.1)
+            nf[name] = {"n_eff": [x["n_eff"] for x in r], "sigma_lnL": [x["sigma_lnL"] for x in r],
+                        "lnL_marg": [x["lnL_marg"] for x in r]}
+        hs.close()
+        out["network_frame"] = {"points": len(sub), "rounds": 10, "samples_per_round": 100_000, **nf}
+
     # FP32 vs FP64 on the same samples (same GPU): |d ln L_marg| and the FP64 rate
     if not args.no_fp64 and w.precision == "fp32" and len(pts) == 1 and not grad:
         nn = min(counts[0], 200_000)
