@@ -261,3 +261,21 @@ def adapt(bins, lnw, *, nb=100, floor_eps=0.1, adapt_mask=0x3F):
     lib().or_adapt(C.c_int64(n), bins.ctypes.data_as(C.POINTER(C.c_uint8)), C.c_int64(bins.shape[1]),
                    _ptr(lnw), nb, C.c_double(floor_eps), C.c_uint(adapt_mask), _ptr(cdf))
     return cdf
+
+
+def quv(data, psd, modes, df, f_low, row0, n_rows):
+    """Q [K, n_rows, M], U, V [K, M, M] (complex) of Eq. (QUV) from
+    frequency-domain data [K, N] (complex), one-sided PSD values S_k(|f_i|)
+    [K, N] and modes [M, N] (complex), on the two-sided grid in FFT order."""
+    data = np.ascontiguousarray(np.asarray(data, dtype=np.complex128))
+    psd = np.ascontiguousarray(np.asarray(psd, dtype=np.float64))
+    modes = np.ascontiguousarray(np.asarray(modes, dtype=np.complex128))
+    K, N = data.shape
+    M = modes.shape[0]
+    Q = np.zeros((K, n_rows, M), dtype=np.complex128)
+    U = np.zeros((K, M, M), dtype=np.complex128)
+    V = np.zeros((K, M, M), dtype=np.complex128)
+    lib().or_quv(K, M, C.c_int64(N), C.c_double(df), C.c_double(f_low), _ptr(data.view(np.float64)), _ptr(psd),
+                 _ptr(modes.view(np.float64)), C.c_int64(row0), C.c_int64(n_rows), _ptr(Q.view(np.float64)),
+                 _ptr(U.view(np.float64)), _ptr(V.view(np.float64)))
+    return Q, U, V

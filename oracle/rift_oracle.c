@@ -739,3 +739,60 @@ void or_adapt(int64_t n, const uint8_t *bins, int64_t stride, const double *lnw,
   }
   free(mass);
 }
+
+/* ------------------------------------------------------------------------
+ * Q, U, V of Eq. (QUV) (App. D), written as the sums they are on a discrete
+ * two-sided frequency grid: the inner product <a|b>_k = 2 int df conj(a~) b~ /
+ * S_k(|f|) over |f| > f_low, with Q_k,lm(t) = <h_lm(. + t)|d>_k (the mode
+ * shifted to time t gives the factor e^{2 pi i f t}), U = <h_lm|h_l'm'>_k and
+ * V = <h*_lm|h_l'm'>_k, where the transform of h*_lm at f is conj(h~_lm(-f)).
+ * ---------------------------------------------------------------------- */
+static double grid_f(int64_t i, int64_t N, double df) { return (double)(i < (N + 1) / 2 ? i : i - N) * df; }
+
+void or_quv(int K, int M, int64_t N, double df, double f_low, const double *data, const double *psd,
+            const double *modes, int64_t row0, int64_t n_rows, double *Q, double *U, double *V) {
+  double *w = (double *)malloc(sizeof(double) * (size_t)N);
+  for (int k = 0; k < K; k++) {
+    for (int64_t i = 0; i < N; i++) w[i] = fabs(grid_f(i, N, df)) > f_low ? 2.0 * df / psd[(size_t)k * N + i] : 0.0;
+    const double *d = data + (size_t)k * N * 2;
+    for (int m = 0; m < M; m++) {
+      const double *h = modes + (size_t)m * N * 2;
+      for (int64_t r = 0; r < n_rows; r++) {
+        const int64_t n = ((row0 + r) % N + N) % N;
+        double sr = 0.0, si = 0.0;
+        for (int64_t i = 0; i < N; i++) {
+          if (w[i] == 0.0) continue;
+          /* conj(h) d */
+          const double xr = h[2 * i] * d[2 * i] + h[2 * i + 1] * d[2 * i + 1];
+          const double xi = h[2 * i] * d[2 * i + 1] - h[2 * i + 1] * d[2 * i];
+          /* e^{2 pi i f_i t_r} = e^{2 pi i (i n mod N) / N} */
+          const int64_t ph = (int64_t)(((__int128)i * n) % N);
+          const double a = 2.0 * M_PI * (double)ph / (double)N;
+          const double c = cos(a), s = sin(a);
+          sr += w[i] * (xr * c - xi * s);
+          si += w[i] * (xr * s + xi * c);
+        }
+        Q[(((size_t)k * n_rows + r) * M + m) * 2] = sr;
+        Q[(((size_t)k * n_rows + r) * M + m) * 2 + 1] = si;
+      }
+      for (int mp = 0; mp < M; mp++) {
+        const double *g = modes + (size_t)mp * N * 2;
+        double ur = 0.0, ui = 0.0, vr = 0.0, vi = 0.0;
+        for (int64_t i = 0; i < N; i++) {
+          if (w[i] == 0.0) continue;
+          const int64_t j = (N - i) % N; /* -f_i */
+          ur += w[i] * (h[2 * i] * g[2 * i] + h[2 * i + 1] * g[2 * i + 1]);
+          ui += w[i] * (h[2 * i] * g[2 * i + 1] - h[2 * i + 1] * g[2 * i]);
+          vr += w[i] * (h[2 * j] * g[2 * i] - h[2 * j + 1] * g[2 * i + 1]);
+          vi += w[i] * (h[2 * j] * g[2 * i + 1] + h[2 * j + 1] * g[2 * i]);
+        }
+        const size_t o = (((size_t)k * M + m) * M + mp) * 2;
+        U[o] = ur;
+        U[o + 1] = ui;
+        V[o] = vr;
+        V[o + 1] = vi;
+      }
+    }
+  }
+  free(w);
+}

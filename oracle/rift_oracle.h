@@ -104,6 +104,18 @@ void or_prior_cdf(int dim, const double *theta, double d_min, double d_max, doub
 void or_adapt(int64_t n, const uint8_t *bins /*[7][stride]*/, int64_t stride, const double *lnw,
               int nb, double floor_eps, unsigned adapt_mask, double *cdf);
 
+/* Overlaps of Eq. (QUV) from frequency-domain inputs on a two-sided grid of N
+ * samples in FFT order (f_i = i df for i < (N+1)/2, (i - N) df otherwise),
+ * bins with |f_i| <= f_low left out, w_ki = 2 df / S_k(|f_i|):
+ *   Q[k][r][m] = sum_i w_ki e^{2 pi i f_i t_r} conj(h_m(f_i)) d_k(f_i),
+ *                t_r = (row0 + r) / (N df), r < n_rows;
+ *   U[k][m][m'] = sum_i w_ki conj(h_m(f_i)) h_m'(f_i);
+ *   V[k][m][m'] = sum_i w_ki h_m(-f_i) h_m'(f_i).
+ * data [K][N][2], psd [K][N], modes [M][N][2]; outputs complex interleaved:
+ * Q [K][n_rows][M][2], U and V [K][M][M][2].  Direct sums, FP64. */
+void or_quv(int K, int M, int64_t N, double df, double f_low, const double *data, const double *psd,
+            const double *modes, int64_t row0, int64_t n_rows, double *Q, double *U, double *V);
+
 #ifdef __cplusplus
 }
 #endif

@@ -344,3 +344,33 @@ def all_specs():
     for w in WORKLOADS:
         out.extend(workload(w).points)
     return out
+
+
+def fd_inputs(seed, n_det=2, n_modes=3, N=4096, df=0.5, f_low=20.0, f_high=None, noise=True):
+    """Synthetic frequency-domain inputs for the Q/U/V precompute: a two-sided
+    grid of N samples in FFT order (numpy.fft.fftfreq of N samples at
+    f_s = N df), a coloured one-sided PSD per detector S_k(|f|) > 0, complex
+    mode spectra h_m(f) ~ |f|^(-7/6) with a smooth random phase, independent on
+    the two sides of the grid and zero outside [f_low, f_high], and data that
+    is complex Gaussian noise (variance S_k / (4 df) per real part) or zero.
+    Returns (data [K, N], psd [K, N], modes [M, N], f [N])."""
+    g = _rng(seed, 21)
+    f = np.fft.fftfreq(N, d=1.0 / (N * df))
+    af = np.abs(f)
+    f_high = f_high if f_high is not None else 0.4 * N * df
+    fs = np.maximum(af, df)
+    psd = np.empty((n_det, N))
+    for k in range(n_det):
+        psd[k] = g.uniform(0.5, 2.0) * (1.0 + (40.0 / fs) ** 4 + (fs / 300.0) ** 2)
+    band = (af > f_low) & (af < f_high)
+    modes = np.zeros((n_modes, N), dtype=np.complex128)
+    for m in range(n_modes):
+        c = g.normal(size=4)
+        phase = c[0] + c[1] * fs / 100.0 + c[2] * np.sign(f) * (fs / 100.0) ** 2 + c[3] * (100.0 / fs)
+        modes[m] = np.where(band, g.uniform(0.5, 2.0) * (fs / 100.0) ** (-7.0 / 6.0) * np.exp(1j * phase), 0.0)
+    if noise:
+        sig = np.sqrt(psd / (4.0 * df))
+        data = sig * (g.normal(size=(n_det, N)) + 1j * g.normal(size=(n_det, N)))
+    else:
+        data = np.zeros((n_det, N), dtype=np.complex128)
+    return data, psd, modes, f
