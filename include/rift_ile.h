@@ -191,6 +191,40 @@ rift_status rift_ile_set_graph(rift_ile *h, int enable);
  * the handle was created (either output may be NULL). */
 rift_status rift_ile_graph_stats(const rift_ile *h, int64_t *captures, int64_t *replays);
 
+/* Frequency-domain inputs of one intrinsic point for rift_ile_precompute:
+ * a two-sided grid of N samples in FFT order, f_i = i df for i < (N + 1) / 2
+ * and (i - N) df otherwise (the time series it transforms to has N samples
+ * at f_s = N df). */
+typedef struct {
+  int n_det;            /* K, 1..RIFT_MAX_DET */
+  int n_modes;          /* M, 1..RIFT_MAX_MODES */
+  int64_t n_f;          /* N, 2..2^30 */
+  double df;            /* grid spacing, Hz, > 0 */
+  double f_low;         /* bins with |f_i| <= f_low are left out of every sum (Hz, >= 0) */
+  const double *data;   /* host [K][N][2]: d~_k(f_i), complex interleaved */
+  const double *psd;    /* host [K][N]: S_n,k(|f_i|), finite and > 0 where |f_i| > f_low */
+  const double *modes;  /* host [M][N][2]: h~_lm(f_i) at the reference distance */
+} rift_ile_fd_point;
+
+/* The overlaps of App. D Eq. (QUV) from frequency-domain inputs, the step
+ * that prepares Q, U and V for rift_ile_create.  With the inner product
+ * <a|b>_k = 2 sum_i df conj(a~(f_i)) b~(f_i) / S_n,k(|f_i|) over |f_i| > f_low:
+ *   Q[k][r][m] = <h_m(. + t_r)|d>_k = 2 sum_i df/S e^{2 pi i f_i t_r} conj(h~_m) d~_k,
+ *                t_r = (row0 + r) / f_s for r < n_rows (rows wrap modulo N),
+ *   U[k][m][m'] = <h_m|h_m'>_k,   V[k][m][m'] = <h*_m|h_m'>_k = 2 sum_i df/S h~_m(-f_i) h~_m'(f_i).
+ * Q is an unnormalized inverse DFT of the weighted product (one batched
+ * complex FFT over detectors and modes, hipFFT), U and V fixed-order FP64
+ * sums per entry.  Outputs are caller-owned host arrays, complex
+ * interleaved FP64: Q [K][n_rows][M][2] (the row layout of
+ * rift_ile_point.Q; NULL allowed when n_rows == 0), U and V [K][M][M][2].
+ * Runs on the current device and blocks; it allocates and frees its own
+ * device buffers (inputs, a K M N scratch, outputs) and FFT plan.  Errors:
+ * RIFT_E_INVALID (NULL array, df or f_low invalid), RIFT_E_SHAPE (K, M, N or
+ * n_rows out of range), RIFT_E_NONFINITE (non-finite input, or a PSD value
+ * <= 0 in band), RIFT_E_OOM, RIFT_E_DEVICE (HIP or FFT failure). */
+rift_status rift_ile_precompute(const rift_ile_fd_point *in, int64_t row0, int64_t n_rows, double *Q, double *U,
+                                double *V);
+
 /* Sky coordinates of the sampler (Sec. II.A, rotated detector-network-frame
  * sky coordinates; Sec. II.C: usable with the GPU integrator).  With
  * enable != 0, rift_ile_sample and rift_ile_marginalize draw the sky of each

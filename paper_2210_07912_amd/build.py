@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librift_ile.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["rift_ile.hip", "k_plain.hip", "k_mfma.hip", "k_bwd.hip", "k_mc.hip", "k_grad.hip"]
+SOURCES = ["rift_ile.hip", "k_plain.hip", "k_mfma.hip", "k_bwd.hip", "k_mc.hip", "k_grad.hip", "k_quv.hip"]
 ARCH = os.environ.get("RIFT_ILE_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -46,7 +46,9 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    subprocess.check_call([_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
+    # hipFFT for the batched transform of the Q/U/V precompute
+    subprocess.check_call([_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-L/opt/rocm/lib", "-lhipfft",
+                           "-Wl,-rpath,/opt/rocm/lib", "-o", tmp])
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")

@@ -235,4 +235,12 @@ hipError_t adapt_launch(const uint8_t *bins, int64_t bin_stride, const R *lnw, c
 
 hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 
+// Q/U/V of Eq. (QUV) from frequency-domain inputs, all pointers device
+// memory: data [K][N] and modes [M][N] complex (interleaved), psd [K][N];
+// X [K][M][N] complex scratch; Q [K][n_rows][M], U and V [K][M][M] complex.
+// Ordered on st; returns hipErrorUnknown when the FFT library fails.
+hipError_t quv_device(int K, int M, int64_t N, double df, double f_low, const double *data, const double *psd,
+                      const double *modes, int64_t row0, int64_t n_rows, double *X, double *Q, double *U, double *V,
+                      hipStream_t st);
+
 }  // namespace rift

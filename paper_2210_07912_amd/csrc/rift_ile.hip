@@ -1062,6 +1062,63 @@ rift_status rift_ile_graph_stats(const rift_ile *h, int64_t *captures, int64_t *
   return RIFT_OK;
 }
 
+rift_status rift_ile_precompute(const rift_ile_fd_point *in, int64_t row0, int64_t n_rows, double *Q, double *U,
+                                double *V) {
+  if (!in || !in->data || !in->psd || !in->modes || !U || !V || (n_rows > 0 && !Q))
+    return fail(nullptr, RIFT_E_INVALID, "precompute: NULL argument");
+  const int K = in->n_det, M = in->n_modes;
+  const int64_t N = in->n_f;
+  if (K < 1 || K > RIFT_MAX_DET || M < 1 || M > RIFT_MAX_MODES || N < 2 || N > ((int64_t)1 << 30) || n_rows < 0 ||
+      n_rows > ((int64_t)1 << 30))
+    return fail(nullptr, RIFT_E_SHAPE, "precompute: K=%d M=%d N=%lld n_rows=%lld out of range", K, M, (long long)N,
+                (long long)n_rows);
+  if (!(in->df > 0.0) || !std::isfinite(in->df) || !(in->f_low >= 0.0) || !std::isfinite(in->f_low))
+    return fail(nullptr, RIFT_E_INVALID, "precompute: df or f_low invalid");
+  if (!finite_all(in->data, 2 * (size_t)K * N) || !finite_all(in->modes, 2 * (size_t)M * N))
+    return fail(nullptr, RIFT_E_NONFINITE, "precompute: data or modes not finite");
+  for (int64_t i = 0; i < N; i++) {
+    const double f = (double)(i < (N + 1) / 2 ? i : i - N) * in->df;
+    if (std::fabs(f) <= in->f_low) continue;
+    for (int k = 0; k < K; k++) {
+      const double S = in->psd[(size_t)k * N + i];
+      if (!(S > 0.0) || !std::isfinite(S))
+        return fail(nullptr, RIFT_E_NONFINITE, "precompute: psd[%d][%lld] = %g in band", k, (long long)i, S);
+    }
+  }
+  const size_t nd = 2 * (size_t)K * N, np_ = (size_t)K * N, nm = 2 * (size_t)M * N, nx = 2 * (size_t)K * M * N;
+  const size_t nq = 2 * (size_t)K * n_rows * M, nu = 2 * (size_t)K * M * M;
+  std::vector<void *> bufs;
+  auto release = [&]() {
+    for (void *b : bufs) (void)hipFree(b);
+  };
+  auto alloc = [&](size_t n, double **p) -> bool {
+    void *v = nullptr;
+    if (hipMalloc(&v, sizeof(double) * std::max<size_t>(n, 1)) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    bufs.push_back(v);
+    *p = (double *)v;
+    return true;
+  };
+  double *dd, *dp, *dm, *dx, *dq, *du, *dv;
+  if (!alloc(nd, &dd) || !alloc(np_, &dp) || !alloc(nm, &dm) || !alloc(nx, &dx) || !alloc(nq, &dq) ||
+      !alloc(nu, &du) || !alloc(nu, &dv)) {
+    release();
+    return fail(nullptr, RIFT_E_OOM, "precompute: device allocation failed");
+  }
+  hipError_t e = hipMemcpy(dd, in->data, sizeof(double) * nd, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dp, in->psd, sizeof(double) * np_, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dm, in->modes, sizeof(double) * nm, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = quv_device(K, M, N, in->df, in->f_low, dd, dp, dm, row0, n_rows, dx, dq, du, dv, nullptr);
+  if (e == hipSuccess && n_rows > 0) e = hipMemcpy(Q, dq, sizeof(double) * nq, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(U, du, sizeof(double) * nu, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(V, dv, sizeof(double) * nu, hipMemcpyDeviceToHost);
+  release();
+  if (e != hipSuccess) return hip_fail(nullptr, e, "precompute");
+  return RIFT_OK;
+}
+
 rift_status rift_ile_set_network_frame(rift_ile *h, int enable) {
   if (!h) return RIFT_E_INVALID;
   h->net_frame = enable != 0;

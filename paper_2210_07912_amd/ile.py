@@ -43,6 +43,11 @@ class Desc(C.Structure):
                 ("d_min", C.c_double), ("d_max", C.c_double), ("tau_width", C.c_double)]
 
 
+class FdPoint(C.Structure):
+    _fields_ = [("n_det", C.c_int), ("n_modes", C.c_int), ("n_f", C.c_int64), ("df", C.c_double),
+                ("f_low", C.c_double), ("data", C.c_void_p), ("psd", C.c_void_p), ("modes", C.c_void_p)]
+
+
 class Item(C.Structure):
     _fields_ = [("point", C.c_int), ("offset", C.c_int64), ("count", C.c_int64)]
 
@@ -77,6 +82,8 @@ FUNCTIONS = {
     "rift_ile_graph_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "rift_ile_set_autotune": (C.c_int, [C.c_void_p, C.c_int]),
     "rift_ile_set_network_frame": (C.c_int, [C.c_void_p, C.c_int]),
+    "rift_ile_precompute": (C.c_int, [C.POINTER(FdPoint), C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]),
     "rift_ile_autotune_table": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
     "rift_ile_profile": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "rift_ile_sample": (C.c_int, [C.c_void_p, C.c_int, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64,
@@ -292,6 +299,27 @@ class RiftILE:
         arr = (Item * len(its))(*[Item(int(p), int(o), int(c)) for p, o, c in its])
         self._check(lib().rift_ile_backward(self.h, len(its), arr, n, _ptr(th), _ptr(g), _ptr(out), _ptr(lt)))
         return (out, lt) if want_lnL else out
+
+
+def precompute(data, psd, modes, df, f_low, row0, n_rows):
+    """Q [K, n_rows, M], U, V [K, M, M] (complex128, host) of Eq. (QUV) from
+    frequency-domain data [K, N], PSD values S_k(|f_i|) [K, N] and modes
+    [M, N] on the two-sided grid in FFT order (rift_ile_precompute)."""
+    data = np.ascontiguousarray(np.asarray(data, dtype=np.complex128))
+    psd = np.ascontiguousarray(np.asarray(psd, dtype=np.float64))
+    modes = np.ascontiguousarray(np.asarray(modes, dtype=np.complex128))
+    K, N = data.shape
+    M = modes.shape[0]
+    if psd.shape != (K, N) or modes.shape[1] != N:
+        raise ValueError("data [K, N], psd [K, N], modes [M, N]")
+    fd = FdPoint(K, M, N, float(df), float(f_low), data.ctypes.data, psd.ctypes.data, modes.ctypes.data)
+    Q = np.zeros((K, n_rows, M), dtype=np.complex128)
+    U = np.zeros((K, M, M), dtype=np.complex128)
+    V = np.zeros((K, M, M), dtype=np.complex128)
+    st = lib().rift_ile_precompute(C.byref(fd), int(row0), int(n_rows), Q.ctypes.data, U.ctypes.data, V.ctypes.data)
+    if st != 0:
+        raise RiftError(st, lib().rift_ile_last_error(None).decode())
+    return Q, U, V
 
 
 class LnLFunction(torch.autograd.Function):

@@ -345,6 +345,65 @@ def test_marginalize_network_frame(ile, orc):
              f"n_eff {out[True]['n_eff']:.1f} ({out[True]['lnL_marg']:.4f} +- {out[True]['sigma_lnL']:.3g})")
 
 
+def test_precompute_matches_oracle(ile, orc):
+    """Q, U, V of Eq. (QUV) from frequency-domain inputs (batched inverse FFT
+    and weighted Gram sums on the GPU) against the oracle's direct sums: a
+    power-of-two and an odd grid, rows that wrap around the end of the time
+    series, and no rows at all; the injection identity Q_m(t0) = (U c)_m."""
+    for N, K, M, row0, n_rows in ((4096, 3, 5, 3900, 300), (3001, 2, 3, 17, 64), (1024, 1, 2, 0, 0)):
+        data, psd, modes, f = synth.fd_inputs(40 + N, n_det=K, n_modes=M, N=N, df=0.25, f_low=20.0)
+        _say(f"precompute N={N} K={K} M={M} rows {row0}+{n_rows}")
+        Q, U, V = ile.precompute(data, psd, modes, 0.25, 20.0, row0, n_rows)
+        oQ, oU, oV = orc.quv(data, psd, modes, 0.25, 20.0, row0, n_rows)
+        for got, ref, name in ((Q, oQ, "Q"), (U, oU, "U"), (V, oV, "V")):
+            if ref.size:
+                err = np.abs(got - ref).max() / np.abs(ref).max()
+                _say(f"  {name}: max rel err {err:.2e}")
+                assert err < 1e-11, name
+    data, psd, modes, f = synth.fd_inputs(7, n_det=2, n_modes=3, N=2048, df=0.5, f_low=20.0, noise=False)
+    c = np.random.default_rng(8).normal(size=(2, 3)) + 1j * np.random.default_rng(9).normal(size=(2, 3))
+    n0 = 1500
+    shift = np.exp(-2j * np.pi * f * n0 / (2048 * 0.5))
+    data = np.array([(c[k][:, None] * modes).sum(axis=0) * shift for k in range(2)])
+    Q, U, V = ile.precompute(data, psd, modes, 0.5, 20.0, n0, 1)
+    for k in range(2):
+        assert np.abs(Q[k, 0] - U[k] @ c[k]).max() < 1e-10 * np.abs(U[k] @ c[k]).max()
+
+
+def test_precompute_to_likelihood(ile, orc):
+    """From frequency-domain data to ln L: a noise-free signal
+    h_k(t) = Re[(D_ref/D) F_k sum_m Y_m h_m(t - t_inj)] in one detector at the
+    geocentre, its Q, U, V from rift_ile_precompute, a handle built on them
+    with a one-sample window at t_inj: ln L_t at the injected parameters is
+    <h|h>/2 (the likelihood's maximum, App. D.1), in FP64 and FP32."""
+    N, df, fl = 4096, 0.5, 20.0
+    fsamp = N * df
+    _, psd, modes, f = synth.fd_inputs(11, n_det=1, n_modes=3, N=N, df=df, f_low=fl, noise=False)
+    ell, em = np.array([2, 2, 3], dtype=np.int32), np.array([2, -2, 3], dtype=np.int32)
+    x, yv = np.array(synth.DETECTORS["H1"]["xarm"]), np.array(synth.DETECTORS["H1"]["yarm"])
+    resp = (0.5 * (np.outer(x, x) - np.outer(yv, yv)))[None]
+    P, n_t, n_inj = 4, 1, 1800
+    point = dict(U=None, V=None, Q=None, det_pos=np.zeros((1, 3)), det_resp=resp, ell=ell, em=em, n_t=n_t, pad=P,
+                 f_s=fsamp, d_ref=100.0, gmst=0.7)
+    th = np.array([1.1, -0.4, 0.3, 0.8, 2.0, 180.0, 0.0])
+    # coefficients x F Y_m at th (the oracle's; U only enters B, so any U works here)
+    probe = dict(point, Q=np.zeros((1, n_t + 2 * P + 3, 3)), U=np.eye(3)[None], V=None)
+    a = orc.coeffs(orc.Point.from_dict(probe), th)[0][0]
+    neg = (-np.arange(N)) % N
+    s = (a[:, None] * modes).sum(axis=0)
+    dtil = 0.5 * (s + s[neg].conj()) * np.exp(-2j * np.pi * f * n_inj / fsamp)
+    rho2 = float(np.sum(np.where(np.abs(f) > fl, 2 * df * np.abs(dtil) ** 2 / psd[0], 0.0)))
+    L = n_t + 2 * P + 3
+    Q, U, V = ile.precompute(dtil[None], psd, modes, df, fl, n_inj - P - 1, L)
+    point.update(Q=Q, U=U, V=V)
+    for prec in ("fp64", "fp32"):
+        h = _handle(ile, [point], prec)
+        got = float(h.lnL(torch.tensor(th[:, None]))[0])
+        _say(f"precompute -> lnL {prec}: {got:.10f}, <h|h>/2 = {rho2 / 2:.10f}")
+        tol = 1e-9 * rho2 if prec == "fp64" else 2e-4 + 4e-6 * (rho2 + 1e3)
+        assert abs(got - rho2 / 2) <= tol
+
+
 def test_reduce_matches_oracle(ile, orc):
     rng = np.random.default_rng(4)
     d = synth.make_point(synth.workload("tiny").points[0])

@@ -64,3 +64,28 @@ def test_f_low_cut_and_inverse_fft(orc):
     d2[0, np.abs(f) <= fl] += 1e3
     Q2, _, _ = orc.quv(d2, psd, modes, df, fl, 0, 16)
     assert np.abs(Q2 - Q[:, :16]).max() == 0.0
+
+
+def test_overlaps_give_the_likelihood_peak(orc):
+    """The overlaps feed the decomposed likelihood (App. D Eq. (def:lnL:Decomposed)):
+    noise-free data h_k(t) = Re[(D_ref/D) F_k sum_m Y_m h_m(t - t_inj)] in one
+    detector at the geocentre, Q/U/V of it, and a one-sample window at t_inj:
+    ln L_t at the injected parameters equals <h|h>/2, the noise-free maximum
+    (App. D.1), with the V term of these complex modes included."""
+    N, df, fl = 4096, 0.5, 20.0
+    _, psd, modes, f = synth.fd_inputs(11, n_det=1, n_modes=3, N=N, df=df, f_low=fl, noise=False)
+    x, yv = np.array(synth.DETECTORS["H1"]["xarm"]), np.array(synth.DETECTORS["H1"]["yarm"])
+    P, n_t, n_inj = 4, 1, 1800
+    point = dict(Q=np.zeros((1, n_t + 2 * P + 3, 3)), U=np.eye(3)[None], V=None, det_pos=np.zeros((1, 3)),
+                 det_resp=(0.5 * (np.outer(x, x) - np.outer(yv, yv)))[None], ell=np.array([2, 2, 3], dtype=np.int32),
+                 em=np.array([2, -2, 3], dtype=np.int32), n_t=n_t, pad=P, f_s=N * df, d_ref=100.0, gmst=0.7)
+    th = np.array([1.1, -0.4, 0.3, 0.8, 2.0, 180.0, 0.0])
+    a = orc.coeffs(orc.Point.from_dict(point), th)[0][0]
+    neg = (-np.arange(N)) % N
+    s = (a[:, None] * modes).sum(axis=0)
+    dtil = 0.5 * (s + s[neg].conj()) * np.exp(-2j * np.pi * f * n_inj / (N * df))
+    rho2 = float(np.sum(np.where(np.abs(f) > fl, 2 * df * np.abs(dtil) ** 2 / psd[0], 0.0)))
+    Q, U, V = orc.quv(dtil[None], psd, modes, df, fl, n_inj - P - 1, n_t + 2 * P + 3)
+    assert np.abs(V).max() > 1e-3 * np.abs(U).max()  # the V term matters here
+    point.update(Q=Q, U=U, V=V)
+    assert abs(orc.lnL_t(orc.Point.from_dict(point), th) - rho2 / 2) < 1e-10 * rho2
