@@ -65,6 +65,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the measurements beside the timed steps (precompute, network frame, refinement)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the multi-GPU path is not part of this build "
@@ -187,7 +189,7 @@ def main():
     # the gradient configuration's second part: 20 rounds of 1e5 samples of
     # adaptive importance sampling, histogram proposal alone and refined by the
     # gradient (the top samples climb ln L_t along the adjoint between rounds)
-    if grad and not args.n:
+    if grad and not args.n and not args.no_extras:
         ref = {}
         for name, gflag in (("histogram", False), ("gradient_refined", True)):
             h.marginalize(seed, counts[0], n_rounds=2, adapt_mask=0x3F, floor_eps=0.1, gradient=gflag)  # warm-up
@@ -202,10 +204,25 @@ def main():
         out["refinement"] = {"rounds": w.rounds, "samples_per_round": counts[0], "adapt": "alpha, delta, psi, iota, "
                              "phi, D histograms", **ref}
 
+    # the Q/U/V precompute at the single-point shape: 3 detectors, 21 modes,
+    # 8 s at 4096 Hz (N = 32768), the 999 stored rows; host arrays in and out
+    if args.workload == "single" and not args.n and not args.no_extras:
+        N, df = 32768, 0.125
+        data, psd, modes, _ = synth.fd_inputs(synth.BASE_SEED + 50, n_det=3, n_modes=21, N=N, df=df, f_low=20.0)
+        L = pts[0]["n_t"] + 2 * pts[0]["pad"] + 3
+        ile.precompute(data, psd, modes, df, 20.0, 0, L)  # warm-up (FFT plan, code objects)
+        t2 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            ile.precompute(data, psd, modes, df, 20.0, 0, L)
+        t3 = time.perf_counter()
+        out["precompute"] = {"K": 3, "M": 21, "N": N, "rows": L, "ms": (t3 - t2) / reps * 1e3,
+                             "note": "host arrays in and out, device buffers allocated per call"}
+
     # adaptive sampling with the sky in each point's detector-network frame
     # against the equatorial frame: n_eff and sigma of ln L_marg on the first
     # points of the workload (10 rounds of 1e5 samples)
-    if w.adaptive and not args.n:
+    if w.adaptive and not args.n and not args.no_extras:
         sub = pts[:8]
         hs = ile.RiftILE(sub, precision=w.precision, tau_width=w.tau_width)
         nf = {}
