@@ -104,3 +104,34 @@ def test_create_validates_points_on_the_host():
     # a valid description passes the host checks (then needs a device)
     st, msg = _create_status([d])
     assert st in (0, -7), msg
+
+
+def test_precompute_validates_on_the_host():
+    """rift_ile_precompute checks shapes, spacing and finiteness (a PSD value
+    <= 0 inside the band) before any device call."""
+    import numpy as np
+    import synth
+    from paper_2210_07912_amd import ile
+    data, psd, modes, f = synth.fd_inputs(1, n_det=2, n_modes=2, N=256, df=1.0, f_low=20.0)
+
+    def status(**kv):
+        a = dict(data=data, psd=psd, modes=modes, df=1.0, f_low=20.0, row0=0, n_rows=4)
+        a.update(kv)
+        try:
+            ile.precompute(**a)
+        except ile.RiftError as e:
+            return e.status, str(e)
+        return 0, ""
+
+    st, msg = status(df=0.0)
+    assert st == -1
+    p2 = psd.copy(); p2[1, 50] = 0.0  # |f| = 50 Hz > f_low
+    st, msg = status(psd=p2)
+    assert st == -5 and "psd" in msg
+    d2 = data.copy(); d2[0, 7] = np.nan
+    st, msg = status(data=d2)
+    assert st == -5
+    st, msg = status(modes=np.zeros((40, 256), complex))  # more modes than the library takes
+    assert st == -2
+    st, msg = status(n_rows=-1)
+    assert st == -2
