@@ -133,5 +133,7 @@ def test_precompute_validates_on_the_host():
     assert st == -5
     st, msg = status(modes=np.zeros((40, 256), complex))  # more modes than the library takes
     assert st == -2
-    st, msg = status(n_rows=-1)
-    assert st == -2
+    # a negative row count, through the C entry point itself
+    fd = ile.FdPoint(2, 2, 256, 1.0, 20.0, data.ctypes.data, psd.ctypes.data, modes.ctypes.data)
+    out = np.zeros(2 * 2 * 2 * 2)
+    assert ile.lib().rift_ile_precompute(ctypes.byref(fd), 0, -1, None, out.ctypes.data, out.ctypes.data) == -2
