@@ -256,15 +256,17 @@ def main():
                              "max_abs_delta_lnL_t": float((l32.double() - l64a).abs().max())}
         h64.close()
 
-    # the adaptive run's estimate against the FP64 plain form on the very same
-    # samples: 4 points, all rounds, their samples and proposal ratios replayed
-    if not args.no_fp64 and w.adaptive and not args.n and not args.no_extras:
-        sub = pts[:4]
+    # the estimate against the FP64 plain form on the very same samples (their
+    # samples and proposal ratios replayed): 4 points of the adaptive workload
+    # over all rounds, 32 points of the batched workload
+    if not args.no_fp64 and (w.adaptive or args.workload == "batched") and not args.n and not args.no_extras:
+        sub = pts[:4] if w.adaptive else pts[:32]
         hs = ile.RiftILE(sub, precision="fp32", tau_width=w.tau_width)
         h64 = ile.RiftILE(sub, precision="fp64", tau_width=w.tau_width)
-        res32, th, lw = hs.marginalize(seed + 13, counts[:4], n_rounds=rounds, adapt_mask=mask, floor_eps=0.1,
+        ns = len(sub)
+        res32, th, lw = hs.marginalize(seed + 13, counts[:ns], n_rounds=rounds, adapt_mask=mask, floor_eps=0.1,
                                        return_samples=True)
-        per_round = sum(counts[:4])
+        per_round = sum(counts[:ns])
         deltas = []
         for i in range(len(sub)):
             cols = torch.cat([torch.arange(r * per_round + sum(counts[:i]), r * per_round + sum(counts[:i + 1]),
@@ -274,7 +276,7 @@ def main():
             l64 = h64.lnL(t_i.double(), [(i, 0, t_i.shape[1])])
             r64 = h64.reduce(l64 + (lw[cols].double() - l32.double()))
             deltas.append(abs(res32[i]["lnL_marg"] - r64["lnL_marg"]))
-        out["fp64_replay"] = {"points": len(sub), "samples_per_point": counts[0] * rounds,
+        out["fp64_replay"] = {"points": ns, "samples": sum(counts[:ns]) * rounds, "max_abs_delta_lnL_marg": max(deltas),
                               "abs_delta_lnL_marg": deltas, "n_eff": [r["n_eff"] for r in res32]}
         hs.close()
         h64.close()
