@@ -94,7 +94,8 @@ struct MfmaArgs {
   uint32_t *item_tiles;   // [n_items + 1] tile prefix over items (filled on device)
   SampleRec *rec;         // [16 max_tiles] sorted samples (flag 0: padding)
   int *tile_item;         // [max_tiles]
-  float *cop;             // per point [tiles][K][2 Mp][16]: B operands of the MFMAs
+  float *cop;             // per point, per tile [K][2 Mp][16] floats; the coefficient pass fills the first
+                          // [2 Mp][16]: Y_m (element 2m + re/im) of the tile's samples
   int64_t *item_cop;      // [n_items] offset of each point's operands in cop
   CoefTile *ctile;        // [max_tiles]
   WorkUnit *unit;         // [max_tiles] work units, bins in order, points in order

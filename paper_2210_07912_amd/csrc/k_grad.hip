@@ -1,7 +1,8 @@
 // Gradient-informed refinement of the histogram proposal.
 //
 // Between rounds, the samples of largest ln w of each point climb ln L_t
-// along its gradient (the adjoint of the likelihood, see k_plain.hip) in the
+// along its gradient (the adjoint of the likelihood: k_bwd.hip on the
+// matrix cores for FP32 handles, k_plain.hip for FP64) in the
 // prior-CDF coordinates u of the adapted parameters, where the prior is
 // uniform on the unit cube.  Steps are normalized, u <- u + eta g_u/|g_u|,
 // and kept only when ln L_t rises (eta grows by 1.25 on success, halves on

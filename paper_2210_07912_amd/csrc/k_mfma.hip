@@ -9,28 +9,31 @@
 // with the real and imaginary parts of Q and a as the inner dimension, so it
 // runs as v_mfma_f32_16x16x4f32 (16 rows x 16 samples per instruction).  The
 // rows a sample needs depend on its own delay, so samples are first sorted
-// into bins of equal integer delay (per detector, bins of kBinW rows); a tile
-// holds 16 samples of one bin, whose windows then start within kBinW-1 rows
-// of each other and share one run of rows (about 3% more rows than the
-// window needs at n_t = 820).  Bins are padded to whole tiles, so tile t is
-// sorted slots [16 t, 16 t + 16).
+// into bins of equal integer delay (per detector, bins of 14 rows); a tile
+// holds 16 samples of one bin, whose windows then start within 13 rows of
+// each other and share one run of rows (about 3% more rows than the window
+// needs at n_t = 820).  Bins are padded to whole tiles, so tile t is sorted
+// slots [16 t, 16 t + 16).
 //
 // Kernels, in launch order:
 //   bin_kernel    integer delays n_k, bin key, per-sort-block bin counts
 //   colscan       per point: offset of each sort block in each bin
-//   tilescan      per point: tiles before each bin
-//   item_scan     tiles before each point; per-class tile counters reset
+//   tilescan      per point: tiles and work units before each bin
+//   item_scan     tiles and units before each point; per-class counters reset
 //   scatter       a 40-byte record (theta, column, n_k) at the sorted slot
 //   tile_item     point of every tile
-//   coef_kernel   one thread per slot, FP64: antenna patterns, harmonics,
-//                 a_{k,lm} (rounded to FP32, in the MFMA operand layout), the
+//   unit_kernel   the work units: up to 4 tiles of one bin each
+//   coef_kernel   one thread per slot, FP64: antenna patterns, harmonics
+//                 (polynomial tables), Y_m (rounded to FP32) and x F_k, the
 //                 quadratic term B, and the interpolation fraction mu_k
-//   mfma_kernel<T> persistent; each wavefront owns a tile and walks the rows
-//                 in 16-row blocks: T MFMAs per detector and block (operands
-//                 of the next block already in flight) -> a 32-row ring in
-//                 LDS -> Catmull-Rom interpolation of the 16 window samples
-//                 whose stencils are complete -> online max-shifted
-//                 log-sum-exp.  ell_j never leaves registers.
+//   mfma_kernel<T,K,DIRECT> persistent, one unit per workgroup, one tile per
+//                 wavefront: forms its B operands a_km = x F_k Y_m, walks the
+//                 rows in 16-row blocks (T MFMAs per detector and block, the
+//                 A operands staged through LDS or loaded directly, per class)
+//                 -> a ring of z in LDS -> Catmull-Rom interpolation of the
+//                 window samples whose stencils are complete -> a lazy
+//                 max-shifted base-2 log-sum-exp.  ell_j never leaves
+//                 registers.
 #include "common.h"
 #include "internal.h"
 #include "mfma_tile.h"
