@@ -1,0 +1,137 @@
+"""Oracle pins for the Gaussian-mixture proposal (Sec. III.B, App. A): the
+truncated-normal sampler against scipy's truncnorm, normalization of the
+proposal (E[p / p_s] = 1 and a Kolmogorov-Smirnov test of the draws), EM
+against closed forms (one component: the weighted moments; integer weights:
+replicated samples), EM recovering a known mixture and never lowering the
+weighted log-likelihood, and the online update against pooled moments."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, stats
+
+from oracle import gmm
+
+
+def test_truncated_normal_ppf_matches_scipy():
+    v = np.linspace(0.0, 1.0, 257)[:-1] + 0.5 / 256
+    for mu, sd in [(0.5, 0.1), (0.02, 0.05), (0.97, 0.3), (0.3, 2.0), (0.999, 1e-3)]:
+        ref = stats.truncnorm.ppf(v, -mu / sd, (1 - mu) / sd, loc=mu, scale=sd)
+        assert np.max(np.abs(gmm.tn_ppf(v, mu, sd) - ref)) < 1e-12
+
+
+def test_proposal_density_integrates_to_one():
+    w, mu, sd = np.array([0.5, 0.3, 0.2]), np.array([0.1, 0.5, 0.95]), np.array([0.05, 0.2, 0.01])
+    for eps in (0.0, 0.1):
+        tot = integrate.quad(lambda x: float(gmm.density(np.array([x]), w, mu, sd, eps)[0]), 0, 1,
+                             points=[0.1, 0.5, 0.95], limit=200, epsabs=1e-13)[0]
+        assert abs(tot - 1.0) < 1e-10
+
+
+def _model():
+    g = gmm.Gmm(3, 0b0010101, 0.1)
+    g.w[0], g.mu[0], g.sd[0] = [0.6, 0.3, 0.1], [0.2, 0.7, 0.9], [0.05, 0.1, 0.02]
+    g.w[2], g.mu[2], g.sd[2] = [0.2, 0.5, 0.3], [0.05, 0.5, 0.99], [0.03, 0.3, 0.05]
+    g.w[4], g.mu[4], g.sd[4] = [1.0, 0.0, 0.0], [0.4, 0.5, 0.6], [0.2, 0.1, 0.1]
+    g.n_trained = 1000.0
+    return g
+
+
+def test_mixture_draws_are_normalized_and_follow_the_mixture():
+    g = _model()
+    n = 6000
+    th, lr, u = gmm.draw(2210079124, 2, 3, n, g)
+    # E_{p_s}[p / p_s] = 1 (the prior is uniform in u)
+    r = np.exp(lr)
+    assert abs(r.mean() - 1.0) < 5 * r.std() / math.sqrt(n)
+    for d in (0, 2, 4):
+        def cdf(x, d=d):
+            c = g.eps * x
+            for k in range(3):
+                if g.w[d, k] > 0:
+                    mu, sd = g.mu[d, k], g.sd[d, k]
+                    c = c + (1 - g.eps) * g.w[d, k] * stats.truncnorm.cdf(x, -mu / sd, (1 - mu) / sd, loc=mu, scale=sd)
+            return c
+        assert stats.kstest(u[d], cdf).pvalue > 1e-3
+    # parameters outside the mask stay on the prior
+    for d in (1, 3, 5, 6):
+        assert stats.kstest(u[d], "uniform").pvalue > 1e-3
+    # theta through the prior inverse CDFs
+    assert np.allclose(th[0], 2 * np.pi * u[0]) and np.allclose(th[3], np.arccos(2 * u[3] - 1))
+
+
+def test_em_one_component_gives_weighted_moments():
+    rng = np.random.default_rng(5)
+    u = rng.beta(2, 5, 4000)
+    wt = rng.exponential(size=4000)
+    w, mu, sd = gmm.em_fit(u, wt, [1.0], [0.5], [0.5], 1)
+    m = np.sum(wt * u) / wt.sum()
+    s = math.sqrt(np.sum(wt * (u - m) ** 2) / wt.sum())
+    assert w[0] == 1.0 and abs(mu[0] - m) < 1e-14 and abs(sd[0] - s) < 1e-14
+
+
+def test_em_integer_weights_equal_replicated_samples():
+    rng = np.random.default_rng(6)
+    u = rng.uniform(size=500)
+    k = rng.integers(1, 4, size=500)
+    a = gmm.em_fit(u, k.astype(float), [0.3, 0.3, 0.4], [0.2, 0.5, 0.8], [0.1, 0.1, 0.1], 5)
+    b = gmm.em_fit(np.repeat(u, k), np.ones(int(k.sum())), [0.3, 0.3, 0.4], [0.2, 0.5, 0.8], [0.1, 0.1, 0.1], 5)
+    for x, y in zip(a, b):
+        assert np.max(np.abs(x - y)) < 1e-12
+
+
+def test_em_recovers_a_known_mixture_and_never_lowers_the_likelihood():
+    rng = np.random.default_rng(7)
+    n = 20000
+    comp = rng.uniform(size=n) < 0.35
+    u = np.where(comp, rng.normal(0.25, 0.04, n), rng.normal(0.7, 0.08, n))
+    u = u[(u > 0) & (u < 1)]
+    wt = np.ones(u.size)
+    par = ([0.5, 0.5], [0.4, 0.6], [0.2, 0.2])
+    ll = []
+    for _ in range(60):
+        w, mu, sd = par
+        dens = sum(w[k] * stats.norm.pdf(u, mu[k], sd[k]) for k in range(2))
+        ll.append(np.sum(wt * np.log(dens)))
+        par = gmm.em_fit(u, wt, *par, 1)
+    assert np.all(np.diff(ll) > -1e-9 * abs(ll[0]))
+    w, mu, sd = par
+    o = np.argsort(mu)
+    assert np.allclose(w[o], [0.35, 0.65], atol=0.02)
+    assert np.allclose(mu[o], [0.25, 0.7], atol=0.005)
+    assert np.allclose(sd[o], [0.04, 0.08], rtol=0.05)
+
+
+def test_online_update_pools_moments():
+    rng = np.random.default_rng(8)
+    x, y = rng.normal(0.3, 0.05, 3000), rng.normal(0.35, 0.08, 1000)
+    old = gmm.Gmm(1, 1, 0.1, w=[[1.0]] * 7, mu=[[x.mean()]] * 7, sd=[[x.std()]] * 7, n_trained=x.size)
+    w, mu, sd = gmm.merge(old, [1.0], [y.mean()], [y.std()], 0, y.size)
+    z = np.concatenate([x, y])
+    assert abs(mu[0] - z.mean()) < 1e-14 and abs(sd[0] - z.std()) < 1e-14 and w[0] == 1.0
+    # merging a model with itself keeps it; shuffled components are matched back
+    g = _model()
+    p = [2, 0, 1]
+    w, mu, sd = gmm.merge(g, g.w[0][p], g.mu[0][p], g.sd[0][p], 0, 500)
+    assert np.allclose(w, g.w[0]) and np.allclose(mu, g.mu[0]) and np.allclose(sd, g.sd[0])
+
+
+def test_weights_and_counts():
+    wt, M = gmm.weights([0.0, -1.0, np.nan, -np.inf, np.inf, 2.0])
+    assert M == 4
+    assert np.allclose(wt, [math.exp(-2), math.exp(-3), 0, 0, 0, 1])
+
+
+def test_adapt_round_from_the_prior():
+    # first update: EM from the initial model, no merge (nothing trained yet)
+    g0 = None
+    th, lr, u = gmm.draw(11, 0, 0, 3000, g0)
+    lnw = -0.5 * ((u[0] - 0.3) / 0.05) ** 2
+    g1 = gmm.adapt(g0, u, lnw, K=2, mask=1, eps=0.05, n_iter=30)
+    assert g1.n_trained == 3000 and g1.mask == 1
+    top = np.argmax(g1.w[0])
+    assert abs(g1.mu[0, top] - 0.3) < 0.01 and abs(g1.sd[0, top] - 0.05) < 0.01
+    # the next round's draws concentrate there and stay unbiased
+    th, lr, u2 = gmm.draw(11, 0, 1, 3000, g1)
+    assert np.mean(np.abs(u2[0] - 0.3) < 0.15) > 0.8
+    assert abs(np.exp(lr).mean() - 1) < 5 * np.exp(lr).std() / math.sqrt(3000)
