@@ -231,8 +231,22 @@ def main():
             r = hs.marginalize(seed + 11, 100_000, n_rounds=10, adapt_mask=0x3F, floor_eps=0.1)
             nf[name] = {"n_eff": [x["n_eff"] for x in r], "sigma_lnL": [x["sigma_lnL"] for x in r],
                         "lnL_marg": [x["lnL_marg"] for x in r]}
-        hs.close()
         out["network_frame"] = {"points": len(sub), "rounds": 10, "samples_per_round": 100_000, **nf}
+        # the Gaussian-mixture proposal (3 components per parameter, 10 EM
+        # iterations per round) against the histograms, equatorial frame
+        hs.set_network_frame(False)
+        gm = {}
+        for name, kk in (("histogram", 0), ("gmm_k3", 3)):
+            hs.marginalize(seed + 12, 100_000, n_rounds=2, adapt_mask=0x3F, floor_eps=0.1, gmm_components=kk)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            r = hs.marginalize(seed + 13, 100_000, n_rounds=10, adapt_mask=0x3F, floor_eps=0.1, gmm_components=kk)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            gm[name] = {"ms": (t3 - t2) * 1e3, "n_eff": [x["n_eff"] for x in r],
+                        "sigma_lnL": [x["sigma_lnL"] for x in r], "lnL_marg": [x["lnL_marg"] for x in r]}
+        hs.close()
+        out["gmm"] = {"points": len(sub), "rounds": 10, "samples_per_round": 100_000, "floor_eps": 0.1, **gm}
 
     # FP32 vs FP64 on the same samples (same GPU): |d ln L_marg| and the FP64 rate
     if not args.no_fp64 and w.precision == "fp32" and len(pts) == 1 and not grad:

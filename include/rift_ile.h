@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define RIFT_ILE_ABI_VERSION 1
+#define RIFT_ILE_ABI_VERSION 2
 
 typedef enum {
   RIFT_OK = 0,
@@ -142,6 +142,15 @@ typedef struct {
   int n_ascent;               /* 1..256 (0: 64) */
   int ascent_steps;           /* >= 1 (0: 12) */
   double ascent_mix;          /* [0, 1 - floor_eps) (0: 0.3) */
+  /* Gaussian-mixture proposal (Sec. III.B, adaptive sampling with Gaussian
+   * mixture models; App. A) in place of the histograms: gmm_components
+   * (1..4) normals per adapted parameter, each truncated to the parameter's
+   * prior-CDF coordinate [0, 1], plus the uniform floor floor_eps; between
+   * rounds gmm_iters weighted EM iterations (0: 10) from the current mixture,
+   * then the online update that combines it with the new fit by sample
+   * counts.  0: histograms.  Not combined with RIFT_MC_GRADIENT. */
+  int gmm_components;
+  int gmm_iters;
 } rift_ile_mc;
 
 #define RIFT_MC_GRADIENT 1u
@@ -303,6 +312,39 @@ rift_status rift_ile_adapt(rift_ile *h, int point, int64_t n, const uint8_t *bin
  * positive steps), mask as in rift_ile_adapt.  get synchronizes. */
 rift_status rift_ile_get_proposal(rift_ile *h, int point, double *cdf, unsigned *mask);
 rift_status rift_ile_set_proposal(rift_ile *h, int point, const double *cdf, unsigned mask);
+
+/* Gaussian-mixture proposal of a point (Sec. III.B, adaptive sampling with
+ * Gaussian mixture models; App. A): for each parameter d in mask,
+ * p_s(u) = floor_eps + (1 - floor_eps) sum_k w[d][k] N_t(u; mu[d][k], sd[d][k])
+ * in the prior-CDF coordinate u in [0, 1), N_t the normal truncated to
+ * [0, 1].  w, mu, sd: host [7][4] row-major (components k >= K ignored).
+ * The sampler draws v from the parameter's usual Philox word and the
+ * component from a second Philox block (counter word 2 = 2^31 | (2 round +
+ * half)); then u = mu + sd Phi^-1(Phi(a) + v (Phi(b) - Phi(a))).
+ * set: K in 1..4, weights of each masked parameter >= 0 summing to 1
+ * (within 1e-9), 0 <= mu <= 1, sd > 0, floor_eps in [0, 1], n_trained >= 0
+ * (the sample count the online update weights the mixture with); returns
+ * RIFT_E_INVALID otherwise.  get: *K = 0 when the point holds a histogram
+ * proposal; any output pointer but K may be NULL; synchronizes.  A later
+ * rift_ile_set_proposal or histogram adaptation replaces the mixture. */
+rift_status rift_ile_get_gmm(rift_ile *h, int point, int *K, unsigned *mask, double *floor_eps, double *n_trained,
+                             double *w, double *mu, double *sd);
+rift_status rift_ile_set_gmm(rift_ile *h, int point, int K, unsigned mask, double floor_eps, double n_trained,
+                             const double *w, const double *mu, const double *sd);
+
+/* One round's update of a point's Gaussian-mixture proposal (App. A) from n
+ * samples: u device float [7][n] prior-CDF coordinates (as the sampler drew
+ * them), lnw device [n] in the handle's precision.  Weights
+ * w = exp(ln w - max ln w) (0 for non-finite ln w); n_iter (1..1000)
+ * weighted EM iterations over the masked parameters, starting from the
+ * point's mixture when it has K components (else from equal weights, means
+ * (k + 1/2) / K, sd 1 / (2 K)), untruncated normals, sd >= 1e-4; then the
+ * online update: components matched by the smallest summed symmetric
+ * Mahalanobis distance over all permutations and combined with weights
+ * N = n_trained and M = the number of samples whose ln w is neither NaN nor
+ * +inf.  Sums are FP64 in a fixed order.  Asynchronous. */
+rift_status rift_ile_adapt_gmm(rift_ile *h, int point, int64_t n, const float *u, const void *lnw, unsigned mask,
+                               double floor_eps, int K, int n_iter);
 
 /* The whole step for every point: for each round, draw samples from the
  * current proposal, evaluate ln L_t, form ln w, fold them into a pooled FP64

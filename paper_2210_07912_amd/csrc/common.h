@@ -53,6 +53,7 @@ constexpr int kMaxHDeg = 8;     // degree of the harmonic polynomial for l <= 8
 constexpr int kNB = RIFT_NBINS;
 constexpr double kC = 299792458.0;
 constexpr double kPi = 3.14159265358979323846;
+constexpr double kSqrt2Pi = 2.50662827463100050242;  // sqrt(2 pi)
 
 // Per-point constants, resident in device memory.
 struct PointDev {

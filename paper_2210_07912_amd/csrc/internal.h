@@ -169,10 +169,17 @@ hipError_t mfma_prepare(const MfmaArgs &a, const int *mclass_M, const int *mclas
                         int n_mclasses, hipStream_t st);
 
 // ---- sampler / reductions / adaptation -------------------------------------
+// Proposal of one point: per parameter d in mask, either the 100-bin
+// histogram (cdf) or, with gk > 0, a mixture of gk normals truncated to the
+// prior-CDF coordinate's [0, 1] plus a uniform floor geps (gca = Phi(a),
+// gz = Phi(b) - Phi(a) of each component; gntr samples fitted so far)
+constexpr int kMaxG = 4;
 struct ProposalDev {
   double cdf[7][kNB + 1];
   unsigned mask;
-  unsigned pad_;
+  int gk;
+  double geps, gntr;
+  double gw[7][kMaxG], gmu[7][kMaxG], gsd[7][kMaxG], gca[7][kMaxG], gz[7][kMaxG];
 };
 
 // pt / pts: the point(s) whose network frame the sky is drawn in, or null for
@@ -180,7 +187,8 @@ struct ProposalDev {
 template <typename R>
 hipError_t sample_launch(const PointDev *pt, const ProposalDev *prop, int point, uint64_t seed, uint32_t round,
                          int64_t first, int64_t n, int64_t stride, int64_t bin_stride, double d_min, double d_max,
-                         double tau_width, R *theta, R *ln_ratio, uint8_t *bins, hipStream_t st);
+                         double tau_width, R *theta, R *ln_ratio, uint8_t *bins, hipStream_t st,
+                         float *ubuf = nullptr);
 // every point of a round in one launch (blk0: [np + 1] prefix of 256-sample
 // blocks; off, cnt: columns and counts of each point; device arrays)
 template <typename R>
@@ -188,7 +196,7 @@ hipError_t sample_multi_launch(const ProposalDev *props, const PointDev *pts, co
                                const int64_t *off,
                                const int64_t *cnt, uint64_t seed, uint32_t round, int64_t stride, int64_t bin_stride,
                                double d_min, double d_max, double tau_width, R *theta, R *ln_ratio, uint8_t *bins,
-                               hipStream_t st);
+                               hipStream_t st, float *ubuf = nullptr);
 
 struct ReduceTuple {
   double m, s1, s2;
@@ -233,6 +241,27 @@ hipError_t adapt_launch(const uint8_t *bins, int64_t bin_stride, const R *lnw, c
                         const ReduceTuple *seg_round, unsigned long long *hist, ProposalDev *props,
                         unsigned mask, double floor_eps, hipStream_t st, const double *ahist = nullptr,
                         double ascent_mix = 0.0);
+
+// Gaussian-mixture adaptation of every segment's proposal from the round's
+// prior-CDF coordinates ubuf [7][u_stride] (FP32) and ln w: n_iter weighted
+// EM iterations from the current mixture (or the initial one when none is
+// fitted yet, or its size differs from K), then the online update; part:
+// scratch [n_seg][bps][7][kMaxG][3], fit: scratch [2 n_seg] mixtures (the
+// current ones, then the EM iterates).
+struct GmmDev {
+  int k;
+  int pad_;
+  double ntr;
+  double w[7][kMaxG], mu[7][kMaxG], sd[7][kMaxG];
+};
+int em_blocks(int64_t max_count);
+template <typename R>
+hipError_t gmm_adapt_launch(const float *ubuf, int64_t u_stride, const R *lnw, const int64_t *seg_off,
+                            const int64_t *seg_cnt, const int *seg_prop, int n_seg, int bps,
+                            const ReduceTuple *seg_round, double *part, GmmDev *fit, ProposalDev *props,
+                            unsigned mask, double floor_eps, int K, int n_iter, hipStream_t st);
+// host: component normalizations gca, gz of a mixture (Phi by erfc)
+void gmm_norms(ProposalDev &p);
 
 hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 

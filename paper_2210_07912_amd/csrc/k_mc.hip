@@ -11,6 +11,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <cmath>
 
 namespace rift {
 
@@ -59,20 +60,53 @@ __device__ __forceinline__ void frame_sky(const double (*fr)[3], double gmst, do
   alpha = al < 0.0 ? al + 2.0 * kPi : al;
 }
 
+// mixture parameters of a proposal, staged in LDS by the sampling kernels
+struct GmmSh {
+  int k;
+  double eps;
+  double w[7][kMaxG], mu[7][kMaxG], sd[7][kMaxG], ca[7][kMaxG], z[7][kMaxG];
+};
+__device__ __forceinline__ void gmm_stage(const ProposalDev *prop, GmmSh &g) {
+  if (threadIdx.x == 0) {
+    g.k = prop->gk;
+    g.eps = prop->geps;
+  }
+  for (int i = threadIdx.x; i < 7 * kMaxG; i += blockDim.x) {
+    const int d = i / kMaxG, c = i % kMaxG;
+    g.w[d][c] = prop->gw[d][c];
+    g.mu[d][c] = prop->gmu[d][c];
+    g.sd[d][c] = prop->gsd[d][c];
+    g.ca[d][c] = prop->gca[d][c];
+    g.z[d][c] = prop->gz[d][c];
+  }
+}
+
 // one draw: Philox words (counter: sample index, 2 round + half, point; key:
 // seed) -> seven parameters through the proposal's inverse CDFs in FP64,
 // rounded once, their bins and ln p - ln p_s.  pt != null: the sky in the
 // point's network frame (u_alpha, u_delta are its azimuth and polar cosine).
+// With a mixture proposal (g->k > 0) an adapted parameter draws its
+// component from a second Philox block (counter word 2: 2^31 | (2 round +
+// half)): below the floor eps the uniform, else component k by the mixture
+// weights, then u by the component's truncated-normal inverse CDF at v.
 template <typename R>
-__device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned mask, uint32_t point, uint64_t seed,
-                                         uint32_t round, uint64_t i, double d_min, double d_max, double tau_width,
-                                         const PointDev *pt, R *theta, int64_t stride, R *ln_ratio, uint8_t *bins,
-                                         int64_t bin_stride, int64_t col) {
-  uint32_t r[8];
+__device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned mask, const GmmSh *g, uint32_t point,
+                                         uint64_t seed, uint32_t round, uint64_t i, double d_min, double d_max,
+                                         double tau_width, const PointDev *pt, R *theta, int64_t stride, R *ln_ratio,
+                                         uint8_t *bins, int64_t bin_stride, int64_t col, float *ubuf) {
+  uint32_t r[8], e[8];
   for (int half = 0; half < 2; half++) {
     uint32_t c[4] = {(uint32_t)i, (uint32_t)(i >> 32), 2u * round + (uint32_t)half, point};
     philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
     for (int q = 0; q < 4; q++) r[4 * half + q] = c[q];
+  }
+  const int gk = g->k;
+  if (gk > 0 && mask) {
+    for (int half = 0; half < 2; half++) {
+      uint32_t c[4] = {(uint32_t)i, (uint32_t)(i >> 32), 0x80000000u | (2u * round + (uint32_t)half), point};
+      philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+      for (int q = 0; q < 4; q++) e[4 * half + q] = c[q];
+    }
   }
   double lr = 0.0, us[2] = {0.0, 0.0};
 #pragma unroll
@@ -81,7 +115,29 @@ __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned 
     double u = v;
     // bin of the raw uniform: floor(v nb), exactly, in integers
     uint32_t bin = (uint32_t)((((uint64_t)(r[d] >> 8) * 2u + 1u) * kNB) >> 25);
-    if ((mask >> d) & 1u) {
+    if (((mask >> d) & 1u) && gk > 0) {
+      const double eps = g->eps, cu = u01(e[d]);
+      if (cu >= eps) {
+        const double c2 = (cu - eps) / (1.0 - eps);
+        int k = 0;
+        double acc = g->w[d][0];
+        while (k < gk - 1 && c2 >= acc) {
+          k++;
+          acc += g->w[d][k];
+        }
+        u = g->mu[d][k] + g->sd[d][k] * normcdfinv(g->ca[d][k] + v * g->z[d][k]);
+        u = fmin(fmax(u, 0.0), 1.0 - 0x1p-53);
+      }
+      double s = 0.0;
+      for (int k = 0; k < gk; k++) {
+        if (g->w[d][k] > 0.0) {
+          const double t = (u - g->mu[d][k]) / g->sd[d][k];
+          s += g->w[d][k] * exp(-0.5 * t * t) / (g->sd[d][k] * g->z[d][k] * kSqrt2Pi);
+        }
+      }
+      lr -= log(eps + (1.0 - eps) * s);
+      bin = (uint32_t)min((int)(u * kNB), kNB - 1);
+    } else if ((mask >> d) & 1u) {
       int lo = 0, hi = kNB;
       while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;
@@ -93,6 +149,7 @@ __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned 
       bin = (uint32_t)lo;
     }
     if (d < 2) us[d] = u;
+    if (ubuf) ubuf[d * bin_stride + col] = (float)u;
     theta[d * stride + col] = prior_inv<R>(d, u, d_min, d_max, tau_width);
     if (bins) bins[d * bin_stride + col] = (uint8_t)bin;
   }
@@ -109,16 +166,19 @@ template <typename R>
 __global__ void __launch_bounds__(256) sample_kernel(const ProposalDev *prop, const PointDev *pt, uint32_t point,
                                                      uint64_t seed, uint32_t round, int64_t first, int64_t n,
                                                      int64_t stride, int64_t bin_stride, double d_min, double d_max,
-                                                     double tau_width, R *theta, R *ln_ratio, uint8_t *bins) {
+                                                     double tau_width, R *theta, R *ln_ratio, uint8_t *bins,
+                                                     float *ubuf) {
   __shared__ double cdf[7][kNB + 1];
   __shared__ unsigned mask;
+  __shared__ GmmSh g;
   for (int i = threadIdx.x; i < 7 * (kNB + 1); i += blockDim.x) cdf[i / (kNB + 1)][i % (kNB + 1)] = prop->cdf[i / (kNB + 1)][i % (kNB + 1)];
   if (threadIdx.x == 0) mask = prop->mask;
+  gmm_stage(prop, g);
   __syncthreads();
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  draw_one<R>(cdf, mask, point, seed, round, (uint64_t)(first + j), d_min, d_max, tau_width, pt, theta, stride,
-              ln_ratio, bins, bin_stride, j);
+  draw_one<R>(cdf, mask, &g, point, seed, round, (uint64_t)(first + j), d_min, d_max, tau_width, pt, theta, stride,
+              ln_ratio, bins, bin_stride, j, ubuf);
 }
 
 // every point of a round in one launch: blocks [blk0[p], blk0[p + 1]) draw
@@ -129,9 +189,10 @@ __global__ void __launch_bounds__(256) sample_multi_kernel(const ProposalDev *pr
                                                            const int64_t *cnt, uint64_t seed, uint32_t round,
                                                            int64_t stride, int64_t bin_stride, double d_min,
                                                            double d_max, double tau_width, R *theta, R *ln_ratio,
-                                                           uint8_t *bins) {
+                                                           uint8_t *bins, float *ubuf) {
   __shared__ double cdf[7][kNB + 1];
   __shared__ unsigned mask;
+  __shared__ GmmSh g;
   int lo = 0, hi = np;  // blk0[lo] <= blockIdx.x < blk0[hi]
   while (hi - lo > 1) {
     int mid = (lo + hi) >> 1;
@@ -141,21 +202,22 @@ __global__ void __launch_bounds__(256) sample_multi_kernel(const ProposalDev *pr
   const ProposalDev *prop = props + p;
   for (int i = threadIdx.x; i < 7 * (kNB + 1); i += blockDim.x) cdf[i / (kNB + 1)][i % (kNB + 1)] = prop->cdf[i / (kNB + 1)][i % (kNB + 1)];
   if (threadIdx.x == 0) mask = prop->mask;
+  gmm_stage(prop, g);
   __syncthreads();
   const int64_t j = (int64_t)(blockIdx.x - blk0[p]) * blockDim.x + threadIdx.x;
   if (j >= cnt[p]) return;
-  draw_one<R>(cdf, mask, (uint32_t)p, seed, round, (uint64_t)j, d_min, d_max, tau_width, pts ? pts + p : nullptr,
-              theta, stride, ln_ratio, bins, bin_stride, off[p] + j);
+  draw_one<R>(cdf, mask, &g, (uint32_t)p, seed, round, (uint64_t)j, d_min, d_max, tau_width, pts ? pts + p : nullptr,
+              theta, stride, ln_ratio, bins, bin_stride, off[p] + j, ubuf);
 }
 
 template <typename R>
 hipError_t sample_launch(const PointDev *pt, const ProposalDev *prop, int point, uint64_t seed, uint32_t round,
                          int64_t first, int64_t n, int64_t stride, int64_t bin_stride, double d_min, double d_max,
-                         double tau_width, R *theta, R *ln_ratio, uint8_t *bins, hipStream_t st) {
+                         double tau_width, R *theta, R *ln_ratio, uint8_t *bins, hipStream_t st, float *ubuf) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(sample_kernel<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, prop, pt,
                      (uint32_t)point, seed, round, first, n, stride, bin_stride, d_min, d_max, tau_width, theta,
-                     ln_ratio, bins);
+                     ln_ratio, bins, ubuf);
   return hipGetLastError();
 }
 
@@ -163,26 +225,26 @@ template <typename R>
 hipError_t sample_multi_launch(const ProposalDev *props, const PointDev *pts, const int *blk0, int n_blocks, int np,
                                const int64_t *off, const int64_t *cnt, uint64_t seed, uint32_t round, int64_t stride,
                                int64_t bin_stride, double d_min, double d_max, double tau_width, R *theta,
-                               R *ln_ratio, uint8_t *bins, hipStream_t st) {
+                               R *ln_ratio, uint8_t *bins, hipStream_t st, float *ubuf) {
   if (n_blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(sample_multi_kernel<R>, dim3((unsigned)n_blocks), dim3(256), 0, st, props, pts, blk0, np, off,
-                     cnt, seed, round, stride, bin_stride, d_min, d_max, tau_width, theta, ln_ratio, bins);
+                     cnt, seed, round, stride, bin_stride, d_min, d_max, tau_width, theta, ln_ratio, bins, ubuf);
   return hipGetLastError();
 }
 template hipError_t sample_multi_launch<float>(const ProposalDev *, const PointDev *, const int *, int, int,
                                                const int64_t *,
                                                const int64_t *, uint64_t, uint32_t, int64_t, int64_t, double, double,
-                                               double, float *, float *, uint8_t *, hipStream_t);
+                                               double, float *, float *, uint8_t *, hipStream_t, float *);
 template hipError_t sample_multi_launch<double>(const ProposalDev *, const PointDev *, const int *, int, int,
                                                 const int64_t *,
                                                 const int64_t *, uint64_t, uint32_t, int64_t, int64_t, double, double,
-                                                double, double *, double *, uint8_t *, hipStream_t);
+                                                double, double *, double *, uint8_t *, hipStream_t, float *);
 template hipError_t sample_launch<float>(const PointDev *, const ProposalDev *, int, uint64_t, uint32_t, int64_t,
                                          int64_t, int64_t, int64_t, double, double, double, float *, float *,
-                                         uint8_t *, hipStream_t);
+                                         uint8_t *, hipStream_t, float *);
 template hipError_t sample_launch<double>(const PointDev *, const ProposalDev *, int, uint64_t, uint32_t, int64_t,
                                           int64_t, int64_t, int64_t, double, double, double, double *, double *,
-                                          uint8_t *, hipStream_t);
+                                          uint8_t *, hipStream_t, float *);
 
 // ---------------------------------------------------------------------------
 // FP64 reduction
@@ -394,7 +456,10 @@ __global__ void cdf_kernel(const unsigned long long *hist, int bps, const int *s
     P.cdf[d][b + 1] = c;
   }
   for (int b = 1; b <= kNB; b++) P.cdf[d][b] /= c;
-  if (d == 0) P.mask = mask;
+  if (d == 0) {
+    P.mask = mask;
+    P.gk = 0;  // histogram proposal
+  }
 }
 
 int hist_blocks(int64_t max_count) { return (int)std::max<int64_t>(1, (max_count + kHistChunk - 1) / kHistChunk); }
@@ -417,6 +482,254 @@ template hipError_t adapt_launch<float>(const uint8_t *, int64_t, const float *,
 template hipError_t adapt_launch<double>(const uint8_t *, int64_t, const double *, const int64_t *, const int64_t *,
                                          const int *, int, int, const ReduceTuple *, unsigned long long *,
                                          ProposalDev *, unsigned, double, hipStream_t, const double *, double);
+
+// ---------------------------------------------------------------------------
+// Gaussian-mixture adaptation (Sec. III.B; App. A): weighted EM in each
+// adapted parameter's prior-CDF coordinate, then the online update.  Sums are
+// FP64 in a fixed order (each block a fixed range of samples, a fixed tree
+// over its threads, blocks merged in block order), so results do not depend
+// on scheduling.
+// ---------------------------------------------------------------------------
+constexpr int kEmChunk = 8192;
+constexpr double kSdMin = 1e-4;
+int em_blocks(int64_t max_count) { return (int)std::max<int64_t>(1, (max_count + kEmChunk - 1) / kEmChunk); }
+
+__device__ __forceinline__ double phi_cdf(double x) { return 0.5 * erfc(-x * 0.70710678118654752440); }
+
+// the mixture a round starts from: the point's own when it has K components,
+// else the initial one (equal weights, means (k + 1/2) / K, sd 1 / (2 K))
+__global__ void gmm_init_kernel(const ProposalDev *props, const int *seg_prop, int n_seg, int K, GmmDev *cur,
+                                GmmDev *fit) {
+  const int seg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (seg >= n_seg) return;
+  const ProposalDev &P = props[seg_prop[seg]];
+  const bool own = P.gk == K;
+  GmmDev &c = cur[seg], &f = fit[seg];
+  c.k = f.k = K;
+  c.pad_ = f.pad_ = 0;
+  c.ntr = f.ntr = own ? P.gntr : 0.0;
+  for (int d = 0; d < 7; d++)
+    for (int k = 0; k < kMaxG; k++) {
+      c.w[d][k] = f.w[d][k] = own ? P.gw[d][k] : (k < K ? 1.0 / K : 0.0);
+      c.mu[d][k] = f.mu[d][k] = own ? P.gmu[d][k] : (k + 0.5) / K;
+      c.sd[d][k] = f.sd[d][k] = own ? P.gsd[d][k] : 0.5 / K;
+    }
+}
+
+// E-step and the M-step sums of one block: for each adapted d and component
+// k, S0 = sum w r, S1 = sum w r (u - mu_k), S2 = sum w r (u - mu_k)^2 with
+// w = e^{ln w - max ln w} and r the responsibility (untruncated normals)
+template <typename R>
+__global__ void __launch_bounds__(256) em_partials_kernel(const float *ub, int64_t us, const R *lnw,
+                                                          const int64_t *seg_off, const int64_t *seg_cnt, int bps,
+                                                          const ReduceTuple *seg_round, const GmmDev *fit,
+                                                          unsigned mask, double *part) {
+  __shared__ double red[256][3 * kMaxG];
+  const int seg = blockIdx.x / bps, j = blockIdx.x % bps;
+  const int64_t cnt = seg_cnt[seg], off = seg_off[seg];
+  const int64_t lo = min(cnt, (int64_t)j * kEmChunk), hi = min(cnt, lo + kEmChunk);
+  const double mx = seg_round[seg].m;
+  const GmmDev &F = fit[seg];
+  const int K = F.k;
+  for (int d = 0; d < 7; d++) {
+    if (!((mask >> d) & 1u)) continue;
+    double acc[3 * kMaxG];
+    double lw[kMaxG], mu[kMaxG], isd[kMaxG];
+#pragma unroll
+    for (int q = 0; q < 3 * kMaxG; q++) acc[q] = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxG; k++) {
+      lw[k] = (k < K && F.w[d][k] > 0.0) ? log(F.w[d][k]) - log(F.sd[d][k]) : -INFINITY;
+      mu[k] = F.mu[d][k];
+      isd[k] = 1.0 / F.sd[d][k];
+    }
+    if (mx > -INFINITY) {
+      for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+        const double x = (double)lnw[off + i];
+        if (!(x == x) || x == INFINITY || x == -INFINITY) continue;
+        const double wt = exp(x - mx);
+        const double uu = (double)ub[d * us + off + i];
+        double lp[kMaxG], m = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < kMaxG; k++) {
+          const double t = (uu - mu[k]) * isd[k];
+          lp[k] = lw[k] - 0.5 * t * t;
+          m = fmax(m, lp[k]);
+        }
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < kMaxG; k++) {
+          lp[k] = lw[k] == -INFINITY ? 0.0 : exp(lp[k] - m);
+          sum += lp[k];
+        }
+#pragma unroll
+        for (int k = 0; k < kMaxG; k++) {
+          const double r = wt * (lp[k] / sum), dk = uu - mu[k];
+          acc[3 * k] += r;
+          acc[3 * k + 1] += r * dk;
+          acc[3 * k + 2] += r * dk * dk;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 3 * kMaxG; q++) red[threadIdx.x][q] = acc[q];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o)
+#pragma unroll
+        for (int q = 0; q < 3 * kMaxG; q++) red[threadIdx.x][q] += red[threadIdx.x + o][q];
+      __syncthreads();
+    }
+    if (threadIdx.x < 3 * kMaxG) part[(((size_t)seg * bps + j) * 7 + d) * 3 * kMaxG + threadIdx.x] = red[0][threadIdx.x];
+    __syncthreads();
+  }
+}
+
+// M-step: merge the blocks' sums in block order, new weights, means, sds
+__global__ void em_update_kernel(const double *part, int n_seg, int bps, GmmDev *fit, unsigned mask) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_seg * 7) return;
+  const int seg = idx / 7, d = idx % 7;
+  if (!((mask >> d) & 1u)) return;
+  GmmDev &F = fit[seg];
+  const int K = F.k;
+  double S[3 * kMaxG];
+  for (int q = 0; q < 3 * kMaxG; q++) S[q] = 0.0;
+  for (int j = 0; j < bps; j++)
+    for (int q = 0; q < 3 * kMaxG; q++) S[q] += part[(((size_t)seg * bps + j) * 7 + d) * 3 * kMaxG + q];
+  double tot = 0.0;
+  for (int k = 0; k < K; k++) tot += S[3 * k];
+  if (!(tot > 0.0)) return;
+  for (int k = 0; k < K; k++) {
+    const double s0 = S[3 * k];
+    if (s0 > 0.0) {
+      const double m1 = S[3 * k + 1] / s0, m2 = S[3 * k + 2] / s0;
+      F.mu[d][k] += m1;
+      F.sd[d][k] = fmax(sqrt(fmax(m2 - m1 * m1, 0.0)), kSdMin);
+    }
+    F.w[d][k] = s0 / tot;
+  }
+}
+
+__device__ bool next_perm(int *p, int n) {
+  int i = n - 2;
+  while (i >= 0 && p[i] >= p[i + 1]) i--;
+  if (i < 0) return false;
+  int j = n - 1;
+  while (p[j] <= p[i]) j--;
+  int t = p[i];
+  p[i] = p[j];
+  p[j] = t;
+  for (int a = i + 1, b = n - 1; a < b; a++, b--) {
+    t = p[a];
+    p[a] = p[b];
+    p[b] = t;
+  }
+  return true;
+}
+
+// online update (App. A): new component i is matched to old component p[i]
+// by the smallest summed symmetric Mahalanobis distance over all
+// permutations (the first minimum in lexicographic order), then combined
+// with the sample counts N (earlier rounds) and M (this round)
+__global__ void gmm_merge_kernel(const GmmDev *cur, const GmmDev *fit, int n_seg, const int *seg_prop,
+                                 const ReduceTuple *seg_round, ProposalDev *props, unsigned mask, double eps) {
+  const int seg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (seg >= n_seg) return;
+  const GmmDev &C = cur[seg], &F = fit[seg];
+  ProposalDev &P = props[seg_prop[seg]];
+  const int K = C.k;
+  const bool any = seg_round[seg].m > -INFINITY;
+  const double N = C.ntr, M = (double)seg_round[seg].n;
+  for (int d = 0; d < 7; d++) {
+    for (int k = 0; k < kMaxG; k++) {
+      P.gw[d][k] = C.w[d][k];
+      P.gmu[d][k] = C.mu[d][k];
+      P.gsd[d][k] = C.sd[d][k];
+    }
+    if (!any || !((mask >> d) & 1u)) continue;
+    if (!(N > 0.0)) {
+      for (int k = 0; k < K; k++) {
+        P.gw[d][k] = F.w[d][k];
+        P.gmu[d][k] = F.mu[d][k];
+        P.gsd[d][k] = F.sd[d][k];
+      }
+      continue;
+    }
+    int p[kMaxG], bp[kMaxG];
+    for (int k = 0; k < K; k++) p[k] = bp[k] = k;
+    double best = INFINITY;
+    do {
+      double s = 0.0;
+      for (int i = 0; i < K; i++) {
+        const double dd = fabs(F.mu[d][i] - C.mu[d][p[i]]);
+        s += dd / F.sd[d][i] + dd / C.sd[d][p[i]];
+      }
+      if (s < best) {
+        best = s;
+        for (int k = 0; k < K; k++) bp[k] = p[k];
+      }
+    } while (next_perm(p, K));
+    for (int i = 0; i < K; i++) {
+      const int jj = bp[i];
+      const double a = N * C.w[d][jj], b = M * F.w[d][i];
+      if (!(a + b > 0.0)) {
+        P.gw[d][jj] = 0.0;
+        continue;
+      }
+      const double mu = (a * C.mu[d][jj] + b * F.mu[d][i]) / (a + b), dm = C.mu[d][jj] - F.mu[d][i];
+      const double var = (a * C.sd[d][jj] * C.sd[d][jj] + b * F.sd[d][i] * F.sd[d][i]) / (a + b) +
+                         a * b * dm * dm / ((a + b) * (a + b));
+      P.gmu[d][jj] = mu;
+      P.gsd[d][jj] = fmax(sqrt(var), kSdMin);
+      P.gw[d][jj] = (a + b) / (N + M);
+    }
+  }
+  for (int d = 0; d < 7; d++)
+    for (int k = 0; k < kMaxG; k++) {
+      const double ca = phi_cdf(-P.gmu[d][k] / P.gsd[d][k]);
+      P.gca[d][k] = ca;
+      P.gz[d][k] = phi_cdf((1.0 - P.gmu[d][k]) / P.gsd[d][k]) - ca;
+    }
+  P.gk = K;
+  P.gntr = any ? N + M : N;
+  P.geps = eps;
+  P.mask = mask;
+}
+
+template <typename R>
+hipError_t gmm_adapt_launch(const float *ubuf, int64_t u_stride, const R *lnw, const int64_t *seg_off,
+                            const int64_t *seg_cnt, const int *seg_prop, int n_seg, int bps,
+                            const ReduceTuple *seg_round, double *part, GmmDev *fit, ProposalDev *props,
+                            unsigned mask, double floor_eps, int K, int n_iter, hipStream_t st) {
+  if (n_seg <= 0) return hipSuccess;
+  const dim3 g1((n_seg + 63) / 64), g7((n_seg * 7 + 63) / 64);
+  hipLaunchKernelGGL(gmm_init_kernel, g1, dim3(64), 0, st, props, seg_prop, n_seg, K, fit, fit + n_seg);
+  for (int it = 0; it < n_iter; it++) {
+    hipLaunchKernelGGL(em_partials_kernel<R>, dim3(n_seg * bps), dim3(256), 0, st, ubuf, u_stride, lnw, seg_off,
+                       seg_cnt, bps, seg_round, fit + n_seg, mask, part);
+    hipLaunchKernelGGL(em_update_kernel, g7, dim3(64), 0, st, part, n_seg, bps, fit + n_seg, mask);
+  }
+  hipLaunchKernelGGL(gmm_merge_kernel, g1, dim3(64), 0, st, fit, fit + n_seg, n_seg, seg_prop, seg_round, props, mask,
+                     floor_eps);
+  return hipGetLastError();
+}
+template hipError_t gmm_adapt_launch<float>(const float *, int64_t, const float *, const int64_t *, const int64_t *,
+                                            const int *, int, int, const ReduceTuple *, double *, GmmDev *,
+                                            ProposalDev *, unsigned, double, int, int, hipStream_t);
+template hipError_t gmm_adapt_launch<double>(const float *, int64_t, const double *, const int64_t *,
+                                             const int64_t *, const int *, int, int, const ReduceTuple *, double *,
+                                             GmmDev *, ProposalDev *, unsigned, double, int, int, hipStream_t);
+
+// host: the same normalizations for a mixture set by the caller
+void gmm_norms(ProposalDev &p) {
+  for (int d = 0; d < 7; d++)
+    for (int k = 0; k < kMaxG; k++) {
+      const double ca = 0.5 * std::erfc(p.gmu[d][k] / p.gsd[d][k] * 0.70710678118654752440);
+      p.gca[d][k] = ca;
+      p.gz[d][k] = 0.5 * std::erfc(-(1.0 - p.gmu[d][k]) / p.gsd[d][k] * 0.70710678118654752440) - ca;
+    }
+}
 
 // ---------------------------------------------------------------------------
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {

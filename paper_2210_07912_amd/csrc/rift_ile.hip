@@ -46,7 +46,7 @@ struct rift_ile {
   int n_cu = 0;
   int lds_max = 65536;
   // grow-only workspace, indexed by name
-  DevBuf ws[40];
+  DevBuf ws[48];
   // side streams for concurrent class kernels, and the workspace budget
   Fanout fan{};
   // captured evaluation runs: key (launch arguments and class layout) -> graph
@@ -73,9 +73,9 @@ enum WsId {
   W_ITEM_POINT, W_ITEM_OFF, W_ITEM_CNT, W_ITEM_TILE0, W_ITEM_SAMP0, W_ITEM_BIN0,
   W_KEY, W_NSH, W_COUNT, W_CURSOR, W_COP, W_BINTILE, W_ITEMTILES, W_PERM, W_TILES, W_CTL, W_CTILE,
   W_PARTIALS, W_ROUND, W_ACCUM, W_RESULT, W_HIST, W_THETA, W_LNW, W_AUX, W_RATIO, W_BINS, W_ITEM_BLK0,
-  W_ITEM_HOFF, W_ITEM_COP, W_SEG_OFF, W_SEG_CNT, W_ASC, W_AHIST, W_UNIT, W_BINUNIT, W_ITEMUNITS, W_GOP, W_HOP, W_SEG_BLK, W_COUNT_IDS
+  W_ITEM_HOFF, W_ITEM_COP, W_SEG_OFF, W_SEG_CNT, W_ASC, W_AHIST, W_UNIT, W_BINUNIT, W_ITEMUNITS, W_GOP, W_HOP, W_SEG_BLK, W_UBUF, W_EMPART, W_GMMFIT, W_COUNT_IDS
 };
-static_assert(W_COUNT_IDS <= 40, "workspace table too small");
+static_assert(W_COUNT_IDS <= 48, "workspace table too small");
 
 rift_status fail(rift_ile *h, rift_status s, const char *fmt, ...) {
   char buf[512];
@@ -375,10 +375,9 @@ rift_status build_point(rift_ile *h, const rift_ile_point &q, PointDev &p) {
 }
 
 void uniform_proposal(ProposalDev &pr) {
+  std::memset(&pr, 0, sizeof pr);  // no mixture (gk = 0)
   for (int d = 0; d < 7; d++)
     for (int b = 0; b <= kNB; b++) pr.cdf[d][b] = (double)b / kNB;
-  pr.mask = 0;
-  pr.pad_ = 0;
 }
 
 // ---- evaluation -------------------------------------------------------------
@@ -814,6 +813,27 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
   const double beta = mc->ascent_mix > 0.0 ? mc->ascent_mix : 0.3;
   if (grad && (ka > 256 || !(beta + mc->floor_eps < 1.0)))
     return fail(h, RIFT_E_INVALID, "n_ascent %d (<= 256) or ascent_mix %g (< 1 - floor_eps)", ka, beta);
+  // Gaussian-mixture proposal: prior-CDF coordinates of every sample, EM sums
+  // and the mixtures being fitted
+  const int gk = mc->gmm_components;
+  const int giter = mc->gmm_iters > 0 ? mc->gmm_iters : 10;
+  if (gk < 0 || gk > kMaxG || mc->gmm_iters < 0 || mc->gmm_iters > 1000 || (gk > 0 && grad))
+    return fail(h, RIFT_E_INVALID, "gmm_components %d (0..%d), gmm_iters %d (0..1000), or both a mixture and the "
+                "gradient refinement", gk, kMaxG, mc->gmm_iters);
+  const bool gmm = gk > 0 && mc->adapt_mask;
+  float *ubuf = nullptr;
+  double *em_part = nullptr;
+  GmmDev *em_fit = nullptr;
+  const int ebps = em_blocks(mxc);
+  if (gmm) {
+    void *pu, *pp, *pf;
+    if ((s = ws_get(h, W_UBUF, 7 * sizeof(float) * (size_t)nr, &pu)) != RIFT_OK) return s;
+    if ((s = ws_get(h, W_EMPART, sizeof(double) * 7 * 3 * kMaxG * (size_t)np * ebps, &pp)) != RIFT_OK) return s;
+    if ((s = ws_get(h, W_GMMFIT, 2 * sizeof(GmmDev) * (size_t)np, &pf)) != RIFT_OK) return s;
+    ubuf = (float *)pu;
+    em_part = (double *)pp;
+    em_fit = (GmmDev *)pf;
+  }
   const int na = np * ka;
   int *a_idx = nullptr;
   R *a_th = nullptr, *a_g = nullptr, *a_l = nullptr;
@@ -856,7 +876,7 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
     HIPCHK(h, sample_multi_launch<R>(h->d_props, h->net_frame ? h->d_pts : nullptr, d_sblk, sblk[np], np, d_soff,
                                      d_scnt, mc->seed, (uint32_t)r,
                                      th_stride, nr, h->d_min, h->d_max, h->tau_width, th, (R *)ratio,
-                                     (uint8_t *)bins, h->stream));
+                                     (uint8_t *)bins, h->stream, ubuf));
     if ((s = eval<R>(h, it, th_stride, th, nullptr, lw, (const R *)ratio)) != RIFT_OK) return s;
     ReduceTuple *round;
     const bool last = r + 1 == mc->n_rounds;
@@ -880,9 +900,13 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
         HIPCHK(h, ascent_hist(a_st, ka, np, mc->adapt_mask, h->d_min, h->d_max, h->tau_width,
                               h->net_frame ? h->d_pts : nullptr, ahist, h->stream));
       }
-      HIPCHK(h, adapt_launch<R>((const uint8_t *)bins, nr, lw, d_soff, d_scnt, d_prop, np, hbps, round,
-                                (unsigned long long *)hist, h->d_props, mc->adapt_mask, mc->floor_eps, h->stream,
-                                grad ? ahist : nullptr, grad ? beta : 0.0));
+      if (gmm)
+        HIPCHK(h, gmm_adapt_launch<R>(ubuf, nr, lw, d_soff, d_scnt, d_prop, np, ebps, round, em_part, em_fit,
+                                      h->d_props, mc->adapt_mask, mc->floor_eps, gk, giter, h->stream));
+      else
+        HIPCHK(h, adapt_launch<R>((const uint8_t *)bins, nr, lw, d_soff, d_scnt, d_prop, np, hbps, round,
+                                  (unsigned long long *)hist, h->d_props, mc->adapt_mask, mc->floor_eps, h->stream,
+                                  grad ? ahist : nullptr, grad ? beta : 0.0));
     }
   }
   HIPCHK(h, hipMemcpyAsync(out, d_res, sizeof(rift_ile_result) * np, hipMemcpyDeviceToHost, h->stream));
@@ -1243,6 +1267,7 @@ rift_status rift_ile_set_proposal(rift_ile *h, int point, const double *cdf, uns
   if (point < 0 || point >= h->n_points || !cdf || (mask >> 7))
     return fail(h, RIFT_E_INVALID, "bad set_proposal arguments");
   ProposalDev pr;
+  std::memset(&pr, 0, sizeof pr);
   for (int d = 0; d < 7; d++) {
     const double *c = cdf + d * (kNB + 1);
     if (c[0] != 0.0 || c[kNB] != 1.0) return fail(h, RIFT_E_INVALID, "cdf[%d] must run from 0 to 1", d);
@@ -1251,8 +1276,96 @@ rift_status rift_ile_set_proposal(rift_ile *h, int point, const double *cdf, uns
     std::memcpy(pr.cdf[d], c, sizeof(double) * (kNB + 1));
   }
   pr.mask = mask;
-  pr.pad_ = 0;
   HIPCHK(h, hipMemcpy(h->d_props + point, &pr, sizeof(pr), hipMemcpyHostToDevice));
+  return RIFT_OK;
+}
+
+rift_status rift_ile_get_gmm(rift_ile *h, int point, int *K, unsigned *mask, double *floor_eps, double *n_trained,
+                             double *w, double *mu, double *sd) {
+  if (!h) return RIFT_E_INVALID;
+  if (point < 0 || point >= h->n_points || !K) return fail(h, RIFT_E_INVALID, "bad get_gmm arguments");
+  ProposalDev pr;
+  HIPCHK(h, hipMemcpyAsync(&pr, h->d_props + point, sizeof(pr), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  *K = pr.gk;
+  if (mask) *mask = pr.mask;
+  if (floor_eps) *floor_eps = pr.geps;
+  if (n_trained) *n_trained = pr.gntr;
+  for (int d = 0; d < 7; d++)
+    for (int k = 0; k < kMaxG; k++) {
+      if (w) w[d * kMaxG + k] = pr.gw[d][k];
+      if (mu) mu[d * kMaxG + k] = pr.gmu[d][k];
+      if (sd) sd[d * kMaxG + k] = pr.gsd[d][k];
+    }
+  return RIFT_OK;
+}
+
+rift_status rift_ile_set_gmm(rift_ile *h, int point, int K, unsigned mask, double floor_eps, double n_trained,
+                             const double *w, const double *mu, const double *sd) {
+  if (!h) return RIFT_E_INVALID;
+  if (point < 0 || point >= h->n_points || K < 1 || K > kMaxG || (mask >> 7) || !w || !mu || !sd)
+    return fail(h, RIFT_E_INVALID, "bad set_gmm arguments");
+  if (!(floor_eps >= 0.0 && floor_eps <= 1.0) || !(n_trained >= 0.0))
+    return fail(h, RIFT_E_INVALID, "floor_eps %g or n_trained %g", floor_eps, n_trained);
+  ProposalDev pr;
+  uniform_proposal(pr);
+  for (int d = 0; d < 7; d++) {
+    double tot = 0.0;
+    for (int k = 0; k < kMaxG; k++) {
+      const double wk = k < K ? w[d * kMaxG + k] : 0.0, m = k < K ? mu[d * kMaxG + k] : 0.5,
+                   s = k < K ? sd[d * kMaxG + k] : 0.5;
+      if (!(wk >= 0.0) || !(m >= 0.0 && m <= 1.0) || !(s > 0.0) || !std::isfinite(s))
+        return fail(h, RIFT_E_INVALID, "component %d of parameter %d", k, d);
+      pr.gw[d][k] = wk;
+      pr.gmu[d][k] = m;
+      pr.gsd[d][k] = s;
+      tot += wk;
+    }
+    if (((mask >> d) & 1u) && !(std::fabs(tot - 1.0) < 1e-9))
+      return fail(h, RIFT_E_INVALID, "weights of parameter %d sum to %g", d, tot);
+  }
+  gmm_norms(pr);
+  pr.gk = K;
+  pr.mask = mask;
+  pr.geps = floor_eps;
+  pr.gntr = n_trained;
+  HIPCHK(h, hipMemcpy(h->d_props + point, &pr, sizeof(pr), hipMemcpyHostToDevice));
+  return RIFT_OK;
+}
+
+rift_status rift_ile_adapt_gmm(rift_ile *h, int point, int64_t n, const float *u, const void *lnw, unsigned mask,
+                               double floor_eps, int K, int n_iter) {
+  if (!h) return RIFT_E_INVALID;
+  if (point < 0 || point >= h->n_points) return fail(h, RIFT_E_INVALID, "point %d", point);
+  if (n < 0 || (n > 0 && (!u || !lnw))) return fail(h, RIFT_E_INVALID, "bad adapt_gmm arguments");
+  if (!(floor_eps > 0.0 && floor_eps <= 1.0)) return fail(h, RIFT_E_INVALID, "floor_eps %g", floor_eps);
+  if ((mask >> 7) || K < 1 || K > kMaxG || n_iter < 1 || n_iter > 1000)
+    return fail(h, RIFT_E_INVALID, "mask 0x%x, K %d (1..%d) or n_iter %d (1..1000)", mask, K, kMaxG, n_iter);
+  std::vector<int64_t> off(1, 0), cnt(1, n);
+  std::vector<int> sp(1, point);
+  ReduceTuple *round;
+  rift_status s;
+  int *d_sp;
+  void *part, *fit;
+  const int bps = em_blocks(n);
+  if ((s = ws_get(h, W_EMPART, sizeof(double) * 7 * 3 * kMaxG * bps, &part)) != RIFT_OK) return s;
+  if ((s = ws_get(h, W_GMMFIT, 2 * sizeof(GmmDev), &fit)) != RIFT_OK) return s;
+  if (h->precision == RIFT_FP32) {
+    if ((s = reduce_segments<float>(h, (const float *)lnw, nullptr, off, cnt, &round, nullptr, 0, nullptr)) != RIFT_OK)
+      return s;
+    if ((s = upload(h, W_AUX, sp, &d_sp)) != RIFT_OK) return s;
+    int64_t *d_off = (int64_t *)h->ws[W_ITEM_OFF].p, *d_cnt = (int64_t *)h->ws[W_ITEM_CNT].p;
+    HIPCHK(h, gmm_adapt_launch<float>(u, n, (const float *)lnw, d_off, d_cnt, d_sp, 1, bps, round, (double *)part,
+                                      (GmmDev *)fit, h->d_props, mask, floor_eps, K, n_iter, h->stream));
+  } else {
+    if ((s = reduce_segments<double>(h, (const double *)lnw, nullptr, off, cnt, &round, nullptr, 0, nullptr)) !=
+        RIFT_OK)
+      return s;
+    if ((s = upload(h, W_AUX, sp, &d_sp)) != RIFT_OK) return s;
+    int64_t *d_off = (int64_t *)h->ws[W_ITEM_OFF].p, *d_cnt = (int64_t *)h->ws[W_ITEM_CNT].p;
+    HIPCHK(h, gmm_adapt_launch<double>(u, n, (const double *)lnw, d_off, d_cnt, d_sp, 1, bps, round, (double *)part,
+                                       (GmmDev *)fit, h->d_props, mask, floor_eps, K, n_iter, h->stream));
+  }
   return RIFT_OK;
 }
 

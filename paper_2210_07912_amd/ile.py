@@ -65,10 +65,12 @@ class MC(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("n_per_round", C.c_int64), ("n_per_point", C.POINTER(C.c_int64)),
                 ("n_rounds", C.c_int), ("adapt_mask", C.c_uint), ("floor_eps", C.c_double),
                 ("reset_proposal", C.c_int), ("flags", C.c_uint), ("n_ascent", C.c_int),
-                ("ascent_steps", C.c_int), ("ascent_mix", C.c_double)]
+                ("ascent_steps", C.c_int), ("ascent_mix", C.c_double), ("gmm_components", C.c_int),
+                ("gmm_iters", C.c_int)]
 
 
 RIFT_MC_GRADIENT = 1
+GMM_MAX = 4  # mixture components per parameter
 
 
 FUNCTIONS = {
@@ -93,6 +95,13 @@ FUNCTIONS = {
     "rift_ile_adapt": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_uint, C.c_double]),
     "rift_ile_get_proposal": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_uint)]),
     "rift_ile_set_proposal": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_uint]),
+    "rift_ile_get_gmm": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_uint),
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "rift_ile_set_gmm": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_uint, C.c_double, C.c_double,
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "rift_ile_adapt_gmm": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_uint,
+                                     C.c_double, C.c_int, C.c_int]),
     "rift_ile_marginalize": (C.c_int, [C.c_void_p, C.POINTER(MC), C.POINTER(Result), C.c_void_p, C.c_void_p]),
     "rift_ile_backward": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(Item), C.c_int64, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p]),
@@ -272,11 +281,36 @@ class RiftILE:
         cdf = np.ascontiguousarray(cdf, dtype=np.float64)
         self._check(lib().rift_ile_set_proposal(self.h, point, _dptr(cdf), mask))
 
+    def get_gmm(self, point):
+        """Mixture proposal of a point: dict K, mask, floor_eps, n_trained and
+        w, mu, sd [7, 4] (K = 0: the point holds a histogram proposal)."""
+        K, mask, eps, ntr = C.c_int(), C.c_uint(), C.c_double(), C.c_double()
+        w, mu, sd = (np.zeros((NPAR, GMM_MAX)) for _ in range(3))
+        self._check(lib().rift_ile_get_gmm(self.h, point, C.byref(K), C.byref(mask), C.byref(eps), C.byref(ntr),
+                                           _dptr(w), _dptr(mu), _dptr(sd)))
+        return dict(K=K.value, mask=mask.value, floor_eps=eps.value, n_trained=ntr.value, w=w, mu=mu, sd=sd)
+
+    def set_gmm(self, point, K, mask, floor_eps, n_trained, w, mu, sd):
+        arrs = []
+        for a in (w, mu, sd):
+            x = np.zeros((NPAR, GMM_MAX))
+            a = np.asarray(a, dtype=np.float64)
+            x[:, :a.shape[1]] = a
+            arrs.append(np.ascontiguousarray(x))
+        self._check(lib().rift_ile_set_gmm(self.h, point, K, mask, floor_eps, n_trained, *(_dptr(a) for a in arrs)))
+
+    def adapt_gmm(self, point, u, lnw, mask, floor_eps, K, n_iter):
+        u = torch.as_tensor(u, device=self.device, dtype=torch.float32).contiguous()
+        lnw = torch.as_tensor(lnw, device=self.device, dtype=self.dtype).contiguous()
+        self._check(lib().rift_ile_adapt_gmm(self.h, point, lnw.numel(), _ptr(u), _ptr(lnw), mask, floor_eps, K,
+                                             n_iter))
+
     def marginalize(self, seed, n_per_point, n_rounds=1, adapt_mask=0, floor_eps=0.1, reset=True,
-                    return_samples=False, gradient=False, n_ascent=0, ascent_steps=0, ascent_mix=0.0):
+                    return_samples=False, gradient=False, n_ascent=0, ascent_steps=0, ascent_mix=0.0,
+                    gmm_components=0, gmm_iters=0):
         npp = np.ascontiguousarray(np.broadcast_to(np.asarray(n_per_point, dtype=np.int64), (self.n_points,)))
         mc = MC(seed, 0, npp.ctypes.data_as(C.POINTER(C.c_int64)), n_rounds, adapt_mask, floor_eps, int(reset),
-                RIFT_MC_GRADIENT if gradient else 0, n_ascent, ascent_steps, ascent_mix)
+                RIFT_MC_GRADIENT if gradient else 0, n_ascent, ascent_steps, ascent_mix, gmm_components, gmm_iters)
         res = (Result * self.n_points)()
         th = lw = None
         if return_samples:

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 def test_host_only_calls():
     from paper_2210_07912_amd import ile
     L = ile.lib()
-    assert L.rift_ile_abi_version() == 1
+    assert L.rift_ile_abi_version() == 2
     assert L.rift_ile_status_string(0) == b"ok"
     assert L.rift_ile_status_string(-4).startswith(b"pad")
     # create rejects bad descriptors on the host, before touching a device
@@ -50,6 +50,11 @@ def test_host_only_calls():
     assert L.rift_ile_precompute(None, 0, 0, None, None, None) == -1
     assert b"NULL" in L.rift_ile_last_error(None)
     assert L.rift_ile_autotune_table(None, None) == -1
+    assert L.rift_ile_get_gmm(None, 0, None, None, None, None, None, None, None) == -1
+    assert L.rift_ile_set_gmm(None, 0, 1, 1, 0.1, 0.0, None, None, None) == -1
+    assert L.rift_ile_adapt_gmm(None, 0, 0, None, None, 1, 0.1, 1, 1) == -1
+    # the Monte Carlo descriptor matches the binding's layout (mixture fields last)
+    assert ctypes.sizeof(ile.MC) == 72 and ile.MC.gmm_iters.offset == 68
 
 
 def test_binding_refuses_without_device():
