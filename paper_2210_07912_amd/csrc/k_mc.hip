@@ -393,8 +393,8 @@ hipError_t reduce_finish(const ReduceTuple *partials, int n_seg, int bps, Reduce
 // adaptation.  Each block histograms at most kHistChunk samples of one
 // segment in 64-bit fixed point (w = e^{ln w - max} <= 1 scaled by 2^50, so a
 // block's sums stay below 2^63), with integer LDS atomics, which are
-// associative; the block histograms are merged in block order in FP64 by the
-// CDF kernel.  The result does not depend on scheduling.
+// associative; the block histograms are merged in block order in FP64, one
+// thread per bin.  The result does not depend on scheduling.
 // ---------------------------------------------------------------------------
 constexpr double kFix = 1125899906842624.0;  // 2^50
 constexpr int kHistChunk = 8192;
@@ -426,6 +426,17 @@ __global__ void __launch_bounds__(256) hist_kernel(const uint8_t *bins, int64_t 
 
 // h_b = (1 - eps - beta) nb m_b / sum m + beta nb a_b / sum a + eps, with a the
 // histogram of the points reached by the gradient ascent (beta = 0 without)
+// one thread per (segment, parameter, bin): the block histograms summed in
+// block order, in FP64, stored over block 0's entry (read only by this thread)
+__global__ void hist_merge_kernel(unsigned long long *hist, int bps, int n_seg) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_seg * 7 * kNB) return;
+  const int seg = idx / (7 * kNB), db = idx % (7 * kNB);
+  double v = 0.0;
+  for (int j = 0; j < bps; j++) v += (double)hist[((size_t)seg * bps + j) * 7 * kNB + db];
+  hist[(size_t)seg * bps * 7 * kNB + db] = (unsigned long long)__double_as_longlong(v);
+}
+
 __global__ void cdf_kernel(const unsigned long long *hist, int bps, const int *seg_prop, int n_seg,
                            ProposalDev *props, unsigned mask, double floor_eps, const double *ahist, double beta) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -435,8 +446,7 @@ __global__ void cdf_kernel(const unsigned long long *hist, int bps, const int *s
   double m[kNB];
   double tot = 0.0;
   for (int b = 0; b < kNB; b++) {
-    double v = 0.0;
-    for (int j = 0; j < bps; j++) v += (double)hist[((size_t)seg * bps + j) * 7 * kNB + d * kNB + b];
+    const double v = __longlong_as_double((long long)hist[(size_t)seg * bps * 7 * kNB + d * kNB + b]);
     m[b] = v;
     tot += v;
   }
@@ -472,6 +482,7 @@ hipError_t adapt_launch(const uint8_t *bins, int64_t bin_stride, const R *lnw, c
   if (n_seg <= 0) return hipSuccess;
   hipLaunchKernelGGL(hist_kernel<R>, dim3(n_seg * bps), dim3(256), 0, st, bins, bin_stride, lnw, seg_off, seg_cnt, bps,
                      seg_round, hist);
+  hipLaunchKernelGGL(hist_merge_kernel, dim3((n_seg * 7 * kNB + 255) / 256), dim3(256), 0, st, hist, bps, n_seg);
   hipLaunchKernelGGL(cdf_kernel, dim3((n_seg * 7 + 63) / 64), dim3(64), 0, st, hist, bps, seg_prop, n_seg, props, mask,
                      floor_eps, ahist, ascent_mix);
   return hipGetLastError();
@@ -490,7 +501,7 @@ template hipError_t adapt_launch<double>(const uint8_t *, int64_t, const double 
 // over its threads, blocks merged in block order), so results do not depend
 // on scheduling.
 // ---------------------------------------------------------------------------
-constexpr int kEmChunk = 8192;
+constexpr int kEmChunk = 2048;
 constexpr double kSdMin = 1e-4;
 int em_blocks(int64_t max_count) { return (int)std::max<int64_t>(1, (max_count + kEmChunk - 1) / kEmChunk); }
 
