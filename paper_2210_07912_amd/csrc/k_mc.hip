@@ -645,28 +645,26 @@ __device__ bool next_perm(int *p, int n) {
 // with the sample counts N (earlier rounds) and M (this round)
 __global__ void gmm_merge_kernel(const GmmDev *cur, const GmmDev *fit, int n_seg, const int *seg_prop,
                                  const ReduceTuple *seg_round, ProposalDev *props, unsigned mask, double eps) {
-  const int seg = blockIdx.x * blockDim.x + threadIdx.x;
-  if (seg >= n_seg) return;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // one thread per (segment, parameter)
+  if (idx >= n_seg * 7) return;
+  const int seg = idx / 7, d = idx % 7;
   const GmmDev &C = cur[seg], &F = fit[seg];
   ProposalDev &P = props[seg_prop[seg]];
   const int K = C.k;
   const bool any = seg_round[seg].m > -INFINITY;
   const double N = C.ntr, M = (double)seg_round[seg].n;
-  for (int d = 0; d < 7; d++) {
-    for (int k = 0; k < kMaxG; k++) {
-      P.gw[d][k] = C.w[d][k];
-      P.gmu[d][k] = C.mu[d][k];
-      P.gsd[d][k] = C.sd[d][k];
+  for (int k = 0; k < kMaxG; k++) {
+    P.gw[d][k] = C.w[d][k];
+    P.gmu[d][k] = C.mu[d][k];
+    P.gsd[d][k] = C.sd[d][k];
+  }
+  if (any && ((mask >> d) & 1u) && !(N > 0.0)) {
+    for (int k = 0; k < K; k++) {
+      P.gw[d][k] = F.w[d][k];
+      P.gmu[d][k] = F.mu[d][k];
+      P.gsd[d][k] = F.sd[d][k];
     }
-    if (!any || !((mask >> d) & 1u)) continue;
-    if (!(N > 0.0)) {
-      for (int k = 0; k < K; k++) {
-        P.gw[d][k] = F.w[d][k];
-        P.gmu[d][k] = F.mu[d][k];
-        P.gsd[d][k] = F.sd[d][k];
-      }
-      continue;
-    }
+  } else if (any && ((mask >> d) & 1u)) {
     int p[kMaxG], bp[kMaxG];
     for (int k = 0; k < K; k++) p[k] = bp[k] = k;
     double best = INFINITY;
@@ -696,16 +694,17 @@ __global__ void gmm_merge_kernel(const GmmDev *cur, const GmmDev *fit, int n_seg
       P.gw[d][jj] = (a + b) / (N + M);
     }
   }
-  for (int d = 0; d < 7; d++)
-    for (int k = 0; k < kMaxG; k++) {
-      const double ca = phi_cdf(-P.gmu[d][k] / P.gsd[d][k]);
-      P.gca[d][k] = ca;
-      P.gz[d][k] = phi_cdf((1.0 - P.gmu[d][k]) / P.gsd[d][k]) - ca;
-    }
-  P.gk = K;
-  P.gntr = any ? N + M : N;
-  P.geps = eps;
-  P.mask = mask;
+  for (int k = 0; k < kMaxG; k++) {
+    const double ca = phi_cdf(-P.gmu[d][k] / P.gsd[d][k]);
+    P.gca[d][k] = ca;
+    P.gz[d][k] = phi_cdf((1.0 - P.gmu[d][k]) / P.gsd[d][k]) - ca;
+  }
+  if (d == 0) {  // the segment's scalars (no thread reads them here)
+    P.gk = K;
+    P.gntr = any ? N + M : N;
+    P.geps = eps;
+    P.mask = mask;
+  }
 }
 
 template <typename R>
@@ -721,7 +720,7 @@ hipError_t gmm_adapt_launch(const float *ubuf, int64_t u_stride, const R *lnw, c
                        seg_cnt, bps, seg_round, fit + n_seg, mask, part);
     hipLaunchKernelGGL(em_update_kernel, g7, dim3(64), 0, st, part, n_seg, bps, fit + n_seg, mask);
   }
-  hipLaunchKernelGGL(gmm_merge_kernel, g1, dim3(64), 0, st, fit, fit + n_seg, n_seg, seg_prop, seg_round, props, mask,
+  hipLaunchKernelGGL(gmm_merge_kernel, g7, dim3(64), 0, st, fit, fit + n_seg, n_seg, seg_prop, seg_round, props, mask,
                      floor_eps);
   return hipGetLastError();
 }
