@@ -101,10 +101,23 @@ def prior_inv(d, u, d_min, d_max, tau_width):
     return (u - 0.5) * tau_width
 
 
-def draw(seed, point, rnd, n, g: Gmm | None, *, d_min=10.0, d_max=1000.0, tau_width=0.0, start=0):
+def frame_sky(det_pos, gmst, u0, u1):
+    """Sky of the network frame of detectors 0 and 1 (the C oracle's axes):
+    azimuth 2 pi u0 and polar cosine 2 u1 - 1 -> (alpha, delta)."""
+    ax = oracle.network_frame(det_pos)
+    ph, ct = 2.0 * math.pi * u0, 2.0 * u1 - 1.0
+    st = np.sqrt(np.maximum(0.0, 1.0 - ct * ct))
+    n = np.outer(ax[0], st * np.cos(ph)) + np.outer(ax[1], st * np.sin(ph)) + np.outer(ax[2], ct)
+    delta = np.arcsin(np.clip(n[2], -1.0, 1.0))
+    alpha = np.mod(np.arctan2(n[1], n[0]) + gmst, 2.0 * math.pi)
+    return alpha, delta
+
+
+def draw(seed, point, rnd, n, g: Gmm | None, *, d_min=10.0, d_max=1000.0, tau_width=0.0, start=0, frame=None):
     """Samples start..start+n-1 of (point, round) from the mixture proposal
     (prior where g is None or a parameter is outside g.mask): theta [7, n],
-    ln p - ln p_s [n], u [7, n]."""
+    ln p - ln p_s [n], u [7, n].  frame = (det_pos, gmst): the sky drawn in
+    the network frame of detectors 0 and 1."""
     _, _, _, raw = oracle.draw(seed, point, rnd, n, d_min=d_min, d_max=d_max, tau_width=tau_width, start=start)
     v = ((raw.astype(np.float64) // 256) + 0.5) / 16777216.0
     u = v.copy()
@@ -136,6 +149,8 @@ def draw(seed, point, rnd, n, g: Gmm | None, *, d_min=10.0, d_max=1000.0, tau_wi
                 u[d, j] = uu
             lr -= np.log(density(u[d], g.w[d], g.mu[d], g.sd[d], g.eps))
     th = np.stack([prior_inv(d, u[d], d_min, d_max, tau_width) for d in range(7)])
+    if frame is not None:
+        th[ALPHA], th[DELTA] = frame_sky(frame[0], frame[1], u[ALPHA], u[DELTA])
     return th, lr, u
 
 

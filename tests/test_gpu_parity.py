@@ -1051,3 +1051,46 @@ def test_marginalize_gmm_matches_oracle(ile, orc):
             assert abs(res[i]["lnL_marg"] - ref[i]["lnL_marg"]) < 1e-3 + 4 * sig
         h.close()
     h64.close()
+
+
+def test_gmm_draws_in_the_network_frame(ile, orc):
+    """Mixture proposal on the sky dimensions with the sky drawn in the
+    detector-network frame: theta and ln ratio against the oracle."""
+    from oracle import gmm
+    d = synth.make_point(synth.workload("tiny").points[0])
+    g = _gmm_model(gmm)
+    g.mask = 0b0000011
+    g.w[1], g.mu[1], g.sd[1] = [0.5, 0.5, 0.0], [0.3, 0.8, 0.5], [0.1, 0.02, 0.1]
+    n, seed = 4099, 2210079127
+    ref_th, ref_lr, _ = gmm.draw(seed, 0, 1, n, g, frame=(d["det_pos"], d["gmst"]))
+    _say("gmm draws, network frame")
+    h = _handle(ile, [d], "fp64")
+    h.set_network_frame(True)
+    _set_gmm(h, 0, g)
+    th, lr, _ = h.sample(0, seed, 1, n)
+    assert np.abs(th.cpu().numpy() - ref_th).max() < 1e-9
+    assert np.abs(lr.cpu().numpy() - ref_lr).max() < 1e-10
+    h.close()
+
+
+def test_gmm_set_validates(ile):
+    """rift_ile_set_gmm refuses bad mixtures on the host; a histogram
+    proposal set afterwards replaces the mixture."""
+    d = synth.make_point(synth.workload("tiny").points[0])
+    h = _handle(ile, [d], "fp32")
+    w = np.full((7, 2), 0.5)
+    mu = np.full((7, 2), 0.5)
+    sd = np.full((7, 2), 0.1)
+    bad = [dict(K=5), dict(w=np.full((7, 2), 0.4)), dict(mu=np.full((7, 2), 1.5)), dict(sd=np.zeros((7, 2))),
+           dict(eps=1.5), dict(ntr=-1.0), dict(mask=1 << 7)]
+    for b in bad:
+        with pytest.raises(ile.RiftError) as e:
+            h.set_gmm(0, b.get("K", 2), b.get("mask", 0x3F), b.get("eps", 0.1), b.get("ntr", 0.0),
+                      b.get("w", w), b.get("mu", mu), b.get("sd", sd))
+        assert e.value.status == -1
+    h.set_gmm(0, 2, 0x3F, 0.1, 10.0, w, mu, sd)
+    assert h.get_gmm(0)["K"] == 2
+    cdf, _ = h.get_proposal(0)
+    h.set_proposal(0, cdf, 0x3F)
+    assert h.get_gmm(0)["K"] == 0
+    h.close()

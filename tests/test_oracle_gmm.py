@@ -135,3 +135,14 @@ def test_adapt_round_from_the_prior():
     th, lr, u2 = gmm.draw(11, 0, 1, 3000, g1)
     assert np.mean(np.abs(u2[0] - 0.3) < 0.15) > 0.8
     assert abs(np.exp(lr).mean() - 1) < 5 * np.exp(lr).std() / math.sqrt(3000)
+
+
+def test_frame_sky_matches_the_c_oracle(orc):
+    """The numpy network-frame map equals the C oracle's on its own draws
+    (prior draws: the sky uniforms are the raw Philox words)."""
+    import synth
+    d = synth.make_point(synth.workload("tiny").points[0])
+    th, _, _, raw = orc.draw(5, 0, 0, 200, frame=(d["det_pos"], d["gmst"]))
+    v = ((raw.astype(np.float64) // 256) + 0.5) / 16777216.0
+    a, dl = gmm.frame_sky(d["det_pos"], d["gmst"], v[0], v[1])
+    assert np.abs(a - th[0]).max() < 1e-12 and np.abs(dl - th[1]).max() < 1e-12
