@@ -27,6 +27,17 @@ Readings where the text is silent or garbled:
 Random numbers: the uniform v of a parameter is the same Philox word as for
 the histogram proposal; the component choice uses a second Philox block with
 counter word 2 = 2^31 | (2 round + half).
+
+Correlated pairs (the paper's correlated sampling in subsets of dimensions):
+up to three disjoint pairs (a, b) of adapted parameters get bivariate
+components in (u_a, u_b).  As the appendix describes, draws come from the
+untruncated mixture and are rejected outside the unit square, so the pair's
+proposal is p = eps + (1 - eps) sum_k pi_k N_k(u) / sum_k pi_k Z_k, Z_k the
+component's mass in the square.  Tries use Philox counter word 2 =
+3 * 2^30 | round << 10 | pair << 8 | try (64 tries; a sample none of them
+accepts is discarded: ln p - ln p_s = NaN).  EM fits bivariate normals (sd >=
+1e-4 per axis, |correlation| <= 0.99); the online update uses the text's
+symmetric Mahalanobis distances with each component's own covariance.
 """
 from __future__ import annotations
 
@@ -43,18 +54,84 @@ SD_MIN = 1e-4
 ALPHA, DELTA, PSI, IOTA, PHI, DIST, TAU = range(7)
 
 
-class Gmm:
-    """Mixture state of one point: per parameter d, K components."""
+PAIR_TRIES = 64
+RHO_MAX = 0.99
 
-    def __init__(self, K, mask, eps, w=None, mu=None, sd=None, n_trained=0.0):
+
+class Gmm:
+    """Mixture state of one point: per parameter d, K components; per pair
+    i (pairs[i] = (a, b)), K bivariate components pw [K], pmu [K, 2],
+    pcov [K, 3] (xx, xy, yy)."""
+
+    def __init__(self, K, mask, eps, w=None, mu=None, sd=None, n_trained=0.0, pairs=()):
         self.K, self.mask, self.eps, self.n_trained = int(K), int(mask), float(eps), float(n_trained)
         k = np.arange(K)
         self.w = np.tile(np.full(K, 1.0 / K), (7, 1)) if w is None else np.array(w, dtype=np.float64)
         self.mu = np.tile((k + 0.5) / K, (7, 1)) if mu is None else np.array(mu, dtype=np.float64)
         self.sd = np.tile(np.full(K, 0.5 / K), (7, 1)) if sd is None else np.array(sd, dtype=np.float64)
+        self.pairs = [tuple(p) for p in pairs]
+        self.pw = [np.full(K, 1.0 / K) for _ in self.pairs]
+        self.pmu = [np.stack([(k + 0.5) / K, (k + 0.5) / K], axis=1) for _ in self.pairs]
+        self.pcov = [np.tile([0.25 / K ** 2, 0.0, 0.25 / K ** 2], (K, 1)) for _ in self.pairs]
 
     def copy(self):
-        return Gmm(self.K, self.mask, self.eps, self.w, self.mu, self.sd, self.n_trained)
+        g = Gmm(self.K, self.mask, self.eps, self.w, self.mu, self.sd, self.n_trained)
+        g.pairs = list(self.pairs)
+        g.pw = [x.copy() for x in self.pw]
+        g.pmu = [x.copy() for x in self.pmu]
+        g.pcov = [x.copy() for x in self.pcov]
+        return g
+
+    def paired(self):
+        return {d for p in self.pairs for d in p}
+
+
+def decode_pairs(code):
+    """Pairs from the byte code: byte i = a | b << 4 with a < b (0: none)."""
+    out = []
+    for i in range(3):
+        c = (code >> (8 * i)) & 0xFF
+        if c:
+            out.append((c & 15, c >> 4))
+    return out
+
+
+# --- bivariate components ------------------------------------------------------
+
+def box_mass(mu, cov):
+    """Mass of N(mu, cov) in [0, 1]^2 (scipy's bivariate normal CDF on the
+    standardized rectangle, by inclusion-exclusion)."""
+    from scipy.stats import multivariate_normal
+    sx, sy = math.sqrt(cov[0]), math.sqrt(cov[2])
+    rho = cov[1] / (sx * sy)
+    R = np.array([[1.0, rho], [rho, 1.0]])
+    F = lambda x, y: multivariate_normal.cdf([(x - mu[0]) / sx, (y - mu[1]) / sy], mean=[0.0, 0.0], cov=R,
+                                             abseps=1e-15, releps=1e-15)
+    return F(1, 1) - F(0, 1) - F(1, 0) + F(0, 0)
+
+
+def pair_logpdf(x, y, mu, cov):
+    """ln N((x, y); mu, cov)."""
+    det = cov[0] * cov[2] - cov[1] * cov[1]
+    dx, dy = x - mu[0], y - mu[1]
+    q = (cov[2] * dx * dx - 2.0 * cov[1] * dx * dy + cov[0] * dy * dy) / det
+    return -math.log(2.0 * math.pi) - 0.5 * math.log(det) - 0.5 * q
+
+
+def pair_density(x, y, w, mu, cov, eps):
+    """Pair proposal density in (u_a, u_b) on the unit square."""
+    zm = sum(w[k] * box_mass(mu[k], cov[k]) for k in range(len(w)) if w[k] > 0.0)
+    s = np.zeros_like(np.asarray(x, dtype=np.float64))
+    for k in range(len(w)):
+        if w[k] > 0.0:
+            s = s + w[k] * np.exp(pair_logpdf(x, y, mu[k], cov[k]))
+    return eps + (1.0 - eps) * s / zm
+
+
+def chol(cov):
+    l11 = math.sqrt(cov[0])
+    l21 = cov[1] / l11
+    return l11, l21, math.sqrt(max(cov[2] - l21 * l21, 0.0))
 
 
 # --- truncated normal on [0, 1] ----------------------------------------------
@@ -132,7 +209,7 @@ def draw(seed, point, rnd, n, g: Gmm | None, *, d_min=10.0, d_max=1000.0, tau_wi
                 for q in range(4):
                     ex[4 * half + q, j] = ((c[q] >> 8) + 0.5) / 16777216.0
         for d in range(7):
-            if not (g.mask >> d) & 1:
+            if not (g.mask >> d) & 1 or d in g.paired():
                 continue
             for j in range(n):
                 cu = ex[d, j]
@@ -148,6 +225,37 @@ def draw(seed, point, rnd, n, g: Gmm | None, *, d_min=10.0, d_max=1000.0, tau_wi
                     uu = min(max(uu, 0.0), 1.0 - 2.0 ** -53)
                 u[d, j] = uu
             lr -= np.log(density(u[d], g.w[d], g.mu[d], g.sd[d], g.eps))
+        for pi, (a, b) in enumerate(g.pairs):
+            L = [chol(c) for c in g.pcov[pi]]
+            for j in range(n):
+                i = start + j
+                if ex[a, j] < g.eps:
+                    continue  # uniform: u_a, u_b stay the raw uniforms
+                c0 = (ex[a, j] - g.eps) / (1.0 - g.eps)
+                ok = False
+                for t in range(PAIR_TRIES):
+                    w4 = oracle.philox([i & 0xFFFFFFFF, i >> 32, 0xC0000000 | (rnd << 10) | (pi << 8) | t, point], key)
+                    c = c0 if t == 0 else (w4[0] + 0.5) * 2.0 ** -32
+                    k, acc = 0, g.pw[pi][0]
+                    while k < g.K - 1 and c >= acc:
+                        k += 1
+                        acc += g.pw[pi][k]
+                    u1 = (((w4[1] >> 6) << 27 | (w4[2] >> 5)) + 0.5) * 2.0 ** -53
+                    u2 = (w4[3] + 0.5) * 2.0 ** -32
+                    r = math.sqrt(-2.0 * math.log(u1))
+                    z1, z2 = r * math.cos(2.0 * math.pi * u2), r * math.sin(2.0 * math.pi * u2)
+                    l11, l21, l22 = L[k]
+                    x = g.pmu[pi][k][0] + l11 * z1
+                    y = g.pmu[pi][k][1] + l21 * z1 + l22 * z2
+                    if 0.0 <= x < 1.0 and 0.0 <= y < 1.0:
+                        ok = True
+                        break
+                if ok:
+                    u[a, j], u[b, j] = x, y
+                else:
+                    lr[j] = np.nan
+            dens = pair_density(u[a], u[b], g.pw[pi], g.pmu[pi], g.pcov[pi], g.eps)
+            lr -= np.log(dens)
     th = np.stack([prior_inv(d, u[d], d_min, d_max, tau_width) for d in range(7)])
     if frame is not None:
         th[ALPHA], th[DELTA] = frame_sky(frame[0], frame[1], u[ALPHA], u[DELTA])
@@ -238,20 +346,103 @@ def merge(old: Gmm, new_w, new_mu, new_sd, d, M):
     return w, mu, sd
 
 
-def adapt(g: Gmm | None, u, lnw, *, K, mask, eps, n_iter):
+def regularize(cov):
+    """sd >= SD_MIN per axis, |correlation| <= RHO_MAX."""
+    sxx, syy = max(cov[0], SD_MIN * SD_MIN), max(cov[2], SD_MIN * SD_MIN)
+    cmax = RHO_MAX * math.sqrt(sxx * syy)
+    return np.array([sxx, min(max(cov[1], -cmax), cmax), syy])
+
+
+def em_fit_pair(x, y, wt, w, mu, cov, n_iter):
+    """n_iter weighted EM iterations for one pair's bivariate components."""
+    w, mu, cov = np.array(w, dtype=np.float64), np.array(mu, dtype=np.float64), np.array(cov, dtype=np.float64)
+    K = w.size
+    for _ in range(n_iter):
+        lp = np.full((x.size, K), -np.inf)
+        for k in range(K):
+            if w[k] > 0.0:
+                lp[:, k] = math.log(w[k]) + pair_logpdf(x, y, mu[k], cov[k]) + math.log(2.0 * math.pi)
+        m = lp.max(axis=1, keepdims=True)
+        r = np.exp(lp - m)
+        r /= r.sum(axis=1, keepdims=True)
+        S0 = (wt[:, None] * r).sum(axis=0)
+        tot = S0.sum()
+        if not tot > 0.0:
+            break
+        for k in range(K):
+            if S0[k] > 0.0:
+                q = wt * r[:, k]
+                dx, dy = x - mu[k, 0], y - mu[k, 1]
+                mx, my = np.sum(q * dx) / S0[k], np.sum(q * dy) / S0[k]
+                cxx = np.sum(q * dx * dx) / S0[k] - mx * mx
+                cxy = np.sum(q * dx * dy) / S0[k] - mx * my
+                cyy = np.sum(q * dy * dy) / S0[k] - my * my
+                mu[k] = mu[k] + [mx, my]
+                cov[k] = regularize([cxx, cxy, cyy])
+            w[k] = S0[k] / tot
+    return w, mu, cov
+
+
+def _inv(c):
+    det = c[0] * c[2] - c[1] * c[1]
+    return np.array([c[2], -c[1], c[0]]) / det
+
+
+def _maha(d, c):
+    i = _inv(c)
+    return math.sqrt(max(i[0] * d[0] * d[0] + 2.0 * i[1] * d[0] * d[1] + i[2] * d[1] * d[1], 0.0))
+
+
+def merge_pair(old: Gmm, pi, nw, nm, nc, M):
+    """Online update of pair pi (App. A): matching by the summed symmetric
+    Mahalanobis distance, combination with the sample counts N and M."""
+    N, K = old.n_trained, old.K
+    if N <= 0.0:
+        return np.array(nw), np.array(nm), np.array(nc)
+    ow, om, oc = old.pw[pi], old.pmu[pi], old.pcov[pi]
+    best, bp = None, None
+    for p in itertools.permutations(range(K)):
+        s = 0.0
+        for i in range(K):
+            d = om[p[i]] - nm[i]
+            s += _maha(d, nc[i]) + _maha(d, oc[p[i]])
+        if best is None or s < best:
+            best, bp = s, p
+    w, mu, cov = ow.copy(), om.copy(), oc.copy()
+    for i in range(K):
+        j = bp[i]
+        a, b = N * ow[j], M * nw[i]
+        if not a + b > 0.0:
+            w[j] = 0.0
+            continue
+        d = om[j] - nm[i]
+        mu[j] = (a * om[j] + b * nm[i]) / (a + b)
+        f = a * b / ((a + b) * (a + b))
+        cov[j] = regularize((a * oc[j] + b * nc[i]) / (a + b) + f * np.array([d[0] * d[0], d[0] * d[1], d[1] * d[1]]))
+        w[j] = (a + b) / (N + M)
+    return w, mu, cov
+
+
+def adapt(g: Gmm | None, u, lnw, *, K, mask, eps, n_iter, pairs=()):
     """One round's update of a point's mixture from the round's u [7, n] and
-    ln w [n]; g None (or a different K): start from the initial model."""
-    cur = g.copy() if (g is not None and g.K == K) else Gmm(K, mask, eps)
+    ln w [n]; g None (or a different K or pair list): start from the
+    initial model."""
+    pairs = [tuple(p) for p in pairs]
+    cur = g.copy() if (g is not None and g.K == K and g.pairs == pairs) else Gmm(K, mask, eps, pairs=pairs)
     wt, M = weights(lnw)
     if not wt.sum() > 0.0:
         cur.mask, cur.eps = mask, eps
         return cur
     out = cur.copy()
     for d in range(7):
-        if not (mask >> d) & 1:
+        if not (mask >> d) & 1 or d in cur.paired():
             continue
         nw, nm, ns = em_fit(u[d], wt, cur.w[d], cur.mu[d], cur.sd[d], n_iter)
         out.w[d], out.mu[d], out.sd[d] = merge(cur, nw, nm, ns, d, M)
+    for pi, (a, b) in enumerate(pairs):
+        nw, nm, nc = em_fit_pair(np.asarray(u[a], dtype=np.float64), np.asarray(u[b], dtype=np.float64), wt,
+                                 cur.pw[pi], cur.pmu[pi], cur.pcov[pi], n_iter)
+        out.pw[pi], out.pmu[pi], out.pcov[pi] = merge_pair(cur, pi, nw, nm, nc, M)
     out.n_trained = cur.n_trained + M
     out.mask, out.eps = mask, eps
     return out

@@ -146,3 +146,75 @@ def test_frame_sky_matches_the_c_oracle(orc):
     v = ((raw.astype(np.float64) // 256) + 0.5) / 16777216.0
     a, dl = gmm.frame_sky(d["det_pos"], d["gmst"], v[0], v[1])
     assert np.abs(a - th[0]).max() < 1e-12 and np.abs(dl - th[1]).max() < 1e-12
+
+
+# --- correlated pairs ---------------------------------------------------------
+
+def _pair_model():
+    g = gmm.Gmm(2, 0b0011100, 0.1, pairs=[(2, 4)])
+    g.pw[0] = np.array([0.7, 0.3])
+    g.pmu[0] = np.array([[0.3, 0.6], [0.8, 0.1]])
+    g.pcov[0] = np.array([[0.01, 0.008, 0.01], [0.04, -0.01, 0.01]])
+    g.n_trained = 2000.0
+    return g
+
+
+def test_box_mass_against_quadrature():
+    from scipy.stats import multivariate_normal
+    for mu, cov in [([0.3, 0.6], [0.01, 0.008, 0.01]), ([0.95, 0.02], [0.09, -0.05, 0.04]), ([0.5, 0.5], [4.0, 0.0, 1e-4])]:
+        C = np.array([[cov[0], cov[1]], [cov[1], cov[2]]])
+        ref = integrate.dblquad(lambda y, x: multivariate_normal.pdf([x, y], mu, C), 0, 1, 0, 1,
+                                epsabs=1e-12, epsrel=1e-12)[0]
+        assert abs(gmm.box_mass(mu, cov) - ref) < 1e-9
+
+
+def test_pair_em_one_component_gives_weighted_moments():
+    rng = np.random.default_rng(9)
+    x, y = rng.beta(2, 5, 3000), rng.beta(3, 3, 3000)
+    y = 0.5 * y + 0.5 * x
+    wt = rng.exponential(size=3000)
+    w, mu, cov = gmm.em_fit_pair(x, y, wt, [1.0], [[0.5, 0.5]], [[0.1, 0.0, 0.1]], 1)
+    W = wt.sum()
+    mx, my = np.sum(wt * x) / W, np.sum(wt * y) / W
+    ref = [np.sum(wt * (x - mx) ** 2) / W, np.sum(wt * (x - mx) * (y - my)) / W, np.sum(wt * (y - my) ** 2) / W]
+    assert np.allclose(mu[0], [mx, my], atol=1e-14) and np.allclose(cov[0], ref, atol=1e-14)
+
+
+def test_pair_online_update_pools_moments():
+    rng = np.random.default_rng(10)
+    A = rng.multivariate_normal([0.3, 0.4], [[0.01, 0.004], [0.004, 0.02]], 3000)
+    B = rng.multivariate_normal([0.35, 0.45], [[0.02, -0.003], [-0.003, 0.01]], 1000)
+    mom = lambda Z: (Z.mean(axis=0), np.array([np.var(Z[:, 0]), np.cov(Z.T, bias=True)[0, 1], np.var(Z[:, 1])]))
+    ma, ca = mom(A)
+    mb, cb = mom(B)
+    old = gmm.Gmm(1, 0b11, 0.1, n_trained=A.shape[0], pairs=[(0, 1)])
+    old.pw[0], old.pmu[0], old.pcov[0] = np.array([1.0]), ma[None], ca[None]
+    w, mu, cov = gmm.merge_pair(old, 0, np.array([1.0]), mb[None], cb[None], B.shape[0])
+    mz, cz = mom(np.concatenate([A, B]))
+    assert np.allclose(mu[0], mz, atol=1e-14) and np.allclose(cov[0], cz, atol=1e-14) and w[0] == 1.0
+
+
+def test_pair_draws_follow_the_truncated_mixture():
+    from scipy.stats import multivariate_normal, chisquare
+    g = _pair_model()
+    n = 8000
+    th, lr, u = gmm.draw(2210079128, 1, 2, n, g)
+    assert np.all(np.isfinite(lr))
+    r = np.exp(lr)
+    assert abs(r.mean() - 1.0) < 5 * r.std() / math.sqrt(n)
+    # cell probabilities of the pair proposal on a 5 x 5 grid, by the bivariate CDF
+    e = np.linspace(0, 1, 6)
+    zm = sum(g.pw[0][k] * gmm.box_mass(g.pmu[0][k], g.pcov[0][k]) for k in range(2))
+    P = np.zeros((5, 5))
+    for k in range(2):
+        C = np.array([[g.pcov[0][k][0], g.pcov[0][k][1]], [g.pcov[0][k][1], g.pcov[0][k][2]]])
+        F = lambda x, y: multivariate_normal.cdf([x, y], mean=g.pmu[0][k], cov=C, abseps=1e-12, releps=1e-12)
+        for i in range(5):
+            for j in range(5):
+                P[i, j] += g.pw[0][k] * (F(e[i + 1], e[j + 1]) - F(e[i], e[j + 1]) - F(e[i + 1], e[j]) + F(e[i], e[j]))
+    P = g.eps / 25 + (1 - g.eps) * P / zm
+    obs = np.histogram2d(u[2], u[4], bins=[e, e])[0]
+    assert abs(P.sum() - 1) < 1e-9
+    assert chisquare(obs.ravel(), n * P.ravel()).pvalue > 1e-3
+    # the 1-D parameter of the mask (3) keeps its own (initial) mixture; others the prior
+    assert stats.kstest(u[0], "uniform").pvalue > 1e-3
