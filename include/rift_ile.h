@@ -151,6 +151,16 @@ typedef struct {
    * counts.  0: histograms.  Not combined with RIFT_MC_GRADIENT. */
   int gmm_components;
   int gmm_iters;
+  /* Correlated pairs of the mixture proposal (needs gmm_components > 0 and
+   * n_rounds <= 2^20): byte i (i < 3) = a | b << 4 names a pair a < b < 7 of
+   * adapted parameters (0: none; pairs disjoint); such a pair gets
+   * gmm_components bivariate components in its two prior-CDF coordinates
+   * (App. A, finite domains): draws from the untruncated mixture rejected
+   * outside the unit square (64 tries, Philox counter word 2 =
+   * 3 2^30 | round << 10 | pair << 8 | try; a sample none accepts is
+   * discarded with ln ratio NaN), p_s = floor_eps + (1 - floor_eps)
+   * sum_k pi_k N_k / sum_k pi_k Z_k, Z_k the component's mass in the square. */
+  unsigned gmm_pairs;
 } rift_ile_mc;
 
 #define RIFT_MC_GRADIENT 1u
@@ -342,9 +352,26 @@ rift_status rift_ile_set_gmm(rift_ile *h, int point, int K, unsigned mask, doubl
  * online update: components matched by the smallest summed symmetric
  * Mahalanobis distance over all permutations and combined with weights
  * N = n_trained and M = the number of samples whose ln w is neither NaN nor
- * +inf.  Sums are FP64 in a fixed order.  Asynchronous. */
+ * +inf.  pairs (coded as in rift_ile_mc, parameters in mask): those
+ * parameters are fitted jointly by bivariate components (sd >= 1e-4 per
+ * axis, |correlation| <= 0.99); starting from the point's mixture needs the
+ * same K and pairs.  Sums are FP64 in a fixed order.  Asynchronous. */
 rift_status rift_ile_adapt_gmm(rift_ile *h, int point, int64_t n, const float *u, const void *lnw, unsigned mask,
-                               double floor_eps, int K, int n_iter);
+                               unsigned pairs, double floor_eps, int K, int n_iter);
+
+/* Correlated pairs of a point's mixture (pairs coded as in rift_ile_mc):
+ * w host [3][4], mu [3][4][2], cov [3][4][3] (xx, xy, yy), pair slot p the
+ * p-th nonzero byte of pairs, components k >= K ignored.  set: the point must
+ * hold a mixture (rift_ile_set_gmm), both parameters of each pair in its
+ * mask; weights >= 0 summing to 1 (within 1e-9), means in [0, 1]^2,
+ * covariances positive definite; computes each component's mass in the
+ * unit square; synchronizes.  get: box_mass [3] (or NULL) receives
+ * sum_k pi_k Z_k per pair; outputs other than pairs may be NULL;
+ * synchronizes.  Errors: RIFT_E_INVALID. */
+rift_status rift_ile_set_gmm_pairs(rift_ile *h, int point, unsigned pairs, const double *w, const double *mu,
+                                   const double *cov);
+rift_status rift_ile_get_gmm_pairs(rift_ile *h, int point, unsigned *pairs, double *w, double *mu, double *cov,
+                                   double *box_mass);
 
 /* The whole step for every point: for each round, draw samples from the
  * current proposal, evaluate ln L_t, form ln w, fold them into a pooled FP64

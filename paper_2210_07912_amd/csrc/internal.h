@@ -173,13 +173,24 @@ hipError_t mfma_prepare(const MfmaArgs &a, const int *mclass_M, const int *mclas
 // histogram (cdf) or, with gk > 0, a mixture of gk normals truncated to the
 // prior-CDF coordinate's [0, 1] plus a uniform floor geps (gca = Phi(a),
 // gz = Phi(b) - Phi(a) of each component; gntr samples fitted so far)
+// Correlated pairs (npair of them, parameters pa < pb, disjoint, in mask):
+// gk bivariate components in (u_a, u_b) (pcov: xx, xy, yy), drawn from the
+// untruncated mixture and rejected outside the unit square; derived: pch
+// (Cholesky l11, l21, l22), pic (inverse xx, xy, yy), plog (ln pi - ln 2 pi -
+// ln det / 2), pzm (sum_k pi_k Z_k, Z_k the component's mass in the square).
 constexpr int kMaxG = 4;
+constexpr int kMaxPair = 3;
 struct ProposalDev {
   double cdf[7][kNB + 1];
   unsigned mask;
   int gk;
   double geps, gntr;
   double gw[7][kMaxG], gmu[7][kMaxG], gsd[7][kMaxG], gca[7][kMaxG], gz[7][kMaxG];
+  int npair;
+  int pa[kMaxPair], pb[kMaxPair];
+  int pad2_;
+  double pw[kMaxPair][kMaxG], pmu[kMaxPair][kMaxG][2], pcov[kMaxPair][kMaxG][3];
+  double pch[kMaxPair][kMaxG][3], pic[kMaxPair][kMaxG][3], plog[kMaxPair][kMaxG], pzm[kMaxPair];
 };
 
 // pt / pts: the point(s) whose network frame the sky is drawn in, or null for
@@ -250,18 +261,25 @@ hipError_t adapt_launch(const uint8_t *bins, int64_t bin_stride, const R *lnw, c
 // current ones, then the EM iterates).
 struct GmmDev {
   int k;
-  int pad_;
+  int npair;
   double ntr;
   double w[7][kMaxG], mu[7][kMaxG], sd[7][kMaxG];
+  int pa[kMaxPair], pb[kMaxPair];
+  double pw[kMaxPair][kMaxG], pmu[kMaxPair][kMaxG][2], pcov[kMaxPair][kMaxG][3];
 };
 int em_blocks(int64_t max_count);
+// pairs: byte i = a | b << 4 (a < b; 0: none); part2: scratch
+// [n_seg][bps][kMaxPair][kMaxG][6]
 template <typename R>
 hipError_t gmm_adapt_launch(const float *ubuf, int64_t u_stride, const R *lnw, const int64_t *seg_off,
                             const int64_t *seg_cnt, const int *seg_prop, int n_seg, int bps,
-                            const ReduceTuple *seg_round, double *part, GmmDev *fit, ProposalDev *props,
-                            unsigned mask, double floor_eps, int K, int n_iter, hipStream_t st);
+                            const ReduceTuple *seg_round, double *part, double *part2, GmmDev *fit,
+                            ProposalDev *props, unsigned mask, unsigned pairs, double floor_eps, int K, int n_iter,
+                            hipStream_t st);
 // host: component normalizations gca, gz of a mixture (Phi by erfc)
 void gmm_norms(ProposalDev &p);
+// derived pair quantities (pch, pic, plog, pzm) of props[p0 .. p0 + n - 1]
+hipError_t pair_norm_launch(ProposalDev *props, int p0, int n, hipStream_t st);
 
 hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 

@@ -19,6 +19,7 @@ namespace rift {
 // sampler
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double u01(uint32_t x) { return ((double)(x >> 8) + 0.5) * (1.0 / 16777216.0); }
+constexpr int kPairTries = 64;  // rejection tries of a correlated pair's draw
 
 // Prior inverse CDFs u -> theta, evaluated in FP64 and rounded once to the
 // bulk precision: asin/acos are ill-conditioned near the poles, where FP32
@@ -62,14 +63,33 @@ __device__ __forceinline__ void frame_sky(const double (*fr)[3], double gmst, do
 
 // mixture parameters of a proposal, staged in LDS by the sampling kernels
 struct GmmSh {
-  int k;
+  int k, npair;
+  int pa[kMaxPair], pb[kMaxPair];
   double eps;
   double w[7][kMaxG], mu[7][kMaxG], sd[7][kMaxG], ca[7][kMaxG], z[7][kMaxG];
+  double pw[kMaxPair][kMaxG], pmu[kMaxPair][kMaxG][2], pch[kMaxPair][kMaxG][3], pic[kMaxPair][kMaxG][3];
+  double plog[kMaxPair][kMaxG], pzm[kMaxPair];
 };
 __device__ __forceinline__ void gmm_stage(const ProposalDev *prop, GmmSh &g) {
   if (threadIdx.x == 0) {
     g.k = prop->gk;
     g.eps = prop->geps;
+    g.npair = prop->gk > 0 ? prop->npair : 0;
+    for (int p = 0; p < kMaxPair; p++) {
+      g.pa[p] = prop->pa[p];
+      g.pb[p] = prop->pb[p];
+      g.pzm[p] = prop->pzm[p];
+    }
+  }
+  for (int i = threadIdx.x; i < kMaxPair * kMaxG; i += blockDim.x) {
+    const int p = i / kMaxG, c = i % kMaxG;
+    g.pw[p][c] = prop->pw[p][c];
+    g.plog[p][c] = prop->plog[p][c];
+    for (int q = 0; q < 2; q++) g.pmu[p][c][q] = prop->pmu[p][c][q];
+    for (int q = 0; q < 3; q++) {
+      g.pch[p][c][q] = prop->pch[p][c][q];
+      g.pic[p][c][q] = prop->pic[p][c][q];
+    }
   }
   for (int i = threadIdx.x; i < 7 * kMaxG; i += blockDim.x) {
     const int d = i / kMaxG, c = i % kMaxG;
@@ -109,13 +129,17 @@ __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned 
     }
   }
   double lr = 0.0, us[2] = {0.0, 0.0};
+  unsigned pm = 0u;  // parameters drawn in correlated pairs (after this loop)
+  for (int p = 0; p < g->npair; p++) pm |= (1u << g->pa[p]) | (1u << g->pb[p]);
 #pragma unroll
   for (int d = 0; d < 7; d++) {
     double v = u01(r[d]);
     double u = v;
     // bin of the raw uniform: floor(v nb), exactly, in integers
     uint32_t bin = (uint32_t)((((uint64_t)(r[d] >> 8) * 2u + 1u) * kNB) >> 25);
-    if (((mask >> d) & 1u) && gk > 0) {
+    if (((mask >> d) & 1u) && gk > 0 && ((pm >> d) & 1u)) {
+      // a pair's parameter: drawn below
+    } else if (((mask >> d) & 1u) && gk > 0) {
       const double eps = g->eps, cu = u01(e[d]);
       if (cu >= eps) {
         const double c2 = (cu - eps) / (1.0 - eps);
@@ -153,6 +177,64 @@ __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned 
     theta[d * stride + col] = prior_inv<R>(d, u, d_min, d_max, tau_width);
     if (bins) bins[d * bin_stride + col] = (uint8_t)bin;
   }
+  // correlated pairs: below the floor the raw uniforms, else up to
+  // kPairTries draws from the untruncated mixture (Philox counter word 2 =
+  // 3 2^30 | round << 10 | pair << 8 | try), the first inside the unit
+  // square kept; none inside: the sample is discarded (ln ratio NaN)
+  bool discard = false;
+  for (int p = 0; p < g->npair; p++) {
+    const int a = g->pa[p], b = g->pb[p];
+    double ua = u01(r[a]), ub = u01(r[b]);
+    const double eps = g->eps, ca = u01(e[a]);
+    if (ca >= eps) {
+      const double c0 = (ca - eps) / (1.0 - eps);
+      bool ok = false;
+      for (int t = 0; t < kPairTries && !ok; t++) {
+        uint32_t w4[4] = {(uint32_t)i, (uint32_t)(i >> 32), 0xC0000000u | (round << 10) | ((uint32_t)p << 8) | (uint32_t)t,
+                          point};
+        philox(w4, (uint32_t)seed, (uint32_t)(seed >> 32));
+        const double c = t == 0 ? c0 : ((double)w4[0] + 0.5) * 0x1p-32;
+        int k = 0;
+        double acc = g->pw[p][0];
+        while (k < gk - 1 && c >= acc) {
+          k++;
+          acc += g->pw[p][k];
+        }
+        const double u1 = ((double)((((uint64_t)(w4[1] >> 6)) << 27) | (uint64_t)(w4[2] >> 5)) + 0.5) * 0x1p-53;
+        const double u2 = ((double)w4[3] + 0.5) * 0x1p-32;
+        const double rr = sqrt(-2.0 * log(u1));
+        double sn, cs;
+        sincos(2.0 * kPi * u2, &sn, &cs);
+        const double z1 = rr * cs, z2 = rr * sn;
+        const double x = g->pmu[p][k][0] + g->pch[p][k][0] * z1;
+        const double y = g->pmu[p][k][1] + g->pch[p][k][1] * z1 + g->pch[p][k][2] * z2;
+        if (x >= 0.0 && x < 1.0 && y >= 0.0 && y < 1.0) {
+          ua = x;
+          ub = y;
+          ok = true;
+        }
+      }
+      discard = discard || !ok;
+    }
+    double sden = 0.0;
+    for (int k = 0; k < gk; k++) {
+      if (g->pw[p][k] > 0.0) {
+        const double dx = ua - g->pmu[p][k][0], dy = ub - g->pmu[p][k][1];
+        const double q = g->pic[p][k][0] * dx * dx + 2.0 * g->pic[p][k][1] * dx * dy + g->pic[p][k][2] * dy * dy;
+        sden += exp(g->plog[p][k] - 0.5 * q);
+      }
+    }
+    lr -= log(eps + (1.0 - eps) * sden / g->pzm[p]);
+    const int dd[2] = {a, b};
+    const double uu[2] = {ua, ub};
+    for (int q = 0; q < 2; q++) {
+      if (dd[q] < 2) us[dd[q]] = uu[q];
+      if (ubuf) ubuf[dd[q] * bin_stride + col] = (float)uu[q];
+      theta[dd[q] * stride + col] = prior_inv<R>(dd[q], uu[q], d_min, d_max, tau_width);
+      if (bins) bins[dd[q] * bin_stride + col] = (uint8_t)min((int)(uu[q] * kNB), kNB - 1);
+    }
+  }
+  if (discard) lr = NAN;
   if (pt) {
     double al, de;
     frame_sky(pt->frame, pt->gmst, us[0], us[1], al, de);
@@ -507,17 +589,29 @@ int em_blocks(int64_t max_count) { return (int)std::max<int64_t>(1, (max_count +
 
 __device__ __forceinline__ double phi_cdf(double x) { return 0.5 * erfc(-x * 0.70710678118654752440); }
 
-// the mixture a round starts from: the point's own when it has K components,
-// else the initial one (equal weights, means (k + 1/2) / K, sd 1 / (2 K))
-__global__ void gmm_init_kernel(const ProposalDev *props, const int *seg_prop, int n_seg, int K, GmmDev *cur,
-                                GmmDev *fit) {
+// the mixture a round starts from: the point's own when it has K components
+// and the same pairs, else the initial one (equal weights, means (k + 1/2) /
+// K, sd 1 / (2 K); pairs: means on the diagonal, no correlation)
+__global__ void gmm_init_kernel(const ProposalDev *props, const int *seg_prop, int n_seg, int K, unsigned pairs,
+                                GmmDev *cur, GmmDev *fit) {
   const int seg = blockIdx.x * blockDim.x + threadIdx.x;
   if (seg >= n_seg) return;
   const ProposalDev &P = props[seg_prop[seg]];
-  const bool own = P.gk == K;
+  int np = 0, pa[kMaxPair], pb[kMaxPair];
+  for (int i = 0; i < kMaxPair; i++) {
+    const unsigned c = (pairs >> (8 * i)) & 0xFFu;
+    pa[i] = pb[i] = 0;
+    if (c) {
+      pa[np] = (int)(c & 15u);
+      pb[np] = (int)(c >> 4);
+      np++;
+    }
+  }
+  bool own = P.gk == K && P.npair == np;
+  for (int i = 0; i < np && own; i++) own = P.pa[i] == pa[i] && P.pb[i] == pb[i];
   GmmDev &c = cur[seg], &f = fit[seg];
   c.k = f.k = K;
-  c.pad_ = f.pad_ = 0;
+  c.npair = f.npair = np;
   c.ntr = f.ntr = own ? P.gntr : 0.0;
   for (int d = 0; d < 7; d++)
     for (int k = 0; k < kMaxG; k++) {
@@ -525,6 +619,18 @@ __global__ void gmm_init_kernel(const ProposalDev *props, const int *seg_prop, i
       c.mu[d][k] = f.mu[d][k] = own ? P.gmu[d][k] : (k + 0.5) / K;
       c.sd[d][k] = f.sd[d][k] = own ? P.gsd[d][k] : 0.5 / K;
     }
+  for (int i = 0; i < kMaxPair; i++) {
+    c.pa[i] = f.pa[i] = pa[i];
+    c.pb[i] = f.pb[i] = pb[i];
+    for (int k = 0; k < kMaxG; k++) {
+      c.pw[i][k] = f.pw[i][k] = own ? P.pw[i][k] : (k < K ? 1.0 / K : 0.0);
+      for (int q = 0; q < 2; q++) c.pmu[i][k][q] = f.pmu[i][k][q] = own ? P.pmu[i][k][q] : (k + 0.5) / K;
+      const double v0 = 0.25 / ((double)K * K);
+      c.pcov[i][k][0] = f.pcov[i][k][0] = own ? P.pcov[i][k][0] : v0;
+      c.pcov[i][k][1] = f.pcov[i][k][1] = own ? P.pcov[i][k][1] : 0.0;
+      c.pcov[i][k][2] = f.pcov[i][k][2] = own ? P.pcov[i][k][2] : v0;
+    }
+  }
 }
 
 // E-step and the M-step sums of one block: for each adapted d and component
@@ -622,6 +728,252 @@ __global__ void em_update_kernel(const double *part, int n_seg, int bps, GmmDev 
   }
 }
 
+// sd >= kSdMin per axis, |correlation| <= kRhoMax
+constexpr double kRhoMax = 0.99;
+__device__ __forceinline__ void regularize(double &xx, double &xy, double &yy) {
+  xx = fmax(xx, kSdMin * kSdMin);
+  yy = fmax(yy, kSdMin * kSdMin);
+  const double cm = kRhoMax * sqrt(xx * yy);
+  xy = fmin(fmax(xy, -cm), cm);
+}
+
+// pairs: E-step and sums of one block, per pair and component S0, Sx, Sy,
+// Sxx, Sxy, Syy (moments about the component's current mean)
+template <typename R>
+__global__ void __launch_bounds__(256) em_pair_partials_kernel(const float *ub, int64_t us, const R *lnw,
+                                                               const int64_t *seg_off, const int64_t *seg_cnt,
+                                                               int bps, const ReduceTuple *seg_round,
+                                                               const GmmDev *fit, double *part2) {
+  __shared__ double red[256][6 * kMaxG];
+  const int seg = blockIdx.x / bps, j = blockIdx.x % bps;
+  const int64_t cnt = seg_cnt[seg], off = seg_off[seg];
+  const int64_t lo = min(cnt, (int64_t)j * kEmChunk), hi = min(cnt, lo + kEmChunk);
+  const double mx = seg_round[seg].m;
+  const GmmDev &F = fit[seg];
+  const int K = F.k;
+  for (int p = 0; p < F.npair; p++) {
+    const int a = F.pa[p], b = F.pb[p];
+    double acc[6 * kMaxG];
+    double lw[kMaxG], m0[kMaxG], m1[kMaxG], i0[kMaxG], i1[kMaxG], i2[kMaxG];
+#pragma unroll
+    for (int q = 0; q < 6 * kMaxG; q++) acc[q] = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxG; k++) {
+      const double c0 = F.pcov[p][k][0], c1 = F.pcov[p][k][1], c2 = F.pcov[p][k][2];
+      const double det = c0 * c2 - c1 * c1;
+      i0[k] = c2 / det;
+      i1[k] = -c1 / det;
+      i2[k] = c0 / det;
+      lw[k] = (k < K && F.pw[p][k] > 0.0) ? log(F.pw[p][k]) - 0.5 * log(det) : -INFINITY;
+      m0[k] = F.pmu[p][k][0];
+      m1[k] = F.pmu[p][k][1];
+    }
+    if (mx > -INFINITY) {
+      for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+        const double x = (double)lnw[off + i];
+        if (!(x == x) || x == INFINITY || x == -INFINITY) continue;
+        const double wt = exp(x - mx);
+        const double ux = (double)ub[a * us + off + i], uy = (double)ub[b * us + off + i];
+        double lp[kMaxG], m = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < kMaxG; k++) {
+          const double dx = ux - m0[k], dy = uy - m1[k];
+          lp[k] = lw[k] - 0.5 * (i0[k] * dx * dx + 2.0 * i1[k] * dx * dy + i2[k] * dy * dy);
+          m = fmax(m, lp[k]);
+        }
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < kMaxG; k++) {
+          lp[k] = lw[k] == -INFINITY ? 0.0 : exp(lp[k] - m);
+          sum += lp[k];
+        }
+#pragma unroll
+        for (int k = 0; k < kMaxG; k++) {
+          const double r = wt * (lp[k] / sum), dx = ux - m0[k], dy = uy - m1[k];
+          acc[6 * k] += r;
+          acc[6 * k + 1] += r * dx;
+          acc[6 * k + 2] += r * dy;
+          acc[6 * k + 3] += r * dx * dx;
+          acc[6 * k + 4] += r * dx * dy;
+          acc[6 * k + 5] += r * dy * dy;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 6 * kMaxG; q++) red[threadIdx.x][q] = acc[q];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o)
+#pragma unroll
+        for (int q = 0; q < 6 * kMaxG; q++) red[threadIdx.x][q] += red[threadIdx.x + o][q];
+      __syncthreads();
+    }
+    if (threadIdx.x < 6 * kMaxG)
+      part2[(((size_t)seg * bps + j) * kMaxPair + p) * 6 * kMaxG + threadIdx.x] = red[0][threadIdx.x];
+    __syncthreads();
+  }
+}
+
+__global__ void em_pair_update_kernel(const double *part2, int n_seg, int bps, GmmDev *fit) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_seg * kMaxPair) return;
+  const int seg = idx / kMaxPair, p = idx % kMaxPair;
+  GmmDev &F = fit[seg];
+  if (p >= F.npair) return;
+  const int K = F.k;
+  double S[6 * kMaxG];
+  for (int q = 0; q < 6 * kMaxG; q++) S[q] = 0.0;
+  for (int j = 0; j < bps; j++)
+    for (int q = 0; q < 6 * kMaxG; q++) S[q] += part2[(((size_t)seg * bps + j) * kMaxPair + p) * 6 * kMaxG + q];
+  double tot = 0.0;
+  for (int k = 0; k < K; k++) tot += S[6 * k];
+  if (!(tot > 0.0)) return;
+  for (int k = 0; k < K; k++) {
+    const double s0 = S[6 * k];
+    if (s0 > 0.0) {
+      const double mx = S[6 * k + 1] / s0, my = S[6 * k + 2] / s0;
+      double xx = S[6 * k + 3] / s0 - mx * mx, xy = S[6 * k + 4] / s0 - mx * my, yy = S[6 * k + 5] / s0 - my * my;
+      F.pmu[p][k][0] += mx;
+      F.pmu[p][k][1] += my;
+      regularize(xx, xy, yy);
+      F.pcov[p][k][0] = xx;
+      F.pcov[p][k][1] = xy;
+      F.pcov[p][k][2] = yy;
+    }
+    F.pw[p][k] = s0 / tot;
+  }
+}
+
+__device__ __forceinline__ double maha(double dx, double dy, const double *c) {
+  const double det = c[0] * c[2] - c[1] * c[1];
+  return sqrt(fmax((c[2] * dx * dx - 2.0 * c[1] * dx * dy + c[0] * dy * dy) / det, 0.0));
+}
+
+__device__ bool next_perm(int *p, int n);
+
+// pairs: online update (App. A) with the text's symmetric Mahalanobis
+// distances, each component's own covariance
+__global__ void gmm_pair_merge_kernel(const GmmDev *cur, const GmmDev *fit, int n_seg, const int *seg_prop,
+                                      const ReduceTuple *seg_round, ProposalDev *props) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_seg * kMaxPair) return;
+  const int seg = idx / kMaxPair, p = idx % kMaxPair;
+  const GmmDev &C = cur[seg], &F = fit[seg];
+  ProposalDev &P = props[seg_prop[seg]];
+  if (p >= C.npair) return;
+  const int K = C.k;
+  const bool any = seg_round[seg].m > -INFINITY;
+  const double N = C.ntr, M = (double)seg_round[seg].n;
+  const bool take_new = any && !(N > 0.0);
+  for (int k = 0; k < kMaxG; k++) {
+    const GmmDev &S = (take_new && k < K) ? F : C;
+    P.pw[p][k] = S.pw[p][k];
+    for (int q = 0; q < 2; q++) P.pmu[p][k][q] = S.pmu[p][k][q];
+    for (int q = 0; q < 3; q++) P.pcov[p][k][q] = S.pcov[p][k][q];
+  }
+  if (!any || take_new) return;
+  int pr[kMaxG], bp[kMaxG];
+  for (int k = 0; k < K; k++) pr[k] = bp[k] = k;
+  double best = INFINITY;
+  do {
+    double s = 0.0;
+    for (int i = 0; i < K; i++) {
+      const int jj = pr[i];
+      const double dx = C.pmu[p][jj][0] - F.pmu[p][i][0], dy = C.pmu[p][jj][1] - F.pmu[p][i][1];
+      s += maha(dx, dy, F.pcov[p][i]) + maha(dx, dy, C.pcov[p][jj]);
+    }
+    if (s < best) {
+      best = s;
+      for (int k = 0; k < K; k++) bp[k] = pr[k];
+    }
+  } while (next_perm(pr, K));
+  for (int i = 0; i < K; i++) {
+    const int jj = bp[i];
+    const double a = N * C.pw[p][jj], b = M * F.pw[p][i];
+    if (!(a + b > 0.0)) {
+      P.pw[p][jj] = 0.0;
+      continue;
+    }
+    const double dx = C.pmu[p][jj][0] - F.pmu[p][i][0], dy = C.pmu[p][jj][1] - F.pmu[p][i][1];
+    const double f = a * b / ((a + b) * (a + b));
+    P.pmu[p][jj][0] = (a * C.pmu[p][jj][0] + b * F.pmu[p][i][0]) / (a + b);
+    P.pmu[p][jj][1] = (a * C.pmu[p][jj][1] + b * F.pmu[p][i][1]) / (a + b);
+    double xx = (a * C.pcov[p][jj][0] + b * F.pcov[p][i][0]) / (a + b) + f * dx * dx;
+    double xy = (a * C.pcov[p][jj][1] + b * F.pcov[p][i][1]) / (a + b) + f * dx * dy;
+    double yy = (a * C.pcov[p][jj][2] + b * F.pcov[p][i][2]) / (a + b) + f * dy * dy;
+    regularize(xx, xy, yy);
+    P.pcov[p][jj][0] = xx;
+    P.pcov[p][jj][1] = xy;
+    P.pcov[p][jj][2] = yy;
+    P.pw[p][jj] = (a + b) / (N + M);
+  }
+}
+
+// derived pair quantities, one 256-thread block per (point, pair): thread
+// (k, q) integrates panel q of 64 of component k's mass in the unit square,
+// Z = int_0^1 N(x; mx, sx) [Phi((1 - m(x)) / s) - Phi(-m(x) / s)] dx with
+// m(x) the conditional mean of y and s its sd, over [mx - 9 sx, mx + 9 sx]
+// clipped to [0, 1], 8-point Gauss-Legendre per panel; a fixed tree sums
+__global__ void __launch_bounds__(256) pair_norm_kernel(ProposalDev *props, int p0) {
+  __shared__ double red[256];
+  ProposalDev &P = props[p0 + blockIdx.x / kMaxPair];
+  const int p = blockIdx.x % kMaxPair;
+  if (P.gk <= 0 || p >= P.npair) return;  // uniform over the block
+  const int K = P.gk, k = threadIdx.x / 64, q = threadIdx.x % 64;
+  double zq = 0.0;
+  if (k < K) {
+    const double mx = P.pmu[p][k][0], my = P.pmu[p][k][1];
+    const double cxx = P.pcov[p][k][0], cxy = P.pcov[p][k][1], cyy = P.pcov[p][k][2];
+    const double sx = sqrt(cxx), bc = cxy / cxx, sc = sqrt(fmax(cyy - cxy * cxy / cxx, 0.0));
+    const double lo = fmax(0.0, mx - 9.0 * sx), hi = fmin(1.0, mx + 9.0 * sx);
+    if (hi > lo) {
+      const double gx[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
+      const double gw[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
+      const double h = (hi - lo) / 64.0, c = lo + (q + 0.5) * h;
+      for (int n = 0; n < 8; n++) {
+        const double x = c + 0.5 * h * (n < 4 ? -gx[3 - n] : gx[n - 4]);
+        const double wgt = n < 4 ? gw[3 - n] : gw[n - 4];
+        const double m = my + bc * (x - mx), A = -m / sc, B = (1.0 - m) / sc;
+        const double d = A > 0.0 ? 0.5 * (erfc(A * 0.70710678118654752440) - erfc(B * 0.70710678118654752440))
+                                 : 0.5 * (erfc(-B * 0.70710678118654752440) - erfc(-A * 0.70710678118654752440));
+        const double t = (x - mx) / sx;
+        zq += wgt * exp(-0.5 * t * t) / (sx * kSqrt2Pi) * d;
+      }
+      zq *= 0.5 * h;
+    }
+  }
+  red[threadIdx.x] = zq;
+  __syncthreads();
+  // per component: a fixed tree over its 64 panels
+  for (int o = 32; o > 0; o >>= 1) {
+    if (q < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  double zm = 0.0;
+  for (int kk = 0; kk < kMaxG; kk++) {
+    const double c0 = P.pcov[p][kk][0], c1 = P.pcov[p][kk][1], c2 = P.pcov[p][kk][2];
+    const double det = c0 * c2 - c1 * c1;
+    const double l11 = sqrt(c0), l21 = c1 / l11;
+    P.pch[p][kk][0] = l11;
+    P.pch[p][kk][1] = l21;
+    P.pch[p][kk][2] = sqrt(fmax(c2 - l21 * l21, 0.0));
+    P.pic[p][kk][0] = c2 / det;
+    P.pic[p][kk][1] = -c1 / det;
+    P.pic[p][kk][2] = c0 / det;
+    const bool on = kk < K && P.pw[p][kk] > 0.0;
+    P.plog[p][kk] = on ? log(P.pw[p][kk]) - log(2.0 * kPi) - 0.5 * log(det) : -INFINITY;
+    if (on) zm += P.pw[p][kk] * red[64 * kk];
+  }
+  P.pzm[p] = zm;
+}
+
+hipError_t pair_norm_launch(ProposalDev *props, int p0, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pair_norm_kernel, dim3(n * kMaxPair), dim3(256), 0, st, props, p0);
+  return hipGetLastError();
+}
+
 __device__ bool next_perm(int *p, int n) {
   int i = n - 2;
   while (i >= 0 && p[i] >= p[i + 1]) i--;
@@ -644,7 +996,8 @@ __device__ bool next_perm(int *p, int n) {
 // permutations (the first minimum in lexicographic order), then combined
 // with the sample counts N (earlier rounds) and M (this round)
 __global__ void gmm_merge_kernel(const GmmDev *cur, const GmmDev *fit, int n_seg, const int *seg_prop,
-                                 const ReduceTuple *seg_round, ProposalDev *props, unsigned mask, double eps) {
+                                 const ReduceTuple *seg_round, ProposalDev *props, unsigned mask, unsigned mask_all,
+                                 double eps) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // one thread per (segment, parameter)
   if (idx >= n_seg * 7) return;
   const int seg = idx / 7, d = idx % 7;
@@ -703,33 +1056,54 @@ __global__ void gmm_merge_kernel(const GmmDev *cur, const GmmDev *fit, int n_seg
     P.gk = K;
     P.gntr = any ? N + M : N;
     P.geps = eps;
-    P.mask = mask;
+    P.mask = mask_all;
+    P.npair = C.npair;
+    for (int i = 0; i < kMaxPair; i++) {
+      P.pa[i] = C.pa[i];
+      P.pb[i] = C.pb[i];
+    }
   }
 }
 
 template <typename R>
 hipError_t gmm_adapt_launch(const float *ubuf, int64_t u_stride, const R *lnw, const int64_t *seg_off,
                             const int64_t *seg_cnt, const int *seg_prop, int n_seg, int bps,
-                            const ReduceTuple *seg_round, double *part, GmmDev *fit, ProposalDev *props,
-                            unsigned mask, double floor_eps, int K, int n_iter, hipStream_t st) {
+                            const ReduceTuple *seg_round, double *part, double *part2, GmmDev *fit,
+                            ProposalDev *props, unsigned mask, unsigned pairs, double floor_eps, int K, int n_iter,
+                            hipStream_t st) {
   if (n_seg <= 0) return hipSuccess;
-  const dim3 g1((n_seg + 63) / 64), g7((n_seg * 7 + 63) / 64);
-  hipLaunchKernelGGL(gmm_init_kernel, g1, dim3(64), 0, st, props, seg_prop, n_seg, K, fit, fit + n_seg);
-  for (int it = 0; it < n_iter; it++) {
-    hipLaunchKernelGGL(em_partials_kernel<R>, dim3(n_seg * bps), dim3(256), 0, st, ubuf, u_stride, lnw, seg_off,
-                       seg_cnt, bps, seg_round, fit + n_seg, mask, part);
-    hipLaunchKernelGGL(em_update_kernel, g7, dim3(64), 0, st, part, n_seg, bps, fit + n_seg, mask);
+  unsigned pm = 0u;  // parameters in pairs: not fitted one by one
+  for (int i = 0; i < kMaxPair; i++) {
+    const unsigned c = (pairs >> (8 * i)) & 0xFFu;
+    if (c) pm |= (1u << (c & 15u)) | (1u << (c >> 4));
   }
-  hipLaunchKernelGGL(gmm_merge_kernel, g7, dim3(64), 0, st, fit, fit + n_seg, n_seg, seg_prop, seg_round, props, mask,
-                     floor_eps);
+  const unsigned m1 = mask & ~pm;
+  const dim3 g1((n_seg + 63) / 64), g7((n_seg * 7 + 63) / 64), g3((n_seg * kMaxPair + 63) / 64);
+  hipLaunchKernelGGL(gmm_init_kernel, g1, dim3(64), 0, st, props, seg_prop, n_seg, K, pairs, fit, fit + n_seg);
+  for (int it = 0; it < n_iter; it++) {
+    if (m1) {
+      hipLaunchKernelGGL(em_partials_kernel<R>, dim3(n_seg * bps), dim3(256), 0, st, ubuf, u_stride, lnw, seg_off,
+                         seg_cnt, bps, seg_round, fit + n_seg, m1, part);
+      hipLaunchKernelGGL(em_update_kernel, g7, dim3(64), 0, st, part, n_seg, bps, fit + n_seg, m1);
+    }
+    if (pairs) {
+      hipLaunchKernelGGL(em_pair_partials_kernel<R>, dim3(n_seg * bps), dim3(256), 0, st, ubuf, u_stride, lnw,
+                         seg_off, seg_cnt, bps, seg_round, fit + n_seg, part2);
+      hipLaunchKernelGGL(em_pair_update_kernel, g3, dim3(64), 0, st, part2, n_seg, bps, fit + n_seg);
+    }
+  }
+  hipLaunchKernelGGL(gmm_merge_kernel, g7, dim3(64), 0, st, fit, fit + n_seg, n_seg, seg_prop, seg_round, props, m1,
+                     mask, floor_eps);
+  hipLaunchKernelGGL(gmm_pair_merge_kernel, g3, dim3(64), 0, st, fit, fit + n_seg, n_seg, seg_prop, seg_round, props);
   return hipGetLastError();
 }
 template hipError_t gmm_adapt_launch<float>(const float *, int64_t, const float *, const int64_t *, const int64_t *,
-                                            const int *, int, int, const ReduceTuple *, double *, GmmDev *,
-                                            ProposalDev *, unsigned, double, int, int, hipStream_t);
+                                            const int *, int, int, const ReduceTuple *, double *, double *, GmmDev *,
+                                            ProposalDev *, unsigned, unsigned, double, int, int, hipStream_t);
 template hipError_t gmm_adapt_launch<double>(const float *, int64_t, const double *, const int64_t *,
                                              const int64_t *, const int *, int, int, const ReduceTuple *, double *,
-                                             GmmDev *, ProposalDev *, unsigned, double, int, int, hipStream_t);
+                                             double *, GmmDev *, ProposalDev *, unsigned, unsigned, double, int, int,
+                                             hipStream_t);
 
 // host: the same normalizations for a mixture set by the caller
 void gmm_norms(ProposalDev &p) {

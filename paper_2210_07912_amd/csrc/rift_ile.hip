@@ -73,7 +73,7 @@ enum WsId {
   W_ITEM_POINT, W_ITEM_OFF, W_ITEM_CNT, W_ITEM_TILE0, W_ITEM_SAMP0, W_ITEM_BIN0,
   W_KEY, W_NSH, W_COUNT, W_CURSOR, W_COP, W_BINTILE, W_ITEMTILES, W_PERM, W_TILES, W_CTL, W_CTILE,
   W_PARTIALS, W_ROUND, W_ACCUM, W_RESULT, W_HIST, W_THETA, W_LNW, W_AUX, W_RATIO, W_BINS, W_ITEM_BLK0,
-  W_ITEM_HOFF, W_ITEM_COP, W_SEG_OFF, W_SEG_CNT, W_ASC, W_AHIST, W_UNIT, W_BINUNIT, W_ITEMUNITS, W_GOP, W_HOP, W_SEG_BLK, W_UBUF, W_EMPART, W_GMMFIT, W_COUNT_IDS
+  W_ITEM_HOFF, W_ITEM_COP, W_SEG_OFF, W_SEG_CNT, W_ASC, W_AHIST, W_UNIT, W_BINUNIT, W_ITEMUNITS, W_GOP, W_HOP, W_SEG_BLK, W_UBUF, W_EMPART, W_EMPART2, W_GMMFIT, W_COUNT_IDS
 };
 static_assert(W_COUNT_IDS <= 48, "workspace table too small");
 
@@ -761,6 +761,21 @@ rift_status reduce_segments(rift_ile *h, const R *lnL, const R *ln_ratio, const 
   return RIFT_OK;
 }
 
+// pairs code: byte i = a | b << 4, a < b < 7, both in mask, pairs disjoint
+rift_status check_pairs(rift_ile *h, unsigned pairs, unsigned mask) {
+  if (pairs >> (8 * kMaxPair)) return fail(h, RIFT_E_INVALID, "pairs 0x%x: at most %d", pairs, kMaxPair);
+  unsigned used = 0u;
+  for (int i = 0; i < kMaxPair; i++) {
+    const unsigned c = (pairs >> (8 * i)) & 0xFFu;
+    if (!c) continue;
+    const unsigned a = c & 15u, b = c >> 4;
+    if (!(a < b) || b >= 7u || !((mask >> a) & 1u) || !((mask >> b) & 1u) || ((used >> a) & 1u) || ((used >> b) & 1u))
+      return fail(h, RIFT_E_INVALID, "pair %d (%u, %u): need a < b < 7, both adapted, pairs disjoint", i, a, b);
+    used |= (1u << a) | (1u << b);
+  }
+  return RIFT_OK;
+}
+
 template <typename R>
 rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result *out, R *theta_out,
                                     R *lnw_out) {
@@ -820,18 +835,24 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
   if (gk < 0 || gk > kMaxG || mc->gmm_iters < 0 || mc->gmm_iters > 1000 || (gk > 0 && grad))
     return fail(h, RIFT_E_INVALID, "gmm_components %d (0..%d), gmm_iters %d (0..1000), or both a mixture and the "
                 "gradient refinement", gk, kMaxG, mc->gmm_iters);
+  if ((s = check_pairs(h, mc->gmm_pairs, mc->adapt_mask)) != RIFT_OK) return s;
+  if (mc->gmm_pairs && (gk == 0 || mc->n_rounds > (1 << 20)))
+    return fail(h, RIFT_E_INVALID, "correlated pairs need gmm_components > 0 and at most 2^20 rounds");
   const bool gmm = gk > 0 && mc->adapt_mask;
   float *ubuf = nullptr;
-  double *em_part = nullptr;
+  double *em_part = nullptr, *em_part2 = nullptr;
   GmmDev *em_fit = nullptr;
   const int ebps = em_blocks(mxc);
   if (gmm) {
-    void *pu, *pp, *pf;
+    void *pu, *pp, *pp2, *pf;
     if ((s = ws_get(h, W_UBUF, 7 * sizeof(float) * (size_t)nr, &pu)) != RIFT_OK) return s;
     if ((s = ws_get(h, W_EMPART, sizeof(double) * 7 * 3 * kMaxG * (size_t)np * ebps, &pp)) != RIFT_OK) return s;
+    if ((s = ws_get(h, W_EMPART2, sizeof(double) * kMaxPair * 6 * kMaxG * (size_t)np * ebps, &pp2)) != RIFT_OK)
+      return s;
     if ((s = ws_get(h, W_GMMFIT, 2 * sizeof(GmmDev) * (size_t)np, &pf)) != RIFT_OK) return s;
     ubuf = (float *)pu;
     em_part = (double *)pp;
+    em_part2 = (double *)pp2;
     em_fit = (GmmDev *)pf;
   }
   const int na = np * ka;
@@ -900,10 +921,12 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
         HIPCHK(h, ascent_hist(a_st, ka, np, mc->adapt_mask, h->d_min, h->d_max, h->tau_width,
                               h->net_frame ? h->d_pts : nullptr, ahist, h->stream));
       }
-      if (gmm)
-        HIPCHK(h, gmm_adapt_launch<R>(ubuf, nr, lw, d_soff, d_scnt, d_prop, np, ebps, round, em_part, em_fit,
-                                      h->d_props, mc->adapt_mask, mc->floor_eps, gk, giter, h->stream));
-      else
+      if (gmm) {
+        HIPCHK(h, gmm_adapt_launch<R>(ubuf, nr, lw, d_soff, d_scnt, d_prop, np, ebps, round, em_part, em_part2,
+                                      em_fit, h->d_props, mc->adapt_mask, mc->gmm_pairs, mc->floor_eps, gk, giter,
+                                      h->stream));
+        HIPCHK(h, pair_norm_launch(h->d_props, 0, np, h->stream));
+      } else
         HIPCHK(h, adapt_launch<R>((const uint8_t *)bins, nr, lw, d_soff, d_scnt, d_prop, np, hbps, round,
                                   (unsigned long long *)hist, h->d_props, mc->adapt_mask, mc->floor_eps, h->stream,
                                   grad ? ahist : nullptr, grad ? beta : 0.0));
@@ -1334,21 +1357,23 @@ rift_status rift_ile_set_gmm(rift_ile *h, int point, int K, unsigned mask, doubl
 }
 
 rift_status rift_ile_adapt_gmm(rift_ile *h, int point, int64_t n, const float *u, const void *lnw, unsigned mask,
-                               double floor_eps, int K, int n_iter) {
+                               unsigned pairs, double floor_eps, int K, int n_iter) {
   if (!h) return RIFT_E_INVALID;
   if (point < 0 || point >= h->n_points) return fail(h, RIFT_E_INVALID, "point %d", point);
   if (n < 0 || (n > 0 && (!u || !lnw))) return fail(h, RIFT_E_INVALID, "bad adapt_gmm arguments");
   if (!(floor_eps > 0.0 && floor_eps <= 1.0)) return fail(h, RIFT_E_INVALID, "floor_eps %g", floor_eps);
   if ((mask >> 7) || K < 1 || K > kMaxG || n_iter < 1 || n_iter > 1000)
     return fail(h, RIFT_E_INVALID, "mask 0x%x, K %d (1..%d) or n_iter %d (1..1000)", mask, K, kMaxG, n_iter);
+  rift_status s;
+  if ((s = check_pairs(h, pairs, mask)) != RIFT_OK) return s;
   std::vector<int64_t> off(1, 0), cnt(1, n);
   std::vector<int> sp(1, point);
   ReduceTuple *round;
-  rift_status s;
   int *d_sp;
-  void *part, *fit;
+  void *part, *part2, *fit;
   const int bps = em_blocks(n);
   if ((s = ws_get(h, W_EMPART, sizeof(double) * 7 * 3 * kMaxG * bps, &part)) != RIFT_OK) return s;
+  if ((s = ws_get(h, W_EMPART2, sizeof(double) * kMaxPair * 6 * kMaxG * bps, &part2)) != RIFT_OK) return s;
   if ((s = ws_get(h, W_GMMFIT, 2 * sizeof(GmmDev), &fit)) != RIFT_OK) return s;
   if (h->precision == RIFT_FP32) {
     if ((s = reduce_segments<float>(h, (const float *)lnw, nullptr, off, cnt, &round, nullptr, 0, nullptr)) != RIFT_OK)
@@ -1356,7 +1381,8 @@ rift_status rift_ile_adapt_gmm(rift_ile *h, int point, int64_t n, const float *u
     if ((s = upload(h, W_AUX, sp, &d_sp)) != RIFT_OK) return s;
     int64_t *d_off = (int64_t *)h->ws[W_ITEM_OFF].p, *d_cnt = (int64_t *)h->ws[W_ITEM_CNT].p;
     HIPCHK(h, gmm_adapt_launch<float>(u, n, (const float *)lnw, d_off, d_cnt, d_sp, 1, bps, round, (double *)part,
-                                      (GmmDev *)fit, h->d_props, mask, floor_eps, K, n_iter, h->stream));
+                                      (double *)part2, (GmmDev *)fit, h->d_props, mask, pairs, floor_eps, K, n_iter,
+                                      h->stream));
   } else {
     if ((s = reduce_segments<double>(h, (const double *)lnw, nullptr, off, cnt, &round, nullptr, 0, nullptr)) !=
         RIFT_OK)
@@ -1364,7 +1390,75 @@ rift_status rift_ile_adapt_gmm(rift_ile *h, int point, int64_t n, const float *u
     if ((s = upload(h, W_AUX, sp, &d_sp)) != RIFT_OK) return s;
     int64_t *d_off = (int64_t *)h->ws[W_ITEM_OFF].p, *d_cnt = (int64_t *)h->ws[W_ITEM_CNT].p;
     HIPCHK(h, gmm_adapt_launch<double>(u, n, (const double *)lnw, d_off, d_cnt, d_sp, 1, bps, round, (double *)part,
-                                       (GmmDev *)fit, h->d_props, mask, floor_eps, K, n_iter, h->stream));
+                                       (double *)part2, (GmmDev *)fit, h->d_props, mask, pairs, floor_eps, K, n_iter,
+                                       h->stream));
+  }
+  HIPCHK(h, pair_norm_launch(h->d_props, point, 1, h->stream));
+  return RIFT_OK;
+}
+
+rift_status rift_ile_set_gmm_pairs(rift_ile *h, int point, unsigned pairs, const double *w, const double *mu,
+                                   const double *cov) {
+  if (!h) return RIFT_E_INVALID;
+  if (point < 0 || point >= h->n_points || (pairs && (!w || !mu || !cov)))
+    return fail(h, RIFT_E_INVALID, "bad set_gmm_pairs arguments");
+  ProposalDev pr;
+  HIPCHK(h, hipMemcpyAsync(&pr, h->d_props + point, sizeof(pr), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (pr.gk < 1) return fail(h, RIFT_E_INVALID, "point %d holds no mixture (rift_ile_set_gmm first)", point);
+  rift_status s = check_pairs(h, pairs, pr.mask);
+  if (s != RIFT_OK) return s;
+  pr.npair = 0;
+  for (int i = 0; i < kMaxPair; i++) {
+    const unsigned c = (pairs >> (8 * i)) & 0xFFu;
+    if (!c) continue;
+    const int p = pr.npair++;
+    pr.pa[p] = (int)(c & 15u);
+    pr.pb[p] = (int)(c >> 4);
+    double tot = 0.0;
+    for (int k = 0; k < kMaxG; k++) {
+      const double *m = mu + (p * kMaxG + k) * 2, *c3 = cov + (p * kMaxG + k) * 3;
+      const double wk = k < pr.gk ? w[p * kMaxG + k] : 0.0;
+      const bool on = k < pr.gk;
+      const double xx = on ? c3[0] : 0.25, xy = on ? c3[1] : 0.0, yy = on ? c3[2] : 0.25;
+      if (!(wk >= 0.0) || (on && !(m[0] >= 0.0 && m[0] <= 1.0 && m[1] >= 0.0 && m[1] <= 1.0)) || !(xx > 0.0) ||
+          !(yy > 0.0) || !(std::fabs(xy) < std::sqrt(xx * yy)) || !std::isfinite(xx * yy))
+        return fail(h, RIFT_E_INVALID, "component %d of pair %d", k, p);
+      pr.pw[p][k] = wk;
+      pr.pmu[p][k][0] = on ? m[0] : 0.5;
+      pr.pmu[p][k][1] = on ? m[1] : 0.5;
+      pr.pcov[p][k][0] = xx;
+      pr.pcov[p][k][1] = xy;
+      pr.pcov[p][k][2] = yy;
+      tot += wk;
+    }
+    if (!(std::fabs(tot - 1.0) < 1e-9)) return fail(h, RIFT_E_INVALID, "weights of pair %d sum to %g", p, tot);
+  }
+  HIPCHK(h, hipMemcpyAsync(h->d_props + point, &pr, sizeof(pr), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, pair_norm_launch(h->d_props, point, 1, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return RIFT_OK;
+}
+
+rift_status rift_ile_get_gmm_pairs(rift_ile *h, int point, unsigned *pairs, double *w, double *mu, double *cov,
+                                   double *box_mass) {
+  if (!h) return RIFT_E_INVALID;
+  if (point < 0 || point >= h->n_points || !pairs) return fail(h, RIFT_E_INVALID, "bad get_gmm_pairs arguments");
+  ProposalDev pr;
+  HIPCHK(h, hipMemcpyAsync(&pr, h->d_props + point, sizeof(pr), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  *pairs = 0u;
+  const int np = pr.gk > 0 ? pr.npair : 0;
+  for (int p = 0; p < np; p++) *pairs |= (unsigned)(pr.pa[p] | (pr.pb[p] << 4)) << (8 * p);
+  for (int p = 0; p < kMaxPair; p++) {
+    if (box_mass) box_mass[p] = p < np ? pr.pzm[p] : 0.0;
+    for (int k = 0; k < kMaxG; k++) {
+      if (w) w[p * kMaxG + k] = p < np ? pr.pw[p][k] : 0.0;
+      for (int q = 0; q < 2; q++)
+        if (mu) mu[(p * kMaxG + k) * 2 + q] = p < np ? pr.pmu[p][k][q] : 0.0;
+      for (int q = 0; q < 3; q++)
+        if (cov) cov[(p * kMaxG + k) * 3 + q] = p < np ? pr.pcov[p][k][q] : 0.0;
+    }
   }
   return RIFT_OK;
 }

@@ -66,11 +66,23 @@ class MC(C.Structure):
                 ("n_rounds", C.c_int), ("adapt_mask", C.c_uint), ("floor_eps", C.c_double),
                 ("reset_proposal", C.c_int), ("flags", C.c_uint), ("n_ascent", C.c_int),
                 ("ascent_steps", C.c_int), ("ascent_mix", C.c_double), ("gmm_components", C.c_int),
-                ("gmm_iters", C.c_int)]
+                ("gmm_iters", C.c_int), ("gmm_pairs", C.c_uint)]
 
 
 RIFT_MC_GRADIENT = 1
 GMM_MAX = 4  # mixture components per parameter
+
+
+def encode_pairs(pairs):
+    """[(a, b), ...] -> byte code (byte i = a | b << 4)."""
+    code = 0
+    for i, (a, b) in enumerate(pairs):
+        code |= (int(a) | int(b) << 4) << (8 * i)
+    return code
+
+
+def decode_pairs(code):
+    return [((code >> (8 * i)) & 15, (code >> (8 * i + 4)) & 15) for i in range(3) if (code >> (8 * i)) & 0xFF]
 
 
 FUNCTIONS = {
@@ -100,8 +112,12 @@ FUNCTIONS = {
                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "rift_ile_set_gmm": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_uint, C.c_double, C.c_double,
                                    C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
-    "rift_ile_adapt_gmm": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_uint,
+    "rift_ile_adapt_gmm": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_uint, C.c_uint,
                                      C.c_double, C.c_int, C.c_int]),
+    "rift_ile_set_gmm_pairs": (C.c_int, [C.c_void_p, C.c_int, C.c_uint, C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "rift_ile_get_gmm_pairs": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_uint), C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "rift_ile_marginalize": (C.c_int, [C.c_void_p, C.POINTER(MC), C.POINTER(Result), C.c_void_p, C.c_void_p]),
     "rift_ile_backward": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(Item), C.c_int64, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p]),
@@ -299,18 +315,35 @@ class RiftILE:
             arrs.append(np.ascontiguousarray(x))
         self._check(lib().rift_ile_set_gmm(self.h, point, K, mask, floor_eps, n_trained, *(_dptr(a) for a in arrs)))
 
-    def adapt_gmm(self, point, u, lnw, mask, floor_eps, K, n_iter):
+    def adapt_gmm(self, point, u, lnw, mask, floor_eps, K, n_iter, pairs=()):
         u = torch.as_tensor(u, device=self.device, dtype=torch.float32).contiguous()
         lnw = torch.as_tensor(lnw, device=self.device, dtype=self.dtype).contiguous()
-        self._check(lib().rift_ile_adapt_gmm(self.h, point, lnw.numel(), _ptr(u), _ptr(lnw), mask, floor_eps, K,
-                                             n_iter))
+        self._check(lib().rift_ile_adapt_gmm(self.h, point, lnw.numel(), _ptr(u), _ptr(lnw), mask,
+                                             encode_pairs(pairs), floor_eps, K, n_iter))
+
+    def set_gmm_pairs(self, point, pairs, w, mu, cov):
+        """pairs: list of (a, b); w [P, K], mu [P, K, 2], cov [P, K, 3]."""
+        W, MU, CV = np.zeros((3, GMM_MAX)), np.zeros((3, GMM_MAX, 2)), np.zeros((3, GMM_MAX, 3))
+        for i in range(len(pairs)):
+            k = np.asarray(w[i]).shape[0]
+            W[i, :k], MU[i, :k], CV[i, :k] = w[i], mu[i], cov[i]
+        self._check(lib().rift_ile_set_gmm_pairs(self.h, point, encode_pairs(pairs), _dptr(W), _dptr(MU),
+                                                 _dptr(CV)))
+
+    def get_gmm_pairs(self, point):
+        code = C.c_uint()
+        W, MU, CV, Z = np.zeros((3, GMM_MAX)), np.zeros((3, GMM_MAX, 2)), np.zeros((3, GMM_MAX, 3)), np.zeros(3)
+        self._check(lib().rift_ile_get_gmm_pairs(self.h, point, C.byref(code), _dptr(W), _dptr(MU), _dptr(CV),
+                                                 _dptr(Z)))
+        return dict(pairs=decode_pairs(code.value), w=W, mu=MU, cov=CV, box_mass=Z)
 
     def marginalize(self, seed, n_per_point, n_rounds=1, adapt_mask=0, floor_eps=0.1, reset=True,
                     return_samples=False, gradient=False, n_ascent=0, ascent_steps=0, ascent_mix=0.0,
-                    gmm_components=0, gmm_iters=0):
+                    gmm_components=0, gmm_iters=0, gmm_pairs=()):
         npp = np.ascontiguousarray(np.broadcast_to(np.asarray(n_per_point, dtype=np.int64), (self.n_points,)))
         mc = MC(seed, 0, npp.ctypes.data_as(C.POINTER(C.c_int64)), n_rounds, adapt_mask, floor_eps, int(reset),
-                RIFT_MC_GRADIENT if gradient else 0, n_ascent, ascent_steps, ascent_mix, gmm_components, gmm_iters)
+                RIFT_MC_GRADIENT if gradient else 0, n_ascent, ascent_steps, ascent_mix, gmm_components, gmm_iters,
+                encode_pairs(gmm_pairs))
         res = (Result * self.n_points)()
         th = lw = None
         if return_samples:

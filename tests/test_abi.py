@@ -52,9 +52,11 @@ def test_host_only_calls():
     assert L.rift_ile_autotune_table(None, None) == -1
     assert L.rift_ile_get_gmm(None, 0, None, None, None, None, None, None, None) == -1
     assert L.rift_ile_set_gmm(None, 0, 1, 1, 0.1, 0.0, None, None, None) == -1
-    assert L.rift_ile_adapt_gmm(None, 0, 0, None, None, 1, 0.1, 1, 1) == -1
+    assert L.rift_ile_adapt_gmm(None, 0, 0, None, None, 1, 0, 0.1, 1, 1) == -1
+    assert L.rift_ile_set_gmm_pairs(None, 0, 0, None, None, None) == -1
+    assert L.rift_ile_get_gmm_pairs(None, 0, None, None, None, None, None) == -1
     # the Monte Carlo descriptor matches the binding's layout (mixture fields last)
-    assert ctypes.sizeof(ile.MC) == 72 and ile.MC.gmm_iters.offset == 68
+    assert ctypes.sizeof(ile.MC) == 80 and ile.MC.gmm_pairs.offset == 72
 
 
 def test_binding_refuses_without_device():

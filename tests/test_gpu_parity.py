@@ -1094,3 +1094,134 @@ def test_gmm_set_validates(ile):
     h.set_proposal(0, cdf, 0x3F)
     assert h.get_gmm(0)["K"] == 0
     h.close()
+
+
+# --- correlated pairs of the mixture proposal ---------------------------------
+
+def _pair_model(gmm):
+    g = _gmm_model(gmm)
+    g.mask = 0b0111101
+    g.pairs = [(2, 4), (3, 5)]
+    g.pw = [np.array([0.7, 0.2, 0.1]), np.array([0.5, 0.5, 0.0])]
+    g.pmu = [np.array([[0.3, 0.6], [0.8, 0.1], [0.02, 0.97]]), np.array([[0.5, 0.5], [0.1, 0.9], [0.5, 0.5]])]
+    g.pcov = [np.array([[0.01, 0.008, 0.01], [0.04, -0.01, 0.01], [0.001, 0.0, 0.002]]),
+              np.array([[0.2, 0.1, 0.1], [0.0004, -0.00039, 0.0004], [0.1, 0.0, 0.1]])]
+    return g
+
+
+def _set_pairs(h, point, g):
+    _set_gmm(h, point, g)
+    h.set_gmm_pairs(point, g.pairs, g.pw, g.pmu, g.pcov)
+
+
+def test_gmm_pair_draws_match_oracle(ile, orc):
+    """Correlated pairs: rejection draws from the untruncated bivariate
+    mixture, the pair density with its box mass, discards, against the
+    oracle on the same Philox streams."""
+    from oracle import gmm
+    d = synth.make_point(synth.workload("tiny").points[0])
+    g = _pair_model(gmm)
+    n, first, seed = 3001, 123, 2210079129
+    ref_th, ref_lr, _ = gmm.draw(seed, 0, 3, n, g, start=first)
+    zref = [sum(g.pw[i][k] * gmm.box_mass(g.pmu[i][k], g.pcov[i][k]) for k in range(3) if g.pw[i][k] > 0)
+            for i in range(2)]
+    for prec in ("fp64", "fp32"):
+        _say(f"gmm pair draws {prec}")
+        h = _handle(ile, [d], prec)
+        _set_pairs(h, 0, g)
+        got = h.get_gmm_pairs(0)
+        assert got["pairs"] == g.pairs
+        assert np.abs(got["box_mass"][:2] - zref).max() < 1e-12
+        th, lr, _ = h.sample(0, seed, 3, n, first=first)
+        th, lr = th.cpu().numpy(), lr.cpu().numpy()
+        assert np.array_equal(np.isnan(lr), np.isnan(ref_lr))
+        fin = np.isfinite(ref_lr)
+        if prec == "fp64":
+            assert np.abs(th - ref_th).max() < 1e-9
+            assert np.abs(lr[fin] - ref_lr[fin]).max() < 1e-10
+        else:
+            assert np.all(np.abs(th - ref_th) <= 2e-7 * np.abs(ref_th) + 1e-7)
+            assert np.abs(lr[fin] - ref_lr[fin]).max() < 1e-5
+        h.close()
+
+
+def test_gmm_pair_adapt_matches_oracle(ile, orc):
+    """Bivariate weighted EM and the pair online update on the device against
+    the oracle, beside a one-dimensional parameter, from the initial mixture
+    and then merged."""
+    from oracle import gmm
+    d = synth.make_point(synth.workload("tiny").points[0])
+    n = 16411
+    rng = np.random.default_rng(13)
+    _, _, u = gmm.draw(31, 0, 0, n, None)
+    u32 = u.astype(np.float32)
+    uu = u32.astype(np.float64)
+    dx, dy = (uu[2] - 0.4) / 0.08, (uu[4] - 0.6) / 0.05
+    lnw = -0.5 * (dx * dx - 1.6 * dx * dy + dy * dy) / 0.36 - 0.5 * ((uu[0] - 0.2) / 0.1) ** 2
+    lnw += 0.2 * rng.normal(size=n)
+    lnw[[3, 77]] = [np.nan, -np.inf]
+    mask, eps, K, it, pairs = 0b0010101, 0.05, 2, 12, [(2, 4)]
+    h = _handle(ile, [d], "fp64")
+    ref = None
+    for step in range(2):
+        lw_s = lnw if step == 0 else lnw[::-1].copy()
+        ref = gmm.adapt(ref, uu, lw_s, K=K, mask=mask, eps=eps, n_iter=it, pairs=pairs)
+        h.adapt_gmm(0, torch.tensor(u32), torch.tensor(lw_s), mask, eps, K, it, pairs=pairs)
+        got, gp = h.get_gmm(0), h.get_gmm_pairs(0)
+        assert got["K"] == K and got["mask"] == mask and gp["pairs"] == pairs
+        assert got["n_trained"] == ref.n_trained == (step + 1) * (n - 1)
+        for name in ("w", "mu", "sd"):
+            assert np.abs(got[name][0, :K] - getattr(ref, name)[0]).max() < 1e-10, (step, name)
+        assert np.abs(gp["w"][0, :K] - ref.pw[0]).max() < 1e-10
+        assert np.abs(gp["mu"][0, :K] - ref.pmu[0]).max() < 1e-10
+        assert np.abs(gp["cov"][0, :K] - ref.pcov[0]).max() < 1e-11
+        zref = sum(ref.pw[0][k] * gmm.box_mass(ref.pmu[0][k], ref.pcov[0][k]) for k in range(K))
+        assert abs(gp["box_mass"][0] - zref) < 1e-12
+    h.close()
+
+
+def test_marginalize_gmm_pairs_matches_oracle(ile, orc):
+    """Adaptive run with correlated pairs (psi, phi) and (iota, D) beside
+    one-dimensional mixtures of the sky: FP64 through the first adapted round
+    sample by sample (1e-8), estimates within the Monte Carlo error."""
+    from oracle import gmm
+    w = synth.workload("tiny_batched")
+    pts = [synth.make_point(s) for s in w.points[:2]]
+    counts = [2500, 2000]
+    seed, rounds, mask, eps, K, it = 2210079130, 3, 0x3F, 0.1, 2, 8
+    pairs = [(2, 4), (3, 5)]
+    ops = [orc.Point.from_dict(d, complex64=False) for d in pts]
+    gs = [None] * len(pts)
+    lnw_all = [[] for _ in pts]
+    trace = []
+    for r in range(rounds):
+        for i, (p, n) in enumerate(zip(ops, counts)):
+            th, lr, u = gmm.draw(seed, i, r, n, gs[i])
+            lnw = orc.lnL_t(p, th) + lr
+            lnw_all[i].append(lnw)
+            trace.append((r, i, th))
+            if r + 1 < rounds:
+                gs[i] = gmm.adapt(gs[i], u.astype(np.float32).astype(np.float64), lnw, K=K, mask=mask, eps=eps,
+                                  n_iter=it, pairs=pairs)
+    ref = [orc.reduce(np.concatenate(x)) for x in lnw_all]
+    _say("gmm pairs marginalize fp64")
+    h = _handle(ile, pts, "fp64")
+    res, th, lw = h.marginalize(seed, counts, n_rounds=rounds, adapt_mask=mask, floor_eps=eps, gmm_components=K,
+                                gmm_iters=it, gmm_pairs=pairs, return_samples=True)
+    per_round = sum(counts)
+    offs = np.concatenate([[0], np.cumsum(counts)])
+    thn = th.cpu().numpy()
+    for r, i, oth in trace:
+        c0 = r * per_round + offs[i]
+        dth = np.abs(thn[:, c0:c0 + counts[i]] - oth)
+        dmax = np.nanmax(dth) if np.isfinite(dth).any() else 0.0
+        _say(f"  round {r} point {i}: max|dtheta|={dmax:.2e}")
+        if r < 2:
+            assert dmax < 1e-8
+    for i, (r, o) in enumerate(zip(res, ref)):
+        _say(f"  point {i}: gpu {r['lnL_marg']:.9f} oracle {o['lnL_marg']:.9f} n_eff {r['n_eff']:.1f}/{o['n_eff']:.1f} "
+             f"discarded {r['n_nonfinite']}/{o['n_nonfinite']}")
+        sig = math.hypot(r["sigma_lnL"], o["sigma_lnL"])
+        assert abs(r["lnL_marg"] - o["lnL_marg"]) < 1e-3 + 4 * sig
+        assert h.get_gmm_pairs(i)["pairs"] == pairs
+    h.close()
