@@ -236,14 +236,18 @@ def main():
         # iterations per round) against the histograms, equatorial frame
         hs.set_network_frame(False)
         gm = {}
-        for name, kk in (("histogram", 0), ("gmm_k3", 3)):
-            hs.marginalize(seed + 12, 100_000, n_rounds=2, adapt_mask=0x3F, floor_eps=0.1, gmm_components=kk)
+        # correlated pairs (psi, phi) and (iota, D): the pairs the polarization-phase and
+        # inclination-distance degeneracies tie together
+        for name, kk, pr in (("histogram", 0, ()), ("gmm_k3", 3, ()), ("gmm_k3_pairs", 3, ((2, 4), (3, 5)))):
+            hs.marginalize(seed + 12, 100_000, n_rounds=2, adapt_mask=0x3F, floor_eps=0.1, gmm_components=kk,
+                           gmm_pairs=pr)
             torch.cuda.synchronize()
             t2 = time.perf_counter()
-            r = hs.marginalize(seed + 13, 100_000, n_rounds=10, adapt_mask=0x3F, floor_eps=0.1, gmm_components=kk)
+            r = hs.marginalize(seed + 13, 100_000, n_rounds=10, adapt_mask=0x3F, floor_eps=0.1, gmm_components=kk,
+                               gmm_pairs=pr)
             torch.cuda.synchronize()
             t3 = time.perf_counter()
-            gm[name] = {"ms": (t3 - t2) * 1e3, "n_eff": [x["n_eff"] for x in r],
+            gm[name] = {"ms": (t3 - t2) * 1e3, "n_eff": [x["n_eff"] for x in r], "discarded": [x["n_nonfinite"] for x in r],
                         "sigma_lnL": [x["sigma_lnL"] for x in r], "lnL_marg": [x["lnL_marg"] for x in r]}
         hs.close()
         out["gmm"] = {"points": len(sub), "rounds": 10, "samples_per_round": 100_000, "floor_eps": 0.1, **gm}
