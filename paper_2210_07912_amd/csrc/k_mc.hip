@@ -109,7 +109,9 @@ __device__ __forceinline__ void gmm_stage(const ProposalDev *prop, GmmSh &g) {
 // component from a second Philox block (counter word 2: 2^31 | (2 round +
 // half)): below the floor eps the uniform, else component k by the mixture
 // weights, then u by the component's truncated-normal inverse CDF at v.
-template <typename R>
+// MIX = false: no point of the launch holds a mixture (the mixture code is
+// compiled out, which keeps the common sampler's registers low)
+template <typename R, bool MIX>
 __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned mask, const GmmSh *g, uint32_t point,
                                          uint64_t seed, uint32_t round, uint64_t i, double d_min, double d_max,
                                          double tau_width, const PointDev *pt, R *theta, int64_t stride, R *ln_ratio,
@@ -120,7 +122,7 @@ __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned 
     philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
     for (int q = 0; q < 4; q++) r[4 * half + q] = c[q];
   }
-  const int gk = g->k;
+  const int gk = MIX ? g->k : 0;
   if (gk > 0 && mask) {
     for (int half = 0; half < 2; half++) {
       uint32_t c[4] = {(uint32_t)i, (uint32_t)(i >> 32), 0x80000000u | (2u * round + (uint32_t)half), point};
@@ -130,7 +132,8 @@ __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned 
   }
   double lr = 0.0, us[2] = {0.0, 0.0};
   unsigned pm = 0u;  // parameters drawn in correlated pairs (after this loop)
-  for (int p = 0; p < g->npair; p++) pm |= (1u << g->pa[p]) | (1u << g->pb[p]);
+  const int npair = MIX ? g->npair : 0;
+  for (int p = 0; p < npair; p++) pm |= (1u << g->pa[p]) | (1u << g->pb[p]);
 #pragma unroll
   for (int d = 0; d < 7; d++) {
     double v = u01(r[d]);
@@ -182,7 +185,7 @@ __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned 
   // 3 2^30 | round << 10 | pair << 8 | try), the first inside the unit
   // square kept; none inside: the sample is discarded (ln ratio NaN)
   bool discard = false;
-  for (int p = 0; p < g->npair; p++) {
+  for (int p = 0; p < npair; p++) {
     const int a = g->pa[p], b = g->pb[p];
     double ua = u01(r[a]), ub = u01(r[b]);
     const double eps = g->eps, ca = u01(e[a]);
@@ -244,7 +247,7 @@ __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned 
   if (ln_ratio) ln_ratio[col] = (R)lr;
 }
 
-template <typename R>
+template <typename R, bool MIX>
 __global__ void __launch_bounds__(256) sample_kernel(const ProposalDev *prop, const PointDev *pt, uint32_t point,
                                                      uint64_t seed, uint32_t round, int64_t first, int64_t n,
                                                      int64_t stride, int64_t bin_stride, double d_min, double d_max,
@@ -255,17 +258,17 @@ __global__ void __launch_bounds__(256) sample_kernel(const ProposalDev *prop, co
   __shared__ GmmSh g;
   for (int i = threadIdx.x; i < 7 * (kNB + 1); i += blockDim.x) cdf[i / (kNB + 1)][i % (kNB + 1)] = prop->cdf[i / (kNB + 1)][i % (kNB + 1)];
   if (threadIdx.x == 0) mask = prop->mask;
-  gmm_stage(prop, g);
+  if (MIX) gmm_stage(prop, g);
   __syncthreads();
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  draw_one<R>(cdf, mask, &g, point, seed, round, (uint64_t)(first + j), d_min, d_max, tau_width, pt, theta, stride,
+  draw_one<R, MIX>(cdf, mask, &g, point, seed, round, (uint64_t)(first + j), d_min, d_max, tau_width, pt, theta, stride,
               ln_ratio, bins, bin_stride, j, ubuf);
 }
 
 // every point of a round in one launch: blocks [blk0[p], blk0[p + 1]) draw
 // point p's samples into columns off[p] ..
-template <typename R>
+template <typename R, bool MIX>
 __global__ void __launch_bounds__(256) sample_multi_kernel(const ProposalDev *props, const PointDev *pts,
                                                            const int *blk0, int np, const int64_t *off,
                                                            const int64_t *cnt, uint64_t seed, uint32_t round,
@@ -284,22 +287,28 @@ __global__ void __launch_bounds__(256) sample_multi_kernel(const ProposalDev *pr
   const ProposalDev *prop = props + p;
   for (int i = threadIdx.x; i < 7 * (kNB + 1); i += blockDim.x) cdf[i / (kNB + 1)][i % (kNB + 1)] = prop->cdf[i / (kNB + 1)][i % (kNB + 1)];
   if (threadIdx.x == 0) mask = prop->mask;
-  gmm_stage(prop, g);
+  if (MIX) gmm_stage(prop, g);
   __syncthreads();
   const int64_t j = (int64_t)(blockIdx.x - blk0[p]) * blockDim.x + threadIdx.x;
   if (j >= cnt[p]) return;
-  draw_one<R>(cdf, mask, &g, (uint32_t)p, seed, round, (uint64_t)j, d_min, d_max, tau_width, pts ? pts + p : nullptr,
+  draw_one<R, MIX>(cdf, mask, &g, (uint32_t)p, seed, round, (uint64_t)j, d_min, d_max, tau_width, pts ? pts + p : nullptr,
               theta, stride, ln_ratio, bins, bin_stride, off[p] + j, ubuf);
 }
 
 template <typename R>
 hipError_t sample_launch(const PointDev *pt, const ProposalDev *prop, int point, uint64_t seed, uint32_t round,
                          int64_t first, int64_t n, int64_t stride, int64_t bin_stride, double d_min, double d_max,
-                         double tau_width, R *theta, R *ln_ratio, uint8_t *bins, hipStream_t st, float *ubuf) {
+                         double tau_width, R *theta, R *ln_ratio, uint8_t *bins, hipStream_t st, float *ubuf,
+                         bool mix) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sample_kernel<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, prop, pt,
-                     (uint32_t)point, seed, round, first, n, stride, bin_stride, d_min, d_max, tau_width, theta,
-                     ln_ratio, bins, ubuf);
+  if (mix)
+    hipLaunchKernelGGL((sample_kernel<R, true>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, prop, pt,
+                       (uint32_t)point, seed, round, first, n, stride, bin_stride, d_min, d_max, tau_width, theta,
+                       ln_ratio, bins, ubuf);
+  else
+    hipLaunchKernelGGL((sample_kernel<R, false>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, prop, pt,
+                       (uint32_t)point, seed, round, first, n, stride, bin_stride, d_min, d_max, tau_width, theta,
+                       ln_ratio, bins, ubuf);
   return hipGetLastError();
 }
 
@@ -307,26 +316,32 @@ template <typename R>
 hipError_t sample_multi_launch(const ProposalDev *props, const PointDev *pts, const int *blk0, int n_blocks, int np,
                                const int64_t *off, const int64_t *cnt, uint64_t seed, uint32_t round, int64_t stride,
                                int64_t bin_stride, double d_min, double d_max, double tau_width, R *theta,
-                               R *ln_ratio, uint8_t *bins, hipStream_t st, float *ubuf) {
+                               R *ln_ratio, uint8_t *bins, hipStream_t st, float *ubuf, bool mix) {
   if (n_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sample_multi_kernel<R>, dim3((unsigned)n_blocks), dim3(256), 0, st, props, pts, blk0, np, off,
-                     cnt, seed, round, stride, bin_stride, d_min, d_max, tau_width, theta, ln_ratio, bins, ubuf);
+  if (mix)
+    hipLaunchKernelGGL((sample_multi_kernel<R, true>), dim3((unsigned)n_blocks), dim3(256), 0, st, props, pts, blk0,
+                       np, off, cnt, seed, round, stride, bin_stride, d_min, d_max, tau_width, theta, ln_ratio, bins,
+                       ubuf);
+  else
+    hipLaunchKernelGGL((sample_multi_kernel<R, false>), dim3((unsigned)n_blocks), dim3(256), 0, st, props, pts, blk0,
+                       np, off, cnt, seed, round, stride, bin_stride, d_min, d_max, tau_width, theta, ln_ratio, bins,
+                       ubuf);
   return hipGetLastError();
 }
 template hipError_t sample_multi_launch<float>(const ProposalDev *, const PointDev *, const int *, int, int,
                                                const int64_t *,
                                                const int64_t *, uint64_t, uint32_t, int64_t, int64_t, double, double,
-                                               double, float *, float *, uint8_t *, hipStream_t, float *);
+                                               double, float *, float *, uint8_t *, hipStream_t, float *, bool);
 template hipError_t sample_multi_launch<double>(const ProposalDev *, const PointDev *, const int *, int, int,
                                                 const int64_t *,
                                                 const int64_t *, uint64_t, uint32_t, int64_t, int64_t, double, double,
-                                                double, double *, double *, uint8_t *, hipStream_t, float *);
+                                                double, double *, double *, uint8_t *, hipStream_t, float *, bool);
 template hipError_t sample_launch<float>(const PointDev *, const ProposalDev *, int, uint64_t, uint32_t, int64_t,
                                          int64_t, int64_t, int64_t, double, double, double, float *, float *,
-                                         uint8_t *, hipStream_t, float *);
+                                         uint8_t *, hipStream_t, float *, bool);
 template hipError_t sample_launch<double>(const PointDev *, const ProposalDev *, int, uint64_t, uint32_t, int64_t,
                                           int64_t, int64_t, int64_t, double, double, double, double *, double *,
-                                          uint8_t *, hipStream_t, float *);
+                                          uint8_t *, hipStream_t, float *, bool);
 
 // ---------------------------------------------------------------------------
 // FP64 reduction

@@ -38,6 +38,7 @@ struct rift_ile {
   std::string err;
   int n_points = 0;
   double d_min = 10.0, d_max = 1000.0, tau_width = 0.0;
+  bool any_mix = false;  // some point may hold a Gaussian-mixture proposal (sampler variant)
   std::vector<PointDev> hp;       // host copies (device pointers inside)
   std::vector<void *> owned;      // per-point allocations
   PointDev *d_pts = nullptr;
@@ -798,6 +799,7 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
     std::vector<ProposalDev> props(np);
     for (auto &p : props) uniform_proposal(p);
     HIPCHK(h, hipMemcpyAsync(h->d_props, props.data(), sizeof(ProposalDev) * np, hipMemcpyHostToDevice, h->stream));
+    h->any_mix = false;
   }
   void *accum, *d_res, *bins, *hist, *ratio, *th_ws = nullptr, *lw_ws = nullptr;
   if ((s = ws_get(h, W_ACCUM, sizeof(ReduceTuple) * np, &accum)) != RIFT_OK) return s;
@@ -854,6 +856,7 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
     em_part = (double *)pp;
     em_part2 = (double *)pp2;
     em_fit = (GmmDev *)pf;
+    h->any_mix = true;
   }
   const int na = np * ka;
   int *a_idx = nullptr;
@@ -897,7 +900,7 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
     HIPCHK(h, sample_multi_launch<R>(h->d_props, h->net_frame ? h->d_pts : nullptr, d_sblk, sblk[np], np, d_soff,
                                      d_scnt, mc->seed, (uint32_t)r,
                                      th_stride, nr, h->d_min, h->d_max, h->tau_width, th, (R *)ratio,
-                                     (uint8_t *)bins, h->stream, ubuf));
+                                     (uint8_t *)bins, h->stream, ubuf, h->any_mix));
     if ((s = eval<R>(h, it, th_stride, th, nullptr, lw, (const R *)ratio)) != RIFT_OK) return s;
     ReduceTuple *round;
     const bool last = r + 1 == mc->n_rounds;
@@ -1200,11 +1203,12 @@ rift_status rift_ile_sample(rift_ile *h, int point, uint64_t seed, uint32_t roun
   hipError_t e = h->precision == RIFT_FP32
                      ? sample_launch<float>(h->net_frame ? h->d_pts + point : nullptr, h->d_props + point, point, seed,
                                             round, first, n, n, n, h->d_min,
-                                            h->d_max, h->tau_width, (float *)theta, (float *)ln_ratio, bins, h->stream)
+                                            h->d_max, h->tau_width, (float *)theta, (float *)ln_ratio, bins, h->stream,
+                                            nullptr, h->any_mix)
                      : sample_launch<double>(h->net_frame ? h->d_pts + point : nullptr, h->d_props + point, point, seed,
                                              round, first, n, n, n, h->d_min,
                                              h->d_max, h->tau_width, (double *)theta, (double *)ln_ratio, bins,
-                                             h->stream);
+                                             h->stream, nullptr, h->any_mix);
   if (e != hipSuccess) return hip_fail(h, e, "sample");
   return RIFT_OK;
 }
@@ -1348,6 +1352,7 @@ rift_status rift_ile_set_gmm(rift_ile *h, int point, int K, unsigned mask, doubl
       return fail(h, RIFT_E_INVALID, "weights of parameter %d sum to %g", d, tot);
   }
   gmm_norms(pr);
+  h->any_mix = true;
   pr.gk = K;
   pr.mask = mask;
   pr.geps = floor_eps;
@@ -1394,6 +1399,7 @@ rift_status rift_ile_adapt_gmm(rift_ile *h, int point, int64_t n, const float *u
                                        h->stream));
   }
   HIPCHK(h, pair_norm_launch(h->d_props, point, 1, h->stream));
+  h->any_mix = true;
   return RIFT_OK;
 }
 
