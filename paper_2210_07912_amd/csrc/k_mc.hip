@@ -717,7 +717,18 @@ __global__ void __launch_bounds__(256) em_partials_kernel(const float *ub, int64
   }
 }
 
-// M-step: merge the blocks' sums in block order, new weights, means, sds
+// the blocks' partial sums [n_seg][bps][X] merged in block order, one
+// thread per (segment, entry), into block 0's entry (read only by this thread)
+__global__ void sum_blocks_kernel(double *part, int n_seg, int bps, int X) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_seg * X) return;
+  const int seg = idx / X, x = idx % X;
+  double v = 0.0;
+  for (int j = 0; j < bps; j++) v += part[((size_t)seg * bps + j) * X + x];
+  part[(size_t)seg * bps * X + x] = v;
+}
+
+// M-step: the summed moments -> new weights, means, sds
 __global__ void em_update_kernel(const double *part, int n_seg, int bps, GmmDev *fit, unsigned mask) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n_seg * 7) return;
@@ -725,10 +736,8 @@ __global__ void em_update_kernel(const double *part, int n_seg, int bps, GmmDev 
   if (!((mask >> d) & 1u)) return;
   GmmDev &F = fit[seg];
   const int K = F.k;
-  double S[3 * kMaxG];
-  for (int q = 0; q < 3 * kMaxG; q++) S[q] = 0.0;
-  for (int j = 0; j < bps; j++)
-    for (int q = 0; q < 3 * kMaxG; q++) S[q] += part[(((size_t)seg * bps + j) * 7 + d) * 3 * kMaxG + q];
+  double S[3 * kMaxG];  // the blocks' sums, merged into block 0 by sum_blocks_kernel
+  for (int q = 0; q < 3 * kMaxG; q++) S[q] = part[((size_t)seg * bps * 7 + d) * 3 * kMaxG + q];
   double tot = 0.0;
   for (int k = 0; k < K; k++) tot += S[3 * k];
   if (!(tot > 0.0)) return;
@@ -836,10 +845,8 @@ __global__ void em_pair_update_kernel(const double *part2, int n_seg, int bps, G
   GmmDev &F = fit[seg];
   if (p >= F.npair) return;
   const int K = F.k;
-  double S[6 * kMaxG];
-  for (int q = 0; q < 6 * kMaxG; q++) S[q] = 0.0;
-  for (int j = 0; j < bps; j++)
-    for (int q = 0; q < 6 * kMaxG; q++) S[q] += part2[(((size_t)seg * bps + j) * kMaxPair + p) * 6 * kMaxG + q];
+  double S[6 * kMaxG];  // the blocks' sums, merged into block 0 by sum_blocks_kernel
+  for (int q = 0; q < 6 * kMaxG; q++) S[q] = part2[((size_t)seg * bps * kMaxPair + p) * 6 * kMaxG + q];
   double tot = 0.0;
   for (int k = 0; k < K; k++) tot += S[6 * k];
   if (!(tot > 0.0)) return;
@@ -1099,11 +1106,15 @@ hipError_t gmm_adapt_launch(const float *ubuf, int64_t u_stride, const R *lnw, c
     if (m1) {
       hipLaunchKernelGGL(em_partials_kernel<R>, dim3(n_seg * bps), dim3(256), 0, st, ubuf, u_stride, lnw, seg_off,
                          seg_cnt, bps, seg_round, fit + n_seg, m1, part);
+      hipLaunchKernelGGL(sum_blocks_kernel, dim3((n_seg * 7 * 3 * kMaxG + 255) / 256), dim3(256), 0, st, part, n_seg,
+                         bps, 7 * 3 * kMaxG);
       hipLaunchKernelGGL(em_update_kernel, g7, dim3(64), 0, st, part, n_seg, bps, fit + n_seg, m1);
     }
     if (pairs) {
       hipLaunchKernelGGL(em_pair_partials_kernel<R>, dim3(n_seg * bps), dim3(256), 0, st, ubuf, u_stride, lnw,
                          seg_off, seg_cnt, bps, seg_round, fit + n_seg, part2);
+      hipLaunchKernelGGL(sum_blocks_kernel, dim3((n_seg * kMaxPair * 6 * kMaxG + 255) / 256), dim3(256), 0, st, part2,
+                         n_seg, bps, kMaxPair * 6 * kMaxG);
       hipLaunchKernelGGL(em_pair_update_kernel, g3, dim3(64), 0, st, part2, n_seg, bps, fit + n_seg);
     }
   }
