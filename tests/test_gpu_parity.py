@@ -1225,3 +1225,26 @@ def test_marginalize_gmm_pairs_matches_oracle(ile, orc):
         assert abs(r["lnL_marg"] - o["lnL_marg"]) < 1e-3 + 4 * sig
         assert h.get_gmm_pairs(i)["pairs"] == pairs
     h.close()
+
+
+def test_marginalize_is_deterministic(ile):
+    """The FP64 reductions, histogram merges and mixture EM sums run in fixed
+    orders: two runs (the same handle, then a fresh one) give bit-identical
+    samples, weights and estimates, with histograms and with the mixture and
+    its pairs."""
+    w = synth.workload("tiny_batched")
+    pts = [synth.make_point(s) for s in w.points[:3]]
+    counts = [4000, 3000, 5000]
+    for kw in (dict(), dict(gmm_components=3, gmm_pairs=((3, 5),))):
+        _say(f"determinism {kw}")
+        outs = []
+        h1, h2 = _handle(ile, pts, "fp32"), _handle(ile, pts, "fp32")
+        for h in (h1, h1, h2):
+            res, th, lw = h.marginalize(2210079131, counts, n_rounds=3, adapt_mask=0x3F, floor_eps=0.1,
+                                        return_samples=True, **kw)
+            outs.append(([(r["lnL_marg"], r["n_eff"], r["n"]) for r in res], th.cpu().numpy(), lw.cpu().numpy()))
+        for o in outs[1:]:
+            assert o[0] == outs[0][0]
+            assert np.array_equal(o[1], outs[0][1]) and np.array_equal(o[2], outs[0][2], equal_nan=True)
+        h1.close()
+        h2.close()
