@@ -284,9 +284,12 @@ rift_status rift_ile_autotune_table(const rift_ile *h, int *modes);
  * with key = seed and counter = (i_lo, i_hi, 2 round + half, point); each
  * parameter takes one 32-bit word, mapped through the prior's inverse CDF or,
  * for a parameter adapted in the point's proposal, through its 100-bin
- * histogram.  theta: device [7][n]; ln_ratio: device [n] (handle precision)
+ * histogram or its Gaussian mixture (see rift_ile_set_gmm; a correlated pair
+ * none of whose tries lands in the unit square gives ln_ratio NaN).
+ * theta: device [7][n]; ln_ratio: device [n] (handle precision)
  * receives ln p - ln p_s (or NULL); bins: device uint8 [7][n] receives each
- * sample's histogram bin per parameter (or NULL).  Asynchronous. */
+ * sample's histogram bin per parameter (floor(100 u) under a mixture) (or
+ * NULL).  Asynchronous. */
 rift_status rift_ile_sample(rift_ile *h, int point, uint64_t seed, uint32_t round, int64_t first,
                             int64_t n, void *theta, void *ln_ratio, uint8_t *bins);
 
