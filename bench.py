@@ -53,6 +53,17 @@ def flops_per_grad(K, M, n_t):
             + 8 * K * M * M + 40 * K * M)
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,7 +328,8 @@ def main():
             rate = ns / (t_b - t_a)
         out["cpu_baseline"] = {"value": rate, "unit": "evals/s", "cores": oracle.threads(), "kind": "oracle",
                                "sample": f"{ns} prior samples of point 0 ({args.workload}), "
-                               + ("ln L_t and gradient" if grad else "ln L_t only") + ", FP64"}
+                               + ("ln L_t and gradient" if grad else "ln L_t only") + ", FP64",
+                               "cpu_model": _cpu_model()}
     print(json.dumps(out), flush=True)
     h.close()
 
