@@ -161,6 +161,13 @@ typedef struct {
    * discarded with ln ratio NaN), p_s = floor_eps + (1 - floor_eps)
    * sum_k pi_k N_k / sum_k pi_k Z_k, Z_k the component's mass in the square. */
   unsigned gmm_pairs;
+  /* Resume: the Philox round index of the first round (counter word 2 uses
+   * first_round + r).  0: a fresh pooled estimate.  > 0 (with
+   * reset_proposal = 0): the rounds continue the handle's pooled estimate and
+   * proposals, as left by an earlier run or rift_ile_load_checkpoint, so a
+   * run split at any round gives bit-identical results to an unsplit one;
+   * RIFT_E_STATE when the handle holds no pooled estimate. */
+  int first_round;
 } rift_ile_mc;
 
 #define RIFT_MC_GRADIENT 1u
@@ -388,6 +395,20 @@ rift_status rift_ile_get_gmm_pairs(rift_ile *h, int point, unsigned *pairs, doub
  * Synchronizes. */
 rift_status rift_ile_marginalize(rift_ile *h, const rift_ile_mc *mc, rift_ile_result *out,
                                  void *theta_out, void *lnw_out);
+
+/* Checkpoint of a Monte Carlo run: every point's proposal (histograms or
+ * mixture, pairs and sample counts included) and its pooled FP64 estimate
+ * (max, sums of e^{ln w - max} and their squares, counts), as raw bytes with a
+ * header (magic, ABI version, point count, record sizes).  bytes: host
+ * buffer size; rift_ile_checkpoint_bytes gives the size needed (-1 for a
+ * NULL handle).  save needs a completed rift_ile_marginalize (RIFT_E_STATE
+ * otherwise); load checks the header against this handle (RIFT_E_INVALID on a
+ * mismatch).  Both synchronize.  With the same points, a load followed by
+ * rift_ile_marginalize with first_round = the rounds done so far continues
+ * the run exactly. */
+int64_t rift_ile_checkpoint_bytes(const rift_ile *h);
+rift_status rift_ile_save_checkpoint(rift_ile *h, void *buf, int64_t bytes);
+rift_status rift_ile_load_checkpoint(rift_ile *h, const void *buf, int64_t bytes);
 
 /* Gradient of ln L_t with respect to the seven parameters, through the
  * antenna patterns F_k(alpha, delta, psi), the delays dt_k(alpha, delta) and

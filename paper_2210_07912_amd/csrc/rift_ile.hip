@@ -39,6 +39,7 @@ struct rift_ile {
   int n_points = 0;
   double d_min = 10.0, d_max = 1000.0, tau_width = 0.0;
   bool any_mix = false;  // some point may hold a Gaussian-mixture proposal (sampler variant)
+  bool have_accum = false;  // the pooled-estimate accumulators hold a run (resume allowed)
   std::vector<PointDev> hp;       // host copies (device pointers inside)
   std::vector<void *> owned;      // per-point allocations
   PointDev *d_pts = nullptr;
@@ -838,8 +839,7 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
     return fail(h, RIFT_E_INVALID, "gmm_components %d (0..%d), gmm_iters %d (0..1000), or both a mixture and the "
                 "gradient refinement", gk, kMaxG, mc->gmm_iters);
   if ((s = check_pairs(h, mc->gmm_pairs, mc->adapt_mask)) != RIFT_OK) return s;
-  if (mc->gmm_pairs && (gk == 0 || mc->n_rounds > (1 << 20)))
-    return fail(h, RIFT_E_INVALID, "correlated pairs need gmm_components > 0 and at most 2^20 rounds");
+  if (mc->gmm_pairs && gk == 0) return fail(h, RIFT_E_INVALID, "correlated pairs need gmm_components > 0");
   const bool gmm = gk > 0 && mc->adapt_mask;
   float *ubuf = nullptr;
   double *em_part = nullptr, *em_part2 = nullptr;
@@ -898,13 +898,13 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
     R *th = theta_out ? theta_out + cb : (R *)th_ws;
     R *lw = lnw_out ? lnw_out + (int64_t)r * per_round : (R *)lw_ws;
     HIPCHK(h, sample_multi_launch<R>(h->d_props, h->net_frame ? h->d_pts : nullptr, d_sblk, sblk[np], np, d_soff,
-                                     d_scnt, mc->seed, (uint32_t)r,
+                                     d_scnt, mc->seed, (uint32_t)(mc->first_round + r),
                                      th_stride, nr, h->d_min, h->d_max, h->tau_width, th, (R *)ratio,
                                      (uint8_t *)bins, h->stream, ubuf, h->any_mix));
     if ((s = eval<R>(h, it, th_stride, th, nullptr, lw, (const R *)ratio)) != RIFT_OK) return s;
     ReduceTuple *round;
     const bool last = r + 1 == mc->n_rounds;
-    if ((s = reduce_segments<R>(h, lw, nullptr, off, cnt, &round, (ReduceTuple *)accum, r > 0,
+    if ((s = reduce_segments<R>(h, lw, nullptr, off, cnt, &round, (ReduceTuple *)accum, r > 0 || mc->first_round > 0,
                                 last ? (rift_ile_result *)d_res : nullptr)) != RIFT_OK)
       return s;
     if (mc->adapt_mask && !last) {
@@ -937,6 +937,7 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
   }
   HIPCHK(h, hipMemcpyAsync(out, d_res, sizeof(rift_ile_result) * np, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->have_accum = true;
   return RIFT_OK;
 }
 
@@ -1469,12 +1470,81 @@ rift_status rift_ile_get_gmm_pairs(rift_ile *h, int point, unsigned *pairs, doub
   return RIFT_OK;
 }
 
+// checkpoint blob: header, then per point its proposal and its pooled tuple
+struct CkptHeader {
+  char magic[8];
+  int32_t version, n_points;
+  int64_t proposal_bytes, tuple_bytes;
+};
+constexpr char kCkptMagic[8] = {'R', 'I', 'F', 'T', 'C', 'K', 'P', '1'};
+
+int64_t rift_ile_checkpoint_bytes(const rift_ile *h) {
+  if (!h) return -1;
+  return (int64_t)sizeof(CkptHeader) + (int64_t)h->n_points * (int64_t)(sizeof(ProposalDev) + sizeof(ReduceTuple));
+}
+
+rift_status rift_ile_save_checkpoint(rift_ile *h, void *buf, int64_t bytes) {
+  if (!h) return RIFT_E_INVALID;
+  if (!buf || bytes < rift_ile_checkpoint_bytes(h)) return fail(h, RIFT_E_INVALID, "checkpoint buffer too small");
+  if (!h->have_accum) return fail(h, RIFT_E_STATE, "no pooled estimate to save (run rift_ile_marginalize first)");
+  const int np = h->n_points;
+  CkptHeader hd;
+  std::memcpy(hd.magic, kCkptMagic, 8);
+  hd.version = RIFT_ILE_ABI_VERSION;
+  hd.n_points = np;
+  hd.proposal_bytes = sizeof(ProposalDev);
+  hd.tuple_bytes = sizeof(ReduceTuple);
+  char *c = (char *)buf;
+  std::memcpy(c, &hd, sizeof hd);
+  c += sizeof hd;
+  HIPCHK(h, hipMemcpyAsync(c, h->d_props, sizeof(ProposalDev) * np, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(c + sizeof(ProposalDev) * np, h->ws[W_ACCUM].p, sizeof(ReduceTuple) * np,
+                           hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return RIFT_OK;
+}
+
+rift_status rift_ile_load_checkpoint(rift_ile *h, const void *buf, int64_t bytes) {
+  if (!h) return RIFT_E_INVALID;
+  if (!buf || bytes < (int64_t)sizeof(CkptHeader)) return fail(h, RIFT_E_INVALID, "checkpoint buffer too small");
+  CkptHeader hd;
+  std::memcpy(&hd, buf, sizeof hd);
+  const int np = h->n_points;
+  if (std::memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != RIFT_ILE_ABI_VERSION || hd.n_points != np ||
+      hd.proposal_bytes != (int64_t)sizeof(ProposalDev) || hd.tuple_bytes != (int64_t)sizeof(ReduceTuple) ||
+      bytes < rift_ile_checkpoint_bytes(h))
+    return fail(h, RIFT_E_INVALID, "checkpoint from another library version or point count");
+  const char *c = (const char *)buf + sizeof hd;
+  std::vector<ProposalDev> props(np);
+  std::memcpy(props.data(), c, sizeof(ProposalDev) * np);
+  for (const auto &p : props) {
+    if (p.gk < 0 || p.gk > kMaxG || p.npair < 0 || p.npair > kMaxPair || (p.mask >> 7))
+      return fail(h, RIFT_E_INVALID, "checkpoint: corrupt proposal");
+    if (p.gk > 0) h->any_mix = true;
+  }
+  void *accum;
+  rift_status s = ws_get(h, W_ACCUM, sizeof(ReduceTuple) * np, &accum);
+  if (s != RIFT_OK) return s;
+  HIPCHK(h, hipMemcpyAsync(h->d_props, props.data(), sizeof(ProposalDev) * np, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(accum, c + sizeof(ProposalDev) * np, sizeof(ReduceTuple) * np, hipMemcpyHostToDevice,
+                           h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->have_accum = true;
+  return RIFT_OK;
+}
+
 rift_status rift_ile_marginalize(rift_ile *h, const rift_ile_mc *mc, rift_ile_result *out, void *theta_out,
                                  void *lnw_out) {
   if (!h) return RIFT_E_INVALID;
   if (!mc || !out || mc->n_rounds < 1 || (mc->adapt_mask >> 7)) return fail(h, RIFT_E_INVALID, "bad mc arguments");
   if (mc->adapt_mask && !(mc->floor_eps > 0.0 && mc->floor_eps <= 1.0))
     return fail(h, RIFT_E_INVALID, "floor_eps %g", mc->floor_eps);
+  if (mc->first_round < 0 || (mc->first_round > 0 && mc->reset_proposal) ||
+      (int64_t)mc->first_round + mc->n_rounds > (mc->gmm_pairs ? (1 << 20) : (1 << 30)))
+    return fail(h, RIFT_E_INVALID, "first_round %d: >= 0, with reset_proposal = 0 when > 0, rounds below 2^30 (2^20 "
+                "with pairs)", mc->first_round);
+  if (mc->first_round > 0 && !h->have_accum)
+    return fail(h, RIFT_E_STATE, "first_round > 0 needs a pooled estimate (an earlier run or a loaded checkpoint)");
   if (h->precision == RIFT_FP32) return marginalize_impl<float>(h, mc, out, (float *)theta_out, (float *)lnw_out);
   return marginalize_impl<double>(h, mc, out, (double *)theta_out, (double *)lnw_out);
 }

@@ -66,7 +66,7 @@ class MC(C.Structure):
                 ("n_rounds", C.c_int), ("adapt_mask", C.c_uint), ("floor_eps", C.c_double),
                 ("reset_proposal", C.c_int), ("flags", C.c_uint), ("n_ascent", C.c_int),
                 ("ascent_steps", C.c_int), ("ascent_mix", C.c_double), ("gmm_components", C.c_int),
-                ("gmm_iters", C.c_int), ("gmm_pairs", C.c_uint)]
+                ("gmm_iters", C.c_int), ("gmm_pairs", C.c_uint), ("first_round", C.c_int)]
 
 
 RIFT_MC_GRADIENT = 1
@@ -119,6 +119,9 @@ FUNCTIONS = {
     "rift_ile_get_gmm_pairs": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_uint), C.POINTER(C.c_double),
                                          C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "rift_ile_marginalize": (C.c_int, [C.c_void_p, C.POINTER(MC), C.POINTER(Result), C.c_void_p, C.c_void_p]),
+    "rift_ile_checkpoint_bytes": (C.c_int64, [C.c_void_p]),
+    "rift_ile_save_checkpoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    "rift_ile_load_checkpoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
     "rift_ile_backward": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(Item), C.c_int64, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p]),
 }
@@ -339,11 +342,11 @@ class RiftILE:
 
     def marginalize(self, seed, n_per_point, n_rounds=1, adapt_mask=0, floor_eps=0.1, reset=True,
                     return_samples=False, gradient=False, n_ascent=0, ascent_steps=0, ascent_mix=0.0,
-                    gmm_components=0, gmm_iters=0, gmm_pairs=()):
+                    gmm_components=0, gmm_iters=0, gmm_pairs=(), first_round=0):
         npp = np.ascontiguousarray(np.broadcast_to(np.asarray(n_per_point, dtype=np.int64), (self.n_points,)))
         mc = MC(seed, 0, npp.ctypes.data_as(C.POINTER(C.c_int64)), n_rounds, adapt_mask, floor_eps, int(reset),
                 RIFT_MC_GRADIENT if gradient else 0, n_ascent, ascent_steps, ascent_mix, gmm_components, gmm_iters,
-                encode_pairs(gmm_pairs))
+                encode_pairs(gmm_pairs), first_round)
         res = (Result * self.n_points)()
         th = lw = None
         if return_samples:
@@ -355,6 +358,17 @@ class RiftILE:
         if return_samples:
             return out, th, lw
         return out
+
+    def save_checkpoint(self):
+        """Proposals and pooled estimates of every point, as bytes."""
+        n = lib().rift_ile_checkpoint_bytes(self.h)
+        buf = C.create_string_buffer(n)
+        self._check(lib().rift_ile_save_checkpoint(self.h, buf, n))
+        return buf.raw
+
+    def load_checkpoint(self, data):
+        buf = C.create_string_buffer(bytes(data), len(data))
+        self._check(lib().rift_ile_load_checkpoint(self.h, buf, len(data)))
 
     def backward(self, theta, grad_lnL=None, items=None, want_lnL=False):
         th = self._as_theta(theta)

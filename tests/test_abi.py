@@ -55,8 +55,10 @@ def test_host_only_calls():
     assert L.rift_ile_adapt_gmm(None, 0, 0, None, None, 1, 0, 0.1, 1, 1) == -1
     assert L.rift_ile_set_gmm_pairs(None, 0, 0, None, None, None) == -1
     assert L.rift_ile_get_gmm_pairs(None, 0, None, None, None, None, None) == -1
+    assert L.rift_ile_checkpoint_bytes(None) == -1
+    assert L.rift_ile_save_checkpoint(None, None, 0) == -1 and L.rift_ile_load_checkpoint(None, None, 0) == -1
     # the Monte Carlo descriptor matches the binding's layout (mixture fields last)
-    assert ctypes.sizeof(ile.MC) == 80 and ile.MC.gmm_pairs.offset == 72
+    assert ctypes.sizeof(ile.MC) == 80 and ile.MC.gmm_pairs.offset == 72 and ile.MC.first_round.offset == 76
 
 
 def test_binding_refuses_without_device():

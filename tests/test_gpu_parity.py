@@ -1248,3 +1248,45 @@ def test_marginalize_is_deterministic(ile):
             assert np.array_equal(o[1], outs[0][1]) and np.array_equal(o[2], outs[0][2], equal_nan=True)
         h1.close()
         h2.close()
+
+
+def test_checkpoint_resume_is_bit_identical(ile):
+    """A run split after two rounds, checkpointed and resumed on a fresh
+    handle with first_round = 2, gives the unsplit run's estimates, samples
+    and weights bit for bit (histograms; mixture with a pair)."""
+    w = synth.workload("tiny_batched")
+    pts = [synth.make_point(s) for s in w.points[:3]]
+    counts = [3000, 2000, 4000]
+    seed = 2210079132
+    for kw in (dict(), dict(gmm_components=2, gmm_pairs=((3, 5),))):
+        _say(f"checkpoint/resume {kw}")
+        h = _handle(ile, pts, "fp32")
+        full, thf, lwf = h.marginalize(seed, counts, n_rounds=4, adapt_mask=0x3F, floor_eps=0.1, return_samples=True,
+                                       **kw)
+        h.close()
+        h1 = _handle(ile, pts, "fp32")
+        _, th1, lw1 = h1.marginalize(seed, counts, n_rounds=2, adapt_mask=0x3F, floor_eps=0.1, return_samples=True,
+                                     **kw)
+        blob = h1.save_checkpoint()
+        h1.close()
+        h2 = _handle(ile, pts, "fp32")
+        with pytest.raises(ile.RiftError) as e:  # no pooled estimate yet
+            h2.marginalize(seed, counts, n_rounds=2, adapt_mask=0x3F, floor_eps=0.1, reset=False, first_round=2, **kw)
+        assert e.value.status == -8
+        h2.load_checkpoint(blob)
+        res, th2, lw2 = h2.marginalize(seed, counts, n_rounds=2, adapt_mask=0x3F, floor_eps=0.1, reset=False,
+                                       first_round=2, return_samples=True, **kw)
+        h2.close()
+        for a, b in zip(full, res):
+            assert (a["lnL_marg"], a["n_eff"], a["n_ess"], a["n"], a["n_nonfinite"]) == \
+                   (b["lnL_marg"], b["n_eff"], b["n_ess"], b["n"], b["n_nonfinite"])
+        half = 2 * sum(counts)
+        assert np.array_equal(thf[:, :half].cpu().numpy(), th1.cpu().numpy())
+        assert np.array_equal(thf[:, half:].cpu().numpy(), th2.cpu().numpy())
+        assert np.array_equal(lwf[half:].cpu().numpy(), lw2.cpu().numpy(), equal_nan=True)
+    # a checkpoint of another point count is refused
+    h3 = _handle(ile, pts[:2], "fp32")
+    with pytest.raises(ile.RiftError) as e:
+        h3.load_checkpoint(blob)
+    assert e.value.status == -1
+    h3.close()
