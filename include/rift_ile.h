@@ -127,7 +127,7 @@ typedef struct {
   int64_t n_per_round;        /* samples per point per round; ignored if n_per_point */
   const int64_t *n_per_point; /* host [n_points] or NULL */
   int n_rounds;               /* >= 1 */
-  unsigned adapt_mask;        /* bit d: adapt parameter d between rounds (0: prior only) */
+  unsigned adapt_mask;        /* bit d: adapt parameter d after each round (0: prior only) */
   double floor_eps;           /* uniform floor mixed into each adapted histogram, (0, 1] */
   int reset_proposal;         /* 1: start from the prior (else from the current tables) */
   /* Gradient-informed refinement (flags & RIFT_MC_GRADIENT, adapt_mask != 0):
@@ -386,7 +386,8 @@ rift_status rift_ile_get_gmm_pairs(rift_ile *h, int point, unsigned *pairs, doub
 /* The whole step for every point: for each round, draw samples from the
  * current proposal, evaluate ln L_t, form ln w, fold them into a pooled FP64
  * estimate over all rounds (each sample weighted with its own round's p_s),
- * and, between rounds, adapt the masked parameters' histograms from that
+ * and after every round (the last included, so the proposals left behind
+ * are the next round's) adapt the masked parameters' histograms from that
  * round's weights.  All points run together in each launch.  out: host
  * [n_points].  theta_out (device [7][total]) and lnw_out (device [total]),
  * both in the handle's precision, if not NULL, receive every sample in

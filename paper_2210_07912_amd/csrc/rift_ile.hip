@@ -907,7 +907,9 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
     if ((s = reduce_segments<R>(h, lw, nullptr, off, cnt, &round, (ReduceTuple *)accum, r > 0 || mc->first_round > 0,
                                 last ? (rift_ile_result *)d_res : nullptr)) != RIFT_OK)
       return s;
-    if (mc->adapt_mask && !last) {
+    // adapted after every round, the last included, so the proposals a run
+    // leaves (and a checkpoint holds) are the next round's
+    if (mc->adapt_mask) {
       if (grad) {
         HIPCHK(h, ascent_select<R>(lw, th, th_stride, d_soff, d_scnt, np, ka, a_idx, a_th, a_st, h->stream));
         const bool prof = h->prof;  // the timing hook follows the evaluation launches only
