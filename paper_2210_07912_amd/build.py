@@ -46,9 +46,10 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    # hipFFT for the batched transform of the Q/U/V precompute
+    # hipFFT for the batched transform of the Q/U/V precompute; roctx for the
+    # per-round trace ranges of the Monte Carlo loop
     subprocess.check_call([_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-L/opt/rocm/lib", "-lhipfft",
-                           "-Wl,-rpath,/opt/rocm/lib", "-o", tmp])
+                           "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib", "-o", tmp])
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")

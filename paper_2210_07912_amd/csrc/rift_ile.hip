@@ -2,6 +2,7 @@
 // device layouts of the per-point data, workspace management and the order
 // of kernel launches for each entry point.  No exception crosses the ABI.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -893,7 +894,16 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
     it.off.push_back(off[p]);
     it.cnt.push_back(cnt[p]);
   }
+  // trace ranges (rocprofv3 --marker-trace): one per round, nested ones per phase
+  struct Range {
+    explicit Range(const char *m) { roctxRangePushA(m); }
+    ~Range() { roctxRangePop(); }
+  };
+  Range run_range("rift_ile_marginalize");
   for (int r = 0; r < mc->n_rounds; r++) {
+    char rname[48];
+    std::snprintf(rname, sizeof rname, "round %d", mc->first_round + r);
+    Range round_range(rname);
     const int64_t cb = theta_out ? (int64_t)r * per_round : 0;
     R *th = theta_out ? theta_out + cb : (R *)th_ws;
     R *lw = lnw_out ? lnw_out + (int64_t)r * per_round : (R *)lw_ws;
@@ -901,7 +911,10 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
                                      d_scnt, mc->seed, (uint32_t)(mc->first_round + r),
                                      th_stride, nr, h->d_min, h->d_max, h->tau_width, th, (R *)ratio,
                                      (uint8_t *)bins, h->stream, ubuf, h->any_mix));
-    if ((s = eval<R>(h, it, th_stride, th, nullptr, lw, (const R *)ratio)) != RIFT_OK) return s;
+    {
+      Range ph("evaluate");
+      if ((s = eval<R>(h, it, th_stride, th, nullptr, lw, (const R *)ratio)) != RIFT_OK) return s;
+    }
     ReduceTuple *round;
     const bool last = r + 1 == mc->n_rounds;
     if ((s = reduce_segments<R>(h, lw, nullptr, off, cnt, &round, (ReduceTuple *)accum, r > 0 || mc->first_round > 0,
@@ -910,6 +923,7 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
     // adapted after every round, the last included, so the proposals a run
     // leaves (and a checkpoint holds) are the next round's
     if (mc->adapt_mask) {
+      Range ph("adapt");
       if (grad) {
         HIPCHK(h, ascent_select<R>(lw, th, th_stride, d_soff, d_scnt, np, ka, a_idx, a_th, a_st, h->stream));
         const bool prof = h->prof;  // the timing hook follows the evaluation launches only
