@@ -1291,3 +1291,20 @@ def test_checkpoint_resume_is_bit_identical(ile):
         h3.load_checkpoint(blob)
     assert e.value.status == -1
     h3.close()
+
+
+def test_readme_example_runs(ile):
+    """The Python example of the README, at smaller sample counts."""
+    d = synth.make_point(synth.workload("single").points[0])
+    h = ile.RiftILE([d], precision="fp32")
+    th, ratio, _ = h.sample(0, seed=1, rnd=0, n=20_000)
+    lnL_t = h.lnL(th)
+    g = h.backward(th[:, :1000])
+    assert lnL_t.shape == (20_000,) and g.shape == (7, 1000) and torch.isfinite(lnL_t).all()
+    res = h.marginalize(seed=1, n_per_point=20_000, n_rounds=3, adapt_mask=0x3F)
+    res2 = h.marginalize(seed=1, n_per_point=20_000, n_rounds=3, adapt_mask=0x3F, gmm_components=3,
+                         gmm_pairs=[(2, 4), (3, 5)])
+    assert np.isfinite(res[0]["lnL_marg"]) and np.isfinite(res2[0]["lnL_marg"])
+    blob = h.save_checkpoint()
+    assert len(blob) == ile.lib().rift_ile_checkpoint_bytes(h.h)
+    h.close()
