@@ -80,8 +80,8 @@ def main():
                     help="skip the measurements beside the timed steps (precompute, network frame, refinement)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the multi-GPU path is not part of this build "
-              "(points shard across GPUs with one 40-byte FP64 exchange per point; see DESIGN.md)",
+        print("bench.py measures one GPU: the library has no multi-GPU path (points would shard across GPUs "
+              "with one 40-byte FP64 exchange per point)",
               file=sys.stderr)
         sys.exit(2)
 
