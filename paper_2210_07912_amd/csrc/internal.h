@@ -269,13 +269,14 @@ struct GmmDev {
 };
 int em_blocks(int64_t max_count);
 // pairs: byte i = a | b << 4 (a < b; 0: none); part2: scratch
-// [n_seg][bps][kMaxPair][kMaxG][6]
+// [n_seg][bps][kMaxPair][kMaxG][6]; blk0 [n_seg + 1]: prefix of 256-sample blocks
+// per segment (wblk in all); wbuf: scratch, one double per sample
 template <typename R>
 hipError_t gmm_adapt_launch(const float *ubuf, int64_t u_stride, const R *lnw, const int64_t *seg_off,
                             const int64_t *seg_cnt, const int *seg_prop, int n_seg, int bps,
                             const ReduceTuple *seg_round, double *part, double *part2, GmmDev *fit,
                             ProposalDev *props, unsigned mask, unsigned pairs, double floor_eps, int K, int n_iter,
-                            hipStream_t st);
+                            const int *blk0, int wblk, double *wbuf, hipStream_t st);
 // host: component normalizations gca, gz of a mixture (Phi by erfc)
 void gmm_norms(ProposalDev &p);
 // derived pair quantities (pch, pic, plog, pzm) of props[p0 .. p0 + n - 1]

@@ -651,8 +651,7 @@ __global__ void gmm_init_kernel(const ProposalDev *props, const int *seg_prop, i
 // E-step and the M-step sums of one block: for each adapted d and component
 // k, S0 = sum w r, S1 = sum w r (u - mu_k), S2 = sum w r (u - mu_k)^2 with
 // w = e^{ln w - max ln w} and r the responsibility (untruncated normals)
-template <typename R>
-__global__ void __launch_bounds__(256) em_partials_kernel(const float *ub, int64_t us, const R *lnw,
+__global__ void __launch_bounds__(256) em_partials_kernel(const float *ub, int64_t us, const double *wbuf,
                                                           const int64_t *seg_off, const int64_t *seg_cnt, int bps,
                                                           const ReduceTuple *seg_round, const GmmDev *fit,
                                                           unsigned mask, double *part) {
@@ -677,9 +676,8 @@ __global__ void __launch_bounds__(256) em_partials_kernel(const float *ub, int64
     }
     if (mx > -INFINITY) {
       for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
-        const double x = (double)lnw[off + i];
-        if (!(x == x) || x == INFINITY || x == -INFINITY) continue;
-        const double wt = exp(x - mx);
+        const double wt = wbuf[off + i];
+        if (!(wt > 0.0)) continue;
         const double uu = (double)ub[d * us + off + i];
         double lp[kMaxG], m = -INFINITY;
 #pragma unroll
@@ -715,6 +713,25 @@ __global__ void __launch_bounds__(256) em_partials_kernel(const float *ub, int64
     if (threadIdx.x < 3 * kMaxG) part[(((size_t)seg * bps + j) * 7 + d) * 3 * kMaxG + threadIdx.x] = red[0][threadIdx.x];
     __syncthreads();
   }
+}
+
+// the round's weights w = e^{ln w - max ln w} (0 for non-finite ln w), once
+// per adaptation for all EM iterations
+template <typename R>
+__global__ void __launch_bounds__(256) em_weight_kernel(const R *lnw, const int64_t *seg_off, const int64_t *seg_cnt,
+                                                        const int *blk0, int n_seg, const ReduceTuple *seg_round,
+                                                        double *wbuf) {
+  int lo = 0, hi = n_seg;  // blk0[lo] <= blockIdx.x < blk0[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (blk0[mid] <= (int)blockIdx.x) lo = mid; else hi = mid;
+  }
+  const int seg = lo;
+  const int64_t i = (int64_t)(blockIdx.x - blk0[seg]) * 256 + threadIdx.x;
+  if (i >= seg_cnt[seg]) return;
+  const int64_t c = seg_off[seg] + i;
+  const double x = (double)lnw[c], mx = seg_round[seg].m;
+  wbuf[c] = (!(x == x) || x == INFINITY || x == -INFINITY || !(mx > -INFINITY)) ? 0.0 : exp(x - mx);
 }
 
 // the blocks' partial sums [n_seg][bps][X] merged in block order, one
@@ -763,8 +780,7 @@ __device__ __forceinline__ void regularize(double &xx, double &xy, double &yy) {
 
 // pairs: E-step and sums of one block, per pair and component S0, Sx, Sy,
 // Sxx, Sxy, Syy (moments about the component's current mean)
-template <typename R>
-__global__ void __launch_bounds__(256) em_pair_partials_kernel(const float *ub, int64_t us, const R *lnw,
+__global__ void __launch_bounds__(256) em_pair_partials_kernel(const float *ub, int64_t us, const double *wbuf,
                                                                const int64_t *seg_off, const int64_t *seg_cnt,
                                                                int bps, const ReduceTuple *seg_round,
                                                                const GmmDev *fit, double *part2) {
@@ -794,9 +810,8 @@ __global__ void __launch_bounds__(256) em_pair_partials_kernel(const float *ub, 
     }
     if (mx > -INFINITY) {
       for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
-        const double x = (double)lnw[off + i];
-        if (!(x == x) || x == INFINITY || x == -INFINITY) continue;
-        const double wt = exp(x - mx);
+        const double wt = wbuf[off + i];
+        if (!(wt > 0.0)) continue;
         const double ux = (double)ub[a * us + off + i], uy = (double)ub[b * us + off + i];
         double lp[kMaxG], m = -INFINITY;
 #pragma unroll
@@ -1092,7 +1107,7 @@ hipError_t gmm_adapt_launch(const float *ubuf, int64_t u_stride, const R *lnw, c
                             const int64_t *seg_cnt, const int *seg_prop, int n_seg, int bps,
                             const ReduceTuple *seg_round, double *part, double *part2, GmmDev *fit,
                             ProposalDev *props, unsigned mask, unsigned pairs, double floor_eps, int K, int n_iter,
-                            hipStream_t st) {
+                            const int *blk0, int wblk, double *wbuf, hipStream_t st) {
   if (n_seg <= 0) return hipSuccess;
   unsigned pm = 0u;  // parameters in pairs: not fitted one by one
   for (int i = 0; i < kMaxPair; i++) {
@@ -1102,16 +1117,19 @@ hipError_t gmm_adapt_launch(const float *ubuf, int64_t u_stride, const R *lnw, c
   const unsigned m1 = mask & ~pm;
   const dim3 g1((n_seg + 63) / 64), g7((n_seg * 7 + 63) / 64), g3((n_seg * kMaxPair + 63) / 64);
   hipLaunchKernelGGL(gmm_init_kernel, g1, dim3(64), 0, st, props, seg_prop, n_seg, K, pairs, fit, fit + n_seg);
+  if (wblk > 0)
+    hipLaunchKernelGGL(em_weight_kernel<R>, dim3(wblk), dim3(256), 0, st, lnw, seg_off, seg_cnt, blk0, n_seg,
+                       seg_round, wbuf);
   for (int it = 0; it < n_iter; it++) {
     if (m1) {
-      hipLaunchKernelGGL(em_partials_kernel<R>, dim3(n_seg * bps), dim3(256), 0, st, ubuf, u_stride, lnw, seg_off,
+      hipLaunchKernelGGL(em_partials_kernel, dim3(n_seg * bps), dim3(256), 0, st, ubuf, u_stride, wbuf, seg_off,
                          seg_cnt, bps, seg_round, fit + n_seg, m1, part);
       hipLaunchKernelGGL(sum_blocks_kernel, dim3((n_seg * 7 * 3 * kMaxG + 255) / 256), dim3(256), 0, st, part, n_seg,
                          bps, 7 * 3 * kMaxG);
       hipLaunchKernelGGL(em_update_kernel, g7, dim3(64), 0, st, part, n_seg, bps, fit + n_seg, m1);
     }
     if (pairs) {
-      hipLaunchKernelGGL(em_pair_partials_kernel<R>, dim3(n_seg * bps), dim3(256), 0, st, ubuf, u_stride, lnw,
+      hipLaunchKernelGGL(em_pair_partials_kernel, dim3(n_seg * bps), dim3(256), 0, st, ubuf, u_stride, wbuf,
                          seg_off, seg_cnt, bps, seg_round, fit + n_seg, part2);
       hipLaunchKernelGGL(sum_blocks_kernel, dim3((n_seg * kMaxPair * 6 * kMaxG + 255) / 256), dim3(256), 0, st, part2,
                          n_seg, bps, kMaxPair * 6 * kMaxG);
@@ -1125,11 +1143,12 @@ hipError_t gmm_adapt_launch(const float *ubuf, int64_t u_stride, const R *lnw, c
 }
 template hipError_t gmm_adapt_launch<float>(const float *, int64_t, const float *, const int64_t *, const int64_t *,
                                             const int *, int, int, const ReduceTuple *, double *, double *, GmmDev *,
-                                            ProposalDev *, unsigned, unsigned, double, int, int, hipStream_t);
+                                            ProposalDev *, unsigned, unsigned, double, int, int, const int *, int,
+                                            double *, hipStream_t);
 template hipError_t gmm_adapt_launch<double>(const float *, int64_t, const double *, const int64_t *,
                                              const int64_t *, const int *, int, int, const ReduceTuple *, double *,
                                              double *, GmmDev *, ProposalDev *, unsigned, unsigned, double, int, int,
-                                             hipStream_t);
+                                             const int *, int, double *, hipStream_t);
 
 // host: the same normalizations for a mixture set by the caller
 void gmm_norms(ProposalDev &p) {

@@ -76,7 +76,7 @@ enum WsId {
   W_ITEM_POINT, W_ITEM_OFF, W_ITEM_CNT, W_ITEM_TILE0, W_ITEM_SAMP0, W_ITEM_BIN0,
   W_KEY, W_NSH, W_COUNT, W_CURSOR, W_COP, W_BINTILE, W_ITEMTILES, W_PERM, W_TILES, W_CTL, W_CTILE,
   W_PARTIALS, W_ROUND, W_ACCUM, W_RESULT, W_HIST, W_THETA, W_LNW, W_AUX, W_RATIO, W_BINS, W_ITEM_BLK0,
-  W_ITEM_HOFF, W_ITEM_COP, W_SEG_OFF, W_SEG_CNT, W_ASC, W_AHIST, W_UNIT, W_BINUNIT, W_ITEMUNITS, W_GOP, W_HOP, W_SEG_BLK, W_UBUF, W_EMPART, W_EMPART2, W_GMMFIT, W_COUNT_IDS
+  W_ITEM_HOFF, W_ITEM_COP, W_SEG_OFF, W_SEG_CNT, W_ASC, W_AHIST, W_UNIT, W_BINUNIT, W_ITEMUNITS, W_GOP, W_HOP, W_SEG_BLK, W_UBUF, W_EMPART, W_EMPART2, W_GMMFIT, W_EMWT, W_COUNT_IDS
 };
 static_assert(W_COUNT_IDS <= 48, "workspace table too small");
 
@@ -843,11 +843,13 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
   if (mc->gmm_pairs && gk == 0) return fail(h, RIFT_E_INVALID, "correlated pairs need gmm_components > 0");
   const bool gmm = gk > 0 && mc->adapt_mask;
   float *ubuf = nullptr;
-  double *em_part = nullptr, *em_part2 = nullptr;
+  double *em_part = nullptr, *em_part2 = nullptr, *em_wt = nullptr;
   GmmDev *em_fit = nullptr;
   const int ebps = em_blocks(mxc);
   if (gmm) {
-    void *pu, *pp, *pp2, *pf;
+    void *pu, *pp, *pp2, *pf, *pw;
+    if ((s = ws_get(h, W_EMWT, sizeof(double) * (size_t)nr, &pw)) != RIFT_OK) return s;
+    em_wt = (double *)pw;
     if ((s = ws_get(h, W_UBUF, 7 * sizeof(float) * (size_t)nr, &pu)) != RIFT_OK) return s;
     if ((s = ws_get(h, W_EMPART, sizeof(double) * 7 * 3 * kMaxG * (size_t)np * ebps, &pp)) != RIFT_OK) return s;
     if ((s = ws_get(h, W_EMPART2, sizeof(double) * kMaxPair * 6 * kMaxG * (size_t)np * ebps, &pp2)) != RIFT_OK)
@@ -943,7 +945,7 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
       if (gmm) {
         HIPCHK(h, gmm_adapt_launch<R>(ubuf, nr, lw, d_soff, d_scnt, d_prop, np, ebps, round, em_part, em_part2,
                                       em_fit, h->d_props, mc->adapt_mask, mc->gmm_pairs, mc->floor_eps, gk, giter,
-                                      h->stream));
+                                      d_sblk, sblk[np], em_wt, h->stream));
         HIPCHK(h, pair_norm_launch(h->d_props, 0, np, h->stream));
       } else
         HIPCHK(h, adapt_launch<R>((const uint8_t *)bins, nr, lw, d_soff, d_scnt, d_prop, np, hbps, round,
@@ -1392,8 +1394,12 @@ rift_status rift_ile_adapt_gmm(rift_ile *h, int point, int64_t n, const float *u
   std::vector<int> sp(1, point);
   ReduceTuple *round;
   int *d_sp;
-  void *part, *part2, *fit;
+  void *part, *part2, *fit, *wt;
+  int *d_blk;
   const int bps = em_blocks(n);
+  const int wblk = (int)((n + 255) / 256);
+  if ((s = ws_get(h, W_EMWT, sizeof(double) * (size_t)std::max<int64_t>(n, 1), &wt)) != RIFT_OK) return s;
+  if ((s = upload(h, W_SEG_BLK, std::vector<int>{0, wblk}, &d_blk)) != RIFT_OK) return s;
   if ((s = ws_get(h, W_EMPART, sizeof(double) * 7 * 3 * kMaxG * bps, &part)) != RIFT_OK) return s;
   if ((s = ws_get(h, W_EMPART2, sizeof(double) * kMaxPair * 6 * kMaxG * bps, &part2)) != RIFT_OK) return s;
   if ((s = ws_get(h, W_GMMFIT, 2 * sizeof(GmmDev), &fit)) != RIFT_OK) return s;
@@ -1404,7 +1410,7 @@ rift_status rift_ile_adapt_gmm(rift_ile *h, int point, int64_t n, const float *u
     int64_t *d_off = (int64_t *)h->ws[W_ITEM_OFF].p, *d_cnt = (int64_t *)h->ws[W_ITEM_CNT].p;
     HIPCHK(h, gmm_adapt_launch<float>(u, n, (const float *)lnw, d_off, d_cnt, d_sp, 1, bps, round, (double *)part,
                                       (double *)part2, (GmmDev *)fit, h->d_props, mask, pairs, floor_eps, K, n_iter,
-                                      h->stream));
+                                      d_blk, wblk, (double *)wt, h->stream));
   } else {
     if ((s = reduce_segments<double>(h, (const double *)lnw, nullptr, off, cnt, &round, nullptr, 0, nullptr)) !=
         RIFT_OK)
@@ -1413,7 +1419,7 @@ rift_status rift_ile_adapt_gmm(rift_ile *h, int point, int64_t n, const float *u
     int64_t *d_off = (int64_t *)h->ws[W_ITEM_OFF].p, *d_cnt = (int64_t *)h->ws[W_ITEM_CNT].p;
     HIPCHK(h, gmm_adapt_launch<double>(u, n, (const double *)lnw, d_off, d_cnt, d_sp, 1, bps, round, (double *)part,
                                        (double *)part2, (GmmDev *)fit, h->d_props, mask, pairs, floor_eps, K, n_iter,
-                                       h->stream));
+                                       d_blk, wblk, (double *)wt, h->stream));
   }
   HIPCHK(h, pair_norm_launch(h->d_props, point, 1, h->stream));
   h->any_mix = true;
