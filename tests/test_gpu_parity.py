@@ -1308,3 +1308,26 @@ def test_readme_example_runs(ile):
     blob = h.save_checkpoint()
     assert len(blob) == ile.lib().rift_ile_checkpoint_bytes(h.h)
     h.close()
+
+
+@pytest.mark.parametrize("K,pairs", [(1, ()), (4, ((0, 1), (2, 4), (3, 5)))])
+def test_gmm_full_floor_is_the_prior(ile, K, pairs):
+    """With floor_eps = 1 every adapted draw takes the uniform branch, so a
+    mixture run (K = 1, or K = 4 with three pairs: 24 matching permutations)
+    draws the prior's samples with ln ratio 0: samples and weights equal a
+    prior-only run bit for bit, while its EM and updates still run."""
+    w = synth.workload("tiny_batched")
+    pts = [synth.make_point(s) for s in w.points[:2]]
+    counts = [3000, 2500]
+    h = _handle(ile, pts, "fp32")
+    ref, th0, lw0 = h.marginalize(2210079133, counts, n_rounds=3, adapt_mask=0, return_samples=True)
+    res, th1, lw1 = h.marginalize(2210079133, counts, n_rounds=3, adapt_mask=0x3F, floor_eps=1.0, gmm_components=K,
+                                  gmm_pairs=pairs, return_samples=True)
+    assert np.array_equal(th0.cpu().numpy(), th1.cpu().numpy())
+    assert np.array_equal(lw0.cpu().numpy(), lw1.cpu().numpy(), equal_nan=True)
+    assert [r["lnL_marg"] for r in res] == [r["lnL_marg"] for r in ref]
+    g = h.get_gmm(0)
+    assert g["K"] == K and g["n_trained"] == 3 * counts[0]
+    assert h.get_gmm_pairs(0)["pairs"] == list(pairs)
+    assert np.all(np.isfinite(g["mu"][:, :K])) and np.all(g["sd"][:, :K] > 0)
+    h.close()
