@@ -293,20 +293,27 @@ def main():
         hs = ile.RiftILE(sub, precision="fp32", tau_width=w.tau_width)
         h64 = ile.RiftILE(sub, precision="fp64", tau_width=w.tau_width)
         ns = len(sub)
-        res32, th, lw = hs.marginalize(seed + 13, counts[:ns], n_rounds=rounds, adapt_mask=mask, floor_eps=0.1,
-                                       return_samples=True)
         per_round = sum(counts[:ns])
-        deltas = []
-        for i in range(len(sub)):
-            cols = torch.cat([torch.arange(r * per_round + sum(counts[:i]), r * per_round + sum(counts[:i + 1]),
-                                           device=th.device) for r in range(rounds)])
-            t_i = th[:, cols]
-            l32 = hs.lnL(t_i, [(i, 0, t_i.shape[1])])
-            l64 = h64.lnL(t_i.double(), [(i, 0, t_i.shape[1])])
-            r64 = h64.reduce(l64 + (lw[cols].double() - l32.double()))
-            deltas.append(abs(res32[i]["lnL_marg"] - r64["lnL_marg"]))
-        out["fp64_replay"] = {"points": ns, "samples": sum(counts[:ns]) * rounds, "max_abs_delta_lnL_marg": max(deltas),
-                              "abs_delta_lnL_marg": deltas, "n_eff": [r["n_eff"] for r in res32]}
+
+        def replay(kw):
+            res32, th, lw = hs.marginalize(seed + 13, counts[:ns], n_rounds=rounds, adapt_mask=mask, floor_eps=0.1,
+                                           return_samples=True, **kw)
+            deltas = []
+            for i in range(len(sub)):
+                cols = torch.cat([torch.arange(r * per_round + sum(counts[:i]), r * per_round + sum(counts[:i + 1]),
+                                               device=th.device) for r in range(rounds)])
+                t_i = th[:, cols]
+                l32 = hs.lnL(t_i, [(i, 0, t_i.shape[1])])
+                l64 = h64.lnL(t_i.double(), [(i, 0, t_i.shape[1])])
+                r64 = h64.reduce(l64 + (lw[cols].double() - l32.double()))
+                deltas.append(abs(res32[i]["lnL_marg"] - r64["lnL_marg"]))
+            return {"points": ns, "samples": per_round * rounds, "max_abs_delta_lnL_marg": max(deltas),
+                    "abs_delta_lnL_marg": deltas, "n_eff": [r["n_eff"] for r in res32]}
+
+        out["fp64_replay"] = replay({})
+        if w.adaptive:
+            # the same with the Gaussian-mixture proposal and the pairs (psi, phi), (iota, D)
+            out["fp64_replay_gmm"] = replay(dict(gmm_components=3, gmm_pairs=((2, 4), (3, 5))))
         hs.close()
         h64.close()
 
