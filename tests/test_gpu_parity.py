@@ -1331,3 +1331,18 @@ def test_gmm_full_floor_is_the_prior(ile, K, pairs):
     assert h.get_gmm_pairs(0)["pairs"] == list(pairs)
     assert np.all(np.isfinite(g["mu"][:, :K])) and np.all(g["sd"][:, :K] > 0)
     h.close()
+
+
+def test_gmm_with_an_empty_point(ile):
+    """A point with no samples among others: its mixture stays the initial
+    one (nothing fitted), the others adapt, no fault and no NaN estimate for
+    the points that have samples."""
+    w = synth.workload("tiny_batched")
+    pts = [synth.make_point(s) for s in w.points[:3]]
+    h = _handle(ile, pts, "fp32")
+    res = h.marginalize(2210079134, [3000, 0, 2000], n_rounds=3, adapt_mask=0x3F, floor_eps=0.1, gmm_components=2,
+                        gmm_pairs=((3, 5),))
+    assert res[1]["n"] == 0 and res[1]["lnL_marg"] == -np.inf
+    assert np.isfinite(res[0]["lnL_marg"]) and np.isfinite(res[2]["lnL_marg"])
+    assert h.get_gmm(1)["n_trained"] == 0 and h.get_gmm(0)["n_trained"] == 9000
+    h.close()
