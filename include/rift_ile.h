@@ -10,7 +10,11 @@
  * Eq. (def:lnL:Decomposed) with the overlaps of Eq. (QUV); the Monte Carlo
  * estimate is Sec. II.A Eq. (lnL:MonteCarlo); the sample-size measures are
  * App. B Eqs. (neff), (neff_ESS) and the variance-based size; the adaptive
- * histogram proposal is Sec. III.B (GPU-accelerated Monte Carlo integration).
+ * histogram proposal is Sec. III.B (GPU-accelerated Monte Carlo integration);
+ * the Gaussian-mixture proposal, separable and with correlated pairs, is
+ * Sec. III.B (adaptive sampling with Gaussian mixture models) with App. A.
+ * Beyond those: the adjoint gradient, the Q/U/V precompute of Eq. (QUV),
+ * network-frame sky coordinates (Sec. II.A), and checkpoints of a run.
  *
  * Conventions common to every call
  *   - No C++ exception crosses this boundary.  Every call returns a
