@@ -31,7 +31,7 @@ PEAK = {"fp32_mfma_tflops": 157.3, "fp64_tflops": 78.6, "hbm_gbs": 8000.0}
 # rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0) passes, the factors read
 # off a plain device copy (profiles/mfma_kernel_single_1e6.md).  It describes
 # the kernel as it was measured and is reported for that workload only.
-MEASURED_TRAFFIC = {"single": 377499280.0}
+MEASURED_TRAFFIC = {"single": 377580268.0}
 
 
 def flops_per_eval(K, M, n_t):
