@@ -269,6 +269,21 @@ rift_status rift_ile_precompute(const rift_ile_fd_point *in, int64_t row0, int64
  * equatorial axes.  Default off.  Returns RIFT_E_INVALID for a NULL handle. */
 rift_status rift_ile_set_network_frame(rift_ile *h, int enable);
 
+/* Precision of the FP32 adjoint (rift_ile_backward on an RIFT_FP32 handle).
+ * The gradient of ln L_t is an average of d ell_j / d theta under the window
+ * softmax p_j (App. D Eq. (def:lnL:Decomposed) differentiated).  For a loud
+ * sample the data term and the quadratic term nearly cancel in each component,
+ * and FP32 rounding of the contraction is then a visible part of the result.
+ * With enable != 0 (the default), every sample whose softmax mass lies in at
+ * most 3 window blocks of 16 samples (the blocks whose maximum came within
+ * 40 of the sample's running maximum ell) is re-evaluated in FP64 over those
+ * blocks: coefficients, quadratic term, contraction, ell_j, p_j and the chain
+ * rule; its gradient and ln L_t output are replaced by the FP64 values (mass
+ * outside the blocks is below n_t e^-40 of the total).  Other samples keep
+ * the FP32 values.  enable == 0: FP32 throughout.  Returns RIFT_E_INVALID for
+ * a NULL handle. */
+rift_status rift_ile_set_grad_refine(rift_ile *h, int enable);
+
 /* Per-class choice of how the FP32 evaluation feeds the matrix cores
  * (batching: every (T, K) class of points, T = ceil(M / 2) MFMA steps and K
  * detectors, is one persistent launch).  Two forms of the same kernel exist:

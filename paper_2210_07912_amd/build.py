@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librift_ile.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["rift_ile.hip", "k_plain.hip", "k_mfma.hip", "k_bwd.hip", "k_mc.hip", "k_grad.hip", "k_quv.hip"]
+SOURCES = ["rift_ile.hip", "k_plain.hip", "k_mfma.hip", "k_bwd.hip", "k_mc.hip", "k_grad.hip", "k_quv.hip", "k_refine.hip"]
 ARCH = os.environ.get("RIFT_ILE_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

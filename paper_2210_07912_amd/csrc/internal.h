@@ -107,6 +107,9 @@ struct MfmaArgs {
   float *grad;            // [7][stride] gradient of ln L_t (times gin)
   float *gop;             // per point [tiles][K][2 Mp][16]: G_k = sum_r c_k[r] Q_k[r] (cop layout)
   float *hop;             // [tiles][kMaxDet][16]: H_k = sum_j p_j Re(a^dag Qtilde'_k(j))
+  int *jrng;              // [16 max_tiles][4] or null: the samples to refine, appended in any order (count in
+                          // ctl[kCtlRefine]): sorted slot, then the window blocks whose maximum is within
+                          // kRefineNats of the sample's (b0 | b1 << 16, b2 | count << 16)
   int n_bins;
   int max_item_bins;      // largest bin count of one point
   int n_sort_blocks;
@@ -164,6 +167,15 @@ inline void fan_join(const Fanout &fo, hipStream_t st, int n_classes) {
     (void)hipStreamWaitEvent(st, fo.join[i], 0);
   }
 }
+// FP64 re-evaluation of the adjoint over the window blocks that hold each
+// sample's softmax mass (samples whose mass lies in at most kRefineBlocks
+// blocks of 16 window samples, anywhere in the window); overwrites grad and
+// lnL of those samples.  Launched after the
+// chain rule on the same stream.
+constexpr int kRefineBlocks = 3;
+constexpr int kCtlRefine = 1 + kMaxClasses;  // ctl slot of the refinement count
+constexpr float kRefineNats = 40.f;
+hipError_t refine_backward(const MfmaArgs &a, hipStream_t st);
 // the part both share: delay-bin sort, tile records, coefficient pass, work units
 hipError_t mfma_prepare(const MfmaArgs &a, const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles,
                         int n_mclasses, hipStream_t st);

@@ -153,10 +153,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) m
         if ((b & 1) == 0) *(f4 *)(wp + k * kTS * kRZ + 32) = acc[k];
       }
     };
-    // window samples 16 c + 4 g + i of block c: ell (base 2) and, when
-    // wanted, the derivative interpolation zd_k
+    // window samples 16 c + 4 g + i of block c: ell + B - m_ref (base 2) and,
+    // when wanted, the derivative interpolation zd_k.  The quadratic term B is
+    // the same for every window sample: it stays out of the softmax (whose
+    // weights it does not change) and enters ln L_t once at the end, so the
+    // window values carry the rounding of the data term only.
+    float m_ref = 0.f;
     auto interp = [&](int c, float (&ell)[4], float (&zd)[K][4], bool want_d) {
-      const float base = -Bf;
+      const float base = -m_ref;
 #pragma unroll
       for (int i = 0; i < 4; i++) ell[i] = (c == JB - 1) ? base + last_pen[i] : base;
 #pragma unroll
@@ -178,14 +182,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) m
     };
 
     // ---- one sweep: z_k, then per window block ell_j, the unnormalized
-    // softmax weights p_j = 2^(ell_j - m_ref), H_k, c_k and G_k = Q_k^T c_k.
+    // softmax weights p_j = 2^(ell_j + B - m_ref), H_k, c_k and G_k = Q_k^T c_k.
     // m_ref is shared by the 4 lanes of a sample (the G products and the
-    // rows' taps mix their p): the first window block's maximum, moved only
+    // rows' taps mix their p): the first window block's maximum of ell + B, moved only
     // when a block's maximum exceeds it by 64, and then every sum kept so far
     // (G, H, the sum of p and the p of the previous block in the ring) is
     // scaled by 2^(m_ref - m_new).  At the end all of them are divided by the
     // sum of p, which also gives ln L_t.
-    float m_ref = 0.f, s_run = 0.f;
+    float s_run = 0.f;
+    // Where the window's mass lies (for the FP64 refinement): the three
+    // largest block maxima (t1 >= t2 >= t3, blocks i1, i2, i3) and the
+    // largest maximum of every other block (rest)
+    constexpr float kRefD2 = kRefineNats * 1.4426950408889634f;  // base 2
+    float t1 = -INFINITY, t2 = -INFINITY, t3 = -INFINITY, rest = -INFINITY;
+    int i1 = 0, i2 = 0, i3 = 0;
     float hsum[K];
 #pragma unroll
     for (int k = 0; k < K; k++) hsum[k] = 0.f;
@@ -236,9 +246,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) m
           float cmax = fmaxf(fmaxf(ell[0], ell[1]), fmaxf(ell[2], ell[3]));
           cmax = fmaxf(cmax, __shfl_xor(cmax, 16));
           cmax = fmaxf(cmax, __shfl_xor(cmax, 32));
-          if ((c == 0 || cmax > m_ref + 64.f) && cmax > -3.0e38f) {  // uniform over a sample's lanes
+          {
+            const float v = cmax > -3.0e38f ? cmax + m_ref : -INFINITY;
+            if (v > t3) {
+              rest = fmaxf(rest, t3);
+              if (v > t1) {
+                t3 = t2; i3 = i2;
+                t2 = t1; i2 = i1;
+                t1 = v; i1 = c;
+              } else if (v > t2) {
+                t3 = t2; i3 = i2;
+                t2 = v; i2 = c;
+              } else {
+                t3 = v; i3 = c;
+              }
+            } else {
+              rest = fmaxf(rest, v);
+            }
+          }
+          if ((c == 0 || cmax > 64.f) && cmax > -3.0e38f) {  // uniform over a sample's lanes
             if (c > 0) {
-              const float f = __builtin_amdgcn_exp2f(m_ref - cmax);
+              const float f = __builtin_amdgcn_exp2f(-cmax);
               s_run *= f;
 #pragma unroll
               for (int k = 0; k < K; k++) {
@@ -251,11 +279,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) m
               *(f4 *)pq = pv;
               if (((c - 1) & 1) == 0) *(f4 *)(pq + 32) = pv;
             }
-            m_ref = cmax;
+            m_ref += cmax;
+#pragma unroll
+            for (int i = 0; i < 4; i++) ell[i] -= cmax;
           }
           float pj[4];
 #pragma unroll
-          for (int i = 0; i < 4; i++) pj[i] = __builtin_amdgcn_exp2f(ell[i] - m_ref);
+          for (int i = 0; i < 4; i++) pj[i] = __builtin_amdgcn_exp2f(ell[i]);
 #pragma unroll
           for (int i = 0; i < 4; i++) s_run += pj[i];
 #pragma unroll
@@ -276,7 +306,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) m
     float ssum = s_run;
     ssum += __shfl_xor(ssum, 16);
     ssum += __shfl_xor(ssum, 32);
-    const float L2 = m_ref + __log2f(ssum);
+    const float L2 = (m_ref - Bf) + __log2f(ssum);
     float lt = L2 * kLn2f - __logf((float)NT);
     if (!valid || !isfinite(lt)) {
       lt = NAN;
@@ -313,6 +343,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) m
               if (e < E) go[((size_t)k * E + e) * kTS + s] = gacc[k][mt][v] * inv;
             }
         if (g == 0) {
+          if (a.jrng) {
+            // the blocks within kRefD2 of the sample's maximum, when every
+            // other block lies further below it: (blocks, count) or count 0
+            const float thr = t1 - kRefD2;
+            const int nb = (t2 >= thr ? (t3 >= thr ? 3 : 2) : 1);
+            const bool ok = valid && t1 > -3.0e38f && rest < thr && i1 < 65536 && i2 < 65536 && i3 < 65536;
+            if (ok) {
+              const uint32_t r = atomicAdd(&a.ctl[kCtlRefine], 1u);
+              RIFT_GLOBAL int *jo = gpw(a.jrng) + 4 * (size_t)r;
+              jo[0] = (int)(t * kTS + s);
+              jo[1] = i1 | ((nb > 1 ? i2 : 0) << 16);
+              jo[2] = (nb > 2 ? i3 : 0) | (nb << 16);
+            }
+          }
           if (a.lnL) gpw(a.lnL)[col] = lt;
           if (a.lnw) gpw(a.lnw)[col] = lt + (a.ln_ratio ? gp(a.ln_ratio)[col] : 0.f);
         }
@@ -519,7 +563,9 @@ hipError_t mfma_backward(const MfmaArgs &a, const int *class_T, const int *class
       default: hipLaunchKernelGGL(chain_kernel<0>, grid, dim3(64), 0, st, a, lo, hi); break;
     }
   }
-  return hipGetLastError();
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return refine_backward(a, st);
 }
 
 }  // namespace rift

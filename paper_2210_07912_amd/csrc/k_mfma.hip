@@ -205,6 +205,7 @@ __global__ void item_scan_kernel(MfmaArgs a) {
     }
     a.ctl[0] = r;
     for (int c = 0; c < kMaxClasses; c++) a.ctl[1 + c] = 0;
+    a.ctl[kCtlRefine] = 0;
     uint32_t u = 0;
     a.item_units[0] = 0;
     for (int i = 0; i < a.items.n_items; i++) {
@@ -620,13 +621,16 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
     };
     // window samples 16 c + 4 g + i (i < 4) of the block in ring slot SL:
     // interpolation, then the log-sum-exp with a lazy reference m_run: sums
-    // are kept as exp2(ell - m_run), m_run is the first block's maximum and
-    // moves only when a value exceeds it by 64, which keeps every sum far
-    // from overflow while terms lost below it are under 2^-126 of the sum
+    // are kept as exp2(ell + B - m_run), m_run is the first block's maximum
+    // and moves only when a value exceeds it by 64, which keeps every sum far
+    // from overflow while terms lost below it are under 2^-126 of the sum.
+    // The quadratic term B is the same for every window sample, so it stays
+    // out of the sums and is subtracted once at the end: the window values
+    // then carry the rounding of the data term only, not of B.
     float m_run = 0.f, s_run = 0.f;
     auto window = [&](auto sl_c, bool last, bool first) {
       constexpr int SL = decltype(sl_c)::value;
-      const float base = -Bf - m_run;
+      const float base = -m_run;
       float ell[4];
 #pragma unroll
       for (int i = 0; i < 4; i++) ell[i] = last ? base + last_pen[i] : base;
@@ -719,7 +723,7 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
       float sc = s_run * __builtin_amdgcn_exp2f(m_run - mo);
       sc += __shfl_xor(sc, 16);
       sc += __shfl_xor(sc, 32);
-      float lt = (mo + __log2f(sc)) * kLn2f - __logf((float)NT);
+      float lt = ((mo - Bf) + __log2f(sc)) * kLn2f - __logf((float)NT);
       if (!valid || !isfinite(lt)) lt = NAN;
       if (flag != 0 && g == 0) {
         if (a.lnL) gpw(a.lnL)[col] = lt;

@@ -11,7 +11,9 @@
 //      from L2 and reused across the tile's samples), then the 4-tap
 //      interpolation of z (which commutes with the linear contraction) is
 //      accumulated into ell_j for the window j = 0..n_t-1;
-//   3. ln L_t = max-shifted log-sum-exp over j minus ln n_t (App. D.2).
+//   3. ln L_t = max-shifted log-sum-exp over j minus ln n_t (App. D.2); the
+//      window sums hold the data term only, and B (the same for every j) is
+//      subtracted once at the end, so the sums carry no rounding of B.
 // The adjoint recomputes ell_j, forms p_j = exp(ell_j - ln L_t - ln n_t) and
 // the detector sums G_k = sum_j p_j Qtilde_k(j), H_k = sum_j p_j Re(a^dag
 // Qtilde'_k(j)), and applies the chain rule through F, Y, D and the delays.
@@ -204,7 +206,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgsT<R> args) {
           int b = P + j + nk[s * kMaxDet + k] - rlo;  // row of tap q = -1
           const R *z = zbuf + s * args.rows_cap + b;
           R v = w[0] * z[0] + w[1] * z[1] + w[2] * z[2] + w[3] * z[3];
-          R prev = (k == 0) ? (R)(-Bs[s]) : lbuf[s * args.nt_cap + j];
+          R prev = (k == 0) ? R(0) : lbuf[s * args.nt_cap + j];
           lbuf[s * args.nt_cap + j] = prev + v;
         }
       } else {
@@ -260,7 +262,10 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgsT<R> args) {
       R sum = R(0);
       for (int j = g; j < NT; j += G) sum += r_exp<R>(lbuf[s * args.nt_cap + j] - mx);
       for (int o = G / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, G);
-      R lt = mx + r_log<R>(sum) - r_log<R>((R)NT);
+      // the window holds the data term only: the quadratic term B is the
+      // same for every window sample and is subtracted once, in FP64
+      const R lse = mx + r_log<R>(sum);
+      R lt = (R)((double)lse - Bs[s] - log((double)NT));
       bool ok = okv[s] && isfinite((double)lt);
       if (!ok) lt = R(NAN);
       if (g == 0) {
@@ -272,8 +277,8 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgsT<R> args) {
       }
       if (BWD) {
         __syncthreads();
-        // p_j = exp(ell_j - ln L_t - ln n_t)
-        R sub = ok ? lt + r_log<R>((R)NT) : R(0);
+        // p_j = exp(ell_j + B - lse)
+        R sub = ok ? lse : R(0);
         for (int j = g; j < NT; j += G)
           lbuf[s * args.nt_cap + j] = ok ? r_exp<R>(lbuf[s * args.nt_cap + j] - sub) : R(0);
       }

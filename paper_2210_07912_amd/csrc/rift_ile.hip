@@ -65,6 +65,8 @@ struct rift_ile {
   int feed = 1;
   int kmode[kMaxT + 1][kMaxDet + 1] = {};
   double ws_budget = 6.0e9;
+  // FP64 refinement of the matrix-core adjoint (rift_ile_set_grad_refine)
+  bool refine = true;
   // optional timing of the dominant evaluation kernel
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
@@ -76,7 +78,7 @@ enum WsId {
   W_ITEM_POINT, W_ITEM_OFF, W_ITEM_CNT, W_ITEM_TILE0, W_ITEM_SAMP0, W_ITEM_BIN0,
   W_KEY, W_NSH, W_COUNT, W_CURSOR, W_COP, W_BINTILE, W_ITEMTILES, W_PERM, W_TILES, W_CTL, W_CTILE,
   W_PARTIALS, W_ROUND, W_ACCUM, W_RESULT, W_HIST, W_THETA, W_LNW, W_AUX, W_RATIO, W_BINS, W_ITEM_BLK0,
-  W_ITEM_HOFF, W_ITEM_COP, W_SEG_OFF, W_SEG_CNT, W_ASC, W_AHIST, W_UNIT, W_BINUNIT, W_ITEMUNITS, W_GOP, W_HOP, W_SEG_BLK, W_UBUF, W_EMPART, W_EMPART2, W_GMMFIT, W_EMWT, W_COUNT_IDS
+  W_ITEM_HOFF, W_ITEM_COP, W_SEG_OFF, W_SEG_CNT, W_ASC, W_AHIST, W_UNIT, W_BINUNIT, W_ITEMUNITS, W_GOP, W_HOP, W_SEG_BLK, W_UBUF, W_EMPART, W_EMPART2, W_GMMFIT, W_EMWT, W_JRNG, W_COUNT_IDS
 };
 static_assert(W_COUNT_IDS <= 48, "workspace table too small");
 
@@ -618,6 +620,10 @@ rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const f
     a.gop = (float *)p;
     if ((s = ws_get(h, W_HOP, sizeof(float) * kMaxDet * 16 * (size_t)max_tiles, &p)) != RIFT_OK) return s;
     a.hop = (float *)p;
+    if (h->refine) {
+      if ((s = ws_get(h, W_JRNG, 4 * sizeof(int) * 16 * (size_t)max_tiles, &p)) != RIFT_OK) return s;
+      a.jrng = (int *)p;
+    }
     a.gin = gin;
     a.grad = grad;
   }
@@ -1191,6 +1197,12 @@ rift_status rift_ile_precompute(const rift_ile_fd_point *in, int64_t row0, int64
 rift_status rift_ile_set_network_frame(rift_ile *h, int enable) {
   if (!h) return RIFT_E_INVALID;
   h->net_frame = enable != 0;
+  return RIFT_OK;
+}
+
+rift_status rift_ile_set_grad_refine(rift_ile *h, int enable) {
+  if (!h) return RIFT_E_INVALID;
+  h->refine = enable != 0;
   return RIFT_OK;
 }
 

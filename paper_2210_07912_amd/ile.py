@@ -96,6 +96,7 @@ FUNCTIONS = {
     "rift_ile_graph_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "rift_ile_set_autotune": (C.c_int, [C.c_void_p, C.c_int]),
     "rift_ile_set_network_frame": (C.c_int, [C.c_void_p, C.c_int]),
+    "rift_ile_set_grad_refine": (C.c_int, [C.c_void_p, C.c_int]),
     "rift_ile_precompute": (C.c_int, [C.POINTER(FdPoint), C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
                                       C.c_void_p]),
     "rift_ile_autotune_table": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
@@ -237,6 +238,11 @@ class RiftILE:
         the baseline of its detectors 0 and 1); the histograms of dimensions
         0 and 1 then adapt in that frame's azimuth and polar cosine."""
         self._check(lib().rift_ile_set_network_frame(self.h, int(enable)))
+
+    def set_grad_refine(self, enable=True):
+        """FP64 re-evaluation of the FP32 adjoint over the window blocks that
+        hold each sample's softmax mass (default on)."""
+        self._check(lib().rift_ile_set_grad_refine(self.h, int(enable)))
 
     def set_autotune(self, mode=1):
         """How FP32 evaluations feed the matrix cores: 1 (default) measure the

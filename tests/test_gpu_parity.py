@@ -478,59 +478,46 @@ def test_backward_matches_oracle(ile, orc):
             assert rel.max() < 1e-9
             assert np.allclose(lg, lt, atol=1e-9)
         else:
-            _grad_check(gg, lg, g, lt, "backward fp32", _tau_sensitivity(orc, p, th), f_s=spec.f_s)
+            _grad_check(gg, lg, g, lt, th, "backward fp32", f_s=spec.f_s)
 
 
-def _fp32_grad_tol(g, lt, sens, f_s):
-    """Tolerance of an FP32 gradient against the oracle, per component.
-
-    alpha, delta, psi, iota, phi, D: 1e-4 of the sample's largest gradient
-    component.  tau: the same plus the FP32 floor of the window softmax.
-    d lnL_t / d tau = sum_j p_j d ell_j / d tau is the residual of terms that
-    largely cancel (a peak sampled on a grid barely moves its sum when the
-    grid shifts), and every p_j carries the FP32 rounding of ell_j = data - B,
-    an error of sqrt(2M x 4 taps x K) ~ 22 unit roundoffs (eps = 2^-24) of
-    the data term's size Z = |lnL_t| + 2 B, since every window value sums
-    that many products, each up to Z in size (the observed |d lnL_t| agree);
-    sens = (Z, A) with A = sum_j p_j |d ell_j / d tau| (the oracle's), so
-    |d g_tau| <~ 32 eps Z A.  A defect in the adjoint shows as errors many
-    times larger."""
-    Z, A = sens
-    scale = np.abs(g).max(axis=0) + 1e-3
-    tol = np.tile(1e-4 * scale, (7, 1))
-    tol[6] += 32 * 2.0 ** -24 * Z * A
-    return scale, tol
+# The gradient target: every component of d lnL_t / d theta within 1e-4 of
+# the sample's gradient, measured in consistent units (angles in radians,
+# distance as ln D, tau in window samples), so that no component's unit
+# decides the scale.
+GRAD_REL = 1e-4
+PLAIN_GRAD_REL = 1e-3
 
 
-def _tau_sensitivity(orc, p, th, h=1e-7):
-    """(Z, A) of every sample from the oracle: Z = |lnL_t| + 2 B and
-    A = sum_j p_j |d ell_j / d tau| (central differences in tau, FP64)."""
-    Z, A = np.zeros(th.shape[1]), np.zeros(th.shape[1])
-    for i in range(th.shape[1]):
-        t = th[:, i].copy()
-        ell = orc.ell(p, t)
-        B = orc.coeffs(p, t)[1]
-        tp, tm = t.copy(), t.copy()
-        tp[6] += h
-        tm[6] -= h
-        d = (orc.ell(p, tp) - orc.ell(p, tm)) / (2 * h)
-        w = np.exp(ell - ell.max())
-        w /= w.sum()
-        Z[i] = abs(ell.max()) + 2 * abs(B)
-        A[i] = np.sum(w * np.abs(d))
-    return Z, A
+def _consistent(g, th, f_s):
+    """Gradient [7, N] in consistent units: d/d(angle), D d/dD, (1/f_s) d/dtau."""
+    u = np.array(g, dtype=np.float64, copy=True)
+    u[5] = u[5] * np.asarray(th)[5]
+    u[6] = u[6] / f_s
+    return u
 
 
-def _grad_check(gg, lg, g, lt, label, sens, f_s=4096.0):
-    scale, tol = _fp32_grad_tol(g, lt, sens, f_s)
-    err = np.abs(gg - g)
-    rel = err / scale
-    _say(f"[{label}] max rel grad err per parameter {np.array2string(rel.max(axis=1), precision=2)}, "
-         f"max err/tol {np.max(err / tol):.3f}, max |d lnL_t| {np.abs(lg - lt).max():.3e}")
-    d, i = np.unravel_index(np.argmax(err / tol), err.shape)
-    _say(f"   worst: param {d} sample {i}: lnL_t {lt[i]:.4f} Z {sens[0][i]:.4g} A {sens[1][i]:.4g} ref {g[d, i]:.6g} "
-         f"got {gg[d, i]:.6g} tol {tol[d, i]:.3g}")
-    assert np.all(err <= tol), (label, d, i)
+def _grad_check(gg, lg, g, lt, th, label, f_s=4096.0, tol=GRAD_REL, own_top=True):
+    """FP32 gradient gg (and ln L_t lg) against the FP64 reference g (lt):
+    every component within tol of the sample's largest component, in
+    consistent units; on the samples that carry the weight (ln L_t within 20
+    of the largest) every component that is at least 1e-3 of that largest one
+    also within tol of its own size (for loud points, whose weight-carrying
+    samples have their mass in a few window blocks and are refined in FP64)."""
+    ug, ur = _consistent(gg, th, f_s), _consistent(g, th, f_s)
+    scale = np.abs(ur).max(axis=0)
+    rel = np.abs(ug - ur) / np.maximum(scale, 1e-300)
+    per = rel.max(axis=1)
+    _say(f"[{label}] n={rel.shape[1]} max |d g_c| / |g|_inf per component "
+         f"(alpha, delta, psi, iota, phi, ln D, tau/f_s) {np.array2string(per, precision=2)}")
+    d, i = np.unravel_index(np.argmax(rel), rel.shape)
+    assert rel.max() <= tol, (label, d, i, lt[i], ur[:, i], ug[:, i])
+    if own_top:
+        top = lt >= np.nanmax(lt) - 20.0
+        big = np.abs(ur) >= 1e-3 * scale
+        own = np.where(big & top[None, :], np.abs(ug - ur) / np.maximum(np.abs(ur), 1e-300), 0.0)
+        _say(f"   weight-carrying samples: {int(top.sum())}, max own-relative error {own.max():.2e}")
+        assert own.max() <= tol, (label, np.unravel_index(np.argmax(own), own.shape))
     _check_fp32(lg, lt, label)
 
 
@@ -545,7 +532,6 @@ def test_backward_mfma_shapes(ile, orc):
     th = synth.mixed_samples(d, 12, 1031, tau_width=tw)
     op = orc.Point.from_dict(d, complex64=True)
     lt, g = orc.grad(op, th)
-    sens = _tau_sensitivity(orc, op, th)
     _say("backward grad shape, mfma and plain")
     h = _handle(ile, [d], "fp32", tau_width=tw)
     gg, lg = h.backward(torch.tensor(th), want_lnL=True)
@@ -553,9 +539,10 @@ def test_backward_mfma_shapes(ile, orc):
     gp_, lp = hp.backward(torch.tensor(th), want_lnL=True)
     gp_, lp = gp_.cpu().numpy(), lp.cpu().numpy()
     try:
-        _grad_check(gg.cpu().numpy(), lg.cpu().numpy(), g, lt, "mfma adjoint, grad shape", sens)
+        _grad_check(gg.cpu().numpy(), lg.cpu().numpy(), g, lt, th, "mfma adjoint, grad shape")
     finally:
-        _grad_check(gp_, lp, g, lt, "plain adjoint, grad shape", sens)
+        # the plain FP32 form has no FP64 refinement: FP32 rounding throughout
+        _grad_check(gp_, lp, g, lt, th, "plain adjoint, grad shape", tol=PLAIN_GRAD_REL, own_top=False)
     # upstream gradient and V != 0
     dv = synth.make_point(synth.PIN_SPECS[3])
     thv = synth.mixed_samples(dv, 13, 257, tau_width=tw)
@@ -565,8 +552,7 @@ def test_backward_mfma_shapes(ile, orc):
     hv = _handle(ile, [dv], "fp32", tau_width=tw)
     _say("backward V != 0 with an upstream gradient")
     ggv, lgv = hv.backward(torch.tensor(thv), grad_lnL=torch.tensor(up), want_lnL=True)
-    Zv, Av = _tau_sensitivity(orc, opv, thv)
-    _grad_check(ggv.cpu().numpy(), lgv.cpu().numpy(), gv * up[None, :], ltv, "mfma adjoint, V != 0", (Zv, Av * up))
+    _grad_check(ggv.cpu().numpy(), lgv.cpu().numpy(), gv * up[None, :], ltv, thv, "mfma adjoint, V != 0")
     # several points in one call
     w = synth.workload("tiny_batched")
     pts = [synth.make_point(sp) for sp in w.points]
@@ -576,7 +562,7 @@ def test_backward_mfma_shapes(ile, orc):
         t_ = synth.mixed_samples(dd, 200 + i, n, tau_width=tw)
         ths.append(t_)
         od = orc.Point.from_dict(dd, complex64=True)
-        refs.append(orc.grad(od, t_) + (_tau_sensitivity(orc, od, t_),))
+        refs.append(orc.grad(od, t_))
         items.append((i, off, n))
         off += n
     hb = _handle(ile, pts, "fp32", tau_width=tw)
@@ -584,7 +570,8 @@ def test_backward_mfma_shapes(ile, orc):
     gb, lb = hb.backward(torch.tensor(np.concatenate(ths, axis=1)), items=items, want_lnL=True)
     gb, lb = gb.cpu().numpy(), lb.cpu().numpy()
     for i, (_, o, n) in enumerate(items):
-        _grad_check(gb[:, o:o + n], lb[o:o + n], refs[i][1], refs[i][0], f"mfma adjoint, point {i}", refs[i][2])
+        _grad_check(gb[:, o:o + n], lb[o:o + n], refs[i][1], refs[i][0], ths[i], f"mfma adjoint, point {i}",
+                    f_s=pts[i]["f_s"])
 
 
 def test_lnL_with_V(ile, orc):
@@ -628,8 +615,9 @@ def test_high_l_modes(ile, orc):
             _check_fp32(out, ref, "high-l fp32")
             lt, g = orc.grad(p, th)
             gg, lg = h.backward(torch.tensor(th), want_lnL=True)
-            _grad_check(gg.cpu().numpy(), lg.cpu().numpy(), g, lt, "high-l backward fp32", _tau_sensitivity(orc, p, th),
-                        f_s=spec.f_s)
+            # noise only (no loud samples to refine): the norm-relative bound only
+            _grad_check(gg.cpu().numpy(), lg.cpu().numpy(), g, lt, th, "high-l backward fp32", f_s=spec.f_s,
+                        own_top=False)
         else:
             assert np.all(np.abs(out - ref) <= 1e-9 * (1 + np.abs(ref)))
 
@@ -656,8 +644,8 @@ def test_single_detector_ragged_window(ile, orc):
         if mode == 0:
             lt, g = orc.grad(p32, th)
             gg, lg = h.backward(torch.tensor(th), want_lnL=True)
-            _grad_check(gg.cpu().numpy(), lg.cpu().numpy(), g, lt, "K=1 backward fp32", _tau_sensitivity(orc, p32, th),
-                        f_s=spec.f_s)
+            _grad_check(gg.cpu().numpy(), lg.cpu().numpy(), g, lt, th, "K=1 backward fp32", f_s=spec.f_s,
+                        own_top=False)
         h.close()
     assert np.array_equal(outs[0], outs[1], equal_nan=True)
     p64 = orc.Point.from_dict(d)
@@ -701,11 +689,23 @@ def test_single_point_full_size(ile, orc):
     assert abs(r32["lnL_marg"] - r64["lnL_marg"]) <= 1e-3
 
 
+def _rounded(d):
+    """The point with Q, U (and V) rounded to complex64: the inputs an FP32
+    handle holds, for an FP64 reference on the same values."""
+    r = dict(d)
+    for k in ("Q", "U", "V"):
+        if r.get(k) is not None:
+            r[k] = np.asarray(r[k]).astype(np.complex64).astype(np.complex128)
+    return r
+
+
 def test_gradient_full_size(ile, orc):
     """The gradient workload at full size through the launch the benchmark
-    times (10^5 samples drawn on the device, one adjoint call): sampled
-    gradients (random samples plus the 20 largest ln L_t) against the oracle's
-    FP64 gradient, with the FP32 tolerance of the smaller adjoint tests."""
+    times (10^5 samples drawn on the device, one adjoint call): every
+    sample's FP32 gradient against the FP64 adjoint on the same FP32-rounded
+    inputs (itself held to the oracle at 1e-9 in the smaller tests), and a
+    sample of them (random plus the 20 largest ln L_t) against the oracle's
+    FP64 gradient directly; per component in consistent units, 1e-4."""
     w = synth.workload("grad")
     d = synth.make_point(w.points[0])
     n = w.n_samples[0]
@@ -713,13 +713,61 @@ def test_gradient_full_size(ile, orc):
     th, _, _ = h.sample(0, 2210079124, 0, n)
     _say(f"gradient full size n={n}")
     g, lt = h.backward(th, want_lnL=True)
+    h64 = _handle(ile, [_rounded(d)], "fp64", tau_width=w.tau_width)
+    g64, l64 = h64.backward(th.double(), want_lnL=True)
     th = th.cpu().numpy().astype(np.float64)
-    g, lt = g.cpu().numpy(), lt.cpu().numpy()
+    g, lt, g64, l64 = g.cpu().numpy(), lt.cpu().numpy(), g64.cpu().numpy(), l64.cpu().numpy()
+    assert np.isfinite(g).all() and np.isfinite(g64).all()
+    _grad_check(g, lt, g64, l64, th, "grad full size vs fp64 adjoint", f_s=d["f_s"])
     idx = np.random.default_rng(1).choice(n, 250, replace=False)
     idx = np.unique(np.concatenate([idx, np.argsort(lt)[-20:]]))
     p = orc.Point.from_dict(d, complex64=True)
     lref, gref = orc.grad(p, th[:, idx])
-    _grad_check(g[:, idx], lt[idx], gref, lref, "grad full size", _tau_sensitivity(orc, p, th[:, idx]), f_s=d["f_s"])
+    _grad_check(g[:, idx], lt[idx], gref, lref, th[:, idx], "grad full size vs oracle", f_s=d["f_s"])
+    rel64 = np.abs(_consistent(g64[:, idx], th[:, idx], d["f_s"]) - _consistent(gref, th[:, idx], d["f_s"]))
+    assert (rel64 / np.abs(_consistent(gref, th[:, idx], d["f_s"])).max(axis=0)).max() <= 1e-9
+
+
+def test_autograd_function(ile, orc):
+    """ln L_t behind torch.autograd.Function: the gradient autograd returns for
+    a weighted sum of ln L_t equals the adjoint called directly with those
+    weights, and matches FP64 central differences of ln L_t taken through an
+    FP64 handle (same FP32-rounded inputs) per component in consistent units."""
+    w = synth.workload("grad")
+    d = synth.make_point(w.points[0])
+    tw = w.tau_width
+    h = _handle(ile, [d], "fp32", tau_width=tw)
+    h64 = _handle(ile, [_rounded(d)], "fp64", tau_width=tw)
+    th = synth.mixed_samples(d, 41, 64, tau_width=tw)
+    t = torch.tensor(th, dtype=torch.float32, device="cuda", requires_grad=True)
+    wts = torch.linspace(0.5, 1.5, th.shape[1], device="cuda")
+    lnl = ile.lnL_autograd(h, t)
+    (wts * lnl).sum().backward()
+    ga = t.grad.detach().cpu().numpy().astype(np.float64)
+    gd = h.backward(t.detach(), grad_lnL=wts).cpu().numpy().astype(np.float64)
+    assert np.array_equal(ga, gd), "autograd backward differs from the direct adjoint call"
+    # central differences in FP64 (steps: 1e-7 rad, 1e-7 relative in D,
+    # 1e-10 s; small enough that a step across a knot of the C^1 interpolant
+    # moves the quotient by well under 1e-5 of the gradient)
+    th32 = t.detach().double()
+    fd = np.zeros_like(th)
+    steps = [1e-7, 1e-7, 1e-7, 1e-7, 1e-7, None, 1e-10]
+    for c in range(7):
+        hc = steps[c] if steps[c] is not None else 1e-7 * th32[5]
+        tp, tm = th32.clone(), th32.clone()
+        tp[c] += hc
+        tm[c] -= hc
+        fd[c] = ((h64.lnL(tp) - h64.lnL(tm)) / (2 * hc)).cpu().numpy()
+    g64 = h64.backward(th32).cpu().numpy()
+    thn = th32.cpu().numpy()
+    u64, ufd = _consistent(g64, thn, d["f_s"]), _consistent(fd, thn, d["f_s"])
+    relfd = np.abs(u64 - ufd) / np.abs(u64).max(axis=0)
+    _say(f"[autograd] FP64 adjoint vs central differences: max {relfd.max():.2e}")
+    assert relfd.max() <= 1e-5
+    ua = _consistent(ga / wts.cpu().numpy()[None, :], thn, d["f_s"])
+    rel = np.abs(ua - ufd) / np.abs(ufd).max(axis=0)
+    _say(f"[autograd] FP32 autograd vs central differences per component {np.array2string(rel.max(axis=1), precision=2)}")
+    assert rel.max() <= GRAD_REL + 1e-5
 
 
 def _oracle_marginalize(orc, pts, seed, counts, rounds, mask, eps, tau_width=0.0, trace=None, frames=None):
