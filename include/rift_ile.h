@@ -335,6 +335,20 @@ rift_status rift_ile_lnL(rift_ile *h, int n_items, const rift_ile_item *items, i
 rift_status rift_ile_reduce(rift_ile *h, int64_t n, const void *lnL_t, const void *ln_ratio,
                             rift_ile_result *out);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the reduction of
+ * rift_ile_reduce, same arguments and identical results, that allocates
+ * nothing.  Its partial sums, segment bounds and result live in a
+ * file-scope device array of the library (about 50 KB, one copy per device,
+ * held until the process ends), whose address rift_ile_create takes once per
+ * device.  Every call on a device shares that array and leaves it as the last
+ * call wrote it; calls that overlap on one device (other threads, other
+ * handles on other streams) race and must be serialized by the caller.  Any
+ * n in 0..2^40 (RIFT_E_SHAPE above that); nothing in the array needs to start
+ * at zero.  Synchronizes the handle's stream and writes *out on the host. */
+rift_status rift_ile_reduce_noalloc(rift_ile *h, int64_t n, const void *lnL_t, const void *ln_ratio,
+                                    rift_ile_result *out);
+
 /* Adapt the point's proposal (Sec. III.B): FP64 weighted 100-bin histograms of
  * w = exp(ln w - max ln w) over each masked parameter's prior-CDF coordinate,
  * mixed with a uniform floor:  h_b = (1 - eps) 100 m_b / sum m + eps.

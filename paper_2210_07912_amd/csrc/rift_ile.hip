@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -67,6 +68,8 @@ struct rift_ile {
   double ws_budget = 6.0e9;
   // FP64 refinement of the matrix-core adjoint (rift_ile_set_grad_refine)
   bool refine = true;
+  // this device's copy of the no-allocation scratch (rift_ile_reduce_noalloc)
+  void *scratch = nullptr;
   // optional timing of the dominant evaluation kernel
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
@@ -81,6 +84,29 @@ enum WsId {
   W_ITEM_HOFF, W_ITEM_COP, W_SEG_OFF, W_SEG_CNT, W_ASC, W_AHIST, W_UNIT, W_BINUNIT, W_ITEMUNITS, W_GOP, W_HOP, W_SEG_BLK, W_UBUF, W_EMPART, W_EMPART2, W_GMMFIT, W_EMWT, W_JRNG, W_COUNT_IDS
 };
 static_assert(W_COUNT_IDS <= 48, "workspace table too small");
+
+// Scratch of rift_ile_reduce_noalloc, for callers that cannot allocate:
+// the partial FP64 tuples of the reduction, the segment's offset and count,
+// the merged tuple and the result.  A file-scope device array: every device
+// the library runs on holds one copy until the process ends.  Host code never
+// uses the array's name as an address: rift_ile_create takes this device's
+// address once with hipGetSymbolAddress and the entry point passes that.
+constexpr int kNoAllocPartials = 1024;                 // partial tuples (blocks of the reduction)
+constexpr int64_t kNoAllocMaxN = (int64_t)1 << 40;     // samples per call
+struct NoAllocScratch {
+  ReduceTuple partials[kNoAllocPartials];
+  ReduceTuple merged;
+  int64_t seg[2];  // offset, count
+  rift_ile_result result;
+};
+__device__ __align__(256) unsigned char scratch[sizeof(NoAllocScratch)];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// blocks of the reduction for a segment of at most mx samples (both reduce
+// entry points use this, so their results are identical)
+int reduce_bps(int64_t mx) { return (int)std::min<int64_t>(kNoAllocPartials, (std::max<int64_t>(mx, 1) + 2047) / 2048); }
 
 rift_status fail(rift_ile *h, rift_status s, const char *fmt, ...) {
   char buf[512];
@@ -756,7 +782,7 @@ rift_status reduce_segments(rift_ile *h, const R *lnL, const R *ln_ratio, const 
   int64_t mx = 1;
   for (auto c : cnt) mx = std::max(mx, c);
   // enough blocks per segment to spread a large segment over the device
-  int bps = (int)std::min<int64_t>(1024, (mx + 2047) / 2048);
+  const int bps = reduce_bps(mx);
   int64_t *d_off, *d_cnt;
   rift_status s;
   if ((s = upload(h, W_ITEM_OFF, off, &d_off)) != RIFT_OK) return s;
@@ -1052,6 +1078,18 @@ rift_status rift_ile_create(rift_ile **out, const rift_ile_desc *desc, void *str
     return s;
   };
   if (hipGetDevice(&h->device) != hipSuccess) return bail(fail(h, RIFT_E_DEVICE, "no HIP device"));
+  {
+    // this device's address of the no-allocation scratch, taken once per device
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (h->device < 0 || h->device >= kMaxDevices) return bail(fail(h, RIFT_E_DEVICE, "device %d", h->device));
+    if (!g_scratch_dev[h->device]) {
+      void *ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr) return bail(hip_fail(h, e != hipSuccess ? e : hipErrorUnknown, "hipGetSymbolAddress"));
+      g_scratch_dev[h->device] = ptr;
+    }
+    h->scratch = g_scratch_dev[h->device];
+  }
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && v > 0) h->n_cu = v;
   else h->n_cu = 256;
@@ -1271,6 +1309,30 @@ rift_status rift_ile_reduce(rift_ile *h, int64_t n, const void *lnL_t, const voi
                                 (rift_ile_result *)d_res);
   if (s != RIFT_OK) return s;
   HIPCHK(h, hipMemcpyAsync(out, d_res, sizeof(rift_ile_result), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return RIFT_OK;
+}
+
+rift_status rift_ile_reduce_noalloc(rift_ile *h, int64_t n, const void *lnL_t, const void *ln_ratio,
+                                   rift_ile_result *out) {
+  if (!h) return RIFT_E_INVALID;
+  if (n < 0 || (n > 0 && !lnL_t) || !out) return fail(h, RIFT_E_INVALID, "bad reduce arguments");
+  if (n > kNoAllocMaxN)
+    return fail(h, RIFT_E_SHAPE, "rift_ile_reduce_noalloc: n = %lld exceeds %lld samples", (long long)n,
+                (long long)kNoAllocMaxN);
+  if (!h->scratch) return fail(h, RIFT_E_STATE, "no scratch address for device %d", h->device);
+  NoAllocScratch *sc = (NoAllocScratch *)h->scratch;  // this device's copy
+  const int bps = reduce_bps(n);
+  const int64_t seg[2] = {0, n};
+  HIPCHK(h, hipMemcpyAsync(sc->seg, seg, sizeof(seg), hipMemcpyHostToDevice, h->stream));
+  if (h->precision == RIFT_FP32)
+    HIPCHK(h, reduce_partials<float>((const float *)lnL_t, (const float *)ln_ratio, &sc->seg[0], &sc->seg[1], 1, bps,
+                                     sc->partials, h->stream));
+  else
+    HIPCHK(h, reduce_partials<double>((const double *)lnL_t, (const double *)ln_ratio, &sc->seg[0], &sc->seg[1], 1,
+                                      bps, sc->partials, h->stream));
+  HIPCHK(h, reduce_finish(sc->partials, 1, bps, &sc->merged, nullptr, 0, &sc->result, h->stream));
+  HIPCHK(h, hipMemcpyAsync(out, &sc->result, sizeof(rift_ile_result), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   return RIFT_OK;
 }

@@ -105,6 +105,7 @@ FUNCTIONS = {
                                   C.c_void_p, C.c_void_p, C.c_void_p]),
     "rift_ile_lnL": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(Item), C.c_int64, C.c_void_p, C.c_void_p]),
     "rift_ile_reduce": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(Result)]),
+    "rift_ile_reduce_noalloc": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(Result)]),
     "rift_ile_adapt": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_uint, C.c_double]),
     "rift_ile_get_proposal": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_uint)]),
     "rift_ile_set_proposal": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_uint]),
@@ -289,6 +290,15 @@ class RiftILE:
         lr = None if ln_ratio is None else torch.as_tensor(ln_ratio, device=self.device, dtype=self.dtype).contiguous()
         r = Result()
         self._check(lib().rift_ile_reduce(self.h, lnL.numel(), _ptr(lnL), _ptr(lr), C.byref(r)))
+        return r.as_dict()
+
+    def reduce_noalloc(self, lnL, ln_ratio=None):
+        """The reduction of ``reduce`` through the entry point that allocates
+        no device memory (its scratch is a static device array)."""
+        lnL = torch.as_tensor(lnL, device=self.device, dtype=self.dtype).contiguous()
+        lr = None if ln_ratio is None else torch.as_tensor(ln_ratio, device=self.device, dtype=self.dtype).contiguous()
+        r = Result()
+        self._check(lib().rift_ile_reduce_noalloc(self.h, lnL.numel(), _ptr(lnL), _ptr(lr), C.byref(r)))
         return r.as_dict()
 
     def adapt(self, point, bins, lnw, mask=0x3F, floor_eps=0.1):
