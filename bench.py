@@ -1,25 +1,30 @@
 """Benchmark of the ILE marginalized-likelihood step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched]
 
 A step is one pass of the whole hot path over one batch: on-device sampling
 of the extrinsic parameters, ln L_t for every sample (geometry, harmonics,
 coefficients, the time-shifted contraction, interpolation and the window
 log-sum-exp), ln w, and the FP64 reduction to ln L_marg with n_eff, n_ESS and
 n_var (one call of rift_ile_marginalize).  Inputs (Q, U) are resident in HBM
-before the timed region.  The steps are timed twice, with direct launches (the
-evaluation kernel timed with HIP events for the roofline) and with each
-evaluation run replayed from a captured hipGraph; for FP32 workloads other
-than the gradient the replayed rate is the headline value.  Prints one JSON
-line.
+before the timed region.  The default workload is the batched one (512
+heterogeneous intrinsic points, 1.98e8 evaluations per step).  The steps are
+timed twice, with direct launches (the evaluation kernels timed with HIP
+events for the roofline) and with each evaluation run replayed from a
+captured hipGraph; the replayed rate is the headline value.  Beside it the
+default run measures the single-point workload (the utilization target) and
+the gradient workload (timing and per-component error of the FP32 adjoint).
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
+import statistics
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -27,11 +32,13 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp32_mfma_tflops": 157.3, "fp64_tflops": 78.6, "hbm_gbs": 8000.0}
 
-# HBM bytes per launch of the evaluation kernel for the default workload, from
-# rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0) passes, the factors read
-# off a plain device copy (profiles/mfma_kernel_single_1e6.md).  It describes
-# the kernel as it was measured and is reported for that workload only.
-MEASURED_TRAFFIC = {"single": 377580268.0}
+# HBM bytes per step of the evaluation kernels, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes (KiB per dispatch, summed over a step's dispatches, scaled
+# by 2.0 and 1.0: what the same counters read for a plain device copy of known
+# size on the same box), keyed by workload, with the SHA-256 of the kernel
+# source they were taken with.  Reported only while that source is unchanged.
+MEASURED_TRAFFIC = {}
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2210_07912_amd", "csrc", "k_mfma.hip")
 
 
 def flops_per_eval(K, M, n_t):
@@ -64,20 +71,250 @@ def _cpu_model():
     return None
 
 
+def _sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _shape(p):
+    return p["det_pos"].shape[0], len(p["ell"]), p["n_t"]
+
+
+def _consistent(g, th, f_s):
+    """Gradient [7, N] in consistent units: d/d(angle), D d/dD, (1/f_s) d/dtau."""
+    u = g.copy()
+    u[5] = u[5] * th[5]
+    u[6] = u[6] / f_s
+    return u
+
+
+def measure_forward(name, steps, warmup, graph=True, n_override=0):
+    """Time the forward step of a workload (direct launches with the
+    evaluation kernels timed by events, then hipGraph replays)."""
+    import torch
+
+    import synth
+    from paper_2210_07912_amd import ile
+
+    w = synth.workload(name)
+    pts = [synth.make_point(s) for s in w.points]
+    counts = [n_override] * len(pts) if n_override else list(w.n_samples)
+    h = ile.RiftILE(pts, precision=w.precision, tau_width=w.tau_width)
+    seed = synth.BASE_SEED + synth.WORKLOADS.index(name)
+    rounds = w.rounds if w.adaptive else 1
+    mask = 0x3F if w.adaptive else 0
+
+    def step(i):
+        return h.marginalize(seed + i, counts, n_rounds=rounds, adapt_mask=mask, floor_eps=0.1)
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    h.profile(True)
+    t0 = time.perf_counter()
+    res = None
+    for i in range(steps):
+        res = step(100 + i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms, k_launches = h.profile(False)
+    evals = sum(counts) * rounds
+    dt = (t1 - t0) / steps
+    fp32 = w.precision == "fp32"
+    # roofline of the dominant kernels (the evaluation kernels of every (T, K)
+    # class, one persistent launch each, fanned out over side streams): the
+    # timed steps' algorithmic FLOP spread over the timed evaluation runs,
+    # over their average duration between the events around each run
+    fl = rounds * sum(c * flops_per_eval(*_shape(p)) for c, p in zip(counts, pts))
+    fl_per_launch = fl * steps / max(k_launches, 1)
+    k_avg_ms = k_ms / max(k_launches, 1)
+    achieved = fl_per_launch / (k_avg_ms * 1e-3) / 1e12 if k_launches else None
+    peak = PEAK["fp32_mfma_tflops"] if fp32 else PEAK["fp64_tflops"]
+    classes = sorted({((len(p["ell"]) + 1) // 2, p["det_pos"].shape[0]) for p in pts})
+    roof = {"bound": "mfma" if fp32 else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": (achieved / peak) if achieved else None, "traffic": None,
+            "kernel": ("mfma_kernel<T,K>" if fp32 else "plain_kernel<double>"),
+            "classes": [f"T{t}K{k}" for t, k in classes] if fp32 else None,
+            "kernel_ms": k_avg_ms, "launches_per_step": k_launches / steps,
+            "flops_per_eval": fl / max(evals, 1), "flops_per_launch": fl_per_launch}
+    if fp32:
+        # matrix-core FLOP the kernels execute per evaluation: 16-row blocks
+        # 0..ceil(n_t/16) of every detector times 2 M_p elements
+        ex = [2 * p["det_pos"].shape[0] * 16 * ((p["n_t"] + 15) // 16 + 1) * 2 * ((len(p["ell"]) + 1) // 2 * 2)
+              for p in pts]
+        roof["mfma_executed_per_eval"] = sum(c * e for c, e in zip(counts, ex)) / max(sum(counts), 1)
+    tr = MEASURED_TRAFFIC.get(name)
+    if tr and not n_override and tr["sha256"] == _sha(KERNEL_SOURCE) and k_launches:
+        roof["traffic"] = tr["bytes_per_step"] * steps / k_launches
+        roof["hbm_gbs"] = roof["traffic"] / (k_avg_ms * 1e-3) / 1e9
+        roof["hbm_frac"] = roof["hbm_gbs"] / PEAK["hbm_gbs"]
+    out = {"value": evals / dt, "ms_per_step": dt * 1e3, "evals_per_step": evals, "points": len(pts),
+           "rounds": rounds, "roofline": roof, "seed": seed,
+           "lnL_marg": [r["lnL_marg"] for r in res][:4], "n_eff": [r["n_eff"] for r in res][:4],
+           "launch": "direct"}
+    if fp32:
+        out["autotune"] = {f"T{t}K{k}": m for (t, k), m in sorted(h.autotune_table().items())}
+    if graph and fp32:
+        h.set_graph(True)
+        for i in range(max(warmup, 1)):
+            step(i)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for i in range(steps):
+            step(100 + i)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        cap, rep = h.graph_stats()
+        h.set_graph(False)
+        gdt = (t3 - t2) / steps
+        out["direct"] = {"value": evals / dt, "ms_per_step": dt * 1e3}
+        out["value"] = evals / gdt
+        out["ms_per_step"] = gdt * 1e3
+        out["graph"] = {"captures": cap, "replays": rep}
+        out["launch"] = "hipGraph replay of each evaluation run"
+    return out, h, pts, counts, seed
+
+
+def measure_grad(steps, warmup, with_errors=True):
+    """The gradient workload: a step draws 1e5 samples on the device and
+    computes ln L_t and its gradient in the seven parameters (one adjoint
+    call, with the FP64 refinement of the samples whose mass lies in a few
+    window blocks), then the FP64 reduction.  The errors: every sample's FP32
+    gradient against the FP64 adjoint on the same FP32-rounded inputs, per
+    component, in consistent units (angles, ln D, tau in window samples)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2210_07912_amd import ile
+
+    w = synth.workload("grad")
+    d = synth.make_point(w.points[0])
+    n = w.n_samples[0]
+    h = ile.RiftILE([d], precision="fp32", tau_width=w.tau_width)
+    seed = synth.BASE_SEED + synth.WORKLOADS.index("grad")
+
+    def step(i):
+        th, _, _ = h.sample(0, seed + i, 0, n)
+        g, lt = h.backward(th, want_lnL=True)
+        return [h.reduce(lt)]
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    h.profile(True)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(100 + i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms, k_launches = h.profile(False)
+    dt = (t1 - t0) / steps
+    K, M, n_t = _shape(d)
+    fl = n * flops_per_grad(K, M, n_t)
+    k_avg = k_ms / max(k_launches, 1)
+    achieved = fl * steps / max(k_launches, 1) / (k_avg * 1e-3) / 1e12 if k_launches else None
+    out = {"value": n / dt, "unit": "gradient evals/s", "ms_per_step": dt * 1e3, "samples": n,
+           "roofline": {"bound": "mfma", "kernel": "mfma_bwd_kernel<11,3>", "achieved": achieved,
+                        "peak": PEAK["fp32_mfma_tflops"], "unit": "TFLOP/s",
+                        "frac": achieved / PEAK["fp32_mfma_tflops"] if achieved else None, "kernel_ms": k_avg,
+                        "flops_per_eval": flops_per_grad(K, M, n_t)}}
+    if with_errors:
+        th, _, _ = h.sample(0, seed + 999, 0, n)
+        g32, l32 = h.backward(th, want_lnL=True)
+        h.set_grad_refine(False)
+        g0, _ = h.backward(th, want_lnL=True)
+        h.set_grad_refine(True)
+        dr = dict(d)
+        for key in ("Q", "U"):
+            dr[key] = np.asarray(d[key]).astype(np.complex64).astype(np.complex128)
+        h64 = ile.RiftILE([dr], precision="fp64", tau_width=w.tau_width)
+        g64, l64 = h64.backward(th.double(), want_lnL=True)
+        thn = th.cpu().numpy().astype(np.float64)
+        f_s = d["f_s"]
+        ur = _consistent(g64.cpu().numpy(), thn, f_s)
+        scale = np.abs(ur).max(axis=0)
+        names = ["alpha", "delta", "psi", "iota", "phi", "lnD", "tau"]
+
+        def errs(gx):
+            ux = _consistent(gx.cpu().numpy().astype(np.float64), thn, f_s)
+            return np.abs(ux - ur) / scale
+
+        e32, e0 = errs(g32), errs(g0)
+        l64n = l64.cpu().numpy()
+        top = l64n >= l64n.max() - 20.0
+        own = np.abs(_consistent(g32.cpu().numpy().astype(np.float64), thn, f_s) - ur) / np.maximum(np.abs(ur), 1e-300)
+        big = np.abs(ur) >= 1e-3 * scale
+        out["error"] = {
+            "reference": "FP64 adjoint on the same FP32-rounded inputs, all samples",
+            "measure": "max over samples of |g32_c - g64_c| / max_c' |g64_c'|, consistent units "
+                       "(angles rad, ln D, tau in window samples)",
+            "per_component": {k: float(e32[i].max()) for i, k in enumerate(names)},
+            "per_component_p99_9": {k: float(np.percentile(e32[i], 99.9)) for i, k in enumerate(names)},
+            "per_component_fp32_only": {k: float(e0[i].max()) for i, k in enumerate(names)},
+            "refined_fraction": float(np.mean(np.any(g32.cpu().numpy() != g0.cpu().numpy(), axis=0))),
+            "weight_carrying_samples": int(top.sum()),
+            "weight_carrying_max_own_relative": float(np.where(big & top[None, :], own, 0.0).max()),
+        }
+        h64.close()
+    h.close()
+    return out
+
+
+def cpu_baseline(pts, counts, precision, seconds, runs, tau_width=0.0):
+    """The oracle (FP64 CPU reference) built for this host (-O3 -march=native,
+    OpenMP over samples) on a bounded sample of the workload: up to 32 of its
+    points (evenly spaced), a fixed number of prior samples each, timing
+    ln L_t of every sample plus the FP64 reduction per point; the median of
+    `runs` runs."""
+    import numpy as np
+
+    import synth
+    from oracle import oracle
+
+    tmp = tempfile.mkdtemp(prefix="rift_oracle_")
+    oracle.use_native_build(tmp)
+    step = max(1, len(pts) // 32)
+    sel = list(range(0, len(pts), step))[:32]
+    ops = [oracle.Point.from_dict(pts[i], complex64=(precision == "fp32")) for i in sel]
+
+    def run(S):
+        ths = [synth.prior_samples(synth.BASE_SEED + 77 + j, min(S, counts[i]), tau_width)
+               .astype(np.float32).astype(np.float64) for j, i in enumerate(sel)]
+        t_a = time.perf_counter()
+        for op, th in zip(ops, ths):
+            oracle.reduce(oracle.lnL_t(op, th))
+        t_b = time.perf_counter()
+        return sum(th.shape[1] for th in ths), t_b - t_a
+
+    n_probe, t_probe = run(64)
+    S = int(max(64, min(min(counts[i] for i in sel), 64 * (seconds / runs) / max(t_probe, 1e-6))))
+    rates, n_run = [], 0
+    for _ in range(runs):
+        n_run, t = run(S)
+        rates.append(n_run / t)
+    return {"value": statistics.median(rates), "unit": "evals/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{len(sel)} of {len(pts)} points (indices 0, {step}, {2 * step}, ...), {S} prior samples each "
+                      f"({n_run} evaluations per run): ln L_t of every sample plus the FP64 reduction per point; "
+                      f"median of {runs} runs; oracle built -O3 -march=native with OpenMP",
+            "runs": rates, "cpu_model": _cpu_model()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="single",
-                    help="plain | single | batched | grad | adaptive (default: single, 1e6 samples)")
-    ap.add_argument("--n", type=int, default=0, help="samples per step (default: the workload's)")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="batched",
+                    help="batched (default: 512 points, 1.98e8 samples) | single | plain | grad | adaptive")
+    ap.add_argument("--n", type=int, default=0, help="samples per point per step (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle time over all baseline runs")
+    ap.add_argument("--cpu-runs", type=int, default=3)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the measurements beside the timed steps (precompute, network frame, refinement)")
+                    help="skip the measurements beside the timed steps (other workloads, FP64 replays, ...)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (points would shard across GPUs "
@@ -85,139 +322,79 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import synth
     from paper_2210_07912_amd import ile
 
-    w = synth.workload(args.workload)
-    pts = [synth.make_point(s) for s in w.points]
-    n = args.n or w.n_samples[0]
-    counts = [n] * len(pts) if args.n else list(w.n_samples)
-    h = ile.RiftILE(pts, precision=w.precision, tau_width=w.tau_width)
-    seed = synth.BASE_SEED + synth.WORKLOADS.index(args.workload)
-    rounds = w.rounds if w.adaptive else 1
-    mask = 0x3F if w.adaptive else 0
-    grad = args.workload == "grad"
-    if grad:
-        # a step: draw the samples on the device, then ln L_t and its gradient
-        # in the seven parameters (one adjoint launch)
-        def step(i):
-            th, _, _ = h.sample(0, seed + i, 0, counts[0])
-            g, lt = h.backward(th, want_lnL=True)
-            return [h.reduce(lt)]
-    else:
-        def step(i):
-            return h.marginalize(seed + i, counts, n_rounds=rounds, adapt_mask=mask, floor_eps=0.1)
+    name = args.workload
+    if name == "grad":
+        g = measure_grad(args.steps, args.warmup, with_errors=not args.no_extras)
+        w = synth.workload("grad")
+        pts = [synth.make_point(s) for s in w.points]
+        out = {"metric": "extrinsic lnL evals/sec (time-marginalized) at |dln L_marg|<=1e-3 vs FP64",
+               "value": g["value"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+               "ms_per_step": g["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "f32", "data": "synthetic",
+               "config": {"workload": "grad", "points": 1, "samples_per_step": g["samples"],
+                          "note": "ln L_t and its gradient in 7 parameters per evaluation"},
+               "roofline": g["roofline"], "grad": g}
+        if not args.no_extras:
+            h = ile.RiftILE(pts, precision="fp32", tau_width=w.tau_width)
+            counts = list(w.n_samples)
+            seed = synth.BASE_SEED + synth.WORKLOADS.index("grad")
+            ref = {}
+            for nm, gflag in (("histogram", False), ("gradient_refined", True)):
+                h.marginalize(seed, counts[0], n_rounds=2, adapt_mask=0x3F, floor_eps=0.1, gradient=gflag)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                r = h.marginalize(seed + 7, counts[0], n_rounds=w.rounds, adapt_mask=0x3F, floor_eps=0.1,
+                                  gradient=gflag, n_ascent=64, ascent_steps=12, ascent_mix=0.3)
+                torch.cuda.synchronize()
+                t3 = time.perf_counter()
+                ref[nm] = {"evals_per_s": counts[0] * w.rounds / (t3 - t2), "s": t3 - t2,
+                           "lnL_marg": r[0]["lnL_marg"], "sigma_lnL": r[0]["sigma_lnL"], "n_eff": r[0]["n_eff"]}
+            out["refinement"] = {"rounds": w.rounds, "samples_per_round": counts[0],
+                                 "adapt": "alpha, delta, psi, iota, phi, D histograms", **ref}
+            h.close()
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(pts, list(w.n_samples), "fp32", args.cpu_seconds, args.cpu_runs,
+                                               w.tau_width)
+        print(json.dumps(out), flush=True)
+        return
 
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    h.profile(True)
-    t0 = time.perf_counter()
-    res = None
-    for i in range(args.steps):
-        res = step(100 + i)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    k_ms, k_launches = h.profile(False)
-    evals_per_step = sum(counts) * rounds
-    dt = (t1 - t0) / args.steps
-    value = evals_per_step / dt
-
-    # roofline of the dominant kernel (the evaluation kernel): algorithmic
-    # FLOP of the timed steps spread over its launches (a step makes one
-    # launch per round and class of points), over its average duration
-    per = flops_per_grad if grad else flops_per_eval
-    fl = rounds * sum(c * per(p["det_pos"].shape[0], len(p["ell"]), p["n_t"]) for c, p in zip(counts, pts))
-    fl_per_launch = fl * args.steps / max(k_launches, 1)
-    k_avg_ms = k_ms / max(k_launches, 1)
-    achieved = fl_per_launch / (k_avg_ms * 1e-3) / 1e12 if k_launches else None
-    dtype = "f32" if w.precision == "fp32" else "f64"
-    mfma = w.precision == "fp32"
-    # the plain kernel (FP64 handles) is FP64 vector-ALU bound (78.6)
-    peak = PEAK["fp32_mfma_tflops"] if mfma else PEAK["fp64_tflops"]
-    roof = {"bound": "mfma" if mfma else "alu", "achieved": achieved, "peak": peak,
-            "unit": "TFLOP/s", "frac": (achieved / peak) if achieved else None,
-            "traffic": MEASURED_TRAFFIC.get(args.workload) if not args.n else None,
-            "kernel": ("mfma_bwd_kernel" if grad else "mfma_kernel") if mfma else "plain_kernel",
-            "kernel_ms": k_avg_ms, "launches_per_step": k_launches / args.steps,
-            "flops_per_eval": fl / max(rounds * sum(counts), 1)}
-    if mfma:
-        # matrix-core FLOP the forward kernel executes per evaluation: 16-row
-        # blocks 0..ceil(n_t/16) of every detector times 2 M_p elements
-        # (excluding the padding slots of partly filled tiles)
-        ex = [2 * p["det_pos"].shape[0] * 16 * ((p["n_t"] + 15) // 16 + 1) * 2 * ((len(p["ell"]) + 1) // 2 * 2)
-              for p in pts]
-        # (the adjoint: z and the transposed product G_k, one sweep)
-        roof["mfma_executed_per_eval"] = sum(c * e for c, e in zip(counts, ex)) / max(sum(counts), 1) * (2 if grad else 1)
-    if roof["traffic"] and k_avg_ms:
-        roof["hbm_gbs"] = roof["traffic"] / (k_avg_ms * 1e-3) / 1e9
-        roof["hbm_frac"] = roof["hbm_gbs"] / PEAK["hbm_gbs"]
-
+    m, h, pts, counts, seed = measure_forward(name, args.steps, args.warmup, graph=not args.no_graph,
+                                              n_override=args.n)
+    w = synth.workload(name)
+    fp32 = w.precision == "fp32"
     out = {
         "metric": "extrinsic lnL evals/sec (time-marginalized) at |dln L_marg|<=1e-3 vs FP64",
-        "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": dtype, "data": "synthetic",
-        "config": {"workload": args.workload, "points": len(pts),
-                   "samples_per_point": counts[0] if len(set(counts)) == 1 else "varied", "samples_per_step": evals_per_step,
-                   "rounds": rounds, "K": [p["det_pos"].shape[0] for p in pts][:1], "M": [len(p["ell"]) for p in pts][:1],
-                   "n_t": [p["n_t"] for p in pts][:1], "seed": seed},
-        "roofline": roof,
-        # matrix-core feed measured per (T, K) class by the handle (staged | direct)
-        "autotune": ({f"T{t}K{k}": m for (t, k), m in sorted(h.autotune_table().items())}
-                     if mfma and not grad else None),
-        "lnL_marg": [r["lnL_marg"] for r in res][:4], "n_eff": [r["n_eff"] for r in res][:4],
+        "value": m["value"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if fp32 else "f64", "data": "synthetic",
+        "config": {"workload": name, "points": len(pts),
+                   "samples_per_point": counts[0] if len(set(counts)) == 1 else "varied",
+                   "samples_per_step": m["evals_per_step"], "rounds": m["rounds"],
+                   "K": sorted({p["det_pos"].shape[0] for p in pts}), "M": sorted({len(p["ell"]) for p in pts}),
+                   "n_t": [min(p["n_t"] for p in pts), max(p["n_t"] for p in pts)], "seed": seed,
+                   "launch": m["launch"]},
+        "roofline": m["roofline"],
     }
+    for k in ("direct", "graph", "autotune", "lnL_marg", "n_eff"):
+        if k in m:
+            out[k] = m[k]
 
-    # the same steps with the evaluation runs replayed from captured hipGraphs
-    # (FP32 handles; host-timed, the kernel timing hook stays off)
-    if not args.no_graph and w.precision == "fp32" and not grad:
-        h.set_graph(True)
-        for i in range(max(args.warmup, 1)):
-            step(i)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        for i in range(args.steps):
-            step(100 + i)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        cap, rep = h.graph_stats()
-        h.set_graph(False)
-        gdt = (t3 - t2) / args.steps
-        # the headline is the replayed form (same work per step: sampling,
-        # evaluation and reduction); the direct launches stay beside it
-        out["direct"] = {"value": value, "ms_per_step": dt * 1e3}
-        out["value"] = evals_per_step / gdt
-        out["ms_per_step"] = gdt * 1e3
-        out["graph"] = {"captures": cap, "replays": rep}
-        out["config"]["launch"] = "hipGraph replay of each evaluation run"
-    else:
-        out["config"]["launch"] = "direct"
-
-    # the gradient configuration's second part: 20 rounds of 1e5 samples of
-    # adaptive importance sampling, histogram proposal alone and refined by the
-    # gradient (the top samples climb ln L_t along the adjoint between rounds)
-    if grad and not args.n and not args.no_extras:
-        ref = {}
-        for name, gflag in (("histogram", False), ("gradient_refined", True)):
-            h.marginalize(seed, counts[0], n_rounds=2, adapt_mask=0x3F, floor_eps=0.1, gradient=gflag)  # warm-up
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            r = h.marginalize(seed + 7, counts[0], n_rounds=w.rounds, adapt_mask=0x3F, floor_eps=0.1, gradient=gflag,
-                              n_ascent=64, ascent_steps=12, ascent_mix=0.3)
-            torch.cuda.synchronize()
-            t3 = time.perf_counter()
-            ref[name] = {"evals_per_s": counts[0] * w.rounds / (t3 - t2), "s": t3 - t2,
-                         "lnL_marg": r[0]["lnL_marg"], "sigma_lnL": r[0]["sigma_lnL"], "n_eff": r[0]["n_eff"]}
-        out["refinement"] = {"rounds": w.rounds, "samples_per_round": counts[0], "adapt": "alpha, delta, psi, iota, "
-                             "phi, D histograms", **ref}
+    # the utilization target's workload (1 point, K = 3, M = 21, n_t = 820, 1e6
+    # samples) and the gradient workload, beside the headline
+    if name == "batched" and not args.no_extras:
+        s, hs, _, _, _ = measure_forward("single", 20, 3, graph=not args.no_graph)
+        hs.close()
+        out["single_point"] = {k: s[k] for k in ("value", "ms_per_step", "roofline", "launch", "lnL_marg")}
+        out["grad"] = measure_grad(10, 2, with_errors=not args.no_fp64)
 
     # the Q/U/V precompute at the single-point shape: 3 detectors, 21 modes,
     # 8 s at 4096 Hz (N = 32768), the 999 stored rows; host arrays in and out
-    if args.workload == "single" and not args.n and not args.no_extras:
+    if name == "single" and not args.n and not args.no_extras:
         N, df = 32768, 0.125
         data, psd, modes, _ = synth.fd_inputs(synth.BASE_SEED + 50, n_det=3, n_modes=21, N=N, df=df, f_low=20.0)
         L = pts[0]["n_t"] + 2 * pts[0]["pad"] + 3
@@ -231,25 +408,23 @@ def main():
                              "note": "host arrays in and out, device buffers allocated per call"}
 
     # adaptive sampling with the sky in each point's detector-network frame
-    # against the equatorial frame: n_eff and sigma of ln L_marg on the first
-    # points of the workload (10 rounds of 1e5 samples)
+    # against the equatorial frame, and the Gaussian-mixture proposal against
+    # the histograms: n_eff on the first points (10 rounds of 1e5 samples)
     if w.adaptive and not args.n and not args.no_extras:
         sub = pts[:8]
         hs = ile.RiftILE(sub, precision=w.precision, tau_width=w.tau_width)
         nf = {}
-        for name, net in (("equatorial", False), ("network_frame", True)):
+        for nm, net in (("equatorial", False), ("network_frame", True)):
             hs.set_network_frame(net)
             r = hs.marginalize(seed + 11, 100_000, n_rounds=10, adapt_mask=0x3F, floor_eps=0.1)
-            nf[name] = {"n_eff": [x["n_eff"] for x in r], "sigma_lnL": [x["sigma_lnL"] for x in r],
-                        "lnL_marg": [x["lnL_marg"] for x in r]}
+            nf[nm] = {"n_eff": [x["n_eff"] for x in r], "sigma_lnL": [x["sigma_lnL"] for x in r],
+                      "lnL_marg": [x["lnL_marg"] for x in r]}
         out["network_frame"] = {"points": len(sub), "rounds": 10, "samples_per_round": 100_000, **nf}
-        # the Gaussian-mixture proposal (3 components per parameter, 10 EM
-        # iterations per round) against the histograms, equatorial frame
         hs.set_network_frame(False)
         gm = {}
         # correlated pairs (psi, phi) and (iota, D): the pairs the polarization-phase and
         # inclination-distance degeneracies tie together
-        for name, kk, pr in (("histogram", 0, ()), ("gmm_k3", 3, ()), ("gmm_k3_pairs", 3, ((2, 4), (3, 5)))):
+        for nm, kk, pr in (("histogram", 0, ()), ("gmm_k3", 3, ()), ("gmm_k3_pairs", 3, ((2, 4), (3, 5)))):
             hs.marginalize(seed + 12, 100_000, n_rounds=2, adapt_mask=0x3F, floor_eps=0.1, gmm_components=kk,
                            gmm_pairs=pr)
             torch.cuda.synchronize()
@@ -258,13 +433,13 @@ def main():
                                gmm_pairs=pr)
             torch.cuda.synchronize()
             t3 = time.perf_counter()
-            gm[name] = {"ms": (t3 - t2) * 1e3, "n_eff": [x["n_eff"] for x in r], "discarded": [x["n_nonfinite"] for x in r],
-                        "sigma_lnL": [x["sigma_lnL"] for x in r], "lnL_marg": [x["lnL_marg"] for x in r]}
+            gm[nm] = {"ms": (t3 - t2) * 1e3, "n_eff": [x["n_eff"] for x in r], "discarded": [x["n_nonfinite"] for x in r],
+                      "sigma_lnL": [x["sigma_lnL"] for x in r], "lnL_marg": [x["lnL_marg"] for x in r]}
         hs.close()
         out["gmm"] = {"points": len(sub), "rounds": 10, "samples_per_round": 100_000, "floor_eps": 0.1, **gm}
 
     # FP32 vs FP64 on the same samples (same GPU): |d ln L_marg| and the FP64 rate
-    if not args.no_fp64 and w.precision == "fp32" and len(pts) == 1 and not grad:
+    if not args.no_fp64 and fp32 and len(pts) == 1:
         nn = min(counts[0], 200_000)
         h64 = ile.RiftILE(pts, precision="fp64", tau_width=w.tau_width)
         th64, _, _ = h64.sample(0, seed, 0, nn)
@@ -272,12 +447,10 @@ def main():
         l32 = h.lnL(th32)
         l64a = h64.lnL(th32.double())
         torch.cuda.synchronize()
-        h64.profile(True)
         t2 = time.perf_counter()
         l64 = h64.lnL(th32.double())
         torch.cuda.synchronize()
         t3 = time.perf_counter()
-        h64.profile(False)
         r32, r64 = h.reduce(l32), h64.reduce(l64)
         out["fp64_plain"] = {"evals_per_s": nn / (t3 - t2), "samples": nn,
                              "lnL_marg_fp32": r32["lnL_marg"], "lnL_marg_fp64": r64["lnL_marg"],
@@ -286,57 +459,48 @@ def main():
         h64.close()
 
     # the estimate against the FP64 plain form on the very same samples (their
-    # samples and proposal ratios replayed): 4 points of the adaptive workload
-    # over all rounds, 32 points of the batched workload
-    if not args.no_fp64 and (w.adaptive or args.workload == "batched") and not args.n and not args.no_extras:
-        sub = pts[:4] if w.adaptive else pts[:32]
+    # samples and proposal ratios replayed): for the adaptive workload the
+    # first 4 points and the 15 loudest (SNR >= 50) over all rounds, for the
+    # batched workload 32 of its points
+    if not args.no_fp64 and (w.adaptive or name == "batched") and not args.n:
+        if w.adaptive:
+            idx = list(range(4)) + [i for i, s in enumerate(w.points) if s.snr >= 50.0]
+        else:
+            idx = list(range(0, len(pts), max(1, len(pts) // 32)))[:32]
+        sub = [pts[i] for i in idx]
+        cs = [counts[i] for i in idx]
         hs = ile.RiftILE(sub, precision="fp32", tau_width=w.tau_width)
         h64 = ile.RiftILE(sub, precision="fp64", tau_width=w.tau_width)
         ns = len(sub)
-        per_round = sum(counts[:ns])
+        per_round = sum(cs)
+        rounds = m["rounds"]
+        mask = 0x3F if w.adaptive else 0
 
         def replay(kw):
-            res32, th, lw = hs.marginalize(seed + 13, counts[:ns], n_rounds=rounds, adapt_mask=mask, floor_eps=0.1,
+            res32, th, lw = hs.marginalize(seed + 13, cs, n_rounds=rounds, adapt_mask=mask, floor_eps=0.1,
                                            return_samples=True, **kw)
             deltas = []
-            for i in range(len(sub)):
-                cols = torch.cat([torch.arange(r * per_round + sum(counts[:i]), r * per_round + sum(counts[:i + 1]),
+            for i in range(ns):
+                cols = torch.cat([torch.arange(r * per_round + sum(cs[:i]), r * per_round + sum(cs[:i + 1]),
                                                device=th.device) for r in range(rounds)])
                 t_i = th[:, cols]
                 l32 = hs.lnL(t_i, [(i, 0, t_i.shape[1])])
                 l64 = h64.lnL(t_i.double(), [(i, 0, t_i.shape[1])])
                 r64 = h64.reduce(l64 + (lw[cols].double() - l32.double()))
                 deltas.append(abs(res32[i]["lnL_marg"] - r64["lnL_marg"]))
-            return {"points": ns, "samples": per_round * rounds, "max_abs_delta_lnL_marg": max(deltas),
-                    "abs_delta_lnL_marg": deltas, "n_eff": [r["n_eff"] for r in res32]}
+            return {"points": idx, "snr": [round(w.points[i].snr, 2) for i in idx], "samples": per_round * rounds,
+                    "max_abs_delta_lnL_marg": max(deltas), "abs_delta_lnL_marg": deltas,
+                    "n_eff": [r["n_eff"] for r in res32]}
 
         out["fp64_replay"] = replay({})
-        if w.adaptive:
+        if w.adaptive and not args.no_extras:
             # the same with the Gaussian-mixture proposal and the pairs (psi, phi), (iota, D)
             out["fp64_replay_gmm"] = replay(dict(gmm_components=3, gmm_pairs=((2, 4), (3, 5))))
         hs.close()
         h64.close()
 
     if not args.no_cpu_baseline:
-        from oracle import oracle
-        p = pts[0]
-        op = oracle.Point.from_dict(p, complex64=(w.precision == "fp32"))
-        th = synth.prior_samples(seed, 4096, w.tau_width)
-        fn = oracle.grad if grad else oracle.lnL_t
-        t_a = time.perf_counter()
-        fn(op, th[:, :256])
-        t_b = time.perf_counter()
-        rate = 256 / (t_b - t_a)
-        ns = int(min(4096, max(256, rate * args.cpu_seconds)))
-        if ns > 256:
-            t_a = time.perf_counter()
-            fn(op, th[:, :ns])
-            t_b = time.perf_counter()
-            rate = ns / (t_b - t_a)
-        out["cpu_baseline"] = {"value": rate, "unit": "evals/s", "cores": oracle.threads(), "kind": "oracle",
-                               "sample": f"{ns} prior samples of point 0 ({args.workload}), "
-                               + ("ln L_t and gradient" if grad else "ln L_t only") + ", FP64",
-                               "cpu_model": _cpu_model()}
+        out["cpu_baseline"] = cpu_baseline(pts, counts, w.precision, args.cpu_seconds, args.cpu_runs, w.tau_width)
     print(json.dumps(out), flush=True)
     h.close()
 

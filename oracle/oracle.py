@@ -54,18 +54,35 @@ _lib = None
 _dp = C.POINTER(C.c_double)
 
 
+def _load(path):
+    L = C.CDLL(path)
+    L.or_delay.restype = C.c_double
+    L.or_lnL_t.restype = C.c_double
+    L.or_u01.restype = C.c_double
+    L.or_rows.restype = C.c_int
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = C.CDLL(LIB_PATH)
-        L.or_delay.restype = C.c_double
-        L.or_lnL_t.restype = C.c_double
-        L.or_u01.restype = C.c_double
-        L.or_rows.restype = C.c_int
-        _lib = L
+        _lib = _load(LIB_PATH)
     return _lib
+
+
+def use_native_build(out_dir):
+    """Compile the oracle for the host it runs on (-O3 -march=native, OpenMP)
+    into out_dir and make this module use that build.  For timing the oracle
+    as a CPU baseline; the portable build stays the one the tests load."""
+    global _lib
+    src = os.path.join(HERE, "rift_oracle.c")
+    path = os.path.join(out_dir, "liboracle_native.so")
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared", "-std=c11", src, "-o", path,
+                           "-lm"])
+    _lib = _load(path)
+    return path
 
 
 def threads():
