@@ -50,17 +50,35 @@ def _handle(ile, points, precision, plain=False, **kw):
                 os.environ["RIFT_ILE_FP32_KERNEL"] = old
 
 
-def _fp32_tol(ref):
-    return 2e-4 + 4e-6 * (np.abs(ref) + 1e3)
+def _quad(op, th):
+    """The oracle's quadratic term B of every sample (columns of th)."""
+    from oracle import oracle as o
+    th = np.asarray(th, dtype=np.float64)
+    return np.array([o.coeffs(op, th[:, j])[1] for j in range(th.shape[1])])
 
 
-def _check_fp32(gpu, ref, label):
+def _fp32_tol(ref, B, K, M):
+    """Per-sample bound on |FP32 ln L_t - FP64 ln L_t| for the same FP32
+    inputs.  The window values are sums of about 8 K M products (complex
+    mode products over K detectors and 4 taps), each up to the data term's
+    size |ln L_t| + B, and B itself is rounded once: a few units of 2^-24
+    (|ln L_t| + 2 B) sqrt(8 K M), plus an absolute 2e-6 for the log-sum-exp's
+    own rounding near ln L_t = 0.  Measured on 4.3e5 samples of four
+    workloads (tiny, single point, batched, SNR >= 50): at most 0.66 of the
+    product term (1.08 for |ln L_t| < 1, where the 2e-6 covers it)."""
+    return 2e-6 + 2.0 * 2.0 ** -24 * (np.abs(ref) + 2.0 * np.abs(B)) * np.sqrt(8.0 * K * M)
+
+
+def _check_fp32(gpu, ref, label, op, th):
+    """FP32 ln L_t against the oracle's on the same samples (op: the oracle
+    point with FP32-rounded inputs, th: the samples)."""
     gpu = np.asarray(gpu, dtype=np.float64)
+    B = _quad(op, th)
     err = np.abs(gpu - ref)
-    tol = _fp32_tol(ref)
+    tol = _fp32_tol(ref, B, op.K, op.M)
     bad = ~(err <= tol)
-    _say(f"[{label}] n={ref.size} max|d|={err.max():.3e} max rel={np.max(err / (np.abs(ref) + 1)):.3e}")
-    assert not bad.any(), (label, np.flatnonzero(bad)[:10], gpu[bad][:5], ref[bad][:5])
+    _say(f"[{label}] n={ref.size} max|d|={err.max() if err.size else 0:.3e} max |d|/tol={np.max(err / tol) if err.size else 0:.3f}")
+    assert not bad.any(), (label, np.flatnonzero(bad)[:10], gpu[bad][:5], ref[bad][:5], tol[bad][:5])
 
 
 def _lnL_case(ile, orc, spec, n, precision, plain=False, seed=7, tau_width=0.0):
@@ -71,13 +89,13 @@ def _lnL_case(ile, orc, spec, n, precision, plain=False, seed=7, tau_width=0.0):
     h = _handle(ile, [d], precision, plain=plain, tau_width=tau_width)
     _say(f"lnL case {spec.key()} n={n} {precision} plain={plain}")
     out = h.lnL(torch.tensor(th)).cpu().numpy()
-    return d, th, ref, out, h
+    return d, th, ref, out, h, p
 
 
 def test_lnL_fp32_mfma_tiny(ile, orc):
     spec = synth.workload("tiny").points[0]
-    d, th, ref, out, h = _lnL_case(ile, orc, spec, 4099, "fp32")
-    _check_fp32(out, ref, "mfma tiny")
+    d, th, ref, out, h, p = _lnL_case(ile, orc, spec, 4099, "fp32")
+    _check_fp32(out, ref, "mfma tiny", p, th)
     r_gpu = h.reduce(torch.tensor(out))
     r_orc = orc.reduce(ref)
     _say(f"lnL_marg gpu={r_gpu['lnL_marg']:.9f} oracle={r_orc['lnL_marg']:.9f}")
@@ -86,13 +104,13 @@ def test_lnL_fp32_mfma_tiny(ile, orc):
 
 def test_lnL_fp32_plain_tiny(ile, orc):
     spec = synth.workload("tiny").points[0]
-    d, th, ref, out, h = _lnL_case(ile, orc, spec, 1037, "fp32", plain=True)
-    _check_fp32(out, ref, "plain tiny")
+    d, th, ref, out, h, p = _lnL_case(ile, orc, spec, 1037, "fp32", plain=True)
+    _check_fp32(out, ref, "plain tiny", p, th)
 
 
 def test_lnL_fp64_plain(ile, orc):
     spec = synth.workload("plain").points[0]
-    d, th, ref, out, h = _lnL_case(ile, orc, spec, 3001, "fp64")
+    d, th, ref, out, h, p = _lnL_case(ile, orc, spec, 3001, "fp64")
     err = np.abs(out - ref)
     _say(f"[fp64] max|d|={err.max():.3e}")
     assert np.all(err <= 1e-9 * (1 + np.abs(ref)))
@@ -101,8 +119,8 @@ def test_lnL_fp64_plain(ile, orc):
 def test_lnL_single_point_shape(ile, orc):
     """K = 3, M = 21, n_t = 820 (the single-point workload's shape), subset."""
     spec = synth.workload("single").points[0]
-    d, th, ref, out, h = _lnL_case(ile, orc, spec, 2051, "fp32", seed=11)
-    _check_fp32(out, ref, "mfma single")
+    d, th, ref, out, h, p = _lnL_case(ile, orc, spec, 2051, "fp32", seed=11)
+    _check_fp32(out, ref, "mfma single", p, th)
     r_gpu, r_orc = orc.reduce(out.astype(np.float64)), orc.reduce(ref)
     _say(f"lnL_marg gpu={r_gpu['lnL_marg']:.9f} oracle={r_orc['lnL_marg']:.9f}")
     assert abs(r_gpu["lnL_marg"] - r_orc["lnL_marg"]) < 1e-3
@@ -110,18 +128,19 @@ def test_lnL_single_point_shape(ile, orc):
 
 def test_lnL_with_tau(ile, orc):
     spec = synth.workload("grad").points[0]
-    d, th, ref, out, h = _lnL_case(ile, orc, spec, 777, "fp32", seed=5, tau_width=1 / 4096)
-    _check_fp32(out, ref, "mfma tau")
+    d, th, ref, out, h, p = _lnL_case(ile, orc, spec, 777, "fp32", seed=5, tau_width=1 / 4096)
+    _check_fp32(out, ref, "mfma tau", p, th)
 
 
 def test_lnL_batched_items(ile, orc):
     w = synth.workload("tiny_batched")
     pts = [synth.make_point(s) for s in w.points]
-    ths, refs, items, off = [], [], [], 0
+    ths, refs, ops, items, off = [], [], [], [], 0
     for i, (d, n) in enumerate(zip(pts, w.n_samples)):
         th = synth.mixed_samples(d, 100 + i, n)
         ths.append(th)
-        refs.append(orc.lnL_t(orc.Point.from_dict(d, complex64=True), th))
+        ops.append(orc.Point.from_dict(d, complex64=True))
+        refs.append(orc.lnL_t(ops[-1], th))
         items.append((i, off, n))
         off += n
     theta = np.concatenate(ths, axis=1)
@@ -130,7 +149,7 @@ def test_lnL_batched_items(ile, orc):
         _say(f"batched items plain={plain} total={off}")
         out = h.lnL(torch.tensor(theta), items).cpu().numpy()
         for i, (_, o, n) in enumerate(items):
-            _check_fp32(out[o:o + n], refs[i], f"batched point {i} plain={plain}")
+            _check_fp32(out[o:o + n], refs[i], f"batched point {i} plain={plain}", ops[i], ths[i])
         h.close()
 
 
@@ -142,11 +161,12 @@ def test_matrix_core_feeds(ile, orc):
     graph replay starts only once every class is measured."""
     w = synth.workload("tiny_batched")
     pts = [synth.make_point(s) for s in w.points]
-    ths, refs, items, off = [], [], [], 0
+    ths, refs, ops, items, off = [], [], [], [], 0
     for i, (d, n) in enumerate(zip(pts, w.n_samples)):
         th = synth.mixed_samples(d, 300 + i, n)
         ths.append(th)
-        refs.append(orc.lnL_t(orc.Point.from_dict(d, complex64=True), th))
+        ops.append(orc.Point.from_dict(d, complex64=True))
+        refs.append(orc.lnL_t(ops[-1], th))
         items.append((i, off, n))
         off += n
     theta = torch.tensor(np.concatenate(ths, axis=1))
@@ -168,7 +188,7 @@ def test_matrix_core_feeds(ile, orc):
     assert np.array_equal(outs[0], outs[2], equal_nan=True)
     assert np.array_equal(outs[0], outs[1], equal_nan=True)
     for i, (_, o, n) in enumerate(items):
-        _check_fp32(outs[2][o:o + n], refs[i], f"direct feed, point {i}")
+        _check_fp32(outs[2][o:o + n], refs[i], f"direct feed, point {i}", ops[i], ths[i])
     h = _handle(ile, pts, "fp32")
     h.set_graph(True)
     a = h.lnL(theta, items).cpu().numpy()
@@ -198,13 +218,16 @@ def test_batched_workload_sampled(ile, orc):
     assert np.array_equal(out, out2, equal_nan=True)
     _say(f"  feeds: {sorted(h.autotune_table().items())}")
     h.close()
-    worst = 0.0
+    worst, worst_rel = 0.0, 0.0
     for i, d in enumerate(pts):
-        ref = orc.lnL_t(orc.Point.from_dict(d, complex64=True), ths[i])
+        op = orc.Point.from_dict(d, complex64=True)
+        ref = orc.lnL_t(op, ths[i])
         err = np.abs(out[i * n:(i + 1) * n] - ref)
-        assert np.all(err <= _fp32_tol(ref)), (i, w.points[i], err.max())
+        tol = _fp32_tol(ref, _quad(op, ths[i]), op.K, op.M)
+        assert np.all(err <= tol), (i, w.points[i], err.max())
         worst = max(worst, float(err.max()))
-    _say(f"  max |d lnL_t| over all points {worst:.3e}")
+        worst_rel = max(worst_rel, float(np.max(err / tol)))
+    _say(f"  max |d lnL_t| over all points {worst:.3e}, max |d|/tol {worst_rel:.3f}")
 
 
 def test_lnL_edge_cases(ile, orc):
@@ -219,7 +242,7 @@ def test_lnL_edge_cases(ile, orc):
     for n in (1, 15, 17):
         _say(f"edge: n={n}")
         th = synth.mixed_samples(d, 3, n)
-        _check_fp32(h.lnL(torch.tensor(th)).cpu().numpy(), orc.lnL_t(p, th), f"n={n}")
+        _check_fp32(h.lnL(torch.tensor(th)).cpu().numpy(), orc.lnL_t(p, th), f"n={n}", p, th)
     # out-of-window tau and bad distance give NaN, the rest are unaffected
     th = synth.mixed_samples(d, 4, 40)
     th[6, 3] = 1.0          # one second: far outside the stored rows
@@ -229,7 +252,7 @@ def test_lnL_edge_cases(ile, orc):
     out = h.lnL(torch.tensor(th)).cpu().numpy()
     assert np.isnan(out[[3, 7, 9]]).all()
     ok = np.ones(40, bool); ok[[3, 7, 9]] = False
-    _check_fp32(out[ok], orc.lnL_t(p, th[:, ok]), "valid neighbours")
+    _check_fp32(out[ok], orc.lnL_t(p, th[:, ok]), "valid neighbours", p, th[:, ok])
     r = h.reduce(torch.tensor(out))
     assert r["n_nonfinite"] == 3 and r["n"] == 37
     # window of one sample
@@ -238,7 +261,8 @@ def test_lnL_edge_cases(ile, orc):
     d1 = dict(d1)
     h1 = _handle(ile, [d1], "fp32")
     th = synth.mixed_samples(d1, 5, 50)
-    _check_fp32(h1.lnL(torch.tensor(th)).cpu().numpy(), orc.lnL_t(orc.Point.from_dict(d1, complex64=True), th), "n_t=16")
+    p1 = orc.Point.from_dict(d1, complex64=True)
+    _check_fp32(h1.lnL(torch.tensor(th)).cpu().numpy(), orc.lnL_t(p1, th), "n_t=16", p1, th)
 
 
 def test_sampler_matches_oracle(ile, orc):
@@ -478,7 +502,7 @@ def test_backward_matches_oracle(ile, orc):
             assert rel.max() < 1e-9
             assert np.allclose(lg, lt, atol=1e-9)
         else:
-            _grad_check(gg, lg, g, lt, th, "backward fp32", f_s=spec.f_s)
+            _grad_check(gg, lg, g, lt, th, "backward fp32", f_s=spec.f_s, op=p)
 
 
 # The gradient target: every component of d lnL_t / d theta within 1e-4 of
@@ -497,13 +521,14 @@ def _consistent(g, th, f_s):
     return u
 
 
-def _grad_check(gg, lg, g, lt, th, label, f_s=4096.0, tol=GRAD_REL, own_top=True):
+def _grad_check(gg, lg, g, lt, th, label, f_s=4096.0, tol=GRAD_REL, own_top=True, op=None):
     """FP32 gradient gg (and ln L_t lg) against the FP64 reference g (lt):
     every component within tol of the sample's largest component, in
     consistent units; on the samples that carry the weight (ln L_t within 20
     of the largest) every component that is at least 1e-3 of that largest one
     also within tol of its own size (for loud points, whose weight-carrying
-    samples have their mass in a few window blocks and are refined in FP64)."""
+    samples have their mass in a few window blocks and are refined in FP64).
+    With op (the oracle point), ln L_t is held to the FP32 tolerance too."""
     ug, ur = _consistent(gg, th, f_s), _consistent(g, th, f_s)
     scale = np.abs(ur).max(axis=0)
     rel = np.abs(ug - ur) / np.maximum(scale, 1e-300)
@@ -518,7 +543,8 @@ def _grad_check(gg, lg, g, lt, th, label, f_s=4096.0, tol=GRAD_REL, own_top=True
         own = np.where(big & top[None, :], np.abs(ug - ur) / np.maximum(np.abs(ur), 1e-300), 0.0)
         _say(f"   weight-carrying samples: {int(top.sum())}, max own-relative error {own.max():.2e}")
         assert own.max() <= tol, (label, np.unravel_index(np.argmax(own), own.shape))
-    _check_fp32(lg, lt, label)
+    if op is not None:
+        _check_fp32(lg, lt, label, op, th)
 
 
 def test_backward_mfma_shapes(ile, orc):
@@ -539,10 +565,10 @@ def test_backward_mfma_shapes(ile, orc):
     gp_, lp = hp.backward(torch.tensor(th), want_lnL=True)
     gp_, lp = gp_.cpu().numpy(), lp.cpu().numpy()
     try:
-        _grad_check(gg.cpu().numpy(), lg.cpu().numpy(), g, lt, th, "mfma adjoint, grad shape")
+        _grad_check(gg.cpu().numpy(), lg.cpu().numpy(), g, lt, th, "mfma adjoint, grad shape", op=op)
     finally:
         # the plain FP32 form has no FP64 refinement: FP32 rounding throughout
-        _grad_check(gp_, lp, g, lt, th, "plain adjoint, grad shape", tol=PLAIN_GRAD_REL, own_top=False)
+        _grad_check(gp_, lp, g, lt, th, "plain adjoint, grad shape", tol=PLAIN_GRAD_REL, own_top=False, op=op)
     # upstream gradient and V != 0
     dv = synth.make_point(synth.PIN_SPECS[3])
     thv = synth.mixed_samples(dv, 13, 257, tau_width=tw)
@@ -552,7 +578,7 @@ def test_backward_mfma_shapes(ile, orc):
     hv = _handle(ile, [dv], "fp32", tau_width=tw)
     _say("backward V != 0 with an upstream gradient")
     ggv, lgv = hv.backward(torch.tensor(thv), grad_lnL=torch.tensor(up), want_lnL=True)
-    _grad_check(ggv.cpu().numpy(), lgv.cpu().numpy(), gv * up[None, :], ltv, thv, "mfma adjoint, V != 0")
+    _grad_check(ggv.cpu().numpy(), lgv.cpu().numpy(), gv * up[None, :], ltv, thv, "mfma adjoint, V != 0", op=opv)
     # several points in one call
     w = synth.workload("tiny_batched")
     pts = [synth.make_point(sp) for sp in w.points]
@@ -571,7 +597,7 @@ def test_backward_mfma_shapes(ile, orc):
     gb, lb = gb.cpu().numpy(), lb.cpu().numpy()
     for i, (_, o, n) in enumerate(items):
         _grad_check(gb[:, o:o + n], lb[o:o + n], refs[i][1], refs[i][0], ths[i], f"mfma adjoint, point {i}",
-                    f_s=pts[i]["f_s"])
+                    f_s=pts[i]["f_s"], op=orc.Point.from_dict(pts[i], complex64=True))
 
 
 def test_lnL_with_V(ile, orc):
@@ -586,7 +612,7 @@ def test_lnL_with_V(ile, orc):
         _say(f"V != 0 {prec} plain={plain}")
         out = h.lnL(torch.tensor(th)).cpu().numpy()
         if prec == "fp32":
-            _check_fp32(out, ref, f"V {prec} plain={plain}")
+            _check_fp32(out, ref, f"V {prec} plain={plain}", p, th)
         else:
             assert np.all(np.abs(out - ref) <= 1e-9 * (1 + np.abs(ref)))
 
@@ -612,12 +638,12 @@ def test_high_l_modes(ile, orc):
         _say(f"high-l modes {prec}")
         out = h.lnL(torch.tensor(th)).cpu().numpy()
         if prec == "fp32":
-            _check_fp32(out, ref, "high-l fp32")
+            _check_fp32(out, ref, "high-l fp32", p, th)
             lt, g = orc.grad(p, th)
             gg, lg = h.backward(torch.tensor(th), want_lnL=True)
             # noise only (no loud samples to refine): the norm-relative bound only
             _grad_check(gg.cpu().numpy(), lg.cpu().numpy(), g, lt, th, "high-l backward fp32", f_s=spec.f_s,
-                        own_top=False)
+                        own_top=False, op=p)
         else:
             assert np.all(np.abs(out - ref) <= 1e-9 * (1 + np.abs(ref)))
 
@@ -639,13 +665,13 @@ def test_single_detector_ragged_window(ile, orc):
         h.set_autotune(mode)
         _say(f"K=1 n_t=37 feed {mode}")
         out = h.lnL(torch.tensor(th)).cpu().numpy()
-        _check_fp32(out, ref, f"K=1 feed {mode}")
+        _check_fp32(out, ref, f"K=1 feed {mode}", p32, th)
         outs.append(out)
         if mode == 0:
             lt, g = orc.grad(p32, th)
             gg, lg = h.backward(torch.tensor(th), want_lnL=True)
             _grad_check(gg.cpu().numpy(), lg.cpu().numpy(), g, lt, th, "K=1 backward fp32", f_s=spec.f_s,
-                        own_top=False)
+                        own_top=False, op=p32)
         h.close()
     assert np.array_equal(outs[0], outs[1], equal_nan=True)
     p64 = orc.Point.from_dict(d)
@@ -676,8 +702,9 @@ def test_single_point_full_size(ile, orc):
     idx = np.random.default_rng(0).choice(n, 1500, replace=False)
     # include the dominant samples
     idx = np.unique(np.concatenate([idx, np.argsort(l64)[-20:]]))
-    ref = orc.lnL_t(orc.Point.from_dict(d, complex64=True), th[:, idx])
-    _check_fp32(l32[idx], ref, "full-size sample")
+    p32 = orc.Point.from_dict(d, complex64=True)
+    ref = orc.lnL_t(p32, th[:, idx])
+    _check_fp32(l32[idx], ref, "full-size sample", p32, th[:, idx])
     ref64 = orc.lnL_t(orc.Point.from_dict(d), th[:, idx])
     err64 = np.abs(l64[idx] - ref64)
     _say(f"  fp64 max|d|={err64.max():.3e}")
@@ -723,7 +750,7 @@ def test_gradient_full_size(ile, orc):
     idx = np.unique(np.concatenate([idx, np.argsort(lt)[-20:]]))
     p = orc.Point.from_dict(d, complex64=True)
     lref, gref = orc.grad(p, th[:, idx])
-    _grad_check(g[:, idx], lt[idx], gref, lref, th[:, idx], "grad full size vs oracle", f_s=d["f_s"])
+    _grad_check(g[:, idx], lt[idx], gref, lref, th[:, idx], "grad full size vs oracle", f_s=d["f_s"], op=p)
     rel64 = np.abs(_consistent(g64[:, idx], th[:, idx], d["f_s"]) - _consistent(gref, th[:, idx], d["f_s"]))
     assert (rel64 / np.abs(_consistent(gref, th[:, idx], d["f_s"])).max(axis=0)).max() <= 1e-9
 
@@ -857,6 +884,48 @@ def test_marginalize_adaptive_matches_oracle(ile, orc):
             assert abs(res[i]["lnL_marg"] - ref[i]["lnL_marg"]) < 1e-3 + 4 * sig
 
 
+def test_adaptive_loud_points_fp64_replay(ile, orc):
+    """The loud end of the adaptive workload: its 15 points with SNR >= 50
+    (up to 59.9, ln L_t up to about 1800), 10 adaptive rounds of 1e5 samples
+    per point (histograms in all six parameters).  The FP32 run's samples and
+    proposal ratios are replayed through the FP64 plain form: |d ln L_marg|
+    <= 1e-3 per point.  Per sample, the 20 heaviest and 100 random samples of
+    each point against the oracle within the FP32 tolerance."""
+    w = synth.workload("adaptive")
+    idx = [i for i, s in enumerate(w.points) if s.snr >= 50.0]
+    assert len(idx) == 15 and max(w.points[i].snr for i in idx) > 59.8
+    pts = [synth.make_point(w.points[i]) for i in idx]
+    n, rounds = 100_000, 10
+    hs = _handle(ile, pts, "fp32")
+    h64 = _handle(ile, pts, "fp64")
+    _say(f"loud adaptive points {idx}: {rounds} rounds x {n}")
+    res32, th, lw = hs.marginalize(2210079124 + 31, n, n_rounds=rounds, adapt_mask=0x3F, floor_eps=0.1,
+                                   return_samples=True)
+    per_round = n * len(pts)
+    deltas = []
+    rng = np.random.default_rng(3)
+    for i, d in enumerate(pts):
+        cols = torch.cat([torch.arange(r * per_round + i * n, r * per_round + (i + 1) * n, device=th.device)
+                          for r in range(rounds)])
+        t_i = th[:, cols]
+        l32 = hs.lnL(t_i, [(i, 0, t_i.shape[1])])
+        l64 = h64.lnL(t_i.double(), [(i, 0, t_i.shape[1])])
+        lr = lw[cols].double() - l32.double()
+        r64 = h64.reduce(l64 + lr)
+        deltas.append(abs(res32[i]["lnL_marg"] - r64["lnL_marg"]))
+        lwn = (l64 + lr).cpu().numpy()
+        pick = np.unique(np.concatenate([np.argsort(lwn)[-20:], rng.choice(t_i.shape[1], 100, replace=False)]))
+        tn = t_i[:, torch.tensor(pick, device=th.device)].cpu().numpy().astype(np.float64)
+        op = orc.Point.from_dict(d, complex64=True)
+        _check_fp32(l32.cpu().numpy()[pick], orc.lnL_t(op, tn), f"loud point {idx[i]} (SNR {w.points[idx[i]].snr:.1f})",
+                    op, tn)
+    _say(f"  |d lnL_marg| per point: {np.array2string(np.array(deltas), precision=2)}; n_eff "
+         f"{np.array2string(np.array([r['n_eff'] for r in res32]), precision=1)}")
+    assert max(deltas) <= 1e-3
+    hs.close()
+    h64.close()
+
+
 def test_gradient_refined_proposal(ile, orc):
     """Gradient-informed proposal refinement.  Every round's importance
     weights use that round's exact proposal density, so (i) the FP32 estimate
@@ -914,9 +983,10 @@ def test_graph_replay_matches_direct(ile, orc):
     theta = torch.tensor(np.concatenate(ths, axis=1), device="cuda", dtype=torch.float32)
     h = _handle(ile, pts, "fp32")
     ref = h.lnL(theta, items).cpu().numpy()
-    refs = [orc.lnL_t(orc.Point.from_dict(d, complex64=True), t_) for d, t_ in zip(pts, ths)]
+    ops = [orc.Point.from_dict(d, complex64=True) for d in pts]
+    refs = [orc.lnL_t(op, t_) for op, t_ in zip(ops, ths)]
     for i, (_, o, n) in enumerate(items):
-        _check_fp32(ref[o:o + n], refs[i], f"direct, point {i}")
+        _check_fp32(ref[o:o + n], refs[i], f"direct, point {i}", ops[i], ths[i])
     h.set_graph(True)
     for rep in range(4):
         _say(f"graph replay {rep}")
