@@ -433,7 +433,7 @@ def main():
                                gmm_pairs=pr)
             torch.cuda.synchronize()
             t3 = time.perf_counter()
-            gm[nm] = {"ms": (t3 - t2) * 1e3, "n_eff": [x["n_eff"] for x in r], "discarded": [x["n_nonfinite"] for x in r],
+            gm[nm] = {"ms": (t3 - t2) * 1e3, "n_eff": [x["n_eff"] for x in r],
                       "sigma_lnL": [x["sigma_lnL"] for x in r], "lnL_marg": [x["lnL_marg"] for x in r]}
         hs.close()
         out["gmm"] = {"points": len(sub), "rounds": 10, "samples_per_round": 100_000, "floor_eps": 0.1, **gm}

@@ -88,7 +88,7 @@ typedef struct {
   int n_det;              /* K, 1..RIFT_MAX_DET */
   int n_modes;            /* M, 1..RIFT_MAX_MODES */
   int n_t;                /* window samples, >= 1 */
-  int pad;                /* rows before and after the window, >= ceil(f_s max|r_k|/c) */
+  int pad;                /* rows before and after the window, ceil(f_s max|r_k|/c) .. 32767 */
   const int *ell, *em;    /* host [M]: mode (l, m), 2 <= l <= 8, |m| <= l */
   double f_s;             /* sample rate, Hz */
   double d_ref;           /* distance at which Q, U, V were computed, Mpc */
@@ -161,9 +161,12 @@ typedef struct {
    * gmm_components bivariate components in its two prior-CDF coordinates
    * (App. A, finite domains): draws from the untruncated mixture rejected
    * outside the unit square (64 tries, Philox counter word 2 =
-   * 3 2^30 | round << 10 | pair << 8 | try; a sample none accepts is
-   * discarded with ln ratio NaN), p_s = floor_eps + (1 - floor_eps)
-   * sum_k pi_k N_k / sum_k pi_k Z_k, Z_k the component's mass in the square. */
+   * 3 2^30 | round << 10 | pair << 8 | try).  A draw none of whose tries
+   * lands in the square (probability f = (1 - Z)^64, Z = sum_k pi_k Z_k,
+   * Z_k the component's mass in the square) is given up: the sample keeps
+   * its raw uniforms and ln ratio -inf (zero weight; it stays in the count).
+   * Kept draws are weighted with p_s = floor_eps + (1 - floor_eps) (1 - f)
+   * sum_k pi_k N_k / Z, their density among all draws. */
   unsigned gmm_pairs;
   /* Resume: the Philox round index of the first round (counter word 2 uses
    * first_round + r).  0: a fresh pooled estimate.  > 0 (with
@@ -311,7 +314,7 @@ rift_status rift_ile_autotune_table(const rift_ile *h, int *modes);
  * parameter takes one 32-bit word, mapped through the prior's inverse CDF or,
  * for a parameter adapted in the point's proposal, through its 100-bin
  * histogram or its Gaussian mixture (see rift_ile_set_gmm; a correlated pair
- * none of whose tries lands in the unit square gives ln_ratio NaN).
+ * none of whose tries lands in the unit square gives ln_ratio -inf).
  * theta: device [7][n]; ln_ratio: device [n] (handle precision)
  * receives ln p - ln p_s (or NULL); bins: device uint8 [7][n] receives each
  * sample's histogram bin per parameter (floor(100 u) under a mixture) (or

@@ -31,11 +31,14 @@ counter word 2 = 2^31 | (2 round + half).
 Correlated pairs (the paper's correlated sampling in subsets of dimensions):
 up to three disjoint pairs (a, b) of adapted parameters get bivariate
 components in (u_a, u_b).  As the appendix describes, draws come from the
-untruncated mixture and are rejected outside the unit square, so the pair's
-proposal is p = eps + (1 - eps) sum_k pi_k N_k(u) / sum_k pi_k Z_k, Z_k the
+untruncated mixture and are rejected outside the unit square; an accepted
+draw follows T(u) = sum_k pi_k N_k(u) / Z with Z = sum_k pi_k Z_k, Z_k the
 component's mass in the square.  Tries use Philox counter word 2 =
-3 * 2^30 | round << 10 | pair << 8 | try (64 tries; a sample none of them
-accepts is discarded: ln p - ln p_s = NaN).  EM fits bivariate normals (sd >=
+3 * 2^30 | round << 10 | pair << 8 | try.  The rejection gives up after 64
+tries, which happens with probability f = (1 - Z)^64, so among all draws the
+pair's coordinates have the sub-density q(u) = eps + (1 - eps)(1 - f) T(u)
+and the draws given up on carry zero weight (ln p - ln p_s = -inf; they stay
+in the sample count, so that E[p/q] over all draws is 1).  EM fits bivariate normals (sd >=
 1e-4 per axis, |correlation| <= 0.99); the online update uses the text's
 symmetric Mahalanobis distances with each component's own covariance.
 """
@@ -119,13 +122,28 @@ def pair_logpdf(x, y, mu, cov):
 
 
 def pair_density(x, y, w, mu, cov, eps):
-    """Pair proposal density in (u_a, u_b) on the unit square."""
+    """Pair proposal density in (u_a, u_b) on the unit square (rejection
+    without a limit on the tries): eps + (1 - eps) T(u)."""
     zm = sum(w[k] * box_mass(mu[k], cov[k]) for k in range(len(w)) if w[k] > 0.0)
     s = np.zeros_like(np.asarray(x, dtype=np.float64))
     for k in range(len(w)):
         if w[k] > 0.0:
             s = s + w[k] * np.exp(pair_logpdf(x, y, mu[k], cov[k]))
     return eps + (1.0 - eps) * s / zm
+
+
+def pair_draw_density(x, y, w, mu, cov, eps, tries=None):
+    """Sub-density of the sampler's pair draws over all draws: the mixture
+    branch keeps a draw with probability 1 - (1 - Z)^tries (Z the per-try
+    acceptance sum_k pi_k Z_k), so q(u) = eps + (1 - eps)(1 - (1 - Z)^tries) T(u)."""
+    tries = PAIR_TRIES if tries is None else tries
+    zm = sum(w[k] * box_mass(mu[k], cov[k]) for k in range(len(w)) if w[k] > 0.0)
+    keep = 1.0 - (1.0 - zm) ** tries
+    s = np.zeros_like(np.asarray(x, dtype=np.float64))
+    for k in range(len(w)):
+        if w[k] > 0.0:
+            s = s + w[k] * np.exp(pair_logpdf(x, y, mu[k], cov[k]))
+    return eps + (1.0 - eps) * keep * s / zm
 
 
 def chol(cov):
@@ -253,8 +271,8 @@ def draw(seed, point, rnd, n, g: Gmm | None, *, d_min=10.0, d_max=1000.0, tau_wi
                 if ok:
                     u[a, j], u[b, j] = x, y
                 else:
-                    lr[j] = np.nan
-            dens = pair_density(u[a], u[b], g.pw[pi], g.pmu[pi], g.pcov[pi], g.eps)
+                    lr[j] = -np.inf  # given up on: zero weight (u_a, u_b stay the raw uniforms)
+            dens = pair_draw_density(u[a], u[b], g.pw[pi], g.pmu[pi], g.pcov[pi], g.eps)
             lr -= np.log(dens)
     th = np.stack([prior_inv(d, u[d], d_min, d_max, tau_width) for d in range(7)])
     if frame is not None:

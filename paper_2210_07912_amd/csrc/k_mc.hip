@@ -69,6 +69,7 @@ struct GmmSh {
   double w[7][kMaxG], mu[7][kMaxG], sd[7][kMaxG], ca[7][kMaxG], z[7][kMaxG];
   double pw[kMaxPair][kMaxG], pmu[kMaxPair][kMaxG][2], pch[kMaxPair][kMaxG][3], pic[kMaxPair][kMaxG][3];
   double plog[kMaxPair][kMaxG], pzm[kMaxPair];
+  double pkeep[kMaxPair];  // probability that a pair's rejection keeps a draw: 1 - (1 - pzm)^kPairTries
 };
 __device__ __forceinline__ void gmm_stage(const ProposalDev *prop, GmmSh &g) {
   if (threadIdx.x == 0) {
@@ -79,6 +80,7 @@ __device__ __forceinline__ void gmm_stage(const ProposalDev *prop, GmmSh &g) {
       g.pa[p] = prop->pa[p];
       g.pb[p] = prop->pb[p];
       g.pzm[p] = prop->pzm[p];
+      g.pkeep[p] = 1.0 - exp((double)kPairTries * log1p(-fmin(prop->pzm[p], 1.0)));
     }
   }
   for (int i = threadIdx.x; i < kMaxPair * kMaxG; i += blockDim.x) {
@@ -183,7 +185,11 @@ __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned 
   // correlated pairs: below the floor the raw uniforms, else up to
   // kPairTries draws from the untruncated mixture (Philox counter word 2 =
   // 3 2^30 | round << 10 | pair << 8 | try), the first inside the unit
-  // square kept; none inside: the sample is discarded (ln ratio NaN)
+  // square kept.  None inside (probability (1 - pzm)^kPairTries): the draw
+  // is given up and the sample carries zero weight (ln ratio -inf) but stays
+  // in the count, and a kept draw's density among all draws is
+  // eps + (1 - eps) pkeep T, T the mixture truncated to the square, so that
+  // the weights average to 1 over all draws.
   bool discard = false;
   for (int p = 0; p < npair; p++) {
     const int a = g->pa[p], b = g->pb[p];
@@ -227,7 +233,7 @@ __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned 
         sden += exp(g->plog[p][k] - 0.5 * q);
       }
     }
-    lr -= log(eps + (1.0 - eps) * sden / g->pzm[p]);
+    lr -= log(eps + (1.0 - eps) * g->pkeep[p] * sden / g->pzm[p]);
     const int dd[2] = {a, b};
     const double uu[2] = {ua, ub};
     for (int q = 0; q < 2; q++) {
@@ -237,7 +243,7 @@ __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned 
       if (bins) bins[dd[q] * bin_stride + col] = (uint8_t)min((int)(uu[q] * kNB), kNB - 1);
     }
   }
-  if (discard) lr = NAN;
+  if (discard) lr = -INFINITY;
   if (pt) {
     double al, de;
     frame_sky(pt->frame, pt->gmst, us[0], us[1], al, de);

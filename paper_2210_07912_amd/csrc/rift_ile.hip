@@ -253,7 +253,8 @@ rift_status check_point(const rift_ile_point &q, int idx, double tau_width) {
   if (q.n_modes < 1 || q.n_modes > RIFT_MAX_MODES)
     return fail(nullptr, RIFT_E_SHAPE, "point %d: n_modes=%d outside 1..%d", idx, q.n_modes, RIFT_MAX_MODES);
   if (q.n_t < 1 || q.n_t > (1 << 20)) return fail(nullptr, RIFT_E_SHAPE, "point %d: n_t=%d", idx, q.n_t);
-  if (q.pad < 0 || q.pad > (1 << 16)) return fail(nullptr, RIFT_E_SHAPE, "point %d: pad=%d", idx, q.pad);
+  // (the matrix-core path stores row offsets in -pad..pad as 16-bit integers)
+  if (q.pad < 0 || q.pad > 32767) return fail(nullptr, RIFT_E_SHAPE, "point %d: pad=%d (at most 32767)", idx, q.pad);
   if (!q.ell || !q.em || !q.det_pos || !q.det_resp || !q.Q || !q.U)
     return fail(nullptr, RIFT_E_INVALID, "point %d: NULL array", idx);
   for (int m = 0; m < q.n_modes; m++)
@@ -1396,7 +1397,10 @@ rift_status rift_ile_set_proposal(rift_ile *h, int point, const double *cdf, uns
     std::memcpy(pr.cdf[d], c, sizeof(double) * (kNB + 1));
   }
   pr.mask = mask;
-  HIPCHK(h, hipMemcpy(h->d_props + point, &pr, sizeof(pr), hipMemcpyHostToDevice));
+  // on the handle's stream, after any pending sampling or adaptation that
+  // reads or writes the proposals, and complete before the host copy is freed
+  HIPCHK(h, hipMemcpyAsync(h->d_props + point, &pr, sizeof(pr), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
   return RIFT_OK;
 }
 
@@ -1450,7 +1454,10 @@ rift_status rift_ile_set_gmm(rift_ile *h, int point, int K, unsigned mask, doubl
   pr.mask = mask;
   pr.geps = floor_eps;
   pr.gntr = n_trained;
-  HIPCHK(h, hipMemcpy(h->d_props + point, &pr, sizeof(pr), hipMemcpyHostToDevice));
+  // on the handle's stream, after any pending sampling or adaptation that
+  // reads or writes the proposals, and complete before the host copy is freed
+  HIPCHK(h, hipMemcpyAsync(h->d_props + point, &pr, sizeof(pr), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
   return RIFT_OK;
 }
 

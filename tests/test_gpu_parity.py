@@ -1233,27 +1233,46 @@ def _set_pairs(h, point, g):
     h.set_gmm_pairs(point, g.pairs, g.pw, g.pmu, g.pcov)
 
 
-def test_gmm_pair_draws_match_oracle(ile, orc):
+def _low_box_model(gmm):
+    """One pair (psi, phi) whose single component sits at the corner (0, 0)
+    with sd 0.05 and correlation -0.99: box mass about 0.0225, so the 64-try
+    rejection gives up on about 21 % of the draws."""
+    g = gmm.Gmm(1, 0b0010100, 0.1, pairs=[(2, 4)])
+    g.pw[0] = np.array([1.0])
+    g.pmu[0] = np.array([[0.0, 0.0]])
+    g.pcov[0] = np.array([[0.0025, -0.002475, 0.0025]])
+    g.n_trained = 1000.0
+    return g
+
+
+@pytest.mark.parametrize("model", ["pairs", "low_box_mass"])
+def test_gmm_pair_draws_match_oracle(ile, orc, model):
     """Correlated pairs: rejection draws from the untruncated bivariate
-    mixture, the pair density with its box mass, discards, against the
-    oracle on the same Philox streams."""
+    mixture, the pair density with its box mass and the kept fraction, the
+    draws given up on (ln ratio -inf), against the oracle on the same
+    Philox streams."""
     from oracle import gmm
     d = synth.make_point(synth.workload("tiny").points[0])
-    g = _pair_model(gmm)
+    g = _pair_model(gmm) if model == "pairs" else _low_box_model(gmm)
     n, first, seed = 3001, 123, 2210079129
     ref_th, ref_lr, _ = gmm.draw(seed, 0, 3, n, g, start=first)
-    zref = [sum(g.pw[i][k] * gmm.box_mass(g.pmu[i][k], g.pcov[i][k]) for k in range(3) if g.pw[i][k] > 0)
-            for i in range(2)]
+    zref = [sum(g.pw[i][k] * gmm.box_mass(g.pmu[i][k], g.pcov[i][k]) for k in range(g.K) if g.pw[i][k] > 0)
+            for i in range(len(g.pairs))]
+    gave_up = np.isneginf(ref_lr)
+    _say(f"  {model}: box mass {np.array2string(np.array(zref), precision=4)}, given up {int(gave_up.sum())} of {n}")
+    if model == "low_box_mass":
+        assert gave_up.sum() > 100
     for prec in ("fp64", "fp32"):
         _say(f"gmm pair draws {prec}")
         h = _handle(ile, [d], prec)
         _set_pairs(h, 0, g)
         got = h.get_gmm_pairs(0)
         assert got["pairs"] == g.pairs
-        assert np.abs(got["box_mass"][:2] - zref).max() < 1e-12
+        assert np.abs(got["box_mass"][:len(g.pairs)] - zref).max() < 1e-12
         th, lr, _ = h.sample(0, seed, 3, n, first=first)
         th, lr = th.cpu().numpy(), lr.cpu().numpy()
-        assert np.array_equal(np.isnan(lr), np.isnan(ref_lr))
+        assert not np.isnan(lr).any()
+        assert np.array_equal(np.isneginf(lr), gave_up)
         fin = np.isfinite(ref_lr)
         if prec == "fp64":
             assert np.abs(th - ref_th).max() < 1e-9
@@ -1339,7 +1358,7 @@ def test_marginalize_gmm_pairs_matches_oracle(ile, orc):
             assert dmax < 1e-8
     for i, (r, o) in enumerate(zip(res, ref)):
         _say(f"  point {i}: gpu {r['lnL_marg']:.9f} oracle {o['lnL_marg']:.9f} n_eff {r['n_eff']:.1f}/{o['n_eff']:.1f} "
-             f"discarded {r['n_nonfinite']}/{o['n_nonfinite']}")
+             f"n {r['n']}/{o['n']}")
         sig = math.hypot(r["sigma_lnL"], o["sigma_lnL"])
         assert abs(r["lnL_marg"] - o["lnL_marg"]) < 1e-3 + 4 * sig
         assert h.get_gmm_pairs(i)["pairs"] == pairs

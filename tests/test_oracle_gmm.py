@@ -218,3 +218,59 @@ def test_pair_draws_follow_the_truncated_mixture():
     assert chisquare(obs.ravel(), n * P.ravel()).pvalue > 1e-3
     # the 1-D parameter of the mask (3) keeps its own (initial) mixture; others the prior
     assert stats.kstest(u[0], "uniform").pvalue > 1e-3
+
+
+def test_pair_draws_with_a_low_box_mass_average_to_one():
+    """A pair whose mixture lies mostly outside the unit square: one
+    component at the corner (0, 0), sd 0.05 per axis, correlation -0.99.
+    Its box mass is the positive-quadrant probability 1/4 + asin(rho)/(2 pi)
+    (about 0.0225), so the 64-try rejection gives up on a fraction
+    (1 - eps)(1 - Z)^64 (about 0.21) of the draws, which carry zero weight,
+    and the kept ones follow q = eps + (1 - eps)(1 - (1 - Z)^64) T.  Checked:
+    q integrates to the kept fraction, the given-up fraction, the cells of the
+    kept draws against q, their weights, and E[p/q] = 1 over all draws."""
+    from scipy.stats import chisquare, multivariate_normal
+    rho, sd = -0.99, 0.05
+    g = gmm.Gmm(1, 0b0010100, 0.1, pairs=[(2, 4)])
+    g.pw[0] = np.array([1.0])
+    g.pmu[0] = np.array([[0.0, 0.0]])
+    g.pcov[0] = np.array([[sd * sd, rho * sd * sd, sd * sd]])
+    Z = gmm.box_mass(g.pmu[0][0], g.pcov[0][0])
+    assert abs(Z - (0.25 + math.asin(rho) / (2.0 * math.pi))) < 1e-10
+    keep = 1.0 - (1.0 - Z) ** 64
+    # q over the square, eps = 0: (1 - eps) keep, T integrating to 1; by a
+    # product Gauss-Legendre rule on [0, 0.4]^2 (beyond 0.4 the component's
+    # mass is below 1e-15), split at 0.1 where the ridge x = -y/rho lies
+    x, wq = np.polynomial.legendre.leggauss(400)
+    xs = np.concatenate([0.05 * (x + 1.0), 0.1 + 0.15 * (x + 1.0)])
+    ws = np.concatenate([0.05 * wq, 0.15 * wq])
+    X, Y = np.meshgrid(xs, xs, indexing="ij")
+    qv = gmm.pair_draw_density(X.ravel(), Y.ravel(), g.pw[0], g.pmu[0], g.pcov[0], 0.0).reshape(X.shape)
+    assert abs(np.einsum("i,j,ij->", ws, ws, qv) - keep) < 1e-8
+    n = 4000
+    th, lr, u = gmm.draw(2210079131, 0, 1, n, g)
+    assert not np.isnan(lr).any()
+    gave_up = np.isneginf(lr)
+    frac = (1.0 - g.eps) * (1.0 - keep)
+    assert abs(gave_up.mean() - frac) < 5.0 * math.sqrt(frac * (1 - frac) / n), (gave_up.mean(), frac)
+    # kept draws in 4 x 4 cells of [0, 1)^2 against q / P(kept)
+    e = np.array([0.0, 0.03, 0.06, 0.12, 1.0])
+    C = np.array([[sd * sd, rho * sd * sd], [rho * sd * sd, sd * sd]])
+    F = lambda a, b: multivariate_normal.cdf([a, b], mean=[0.0, 0.0], cov=C, abseps=1e-12, releps=1e-12)
+    P = np.zeros((4, 4))
+    for i in range(4):
+        for j in range(4):
+            cell = F(e[i + 1], e[j + 1]) - F(e[i], e[j + 1]) - F(e[i + 1], e[j]) + F(e[i], e[j])
+            P[i, j] = g.eps * (e[i + 1] - e[i]) * (e[j + 1] - e[j]) + (1 - g.eps) * keep * cell / Z
+    P /= P.sum()
+    kept = ~gave_up
+    obs = np.histogram2d(u[2][kept], u[4][kept], bins=[e, e])[0]
+    ok = kept.sum() * P.ravel() > 5
+    assert chisquare(obs.ravel()[ok], kept.sum() * P.ravel()[ok] * obs.ravel()[ok].sum()
+                     / (kept.sum() * P.ravel()[ok]).sum()).pvalue > 1e-3
+    # the kept draws carry the weight of that density (the pair is the only
+    # adapted part of the mask here: parameters 2 and 4)
+    q = gmm.pair_draw_density(u[2][kept], u[4][kept], g.pw[0], g.pmu[0], g.pcov[0], g.eps)
+    assert np.allclose(lr[kept], -np.log(q), rtol=0, atol=1e-12)
+    r = np.exp(lr)
+    assert abs(r.mean() - 1.0) < 5 * r.std() / math.sqrt(n)
