@@ -193,7 +193,9 @@ void rift_ile_destroy(rift_ile *h);
 
 /* Text of the last error on h (or of the last failed create when h is NULL). */
 const char *rift_ile_last_error(const rift_ile *h);
-const char *rift_ile_status_string(rift_status s);
+/* Text of a status (an int, so that any value a caller holds is valid;
+ * values that are no rift_status give "unknown status"). */
+const char *rift_ile_status_string(int s);
 int rift_ile_abi_version(void);
 
 /* Diagnostics: time the dominant evaluation kernel (the persistent matrix-

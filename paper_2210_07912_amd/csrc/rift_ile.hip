@@ -1001,7 +1001,7 @@ extern "C" {
 
 int rift_ile_abi_version(void) { return RIFT_ILE_ABI_VERSION; }
 
-const char *rift_ile_status_string(rift_status s) {
+const char *rift_ile_status_string(int s) {
   switch (s) {
     case RIFT_OK: return "ok";
     case RIFT_E_INVALID: return "invalid argument";
@@ -1620,11 +1620,31 @@ rift_status rift_ile_load_checkpoint(rift_ile *h, const void *buf, int64_t bytes
   const char *c = (const char *)buf + sizeof hd;
   std::vector<ProposalDev> props(np);
   std::memcpy(props.data(), c, sizeof(ProposalDev) * np);
+  // every field a kernel uses as an index or divides by is checked before
+  // anything reaches the device
+  bool mix = false;
   for (const auto &p : props) {
-    if (p.gk < 0 || p.gk > kMaxG || p.npair < 0 || p.npair > kMaxPair || (p.mask >> 7))
-      return fail(h, RIFT_E_INVALID, "checkpoint: corrupt proposal");
-    if (p.gk > 0) h->any_mix = true;
+    bool ok = p.gk >= 0 && p.gk <= kMaxG && p.npair >= 0 && p.npair <= kMaxPair && !(p.mask >> 7) &&
+              (p.npair == 0 || p.gk > 0);
+    for (int d = 0; ok && d < 7; d++) {
+      ok = p.cdf[d][0] == 0.0 && p.cdf[d][kNB] == 1.0;
+      for (int b = 0; ok && b < kNB; b++) ok = p.cdf[d][b + 1] > p.cdf[d][b];
+    }
+    for (int d = 0; ok && d < 7; d++)
+      for (int k = 0; ok && k < p.gk; k++)
+        ok = std::isfinite(p.gw[d][k]) && std::isfinite(p.gmu[d][k]) && p.gsd[d][k] > 0 && std::isfinite(p.gsd[d][k]) &&
+             std::isfinite(p.gca[d][k]) && p.gz[d][k] > 0 && std::isfinite(p.gz[d][k]);
+    unsigned used = 0u;
+    for (int q = 0; ok && q < p.npair; q++) {
+      ok = p.pa[q] >= 0 && p.pa[q] < p.pb[q] && p.pb[q] < 7 && ((p.mask >> p.pa[q]) & 1u) &&
+           ((p.mask >> p.pb[q]) & 1u) && !((used >> p.pa[q]) & 1u) && !((used >> p.pb[q]) & 1u) && p.pzm[q] > 0 &&
+           p.pzm[q] <= 1.0 + 1e-12;
+      used |= (1u << p.pa[q]) | (1u << p.pb[q]);
+    }
+    if (!ok || !(p.geps >= 0 && p.geps <= 1)) return fail(h, RIFT_E_INVALID, "checkpoint: corrupt proposal");
+    mix = mix || p.gk > 0;
   }
+  if (mix) h->any_mix = true;
   void *accum;
   rift_status s = ws_get(h, W_ACCUM, sizeof(ReduceTuple) * np, &accum);
   if (s != RIFT_OK) return s;

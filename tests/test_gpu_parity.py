@@ -1365,6 +1365,21 @@ def test_marginalize_gmm_pairs_matches_oracle(ile, orc):
     h.close()
 
 
+def test_out_of_memory_is_reported(ile):
+    """A run whose workspace cannot be allocated (2^37 samples per round:
+    about a terabyte of per-sample arrays) returns RIFT_E_OOM before any
+    kernel runs, and the handle keeps working afterwards."""
+    d = synth.make_point(synth.workload("tiny").points[0])
+    h = _handle(ile, [d], "fp32")
+    _say("out of memory: 2^37 samples per round")
+    with pytest.raises(ile.RiftError) as e:
+        h.marginalize(2210079141, 1 << 37, n_rounds=1)
+    assert e.value.status == -6, e.value
+    r = h.marginalize(2210079141, 4096, n_rounds=1)
+    assert r[0]["n"] == 4096 and np.isfinite(r[0]["lnL_marg"])
+    h.close()
+
+
 def test_marginalize_is_deterministic(ile):
     """The FP64 reductions, histogram merges and mixture EM sums run in fixed
     orders: two runs (the same handle, then a fresh one) give bit-identical
