@@ -421,8 +421,10 @@ rift_status rift_ile_set_gmm_pairs(rift_ile *h, int point, unsigned pairs, const
 rift_status rift_ile_get_gmm_pairs(rift_ile *h, int point, unsigned *pairs, double *w, double *mu, double *cov,
                                    double *box_mass);
 
-/* The whole step for every point: for each round, draw samples from the
- * current proposal, evaluate ln L_t, form ln w, fold them into a pooled FP64
+/* The whole step for every point (Sec. II.A Eq. (lnL:MonteCarlo) estimated
+ * with adaptive importance sampling as in Sec. III.B, GPU-accelerated Monte
+ * Carlo integration; sample sizes of App. B): for each round, draw samples
+ * from the current proposal, evaluate ln L_t, form ln w, fold them into a pooled FP64
  * estimate over all rounds (each sample weighted with its own round's p_s),
  * and after every round (the last included, so the proposals left behind
  * are the next round's) adapt the masked parameters' histograms from that
@@ -449,13 +451,17 @@ int64_t rift_ile_checkpoint_bytes(const rift_ile *h);
 rift_status rift_ile_save_checkpoint(rift_ile *h, void *buf, int64_t bytes);
 rift_status rift_ile_load_checkpoint(rift_ile *h, const void *buf, int64_t bytes);
 
-/* Gradient of ln L_t with respect to the seven parameters, through the
+/* Gradient of ln L_t (App. D Eq. (def:lnL:Decomposed) with the window
+ * log-sum-exp, differentiated; the paper gives no passage on the gradient
+ * itself) with respect to the seven parameters, through the
  * antenna patterns F_k(alpha, delta, psi), the delays dt_k(alpha, delta) and
  * tau (via the Catmull-Rom derivative of Q), the harmonics Y_lm(iota, phi) and
  * the distance.  grad_theta[d][i] = g_i d ln L_t,i / d theta_d with
  * g = grad_lnL_t (device [stride], or NULL for 1).  lnL_t_out (device
  * [stride] or NULL) receives ln L_t.  Same items/stride/layout as
- * rift_ile_lnL.  Asynchronous. */
+ * rift_ile_lnL.  On an RIFT_FP32 handle the samples whose softmax mass lies
+ * in at most three window blocks are re-evaluated in FP64 (see
+ * rift_ile_set_grad_refine).  Asynchronous. */
 rift_status rift_ile_backward(rift_ile *h, int n_items, const rift_ile_item *items, int64_t stride,
                               const void *theta, const void *grad_lnL_t, void *grad_theta,
                               void *lnL_t_out);
