@@ -208,11 +208,20 @@ def frame_sky(det_pos, gmst, u0, u1):
     return alpha, delta
 
 
-def draw(seed, point, rnd, n, g: Gmm | None, *, d_min=10.0, d_max=1000.0, tau_width=0.0, start=0, frame=None):
+def phase_rot(us, ud):
+    """Phase-rotated coordinates (the C oracle's map): psi = 2 pi (u_s - u_d)
+    mod pi, phi = 2 pi (u_s + u_d) mod 2 pi."""
+    x, y = 2.0 * math.pi * (us - ud), 2.0 * math.pi * (us + ud)
+    return x - math.pi * np.floor(x / math.pi), y - 2.0 * math.pi * np.floor(y / (2.0 * math.pi))
+
+
+def draw(seed, point, rnd, n, g: Gmm | None, *, d_min=10.0, d_max=1000.0, tau_width=0.0, start=0, frame=None,
+         phase=False):
     """Samples start..start+n-1 of (point, round) from the mixture proposal
     (prior where g is None or a parameter is outside g.mask): theta [7, n],
     ln p - ln p_s [n], u [7, n].  frame = (det_pos, gmst): the sky drawn in
-    the network frame of detectors 0 and 1."""
+    the network frame of detectors 0 and 1.  phase: polarization and phase
+    from the phase-rotated coordinates u[PSI] = u_s, u[PHI] = u_d."""
     _, _, _, raw = oracle.draw(seed, point, rnd, n, d_min=d_min, d_max=d_max, tau_width=tau_width, start=start)
     v = ((raw.astype(np.float64) // 256) + 0.5) / 16777216.0
     u = v.copy()
@@ -277,6 +286,8 @@ def draw(seed, point, rnd, n, g: Gmm | None, *, d_min=10.0, d_max=1000.0, tau_wi
     th = np.stack([prior_inv(d, u[d], d_min, d_max, tau_width) for d in range(7)])
     if frame is not None:
         th[ALPHA], th[DELTA] = frame_sky(frame[0], frame[1], u[ALPHA], u[DELTA])
+    if phase:
+        th[PSI], th[PHI] = phase_rot(u[PSI], u[PHI])
     return th, lr, u
 
 

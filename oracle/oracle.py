@@ -227,10 +227,11 @@ def u01(x):
 
 
 def draw(seed, point, rnd, n, *, d_min=10.0, d_max=1000.0, tau_width=0.0, cdf=None, nb=100,
-         adapt_mask=0, start=0, frame=None):
+         adapt_mask=0, start=0, frame=None, phase=False):
     """Samples start..start+n-1 of (point, round): theta [7, n], ln_ratio [n],
     bins [7, n] (uint8), raw Philox words [8, n].  frame = (det_pos [>=2, 3],
-    gmst): the sky is drawn in the network frame of detectors 0 and 1."""
+    gmst): the sky is drawn in the network frame of detectors 0 and 1.
+    phase: polarization and phase drawn in phase-rotated coordinates."""
     th = np.zeros((7, n))
     lr = np.zeros(n)
     bins = np.zeros((7, n), dtype=np.uint8)
@@ -244,14 +245,22 @@ def draw(seed, point, rnd, n, *, d_min=10.0, d_max=1000.0, tau_width=0.0, cdf=No
     fp = None if frame is None else np.ascontiguousarray(np.asarray(frame[0], dtype=np.float64)[:2].reshape(6))
     gm = 0.0 if frame is None else float(frame[1])
     for i in range(n):
-        L.or_draw_frame(C.c_uint64(seed), C.c_uint32(point), C.c_uint32(rnd), C.c_uint64(start + i),
-                        C.c_double(d_min), C.c_double(d_max), C.c_double(tau_width), _ptr(cd), nb,
-                        C.c_uint(adapt_mask), _ptr(fp), C.c_double(gm), _ptr(t7), C.byref(l1), b7, r8)
+        L.or_draw_coords(C.c_uint64(seed), C.c_uint32(point), C.c_uint32(rnd), C.c_uint64(start + i),
+                         C.c_double(d_min), C.c_double(d_max), C.c_double(tau_width), _ptr(cd), nb,
+                         C.c_uint(adapt_mask), _ptr(fp), C.c_double(gm), int(bool(phase)), _ptr(t7), C.byref(l1),
+                         b7, r8)
         th[:, i] = t7
         lr[i] = l1.value
         bins[:, i] = list(b7)
         raw[:, i] = list(r8)
     return th, lr, bins, raw
+
+
+def phase_rot(us, ud):
+    """Phase-rotated coordinates (u_s, u_d) -> (psi, phi)."""
+    psi, phi = C.c_double(), C.c_double()
+    lib().or_phase_rot(C.c_double(us), C.c_double(ud), C.byref(psi), C.byref(phi))
+    return psi.value, phi.value
 
 
 def network_frame(det_pos):

@@ -660,9 +660,31 @@ static void frame_sky(const double *pos, double gmst, double u0, double u1, doub
   *alpha = a;
 }
 
-void or_draw_frame(uint64_t seed, uint32_t point, uint32_t round, uint64_t i, double d_min, double d_max,
-                   double tau_width, const double *cdf, int nb, unsigned adapt_mask, const double *frame_pos,
-                   double gmst, double theta[7], double *ln_ratio, uint8_t bins[7], uint32_t raw[8]) {
+/* Phase-rotated coordinates for the polarization and the orbital phase (the
+ * paper's outlook on coordinates that simplify the phase posterior of loud
+ * sources, with its recommendation of sky- and phase-rotated coordinates for
+ * them).  The polarization rotates every detector's F_k by exp(-2 i psi) and
+ * Y_lm carries exp(i m phi), so a (2, 2) mode depends on (psi, phi) only
+ * through d = phi - psi and a (2, -2) mode only through s = phi + psi: a loud
+ * source dominated by one of them has its likelihood flat along one of the
+ * two and peaked along the other.  The two uniforms of the psi and phi
+ * dimensions become u_s = s / 4 pi and u_d = d / 4 pi in [0, 1):
+ *   psi = 2 pi (u_s - u_d) mod pi,   phi = 2 pi (u_s + u_d) mod 2 pi.
+ * The map from [0, 1)^2 onto the (psi, phi) torus [0, pi) x [0, 2 pi) is
+ * four to one with constant Jacobian, so it carries the uniform measure to
+ * the uniform one: the prior stays uniform in (u_s, u_d) and the importance
+ * ratio of a draw is 1 / p_s(u_s, u_d) in those coordinates. */
+static void phase_rot(double us, double ud, double *psi, double *phi) {
+  const double x = 2.0 * M_PI * (us - ud), y = 2.0 * M_PI * (us + ud);
+  *psi = x - M_PI * floor(x / M_PI);
+  *phi = y - 2.0 * M_PI * floor(y / (2.0 * M_PI));
+}
+
+void or_phase_rot(double us, double ud, double *psi, double *phi) { phase_rot(us, ud, psi, phi); }
+
+void or_draw_coords(uint64_t seed, uint32_t point, uint32_t round, uint64_t i, double d_min, double d_max,
+                    double tau_width, const double *cdf, int nb, unsigned adapt_mask, const double *frame_pos,
+                    double gmst, int phase, double theta[7], double *ln_ratio, uint8_t bins[7], uint32_t raw[8]) {
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   uint32_t r[8];
   for (int half = 0; half < 2; half++) {
@@ -693,7 +715,15 @@ void or_draw_frame(uint64_t seed, uint32_t point, uint32_t round, uint64_t i, do
     theta[d] = prior_inv(d, u, d_min, d_max, tau_width);
   }
   if (frame_pos) frame_sky(frame_pos, gmst, us[OR_ALPHA], us[OR_DELTA], &theta[OR_ALPHA], &theta[OR_DELTA]);
+  if (phase) phase_rot(us[OR_PSI], us[OR_PHI], &theta[OR_PSI], &theta[OR_PHI]);
   *ln_ratio = lr;
+}
+
+void or_draw_frame(uint64_t seed, uint32_t point, uint32_t round, uint64_t i, double d_min, double d_max,
+                   double tau_width, const double *cdf, int nb, unsigned adapt_mask, const double *frame_pos,
+                   double gmst, double theta[7], double *ln_ratio, uint8_t bins[7], uint32_t raw[8]) {
+  or_draw_coords(seed, point, round, i, d_min, d_max, tau_width, cdf, nb, adapt_mask, frame_pos, gmst, 0, theta,
+                 ln_ratio, bins, raw);
 }
 
 void or_draw(uint64_t seed, uint32_t point, uint32_t round, uint64_t i, double d_min, double d_max,

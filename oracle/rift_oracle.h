@@ -94,6 +94,16 @@ void or_draw_frame(uint64_t seed, uint32_t point, uint32_t round, uint64_t i,
                    const double *cdf, int nb, unsigned adapt_mask,
                    const double *frame_pos, double gmst,
                    double theta[7], double *ln_ratio, uint8_t bins[7], uint32_t raw[8]);
+/* The same with the polarization and orbital phase drawn in phase-rotated
+ * coordinates when phase != 0: the uniforms of dimensions psi and phi are
+ * u_s, u_d and psi = 2 pi (u_s - u_d) mod pi, phi = 2 pi (u_s + u_d) mod 2 pi
+ * (or_phase_rot); bins and ln_ratio refer to (u_s, u_d). */
+void or_draw_coords(uint64_t seed, uint32_t point, uint32_t round, uint64_t i,
+                    double d_min, double d_max, double tau_width,
+                    const double *cdf, int nb, unsigned adapt_mask,
+                    const double *frame_pos, double gmst, int phase,
+                    double theta[7], double *ln_ratio, uint8_t bins[7], uint32_t raw[8]);
+void or_phase_rot(double us, double ud, double *psi, double *phi);
 /* axes[3][3]: rows x', y', z' of the network frame in Earth-fixed coordinates */
 void or_network_frame(const double *frame_pos, double axes[9]);
 /* (alpha, delta) -> the frame's prior-CDF coordinates (u_phi', u_cos theta') */

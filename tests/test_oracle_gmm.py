@@ -148,6 +148,14 @@ def test_frame_sky_matches_the_c_oracle(orc):
     assert np.abs(a - th[0]).max() < 1e-12 and np.abs(dl - th[1]).max() < 1e-12
 
 
+def test_phase_rotation_matches_the_c_oracle(orc):
+    """The numpy phase-rotated map equals the C oracle's on its own draws."""
+    th, _, _, _ = orc.draw(5, 0, 0, 300, phase=True)
+    th2, _, u = gmm.draw(5, 0, 0, 300, None, phase=True)
+    assert np.array_equal(th[[2, 4]], th2[[2, 4]])
+    assert np.abs(th - th2).max() < 1e-12
+
+
 # --- correlated pairs ---------------------------------------------------------
 
 def _pair_model():

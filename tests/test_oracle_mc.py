@@ -98,6 +98,147 @@ def test_network_frame_draws(orc):
     assert np.array_equal(th[2:], th_e[2:]) and np.array_equal(bins, bins_e) and np.array_equal(raw, raw_e)
 
 
+def _modes(d, keep):
+    """The point restricted to the modes listed in keep."""
+    e, idx = dict(d), np.asarray(keep)
+    e["Q"] = d["Q"][:, :, idx]
+    e["U"] = d["U"][:, idx][:, :, idx]
+    if d.get("V") is not None:
+        e["V"] = d["V"][:, idx][:, :, idx]
+    e["ell"], e["em"] = np.asarray(d["ell"])[idx], np.asarray(d["em"])[idx]
+    return e
+
+
+def test_phase_rotation_map(orc):
+    """(u_s, u_d) -> (psi, phi): into [0, pi) x [0, 2 pi), exactly four
+    preimages in the unit square for every image point (u_s - u_d fixed mod
+    1/2, u_s + u_d mod 1), constant Jacobian 8 pi^2 = 4 x the torus area, so
+    the uniform measure goes to the uniform measure."""
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        psi, phi = rng.uniform(0, math.pi), rng.uniform(0, 2 * math.pi)
+        pre = []
+        for a in range(-2, 3):
+            for b in range(-2, 3):
+                x, y = psi / (2 * math.pi) + a / 2, phi / (2 * math.pi) + b
+                us, ud = (x + y) / 2, (y - x) / 2
+                if 0 <= us < 1 and 0 <= ud < 1:
+                    pre.append((us, ud))
+        assert len(pre) == 4
+        for us, ud in pre:
+            p2, f2 = orc.phase_rot(us, ud)
+            assert abs(p2 - psi) < 1e-12 or abs(abs(p2 - psi) - math.pi) < 1e-12
+            assert abs(f2 - phi) < 1e-12 or abs(abs(f2 - phi) - 2 * math.pi) < 1e-12
+    h = 1e-7
+    for us, ud in rng.uniform(0.05, 0.95, size=(50, 2)):
+        p0, f0 = orc.phase_rot(us, ud)
+        p1, f1 = orc.phase_rot(us + h, ud)
+        p2, f2 = orc.phase_rot(us, ud + h)
+        J = np.array([[p1 - p0, p2 - p0], [f1 - f0, f2 - f0]]) / h
+        if np.abs(J).max() < 100:  # not across a wrap
+            assert abs(abs(np.linalg.det(J)) - 8 * math.pi ** 2) < 1e-5
+    for us, ud in rng.uniform(0, 1, size=(1000, 2)):
+        p0, f0 = orc.phase_rot(us, ud)
+        assert 0 <= p0 < math.pi and 0 <= f0 < 2 * math.pi
+
+
+def test_phase_rotated_draws(orc):
+    """Draws in phase-rotated coordinates: (psi, phi) jointly uniform on the
+    torus (Kolmogorov-Smirnov per axis, chi^2 on an 8 x 8 grid), ln p - ln p_s
+    = 0 for the prior, theta[psi, phi] the map of the raw uniforms of those
+    two dimensions, everything else as in the plain draw (bins, raw words,
+    the other five parameters; with the network frame too)."""
+    n = 20000
+    th, lr, bins, raw = orc.draw(2210079120, 3, 1, n, tau_width=1 / 4096, phase=True)
+    assert np.all(lr == 0.0)
+    assert stats.kstest(th[2], lambda x: x / math.pi).pvalue > 1e-3
+    assert stats.kstest(th[4], lambda x: x / (2 * math.pi)).pvalue > 1e-3
+    cnt, _, _ = np.histogram2d(th[2], th[4], bins=8, range=[[0, math.pi], [0, 2 * math.pi]])
+    chi2 = ((cnt - n / 64) ** 2 / (n / 64)).sum()
+    assert stats.chi2.sf(chi2, 63) > 1e-3
+    u = ((raw[:7] >> 8).astype(np.float64) + 0.5) / 2 ** 24
+    for i in range(0, n, 211):
+        assert (th[2, i], th[4, i]) == orc.phase_rot(u[2, i], u[4, i])
+    th_e, lr_e, bins_e, raw_e = orc.draw(2210079120, 3, 1, n, tau_width=1 / 4096)
+    keep = [0, 1, 3, 5, 6]
+    assert np.array_equal(th[keep], th_e[keep]) and np.array_equal(bins, bins_e) and np.array_equal(raw, raw_e)
+    pos = _hl_positions()
+    th_f, _, _, _ = orc.draw(2210079120, 3, 1, 500, tau_width=1 / 4096, frame=(pos, 0.4), phase=True)
+    th_g, _, _, _ = orc.draw(2210079120, 3, 1, 500, tau_width=1 / 4096, frame=(pos, 0.4))
+    assert np.array_equal(th_f[[0, 1, 3, 5, 6]], th_g[[0, 1, 3, 5, 6]])
+    assert np.array_equal(th_f[[2, 4]], th[[2, 4], :500])
+
+
+def test_phase_rotated_coordinates_separate_the_modes(orc):
+    """The point of the coordinates: with only the (2, 2) mode, ln L_t does
+    not depend on u_s (the likelihood is flat along phi + psi); with only the
+    (2, -2) mode it does not depend on u_d; with both it depends on both."""
+    d = synth.make_point(synth.PIN_SPECS[5])
+    ell, em = list(d["ell"]), list(d["em"])
+    i22 = [i for i in range(len(ell)) if ell[i] == 2 and em[i] == 2]
+    i2m = [i for i in range(len(ell)) if ell[i] == 2 and em[i] == -2]
+    assert i22 and i2m
+    th = np.tile(d["theta_inj"][:, None], (1, 16)).astype(np.float64)
+    th[3] = 1.2  # inclined, so that both modes carry weight
+    rng = np.random.default_rng(5)
+
+    def spread(p, fixed):
+        out = []
+        for _ in range(4):
+            c = rng.uniform()
+            v = rng.uniform(size=16)
+            us, ud = (v, np.full(16, c)) if fixed == "ud" else (np.full(16, c), v)
+            t = th.copy()
+            for j in range(16):
+                t[2, j], t[4, j] = orc.phase_rot(us[j], ud[j])
+            out.append(np.ptp(orc.lnL_t(p, t)))
+        return max(out)
+
+    p22 = orc.Point.from_dict(_modes(d, i22))
+    p2m = orc.Point.from_dict(_modes(d, i2m))
+    pall = orc.Point.from_dict(d)
+    assert spread(p22, "ud") < 1e-9 and spread(p22, "us") > 1e-2
+    assert spread(p2m, "us") < 1e-9 and spread(p2m, "ud") > 1e-2
+    assert spread(pall, "ud") > 1e-2 and spread(pall, "us") > 1e-2
+
+
+def test_phase_rotated_mc_matches_quadrature(orc):
+    """Marginalize over (psi, phi) with the other parameters at the
+    injection: histogram proposals adapted in (u_s, u_d) over three rounds,
+    pooled, against the periodic trapezoid rule on the torus (spectrally
+    accurate for this smooth periodic integrand)."""
+    spec = synth.PIN_SPECS[5]
+    d = synth.make_point(spec)
+    p = orc.Point.from_dict(d)
+    t0 = d["theta_inj"]
+
+    def lnL_pp(psi, phi):
+        th = np.tile(t0[:, None], (1, psi.size))
+        th[2], th[4] = psi, phi
+        return orc.lnL_t(p, th)
+
+    def quad(n):
+        ps = np.arange(n) * math.pi / n
+        fs = np.arange(2 * n) * math.pi / n
+        P, F = np.meshgrid(ps, fs, indexing="ij")
+        lnl = lnL_pp(P.ravel(), F.ravel())
+        m = lnl.max()
+        return m + math.log(np.exp(lnl - m).mean())
+
+    q1, q2 = quad(96), quad(128)
+    assert abs(q1 - q2) < 1e-9
+    cdf, mask, lnw_all = None, 0, []
+    for r in range(3):
+        th, lr, bins, _ = orc.draw(91, 0, r, 20000, cdf=cdf, adapt_mask=mask, phase=True)
+        lnw = lnL_pp(th[2], th[4]) + lr
+        lnw_all.append(lnw)
+        cdf = orc.adapt(bins, lnw, floor_eps=0.1, adapt_mask=0b10100)
+        mask = 0b10100
+    r = orc.reduce(np.concatenate(lnw_all))
+    assert r["n_var"] > 1000
+    assert abs(r["lnL_marg"] - q2) < 4 * r["sigma_lnL"], (r, q2)
+
+
 def test_histogram_proposal(orc):
     rng = np.random.default_rng(8)
     nb = 100
