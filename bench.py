@@ -327,6 +327,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    import math
+
+    import numpy as np
     import torch
 
     import synth
@@ -412,20 +415,40 @@ def main():
         out["precompute"] = {"K": 3, "M": 21, "N": N, "rows": L, "ms": (t3 - t2) / reps * 1e3,
                              "note": "host arrays in and out, device buffers allocated per call"}
 
-    # adaptive sampling with the sky in each point's detector-network frame
-    # against the equatorial frame, and the Gaussian-mixture proposal against
-    # the histograms: n_eff on the first points (10 rounds of 1e5 samples)
+    # sampling coordinates: the sky in each point's detector-network frame and
+    # the polarization and phase in phase-rotated coordinates against the
+    # equatorial, unrotated ones, with histograms in the six angles and
+    # distance over 10 rounds: on the first 8 points of this workload (1e5
+    # samples per round) and on the (2, +-2) workload of 4 face-on/off and 4
+    # edge-on points at SNR 25 (1e6 per round, three seeds: per-point median
+    # n_eff).  Then the Gaussian-mixture proposal against the histograms on
+    # the first 8 points.
     if w.adaptive and not args.n and not args.no_extras:
+        cfgs = (("equatorial", False, False), ("network_frame", True, False), ("phase_rotation", False, True),
+                ("network_frame_phase_rotation", True, True))
+        wq = synth.workload("quadrupole")
+        coords = {}
+        for sname, spts, n_r, seeds in (("first8", pts[:8], 100_000, (seed + 11,)),
+                                        ("quadrupole", [synth.make_point(sp) for sp in wq.points], 1_000_000,
+                                         (seed + 21, seed + 22, seed + 23))):
+            hs = ile.RiftILE(spts, precision=w.precision, tau_width=w.tau_width)
+            cc = {"samples_per_round": n_r, "seeds": len(seeds),
+                  "cos_iota": [round(math.cos(p["theta_inj"][3]), 3) for p in spts]}
+            for nm, net, ph in cfgs:
+                hs.set_network_frame(net)
+                hs.set_phase_rotation(ph)
+                rs = [hs.marginalize(sd, n_r, n_rounds=10, adapt_mask=0x3F, floor_eps=0.1) for sd in seeds]
+                ne = np.array([[x["n_eff"] for x in r] for r in rs])
+                lm = np.array([[x["lnL_marg"] for x in r] for r in rs])
+                cc[nm] = {"n_eff_median": np.median(ne, axis=0).tolist(),
+                          "n_eff_geomean": float(np.exp(np.log(np.median(ne, axis=0)).mean())),
+                          "lnL_marg_median": np.median(lm, axis=0).tolist(),
+                          "lnL_marg_spread": np.ptp(lm, axis=0).tolist()}
+            hs.close()
+            coords[sname] = cc
+        out["coordinates"] = {"rounds": 10, "floor_eps": 0.1, **coords}
         sub = pts[:8]
         hs = ile.RiftILE(sub, precision=w.precision, tau_width=w.tau_width)
-        nf = {}
-        for nm, net in (("equatorial", False), ("network_frame", True)):
-            hs.set_network_frame(net)
-            r = hs.marginalize(seed + 11, 100_000, n_rounds=10, adapt_mask=0x3F, floor_eps=0.1)
-            nf[nm] = {"n_eff": [x["n_eff"] for x in r], "sigma_lnL": [x["sigma_lnL"] for x in r],
-                      "lnL_marg": [x["lnL_marg"] for x in r]}
-        out["network_frame"] = {"points": len(sub), "rounds": 10, "samples_per_round": 100_000, **nf}
-        hs.set_network_frame(False)
         gm = {}
         # correlated pairs (psi, phi) and (iota, D): the pairs the polarization-phase and
         # inclination-distance degeneracies tie together

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define RIFT_ILE_ABI_VERSION 2
+#define RIFT_ILE_ABI_VERSION 3
 
 typedef enum {
   RIFT_OK = 0,
@@ -273,6 +273,27 @@ rift_status rift_ile_precompute(const rift_ile_fd_point *in, int64_t row0, int64
  * theta is still (alpha, delta).  A point with one detector keeps the
  * equatorial axes.  Default off.  Returns RIFT_E_INVALID for a NULL handle. */
 rift_status rift_ile_set_network_frame(rift_ile *h, int enable);
+
+/* Polarization and orbital phase of the sampler in phase-rotated coordinates
+ * (App. D, more flexible sampling models: sky- and phase-rotated coordinates
+ * for the loudest signals; App. E, better ILE integration: polarization and
+ * phase coordinates that simplify the phase posterior).
+ * With enable != 0, rift_ile_sample and rift_ile_marginalize draw the two
+ * uniforms of dimensions psi and phi as u_s = (phi + psi) / 4 pi and
+ * u_d = (phi - psi) / 4 pi and return
+ *   psi = 2 pi (u_s - u_d) mod pi,   phi = 2 pi (u_s + u_d) mod 2 pi.
+ * A (2, 2) mode depends on (psi, phi) only through phi - psi and a (2, -2)
+ * mode only through phi + psi, so for a source dominated by either the
+ * likelihood varies along one of u_s, u_d and is flat along the other, which
+ * a product proposal captures.  The map is four to one with a constant
+ * Jacobian: the prior is uniform in (u_s, u_d), ln p - ln p_s keeps its form,
+ * and the adaptive histograms and mixtures of dimensions psi and phi (and the
+ * bins rift_ile_sample writes) refer to u_s and u_d.  Combines with the
+ * network frame.  rift_ile_marginalize returns RIFT_E_INVALID when this is on
+ * together with RIFT_MC_GRADIENT.  A checkpoint records both coordinate
+ * switches and loads only into a handle with the same ones.  Default off.
+ * Returns RIFT_E_INVALID for a NULL handle. */
+rift_status rift_ile_set_phase_rotation(rift_ile *h, int enable);
 
 /* Precision of the FP32 adjoint (rift_ile_backward on an RIFT_FP32 handle).
  * The gradient of ln L_t is an average of d ell_j / d theta under the window

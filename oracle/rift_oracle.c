@@ -660,10 +660,10 @@ static void frame_sky(const double *pos, double gmst, double u0, double u1, doub
   *alpha = a;
 }
 
-/* Phase-rotated coordinates for the polarization and the orbital phase (the
- * paper's outlook on coordinates that simplify the phase posterior of loud
- * sources, with its recommendation of sky- and phase-rotated coordinates for
- * them).  The polarization rotates every detector's F_k by exp(-2 i psi) and
+/* Phase-rotated coordinates for the polarization and the orbital phase
+ * (App. D, more flexible sampling models: sky- and phase-rotated coordinates
+ * for the loudest signals; App. E, better ILE integration: coordinates that
+ * simplify the phase posterior).  The polarization rotates every detector's F_k by exp(-2 i psi) and
  * Y_lm carries exp(i m phi), so a (2, 2) mode depends on (psi, phi) only
  * through d = phi - psi and a (2, -2) mode only through s = phi + psi: a loud
  * source dominated by one of them has its likelihood flat along one of the

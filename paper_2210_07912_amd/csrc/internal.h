@@ -206,12 +206,13 @@ struct ProposalDev {
 };
 
 // pt / pts: the point(s) whose network frame the sky is drawn in, or null for
-// the equatorial coordinates
+// the equatorial coordinates; phase: polarization and orbital phase drawn in
+// the phase-rotated coordinates (u_s, u_d)
 template <typename R>
 hipError_t sample_launch(const PointDev *pt, const ProposalDev *prop, int point, uint64_t seed, uint32_t round,
                          int64_t first, int64_t n, int64_t stride, int64_t bin_stride, double d_min, double d_max,
                          double tau_width, R *theta, R *ln_ratio, uint8_t *bins, hipStream_t st,
-                         float *ubuf = nullptr, bool mix = true);
+                         float *ubuf = nullptr, bool mix = true, bool phase = false);
 // every point of a round in one launch (blk0: [np + 1] prefix of 256-sample
 // blocks; off, cnt: columns and counts of each point; device arrays)
 template <typename R>
@@ -219,7 +220,7 @@ hipError_t sample_multi_launch(const ProposalDev *props, const PointDev *pts, co
                                const int64_t *off,
                                const int64_t *cnt, uint64_t seed, uint32_t round, int64_t stride, int64_t bin_stride,
                                double d_min, double d_max, double tau_width, R *theta, R *ln_ratio, uint8_t *bins,
-                               hipStream_t st, float *ubuf = nullptr, bool mix = true);
+                               hipStream_t st, float *ubuf = nullptr, bool mix = true, bool phase = false);
 
 struct ReduceTuple {
   double m, s1, s2;

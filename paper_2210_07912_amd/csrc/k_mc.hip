@@ -61,6 +61,21 @@ __device__ __forceinline__ void frame_sky(const double (*fr)[3], double gmst, do
   alpha = al < 0.0 ? al + 2.0 * kPi : al;
 }
 
+// Phase-rotated coordinates of the polarization and orbital phase: the
+// uniforms of those two dimensions are u_s = (phi + psi) / 4 pi and
+// u_d = (phi - psi) / 4 pi, so that psi = 2 pi (u_s - u_d) mod pi and
+// phi = 2 pi (u_s + u_d) mod 2 pi.  A (2, 2) mode depends on (psi, phi) only
+// through phi - psi and a (2, -2) mode only through phi + psi (F_k turns as
+// exp(-2 i psi), Y_lm as exp(i m phi)), so for a source dominated by either
+// the likelihood varies along one coordinate only.  The map is four to one
+// with a constant Jacobian: the uniform prior stays uniform in (u_s, u_d),
+// and the proposal's ratio keeps its form in those coordinates.
+__device__ __forceinline__ void phase_rotated(double us, double ud, double &psi, double &phi) {
+  const double x = 2.0 * kPi * (us - ud), y = 2.0 * kPi * (us + ud);
+  psi = x - kPi * floor(x / kPi);
+  phi = y - 2.0 * kPi * floor(y / (2.0 * kPi));
+}
+
 // mixture parameters of a proposal, staged in LDS by the sampling kernels
 struct GmmSh {
   int k, npair;
@@ -116,8 +131,8 @@ __device__ __forceinline__ void gmm_stage(const ProposalDev *prop, GmmSh &g) {
 template <typename R, bool MIX>
 __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned mask, const GmmSh *g, uint32_t point,
                                          uint64_t seed, uint32_t round, uint64_t i, double d_min, double d_max,
-                                         double tau_width, const PointDev *pt, R *theta, int64_t stride, R *ln_ratio,
-                                         uint8_t *bins, int64_t bin_stride, int64_t col, float *ubuf) {
+                                         double tau_width, const PointDev *pt, bool phase, R *theta, int64_t stride,
+                                         R *ln_ratio, uint8_t *bins, int64_t bin_stride, int64_t col, float *ubuf) {
   uint32_t r[8], e[8];
   for (int half = 0; half < 2; half++) {
     uint32_t c[4] = {(uint32_t)i, (uint32_t)(i >> 32), 2u * round + (uint32_t)half, point};
@@ -132,7 +147,7 @@ __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned 
       for (int q = 0; q < 4; q++) e[4 * half + q] = c[q];
     }
   }
-  double lr = 0.0, us[2] = {0.0, 0.0};
+  double lr = 0.0, u_al = 0.0, u_de = 0.0, u_ps = 0.0, u_ph = 0.0;  // uniforms the frame maps read
   unsigned pm = 0u;  // parameters drawn in correlated pairs (after this loop)
   const int npair = MIX ? g->npair : 0;
   for (int p = 0; p < npair; p++) pm |= (1u << g->pa[p]) | (1u << g->pb[p]);
@@ -177,7 +192,10 @@ __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned 
       lr -= log(mass * kNB);
       bin = (uint32_t)lo;
     }
-    if (d < 2) us[d] = u;
+    if (d == RIFT_ALPHA) u_al = u;
+    if (d == RIFT_DELTA) u_de = u;
+    if (d == RIFT_PSI) u_ps = u;
+    if (d == RIFT_PHI) u_ph = u;
     if (ubuf) ubuf[d * bin_stride + col] = (float)u;
     theta[d * stride + col] = prior_inv<R>(d, u, d_min, d_max, tau_width);
     if (bins) bins[d * bin_stride + col] = (uint8_t)bin;
@@ -237,7 +255,10 @@ __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned 
     const int dd[2] = {a, b};
     const double uu[2] = {ua, ub};
     for (int q = 0; q < 2; q++) {
-      if (dd[q] < 2) us[dd[q]] = uu[q];
+      if (dd[q] == RIFT_ALPHA) u_al = uu[q];
+      if (dd[q] == RIFT_DELTA) u_de = uu[q];
+      if (dd[q] == RIFT_PSI) u_ps = uu[q];
+      if (dd[q] == RIFT_PHI) u_ph = uu[q];
       if (ubuf) ubuf[dd[q] * bin_stride + col] = (float)uu[q];
       theta[dd[q] * stride + col] = prior_inv<R>(dd[q], uu[q], d_min, d_max, tau_width);
       if (bins) bins[dd[q] * bin_stride + col] = (uint8_t)min((int)(uu[q] * kNB), kNB - 1);
@@ -246,9 +267,15 @@ __device__ __forceinline__ void draw_one(const double (*cdf)[kNB + 1], unsigned 
   if (discard) lr = -INFINITY;
   if (pt) {
     double al, de;
-    frame_sky(pt->frame, pt->gmst, us[0], us[1], al, de);
+    frame_sky(pt->frame, pt->gmst, u_al, u_de, al, de);
     theta[RIFT_ALPHA * stride + col] = (R)al;
     theta[RIFT_DELTA * stride + col] = (R)de;
+  }
+  if (phase) {
+    double ps, ph;
+    phase_rotated(u_ps, u_ph, ps, ph);
+    theta[RIFT_PSI * stride + col] = (R)ps;
+    theta[RIFT_PHI * stride + col] = (R)ph;
   }
   if (ln_ratio) ln_ratio[col] = (R)lr;
 }
@@ -258,7 +285,7 @@ __global__ void __launch_bounds__(256) sample_kernel(const ProposalDev *prop, co
                                                      uint64_t seed, uint32_t round, int64_t first, int64_t n,
                                                      int64_t stride, int64_t bin_stride, double d_min, double d_max,
                                                      double tau_width, R *theta, R *ln_ratio, uint8_t *bins,
-                                                     float *ubuf) {
+                                                     float *ubuf, int phase) {
   __shared__ double cdf[7][kNB + 1];
   __shared__ unsigned mask;
   __shared__ GmmSh g;
@@ -268,8 +295,8 @@ __global__ void __launch_bounds__(256) sample_kernel(const ProposalDev *prop, co
   __syncthreads();
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  draw_one<R, MIX>(cdf, mask, &g, point, seed, round, (uint64_t)(first + j), d_min, d_max, tau_width, pt, theta, stride,
-              ln_ratio, bins, bin_stride, j, ubuf);
+  draw_one<R, MIX>(cdf, mask, &g, point, seed, round, (uint64_t)(first + j), d_min, d_max, tau_width, pt, phase != 0,
+                   theta, stride, ln_ratio, bins, bin_stride, j, ubuf);
 }
 
 // every point of a round in one launch: blocks [blk0[p], blk0[p + 1]) draw
@@ -280,7 +307,7 @@ __global__ void __launch_bounds__(256) sample_multi_kernel(const ProposalDev *pr
                                                            const int64_t *cnt, uint64_t seed, uint32_t round,
                                                            int64_t stride, int64_t bin_stride, double d_min,
                                                            double d_max, double tau_width, R *theta, R *ln_ratio,
-                                                           uint8_t *bins, float *ubuf) {
+                                                           uint8_t *bins, float *ubuf, int phase) {
   __shared__ double cdf[7][kNB + 1];
   __shared__ unsigned mask;
   __shared__ GmmSh g;
@@ -298,23 +325,23 @@ __global__ void __launch_bounds__(256) sample_multi_kernel(const ProposalDev *pr
   const int64_t j = (int64_t)(blockIdx.x - blk0[p]) * blockDim.x + threadIdx.x;
   if (j >= cnt[p]) return;
   draw_one<R, MIX>(cdf, mask, &g, (uint32_t)p, seed, round, (uint64_t)j, d_min, d_max, tau_width, pts ? pts + p : nullptr,
-              theta, stride, ln_ratio, bins, bin_stride, off[p] + j, ubuf);
+                   phase != 0, theta, stride, ln_ratio, bins, bin_stride, off[p] + j, ubuf);
 }
 
 template <typename R>
 hipError_t sample_launch(const PointDev *pt, const ProposalDev *prop, int point, uint64_t seed, uint32_t round,
                          int64_t first, int64_t n, int64_t stride, int64_t bin_stride, double d_min, double d_max,
                          double tau_width, R *theta, R *ln_ratio, uint8_t *bins, hipStream_t st, float *ubuf,
-                         bool mix) {
+                         bool mix, bool phase) {
   if (n <= 0) return hipSuccess;
   if (mix)
     hipLaunchKernelGGL((sample_kernel<R, true>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, prop, pt,
                        (uint32_t)point, seed, round, first, n, stride, bin_stride, d_min, d_max, tau_width, theta,
-                       ln_ratio, bins, ubuf);
+                       ln_ratio, bins, ubuf, (int)phase);
   else
     hipLaunchKernelGGL((sample_kernel<R, false>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, prop, pt,
                        (uint32_t)point, seed, round, first, n, stride, bin_stride, d_min, d_max, tau_width, theta,
-                       ln_ratio, bins, ubuf);
+                       ln_ratio, bins, ubuf, (int)phase);
   return hipGetLastError();
 }
 
@@ -322,32 +349,32 @@ template <typename R>
 hipError_t sample_multi_launch(const ProposalDev *props, const PointDev *pts, const int *blk0, int n_blocks, int np,
                                const int64_t *off, const int64_t *cnt, uint64_t seed, uint32_t round, int64_t stride,
                                int64_t bin_stride, double d_min, double d_max, double tau_width, R *theta,
-                               R *ln_ratio, uint8_t *bins, hipStream_t st, float *ubuf, bool mix) {
+                               R *ln_ratio, uint8_t *bins, hipStream_t st, float *ubuf, bool mix, bool phase) {
   if (n_blocks <= 0) return hipSuccess;
   if (mix)
     hipLaunchKernelGGL((sample_multi_kernel<R, true>), dim3((unsigned)n_blocks), dim3(256), 0, st, props, pts, blk0,
                        np, off, cnt, seed, round, stride, bin_stride, d_min, d_max, tau_width, theta, ln_ratio, bins,
-                       ubuf);
+                       ubuf, (int)phase);
   else
     hipLaunchKernelGGL((sample_multi_kernel<R, false>), dim3((unsigned)n_blocks), dim3(256), 0, st, props, pts, blk0,
                        np, off, cnt, seed, round, stride, bin_stride, d_min, d_max, tau_width, theta, ln_ratio, bins,
-                       ubuf);
+                       ubuf, (int)phase);
   return hipGetLastError();
 }
 template hipError_t sample_multi_launch<float>(const ProposalDev *, const PointDev *, const int *, int, int,
                                                const int64_t *,
                                                const int64_t *, uint64_t, uint32_t, int64_t, int64_t, double, double,
-                                               double, float *, float *, uint8_t *, hipStream_t, float *, bool);
+                                               double, float *, float *, uint8_t *, hipStream_t, float *, bool, bool);
 template hipError_t sample_multi_launch<double>(const ProposalDev *, const PointDev *, const int *, int, int,
                                                 const int64_t *,
                                                 const int64_t *, uint64_t, uint32_t, int64_t, int64_t, double, double,
-                                                double, double *, double *, uint8_t *, hipStream_t, float *, bool);
+                                                double, double *, double *, uint8_t *, hipStream_t, float *, bool, bool);
 template hipError_t sample_launch<float>(const PointDev *, const ProposalDev *, int, uint64_t, uint32_t, int64_t,
                                          int64_t, int64_t, int64_t, double, double, double, float *, float *,
-                                         uint8_t *, hipStream_t, float *, bool);
+                                         uint8_t *, hipStream_t, float *, bool, bool);
 template hipError_t sample_launch<double>(const PointDev *, const ProposalDev *, int, uint64_t, uint32_t, int64_t,
                                           int64_t, int64_t, int64_t, double, double, double, double *, double *,
-                                          uint8_t *, hipStream_t, float *, bool);
+                                          uint8_t *, hipStream_t, float *, bool, bool);
 
 // ---------------------------------------------------------------------------
 // FP64 reduction

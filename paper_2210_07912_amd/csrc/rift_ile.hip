@@ -61,6 +61,7 @@ struct rift_ile {
   int64_t n_captures = 0, n_replays = 0;
   // sky drawn in each point's network frame (rift_ile_set_network_frame)
   bool net_frame = false;
+  bool phase_rot = false;  // polarization and phase in phase-rotated coordinates
   // how each (T, K) class feeds the matrix cores: 0 not measured, 1 staged, 2
   // direct; feed: 1 measure on first use, 0 all staged, 2 all direct
   int feed = 1;
@@ -865,6 +866,11 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
   const double beta = mc->ascent_mix > 0.0 ? mc->ascent_mix : 0.3;
   if (grad && (ka > 256 || !(beta + mc->floor_eps < 1.0)))
     return fail(h, RIFT_E_INVALID, "n_ascent %d (<= 256) or ascent_mix %g (< 1 - floor_eps)", ka, beta);
+  // the ascent places its points in the histograms by the prior-CDF
+  // coordinates of (psi, phi), which the four-to-one phase rotation does not
+  // give back
+  if (grad && h->phase_rot)
+    return fail(h, RIFT_E_INVALID, "the gradient refinement is not combined with phase-rotated coordinates");
   // Gaussian-mixture proposal: prior-CDF coordinates of every sample, EM sums
   // and the mixtures being fitted
   const int gk = mc->gmm_components;
@@ -945,7 +951,7 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
     HIPCHK(h, sample_multi_launch<R>(h->d_props, h->net_frame ? h->d_pts : nullptr, d_sblk, sblk[np], np, d_soff,
                                      d_scnt, mc->seed, (uint32_t)(mc->first_round + r),
                                      th_stride, nr, h->d_min, h->d_max, h->tau_width, th, (R *)ratio,
-                                     (uint8_t *)bins, h->stream, ubuf, h->any_mix));
+                                     (uint8_t *)bins, h->stream, ubuf, h->any_mix, h->phase_rot));
     {
       Range ph("evaluate");
       if ((s = eval<R>(h, it, th_stride, th, nullptr, lw, (const R *)ratio)) != RIFT_OK) return s;
@@ -1239,6 +1245,12 @@ rift_status rift_ile_set_network_frame(rift_ile *h, int enable) {
   return RIFT_OK;
 }
 
+rift_status rift_ile_set_phase_rotation(rift_ile *h, int enable) {
+  if (!h) return RIFT_E_INVALID;
+  h->phase_rot = enable != 0;
+  return RIFT_OK;
+}
+
 rift_status rift_ile_set_grad_refine(rift_ile *h, int enable) {
   if (!h) return RIFT_E_INVALID;
   h->refine = enable != 0;
@@ -1274,11 +1286,11 @@ rift_status rift_ile_sample(rift_ile *h, int point, uint64_t seed, uint32_t roun
                      ? sample_launch<float>(h->net_frame ? h->d_pts + point : nullptr, h->d_props + point, point, seed,
                                             round, first, n, n, n, h->d_min,
                                             h->d_max, h->tau_width, (float *)theta, (float *)ln_ratio, bins, h->stream,
-                                            nullptr, h->any_mix)
+                                            nullptr, h->any_mix, h->phase_rot)
                      : sample_launch<double>(h->net_frame ? h->d_pts + point : nullptr, h->d_props + point, point, seed,
                                              round, first, n, n, n, h->d_min,
                                              h->d_max, h->tau_width, (double *)theta, (double *)ln_ratio, bins,
-                                             h->stream, nullptr, h->any_mix);
+                                             h->stream, nullptr, h->any_mix, h->phase_rot);
   if (e != hipSuccess) return hip_fail(h, e, "sample");
   return RIFT_OK;
 }
@@ -1578,7 +1590,9 @@ struct CkptHeader {
   char magic[8];
   int32_t version, n_points;
   int64_t proposal_bytes, tuple_bytes;
+  int32_t coords, reserved;  // coordinates the proposals refer to: bit 0 network frame, bit 1 phase rotation
 };
+int32_t coords_of(const rift_ile *h) { return (h->net_frame ? 1 : 0) | (h->phase_rot ? 2 : 0); }
 constexpr char kCkptMagic[8] = {'R', 'I', 'F', 'T', 'C', 'K', 'P', '1'};
 
 int64_t rift_ile_checkpoint_bytes(const rift_ile *h) {
@@ -1597,6 +1611,8 @@ rift_status rift_ile_save_checkpoint(rift_ile *h, void *buf, int64_t bytes) {
   hd.n_points = np;
   hd.proposal_bytes = sizeof(ProposalDev);
   hd.tuple_bytes = sizeof(ReduceTuple);
+  hd.coords = coords_of(h);
+  hd.reserved = 0;
   char *c = (char *)buf;
   std::memcpy(c, &hd, sizeof hd);
   c += sizeof hd;
@@ -1617,6 +1633,11 @@ rift_status rift_ile_load_checkpoint(rift_ile *h, const void *buf, int64_t bytes
       hd.proposal_bytes != (int64_t)sizeof(ProposalDev) || hd.tuple_bytes != (int64_t)sizeof(ReduceTuple) ||
       bytes < rift_ile_checkpoint_bytes(h))
     return fail(h, RIFT_E_INVALID, "checkpoint from another library version or point count");
+  // the proposals' tables live in the coordinates the sampler used: a resumed
+  // run must draw in the same ones
+  if (hd.coords != coords_of(h))
+    return fail(h, RIFT_E_INVALID, "checkpoint drawn with network frame %d, phase rotation %d; the handle has %d, %d",
+                hd.coords & 1, (hd.coords >> 1) & 1, h->net_frame ? 1 : 0, h->phase_rot ? 1 : 0);
   const char *c = (const char *)buf + sizeof hd;
   std::vector<ProposalDev> props(np);
   std::memcpy(props.data(), c, sizeof(ProposalDev) * np);

@@ -96,6 +96,7 @@ FUNCTIONS = {
     "rift_ile_graph_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "rift_ile_set_autotune": (C.c_int, [C.c_void_p, C.c_int]),
     "rift_ile_set_network_frame": (C.c_int, [C.c_void_p, C.c_int]),
+    "rift_ile_set_phase_rotation": (C.c_int, [C.c_void_p, C.c_int]),
     "rift_ile_set_grad_refine": (C.c_int, [C.c_void_p, C.c_int]),
     "rift_ile_precompute": (C.c_int, [C.POINTER(FdPoint), C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
                                       C.c_void_p]),
@@ -239,6 +240,12 @@ class RiftILE:
         the baseline of its detectors 0 and 1); the histograms of dimensions
         0 and 1 then adapt in that frame's azimuth and polar cosine."""
         self._check(lib().rift_ile_set_network_frame(self.h, int(enable)))
+
+    def set_phase_rotation(self, enable=True):
+        """Draw polarization and orbital phase in the phase-rotated
+        coordinates u_s = (phi + psi) / 4 pi, u_d = (phi - psi) / 4 pi; the
+        histograms and mixtures of dimensions 2 and 4 then adapt in those."""
+        self._check(lib().rift_ile_set_phase_rotation(self.h, int(enable)))
 
     def set_grad_refine(self, enable=True):
         """FP64 re-evaluation of the FP32 adjoint over the window blocks that

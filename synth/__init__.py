@@ -273,6 +273,19 @@ def workload(name: str) -> Workload:
         pts = [PointSpec(seed=BASE_SEED + 4 + 1000 * (i + 1), n_modes=21, n_t=820,
                          snr=float(g.uniform(10, 60))) for i in range(64)]
         return Workload(name, "fp32", pts, [1_000_000] * 64, rounds=10, adaptive=True)
+    if name == "quadrupole":   # 8 points, (2, +-2) only, SNR 25: 4 near face-on/off, 4 near edge-on
+        pts, face, edge, i = [], 0, 0, 0
+        while face < 4 or edge < 4:
+            s = PointSpec(seed=BASE_SEED + 5 + 1000 * (i + 1), n_modes=2, n_t=410, snr=25.0)
+            ci = abs(math.cos(draw_injection(s)[0][3]))
+            if ci > 0.85 and face < 4:
+                pts.append(s)
+                face += 1
+            elif ci < 0.3 and edge < 4:
+                pts.append(s)
+                edge += 1
+            i += 1
+        return Workload(name, "fp32", pts, [100_000] * 8, rounds=10, adaptive=True)
     if name == "tiny":
         s = PointSpec(seed=BASE_SEED + 10, dets=("H1", "L1", "V1"), n_modes=5, n_t=100, snr=12.0)
         return Workload(name, "fp32", [s], [4096])
@@ -289,7 +302,7 @@ def workload(name: str) -> Workload:
     raise KeyError(name)
 
 
-WORKLOADS = ("plain", "single", "batched", "grad", "adaptive", "tiny", "tiny_batched")
+WORKLOADS = ("plain", "single", "batched", "grad", "adaptive", "quadrupole", "tiny", "tiny_batched")
 
 # specs used only by the oracle's pin tests (quadratic kernel, no noise)
 PIN_SPECS = [

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 def test_host_only_calls():
     from paper_2210_07912_amd import ile
     L = ile.lib()
-    assert L.rift_ile_abi_version() == 2
+    assert L.rift_ile_abi_version() == 3
     assert L.rift_ile_status_string(0) == b"ok"
     assert L.rift_ile_status_string(-4).startswith(b"pad")
     # create rejects bad descriptors on the host, before touching a device
@@ -47,6 +47,7 @@ def test_host_only_calls():
     # handle-less calls are refused without touching a device
     assert L.rift_ile_set_autotune(None, 1) == -1
     assert L.rift_ile_set_network_frame(None, 1) == -1
+    assert L.rift_ile_set_phase_rotation(None, 1) == -1
     assert L.rift_ile_set_grad_refine(None, 1) == -1
     assert L.rift_ile_precompute(None, 0, 0, None, None, None) == -1
     assert b"NULL" in L.rift_ile_last_error(None)

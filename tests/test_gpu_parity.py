@@ -369,6 +369,87 @@ def test_marginalize_network_frame(ile, orc):
              f"n_eff {out[True]['n_eff']:.1f} ({out[True]['lnL_marg']:.4f} +- {out[True]['sigma_lnL']:.3g})")
 
 
+def _wrap_err(th, ref):
+    """|th - ref| per element, alpha, psi and phi modulo their periods."""
+    err = np.abs(th - ref)
+    for dd, per in ((0, 2 * math.pi), (2, math.pi), (4, 2 * math.pi)):
+        err[dd] = np.minimum(err[dd], per - err[dd])
+    return err
+
+
+@pytest.mark.parametrize("frame", [False, True])
+def test_sampler_phase_rotation(ile, orc, frame):
+    """Polarization and phase drawn in phase-rotated coordinates (alone and
+    with the network frame), a histogram proposal in every dimension: bins
+    exact, ln ratio and theta within one rounding of the oracle's draw (psi
+    and phi compared modulo their periods)."""
+    d = synth.make_point(synth.workload("tiny").points[0])
+    rng = np.random.default_rng(14)
+    cdf = np.zeros((7, 101))
+    cdf[:, 1:] = np.cumsum(rng.dirichlet(np.ones(100) * 0.5, size=7) * 0.9 + 0.001, axis=1)
+    cdf /= cdf[:, -1:]
+    cdf[:, -1] = 1.0
+    mask = 0b1111111
+    fr = (d["det_pos"], d["gmst"]) if frame else None
+    n, seed = 3001, 2210079130
+    oth, olr, obins, _ = orc.draw(seed, 0, 2, n, tau_width=1 / 4096, cdf=cdf, adapt_mask=mask, start=55, frame=fr,
+                                  phase=True)
+    for prec in ("fp64", "fp32"):
+        _say(f"phase-rotated sampler {prec} frame={frame}")
+        h = _handle(ile, [d], prec, tau_width=1 / 4096)
+        h.set_network_frame(frame)
+        h.set_phase_rotation(True)
+        h.set_proposal(0, cdf, mask)
+        th, lr, bins = h.sample(0, seed, 2, n, first=55)
+        th, lr, bins = th.cpu().numpy(), lr.cpu().numpy(), bins.cpu().numpy()
+        assert np.array_equal(bins, obins)
+        rel = 1e-13 if prec == "fp64" else 6e-8
+        assert np.all(np.abs(lr - olr) <= rel * np.abs(olr) + 1e-13)
+        err = _wrap_err(th, oth)
+        for dd in range(7):
+            extra = 2e-7 if prec == "fp32" and dd in (0, 1, 2, 4) else 0.0
+            assert np.all(err[dd] <= rel * np.abs(oth[dd]) + 1e-12 + extra), (dd, err[dd].max())
+        assert np.all((th[2] >= 0) & (th[2] <= math.pi)) and np.all((th[4] >= 0) & (th[4] <= 2 * math.pi))
+        h.close()
+
+
+def test_marginalize_phase_rotation(ile, orc):
+    """Adaptive marginalization in phase-rotated coordinates with the network
+    frame (FP64): the GPU run follows the oracle's run round by round (1e-6
+    on ln L_marg).  A checkpoint records the coordinates: it loads into a
+    handle with the same switches and is refused by one without; the
+    gradient refinement is refused together with the rotation."""
+    w = synth.workload("tiny_batched")
+    pts = [synth.make_point(s) for s in w.points[:2]]
+    counts = [2500, 2000]
+    seed, rounds, mask, eps = 2210079131, 3, 0x3F, 0.1
+    ops = [orc.Point.from_dict(d) for d in pts]
+    ref = _oracle_marginalize(orc, ops, seed, counts, rounds, mask, eps,
+                              frames=[(d["det_pos"], d["gmst"]) for d in pts], phase=True)
+    h = _handle(ile, pts, "fp64")
+    h.set_network_frame(True)
+    h.set_phase_rotation(True)
+    _say("phase-rotated adaptive marginalize fp64")
+    res = h.marginalize(seed, counts, n_rounds=rounds, adapt_mask=mask, floor_eps=eps)
+    for r, o in zip(res, ref):
+        _say(f"  gpu {r['lnL_marg']:.9f} oracle {o['lnL_marg']:.9f} n_eff {r['n_eff']:.1f}/{o['n_eff']:.1f}")
+        assert r["n"] == o["n"]
+        assert abs(r["lnL_marg"] - o["lnL_marg"]) < 1e-6
+    ck = h.save_checkpoint()
+    h2 = _handle(ile, pts, "fp64")
+    with pytest.raises(ile.RiftError) as e:
+        h2.load_checkpoint(ck)
+    assert e.value.status == -1 and "phase rotation" in str(e.value)
+    h2.set_network_frame(True)
+    h2.set_phase_rotation(True)
+    h2.load_checkpoint(ck)
+    with pytest.raises(ile.RiftError) as e:
+        h2.marginalize(seed, counts, n_rounds=2, adapt_mask=mask, floor_eps=eps, gradient=True)
+    assert e.value.status == -1
+    h2.close()
+    h.close()
+
+
 def test_precompute_matches_oracle(ile, orc):
     """Q, U, V of Eq. (QUV) from frequency-domain inputs (batched inverse FFT
     and weighted Gram sums on the GPU) against the oracle's direct sums: a
@@ -797,19 +878,21 @@ def test_autograd_function(ile, orc):
     assert rel.max() <= GRAD_REL + 1e-5
 
 
-def _oracle_marginalize(orc, pts, seed, counts, rounds, mask, eps, tau_width=0.0, trace=None, frames=None):
+def _oracle_marginalize(orc, pts, seed, counts, rounds, mask, eps, tau_width=0.0, trace=None, frames=None,
+                        phase=False):
     """Adaptive importance sampling composed from the oracle's pinned pieces:
     draw (Philox + histogram proposal) -> ln L_t -> ln w -> adapt, pooled over
     rounds.  trace (a list) receives (round, point, theta, lnw) for
     diagnostics; frames (per point (det_pos, gmst)) draws the sky in the
-    network frame."""
+    network frame; phase: polarization and phase in phase-rotated
+    coordinates."""
     cdf = [None] * len(pts)
     masks = [0] * len(pts)
     lnw_all = [[] for _ in pts]
     for r in range(rounds):
         for i, (p, n) in enumerate(zip(pts, counts)):
             th, lr, bins, _ = orc.draw(seed, i, r, n, tau_width=tau_width, cdf=cdf[i], adapt_mask=masks[i],
-                                       frame=None if frames is None else frames[i])
+                                       frame=None if frames is None else frames[i], phase=phase)
             lnw = orc.lnL_t(p, th) + lr
             lnw_all[i].append(lnw)
             if trace is not None:
@@ -1245,17 +1328,18 @@ def _low_box_model(gmm):
     return g
 
 
-@pytest.mark.parametrize("model", ["pairs", "low_box_mass"])
+@pytest.mark.parametrize("model", ["pairs", "low_box_mass", "pairs_phase_rotated"])
 def test_gmm_pair_draws_match_oracle(ile, orc, model):
     """Correlated pairs: rejection draws from the untruncated bivariate
     mixture, the pair density with its box mass and the kept fraction, the
     draws given up on (ln ratio -inf), against the oracle on the same
-    Philox streams."""
+    Philox streams; with the (psi, phi) pair in phase-rotated coordinates."""
     from oracle import gmm
     d = synth.make_point(synth.workload("tiny").points[0])
-    g = _pair_model(gmm) if model == "pairs" else _low_box_model(gmm)
+    g = _low_box_model(gmm) if model == "low_box_mass" else _pair_model(gmm)
+    phase = model == "pairs_phase_rotated"
     n, first, seed = 3001, 123, 2210079129
-    ref_th, ref_lr, _ = gmm.draw(seed, 0, 3, n, g, start=first)
+    ref_th, ref_lr, _ = gmm.draw(seed, 0, 3, n, g, start=first, phase=phase)
     zref = [sum(g.pw[i][k] * gmm.box_mass(g.pmu[i][k], g.pcov[i][k]) for k in range(g.K) if g.pw[i][k] > 0)
             for i in range(len(g.pairs))]
     gave_up = np.isneginf(ref_lr)
@@ -1265,6 +1349,7 @@ def test_gmm_pair_draws_match_oracle(ile, orc, model):
     for prec in ("fp64", "fp32"):
         _say(f"gmm pair draws {prec}")
         h = _handle(ile, [d], prec)
+        h.set_phase_rotation(phase)
         _set_pairs(h, 0, g)
         got = h.get_gmm_pairs(0)
         assert got["pairs"] == g.pairs
@@ -1274,11 +1359,12 @@ def test_gmm_pair_draws_match_oracle(ile, orc, model):
         assert not np.isnan(lr).any()
         assert np.array_equal(np.isneginf(lr), gave_up)
         fin = np.isfinite(ref_lr)
+        err = _wrap_err(th, ref_th)
         if prec == "fp64":
-            assert np.abs(th - ref_th).max() < 1e-9
+            assert err.max() < 1e-9
             assert np.abs(lr[fin] - ref_lr[fin]).max() < 1e-10
         else:
-            assert np.all(np.abs(th - ref_th) <= 2e-7 * np.abs(ref_th) + 1e-7)
+            assert np.all(err <= 2e-7 * np.abs(ref_th) + 1e-7)
             assert np.abs(lr[fin] - ref_lr[fin]).max() < 1e-5
         h.close()
 
