@@ -58,6 +58,7 @@ def _load(path):
     L = C.CDLL(path)
     L.or_delay.restype = C.c_double
     L.or_lnL_t.restype = C.c_double
+    L.or_lnL_tD.restype = C.c_double
     L.or_u01.restype = C.c_double
     L.or_rows.restype = C.c_int
     return L
@@ -192,6 +193,26 @@ def lnL_t(p: Point, theta):
     out = np.zeros(n)
     lib().or_lnL_t_batch(C.byref(p.s), C.c_int64(n), C.c_int64(n), _ptr(th), _ptr(out))
     return out
+
+
+def lnL_tD(p: Point, theta, d_min=10.0, d_max=1000.0, panels=0):
+    """Distance-marginalized ln L_tD: theta [7] (theta[5] not read) -> float,
+    or [7, N] -> [N] (OpenMP over samples)."""
+    th = np.asarray(theta, dtype=np.float64)
+    if th.ndim == 1:
+        return lib().or_lnL_tD(C.byref(p.s), _ptr(_theta7(th)), C.c_double(d_min), C.c_double(d_max), int(panels))
+    th = np.ascontiguousarray(th)
+    n = th.shape[1]
+    out = np.zeros(n)
+    lib().or_lnL_tD_batch(C.byref(p.s), C.c_int64(n), C.c_int64(n), _ptr(th), C.c_double(d_min), C.c_double(d_max),
+                          int(panels), _ptr(out))
+    return out
+
+
+def gauss_legendre(n):
+    x, w = np.zeros(n), np.zeros(n)
+    lib().or_gauss_legendre(int(n), _ptr(x), _ptr(w))
+    return x, w
 
 
 def grad(p: Point, theta):

@@ -323,6 +323,114 @@ void or_lnL_t_batch(const or_point *p, int64_t n, int64_t stride, const double *
 }
 
 /* ------------------------------------------------------------------------
+ * Distance marginalization (Sec. III.B, distance marginalization, and the
+ * production configuration of Sec. III that pairs it with the adaptive
+ * integrator).  The paper cites the technique without its formulas; the
+ * definition written out here is this oracle's reading:
+ *   L_tD(theta) = int_{d_min}^{d_max} p(D) (1/n_t) sum_j exp(ell_j(D)) dD,
+ *   p(D) = 3 D^2 / (d_max^3 - d_min^3)   (the sampler's distance prior),
+ * ell_j(D) the window values of Eq. (def:lnL:Decomposed) at distance D and
+ * the other six parameters of theta (theta[OR_DIST] is not read).  a_km is
+ * proportional to 1/D and B to 1/D^2, so with x = D_ref / D
+ *   ell_j(D) = x A_j - x^2 B_1,  A_j = ell_j(D_ref) + B_1,  B_1 = B(D_ref).
+ * The integral is a composite Gauss-Legendre rule of 8 nodes per panel over
+ * `panels` equal panels in ln D; the double sum over (node, j) is taken in
+ * log space with its largest term factored out.  panels <= 0 picks
+ * max(2000, 8 B_1 x_min^2 ln(d_max / d_min)) panels, x_min = D_ref / d_max:
+ * at least four panels per e-fold of the steepest factor exp(-x^2 B_1) in
+ * ln D near d_max, where a loud point's prior samples put their mass.  A
+ * node whose bound x A_max - x^2 B_1 + ln(weight) lies more than 60 below
+ * the largest is skipped (its n_t terms together are below e^-53 of it).
+ * ---------------------------------------------------------------------- */
+
+/* n-point Gauss-Legendre nodes and weights on [-1, 1]: Newton's method on
+ * the three-term recurrence of the Legendre polynomials */
+static void gauss_legendre(int n, double *x, double *w) {
+  for (int i = 0; i < (n + 1) / 2; i++) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; it++) {
+      double p0 = 1.0, p1 = 0.0;
+      for (int k = 1; k <= n; k++) {
+        double p2 = p1;
+        p1 = p0;
+        p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+      }
+      dp = n * (z * p0 - p1) / (z * z - 1.0);
+      double dz = p0 / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+void or_gauss_legendre(int n, double *x, double *w) { gauss_legendre(n, x, w); }
+
+double or_lnL_tD(const or_point *p, const double *theta, double d_min, double d_max, int panels) {
+  const int NT = p->n_t, NG = 8;
+  double th[OR_NPAR];
+  for (int d = 0; d < OR_NPAR; d++) th[d] = theta[d];
+  th[OR_DIST] = p->d_ref;
+  double *A = (double *)malloc(sizeof(double) * NT);
+  double *a = (double *)malloc(sizeof(double) * 2 * p->K * p->M);
+  double B1;
+  or_ell(p, th, A);
+  or_coeffs(p, th, a, &B1);
+  free(a);
+  double amax = -INFINITY;
+  for (int j = 0; j < NT; j++) {
+    if (isnan(A[j])) { free(A); return NAN; }
+    A[j] += B1;
+    if (A[j] > amax) amax = A[j];
+  }
+  if (panels <= 0) {
+    const double xm = p->d_ref / d_max, need = 8.0 * B1 * xm * xm * log(d_max / d_min);
+    panels = need > 2000.0 ? (int)ceil(need) : 2000;
+  }
+  double gx[8], gw[8];
+  gauss_legendre(NG, gx, gw);
+  const double s0 = log(d_min), h = (log(d_max) - s0) / panels;
+  const double norm = 3.0 / (d_max * d_max * d_max - d_min * d_min * d_min);
+  /* node i: x_i and ln of its weight h/2 w p(D) D (dD = D ds) */
+  const int NN = panels * NG;
+  double *xs = (double *)malloc(sizeof(double) * NN), *lw = (double *)malloc(sizeof(double) * NN);
+  double *top = (double *)malloc(sizeof(double) * NN);
+  double mx = -INFINITY;
+  for (int q = 0; q < panels; q++)
+    for (int g = 0; g < NG; g++) {
+      const int i = q * NG + g;
+      const double D = exp(s0 + h * (q + 0.5 + 0.5 * gx[g]));
+      xs[i] = p->d_ref / D;
+      lw[i] = log(0.5 * h * gw[g] * norm * D * D * D);
+      top[i] = xs[i] * amax - xs[i] * xs[i] * B1 + lw[i];
+      if (top[i] > mx) mx = top[i];
+    }
+  double sum = 0.0;
+  for (int i = 0; i < NN; i++) {
+    if (top[i] < mx - 60.0) continue;
+    const double c = lw[i] - xs[i] * xs[i] * B1 - mx;
+    for (int j = 0; j < NT; j++) sum += exp(xs[i] * A[j] + c);
+  }
+  free(xs);
+  free(lw);
+  free(top);
+  free(A);
+  return mx + log(sum) - log((double)NT);
+}
+
+void or_lnL_tD_batch(const or_point *p, int64_t n, int64_t stride, const double *theta, double d_min,
+                     double d_max, int panels, double *out) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < n; i++) {
+    double th[OR_NPAR];
+    for (int d = 0; d < OR_NPAR; d++) th[d] = theta[d * stride + i];
+    out[i] = or_lnL_tD(p, th, d_min, d_max, panels);
+  }
+}
+
+/* ------------------------------------------------------------------------
  * Gradient of ln L_t with respect to the seven extrinsic parameters.
  *   d lnL_t = sum_j p_j d ell_j,  p_j = softmax_j(ell_j)
  *   d ell_j = sum_k Re( sum_m conj(d a_km) Qtilde_km(j) )

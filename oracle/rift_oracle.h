@@ -68,6 +68,15 @@ void or_ell(const or_point *p, const double *theta, double *ell /*[n_t]*/);
 double or_lnL_t(const or_point *p, const double *theta);
 /* theta: [7][stride]; out[N]; OpenMP over samples */
 void or_lnL_t_batch(const or_point *p, int64_t n, int64_t stride, const double *theta, double *out);
+/* Distance-marginalized ln L_tD (theta[OR_DIST] not read): the window values
+ * ell_j(D) = x A_j - x^2 B_1 (x = D_ref / D) integrated against the prior
+ * p(D) = 3 D^2 / (d_max^3 - d_min^3) by composite 8-point Gauss-Legendre over
+ * `panels` equal panels in ln D (<= 0: a count from B_1 that resolves the
+ * steepest factor), then averaged over the window. */
+double or_lnL_tD(const or_point *p, const double *theta, double d_min, double d_max, int panels);
+void or_lnL_tD_batch(const or_point *p, int64_t n, int64_t stride, const double *theta, double d_min,
+                     double d_max, int panels, double *out);
+void or_gauss_legendre(int n, double *x, double *w);
 void or_grad(const or_point *p, const double *theta, double *lnL_t, double grad[7]);
 void or_grad_batch(const or_point *p, int64_t n, int64_t stride, const double *theta,
                    double *lnL_t, double *grad /*[7][stride]*/);
