@@ -290,10 +290,33 @@ rift_status rift_ile_set_network_frame(rift_ile *h, int enable);
  * and the adaptive histograms and mixtures of dimensions psi and phi (and the
  * bins rift_ile_sample writes) refer to u_s and u_d.  Combines with the
  * network frame.  rift_ile_marginalize returns RIFT_E_INVALID when this is on
- * together with RIFT_MC_GRADIENT.  A checkpoint records both coordinate
- * switches and loads only into a handle with the same ones.  Default off.
+ * together with RIFT_MC_GRADIENT.  A checkpoint records the coordinate
+ * switches (and distance marginalization) and loads only into a handle with
+ * the same ones.  Default off.
  * Returns RIFT_E_INVALID for a NULL handle. */
 rift_status rift_ile_set_phase_rotation(rift_ile *h, int enable);
+
+/* Distance marginalization (Sec. III.B, distance marginalization; Sec. III's
+ * production configuration pairs it with the adaptive integrator).  With
+ * enable != 0, rift_ile_lnL and rift_ile_marginalize return, in place of
+ * ln L_t, the distance-marginalized
+ *   ln L_tD = ln int p(D) (1/n_t) sum_j exp(ell_j(D)) dD,
+ *   p(D) = 3 D^2 / (d_max^3 - d_min^3) on the handle's [d_min, d_max],
+ * and theta's distance row is not read (any value, NaN included).  With
+ * x = D_ref / D every window value is x A_j - x^2 B (A_j the data term, B the
+ * quadratic term at D_ref), so each sample is evaluated once at D_ref and
+ * integrated over D by a Gauss-Legendre rule in ln x placed on the part of
+ * the prior range where the integrand's envelope is within T of its peak:
+ * 24 nodes and T = 30 nats on FP32 handles (rule error below 1e-5), 3 x 24
+ * nodes and T = 50 on FP64 handles (below 1e-10).  FP32 handles take two
+ * passes over the window (its largest data term, then the sums per node).
+ * rift_ile_marginalize then draws the six other parameters (the distance row
+ * of theta_out is a prior draw that enters no weight) and returns
+ * RIFT_E_INVALID if adapt_mask or a proposal it continues from adapts the
+ * distance, or with RIFT_MC_GRADIENT; rift_ile_backward returns
+ * RIFT_E_INVALID.  A checkpoint records the switch.  Default off.  Returns
+ * RIFT_E_INVALID for a NULL handle. */
+rift_status rift_ile_set_distance_marginalization(rift_ile *h, int enable);
 
 /* Precision of the FP32 adjoint (rift_ile_backward on an RIFT_FP32 handle).
  * The gradient of ln L_t is an average of d ell_j / d theta under the window

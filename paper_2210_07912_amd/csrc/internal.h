@@ -36,6 +36,8 @@ struct PlainArgsT {
   const R *gin;         // adjoint: upstream gradient [stride] or null (1)
   R *grad;              // adjoint: [7][stride]
   int rows_cap, nt_cap;
+  int dmarg;            // 1: distance-marginalized ln L_tD (theta's distance not read; forward only)
+  double dm_lo, dm_hi;  // the distance prior's range
 };
 
 template <typename R>
@@ -110,6 +112,11 @@ struct MfmaArgs {
   int *jrng;              // [16 max_tiles][4] or null: the samples to refine, appended in any order (count in
                           // ctl[kCtlRefine]): sorted slot, then the window blocks whose maximum is within
                           // kRefineNats of the sample's (b0 | b1 << 16, b2 | count << 16)
+  // distance marginalization (forward only): a first pass writes each slot's
+  // largest window data term, a second integrates over D
+  int dmarg;
+  float *amax;            // [16 max_tiles] base 2, by sorted slot
+  double dm_lo, dm_hi;    // the distance prior's range
   int n_bins;
   int max_item_bins;      // largest bin count of one point
   int n_sort_blocks;

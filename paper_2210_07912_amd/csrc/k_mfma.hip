@@ -35,6 +35,7 @@
 //                 max-shifted base-2 log-sum-exp.  ell_j never leaves
 //                 registers.
 #include "common.h"
+#include "dmarg.h"
 #include "internal.h"
 #include "mfma_tile.h"
 
@@ -96,7 +97,7 @@ __global__ void __launch_bounds__(kSortThreads) bin_kernel(MfmaArgs a) {
     double di = a.theta[RIFT_DIST * a.stride + col], ta = a.theta[RIFT_TAU * a.stride + col];
     SkyTrig tr = sky_trig(al, de, 0.0, p.gmst);
     Shift sh = shifts(p, tr, ta);
-    bool ok = sh.ok && isfinite(io) && isfinite(ph) && isfinite(di) && di > 0.0 &&
+    bool ok = sh.ok && isfinite(io) && isfinite(ph) && (a.dmarg || (isfinite(di) && di > 0.0)) &&
               isfinite((double)a.theta[RIFT_PSI * a.stride + col]);
     uint32_t key = 0, mul = 1;
     for (int k = 0; k < p.K; k++) {
@@ -329,7 +330,7 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
   double th[7];
 #pragma unroll
   for (int d = 0; d < 7; d++) th[d] = valid ? (double)rec.th[d] : (d == RIFT_DIST ? 1.0 : 0.0);
-  const double x = p.d_ref / th[RIFT_DIST];
+  const double x = a.dmarg ? 1.0 : p.d_ref / th[RIFT_DIST];  // distance marginalization: the terms at D_ref
   const double xl = valid ? x * kLog2e : 0.0;
   SkyTrig tr = sky_trig(th[RIFT_ALPHA], th[RIFT_DELTA], th[RIFT_PSI], p.gmst);
   double Fr[kMaxDet], Fi[kMaxDet];
@@ -454,7 +455,15 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
 //    global memory one block ahead (the four wavefronts of a unit read the
 //    same rows, so three of the four reads hit in L1), with no stage and no
 //    barrier between blocks; less LDS, so more workgroups per compute unit.
-template <int T, int K, bool DIRECT>
+// MODE 0: ln L_t.  Distance marginalization (coefficients at D = D_ref, so
+// the window values are the data terms A_j, base 2): MODE 1 writes each
+// slot's largest A_j; MODE 2 reads it back, places the slot's nodes x_i over
+// D (dmarg.h) and sums exp2(x_i (A_j - A_max)) per node over the window,
+// skipping window samples where even the smallest node's term is below
+// 2^-(T + 10) log2 e (their n_t terms together are far under the rule's
+// error), then combines the nodes in FP64.  Both passes recompute the same
+// window values bit for bit.
+template <int T, int K, bool DIRECT, int MODE>
 __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int item_hi, int cls) {
   constexpr int E = 4 * T, J = T / 4, R = T % 4;
   constexpr int JA = J > 0 ? J : 1, RA = R > 0 ? R : 1;
@@ -628,9 +637,29 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
     // out of the sums and is subtracted once at the end: the window values
     // then carry the rounding of the data term only, not of B.
     float m_run = 0.f, s_run = 0.f;
+    // distance marginalization: the slot's A_max (MODE 2 reads it), its
+    // nodes and per-node sums
+    constexpr int NQ = MODE == 2 ? kDmGL : 1;
+    float am = MODE == 1 ? -INFINITY : 0.f, skip = INFINITY, ta = 0.f, hq = 0.f;
+    float xs[NQ], Sq[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; q++) xs[q] = Sq[q] = 0.f;
+    if constexpr (MODE == 2) {
+      const float av = active ? a.amax[(int64_t)t * kTS + s] : 0.f;
+      if (valid && isfinite(av)) {
+        am = av;
+        const float tlo = logf((float)(p.d_ref / a.dm_hi)), thi = logf((float)(p.d_ref / a.dm_lo));
+        float tb;
+        dm_interval<float>(av * kLn2f, Bf * kLn2f, tlo, thi, (float)DmRule<float>::T, 24, ta, tb);
+        hq = tb - ta;
+#pragma unroll
+        for (int q = 0; q < NQ; q++) xs[q] = expf(ta + hq * (float)(0.5 + 0.5 * dm_gl_node(q)));
+        skip = -(float)((DmRule<float>::T + 10.0) * kLog2e) / xs[0];
+      }
+    }
     auto window = [&](auto sl_c, bool last, bool first) {
       constexpr int SL = decltype(sl_c)::value;
-      const float base = -m_run;
+      const float base = MODE == 0 ? -m_run : 0.f;
       float ell[4];
 #pragma unroll
       for (int i = 0; i < 4; i++) ell[i] = last ? base + last_pen[i] : base;
@@ -649,16 +678,33 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
         }
       }
       const float cmax = fmaxf(fmaxf(ell[0], ell[1]), fmaxf(ell[2], ell[3]));
-      if ((first || cmax > 64.f) && cmax > -3.0e38f) {  // rare after the first block
-        // (the first block starts from an empty sum; its maximum can be far
-        // below zero, where exp2(-cmax) would overflow)
-        s_run = first ? 0.f : s_run * __builtin_amdgcn_exp2f(-cmax);
-        m_run += cmax;
+      if constexpr (MODE == 1) {
+        am = fmaxf(am, cmax);
+      } else if constexpr (MODE == 2) {
+        float d[4];
 #pragma unroll
-        for (int i = 0; i < 4; i++) ell[i] -= cmax;
+        for (int i = 0; i < 4; i++) d[i] = ell[i] - am;
+        if (fmaxf(fmaxf(d[0], d[1]), fmaxf(d[2], d[3])) >= skip) {
+#pragma unroll
+          for (int q = 0; q < NQ; q++) {
+            float e = 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; i++) e += __builtin_amdgcn_exp2f(xs[q] * d[i]);
+            Sq[q] += e;
+          }
+        }
+      } else {
+        if ((first || cmax > 64.f) && cmax > -3.0e38f) {  // rare after the first block
+          // (the first block starts from an empty sum; its maximum can be far
+          // below zero, where exp2(-cmax) would overflow)
+          s_run = first ? 0.f : s_run * __builtin_amdgcn_exp2f(-cmax);
+          m_run += cmax;
+#pragma unroll
+          for (int i = 0; i < 4; i++) ell[i] -= cmax;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++) s_run += __builtin_amdgcn_exp2f(ell[i]);
       }
-#pragma unroll
-      for (int i = 0; i < 4; i++) s_run += __builtin_amdgcn_exp2f(ell[i]);
     };
     using C0 = std::integral_constant<int, 0>;
     using C2 = std::integral_constant<int, 2>;
@@ -715,7 +761,46 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
       if (b <= JB) pair(C0{}, b);
       if (b + 2 <= JB) pair(C2{}, b + 2);
     }
-    if (active) {
+    if (active && MODE == 1) {
+      // the slot's largest data term over the four lanes of the sample
+      float mo = am;
+      mo = fmaxf(mo, __shfl_xor(mo, 16));
+      mo = fmaxf(mo, __shfl_xor(mo, 32));
+      if (g == 0) gpw(a.amax)[(int64_t)t * kTS + s] = valid ? mo : NAN;
+    } else if (active && MODE == 2) {
+      // per-node sums over the four lanes, then the nodes in FP64:
+      // ln L_tD = ln sum_i W_i exp(x_i A_max - x_i^2 B) S_i - ln n_t (nats)
+#pragma unroll
+      for (int q = 0; q < NQ; q++) {
+        Sq[q] += __shfl_xor(Sq[q], 16);
+        Sq[q] += __shfl_xor(Sq[q], 32);
+      }
+      float lt = NAN;
+      if (valid && g == 0 && hq > 0.f) {
+        const double A = (double)am * (double)kLn2f, Bv = (double)Bf * (double)kLn2f;
+        const double c = 3.0 * p.d_ref * p.d_ref * p.d_ref / (a.dm_hi * a.dm_hi * a.dm_hi - a.dm_lo * a.dm_lo * a.dm_lo);
+        const double lc = log(0.5 * (double)hq * c);
+        double cmax = -INFINITY, acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; q++) {
+          const double tq = (double)(ta + hq * (float)(0.5 + 0.5 * dm_gl_node(q)));
+          const double xd = (double)xs[q];
+          const double ci = lc + log(dm_gl_weight(q)) - 3.0 * tq + xd * A - xd * xd * Bv + log((double)Sq[q]);
+          if (ci > cmax) {
+            acc = acc * exp(cmax - ci) + 1.0;
+            cmax = ci;
+          } else {
+            acc += exp(ci - cmax);
+          }
+        }
+        lt = (float)(cmax + log(acc) - log((double)NT));
+      }
+      if (!isfinite(lt)) lt = NAN;
+      if (flag != 0 && g == 0) {
+        if (a.lnL) gpw(a.lnL)[col] = lt;
+        if (a.lnw) gpw(a.lnw)[col] = lt + (a.ln_ratio ? gp(a.ln_ratio)[col] : 0.f);
+      }
+    } else if (active) {
       // combine the four lanes of each sample (base 2), then ln L_t
       float mo = m_run;
       mo = fmaxf(mo, __shfl_xor(mo, 16));
@@ -734,35 +819,41 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
 }
 
 // persistent grid: as many workgroups as the device keeps resident
-template <int T, int K, bool D>
+template <int T, int K, bool D, int MODE>
 static void launch_tk(const MfmaArgs &a, int lo, int hi, int cls, hipStream_t st) {
   static int per_cu = 0;
   if (per_cu == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mfma_kernel<T, K, D>, 256, 0) != hipSuccess || nb < 1) nb = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mfma_kernel<T, K, D, MODE>, 256, 0) != hipSuccess || nb < 1)
+      nb = 1;
     per_cu = nb;
   }
   const int grid = std::max(1, a.grid / 4 * per_cu);  // a.grid = 4 per compute unit
-  hipLaunchKernelGGL((mfma_kernel<T, K, D>), dim3(grid), dim3(256), 0, st, a, lo, hi, cls);
+  hipLaunchKernelGGL((mfma_kernel<T, K, D, MODE>), dim3(grid), dim3(256), 0, st, a, lo, hi, cls);
 }
 
+// pass: 0 ln L_t (staged or direct feed); 1, 2 the passes of distance
+// marginalization (staged feed)
 template <int T, int K>
-static void launch_tkm(const MfmaArgs &a, bool direct, int lo, int hi, int cls, hipStream_t st) {
-  if (direct) launch_tk<T, K, true>(a, lo, hi, cls, st);
-  else launch_tk<T, K, false>(a, lo, hi, cls, st);
+static void launch_tkm(const MfmaArgs &a, bool direct, int pass, int lo, int hi, int cls, hipStream_t st) {
+  if (pass == 1) launch_tk<T, K, false, 1>(a, lo, hi, cls, st);
+  else if (pass == 2) launch_tk<T, K, false, 2>(a, lo, hi, cls, st);
+  else if (direct) launch_tk<T, K, true, 0>(a, lo, hi, cls, st);
+  else launch_tk<T, K, false, 0>(a, lo, hi, cls, st);
 }
 
 template <int T>
-static void launch_class(const MfmaArgs &a, int K, bool direct, int lo, int hi, int cls, hipStream_t st) {
-  if (K == 1) launch_tkm<T, 1>(a, direct, lo, hi, cls, st);
-  else if (K == 2) launch_tkm<T, 2>(a, direct, lo, hi, cls, st);
-  else launch_tkm<T, 3>(a, direct, lo, hi, cls, st);
+static void launch_class(const MfmaArgs &a, int K, bool direct, int pass, int lo, int hi, int cls, hipStream_t st) {
+  if (K == 1) launch_tkm<T, 1>(a, direct, pass, lo, hi, cls, st);
+  else if (K == 2) launch_tkm<T, 2>(a, direct, pass, lo, hi, cls, st);
+  else launch_tkm<T, 3>(a, direct, pass, lo, hi, cls, st);
 }
 
-static hipError_t launch_mode(const MfmaArgs &a, int T, int K, bool direct, int lo, int hi, int cls, hipStream_t st) {
+static hipError_t launch_mode(const MfmaArgs &a, int T, int K, bool direct, int lo, int hi, int cls, hipStream_t st,
+                              int pass = 0) {
   switch (T) {
 #define RIFT_T_CASE(TT) \
-  case TT: launch_class<TT>(a, K, direct, lo, hi, cls, st); break;
+  case TT: launch_class<TT>(a, K, direct, pass, lo, hi, cls, st); break;
     RIFT_T_CASE(1) RIFT_T_CASE(2) RIFT_T_CASE(3) RIFT_T_CASE(4) RIFT_T_CASE(5) RIFT_T_CASE(6) RIFT_T_CASE(7)
     RIFT_T_CASE(8) RIFT_T_CASE(9) RIFT_T_CASE(10) RIFT_T_CASE(11) RIFT_T_CASE(12) RIFT_T_CASE(13)
     RIFT_T_CASE(14) RIFT_T_CASE(15) RIFT_T_CASE(16)
@@ -831,7 +922,7 @@ hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_
   hipError_t e = mfma_prepare(a, mclass_M, mclass_item0, mclass_tiles, n_mclasses, st);
   if (e != hipSuccess) return e;
   uint64_t done = 0;  // classes evaluated while being measured
-  if (tune)
+  if (tune && !a.dmarg)
     for (int c = 0; c < n_classes && c < 64; c++)
       if (class_mode[c] == 0) {
         e = tune_class(a, class_T[c], class_K[c], class_item0[c], class_item0[c + 1], c, st, class_mode[c]);
@@ -839,6 +930,27 @@ hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_
         done |= 1ull << c;
       }
   if (ev0) (void)hipEventRecord(ev0, st);
+  if (a.dmarg) {
+    // distance marginalization: every class's largest data terms, then (the
+    // work-unit counters cleared by a fill kernel) the integrals over D
+    for (int pass = 1; pass <= 2; pass++) {
+      if (pass == 2) {
+        e = fill_u32(a.ctl + 1, n_classes, 0u, st);
+        if (e != hipSuccess) return e;
+      }
+      fan_fork(fo, st, n_classes);
+      for (int c = 0; c < n_classes; c++) {
+        e = launch_mode(a, class_T[c], class_K[c], false, class_item0[c], class_item0[c + 1], c,
+                        fan_stream(fo, st, c), pass);
+        if (e != hipSuccess) return e;
+      }
+      e = hipGetLastError();
+      fan_join(fo, st, n_classes);
+      if (e != hipSuccess) return e;
+    }
+    if (ev1) (void)hipEventRecord(ev1, st);
+    return e;
+  }
   fan_fork(fo, st, n_classes);
   for (int c = 0; c < n_classes; c++) {
     if (c < 64 && (done >> c) & 1) continue;

@@ -14,10 +14,14 @@
 //   3. ln L_t = max-shifted log-sum-exp over j minus ln n_t (App. D.2); the
 //      window sums hold the data term only, and B (the same for every j) is
 //      subtracted once at the end, so the sums carry no rounding of B.
+// With distance marginalization the prologue takes x = 1 (D = D_ref), so the
+// window holds the data terms A_j, and step 3 integrates over D by the
+// per-sample rule of dmarg.h (in FP64 for the weights, the sums over j in R).
 // The adjoint recomputes ell_j, forms p_j = exp(ell_j - ln L_t - ln n_t) and
 // the detector sums G_k = sum_j p_j Qtilde_k(j), H_k = sum_j p_j Re(a^dag
 // Qtilde'_k(j)), and applies the chain rule through F, Y, D and the delays.
 #include "common.h"
+#include "dmarg.h"
 #include "internal.h"
 
 namespace rift {
@@ -85,9 +89,9 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgsT<R> args) {
       for (int d = 0; d < 7; d++) th[d] = (double)args.theta[d * args.stride + i];
       SkyTrig tr = sky_trig(th[RIFT_ALPHA], th[RIFT_DELTA], th[RIFT_PSI], p.gmst);
       Shift sh = shifts(p, tr, th[RIFT_TAU]);
-      ok = sh.ok && isfinite(th[RIFT_IOTA]) && isfinite(th[RIFT_PHI]) && th[RIFT_DIST] > 0.0 &&
-           isfinite(th[RIFT_DIST]);
-      double x = p.d_ref / th[RIFT_DIST];
+      ok = sh.ok && isfinite(th[RIFT_IOTA]) && isfinite(th[RIFT_PHI]) &&
+           (args.dmarg || (th[RIFT_DIST] > 0.0 && isfinite(th[RIFT_DIST])));
+      double x = args.dmarg ? 1.0 : p.d_ref / th[RIFT_DIST];
       double ci, si, cph, sph;
       sincos(0.5 * th[RIFT_IOTA], &si, &ci);
       sincos(th[RIFT_PHI], &sph, &cph);
@@ -266,6 +270,36 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgsT<R> args) {
       // same for every window sample and is subtracted once, in FP64
       const R lse = mx + r_log<R>(sum);
       R lt = (R)((double)lse - Bs[s] - log((double)NT));
+      if (!BWD && args.dmarg) {
+        // over D: nodes x_i on the envelope's interval, S_i = sum_j exp(x_i (A_j - A_max)) in R,
+        // the weighted sum over nodes in FP64 (online log-sum-exp)
+        using DR = DmRule<R>;
+        const double A = (double)mx, Bv = Bs[s];
+        const double tlo = log(p.d_ref / args.dm_hi), thi = log(p.d_ref / args.dm_lo);
+        double ta, tb;
+        dm_interval<double>(A, Bv, tlo, thi, DR::T, 60, ta, tb);
+        const double c = 3.0 * p.d_ref * p.d_ref * p.d_ref /
+                         (args.dm_hi * args.dm_hi * args.dm_hi - args.dm_lo * args.dm_lo * args.dm_lo);
+        const double h = (tb - ta) / DR::P;
+        double cmax = -INFINITY, acc = 0.0;
+        for (int pp = 0; pp < DR::P; pp++)
+          for (int q = 0; q < kDmGL; q++) {
+            const double t = ta + h * (pp + 0.5 + 0.5 * dm_gl_node(q));
+            const R xr = (R)exp(t);
+            R sq = R(0);
+            for (int j = g; j < NT; j += G) sq += r_exp<R>(xr * (lbuf[s * args.nt_cap + j] - mx));
+            for (int o = G / 2; o > 0; o >>= 1) sq += __shfl_xor(sq, o, G);
+            const double xd = (double)xr;
+            const double ci = log(0.5 * h * dm_gl_weight(q) * c) - 3.0 * t + xd * A - xd * xd * Bv + log((double)sq);
+            if (ci > cmax) {
+              acc = acc * exp(cmax - ci) + 1.0;
+              cmax = ci;
+            } else {
+              acc += exp(ci - cmax);
+            }
+          }
+        lt = (R)(cmax + log(acc) - log((double)NT));
+      }
       bool ok = okv[s] && isfinite((double)lt);
       if (!ok) lt = R(NAN);
       if (g == 0) {

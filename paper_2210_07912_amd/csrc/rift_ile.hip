@@ -62,6 +62,7 @@ struct rift_ile {
   // sky drawn in each point's network frame (rift_ile_set_network_frame)
   bool net_frame = false;
   bool phase_rot = false;  // polarization and phase in phase-rotated coordinates
+  bool dmarg = false;      // distance-marginalized ln L_tD (theta's distance not read)
   // how each (T, K) class feeds the matrix cores: 0 not measured, 1 staged, 2
   // direct; feed: 1 measure on first use, 0 all staged, 2 all direct
   int feed = 1;
@@ -82,7 +83,7 @@ enum WsId {
   W_ITEM_POINT, W_ITEM_OFF, W_ITEM_CNT, W_ITEM_TILE0, W_ITEM_SAMP0, W_ITEM_BIN0,
   W_KEY, W_NSH, W_COUNT, W_CURSOR, W_COP, W_BINTILE, W_ITEMTILES, W_PERM, W_TILES, W_CTL, W_CTILE,
   W_PARTIALS, W_ROUND, W_ACCUM, W_RESULT, W_HIST, W_THETA, W_LNW, W_AUX, W_RATIO, W_BINS, W_ITEM_BLK0,
-  W_ITEM_HOFF, W_ITEM_COP, W_SEG_OFF, W_SEG_CNT, W_ASC, W_AHIST, W_UNIT, W_BINUNIT, W_ITEMUNITS, W_GOP, W_HOP, W_SEG_BLK, W_UBUF, W_EMPART, W_EMPART2, W_GMMFIT, W_EMWT, W_JRNG, W_COUNT_IDS
+  W_ITEM_HOFF, W_ITEM_COP, W_SEG_OFF, W_SEG_CNT, W_ASC, W_AHIST, W_UNIT, W_BINUNIT, W_ITEMUNITS, W_GOP, W_HOP, W_SEG_BLK, W_UBUF, W_EMPART, W_EMPART2, W_GMMFIT, W_EMWT, W_JRNG, W_AMAX, W_COUNT_IDS
 };
 static_assert(W_COUNT_IDS <= 48, "workspace table too small");
 
@@ -465,6 +466,9 @@ rift_status run_plain(rift_ile *h, const Items &it, int64_t stride, const R *the
   a.grad = grad;
   a.rows_cap = h->max_L;
   a.nt_cap = h->max_nt;
+  a.dmarg = h->dmarg && !bwd ? 1 : 0;
+  a.dm_lo = h->d_min;
+  a.dm_hi = h->d_max;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (h->prof) {
     HIPCHK(h, hipEventCreate(&e0));
@@ -655,6 +659,13 @@ rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const f
     a.gin = gin;
     a.grad = grad;
   }
+  if (h->dmarg && !grad) {  // distance marginalization: each slot's largest data term
+    if ((s = ws_get(h, W_AMAX, sizeof(float) * 16 * (size_t)max_tiles, &p)) != RIFT_OK) return s;
+    a.amax = (float *)p;
+    a.dmarg = 1;
+    a.dm_lo = h->d_min;
+    a.dm_hi = h->d_max;
+  }
   if ((s = ws_get(h, W_ITEM_COP, sizeof(int64_t) * (size_t)ni, &p)) != RIFT_OK) return s;
   a.item_cop = (int64_t *)p;
   if ((s = ws_get(h, W_CTILE, sizeof(CoefTile) * (size_t)max_tiles, &p)) != RIFT_OK) return s;
@@ -726,7 +737,8 @@ rift_status run_mfma(rift_ile *h, const Items &it_in, int64_t stride, const floa
     const PointDev &p = h->hp[it_in.point[oi]];
     int64_t remaining = it_in.cnt[oi], off = it_in.off[oi];
     while (remaining > 0) {
-      const double per = 4.0 + 8.0 + 44.0 + 40.0 + (double)p.K * 2 * p.Mp * 4 * 1.1 * (grad ? 2.0 : 1.0);
+      const double per = 4.0 + 8.0 + 44.0 + 40.0 + (double)p.K * 2 * p.Mp * 4 * 1.1 * (grad ? 2.0 : 1.0) +
+                         (h->dmarg ? 4.4 : 0.0);
       int64_t take = remaining;
       if (used + per * take > budget) {
         if (!grp.point.empty()) {
@@ -831,6 +843,42 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
   const int64_t total = per_round * mc->n_rounds;
   const int64_t nr = std::max<int64_t>(per_round, 1);
   rift_status s;
+  // every argument is checked before the handle's state changes
+  // gradient-informed refinement: ascent set of k points per point
+  const bool grad = (mc->flags & RIFT_MC_GRADIENT) && mc->adapt_mask;
+  const int ka = mc->n_ascent > 0 ? mc->n_ascent : 64;
+  const int steps = mc->ascent_steps > 0 ? mc->ascent_steps : 12;
+  const double beta = mc->ascent_mix > 0.0 ? mc->ascent_mix : 0.3;
+  if (grad && (ka > 256 || !(beta + mc->floor_eps < 1.0)))
+    return fail(h, RIFT_E_INVALID, "n_ascent %d (<= 256) or ascent_mix %g (< 1 - floor_eps)", ka, beta);
+  // the ascent places its points in the histograms by the prior-CDF
+  // coordinates of (psi, phi), which the four-to-one phase rotation does not
+  // give back
+  if (grad && h->phase_rot)
+    return fail(h, RIFT_E_INVALID, "the gradient refinement is not combined with phase-rotated coordinates");
+  // with distance marginalization D is integrated per sample, not sampled:
+  // no proposal over it, and no adjoint for the ascent
+  if (h->dmarg && (grad || ((mc->adapt_mask >> RIFT_DIST) & 1u)))
+    return fail(h, RIFT_E_INVALID, "distance marginalization: adapt_mask must leave out the distance (bit %d) and "
+                "the gradient refinement is not available", RIFT_DIST);
+  // Gaussian-mixture proposal: prior-CDF coordinates of every sample, EM sums
+  // and the mixtures being fitted
+  const int gk = mc->gmm_components;
+  const int giter = mc->gmm_iters > 0 ? mc->gmm_iters : 10;
+  if (gk < 0 || gk > kMaxG || mc->gmm_iters < 0 || mc->gmm_iters > 1000 || (gk > 0 && grad))
+    return fail(h, RIFT_E_INVALID, "gmm_components %d (0..%d), gmm_iters %d (0..1000), or both a mixture and the "
+                "gradient refinement", gk, kMaxG, mc->gmm_iters);
+  if ((s = check_pairs(h, mc->gmm_pairs, mc->adapt_mask)) != RIFT_OK) return s;
+  if (mc->gmm_pairs && gk == 0) return fail(h, RIFT_E_INVALID, "correlated pairs need gmm_components > 0");
+  if (h->dmarg && !mc->reset_proposal) {
+    // the proposals a run continues from must leave the distance to the prior
+    std::vector<ProposalDev> props(np);
+    HIPCHK(h, hipMemcpyAsync(props.data(), h->d_props, sizeof(ProposalDev) * np, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int p = 0; p < np; p++)
+      if ((props[p].mask >> RIFT_DIST) & 1u)
+        return fail(h, RIFT_E_INVALID, "distance marginalization: the proposal of point %d adapts the distance", p);
+  }
   if (mc->reset_proposal) {
     std::vector<ProposalDev> props(np);
     for (auto &p : props) uniform_proposal(p);
@@ -859,27 +907,6 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
   int *d_sblk;
   if ((s = upload(h, W_SEG_BLK, sblk, &d_sblk)) != RIFT_OK) return s;
   const int64_t th_stride = theta_out ? total : nr;
-  // gradient-informed refinement: ascent set of k points per point
-  const bool grad = (mc->flags & RIFT_MC_GRADIENT) && mc->adapt_mask;
-  const int ka = mc->n_ascent > 0 ? mc->n_ascent : 64;
-  const int steps = mc->ascent_steps > 0 ? mc->ascent_steps : 12;
-  const double beta = mc->ascent_mix > 0.0 ? mc->ascent_mix : 0.3;
-  if (grad && (ka > 256 || !(beta + mc->floor_eps < 1.0)))
-    return fail(h, RIFT_E_INVALID, "n_ascent %d (<= 256) or ascent_mix %g (< 1 - floor_eps)", ka, beta);
-  // the ascent places its points in the histograms by the prior-CDF
-  // coordinates of (psi, phi), which the four-to-one phase rotation does not
-  // give back
-  if (grad && h->phase_rot)
-    return fail(h, RIFT_E_INVALID, "the gradient refinement is not combined with phase-rotated coordinates");
-  // Gaussian-mixture proposal: prior-CDF coordinates of every sample, EM sums
-  // and the mixtures being fitted
-  const int gk = mc->gmm_components;
-  const int giter = mc->gmm_iters > 0 ? mc->gmm_iters : 10;
-  if (gk < 0 || gk > kMaxG || mc->gmm_iters < 0 || mc->gmm_iters > 1000 || (gk > 0 && grad))
-    return fail(h, RIFT_E_INVALID, "gmm_components %d (0..%d), gmm_iters %d (0..1000), or both a mixture and the "
-                "gradient refinement", gk, kMaxG, mc->gmm_iters);
-  if ((s = check_pairs(h, mc->gmm_pairs, mc->adapt_mask)) != RIFT_OK) return s;
-  if (mc->gmm_pairs && gk == 0) return fail(h, RIFT_E_INVALID, "correlated pairs need gmm_components > 0");
   const bool gmm = gk > 0 && mc->adapt_mask;
   float *ubuf = nullptr;
   double *em_part = nullptr, *em_part2 = nullptr, *em_wt = nullptr;
@@ -1251,6 +1278,12 @@ rift_status rift_ile_set_phase_rotation(rift_ile *h, int enable) {
   return RIFT_OK;
 }
 
+rift_status rift_ile_set_distance_marginalization(rift_ile *h, int enable) {
+  if (!h) return RIFT_E_INVALID;
+  h->dmarg = enable != 0;
+  return RIFT_OK;
+}
+
 rift_status rift_ile_set_grad_refine(rift_ile *h, int enable) {
   if (!h) return RIFT_E_INVALID;
   h->refine = enable != 0;
@@ -1590,9 +1623,12 @@ struct CkptHeader {
   char magic[8];
   int32_t version, n_points;
   int64_t proposal_bytes, tuple_bytes;
-  int32_t coords, reserved;  // coordinates the proposals refer to: bit 0 network frame, bit 1 phase rotation
+  int32_t coords, reserved;  // what the proposals and estimates refer to: bit 0 network frame, bit 1 phase
+                             // rotation, bit 2 distance marginalization
 };
-int32_t coords_of(const rift_ile *h) { return (h->net_frame ? 1 : 0) | (h->phase_rot ? 2 : 0); }
+int32_t coords_of(const rift_ile *h) {
+  return (h->net_frame ? 1 : 0) | (h->phase_rot ? 2 : 0) | (h->dmarg ? 4 : 0);
+}
 constexpr char kCkptMagic[8] = {'R', 'I', 'F', 'T', 'C', 'K', 'P', '1'};
 
 int64_t rift_ile_checkpoint_bytes(const rift_ile *h) {
@@ -1636,8 +1672,9 @@ rift_status rift_ile_load_checkpoint(rift_ile *h, const void *buf, int64_t bytes
   // the proposals' tables live in the coordinates the sampler used: a resumed
   // run must draw in the same ones
   if (hd.coords != coords_of(h))
-    return fail(h, RIFT_E_INVALID, "checkpoint drawn with network frame %d, phase rotation %d; the handle has %d, %d",
-                hd.coords & 1, (hd.coords >> 1) & 1, h->net_frame ? 1 : 0, h->phase_rot ? 1 : 0);
+    return fail(h, RIFT_E_INVALID, "checkpoint drawn with network frame %d, phase rotation %d, distance "
+                "marginalization %d; the handle has %d, %d, %d", hd.coords & 1, (hd.coords >> 1) & 1,
+                (hd.coords >> 2) & 1, h->net_frame ? 1 : 0, h->phase_rot ? 1 : 0, h->dmarg ? 1 : 0);
   const char *c = (const char *)buf + sizeof hd;
   std::vector<ProposalDev> props(np);
   std::memcpy(props.data(), c, sizeof(ProposalDev) * np);
@@ -1696,6 +1733,7 @@ rift_status rift_ile_marginalize(rift_ile *h, const rift_ile_mc *mc, rift_ile_re
 rift_status rift_ile_backward(rift_ile *h, int n_items, const rift_ile_item *items, int64_t stride, const void *theta,
                               const void *grad_lnL_t, void *grad_theta, void *lnL_t_out) {
   if (!h) return RIFT_E_INVALID;
+  if (h->dmarg) return fail(h, RIFT_E_INVALID, "no adjoint of the distance-marginalized likelihood");
   rift_status s = check_items(h, n_items, items, stride);
   if (s != RIFT_OK) return s;
   if (n_items > 0 && stride > 0 && (!theta || !grad_theta)) return fail(h, RIFT_E_INVALID, "NULL theta or grad");

@@ -97,6 +97,7 @@ FUNCTIONS = {
     "rift_ile_set_autotune": (C.c_int, [C.c_void_p, C.c_int]),
     "rift_ile_set_network_frame": (C.c_int, [C.c_void_p, C.c_int]),
     "rift_ile_set_phase_rotation": (C.c_int, [C.c_void_p, C.c_int]),
+    "rift_ile_set_distance_marginalization": (C.c_int, [C.c_void_p, C.c_int]),
     "rift_ile_set_grad_refine": (C.c_int, [C.c_void_p, C.c_int]),
     "rift_ile_precompute": (C.c_int, [C.POINTER(FdPoint), C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
                                       C.c_void_p]),
@@ -246,6 +247,11 @@ class RiftILE:
         coordinates u_s = (phi + psi) / 4 pi, u_d = (phi - psi) / 4 pi; the
         histograms and mixtures of dimensions 2 and 4 then adapt in those."""
         self._check(lib().rift_ile_set_phase_rotation(self.h, int(enable)))
+
+    def set_distance_marginalization(self, enable=True):
+        """lnL and marginalize return ln L_tD, integrated over the distance
+        prior p(D) ~ D^2 on [d_min, d_max]; theta's distance is not read."""
+        self._check(lib().rift_ile_set_distance_marginalization(self.h, int(enable)))
 
     def set_grad_refine(self, enable=True):
         """FP64 re-evaluation of the FP32 adjoint over the window blocks that
