@@ -400,6 +400,29 @@ def main():
         out["single_point"] = {k: s[k] for k in ("value", "ms_per_step", "roofline", "launch", "lnL_marg")}
         out["grad"] = measure_grad(10, 2, with_errors=not args.no_fp64)
 
+    # distance marginalization on the same step (ln L_tD in place of ln L_t:
+    # each sample evaluated at D_ref, its largest data term, then 24 nodes in
+    # D): its rate against the step's, measured on the same handle
+    if fp32 and not args.n and not args.no_extras and name in ("batched", "single"):
+        h.set_distance_marginalization(True)
+        h.set_graph(not args.no_graph)
+        rounds = m["rounds"]
+        nd = max(1, min(args.steps, 5))
+        for i in range(max(1, min(args.warmup, 2))):
+            h.marginalize(seed + i, counts, n_rounds=rounds, adapt_mask=0, floor_eps=0.1)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for i in range(nd):
+            r = h.marginalize(seed + 100 + i, counts, n_rounds=rounds, adapt_mask=0, floor_eps=0.1)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        h.set_distance_marginalization(False)
+        h.set_graph(False)
+        ddt = (t3 - t2) / nd
+        out["distance_marginalization"] = {"evals_per_s": m["evals_per_step"] / ddt, "ms_per_step": ddt * 1e3,
+                                           "steps": nd, "cost_vs_time_only": ddt * 1e3 / m["ms_per_step"],
+                                           "lnL_marg": [x["lnL_marg"] for x in r][:4]}
+
     # the Q/U/V precompute at the single-point shape: 3 detectors, 21 modes,
     # 8 s at 4096 Hz (N = 32768), the 999 stored rows; host arrays in and out
     if name == "single" and not args.n and not args.no_extras:
@@ -447,6 +470,32 @@ def main():
             hs.close()
             coords[sname] = cc
         out["coordinates"] = {"rounds": 10, "floor_eps": 0.1, **coords}
+        # distance marginalization in the adaptive runs: all six angles and
+        # the distance adapted (no marginalization) against the distance
+        # integrated per sample with the five angles adapted, and with the
+        # sky alone adapted (the production setting of Sec. III), on the
+        # first 8 points and the 8 loudest; 10 rounds of 1e5 samples
+        loud = sorted(range(len(w.points)), key=lambda i: -w.points[i].snr)[:8]
+        dm = {}
+        for sname, idx in (("first8", list(range(8))), ("loudest8", loud)):
+            hs = ile.RiftILE([pts[i] for i in idx], precision=w.precision, tau_width=w.tau_width)
+            cc = {"points": idx, "snr": [round(w.points[i].snr, 2) for i in idx]}
+            for nm, dmarg, amask in (("sampled_D_adapt_all", False, 0x3F), ("dmarg_adapt_angles", True, 0x1F),
+                                     ("dmarg_adapt_sky", True, 0x03)):
+                hs.set_distance_marginalization(dmarg)
+                hs.marginalize(seed + 30, 100_000, n_rounds=1, adapt_mask=amask, floor_eps=0.1)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                r = hs.marginalize(seed + 31, 100_000, n_rounds=10, adapt_mask=amask, floor_eps=0.1)
+                torch.cuda.synchronize()
+                t3 = time.perf_counter()
+                ne = np.array([x["n_eff"] for x in r])
+                cc[nm] = {"ms": (t3 - t2) * 1e3, "n_eff": ne.tolist(), "n_eff_geomean": float(np.exp(np.log(ne).mean())),
+                          "sigma_lnL": [x["sigma_lnL"] for x in r], "lnL_marg": [x["lnL_marg"] for x in r]}
+            hs.close()
+            dm[sname] = cc
+        out["distance_marginalization_adaptive"] = {"rounds": 10, "samples_per_round": 100_000, "floor_eps": 0.1,
+                                                    **dm}
         sub = pts[:8]
         hs = ile.RiftILE(sub, precision=w.precision, tau_width=w.tau_width)
         gm = {}

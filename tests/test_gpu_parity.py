@@ -7,9 +7,9 @@ interpolation and log-sum-exp run in FP32 with FP32 accumulation, while the
 per-sample prologue (geometry, harmonics, B) runs in FP64.  With |z| terms
 of order |ell| + 2B summed over K detectors, 4 taps and up to 2M products,
 the rounding error per sample is bounded by a few FP32 ulps of that
-magnitude: |d lnL_t| <= 2e-4 + 4e-6 (|lnL_t| + B) (the test checks the
-looser form with B folded into |lnL_t| + 1e3).  The estimate ln L_marg must
-agree to 1e-3.  FP64 handles: 1e-9 relative.
+magnitude: |d lnL_t| <= 2e-6 + 2 2^-24 (|lnL_t| + 2B) sqrt(8 K M), B the
+oracle's quadratic term of the sample (_fp32_tol).  The estimate ln L_marg
+must agree to 1e-3.  FP64 handles: 1e-9 relative.
 """
 import math
 import os
