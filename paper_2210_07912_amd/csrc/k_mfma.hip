@@ -100,13 +100,15 @@ __global__ void __launch_bounds__(kSortThreads) bin_kernel(MfmaArgs a) {
     bool ok = sh.ok && isfinite(io) && isfinite(ph) && (a.dmarg || (isfinite(di) && di > 0.0)) &&
               isfinite((double)a.theta[RIFT_PSI * a.stride + col]);
     uint32_t key = 0, mul = 1;
+    uint32_t nw[2] = {0u, ok ? 1u << 16 : 0u};  // the four int16 of the sample, one 8-byte store
     for (int k = 0; k < p.K; k++) {
       int q = ok ? (sh.n[k] + p.pad) / p.bin_w : 0;
       key += q * mul;
       mul *= p.nq;
-      a.nsh[f * 4 + k] = (int16_t)(ok ? sh.n[k] : 0);
+      const uint32_t v = (uint16_t)(int16_t)(ok ? sh.n[k] : 0);
+      nw[k >> 1] |= (k & 1) ? v << 16 : v;
     }
-    a.nsh[f * 4 + 3] = ok ? 1 : 0;
+    *(uint2 *)(a.nsh + f * 4) = make_uint2(nw[0], nw[1]);
     a.key[f] = key;
     atomicAdd(&cnt[key], 1u);
   }
@@ -249,10 +251,11 @@ __global__ void __launch_bounds__(kSortThreads) scatter_kernel(MfmaArgs a) {
 #pragma unroll
     for (int d = 0; d < 7; d++) rec.th[d] = a.theta[d * a.stride + col];
     rec.col = (int)col;
-    rec.n[0] = a.nsh[f * 4 + 0];
-    rec.n[1] = a.nsh[f * 4 + 1];
-    rec.n[2] = a.nsh[f * 4 + 2];
-    rec.flag = a.nsh[f * 4 + 3] ? 1 : 2;
+    const uint2 nw = *(const uint2 *)(a.nsh + f * 4);
+    rec.n[0] = (int16_t)(nw.x & 0xffffu);
+    rec.n[1] = (int16_t)(nw.x >> 16);
+    rec.n[2] = (int16_t)(nw.y & 0xffffu);
+    rec.flag = (nw.y >> 16) ? 1 : 2;
     a.rec[pos] = rec;
   }
 }
@@ -269,12 +272,16 @@ __global__ void __launch_bounds__(256) tile_item_kernel(MfmaArgs a) {
   a.tile_item[t] = lo;
 }
 
-// work units of every bin: consecutive runs of up to 4 of its tiles
+// work units of every bin: consecutive runs of up to 4 of its tiles.  Also
+// the padding slots (flag 0): the rest of the bin's last tile and, for the
+// last bin of a point, the tiles that round the point up to groups of 4; the
+// scatter fills every other slot of the point's tiles.
 __global__ void __launch_bounds__(64) unit_kernel(MfmaArgs a) {
   const int g = blockIdx.x * 64 + threadIdx.x;
   if (g >= a.n_bins) return;
   const int it = item_of_bin(a.items, g);
-  const uint32_t tb = (a.count[g] + kTS - 1) / kTS;
+  const uint32_t cnt = a.count[g];
+  const uint32_t tb = (cnt + kTS - 1) / kTS;
   const uint32_t t0 = a.item_tiles[it] + a.bin_tile[g], u0 = a.item_units[it] + a.bin_unit[g];
   for (uint32_t c = 0; 4 * c < tb; c++) {
     WorkUnit w;
@@ -283,6 +290,15 @@ __global__ void __launch_bounds__(64) unit_kernel(MfmaArgs a) {
     w.key = (uint32_t)(g - a.items.bin0[it]);
     a.unit[u0 + c] = w;
   }
+  SampleRec z;
+  for (int d = 0; d < 7; d++) z.th[d] = 0.f;
+  z.col = 0;
+  z.n[0] = z.n[1] = z.n[2] = 0;
+  z.flag = 0;
+  const int64_t s0 = (int64_t)kTS * t0;
+  int64_t s1 = s0 + (int64_t)kTS * tb;
+  if (g == a.items.bin0[it + 1] - 1) s1 = (int64_t)kTS * a.item_tiles[it + 1];
+  for (int64_t q = s0 + cnt; q < s1; q++) a.rec[q] = z;
 }
 
 // ---- 4. per-sample coefficients (FP64), tile-major ---------------------------
@@ -367,18 +383,8 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
 #pragma unroll
   for (int m = 0; m < (MC > 0 ? MC : kMaxModes); m++) {
     if (m >= M) break;
-    const int deg = p.hdeg[m];
-    double d = p.hpoly[m][deg];
-    for (int j = deg - 1; j >= 0; j--) d = fma(d, u, p.hpoly[m][j]);
-    if (p.hpar[m]) d *= hs;
-    const int em = p.em[m], am = em < 0 ? -em : em;
-    double cr = d, cim = 0.0;
-    for (int q = 0; q < am; q++) {
-      double nr = cr * c1 - cim * s1;
-      cim = cr * s1 + cim * c1;
-      cr = nr;
-    }
-    const double yr = cr, yi = em < 0 ? -cim : cim;
+    double yr, yi;
+    harmonic_ym(p, m, u, hs, c1, s1, yr, yi);
     if constexpr (MC > 0) {
       Yr[m] = yr;
       Yi[m] = yi;
@@ -521,10 +527,10 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
       qk[k] = gp(uniform_ptr(p.Qm + (size_t)(k * Lpad + P + lo_k[k]) * E));
     }
     const RIFT_GLOBAL CoefTile *ct = gp(a.ctile + t);
-    const RIFT_GLOBAL float *yop = gp(a.cop + a.item_cop[it] + (int64_t)(t - a.item_tiles[it]) * K * E * kTS + s);
     const int flag = active ? ct->flag[s] : 0;
     const int col = ct->col[s];
     const float Bf = active ? ct->B[s] : 0.f;
+    const RIFT_GLOBAL float *yop = gp(a.cop + a.item_cop[it] + (int64_t)(t - a.item_tiles[it]) * K * E * kTS + s);
     float Bop[K][T];
     b_operands<T, K>(yop, ct, s, g, active, Bop);
     float w[K][4];
@@ -889,8 +895,6 @@ static hipError_t tune_class(const MfmaArgs &a, int T, int K, int lo, int hi, in
 
 hipError_t mfma_prepare(const MfmaArgs &a, const int *mclass_M, const int *mclass_item0, const int64_t *mclass_tiles,
                         int n_mclasses, hipStream_t st) {
-  hipError_t e = fill_u32((uint32_t *)a.rec, (int64_t)kTS * a.max_tiles * (sizeof(SampleRec) / 4), 0u, st);
-  if (e != hipSuccess) return e;
   const size_t lds = sizeof(uint32_t) * (size_t)std::min(a.max_item_bins, kLdsBins);
   hipLaunchKernelGGL(bin_kernel, dim3(a.n_sort_blocks), dim3(kSortThreads), lds, st, a);
   hipLaunchKernelGGL(colscan_kernel, dim3((unsigned)((a.max_item_bins + kScanBins - 1) / kScanBins), std::min(a.items.n_items, 65535)),

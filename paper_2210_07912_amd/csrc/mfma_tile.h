@@ -64,6 +64,28 @@ __device__ __forceinline__ void b_operands(const RIFT_GLOBAL float *yop, const R
   }
 }
 
+// Harmonic Y_m = (sin(iota)/2)^par P_m(cos^2(iota/2)) exp(i m phi) of one
+// mode from the point's polynomial table (Horner in u = cos^2(iota/2), FP64),
+// with exp(i m phi) by repeated products of exp(i phi) = (c1, s1) and
+// hs = sin(iota/2) cos(iota/2).
+template <typename PT>
+__device__ __forceinline__ void harmonic_ym(const PT &p, int m, double u, double hs, double c1, double s1, double &yr,
+                                            double &yi) {
+  const int deg = p.hdeg[m];
+  double d = p.hpoly[m][deg];
+  for (int j = deg - 1; j >= 0; j--) d = fma(d, u, p.hpoly[m][j]);
+  if (p.hpar[m]) d *= hs;
+  const int em = p.em[m], am = em < 0 ? -em : em;
+  double cr = d, cim = 0.0;
+  for (int q = 0; q < am; q++) {
+    double nr = cr * c1 - cim * s1;
+    cim = cr * s1 + cim * c1;
+    cr = nr;
+  }
+  yr = cr;
+  yi = em < 0 ? -cim : cim;
+}
+
 // Row stride (floats) of a staged block of Q in LDS: 4T elements, padded to
 // an odd number of 16-byte groups so that the 16-byte reads of 8 consecutive
 // rows fall in distinct banks.
