@@ -333,26 +333,41 @@ rift_status rift_ile_set_distance_marginalization(rift_ile *h, int enable);
  * a NULL handle. */
 rift_status rift_ile_set_grad_refine(rift_ile *h, int enable);
 
-/* Per-class choice of how the FP32 evaluation feeds the matrix cores
- * (batching: every (T, K) class of points, T = ceil(M / 2) MFMA steps and K
- * detectors, is one persistent launch).  Two forms of the same kernel exist:
- * "staged" (each workgroup copies the rows of Q its unit needs into LDS, one
- * barrier per two 16-row blocks) and "direct" (each wavefront loads its own
- * operands from global memory one block ahead, no barrier, less LDS and more
- * resident workgroups).  Their results are bit-identical; which is faster
- * depends on T and K.  mode 1 (the default): the first evaluation of each
- * class on the handle runs both forms on that call's data, timed with events
- * (that call waits for them), and later calls use the faster.  mode 0: every
- * class runs staged; mode 2: every class runs direct (measurements made so
- * far are kept for a later mode 1).  Runs with a class not yet measured are
- * not captured by the graph replay.  Returns RIFT_E_INVALID for a NULL
- * handle or another mode. */
+/* Per-class launch configuration of the FP32 evaluation (batching: every
+ * (T, K) class of points, T = ceil(M / 2) MFMA steps and K detectors, is one
+ * persistent launch).  Two forms of the same kernel exist: "staged" (each
+ * workgroup copies the rows of Q its unit needs into LDS, one barrier per two
+ * 16-row blocks) and "direct" (each wavefront loads its own operands from
+ * global memory one block ahead, no barrier, less LDS and more resident
+ * workgroups); each runs with as many workgroups as the device keeps resident
+ * or with half as many per compute unit.  The four configurations are
+ * numbered 1 staged, 2 direct, 3 staged at half residency, 4 direct at half
+ * residency; their results are bit-identical.  mode 1 (the default): the
+ * first evaluation of a class on the handle, for each n_t bucket
+ * (floor(log2) of the class's longest window), runs all four on that call's
+ * data, timed with events (that call waits for them), and later calls use
+ * the fastest (configuration 1 unless another is at least 3 % faster).
+ * mode 0: every class runs staged; mode 2: every class runs direct
+ * (measurements made so far are kept for a later mode 1).  Runs with a class
+ * not yet measured are not captured by the graph replay.  Returns
+ * RIFT_E_INVALID for a NULL handle or another mode. */
 rift_status rift_ile_set_autotune(rift_ile *h, int mode);
 
-/* The measured choices: modes[(T - 1) * 3 + (K - 1)] for T = 1..16 and
- * K = 1..3 (48 ints, caller-owned) is 0 (not measured), 1 (staged) or
- * 2 (direct).  Returns RIFT_E_INVALID for a NULL handle or array. */
+/* The configuration each (T, K) class ran with last: modes[(T - 1) * 3 +
+ * (K - 1)] for T = 1..16 and K = 1..3 (48 ints, caller-owned) is 0 (not run
+ * yet) or 1..4 as numbered above.  Returns RIFT_E_INVALID for a NULL handle
+ * or array. */
 rift_status rift_ile_autotune_table(const rift_ile *h, int *modes);
+
+/* Persisted autotuning.  path: a text file of lines
+ * "<arch> <T> <K> <n_t bucket> <configuration>" (arch: the device's gfx
+ * name).  The lines for this device's arch are read now (later lines win;
+ * malformed lines are skipped; a missing file is not an error) and every
+ * configuration the handle measures from now on is appended, so another
+ * handle or process that loads the file starts with those classes measured.
+ * NULL: stop appending.  Errors: RIFT_E_INVALID for a NULL handle or a file
+ * that exists but cannot be read; a failed append is skipped silently. */
+rift_status rift_ile_set_autotune_cache(rift_ile *h, const char *path);
 
 /* Extrinsic sample draw (Sec. II.A; Sec. III.B: random numbers generated on
  * the GPU).  Writes samples first..first+n-1 of (point, round): Philox4x32-10

@@ -825,8 +825,11 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
 }
 
 // persistent grid: as many workgroups as the device keeps resident
+// Persistent grid: as many workgroups as the device keeps resident
+// (residency 0), or half as many per compute unit, at least one (residency 1:
+// fewer workgroups sharing a compute unit's LDS, caches and issue slots).
 template <int T, int K, bool D, int MODE>
-static void launch_tk(const MfmaArgs &a, int lo, int hi, int cls, hipStream_t st) {
+static void launch_tk(const MfmaArgs &a, int lo, int hi, int cls, hipStream_t st, int residency) {
   static int per_cu = 0;
   if (per_cu == 0) {
     int nb = 0;
@@ -834,32 +837,39 @@ static void launch_tk(const MfmaArgs &a, int lo, int hi, int cls, hipStream_t st
       nb = 1;
     per_cu = nb;
   }
-  const int grid = std::max(1, a.grid / 4 * per_cu);  // a.grid = 4 per compute unit
+  const int pc = residency ? std::max(1, per_cu / 2) : per_cu;
+  const int grid = std::max(1, a.grid / 4 * pc);  // a.grid = 4 per compute unit
   hipLaunchKernelGGL((mfma_kernel<T, K, D, MODE>), dim3(grid), dim3(256), 0, st, a, lo, hi, cls);
 }
 
 // pass: 0 ln L_t (staged or direct feed); 1, 2 the passes of distance
 // marginalization (staged feed)
 template <int T, int K>
-static void launch_tkm(const MfmaArgs &a, bool direct, int pass, int lo, int hi, int cls, hipStream_t st) {
-  if (pass == 1) launch_tk<T, K, false, 1>(a, lo, hi, cls, st);
-  else if (pass == 2) launch_tk<T, K, false, 2>(a, lo, hi, cls, st);
-  else if (direct) launch_tk<T, K, true, 0>(a, lo, hi, cls, st);
-  else launch_tk<T, K, false, 0>(a, lo, hi, cls, st);
+static void launch_tkm(const MfmaArgs &a, bool direct, int pass, int lo, int hi, int cls, hipStream_t st, int res) {
+  if (pass == 1) launch_tk<T, K, false, 1>(a, lo, hi, cls, st, res);
+  else if (pass == 2) launch_tk<T, K, false, 2>(a, lo, hi, cls, st, res);
+  else if (direct) launch_tk<T, K, true, 0>(a, lo, hi, cls, st, res);
+  else launch_tk<T, K, false, 0>(a, lo, hi, cls, st, res);
 }
 
 template <int T>
-static void launch_class(const MfmaArgs &a, int K, bool direct, int pass, int lo, int hi, int cls, hipStream_t st) {
-  if (K == 1) launch_tkm<T, 1>(a, direct, pass, lo, hi, cls, st);
-  else if (K == 2) launch_tkm<T, 2>(a, direct, pass, lo, hi, cls, st);
-  else launch_tkm<T, 3>(a, direct, pass, lo, hi, cls, st);
+static void launch_class(const MfmaArgs &a, int K, bool direct, int pass, int lo, int hi, int cls, hipStream_t st,
+                         int res) {
+  if (K == 1) launch_tkm<T, 1>(a, direct, pass, lo, hi, cls, st, res);
+  else if (K == 2) launch_tkm<T, 2>(a, direct, pass, lo, hi, cls, st, res);
+  else launch_tkm<T, 3>(a, direct, pass, lo, hi, cls, st, res);
 }
 
+// Launch configuration of a class, as the autotuner numbers it: 1 staged,
+// 2 direct, 3 staged at half residency, 4 direct at half residency
+static bool cfg_direct(int mode) { return mode == 2 || mode == 4; }
+static int cfg_residency(int mode) { return mode >= 3 ? 1 : 0; }
+
 static hipError_t launch_mode(const MfmaArgs &a, int T, int K, bool direct, int lo, int hi, int cls, hipStream_t st,
-                              int pass = 0) {
+                              int pass = 0, int res = 0) {
   switch (T) {
 #define RIFT_T_CASE(TT) \
-  case TT: launch_class<TT>(a, K, direct, pass, lo, hi, cls, st); break;
+  case TT: launch_class<TT>(a, K, direct, pass, lo, hi, cls, st, res); break;
     RIFT_T_CASE(1) RIFT_T_CASE(2) RIFT_T_CASE(3) RIFT_T_CASE(4) RIFT_T_CASE(5) RIFT_T_CASE(6) RIFT_T_CASE(7)
     RIFT_T_CASE(8) RIFT_T_CASE(9) RIFT_T_CASE(10) RIFT_T_CASE(11) RIFT_T_CASE(12) RIFT_T_CASE(13)
     RIFT_T_CASE(14) RIFT_T_CASE(15) RIFT_T_CASE(16)
@@ -869,26 +879,36 @@ static hipError_t launch_mode(const MfmaArgs &a, int T, int K, bool direct, int 
   return hipSuccess;
 }
 
-// Both forms of class c on the call's own data, one after the other on st
-// (direct first, so a tie keeps the staged form), timed with events; the
-// results are bit-identical, so the second run only rewrites the outputs.
+// Every launch configuration of class c on the call's own data, one after the
+// other on st, timed with events (the class's work-unit counter cleared
+// before each); the results are bit-identical, so the later runs only
+// rewrite the outputs.  The staged form at full residency is kept unless
+// another configuration is at least 3 % faster.
 static hipError_t tune_class(const MfmaArgs &a, int T, int K, int lo, int hi, int c, hipStream_t st, int &mode) {
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  constexpr int kCfg = 4;
+  hipEvent_t ev[2 * kCfg] = {};
   hipError_t e = hipSuccess;
-  for (int i = 0; i < 4 && e == hipSuccess; i++) e = hipEventCreate(&ev[i]);
-  if (e == hipSuccess) e = hipEventRecord(ev[0], st);
-  if (e == hipSuccess) e = launch_mode(a, T, K, true, lo, hi, c, st);
-  if (e == hipSuccess) e = hipEventRecord(ev[1], st);
-  if (e == hipSuccess) e = fill_u32(a.ctl + 1 + c, 1, 0u, st);  // the class's unit counter
-  if (e == hipSuccess) e = hipEventRecord(ev[2], st);
-  if (e == hipSuccess) e = launch_mode(a, T, K, false, lo, hi, c, st);
-  if (e == hipSuccess) e = hipEventRecord(ev[3], st);
-  if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
-  float td = 0.f, ts = 0.f;
-  if (e == hipSuccess) e = hipEventElapsedTime(&td, ev[0], ev[1]);
-  if (e == hipSuccess) e = hipEventElapsedTime(&ts, ev[2], ev[3]);
-  if (e == hipSuccess) mode = td < 0.97f * ts ? 2 : 1;
-  for (int i = 0; i < 4; i++)
+  for (int i = 0; i < 2 * kCfg && e == hipSuccess; i++) e = hipEventCreate(&ev[i]);
+  for (int m = 1; m <= kCfg && e == hipSuccess; m++) {
+    if (m > 1) e = fill_u32(a.ctl + 1 + c, 1, 0u, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * (m - 1)], st);
+    if (e == hipSuccess) e = launch_mode(a, T, K, cfg_direct(m), lo, hi, c, st, 0, cfg_residency(m));
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * (m - 1) + 1], st);
+  }
+  if (e == hipSuccess) e = hipEventSynchronize(ev[2 * kCfg - 1]);
+  float best = 0.f;
+  int pick = 1;
+  for (int m = 1; m <= kCfg && e == hipSuccess; m++) {
+    float t = 0.f;
+    e = hipEventElapsedTime(&t, ev[2 * (m - 1)], ev[2 * (m - 1) + 1]);
+    if (e != hipSuccess) break;
+    if (m == 1 || t < 0.97f * best) {
+      best = t;
+      pick = m;
+    }
+  }
+  if (e == hipSuccess) mode = pick;
+  for (int i = 0; i < 2 * kCfg; i++)
     if (ev[i]) (void)hipEventDestroy(ev[i]);
   return e;
 }
@@ -958,8 +978,8 @@ hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_
   fan_fork(fo, st, n_classes);
   for (int c = 0; c < n_classes; c++) {
     if (c < 64 && (done >> c) & 1) continue;
-    e = launch_mode(a, class_T[c], class_K[c], class_mode[c] == 2, class_item0[c], class_item0[c + 1], c,
-                    fan_stream(fo, st, c));
+    e = launch_mode(a, class_T[c], class_K[c], cfg_direct(class_mode[c]), class_item0[c], class_item0[c + 1], c,
+                    fan_stream(fo, st, c), 0, cfg_residency(class_mode[c]));
     if (e != hipSuccess) return e;
   }
   e = hipGetLastError();

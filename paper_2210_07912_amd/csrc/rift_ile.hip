@@ -5,6 +5,7 @@
 #include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
+#include <cerrno>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -63,10 +64,16 @@ struct rift_ile {
   bool net_frame = false;
   bool phase_rot = false;  // polarization and phase in phase-rotated coordinates
   bool dmarg = false;      // distance-marginalized ln L_tD (theta's distance not read)
-  // how each (T, K) class feeds the matrix cores: 0 not measured, 1 staged, 2
-  // direct; feed: 1 measure on first use, 0 all staged, 2 all direct
+  // launch configuration of each class (1 staged, 2 direct, 3 and 4 the same
+  // at half residency; 0 not measured), by (T, K, n_t bucket = floor(log2 of
+  // the class's longest window)); kmode: the configuration each (T, K) ran
+  // last.  feed: 1 measure on first use, 0 all staged, 2 all direct.
+  // tune_path: a file the measurements are read from and appended to.
   int feed = 1;
   int kmode[kMaxT + 1][kMaxDet + 1] = {};
+  int tune[kMaxT + 1][kMaxDet + 1][kNtBuckets] = {};
+  std::string tune_path;
+  std::string arch;
   double ws_budget = 6.0e9;
   // FP64 refinement of the matrix-core adjoint (rift_ile_set_grad_refine)
   bool refine = true;
@@ -685,15 +692,24 @@ rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const f
     HIPCHK(h, hipEventCreate(&e1));
     h->prof_ev.emplace_back(e0, e1);
   }
-  // matrix-core feed of each class (measured on first use when autotuning)
-  std::vector<int> class_mode(class_T.size());
+  // launch configuration of each class (measured on first use when autotuning)
+  std::vector<int> class_mode(class_T.size()), class_ntb(class_T.size(), 0);
+  for (size_t c = 0; c < class_T.size(); c++) {
+    int nt = 1;
+    for (int i = class_item0[c]; i < class_item0[c + 1]; i++) nt = std::max(nt, h->hp[it.point[i]].n_t);
+    int b = 0;
+    while (b + 1 < kNtBuckets && (nt >> (b + 1)) > 0) b++;
+    class_ntb[c] = b;
+  }
   bool measured = true;
   for (size_t c = 0; c < class_T.size(); c++) {
-    class_mode[c] = h->feed == 1 ? h->kmode[class_T[c]][class_K[c]] : h->feed == 2 ? 2 : 1;
+    class_mode[c] = h->feed == 1 ? h->tune[class_T[c]][class_K[c]][class_ntb[c]] : h->feed == 2 ? 2 : 1;
     measured = measured && class_mode[c] != 0;
   }
-  if (!grad && h->use_graph && !h->prof && measured)
+  if (!grad && h->use_graph && !h->prof && measured) {
+    for (size_t c = 0; c < class_T.size(); c++) h->kmode[class_T[c]][class_K[c]] = class_mode[c];
     return launch_graph(h, a, class_T, class_K, class_item0, mclass_M, mclass_item0, mclass_tiles, class_mode);
+  }
   if (grad)
     HIPCHK(h, mfma_backward(a, class_T.data(), class_K.data(), class_item0.data(), (int)class_T.size(),
                             mclass_M.data(), mclass_item0.data(), mclass_tiles.data(), (int)mclass_M.size(), h->stream,
@@ -702,8 +718,26 @@ rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const f
     HIPCHK(h, mfma_forward(a, class_T.data(), class_K.data(), class_item0.data(), (int)class_T.size(),
                            mclass_M.data(), mclass_item0.data(), mclass_tiles.data(), (int)mclass_M.size(),
                            class_mode.data(), h->feed == 1, h->stream, h->fan, e0, e1));
-    if (h->feed == 1)
-      for (size_t c = 0; c < class_T.size(); c++) h->kmode[class_T[c]][class_K[c]] = class_mode[c];
+    std::string lines;
+    for (size_t c = 0; c < class_T.size(); c++) {
+      if (class_mode[c] == 0) continue;  // distance marginalization: the fixed passes
+      h->kmode[class_T[c]][class_K[c]] = class_mode[c];
+      int &slot = h->tune[class_T[c]][class_K[c]][class_ntb[c]];
+      if (h->feed == 1 && slot == 0) {
+        slot = class_mode[c];
+        char ln[96];
+        std::snprintf(ln, sizeof ln, "%s %d %d %d %d\n", h->arch.c_str(), class_T[c], class_K[c], class_ntb[c],
+                      class_mode[c]);
+        lines += ln;
+      }
+    }
+    if (!lines.empty() && !h->tune_path.empty()) {
+      // appended in one write; a cache that cannot be written is skipped
+      if (FILE *f = std::fopen(h->tune_path.c_str(), "a")) {
+        (void)std::fwrite(lines.data(), 1, lines.size(), f);
+        std::fclose(f);
+      }
+    }
   }
   return RIFT_OK;
 }
@@ -1127,6 +1161,14 @@ rift_status rift_ile_create(rift_ile **out, const rift_ile_desc *desc, void *str
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && v > 0) h->n_cu = v;
   else h->n_cu = 256;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) {
+      std::string an(prop.gcnArchName);
+      h->arch = an.substr(0, an.find(':'));
+    }
+    if (h->arch.empty()) h->arch = "unknown";
+  }
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess && v > 0)
     h->lds_max = std::min(v, 160 * 1024) - 1024;
   // per-sample workspace of one evaluation run: a third of the free device
@@ -1293,6 +1335,32 @@ rift_status rift_ile_set_grad_refine(rift_ile *h, int enable) {
 rift_status rift_ile_set_autotune(rift_ile *h, int mode) {
   if (!h || mode < 0 || mode > 2) return RIFT_E_INVALID;
   h->feed = mode;
+  return RIFT_OK;
+}
+
+rift_status rift_ile_set_autotune_cache(rift_ile *h, const char *path) {
+  if (!h) return RIFT_E_INVALID;
+  if (!path) {
+    h->tune_path.clear();
+    return RIFT_OK;
+  }
+  FILE *f = std::fopen(path, "r");
+  if (!f) {
+    if (errno != ENOENT) return fail(h, RIFT_E_INVALID, "cannot read the autotune cache %s", path);
+  } else {
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+      char arch[96];
+      int T, K, b, m;
+      if (std::sscanf(line, "%95s %d %d %d %d", arch, &T, &K, &b, &m) != 5) continue;
+      if (h->arch != arch || T < 1 || T > kMaxT || K < 1 || K > kMaxDet || b < 0 || b >= kNtBuckets || m < 1 ||
+          m > 4)
+        continue;
+      h->tune[T][K][b] = m;  // later lines win
+    }
+    std::fclose(f);
+  }
+  h->tune_path = path;
   return RIFT_OK;
 }
 

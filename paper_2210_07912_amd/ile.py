@@ -98,6 +98,7 @@ FUNCTIONS = {
     "rift_ile_set_network_frame": (C.c_int, [C.c_void_p, C.c_int]),
     "rift_ile_set_phase_rotation": (C.c_int, [C.c_void_p, C.c_int]),
     "rift_ile_set_distance_marginalization": (C.c_int, [C.c_void_p, C.c_int]),
+    "rift_ile_set_autotune_cache": (C.c_int, [C.c_void_p, C.c_char_p]),
     "rift_ile_set_grad_refine": (C.c_int, [C.c_void_p, C.c_int]),
     "rift_ile_precompute": (C.c_int, [C.POINTER(FdPoint), C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
                                       C.c_void_p]),
@@ -259,18 +260,25 @@ class RiftILE:
         self._check(lib().rift_ile_set_grad_refine(self.h, int(enable)))
 
     def set_autotune(self, mode=1):
-        """How FP32 evaluations feed the matrix cores: 1 (default) measure the
-        staged and the direct form of each (T, K) class on its first
-        evaluation and use the faster; 0 always staged; 2 always direct.
-        ``True``/``False`` mean 1/0."""
+        """Launch configuration of FP32 evaluations: 1 (default) measure the
+        four configurations (staged or direct feed, full or half residency) of
+        each (T, K) class and n_t bucket on its first evaluation and use the
+        fastest; 0 always staged; 2 always direct.  ``True``/``False`` mean 1/0."""
         self._check(lib().rift_ile_set_autotune(self.h, int(mode)))
 
     def autotune_table(self):
-        """{(T, K): "staged" | "direct"} for the classes measured so far."""
+        """{(T, K): configuration} for the classes run so far: "staged",
+        "direct", "staged/half" or "direct/half" (half: half the resident
+        workgroups per compute unit)."""
         arr = (C.c_int * 48)()
         self._check(lib().rift_ile_autotune_table(self.h, arr))
-        names = {1: "staged", 2: "direct"}
+        names = {1: "staged", 2: "direct", 3: "staged/half", 4: "direct/half"}
         return {(i // 3 + 1, i % 3 + 1): names[v] for i, v in enumerate(arr) if v in names}
+
+    def set_autotune_cache(self, path):
+        """Read measured launch configurations from ``path`` (if it exists)
+        and append new measurements to it; None: stop appending."""
+        self._check(lib().rift_ile_set_autotune_cache(self.h, None if path is None else str(path).encode()))
 
     def profile(self, enable=True):
         """(ms, launches) of the dominant kernel since the last call; then

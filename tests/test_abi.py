@@ -49,6 +49,7 @@ def test_host_only_calls():
     assert L.rift_ile_set_network_frame(None, 1) == -1
     assert L.rift_ile_set_phase_rotation(None, 1) == -1
     assert L.rift_ile_set_distance_marginalization(None, 1) == -1
+    assert L.rift_ile_set_autotune_cache(None, None) == -1
     assert L.rift_ile_set_grad_refine(None, 1) == -1
     assert L.rift_ile_precompute(None, 0, 0, None, None, None) == -1
     assert b"NULL" in L.rift_ile_last_error(None)

@@ -199,6 +199,46 @@ def test_matrix_core_feeds(ile, orc):
     h.close()
 
 
+def test_autotune_cache(ile, orc, tmp_path):
+    """Measured launch configurations persist: a handle given a cache file
+    measures each (T, K) class once and appends one line per class; a second
+    handle loading the file starts with every class measured (its first run
+    is already captured by the graph replay), appends nothing and gives
+    bit-identical ln L_t; malformed lines and other archs are skipped."""
+    w = synth.workload("tiny_batched")
+    pts = [synth.make_point(s) for s in w.points]
+    ths, items, off = [], [], 0
+    for i, (d, n) in enumerate(zip(pts, w.n_samples)):
+        ths.append(synth.mixed_samples(d, 900 + i, n))
+        items.append((i, off, n))
+        off += n
+    theta = torch.tensor(np.concatenate(ths, axis=1))
+    classes = {((s.n_modes + 1) // 2, len(s.dets)) for s in w.points}
+    path = tmp_path / "tune.txt"
+    h = _handle(ile, pts, "fp32")
+    h.set_autotune_cache(path)
+    a = h.lnL(theta, items).cpu().numpy()
+    text = path.read_text()
+    lines = [ln.split() for ln in text.splitlines() if ln.strip()]
+    _say(f"autotune cache: {lines}")
+    assert {(int(x[1]), int(x[2])) for x in lines} == classes and len(lines) == len(classes)
+    assert all(1 <= int(x[4]) <= 4 for x in lines) and len({x[0] for x in lines}) == 1
+    table = h.autotune_table()
+    assert set(table) == classes
+    h.close()
+    path.write_text("junk line\nother_arch 1 3 5 4\n" + lines[0][0] + " 99 1 3 2\n" + text)
+    h2 = _handle(ile, pts, "fp32")
+    h2.set_autotune_cache(path)
+    h2.set_graph(True)
+    b = h2.lnL(theta, items).cpu().numpy()
+    assert h2.graph_stats()[0] == 1
+    assert np.array_equal(a, b, equal_nan=True)
+    assert h2.autotune_table() == table
+    assert path.read_text().endswith(text)
+    h2.set_autotune_cache(None)
+    h2.close()
+
+
 def test_batched_workload_sampled(ile, orc):
     """All 512 points of the batched workload (M in {2, 5, 9, 21}, K in {2, 3},
     n_t in 200..800, SNR 8..40) in one call, 48 samples per point (half prior,
