@@ -43,7 +43,15 @@
 
 namespace rift {
 
-constexpr int kRS = 52;          // floats per z ring row: two 16-row slots and slot 0 again (48 rows), padded
+// z ring of a detector: 48 logical rows (two 16-row slots and slot 0 again)
+// of 16 samples, stored row-major with one pad row after every 4: logical
+// row r sits at physical row 5 (r >> 2) + (r & 3), sample s at column s.
+// A window read takes 7 consecutive logical rows from r = 4 g + sh_k for
+// each lane (g the lane's row group, sh_k its sample's shift): lanes of
+// different samples differ in the column's bank, and the two row groups of a
+// half-wavefront (4 logical rows apart, 5 physical) differ in the row's
+// parity, so the reads are free of bank conflicts whatever the shifts.
+constexpr int kRR = 60;
 constexpr int kSortThreads = 1024;  // threads per sort block (kSortBlock samples)
 
 __device__ __forceinline__ int item_of_flat(const ItemsDev &it, int64_t f) {
@@ -475,11 +483,11 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
   constexpr int JA = J > 0 ? J : 1, RA = R > 0 ? R : 1;
   constexpr int ES = stage_stride<T>();
   constexpr int SF = K * kTS * ES;  // floats of one staged block
-  __shared__ __align__(16) float ring_all[kWaves * K * kTS * kRS];
+  __shared__ __align__(16) float ring_all[kWaves * K * kRR * kTS];
   __shared__ __align__(16) float stage[DIRECT ? 1 : 4][DIRECT ? 4 : SF];  // staged: block b in slot b % 4
   __shared__ WorkUnit unit_sh;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  float *ring = ring_all + wave * (K * kTS * kRS);  // [det][sample][kRS]
+  float *ring = ring_all + wave * (K * kRR * kTS);  // [det][physical row][sample]
   const int s = lane & 15, g = lane >> 4;
   const uint32_t u_lo = a.item_units[item_lo], u_hi = a.item_units[item_hi];
   // staging: thread i < 16 T copies 16-byte group i of the 16 rows x 4 T
@@ -546,12 +554,18 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
       }
     }
     const int JB = (NT + 15) >> 4;
-    // z ring: block b in rows 16 (b % 2) .. + 15 (slot 0 also in rows 32..47),
-    // so the 7 rows a window read needs are contiguous
-    const float *rz[K];
+    // z ring: block b in logical rows 16 (b % 2) .. + 15 (slot 0 also in rows
+    // 32..47), so the 7 rows a window read needs are consecutive; zo: the
+    // lane's read positions in slot 0 (slot 1 is 20 physical rows further)
+    int zo[K][7];
 #pragma unroll
-    for (int k = 0; k < K; k++) rz[k] = ring + (k * kTS + s) * kRS + 4 * g + sh[k];
-    float *const wz = ring + s * kRS + 4 * g;
+    for (int k = 0; k < K; k++)
+#pragma unroll
+      for (int o = 0; o < 7; o++) {
+        const int x = sh[k] + o;
+        zo[k][o] = k * kRR * kTS + kTS * (5 * g + x + (x >> 2)) + s;
+      }
+    float *const wz = ring + kTS * (5 * g) + s;
     const float *const sa = &stage[0][s * ES + 4 * g];       // this lane's quads in slot 0
     const float *const st = &stage[0][s * ES + 16 * J + g];  // and the rest
     const int rem = NT - 16 * (JB - 1);
@@ -630,8 +644,11 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
         }
 #pragma unroll
       for (int k = 0; k < K; k++) {
-        *(f4 *)(wz + k * kTS * kRS + 16 * (S4 & 1)) = acc[k];
-        if constexpr ((S4 & 1) == 0) *(f4 *)(wz + k * kTS * kRS + 32) = acc[k];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          wz[k * kRR * kTS + kTS * (20 * (S4 & 1) + i)] = acc[k][i];
+          if constexpr ((S4 & 1) == 0) wz[k * kRR * kTS + kTS * (40 + i)] = acc[k][i];
+        }
       }
     };
     // window samples 16 c + 4 g + i (i < 4) of the block in ring slot SL:
@@ -671,10 +688,9 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
       for (int i = 0; i < 4; i++) ell[i] = last ? base + last_pen[i] : base;
 #pragma unroll
       for (int k = 0; k < K; k++) {
-        const float *zr = rz[k] + 16 * SL;
         float z[7];
 #pragma unroll
-        for (int o = 0; o < 7; o++) z[o] = zr[o];
+        for (int o = 0; o < 7; o++) z[o] = ring[zo[k][o] + kTS * 20 * SL];
 #pragma unroll
         for (int i = 0; i < 4; i++) {
           ell[i] = fmaf(w[k][0], z[i], ell[i]);
