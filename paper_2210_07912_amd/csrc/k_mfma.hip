@@ -555,16 +555,21 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
     }
     const int JB = (NT + 15) >> 4;
     // z ring: block b in logical rows 16 (b % 2) .. + 15 (slot 0 also in rows
-    // 32..47), so the 7 rows a window read needs are consecutive; zo: the
-    // lane's read positions in slot 0 (slot 1 is 20 physical rows further)
-    int zo[K][7];
+    // 32..47), so the 7 rows a window read needs are consecutive.  Read o of
+    // a lane sits 16 (o + ((c + o) >> 2)) floats past its first, c = sh_k & 3:
+    // 0, 16 + e3, 32 + e2, 48 + e1, 80, 96 + e3, 112 + e2 with e_i = 16 [c >= i],
+    // so four position registers per detector (zb: + 0, e3, e2, e1) and the
+    // rest as instruction offsets; slot 1 is 20 physical rows further
+    int zb[K][4];
 #pragma unroll
-    for (int k = 0; k < K; k++)
-#pragma unroll
-      for (int o = 0; o < 7; o++) {
-        const int x = sh[k] + o;
-        zo[k][o] = k * kRR * kTS + kTS * (5 * g + x + (x >> 2)) + s;
-      }
+    for (int k = 0; k < K; k++) {
+      const int c = sh[k] & 3;
+      const int b0 = k * kRR * kTS + kTS * (5 * g + sh[k] + (sh[k] >> 2)) + s;
+      zb[k][0] = b0;
+      zb[k][1] = b0 + (c >= 3 ? kTS : 0);
+      zb[k][2] = b0 + (c >= 2 ? kTS : 0);
+      zb[k][3] = b0 + (c >= 1 ? kTS : 0);
+    }
     float *const wz = ring + kTS * (5 * g) + s;
     const float *const sa = &stage[0][s * ES + 4 * g];       // this lane's quads in slot 0
     const float *const st = &stage[0][s * ES + 16 * J + g];  // and the rest
@@ -689,8 +694,14 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
 #pragma unroll
       for (int k = 0; k < K; k++) {
         float z[7];
-#pragma unroll
-        for (int o = 0; o < 7; o++) z[o] = ring[zo[k][o] + kTS * 20 * SL];
+        constexpr int R0 = kTS * 20 * SL;
+        z[0] = ring[zb[k][0] + R0];
+        z[1] = ring[zb[k][1] + R0 + kTS];
+        z[2] = ring[zb[k][2] + R0 + 2 * kTS];
+        z[3] = ring[zb[k][3] + R0 + 3 * kTS];
+        z[4] = ring[zb[k][0] + R0 + 5 * kTS];
+        z[5] = ring[zb[k][1] + R0 + 6 * kTS];
+        z[6] = ring[zb[k][2] + R0 + 7 * kTS];
 #pragma unroll
         for (int i = 0; i < 4; i++) {
           ell[i] = fmaf(w[k][0], z[i], ell[i]);
