@@ -668,7 +668,8 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
     // distance marginalization: the slot's A_max (MODE 2 reads it), its
     // nodes and per-node sums
     constexpr int NQ = MODE == 2 ? kDmGL : 1;
-    float am = MODE == 1 ? -INFINITY : 0.f, skip = INFINITY, ta = 0.f, hq = 0.f;
+    float am = MODE == 1 ? -INFINITY : 0.f, skip = INFINITY;
+    double ta = 0.0, hq = 0.0;  // the nodes' interval in t = ln x
     float xs[NQ], Sq[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; q++) xs[q] = Sq[q] = 0.f;
@@ -676,12 +677,17 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
       const float av = active ? a.amax[(int64_t)t * kTS + s] : 0.f;
       if (valid && isfinite(av)) {
         am = av;
-        const float tlo = logf((float)(p.d_ref / a.dm_hi)), thi = logf((float)(p.d_ref / a.dm_lo));
-        float tb;
-        dm_interval<float>(av * kLn2f, Bf * kLn2f, tlo, thi, (float)DmRule<float>::T, 24, ta, tb);
+        // the interval is searched in FP32; an end at the prior's edge takes
+        // the edge's FP64 value, so a range much narrower than the FP32
+        // spacing of t keeps its exact width (the rule's weights scale with it)
+        const double tlo = log(p.d_ref / a.dm_hi), thi = log(p.d_ref / a.dm_lo);
+        float taf, tbf;
+        dm_interval<float>(av * kLn2f, Bf * kLn2f, (float)tlo, (float)thi, (float)DmRule<float>::T, 24, taf, tbf);
+        ta = taf <= (float)tlo ? tlo : (double)taf;
+        const double tb = tbf >= (float)thi ? thi : (double)tbf;
         hq = tb - ta;
 #pragma unroll
-        for (int q = 0; q < NQ; q++) xs[q] = expf(ta + hq * (float)(0.5 + 0.5 * dm_gl_node(q)));
+        for (int q = 0; q < NQ; q++) xs[q] = expf((float)(ta + hq * (0.5 + 0.5 * dm_gl_node(q))));
         skip = -(float)((DmRule<float>::T + 10.0) * kLog2e) / xs[0];
       }
     }
@@ -809,14 +815,14 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
         Sq[q] += __shfl_xor(Sq[q], 32);
       }
       float lt = NAN;
-      if (valid && g == 0 && hq > 0.f) {
+      if (valid && g == 0 && hq > 0.0) {
         const double A = (double)am * (double)kLn2f, Bv = (double)Bf * (double)kLn2f;
         const double c = 3.0 * p.d_ref * p.d_ref * p.d_ref / (a.dm_hi * a.dm_hi * a.dm_hi - a.dm_lo * a.dm_lo * a.dm_lo);
-        const double lc = log(0.5 * (double)hq * c);
+        const double lc = log(0.5 * hq * c);
         double cmax = -INFINITY, acc = 0.0;
 #pragma unroll
         for (int q = 0; q < NQ; q++) {
-          const double tq = (double)(ta + hq * (float)(0.5 + 0.5 * dm_gl_node(q)));
+          const double tq = ta + hq * (0.5 + 0.5 * dm_gl_node(q));
           const double xd = (double)xs[q];
           const double ci = lc + log(dm_gl_weight(q)) - 3.0 * tq + xd * A - xd * xd * Bv + log((double)Sq[q]);
           if (ci > cmax) {

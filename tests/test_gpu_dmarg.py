@@ -215,3 +215,43 @@ def test_dmarg_fp32_marginalize_against_fp64_replay(ile, orc):
     del items
     h.close()
     h64.close()
+
+
+def test_dmarg_edge_cases(ile, orc):
+    """Degenerate integrands: no quadratic term (U = 0, every row of Q the
+    same, so ell_j = A D_ref / D: the envelope has no interior maximum for
+    A < 0 and one at x = 3 / A for A > 0), against the oracle's integral
+    (itself pinned by the exponential-integral closed form); and a prior
+    range narrowed to 2e-6 of its width, where ln L_tD must equal ln L_t at
+    that distance (the time-only evaluation of the same handle type)."""
+    spec = synth.workload("tiny").points[0]
+    d = synth.make_point(spec)
+    flat = dict(d)
+    q = np.zeros_like(d["Q"])
+    q[:] = d["Q"][:, d["Q"].shape[1] // 2: d["Q"].shape[1] // 2 + 1, :]
+    flat["Q"], flat["U"] = q, np.zeros_like(d["U"])
+    th = synth.prior_samples(31, 300)
+    for prec in ("fp64", "fp32"):
+        h = _handle(ile, [flat], prec)
+        h.set_distance_marginalization(True)
+        t = th.astype(np.float32).astype(np.float64) if prec == "fp32" else th
+        got = h.lnL(torch.tensor(t, dtype=torch.float32 if prec == "fp32" else torch.float64)).cpu().numpy()
+        ref = orc.lnL_tD(orc.Point.from_dict(flat, complex64=(prec == "fp32")), t)
+        err = np.abs(got - ref)
+        tol = (1e-8 if prec == "fp64" else 2e-5) * (1 + np.abs(ref))
+        _say(f"dmarg U = 0 {prec}: max|d| {err.max():.2e}, ln L_tD {ref.min():.2f}..{ref.max():.2f}")
+        assert np.all(err <= tol)
+        h.close()
+    D0 = 321.0
+    th2 = synth.mixed_samples(d, 32, 200)
+    th2[5] = D0
+    for prec in ("fp64", "fp32"):
+        h = _handle(ile, [d], prec, d_min=D0 * (1 - 1e-6), d_max=D0 * (1 + 1e-6))
+        dt = torch.float32 if prec == "fp32" else torch.float64
+        lt = h.lnL(torch.tensor(th2, dtype=dt)).cpu().numpy().astype(np.float64)
+        h.set_distance_marginalization(True)
+        ld = h.lnL(torch.tensor(th2, dtype=dt)).cpu().numpy().astype(np.float64)
+        err = np.abs(ld - lt)
+        _say(f"dmarg narrow prior {prec}: max|d| {err.max():.2e}")
+        assert np.all(err <= (1e-7 if prec == "fp64" else 5e-4) * (1 + np.abs(lt)))
+        h.close()
