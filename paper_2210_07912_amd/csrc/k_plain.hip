@@ -40,6 +40,16 @@ __device__ __forceinline__ float r_log<float>(float x) { return logf(x); }
 template <>
 __device__ __forceinline__ double r_log<double>(double x) { return log(x); }
 
+// bytes of the z rows' space: [TS][rows_cap] in the bulk precision, and in
+// the forward at least the (U a), (V a) arrays it also holds (16-byte
+// multiple, so the window buffer after it stays aligned)
+__host__ __device__ inline size_t plain_zbuf_bytes(int elem, int TS, int rows_cap, bool bwd) {
+  size_t z = (size_t)TS * rows_cap * elem;
+  const size_t uv = (size_t)2 * TS * kMaxDet * kMaxModes * 2 * 8;
+  if (!bwd && uv > z) z = uv;
+  return (z + 15) & ~(size_t)15;
+}
+
 // maps a flat tile index to (item, first sample, count)
 __device__ __forceinline__ int find_item(const int *tile0, int n_items, int t) {
   int lo = 0, hi = n_items;  // tile0[lo] <= t < tile0[hi]
@@ -52,6 +62,7 @@ __device__ __forceinline__ int find_item(const int *tile0, int n_items, int t) {
 
 template <typename R, int TS, bool BWD>
 __global__ void __launch_bounds__(256) plain_kernel(PlainArgsT<R> args) {
+  static_assert(256 / TS <= 64, "a sample's window reductions must stay within one wavefront");
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   const int t = blockIdx.x;
@@ -63,26 +74,36 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgsT<R> args) {
   const int K = p.K, M = p.M, NT = p.n_t, P = p.pad;
   const int MM = kMaxModes;
 
-  // LDS carve-up
+  // LDS carve-up.  (U a) and (V a) are needed by the quadratic term and the
+  // adjoint's chain rule only: the forward keeps them in the space the rows
+  // of z take later.
+  constexpr int AKM = TS * kMaxDet * MM * 2;             // doubles of one [TS][K][MM][2] array
   double *a_d = (double *)smem;                          // [TS][K][MM][2]
-  double *ua = a_d + TS * kMaxDet * MM * 2;              // [TS][K][MM][2]  (U a)_m
-  double *va = ua + TS * kMaxDet * MM * 2;               // [TS][K][MM][2]  (V a)_m
-  double *gk = va + TS * kMaxDet * MM * 2;               // [TS][K][MM][2]  G_k (adjoint)
-  double *Bs = gk + (BWD ? TS * kMaxDet * MM * 2 : 0);   // [TS]
+  double *gk = a_d + AKM;                                // [TS][K][MM][2]  G_k (adjoint)
+  double *ua_b = gk + (BWD ? AKM : 0);                   // adjoint: (U a)_m, (V a)_m
+  double *Bs = ua_b + (BWD ? 2 * AKM : 0);               // [TS]
   double *Hk = Bs + TS;                                  // [TS][K]
   double *lnl = Hk + TS * kMaxDet;                       // [TS]
-  R *wq = (R *)(lnl + TS);                               // [TS][K][4]
+  double *F_l = lnl + TS;                                // [TS][K][2] antenna patterns F+, Fx
+  double *sc_l = F_l + TS * kMaxDet * 2;                 // [TS][4] cos, sin of iota/2, phi, x
+  R *wq = (R *)(sc_l + TS * 4);                          // [TS][K][4]
   R *wd = wq + TS * kMaxDet * 4;                         // [TS][K][4]
   int *nk = (int *)(wd + TS * kMaxDet * 4);              // [TS][K]
   int *okv = nk + TS * kMaxDet;                          // [TS]
   int *rng = okv + TS;                                   // [K][2] row range
   R *zbuf = (R *)(((uintptr_t)(rng + 2 * kMaxDet) + 15) & ~(uintptr_t)15);  // [TS][rows_cap]
-  R *lbuf = zbuf + TS * args.rows_cap;                   // [TS][nt_cap]
+  double *ua = BWD ? ua_b : (double *)zbuf;              // [TS][K][MM][2]  (U a)_m
+  double *va = ua + AKM;                                 // [TS][K][MM][2]  (V a)_m
+  R *lbuf = (R *)((char *)zbuf + plain_zbuf_bytes(sizeof(R), TS, args.rows_cap, BWD));  // [TS][nt_cap]
 
-  // ---- 1. per-sample prologue (FP64) ----
-  if (tid < TS) {
-    const int s = tid;
+  // ---- 1. per-sample prologue (FP64), spread over the workgroup ----
+  // 1a. one thread per (sample, detector): geometry, antenna pattern, the
+  // row offset and interpolation weights of that detector
+  for (int idx = tid; idx < TS * K; idx += blockDim.x) {
+    const int s = idx / K, k = idx % K;
     bool ok = false;
+    double Fp = 0.0, Fc = 0.0, x = 0.0, mu = 0.0;
+    int n = 0;
     if (s < ns) {
       const int64_t i = first + s;
       double th[7];
@@ -91,42 +112,47 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgsT<R> args) {
       Shift sh = shifts(p, tr, th[RIFT_TAU]);
       ok = sh.ok && isfinite(th[RIFT_IOTA]) && isfinite(th[RIFT_PHI]) &&
            (args.dmarg || (th[RIFT_DIST] > 0.0 && isfinite(th[RIFT_DIST])));
-      double x = args.dmarg ? 1.0 : p.d_ref / th[RIFT_DIST];
-      double ci, si, cph, sph;
-      sincos(0.5 * th[RIFT_IOTA], &si, &ci);
-      sincos(th[RIFT_PHI], &sph, &cph);
-      for (int k = 0; k < K; k++) {
-        double Fp, Fc;
-        antenna(p.D[k], tr, Fp, Fc);
-        for (int m = 0; m < M; m++) {
-          double yr, yi;
-          double cm, sm;
-          sincos(p.em[m] * th[RIFT_PHI], &sm, &cm);
-          harmonic(p, m, ci, si, cm, sm, yr, yi);
-          double ar = x * (Fp * yr - Fc * yi), ai = x * (Fp * yi + Fc * yr);
-          a_d[((s * kMaxDet + k) * MM + m) * 2 + 0] = ok ? ar : 0.0;
-          a_d[((s * kMaxDet + k) * MM + m) * 2 + 1] = ok ? ai : 0.0;
-        }
-        R w[4], dw[4];
-        cr_weights<R>((R)sh.mu[k], w);
-        cr_dweights<R>((R)sh.mu[k], dw);
-        for (int q = 0; q < 4; q++) {
-          wq[(s * kMaxDet + k) * 4 + q] = w[q];
-          wd[(s * kMaxDet + k) * 4 + q] = dw[q];
-        }
-        nk[s * kMaxDet + k] = sh.n[k];
+      x = args.dmarg ? 1.0 : p.d_ref / th[RIFT_DIST];
+      antenna(p.D[k], tr, Fp, Fc);
+      mu = sh.mu[k];
+      n = sh.n[k];
+      if (k == 0) {
+        double ci, si;
+        sincos(0.5 * th[RIFT_IOTA], &si, &ci);
+        sc_l[s * 4 + 0] = ci;
+        sc_l[s * 4 + 1] = si;
+        sc_l[s * 4 + 2] = th[RIFT_PHI];
+        sc_l[s * 4 + 3] = x;
       }
     }
-    okv[s] = ok ? 1 : 0;
-    if (!ok) {
-      for (int k = 0; k < kMaxDet; k++) {
-        nk[s * kMaxDet + k] = 0;
-        for (int m = 0; m < MM; m++) {
-          a_d[((s * kMaxDet + k) * MM + m) * 2 + 0] = 0.0;
-          a_d[((s * kMaxDet + k) * MM + m) * 2 + 1] = 0.0;
-        }
-        for (int q = 0; q < 4; q++) wq[(s * kMaxDet + k) * 4 + q] = wd[(s * kMaxDet + k) * 4 + q] = R(0);
-      }
+    if (k == 0) okv[s] = ok ? 1 : 0;
+    F_l[(s * kMaxDet + k) * 2 + 0] = ok ? Fp : 0.0;
+    F_l[(s * kMaxDet + k) * 2 + 1] = ok ? Fc : 0.0;
+    R w[4], dw[4];
+    cr_weights<R>((R)mu, w);
+    cr_dweights<R>((R)mu, dw);
+    for (int q = 0; q < 4; q++) {
+      wq[(s * kMaxDet + k) * 4 + q] = ok ? w[q] : R(0);
+      wd[(s * kMaxDet + k) * 4 + q] = ok ? dw[q] : R(0);
+    }
+    nk[s * kMaxDet + k] = ok ? n : 0;
+  }
+  __syncthreads();
+  // 1b. one thread per (sample, mode): the harmonic, then a_km = x F_k Y_m
+  // for every detector (zero for an invalid sample)
+  for (int idx = tid; idx < TS * M; idx += blockDim.x) {
+    const int s = idx / M, m = idx % M;
+    double yr = 0.0, yi = 0.0, x = 0.0;
+    if (okv[s]) {
+      double cm, sm;
+      sincos(p.em[m] * sc_l[s * 4 + 2], &sm, &cm);
+      harmonic(p, m, sc_l[s * 4 + 0], sc_l[s * 4 + 1], cm, sm, yr, yi);
+      x = sc_l[s * 4 + 3];
+    }
+    for (int k = 0; k < K; k++) {
+      const double Fp = F_l[(s * kMaxDet + k) * 2 + 0], Fc = F_l[(s * kMaxDet + k) * 2 + 1];
+      a_d[((s * kMaxDet + k) * MM + m) * 2 + 0] = x * (Fp * yr - Fc * yi);
+      a_d[((s * kMaxDet + k) * MM + m) * 2 + 1] = x * (Fp * yi + Fc * yr);
     }
   }
   __syncthreads();
@@ -390,11 +416,11 @@ static hipError_t launch_ts(const PlainArgsT<R> &a, int n_tiles, size_t lds, hip
 
 size_t plain_lds_bytes(int elem, int TS, int rows_cap, int nt_cap, bool bwd) {
   size_t b = 0;
-  b += (size_t)TS * kMaxDet * kMaxModes * 2 * 8 * (bwd ? 4 : 3);
-  b += (size_t)TS * 8 * (2 + kMaxDet);
+  b += (size_t)TS * kMaxDet * kMaxModes * 2 * 8 * (bwd ? 4 : 1);
+  b += (size_t)TS * 8 * (2 + kMaxDet + 2 * kMaxDet + 4);
   b += (size_t)TS * kMaxDet * 4 * elem * 2;
   b += (size_t)TS * (kMaxDet + 1) * 4 + 2 * kMaxDet * 4 + 16;
-  b += (size_t)TS * rows_cap * elem + (size_t)TS * nt_cap * elem;
+  b += plain_zbuf_bytes(elem, TS, rows_cap, bwd) + (size_t)TS * nt_cap * elem;
   return b;
 }
 
@@ -406,9 +432,7 @@ hipError_t plain_launch(const PlainArgsT<R> &a, int TS, int n_tiles, bool bwd, h
 #define RIFT_TS_CASE(T)                                                   \
   case T:                                                                 \
     return bwd ? launch_ts<R, T, true>(a, n_tiles, lds, st, ev0, ev1) : launch_ts<R, T, false>(a, n_tiles, lds, st, ev0, ev1);
-  switch (TS) {
-    RIFT_TS_CASE(1)
-    RIFT_TS_CASE(2)
+  switch (TS) {  // a sample's reductions span 256 / TS <= 64 lanes
     RIFT_TS_CASE(4)
     RIFT_TS_CASE(8)
     RIFT_TS_CASE(16)

@@ -443,10 +443,17 @@ template <typename R>
 rift_status run_plain(rift_ile *h, const Items &it, int64_t stride, const R *theta, R *lnL, R *lnw,
                       const R *ln_ratio, const R *gin, R *grad, bool bwd) {
   const int n = (int)it.point.size();
+  // samples per workgroup (4, 8 or 16: each sample's window reductions take
+  // 256 / TS lanes of one wavefront): the most that still let two workgroups
+  // share a compute unit's LDS, else the most that fit at all
+  auto lds = [&](int ts) { return plain_lds_bytes(sizeof(R), ts, h->max_L, h->max_nt, bwd); };
   int TS = 16;
-  while (TS > 1 && plain_lds_bytes(sizeof(R), TS, h->max_L, h->max_nt, bwd) > (size_t)h->lds_max) TS >>= 1;
-  if (plain_lds_bytes(sizeof(R), TS, h->max_L, h->max_nt, bwd) > (size_t)h->lds_max)
-    return fail(h, RIFT_E_SHAPE, "window too long for the plain kernel's LDS");
+  while (TS > 4 && lds(TS) > (size_t)h->lds_max / 2) TS >>= 1;
+  if (lds(TS) > (size_t)h->lds_max / 2) {
+    TS = 16;
+    while (TS > 4 && lds(TS) > (size_t)h->lds_max) TS >>= 1;
+  }
+  if (lds(TS) > (size_t)h->lds_max) return fail(h, RIFT_E_SHAPE, "window too long for the plain kernel's LDS");
   std::vector<int> tile0(n + 1, 0);
   for (int i = 0; i < n; i++) tile0[i + 1] = tile0[i] + (int)((it.cnt[i] + TS - 1) / TS);
   if (tile0[n] == 0) return RIFT_OK;
