@@ -802,6 +802,42 @@ def test_single_detector_ragged_window(ile, orc):
     assert np.all(np.abs(out - ref64) <= 1e-9 * (1 + np.abs(ref64)))
 
 
+def test_plain_long_window(ile, orc):
+    """FP64 plain form on a long window (n_t = 1900, H1 + L1, two modes): the
+    workgroup then holds the fewest samples it allows (4, each sample's window
+    reductions within one wavefront), forward and adjoint against the oracle;
+    a window too long for that (n_t = 8000) is refused with a shape error
+    instead of being evaluated with fewer samples per workgroup."""
+    spec = synth.PointSpec(seed=synth.BASE_SEED + 1303, dets=("H1", "L1"), n_modes=2, n_t=1900, snr=1.0,
+                           kernel="none")
+    d = dict(synth.make_point(spec))
+    d["U"] = d["U"] * 1e4  # noise-only Q scaled like the ragged-window case
+    d["Q"] = d["Q"] * 1e2
+    th = synth.mixed_samples(d, 41, 120)
+    p64 = orc.Point.from_dict(d)
+    h = _handle(ile, [d], "fp64")
+    _say("fp64 n_t=1900 forward and adjoint")
+    out = h.lnL(torch.tensor(th)).cpu().numpy()
+    ref = orc.lnL_t(p64, th)
+    assert np.all(np.abs(out - ref) <= 1e-9 * (1 + np.abs(ref))), np.abs(out - ref).max()
+    lt, g = orc.grad(p64, th)
+    gg, lg = h.backward(torch.tensor(th), want_lnL=True)
+    cg, cr = _consistent(gg.cpu().numpy(), th, spec.f_s), _consistent(g, th, spec.f_s)
+    rel = np.abs(cg - cr) / (np.abs(cr).max(axis=0) + 1e-3)
+    _say(f"  max rel grad err per parameter {np.array2string(rel.max(axis=1), precision=2)}")
+    assert rel.max() < 1e-9
+    assert np.allclose(lg.cpu().numpy(), lt, atol=1e-9)
+    h.close()
+    long = synth.make_point(synth.PointSpec(seed=synth.BASE_SEED + 1304, dets=("H1", "L1"), n_modes=2, n_t=8000,
+                                            snr=1.0, kernel="none"))
+    h = _handle(ile, [long], "fp64")
+    _say("fp64 n_t=8000 refused")
+    with pytest.raises(ile.RiftError) as e:
+        h.lnL(torch.tensor(synth.mixed_samples(long, 42, 8)))
+    assert e.value.status == -2
+    h.close()
+
+
 def test_single_point_full_size(ile, orc):
     """10^6 samples through the FP32 launch the benchmark times: sampled
     per-sample parity against the oracle, the FP64 reduction against the
