@@ -388,7 +388,10 @@ rift_status rift_ile_sample(rift_ile *h, int point, uint64_t seed, uint32_t roun
  * theta are evaluated against the item's point and
  *   ln L_t = ln[(1/n_t) sum_j exp(ell_j)]
  * is written to the same columns of lnL_t.  theta: device [7][stride];
- * lnL_t: device [stride].  items: host [n_items].  Asynchronous. */
+ * lnL_t: device [stride].  items: host [n_items].  Asynchronous.  Errors:
+ * RIFT_E_INVALID (NULL handle or arrays, items outside stride); RIFT_E_SHAPE
+ * on the plain (VALU) form when the handle's longest window does not fit four
+ * samples' rows in LDS (FP64: n_t above about 2300). */
 rift_status rift_ile_lnL(rift_ile *h, int n_items, const rift_ile_item *items, int64_t stride,
                          const void *theta, void *lnL_t);
 
