@@ -53,6 +53,7 @@ namespace rift {
 // parity, so the reads are free of bank conflicts whatever the shifts.
 constexpr int kRR = 60;
 constexpr int kSortThreads = 1024;  // threads per sort block (kSortBlock samples)
+static_assert(kSortBlock % kSortThreads == 0, "a whole number of samples per sort thread");
 
 __device__ __forceinline__ int item_of_flat(const ItemsDev &it, int64_t f) {
   int lo = 0, hi = it.n_items;  // samp0[lo] <= f < samp0[hi]
@@ -97,16 +98,29 @@ __global__ void __launch_bounds__(kSortThreads) bin_kernel(MfmaArgs a) {
   __syncthreads();
   const int64_t n = a.items.cnt[it];
   const int64_t j0 = (int64_t)lb * kSortBlock, j1 = min(n, j0 + kSortBlock);
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += kSortThreads) {
+  // the sort block's samples, kSortBlock / kSortThreads per thread: all
+  // their parameters are loaded before any is used, so the loads of a
+  // thread's samples are in flight together
+  constexpr int U = kSortBlock / kSortThreads;
+  float th[U][7];
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const int64_t j = j0 + threadIdx.x + (int64_t)u * kSortThreads;
+    const int64_t col = a.items.off[it] + (j < j1 ? j : j0);
+#pragma unroll
+    for (int d = 0; d < 7; d++) th[u][d] = a.theta[d * a.stride + col];
+  }
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const int64_t j = j0 + threadIdx.x + (int64_t)u * kSortThreads;
+    if (j >= j1) break;
     const int64_t f = a.items.samp0[it] + j;
-    const int64_t col = a.items.off[it] + j;
-    double al = a.theta[RIFT_ALPHA * a.stride + col], de = a.theta[RIFT_DELTA * a.stride + col];
-    double io = a.theta[RIFT_IOTA * a.stride + col], ph = a.theta[RIFT_PHI * a.stride + col];
-    double di = a.theta[RIFT_DIST * a.stride + col], ta = a.theta[RIFT_TAU * a.stride + col];
+    const double al = th[u][RIFT_ALPHA], de = th[u][RIFT_DELTA], io = th[u][RIFT_IOTA], ph = th[u][RIFT_PHI];
+    const double di = th[u][RIFT_DIST], ta = th[u][RIFT_TAU];
     SkyTrig tr = sky_trig(al, de, 0.0, p.gmst);
     Shift sh = shifts(p, tr, ta);
     bool ok = sh.ok && isfinite(io) && isfinite(ph) && (a.dmarg || (isfinite(di) && di > 0.0)) &&
-              isfinite((double)a.theta[RIFT_PSI * a.stride + col]);
+              isfinite((double)th[u][RIFT_PSI]);
     uint32_t key = 0, mul = 1;
     uint32_t nw[2] = {0u, ok ? 1u << 16 : 0u};  // the four int16 of the sample, one 8-byte store
     for (int k = 0; k < p.K; k++) {
@@ -249,22 +263,30 @@ __global__ void __launch_bounds__(kSortThreads) scatter_kernel(MfmaArgs a) {
   const int64_t n = a.items.cnt[it];
   const int64_t j0 = (int64_t)lb * kSortBlock, j1 = min(n, j0 + kSortBlock);
   const uint32_t tbase = a.item_tiles[it];
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += kSortThreads) {
+  // kSortBlock / kSortThreads samples per thread, their loads issued together
+  constexpr int U = kSortBlock / kSortThreads;
+  SampleRec rec[U];
+  uint32_t key[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const int64_t jj = j0 + threadIdx.x + (int64_t)u * kSortThreads, j = jj < j1 ? jj : j0;
     const int64_t f = a.items.samp0[it] + j;
     const int64_t col = a.items.off[it] + j;
-    const uint32_t key = a.key[f];
-    const uint32_t r = atomicAdd(&cur[key], 1u);
-    const uint32_t pos = kTS * (tbase + a.bin_tile[b0 + key]) + r;
-    SampleRec rec;
+    key[u] = a.key[f];
 #pragma unroll
-    for (int d = 0; d < 7; d++) rec.th[d] = a.theta[d * a.stride + col];
-    rec.col = (int)col;
+    for (int d = 0; d < 7; d++) rec[u].th[d] = a.theta[d * a.stride + col];
+    rec[u].col = (int)col;
     const uint2 nw = *(const uint2 *)(a.nsh + f * 4);
-    rec.n[0] = (int16_t)(nw.x & 0xffffu);
-    rec.n[1] = (int16_t)(nw.x >> 16);
-    rec.n[2] = (int16_t)(nw.y & 0xffffu);
-    rec.flag = (nw.y >> 16) ? 1 : 2;
-    a.rec[pos] = rec;
+    rec[u].n[0] = (int16_t)(nw.x & 0xffffu);
+    rec[u].n[1] = (int16_t)(nw.x >> 16);
+    rec[u].n[2] = (int16_t)(nw.y & 0xffffu);
+    rec[u].flag = (nw.y >> 16) ? 1 : 2;
+  }
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    if (j0 + threadIdx.x + (int64_t)u * kSortThreads >= j1) break;
+    const uint32_t r = atomicAdd(&cur[key[u]], 1u);
+    a.rec[kTS * (tbase + a.bin_tile[b0 + key[u]]) + r] = rec[u];
   }
 }
 
