@@ -287,10 +287,12 @@ __global__ void __launch_bounds__(256) sample_kernel(const ProposalDev *prop, co
                                                      double tau_width, R *theta, R *ln_ratio, uint8_t *bins,
                                                      float *ubuf, int phase) {
   __shared__ double cdf[7][kNB + 1];
-  __shared__ unsigned mask;
   __shared__ GmmSh g;
-  for (int i = threadIdx.x; i < 7 * (kNB + 1); i += blockDim.x) cdf[i / (kNB + 1)][i % (kNB + 1)] = prop->cdf[i / (kNB + 1)][i % (kNB + 1)];
-  if (threadIdx.x == 0) mask = prop->mask;
+  // the histogram tables are staged only when some dimension draws from one
+  const unsigned mask = prop->mask;
+  if (mask)
+    for (int i = threadIdx.x; i < 7 * (kNB + 1); i += blockDim.x)
+      cdf[i / (kNB + 1)][i % (kNB + 1)] = prop->cdf[i / (kNB + 1)][i % (kNB + 1)];
   if (MIX) gmm_stage(prop, g);
   __syncthreads();
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -309,7 +311,6 @@ __global__ void __launch_bounds__(256) sample_multi_kernel(const ProposalDev *pr
                                                            double d_max, double tau_width, R *theta, R *ln_ratio,
                                                            uint8_t *bins, float *ubuf, int phase) {
   __shared__ double cdf[7][kNB + 1];
-  __shared__ unsigned mask;
   __shared__ GmmSh g;
   int lo = 0, hi = np;  // blk0[lo] <= blockIdx.x < blk0[hi]
   while (hi - lo > 1) {
@@ -318,8 +319,11 @@ __global__ void __launch_bounds__(256) sample_multi_kernel(const ProposalDev *pr
   }
   const int p = lo;
   const ProposalDev *prop = props + p;
-  for (int i = threadIdx.x; i < 7 * (kNB + 1); i += blockDim.x) cdf[i / (kNB + 1)][i % (kNB + 1)] = prop->cdf[i / (kNB + 1)][i % (kNB + 1)];
-  if (threadIdx.x == 0) mask = prop->mask;
+  // the histogram tables are staged only when some dimension draws from one
+  const unsigned mask = prop->mask;
+  if (mask)
+    for (int i = threadIdx.x; i < 7 * (kNB + 1); i += blockDim.x)
+      cdf[i / (kNB + 1)][i % (kNB + 1)] = prop->cdf[i / (kNB + 1)][i % (kNB + 1)];
   if (MIX) gmm_stage(prop, g);
   __syncthreads();
   const int64_t j = (int64_t)(blockIdx.x - blk0[p]) * blockDim.x + threadIdx.x;
