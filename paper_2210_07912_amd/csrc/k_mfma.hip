@@ -499,8 +499,11 @@ __global__ void __launch_bounds__(64) coef_kernel(MfmaArgs a, int item_lo, int i
 // 2^-(T + 10) log2 e (their n_t terms together are far under the rule's
 // error), then combines the nodes in FP64.  Both passes recompute the same
 // window values bit for bit.
-template <int T, int K, bool DIRECT, int MODE>
-__global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int item_hi, int cls) {
+// WPE: wavefronts per SIMD the register allocation must allow (1: no cap;
+// the capped direct forms are extra configurations for the autotuner)
+template <int T, int K, bool DIRECT, int MODE, int WPE = 1>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) mfma_kernel(MfmaArgs a, int item_lo,
+                                                                                         int item_hi, int cls) {
   constexpr int E = 4 * T, J = T / 4, R = T % 4;
   constexpr int JA = J > 0 ? J : 1, RA = R > 0 ? R : 1;
   constexpr int ES = stage_stride<T>();
@@ -883,48 +886,55 @@ __global__ void __launch_bounds__(256) mfma_kernel(MfmaArgs a, int item_lo, int 
 // Persistent grid: as many workgroups as the device keeps resident
 // (residency 0), or half as many per compute unit, at least one (residency 1:
 // fewer workgroups sharing a compute unit's LDS, caches and issue slots).
-template <int T, int K, bool D, int MODE>
+template <int T, int K, bool D, int MODE, int WPE = 1>
 static void launch_tk(const MfmaArgs &a, int lo, int hi, int cls, hipStream_t st, int residency) {
   static int per_cu = 0;
   if (per_cu == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mfma_kernel<T, K, D, MODE>, 256, 0) != hipSuccess || nb < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mfma_kernel<T, K, D, MODE, WPE>, 256, 0) != hipSuccess ||
+        nb < 1)
       nb = 1;
     per_cu = nb;
   }
   const int pc = residency ? std::max(1, per_cu / 2) : per_cu;
   const int grid = std::max(1, a.grid / 4 * pc);  // a.grid = 4 per compute unit
-  hipLaunchKernelGGL((mfma_kernel<T, K, D, MODE>), dim3(grid), dim3(256), 0, st, a, lo, hi, cls);
+  hipLaunchKernelGGL((mfma_kernel<T, K, D, MODE, WPE>), dim3(grid), dim3(256), 0, st, a, lo, hi, cls);
 }
 
 // pass: 0 ln L_t (staged or direct feed); 1, 2 the passes of distance
 // marginalization (staged feed)
 template <int T, int K>
-static void launch_tkm(const MfmaArgs &a, bool direct, int pass, int lo, int hi, int cls, hipStream_t st, int res) {
+static void launch_tkm(const MfmaArgs &a, bool direct, int pass, int lo, int hi, int cls, hipStream_t st, int res,
+                       int wpe) {
   if (pass == 1) launch_tk<T, K, false, 1>(a, lo, hi, cls, st, res);
   else if (pass == 2) launch_tk<T, K, false, 2>(a, lo, hi, cls, st, res);
+  else if (direct && wpe == 3) launch_tk<T, K, true, 0, 3>(a, lo, hi, cls, st, res);
+  else if (direct && wpe == 4) launch_tk<T, K, true, 0, 4>(a, lo, hi, cls, st, res);
   else if (direct) launch_tk<T, K, true, 0>(a, lo, hi, cls, st, res);
   else launch_tk<T, K, false, 0>(a, lo, hi, cls, st, res);
 }
 
 template <int T>
 static void launch_class(const MfmaArgs &a, int K, bool direct, int pass, int lo, int hi, int cls, hipStream_t st,
-                         int res) {
-  if (K == 1) launch_tkm<T, 1>(a, direct, pass, lo, hi, cls, st, res);
-  else if (K == 2) launch_tkm<T, 2>(a, direct, pass, lo, hi, cls, st, res);
-  else launch_tkm<T, 3>(a, direct, pass, lo, hi, cls, st, res);
+                         int res, int wpe) {
+  if (K == 1) launch_tkm<T, 1>(a, direct, pass, lo, hi, cls, st, res, wpe);
+  else if (K == 2) launch_tkm<T, 2>(a, direct, pass, lo, hi, cls, st, res, wpe);
+  else launch_tkm<T, 3>(a, direct, pass, lo, hi, cls, st, res, wpe);
 }
 
 // Launch configuration of a class, as the autotuner numbers it: 1 staged,
-// 2 direct, 3 staged at half residency, 4 direct at half residency
-static bool cfg_direct(int mode) { return mode == 2 || mode == 4; }
-static int cfg_residency(int mode) { return mode >= 3 ? 1 : 0; }
+// 2 direct, 3 staged at half residency, 4 direct at half residency, 5 and 6
+// direct with registers capped so that three (5) or four (6) wavefronts fit
+// on a SIMD
+static bool cfg_direct(int mode) { return mode == 2 || mode >= 4; }
+static int cfg_residency(int mode) { return mode == 3 || mode == 4 ? 1 : 0; }
+static int cfg_wpe(int mode) { return mode == 5 ? 3 : mode == 6 ? 4 : 1; }
 
 static hipError_t launch_mode(const MfmaArgs &a, int T, int K, bool direct, int lo, int hi, int cls, hipStream_t st,
-                              int pass = 0, int res = 0) {
+                              int pass = 0, int res = 0, int wpe = 1) {
   switch (T) {
 #define RIFT_T_CASE(TT) \
-  case TT: launch_class<TT>(a, K, direct, pass, lo, hi, cls, st, res); break;
+  case TT: launch_class<TT>(a, K, direct, pass, lo, hi, cls, st, res, wpe); break;
     RIFT_T_CASE(1) RIFT_T_CASE(2) RIFT_T_CASE(3) RIFT_T_CASE(4) RIFT_T_CASE(5) RIFT_T_CASE(6) RIFT_T_CASE(7)
     RIFT_T_CASE(8) RIFT_T_CASE(9) RIFT_T_CASE(10) RIFT_T_CASE(11) RIFT_T_CASE(12) RIFT_T_CASE(13)
     RIFT_T_CASE(14) RIFT_T_CASE(15) RIFT_T_CASE(16)
@@ -940,14 +950,14 @@ static hipError_t launch_mode(const MfmaArgs &a, int T, int K, bool direct, int 
 // rewrite the outputs.  The staged form at full residency is kept unless
 // another configuration is at least 3 % faster.
 static hipError_t tune_class(const MfmaArgs &a, int T, int K, int lo, int hi, int c, hipStream_t st, int &mode) {
-  constexpr int kCfg = 4;
+  constexpr int kCfg = kFeedConfigs;
   hipEvent_t ev[2 * kCfg] = {};
   hipError_t e = hipSuccess;
   for (int i = 0; i < 2 * kCfg && e == hipSuccess; i++) e = hipEventCreate(&ev[i]);
   for (int m = 1; m <= kCfg && e == hipSuccess; m++) {
     if (m > 1) e = fill_u32(a.ctl + 1 + c, 1, 0u, st);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * (m - 1)], st);
-    if (e == hipSuccess) e = launch_mode(a, T, K, cfg_direct(m), lo, hi, c, st, 0, cfg_residency(m));
+    if (e == hipSuccess) e = launch_mode(a, T, K, cfg_direct(m), lo, hi, c, st, 0, cfg_residency(m), cfg_wpe(m));
     if (e == hipSuccess) e = hipEventRecord(ev[2 * (m - 1) + 1], st);
   }
   if (e == hipSuccess) e = hipEventSynchronize(ev[2 * kCfg - 1]);
@@ -1034,7 +1044,7 @@ hipError_t mfma_forward(const MfmaArgs &a, const int *class_T, const int *class_
   for (int c = 0; c < n_classes; c++) {
     if (c < 64 && (done >> c) & 1) continue;
     e = launch_mode(a, class_T[c], class_K[c], cfg_direct(class_mode[c]), class_item0[c], class_item0[c + 1], c,
-                    fan_stream(fo, st, c), 0, cfg_residency(class_mode[c]));
+                    fan_stream(fo, st, c), 0, cfg_residency(class_mode[c]), cfg_wpe(class_mode[c]));
     if (e != hipSuccess) return e;
   }
   e = hipGetLastError();

@@ -65,9 +65,11 @@ struct rift_ile {
   bool phase_rot = false;  // polarization and phase in phase-rotated coordinates
   bool dmarg = false;      // distance-marginalized ln L_tD (theta's distance not read)
   // launch configuration of each class (1 staged, 2 direct, 3 and 4 the same
-  // at half residency; 0 not measured), by (T, K, n_t bucket = floor(log2 of
+  // at half residency, 5 and 6 direct with registers capped for three or four
+  // wavefronts per SIMD; 0 not measured), by (T, K, n_t bucket = floor(log2 of
   // the class's longest window)); kmode: the configuration each (T, K) ran
-  // last.  feed: 1 measure on first use, 0 all staged, 2 all direct.
+  // last.  feed: 1 measure on first use, 0 all staged, 2 all direct, 3 and 4
+  // all direct with registers capped for three or four wavefronts per SIMD.
   // tune_path: a file the measurements are read from and appended to.
   int feed = 1;
   int kmode[kMaxT + 1][kMaxDet + 1] = {};
@@ -710,7 +712,12 @@ rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const f
   }
   bool measured = true;
   for (size_t c = 0; c < class_T.size(); c++) {
-    class_mode[c] = h->feed == 1 ? h->tune[class_T[c]][class_K[c]][class_ntb[c]] : h->feed == 2 ? 2 : 1;
+    // feed 0: staged, 1: measured, 2: direct, 3 and 4: direct with registers
+    // capped for three or four wavefronts per SIMD (configurations 5, 6)
+    class_mode[c] = h->feed == 1 ? h->tune[class_T[c]][class_K[c]][class_ntb[c]]
+                    : h->feed == 0 ? 1
+                    : h->feed == 2 ? 2
+                                   : h->feed + 2;
     measured = measured && class_mode[c] != 0;
   }
   if (!grad && h->use_graph && !h->prof && measured) {
@@ -1340,7 +1347,7 @@ rift_status rift_ile_set_grad_refine(rift_ile *h, int enable) {
 }
 
 rift_status rift_ile_set_autotune(rift_ile *h, int mode) {
-  if (!h || mode < 0 || mode > 2) return RIFT_E_INVALID;
+  if (!h || mode < 0 || mode > 4) return RIFT_E_INVALID;
   h->feed = mode;
   return RIFT_OK;
 }
@@ -1361,7 +1368,7 @@ rift_status rift_ile_set_autotune_cache(rift_ile *h, const char *path) {
       int T, K, b, m;
       if (std::sscanf(line, "%95s %d %d %d %d", arch, &T, &K, &b, &m) != 5) continue;
       if (h->arch != arch || T < 1 || T > kMaxT || K < 1 || K > kMaxDet || b < 0 || b >= kNtBuckets || m < 1 ||
-          m > 4)
+          m > kFeedConfigs)
         continue;
       h->tune[T][K][b] = m;  // later lines win
     }
