@@ -1026,7 +1026,9 @@ rift_status marginalize_impl(rift_ile *h, const rift_ile_mc *mc, rift_ile_result
     HIPCHK(h, sample_multi_launch<R>(h->d_props, h->net_frame ? h->d_pts : nullptr, d_sblk, sblk[np], np, d_soff,
                                      d_scnt, mc->seed, (uint32_t)(mc->first_round + r),
                                      th_stride, nr, h->d_min, h->d_max, h->tau_width, th, (R *)ratio,
-                                     (uint8_t *)bins, h->stream, ubuf, h->any_mix, h->phase_rot));
+                                     // bins only for the histogram adaptation that reads them
+                                     mc->adapt_mask && !gmm ? (uint8_t *)bins : nullptr, h->stream, ubuf,
+                                     h->any_mix, h->phase_rot));
     {
       Range ph("evaluate");
       if ((s = eval<R>(h, it, th_stride, th, nullptr, lw, (const R *)ratio)) != RIFT_OK) return s;
