@@ -390,16 +390,13 @@ __device__ __forceinline__ void tup_add(ReduceTuple &t, double x) {
   }
   t.n++;
   if (x == -INFINITY) return;
-  if (x > t.m) {
-    double e = exp(t.m - x);  // 0 when t.m = -inf
-    t.s1 = t.s1 * e + 1.0;
-    t.s2 = t.s2 * e * e + 1.0;
-    t.m = x;
-  } else {
-    double e = exp(x - t.m);
-    t.s1 += e;
-    t.s2 += e * e;
-  }
+  // one exponential either way: exp(-|x - m|) rescales the sums to a new
+  // maximum or weighs x against the current one (0 when m = -inf)
+  const bool up = x > t.m;
+  const double e = exp(up ? t.m - x : x - t.m);
+  t.s1 = up ? t.s1 * e + 1.0 : t.s1 + e;
+  t.s2 = up ? t.s2 * e * e + 1.0 : t.s2 + e * e;
+  t.m = up ? x : t.m;
 }
 
 __device__ __forceinline__ ReduceTuple tup_merge(const ReduceTuple &a, const ReduceTuple &b) {
