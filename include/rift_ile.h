@@ -341,25 +341,26 @@ rift_status rift_ile_set_grad_refine(rift_ile *h, int enable);
  * global memory one block ahead, no barrier, less LDS and more resident
  * workgroups); each runs with as many workgroups as the device keeps resident
  * or with half as many per compute unit; the direct form also comes compiled
- * with its registers capped so that three or four wavefronts fit on a SIMD
- * (more resident workgroups where LDS allows them).  The six configurations
- * are numbered 1 staged, 2 direct, 3 staged at half residency, 4 direct at
- * half residency, 5 direct capped for three wavefronts per SIMD, 6 direct
- * capped for four; their results are bit-identical.  mode 1 (the default):
- * the first evaluation of a class on the handle, for each n_t bucket
- * (floor(log2) of the class's longest window), runs all six on that call's
- * data, timed with events (that call waits for them), and later calls use
- * the fastest (configuration 1 unless another is at least 3 % faster).
- * mode 0: every class runs staged; mode 2: every class runs direct; modes 3
- * and 4: every class runs configuration 5 or 6 (measurements made so far are
- * kept for a later mode 1).  Runs with a class not yet measured are not
+ * with its registers capped so that three or four wavefronts fit on a SIMD,
+ * the staged form capped for three (more resident workgroups where LDS allows
+ * them).  The seven configurations are numbered 1 staged, 2 direct, 3 staged
+ * at half residency, 4 direct at half residency, 5 direct capped for three
+ * wavefronts per SIMD, 6 direct capped for four, 7 staged capped for three;
+ * their results are bit-identical.  mode 1 (the default): the first
+ * evaluation of a class on the handle, for each n_t bucket (floor(log2) of
+ * the class's longest window), runs all seven on that call's data, timed with
+ * events (that call waits for them), and later calls use the fastest
+ * (configuration 1 unless another is at least 3 % faster).  mode 0: every
+ * class runs staged; mode 2: every class runs direct; modes 3, 4 and 5: every
+ * class runs configuration 5, 6 or 7 (measurements made so far are kept for a
+ * later mode 1).  Runs with a class not yet measured are not
  * captured by the graph replay.  Returns RIFT_E_INVALID for a NULL handle or
  * another mode. */
 rift_status rift_ile_set_autotune(rift_ile *h, int mode);
 
 /* The configuration each (T, K) class ran with last: modes[(T - 1) * 3 +
  * (K - 1)] for T = 1..16 and K = 1..3 (48 ints, caller-owned) is 0 (not run
- * yet) or 1..6 as numbered above.  Returns RIFT_E_INVALID for a NULL handle
+ * yet) or 1..7 as numbered above.  Returns RIFT_E_INVALID for a NULL handle
  * or array. */
 rift_status rift_ile_autotune_table(const rift_ile *h, int *modes);
 

@@ -49,7 +49,7 @@ size_t plain_lds_bytes(int elem, int TS, int rows_cap, int nt_cap, bool bwd);
 constexpr int kMaxT = kMaxModes / 2;  // MFMA steps of 4 elements per detector: M_p / 2
 constexpr int kMaxClasses = 48;  // one persistent launch per distinct (T = Mp / 2, K)
 constexpr int kNtBuckets = 17;   // autotuner key: floor(log2 n_t) of a class's longest window
-constexpr int kFeedConfigs = 6;  // launch configurations the autotuner measures per class
+constexpr int kFeedConfigs = 7;  // launch configurations the autotuner measures per class
 
 constexpr int kSortBlock = 4096;  // samples per sort block
 constexpr int kLdsBins = 8192;    // delay bins counted in LDS (more: in global memory)

@@ -51,7 +51,10 @@ namespace rift {
 // different samples differ in the column's bank, and the two row groups of a
 // half-wavefront (4 logical rows apart, 5 physical) differ in the row's
 // parity, so the reads are free of bank conflicts whatever the shifts.
-constexpr int kRR = 60;
+// Logical rows 0..47 occupy physical rows 0..58 (the pad after row 47 is
+// never stored), which keeps the staged K = 3, T <= 3 instances within a
+// third of a compute unit's LDS.
+constexpr int kRR = 59;
 constexpr int kSortThreads = 1024;  // threads per sort block (kSortBlock samples)
 static_assert(kSortBlock % kSortThreads == 0, "a whole number of samples per sort thread");
 
@@ -909,6 +912,7 @@ static void launch_tkm(const MfmaArgs &a, bool direct, int pass, int lo, int hi,
   if (pass == 1) launch_tk<T, K, false, 1>(a, lo, hi, cls, st, res);
   else if (pass == 2) launch_tk<T, K, false, 2>(a, lo, hi, cls, st, res);
   else if (direct && wpe == 3) launch_tk<T, K, true, 0, 3>(a, lo, hi, cls, st, res);
+  else if (wpe == 3) launch_tk<T, K, false, 0, 3>(a, lo, hi, cls, st, res);
   else if (direct && wpe == 4) launch_tk<T, K, true, 0, 4>(a, lo, hi, cls, st, res);
   else if (direct) launch_tk<T, K, true, 0>(a, lo, hi, cls, st, res);
   else launch_tk<T, K, false, 0>(a, lo, hi, cls, st, res);
@@ -925,10 +929,10 @@ static void launch_class(const MfmaArgs &a, int K, bool direct, int pass, int lo
 // Launch configuration of a class, as the autotuner numbers it: 1 staged,
 // 2 direct, 3 staged at half residency, 4 direct at half residency, 5 and 6
 // direct with registers capped so that three (5) or four (6) wavefronts fit
-// on a SIMD
-static bool cfg_direct(int mode) { return mode == 2 || mode >= 4; }
+// on a SIMD, 7 staged capped for three
+static bool cfg_direct(int mode) { return mode == 2 || (mode >= 4 && mode <= 6); }
 static int cfg_residency(int mode) { return mode == 3 || mode == 4 ? 1 : 0; }
-static int cfg_wpe(int mode) { return mode == 5 ? 3 : mode == 6 ? 4 : 1; }
+static int cfg_wpe(int mode) { return mode == 5 || mode == 7 ? 3 : mode == 6 ? 4 : 1; }
 
 static hipError_t launch_mode(const MfmaArgs &a, int T, int K, bool direct, int lo, int hi, int cls, hipStream_t st,
                               int pass = 0, int res = 0, int wpe = 1) {

@@ -66,10 +66,11 @@ struct rift_ile {
   bool dmarg = false;      // distance-marginalized ln L_tD (theta's distance not read)
   // launch configuration of each class (1 staged, 2 direct, 3 and 4 the same
   // at half residency, 5 and 6 direct with registers capped for three or four
-  // wavefronts per SIMD; 0 not measured), by (T, K, n_t bucket = floor(log2 of
-  // the class's longest window)); kmode: the configuration each (T, K) ran
-  // last.  feed: 1 measure on first use, 0 all staged, 2 all direct, 3 and 4
-  // all direct with registers capped for three or four wavefronts per SIMD.
+  // wavefronts per SIMD, 7 staged capped for three; 0 not measured), by (T, K,
+  // n_t bucket = floor(log2 of the class's longest window)); kmode: the
+  // configuration each (T, K) ran last.  feed: 1 measure on first use, 0 all
+  // staged, 2 all direct, 3 and 4 all direct with registers capped for three
+  // or four wavefronts per SIMD, 5 all staged capped for three.
   // tune_path: a file the measurements are read from and appended to.
   int feed = 1;
   int kmode[kMaxT + 1][kMaxDet + 1] = {};
@@ -713,7 +714,8 @@ rift_status run_mfma_group(rift_ile *h, const Items &it, int64_t stride, const f
   bool measured = true;
   for (size_t c = 0; c < class_T.size(); c++) {
     // feed 0: staged, 1: measured, 2: direct, 3 and 4: direct with registers
-    // capped for three or four wavefronts per SIMD (configurations 5, 6)
+    // capped for three or four wavefronts per SIMD (configurations 5, 6),
+    // 5: staged capped for three (configuration 7)
     class_mode[c] = h->feed == 1 ? h->tune[class_T[c]][class_K[c]][class_ntb[c]]
                     : h->feed == 0 ? 1
                     : h->feed == 2 ? 2
@@ -1349,7 +1351,7 @@ rift_status rift_ile_set_grad_refine(rift_ile *h, int enable) {
 }
 
 rift_status rift_ile_set_autotune(rift_ile *h, int mode) {
-  if (!h || mode < 0 || mode > 4) return RIFT_E_INVALID;
+  if (!h || mode < 0 || mode > 5) return RIFT_E_INVALID;
   h->feed = mode;
   return RIFT_OK;
 }

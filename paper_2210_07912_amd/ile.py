@@ -261,21 +261,23 @@ class RiftILE:
 
     def set_autotune(self, mode=1):
         """Launch configuration of FP32 evaluations: 1 (default) measure the
-        six configurations (staged or direct feed, full or half residency, and
+        seven configurations (staged or direct feed, full or half residency,
         the direct feed with registers capped for three or four wavefronts per
-        SIMD) of each (T, K) class and n_t bucket on its first evaluation and
-        use the fastest; 0 always staged; 2 always direct; 3, 4 always the
-        capped direct forms.  ``True``/``False`` mean 1/0."""
+        SIMD, the staged feed capped for three) of each (T, K) class and n_t
+        bucket on its first evaluation and use the fastest; 0 always staged;
+        2 always direct; 3, 4 always the capped direct forms; 5 always the
+        capped staged form.  ``True``/``False`` mean 1/0."""
         self._check(lib().rift_ile_set_autotune(self.h, int(mode)))
 
     def autotune_table(self):
         """{(T, K): configuration} for the classes run so far: "staged",
         "direct", "staged/half", "direct/half" (half: half the resident
-        workgroups per compute unit), "direct/3w" or "direct/4w" (registers
-        capped for three or four wavefronts per SIMD)."""
+        workgroups per compute unit), "direct/3w", "direct/4w" or "staged/3w"
+        (registers capped for three or four wavefronts per SIMD)."""
         arr = (C.c_int * 48)()
         self._check(lib().rift_ile_autotune_table(self.h, arr))
-        names = {1: "staged", 2: "direct", 3: "staged/half", 4: "direct/half", 5: "direct/3w", 6: "direct/4w"}
+        names = {1: "staged", 2: "direct", 3: "staged/half", 4: "direct/half", 5: "direct/3w", 6: "direct/4w",
+                 7: "staged/3w"}
         return {(i // 3 + 1, i % 3 + 1): names[v] for i, v in enumerate(arr) if v in names}
 
     def set_autotune_cache(self, path):

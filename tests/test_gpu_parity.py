@@ -156,7 +156,7 @@ def test_lnL_batched_items(ile, orc):
 def test_matrix_core_feeds(ile, orc):
     """The staged (LDS) and the direct (global-memory) feed of the matrix
     cores, the latter also with registers capped for three and four
-    wavefronts per SIMD, give bit-identical ln L_t for every (T, K) class of
+    wavefronts per SIMD and the former for three, give bit-identical ln L_t for every (T, K) class of
     the batched parity case, the direct one within the oracle tolerance; the autotuner
     measures each class once, its later runs agree with both forms, and the
     graph replay starts only once every class is measured."""
@@ -173,7 +173,7 @@ def test_matrix_core_feeds(ile, orc):
     theta = torch.tensor(np.concatenate(ths, axis=1))
     classes = {((s.n_modes + 1) // 2, len(s.dets)) for s in w.points}
     outs = {}
-    for mode in (0, 2, 3, 4, 1):
+    for mode in (0, 2, 3, 4, 5, 1):
         h = _handle(ile, pts, "fp32")
         h.set_autotune(mode)
         _say(f"feed mode {mode}")
@@ -186,7 +186,7 @@ def test_matrix_core_feeds(ile, orc):
             _say(f"  measured: {sorted(table.items())}")
             assert set(table) == classes
         h.close()
-    for mode in (1, 2, 3, 4):  # every configuration bit-identical
+    for mode in (1, 2, 3, 4, 5):  # every configuration bit-identical
         assert np.array_equal(outs[0], outs[mode], equal_nan=True), mode
     for i, (_, o, n) in enumerate(items):
         _check_fp32(outs[2][o:o + n], refs[i], f"direct feed, point {i}", ops[i], ths[i])
