@@ -348,9 +348,10 @@ rift_status rift_ile_set_grad_refine(rift_ile *h, int enable);
  * wavefronts per SIMD, 6 direct capped for four, 7 staged capped for three;
  * their results are bit-identical.  mode 1 (the default): the first
  * evaluation of a class on the handle, for each n_t bucket (floor(log2) of
- * the class's longest window), runs all seven on that call's data, timed with
- * events (that call waits for them), and later calls use the fastest
- * (configuration 1 unless another is at least 3 % faster).  mode 0: every
+ * the class's longest window), runs all seven twice on that call's data,
+ * timed with events (that call waits for them), and later calls use the
+ * fastest by the better of its two runs (configuration 1 unless another is
+ * at least 3 % faster).  mode 0: every
  * class runs staged; mode 2: every class runs direct; modes 3, 4 and 5: every
  * class runs configuration 5, 6 or 7 (measurements made so far are kept for a
  * later mode 1).  Runs with a class not yet measured are not

@@ -951,25 +951,35 @@ static hipError_t launch_mode(const MfmaArgs &a, int T, int K, bool direct, int 
 // Every launch configuration of class c on the call's own data, one after the
 // other on st, timed with events (the class's work-unit counter cleared
 // before each); the results are bit-identical, so the later runs only
-// rewrite the outputs.  The staged form at full residency is kept unless
+// rewrite the outputs.  The configurations are run in two passes and each is
+// judged by the faster of its two runs, so none pays alone for the class's
+// first touch of Q and its tile records or for clocks still rising at the
+// start of the pass.  The staged form at full residency is kept unless
 // another configuration is at least 3 % faster.
 static hipError_t tune_class(const MfmaArgs &a, int T, int K, int lo, int hi, int c, hipStream_t st, int &mode) {
-  constexpr int kCfg = kFeedConfigs;
-  hipEvent_t ev[2 * kCfg] = {};
+  constexpr int kCfg = kFeedConfigs, kPasses = 2, kEv = 2 * kPasses * kCfg;
+  hipEvent_t ev[kEv] = {};
   hipError_t e = hipSuccess;
-  for (int i = 0; i < 2 * kCfg && e == hipSuccess; i++) e = hipEventCreate(&ev[i]);
-  for (int m = 1; m <= kCfg && e == hipSuccess; m++) {
-    if (m > 1) e = fill_u32(a.ctl + 1 + c, 1, 0u, st);
-    if (e == hipSuccess) e = hipEventRecord(ev[2 * (m - 1)], st);
-    if (e == hipSuccess) e = launch_mode(a, T, K, cfg_direct(m), lo, hi, c, st, 0, cfg_residency(m), cfg_wpe(m));
-    if (e == hipSuccess) e = hipEventRecord(ev[2 * (m - 1) + 1], st);
-  }
-  if (e == hipSuccess) e = hipEventSynchronize(ev[2 * kCfg - 1]);
+  for (int i = 0; i < kEv && e == hipSuccess; i++) e = hipEventCreate(&ev[i]);
+  for (int r = 0; r < kPasses; r++)
+    for (int m = 1; m <= kCfg && e == hipSuccess; m++) {
+      hipEvent_t *em = ev + 2 * (r * kCfg + m - 1);
+      if (r > 0 || m > 1) e = fill_u32(a.ctl + 1 + c, 1, 0u, st);
+      if (e == hipSuccess) e = hipEventRecord(em[0], st);
+      if (e == hipSuccess) e = launch_mode(a, T, K, cfg_direct(m), lo, hi, c, st, 0, cfg_residency(m), cfg_wpe(m));
+      if (e == hipSuccess) e = hipEventRecord(em[1], st);
+    }
+  if (e == hipSuccess) e = hipEventSynchronize(ev[kEv - 1]);
   float best = 0.f;
   int pick = 1;
   for (int m = 1; m <= kCfg && e == hipSuccess; m++) {
     float t = 0.f;
-    e = hipEventElapsedTime(&t, ev[2 * (m - 1)], ev[2 * (m - 1) + 1]);
+    for (int r = 0; r < kPasses && e == hipSuccess; r++) {
+      const hipEvent_t *em = ev + 2 * (r * kCfg + m - 1);
+      float tr = 0.f;
+      e = hipEventElapsedTime(&tr, em[0], em[1]);
+      t = r == 0 ? tr : std::min(t, tr);
+    }
     if (e != hipSuccess) break;
     if (m == 1 || t < 0.97f * best) {
       best = t;
@@ -977,7 +987,7 @@ static hipError_t tune_class(const MfmaArgs &a, int T, int K, int lo, int hi, in
     }
   }
   if (e == hipSuccess) mode = pick;
-  for (int i = 0; i < 2 * kCfg; i++)
+  for (int i = 0; i < kEv; i++)
     if (ev[i]) (void)hipEventDestroy(ev[i]);
   return e;
 }
